@@ -1,0 +1,199 @@
+/*
+ * mphx.h -- C ABI of the MI355X (gfx950) MWHC build library: hypergraph peeling and minimal
+ * perfect hashing after Belazzougui, Boldi, Ottaviano, Venturini, Vigna, "Cache-Oblivious
+ * Peeling of Random Hypergraphs" (arXiv 1312.0526).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers marked (dev) are device pointers on the current HIP device; (host) are host
+ *    pointers.  The caller allocates and owns every buffer, including the workspace; the
+ *    library never frees caller memory and allocates no device memory in these calls (the
+ *    server API is the exception: it owns a pool sized by its budget).
+ *  - `stream` is a hipStream_t passed as void*; all device work is enqueued on it.  Calls
+ *    that return data-dependent results (status, info) synchronise that stream once or a
+ *    few times before returning; the others only enqueue.
+ *  - Status: 0 = MPHX_OK; negative = error (MPHX_EINVAL bad argument, MPHX_ERANGE a limit
+ *    exceeded, MPHX_ENOMEM workspace too small, MPHX_EDEVICE a HIP runtime error); positive
+ *    = the method's own failure outcomes (MPHX_ECORE a 2-core remained after every try,
+ *    MPHX_EDUP duplicate keys).  mphx_last_error() returns a message for the calling thread.
+ *    No C++ exception crosses the ABI.
+ *  - Vertex layout of the tripartite hypergraph (Section 4.3, "Exploiting the
+ *    tripartition"): P = ceil(n * gamma_num / (3 * gamma_den)) vertices per part, m = 3P;
+ *    vertex k of every key's edge lies in part k, i.e. in [k*P, (k+1)*P).
+ *  - Hashing (Section 3; SplitMix64 stands in for the paper's Jenkins hash): a u64 key x
+ *    under seed s has state a = b = x XOR s; a byte string has the 128-bit digest (a, b)
+ *    (two lanes, each the sum over the key's little-endian 8-byte words w_j, tail padded
+ *    with zeros, of fin(w_j XOR (s_lane + j*GAMMA)), then fin(sum XOR s_lane XOR length),
+ *    s_A = SplitMix64 output 1 at state s, s_B = output 2).  Vertex k is
+ *    k*P + floor(z_k * P / 2^64) with z_0 = fin(a + GAMMA), z_1 = fin(a + 2 GAMMA),
+ *    z_2 = fin(b + 3 GAMMA); fin is SplitMix64's output function, GAMMA = 0x9E3779B97F4A7C15.
+ */
+#ifndef MPHX_H
+#define MPHX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define MPHX_API __attribute__((visibility("default")))
+#else
+#define MPHX_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPHX_OK 0
+#define MPHX_EINVAL (-1)
+#define MPHX_ERANGE (-2)
+#define MPHX_ENOMEM (-3)
+#define MPHX_EDEVICE (-4)
+#define MPHX_ECORE 1
+#define MPHX_EDUP 2
+
+/* round[] value of an edge that stays in the 2-core */
+#define MPHX_ROUND_CORE 0xFFFFFFFFu
+/* largest degree a vertex may reach (degrees are 8-bit quantities) */
+#define MPHX_MAX_DEGREE 255u
+
+typedef struct mphx_peel_info {
+    uint64_t n_peeled;   /* edges removed; n - n_peeled edges form the 2-core */
+    uint32_t n_rounds;   /* number of non-empty layers */
+    uint32_t reserved;
+} mphx_peel_info;
+
+typedef struct mphx_mphf_info {
+    uint64_t P;          /* vertices per part */
+    uint64_t m;          /* 3P vertices */
+    uint64_t seed_used;  /* seed of the successful (or last) try */
+    uint32_t tries;      /* tries made: seed, seed+1, ... */
+    uint32_t n_rounds;   /* peeling rounds of the last try */
+    uint64_t n_core;     /* 2-core edges left on the last try (0 on success) */
+} mphx_mphf_info;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+MPHX_API const char* mphx_last_error(void);
+
+/* Vertices per part, P = ceil(n * gamma_num / (3 * gamma_den)) (Section 3: gamma*n vertices,
+ * Section 4.3: three equal parts). */
+MPHX_API uint64_t mphx_part_size(uint64_t n, uint32_t gamma_num, uint32_t gamma_den);
+
+/* ---------------------------------------------------------------------------------------
+ * Peeling (Section 1 definition of a peeling order and 2-core; Section 4.2 layered peeling;
+ * Section 4.1 packed incidence lists).
+ *
+ * Synchronous rounds: round r removes every edge that has a vertex of degree 1 at the start
+ * of round r.  Outputs, per edge e (all (dev), length n):
+ *   round[e]     round that removed e, or MPHX_ROUND_CORE if e is in the 2-core;
+ *   core_mask[e] 1 if e is in the 2-core, else 0;
+ *   hinge[e]     lowest tuple position (0..2) among e's vertices that had degree 1 at the
+ *                start of its round; 0xFF for 2-core edges.  May be NULL;
+ *   order        edge ids sorted by round, ascending id inside a round, then the 2-core
+ *                edges in ascending id (a peeling order of the peeled prefix).
+ * Input edges (dev): n x 3 row-major uint32 vertex ids, each < m, three distinct ids per
+ * edge.  n < 2^32, m <= 2^32.  Duplicate edges are legal (they end in the 2-core).
+ * A non-empty 2-core is a result, not an error.
+ * Errors: MPHX_EINVAL (null pointer, vertex >= m, a repeated vertex in an edge, sizes out of
+ * range, misaligned workspace), MPHX_ERANGE (a degree above 255, or more rounds than the
+ * workspace holds: mphx_peel_workspace_bytes reserves min(n, 2^22) + 2 rounds),
+ * MPHX_ENOMEM (ws_bytes too small), MPHX_EDEVICE.
+ * ws (dev): at least mphx_peel_workspace_bytes(n, m) bytes, 256-byte aligned, contents
+ * ignored on entry.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API size_t mphx_peel_workspace_bytes(uint64_t n, uint64_t m);
+MPHX_API int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, uint32_t* round,
+              uint8_t* core_mask, uint8_t* hinge, void* ws, size_t ws_bytes, void* stream,
+              mphx_peel_info* info /* host, may be NULL */);
+
+/* ---------------------------------------------------------------------------------------
+ * MWHC minimal perfect hash build (Section 3): hash the keys to a tripartite 3-hypergraph,
+ * peel it (retrying with seed+1, seed+2, ... while a 2-core remains, up to max_tries),
+ * assign g in {0,1,2} to the hinge vertices by backward substitution along the layers in
+ * reverse round order (Section 4.3, "Avoiding backward scans"), and build the ranking table.
+ *
+ * Outputs (dev, caller-allocated):
+ *   codes  ceil(m/32) uint64 words; vertex v's 2-bit code sits at bits 2*(v%32) of word
+ *          v/32: 0 = not a hinge, 1 or 2 = hinge with g = 1 or 2, 3 = hinge with g = 0;
+ *   rank   ceil(m/512) uint64; rank[b] = number of hinge vertices in [0, 512*b).
+ * The MPHF of a key with edge (v0, v1, v2) is rank(v_i), i = (g0 + g1 + g2) mod 3 with
+ * g = code mod 3, rank(h) = rank[h/512] + non-zero codes in [512*(h/512), h)  (Section 5
+ * broadword ranking); it maps the n keys onto [0, n) bijectively.
+ * gamma = gamma_num / gamma_den (1.23 = 123/100).  max_tries >= 1.
+ * Byte-string keys: bytes (dev, 4-byte aligned), offs (dev) n+1 uint64 offsets, key i is
+ * bytes[offs[i], offs[i+1]).
+ * Errors: as mphx_peel, plus MPHX_ECORE (a 2-core remained on every try; info->n_core says
+ * how large on the last) and MPHX_EDUP (on the last try the 2-core held two identical edges
+ * from equal keys, which no seed can separate).
+ * ws (dev): at least mphx_mphf_workspace_bytes(n, ...) bytes, 256-byte aligned.
+ * --------------------------------------------------------------------------------------- */
+#define MPHX_KEYS_U64 0
+#define MPHX_KEYS_STR 1
+MPHX_API size_t mphx_mphf_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, int key_kind);
+MPHX_API int mphx_mphf_build_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gamma_num,
+                        uint32_t gamma_den, uint32_t max_tries, uint64_t* codes, uint64_t* rank,
+                        void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_mphf_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed,
+                        uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* codes,
+                        uint64_t* rank, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
+
+/* Evaluate a built MPHF (Section 3 definition; Section 5 lookup): out[i] = f(key i) (dev,
+ * n uint64).  P and seed are the build's info->P and info->seed_used.  Enqueue only. */
+MPHX_API int mphx_mphf_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                         const uint64_t* keys, uint64_t n, uint64_t* out, void* stream);
+MPHX_API int mphx_mphf_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                         const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
+                         void* stream);
+
+/* Hash keys to edges (Section 3 / Section 4.3), edges (dev) n x 3 uint32.  Enqueue only. */
+MPHX_API int mphx_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
+                  void* stream);
+MPHX_API int mphx_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
+                  uint32_t* edges, void* stream);
+
+/* Check that vals (dev, n uint64) is a permutation of [0, n) (the MPHF definition,
+ * Section 1).  scratch (dev, 256-byte aligned) must hold mphx_bijection_scratch_bytes(n)
+ * bytes.  Returns the number of out-of-range or repeated values in *n_bad (host).
+ * Synchronises the stream. */
+MPHX_API size_t mphx_bijection_scratch_bytes(uint64_t n);
+MPHX_API int mphx_check_bijection(const uint64_t* vals, uint64_t n, void* scratch, uint64_t* n_bad,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Synthetic key sets on the device (benchmark inputs; the same definitions as the host-side
+ * generators that the tests use).  GAMMA and fin as above; S(s, t) = fin(s + t*GAMMA).
+ *   u64 keys:     key_i = S(gen_seed, i + 1), i in [start, start + n).
+ *   string keys:  with x_i the u64 key i: length = qtable[S(x_i, 1) >> 48]; bytes 0..4 are
+ *                 0x20 + the base-95 digits of i (least significant first); byte j >= 5 is
+ *                 0x20 + ((b * 95) >> 8) with b byte (j-5)%8 (little-endian) of S(x_i, 2 + (j-5)/8).
+ * mphx_gen_str_lengths writes the n lengths (dev uint32) and mphx_gen_str_offsets their
+ * exclusive prefix sums (dev, n+1 uint64; scratch (dev) >= mphx_scan_scratch_bytes(n+1));
+ * mphx_gen_str_bytes then fills bytes (dev) from the offsets.  qtable (dev): 65536 uint16.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API int mphx_gen_keys_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, void* stream);
+MPHX_API int mphx_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start,
+                         const uint16_t* qtable, void* stream);
+MPHX_API size_t mphx_scan_scratch_bytes(uint64_t count);
+MPHX_API int mphx_gen_str_offsets(const uint32_t* lens, uint64_t n, uint64_t* offs, void* scratch,
+                         size_t scratch_bytes, void* stream);
+MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t gen_seed,
+                       uint64_t start, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Tuning and diagnostics.
+ * mphx_set_option / mphx_get_option (process-wide):
+ *   "record"      0 = per-vertex record {XOR of incident edge ids, degree} updated with two
+ *                 32-bit atomics (Section 4.1, labelled XOR trick); 1 = {degree, sum of
+ *                 incident edge ids} updated with one 64-bit atomic add (the same packed
+ *                 incidence list over the group Z/2^40 instead of XOR).  Results identical.
+ *   "grid"        blocks per launch of the grid-stride peeling kernels (0 = automatic).
+ *   "round_batch" peeling rounds enqueued between two checks of the termination flag.
+ * Returns MPHX_EINVAL for an unknown key or value.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API int mphx_set_option(const char* key, int64_t value);
+MPHX_API int64_t mphx_get_option(const char* key);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPHX_H */

@@ -1,0 +1,278 @@
+"""ctypes binding of libmphx.so (include/mphx.h): argument marshalling only.
+
+torch provides device memory and the current stream; every step of the path runs in the
+library's HIP kernels.  There is no CPU fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # loads the HIP runtime first, so the library binds to the same one
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmphx.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ECORE, EDUP = 0, -1, -2, -3, -4, 1, 2
+ROUND_CORE = 0xFFFFFFFF
+KEYS_U64, KEYS_STR = 0, 1
+_NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECORE: "ECORE", EDUP: "EDUP"}
+
+
+class MphxError(RuntimeError):
+    def __init__(self, status: int, message: str, info=None):
+        super().__init__(f"{_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.info = info
+
+
+class PeelInfo(C.Structure):
+    _fields_ = [("n_peeled", C.c_uint64), ("n_rounds", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class MphfInfo(C.Structure):
+    _fields_ = [("P", C.c_uint64), ("m", C.c_uint64), ("seed_used", C.c_uint64), ("tries", C.c_uint32),
+                ("n_rounds", C.c_uint32), ("n_core", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+_vp, _u64, _u32, _i32, _sz = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int, C.c_size_t
+_SIGS = {
+    "mphx_last_error": (C.c_char_p, []),
+    "mphx_part_size": (_u64, [_u64, _u32, _u32]),
+    "mphx_peel_workspace_bytes": (_sz, [_u64, _u64]),
+    "mphx_peel": (_i32, [_vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp, _sz, _vp, C.POINTER(PeelInfo)]),
+    "mphx_mphf_workspace_bytes": (_sz, [_u64, _u32, _u32, _i32]),
+    "mphx_mphf_build_u64": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
+    "mphx_mphf_build_str": (_i32, [_vp, _vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp,
+                                   C.POINTER(MphfInfo)]),
+    "mphx_mphf_lookup_u64": (_i32, [_vp, _vp, _u64, _u64, _vp, _u64, _vp, _vp]),
+    "mphx_mphf_lookup_str": (_i32, [_vp, _vp, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
+    "mphx_hash_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp]),
+    "mphx_hash_str": (_i32, [_vp, _vp, _u64, _u64, _u64, _vp, _vp]),
+    "mphx_bijection_scratch_bytes": (_sz, [_u64]),
+    "mphx_check_bijection": (_i32, [_vp, _u64, _vp, C.POINTER(C.c_uint64), _vp]),
+    "mphx_gen_keys_u64": (_i32, [_vp, _u64, _u64, _u64, _vp]),
+    "mphx_gen_str_lengths": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp]),
+    "mphx_scan_scratch_bytes": (_sz, [_u64]),
+    "mphx_gen_str_offsets": (_i32, [_vp, _u64, _vp, _vp, _sz, _vp]),
+    "mphx_gen_str_bytes": (_i32, [_vp, _vp, _u64, _u64, _u64, _vp]),
+    "mphx_set_option": (_i32, [C.c_char_p, C.c_int64]),
+    "mphx_get_option": (C.c_int64, [C.c_char_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1312_0526_amd.build`")
+        h = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _err(status, info=None):
+    msg = lib().mphx_last_error().decode(errors="replace")
+    raise MphxError(status, msg, info)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _check(t, dtype, name, numel=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# ------------------------------------------------------------------------------------------
+def set_option(key: str, value: int) -> None:
+    rc = lib().mphx_set_option(key.encode(), int(value))
+    if rc:
+        _err(rc)
+
+
+def get_option(key: str) -> int:
+    return int(lib().mphx_get_option(key.encode()))
+
+
+def part_size(n: int, gamma=(123, 100)) -> int:
+    return int(lib().mphx_part_size(n, gamma[0], gamma[1]))
+
+
+def peel(edges: torch.Tensor, m: int, with_hinge: bool = True) -> dict:
+    """Layered peel of an n x 3 uint32 edge list (device).  Returns device tensors
+    order/round (int32 views of uint32 data), core_mask/hinge (uint8) and host counts."""
+    if edges.dim() != 2 or edges.shape[1] != 3:
+        raise ValueError("edges must be n x 3")
+    _check(edges, torch.int32, "edges")
+    n = edges.shape[0]
+    dev = edges.device
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    rnd = torch.empty(n, dtype=torch.int32, device=dev)
+    core = torch.empty(n, dtype=torch.uint8, device=dev)
+    hinge = torch.empty(n, dtype=torch.uint8, device=dev) if with_hinge else None
+    ws = _workspace(lib().mphx_peel_workspace_bytes(n, m), dev)
+    info = PeelInfo()
+    rc = lib().mphx_peel(_ptr(edges), n, m, _ptr(order), _ptr(rnd), _ptr(core), _ptr(hinge), _ptr(ws), ws.numel(),
+                         _stream(dev), C.byref(info))
+    if rc:
+        _err(rc)
+    return dict(order=order, round=rnd, core_mask=core, hinge=hinge, n_peeled=int(info.n_peeled),
+                n_rounds=int(info.n_rounds))
+
+
+def _mphf_outputs(n, gamma, kind, dev):
+    P = part_size(n, gamma)
+    m = 3 * P
+    codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
+    rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
+    ws = _workspace(lib().mphx_mphf_workspace_bytes(n, gamma[0], gamma[1], kind), dev)
+    return P, m, codes, rank, ws
+
+
+def _result(codes, rank, info, m):
+    d = info.as_dict()
+    d["codes"] = codes[: (m + 31) // 32]
+    d["rank"] = rank[: (m + 511) // 512]
+    return d
+
+
+def mphf_build_u64(keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64, ws=None) -> dict:
+    _check(keys, torch.int64, "keys")
+    n = keys.numel()
+    P, m, codes, rank, ws_new = _mphf_outputs(n, gamma, KEYS_U64, keys.device)
+    ws = ws_new if ws is None else ws
+    info = MphfInfo()
+    rc = lib().mphx_mphf_build_u64(_ptr(keys), n, seed, gamma[0], gamma[1], max_tries, _ptr(codes), _ptr(rank),
+                                   _ptr(ws), ws.numel(), _stream(keys.device), C.byref(info))
+    if rc:
+        _err(rc, info.as_dict())
+    return _result(codes, rank, info, m)
+
+
+def mphf_build_str(data: torch.Tensor, offs: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64,
+                   ws=None) -> dict:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    P, m, codes, rank, ws_new = _mphf_outputs(n, gamma, KEYS_STR, data.device)
+    ws = ws_new if ws is None else ws
+    info = MphfInfo()
+    rc = lib().mphx_mphf_build_str(_ptr(data), _ptr(offs), n, seed, gamma[0], gamma[1], max_tries, _ptr(codes),
+                                   _ptr(rank), _ptr(ws), ws.numel(), _stream(data.device), C.byref(info))
+    if rc:
+        _err(rc, info.as_dict())
+    return _result(codes, rank, info, m)
+
+
+def mphf_workspace_bytes(n: int, gamma=(123, 100), kind: int = KEYS_U64) -> int:
+    return int(lib().mphx_mphf_workspace_bytes(n, gamma[0], gamma[1], kind))
+
+
+def lookup_u64(codes, rank, P: int, seed: int, keys: torch.Tensor) -> torch.Tensor:
+    _check(keys, torch.int64, "keys")
+    out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    rc = lib().mphx_mphf_lookup_u64(_ptr(codes), _ptr(rank), P, seed, _ptr(keys), keys.numel(), _ptr(out),
+                                    _stream(keys.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+def lookup_str(codes, rank, P: int, seed: int, data: torch.Tensor, offs: torch.Tensor) -> torch.Tensor:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    out = torch.empty(n, dtype=torch.int64, device=data.device)
+    rc = lib().mphx_mphf_lookup_str(_ptr(codes), _ptr(rank), P, seed, _ptr(data), _ptr(offs), n, _ptr(out),
+                                    _stream(data.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+def hash_u64(keys: torch.Tensor, seed: int, P: int) -> torch.Tensor:
+    _check(keys, torch.int64, "keys")
+    edges = torch.empty((keys.numel(), 3), dtype=torch.int32, device=keys.device)
+    rc = lib().mphx_hash_u64(_ptr(keys), keys.numel(), seed, P, _ptr(edges), _stream(keys.device))
+    if rc:
+        _err(rc)
+    return edges
+
+
+def hash_str(data: torch.Tensor, offs: torch.Tensor, seed: int, P: int) -> torch.Tensor:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    edges = torch.empty((n, 3), dtype=torch.int32, device=data.device)
+    rc = lib().mphx_hash_str(_ptr(data), _ptr(offs), n, seed, P, _ptr(edges), _stream(data.device))
+    if rc:
+        _err(rc)
+    return edges
+
+
+def check_bijection(vals: torch.Tensor) -> int:
+    _check(vals, torch.int64, "vals")
+    n = vals.numel()
+    scratch = _workspace(lib().mphx_bijection_scratch_bytes(n), vals.device)
+    bad = C.c_uint64(0)
+    rc = lib().mphx_check_bijection(_ptr(vals), n, _ptr(scratch), C.byref(bad), _stream(vals.device))
+    if rc:
+        _err(rc)
+    return int(bad.value)
+
+
+def gen_keys_u64(n: int, gen_seed: int = 0, start: int = 0, device="cuda") -> torch.Tensor:
+    keys = torch.empty(n, dtype=torch.int64, device=device)
+    rc = lib().mphx_gen_keys_u64(_ptr(keys), n, gen_seed, start, _stream(keys.device))
+    if rc:
+        _err(rc)
+    return keys
+
+
+def gen_str_keys(n: int, qtable: torch.Tensor, gen_seed: int = 0, start: int = 0, device="cuda"):
+    """Device-generated string keys; qtable is the 65536-entry uint16 length table (as int16)."""
+    _check(qtable, torch.int16, "qtable", 1 << 16)
+    lens = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    dev = lens.device
+    rc = lib().mphx_gen_str_lengths(_ptr(lens), n, gen_seed, start, _ptr(qtable), _stream(dev))
+    if rc:
+        _err(rc)
+    offs = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    scratch = _workspace(lib().mphx_scan_scratch_bytes(n + 1), dev)
+    rc = lib().mphx_gen_str_offsets(_ptr(lens), n, _ptr(offs), _ptr(scratch), scratch.numel(), _stream(dev))
+    if rc:
+        _err(rc)
+    del lens
+    total = int(offs[-1].item())
+    data = torch.empty(max(total, 4), dtype=torch.uint8, device=dev)
+    rc = lib().mphx_gen_str_bytes(_ptr(data), _ptr(offs), n, gen_seed, start, _stream(dev))
+    if rc:
+        _err(rc)
+    return data, offs

@@ -1,0 +1,602 @@
+// Host orchestration of the C ABI declared in include/mphx.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "mphx.h"
+
+using namespace mphx;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Options {
+    std::atomic<int> record{1};        // 0 = XOR record, 1 = sum record
+    std::atomic<int> grid{0};          // 0 = automatic
+    std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
+};
+Options g_opt;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                             \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(MPHX_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));             \
+    } while (0)
+
+constexpr uint64_t kRoundCapMax = 1ull << 22;
+
+uint64_t round_cap(uint64_t n) { return std::min<uint64_t>(std::max<uint64_t>(n, 1), kRoundCapMax) + 1; }
+
+// Bump allocator over the caller's workspace; with base == nullptr it only measures.
+struct Carve {
+    uint8_t* base;
+    size_t off = 0;
+    explicit Carve(void* b) : base((uint8_t*)b) {}
+    template <class T>
+    T* take(uint64_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += (size_t)count * sizeof(T);
+        return p;
+    }
+};
+
+struct PeelLayout {
+    Ctrl* ctrl;
+    uint64_t *fstart, *lstart, *rec;
+    uint32_t *front, *layer, *hmask32, *tilehist;
+    void* scan;
+    size_t scan_bytes;
+};
+
+void layout_peel(Carve& c, uint64_t n, uint64_t m, PeelLayout& L)
+{
+    uint64_t rcap = round_cap(n);
+    L.ctrl = c.take<Ctrl>(1);
+    L.fstart = c.take<uint64_t>(rcap + 2);
+    L.lstart = c.take<uint64_t>(rcap + 2);
+    L.rec = c.take<uint64_t>(m);
+    L.front = c.take<uint32_t>(m);
+    L.layer = c.take<uint32_t>(n);
+    L.hmask32 = c.take<uint32_t>((n + 3) / 4);
+    uint64_t hist_entries = 256 * sort_tiles(n);
+    L.tilehist = c.take<uint32_t>(hist_entries);
+    L.scan_bytes = scan_scratch_bytes(hist_entries);
+    L.scan = c.take<uint8_t>(L.scan_bytes);
+}
+
+struct MphfLayout {
+    Ctrl* ctrl;
+    uint64_t *fstart, *lstart, *rec;
+    uint32_t *edges, *front, *layer, *hmask32, *bcount;
+    void* scan;
+    size_t scan_bytes;
+};
+
+void layout_mphf(Carve& c, uint64_t n, uint64_t m, MphfLayout& L)
+{
+    uint64_t rcap = round_cap(n);
+    L.ctrl = c.take<Ctrl>(1);
+    L.fstart = c.take<uint64_t>(rcap + 2);
+    L.lstart = c.take<uint64_t>(rcap + 2);
+    L.edges = c.take<uint32_t>(3 * n);
+    L.rec = c.take<uint64_t>(m);
+    L.front = c.take<uint32_t>(std::max<uint64_t>(m, (m + 3) / 4));  // also the byte codes after peeling
+    L.layer = c.take<uint32_t>(n);
+    L.hmask32 = c.take<uint32_t>((n + 3) / 4);
+    uint64_t nblocks = (m + 511) / 512;
+    L.bcount = c.take<uint32_t>(nblocks);
+    L.scan_bytes = scan_scratch_bytes(nblocks);
+    L.scan = c.take<uint8_t>(L.scan_bytes);
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255) == 0; }
+
+int read_ctrl(Ctrl* dctrl, Ctrl& h, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(&h, dctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MPHX_OK;
+}
+
+unsigned auto_grid(uint64_t work)
+{
+    int g = g_opt.grid.load();
+    if (g > 0) return (unsigned)g;
+    uint64_t b = (work + 255) / 256;
+    return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 64), 8192);
+}
+
+// Enqueue rounds in growing batches until a round finds an empty layer.  On return
+// h.nrounds holds the number of non-empty layers and h.ltail the number of peeled edges.
+int run_rounds(PeelState& st, Ctrl& h, uint64_t first_front, hipStream_t s)
+{
+    uint32_t r = 0;
+    uint32_t batch = (uint32_t)std::max(1, g_opt.round_batch.load());
+    uint64_t last_front = first_front;
+    for (;;) {
+        uint64_t upto = std::min<uint64_t>((uint64_t)r + batch, st.rcap);
+        st.grid_cap = auto_grid(last_front);
+        for (; r < upto; r++)
+            HIP_TRY(launch_round(st, r, s));
+        uint64_t fs = 0;
+        HIP_TRY(hipMemcpyAsync(&fs, st.fstart + r, sizeof fs, hipMemcpyDeviceToHost, s));
+        int rc = read_ctrl(st.ctrl, h, s);
+        if (rc) return rc;
+        if (h.nrounds != 0xFFFFFFFFu) return MPHX_OK;
+        if (r >= st.rcap)
+            return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
+        // size of the frontier the next round starts from; later rounds of the batch may be
+        // larger, which only costs them more grid-stride iterations
+        last_front = h.ftail - std::min<uint64_t>(fs, h.ftail);
+        batch = std::min<uint32_t>(batch * 2, 64);
+    }
+}
+
+int check_build_errors(Ctrl* dctrl, hipStream_t s, uint64_t& first_front)
+{
+    Ctrl h;
+    int rc = read_ctrl(dctrl, h, s);
+    if (rc) return rc;
+    first_front = h.ftail;
+    if (h.err & kErrBadEdge)
+        return fail(MPHX_EINVAL, "edge with a vertex id >= m or a repeated vertex");
+    if (h.err & kErrDegree)
+        return fail(MPHX_ERANGE, "a vertex has degree above %u", MPHX_MAX_DEGREE);
+    return MPHX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mphx_last_error(void) { return g_err.c_str(); }
+
+uint64_t mphx_part_size(uint64_t n, uint32_t gamma_num, uint32_t gamma_den)
+{
+    if (gamma_den == 0) return 0;
+    unsigned __int128 num = (unsigned __int128)n * gamma_num;
+    unsigned __int128 den = (unsigned __int128)3 * gamma_den;
+    return (uint64_t)((num + den - 1) / den);
+}
+
+int mphx_set_option(const char* key, int64_t value)
+{
+    if (!key) return fail(MPHX_EINVAL, "null option key");
+    if (!strcmp(key, "record")) {
+        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "record must be 0 or 1");
+        g_opt.record = (int)value;
+    } else if (!strcmp(key, "grid")) {
+        if (value < 0 || value > (1 << 20)) return fail(MPHX_EINVAL, "grid out of range");
+        g_opt.grid = (int)value;
+    } else if (!strcmp(key, "round_batch")) {
+        if (value < 1 || value > 4096) return fail(MPHX_EINVAL, "round_batch out of range");
+        g_opt.round_batch = (int)value;
+    } else {
+        return fail(MPHX_EINVAL, "unknown option '%s'", key);
+    }
+    return MPHX_OK;
+}
+
+int64_t mphx_get_option(const char* key)
+{
+    if (!key) return MPHX_EINVAL;
+    if (!strcmp(key, "record")) return g_opt.record;
+    if (!strcmp(key, "grid")) return g_opt.grid;
+    if (!strcmp(key, "round_batch")) return g_opt.round_batch;
+    fail(MPHX_EINVAL, "unknown option '%s'", key);
+    return MPHX_EINVAL;
+}
+
+size_t mphx_peel_workspace_bytes(uint64_t n, uint64_t m)
+{
+    Carve c(nullptr);
+    PeelLayout L;
+    layout_peel(c, n, m, L);
+    return c.off;
+}
+
+int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, uint32_t* round, uint8_t* core_mask,
+              uint8_t* hinge, void* ws, size_t ws_bytes, void* stream, mphx_peel_info* info)
+{
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (n >= 0xFFFFFFFFull || m > 0x100000000ull)
+        return fail(MPHX_EINVAL, "n must be < 2^32 - 1 and m <= 2^32");
+    if (n > 0 && (!edges || !order || !round || !core_mask))
+        return fail(MPHX_EINVAL, "null pointer argument");
+    if (!ws || !aligned256(ws))
+        return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < mphx_peel_workspace_bytes(n, m))
+        return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, mphx_peel_workspace_bytes(n, m));
+    if (info) memset(info, 0, sizeof *info);
+    if (n == 0) return MPHX_OK;
+
+    Carve c(ws);
+    PeelLayout L;
+    layout_peel(c, n, m, L);
+    const int record = g_opt.record.load();
+
+    HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
+    HIP_TRY(launch_zero(L.hmask32, ((n + 3) / 4) * 4, s));
+    HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
+    HIP_TRY(launch_fill_u32(round, n, kRoundCore, s));
+    HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, record, s));
+    HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+    uint64_t f0 = 0;
+    int rc = check_build_errors(L.ctrl, s, f0);
+    if (rc) return rc;
+
+    PeelState st{};
+    st.edges = edges;
+    st.n = n;
+    st.m = m;
+    st.P = 0;
+    st.tripartite = false;
+    st.record = record;
+    st.rec = L.rec;
+    st.front = L.front;
+    st.layer = L.layer;
+    st.hmask32 = L.hmask32;
+    st.fstart = L.fstart;
+    st.lstart = L.lstart;
+    st.round_out = round;
+    st.ctrl = L.ctrl;
+    st.rcap = round_cap(n);
+    Ctrl h;
+    rc = run_rounds(st, h, f0, s);
+    if (rc) return rc;
+
+    HIP_TRY(launch_peel_finalize(round, L.hmask32, n, core_mask, hinge, s));
+    HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.layer, L.tilehist, L.scan, L.scan_bytes, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->n_peeled = h.ltail;
+        info->n_rounds = h.nrounds;
+    }
+    return MPHX_OK;
+}
+
+size_t mphx_mphf_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, int key_kind)
+{
+    (void)key_kind;
+    uint64_t m = 3 * mphx_part_size(n, gamma_num, gamma_den);
+    Carve c(nullptr);
+    MphfLayout L;
+    layout_mphf(c, n, m, L);
+    return c.off;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct KeySrc {
+    int kind;  // MPHX_KEYS_U64 / MPHX_KEYS_STR
+    const uint64_t* keys;
+    const uint8_t* bytes;
+    const uint64_t* offs;
+};
+
+// Are the keys of edges a and b equal?  (Only called on the failure path.)
+int keys_equal(const KeySrc& k, uint64_t a, uint64_t b, bool& eq, hipStream_t s)
+{
+    if (k.kind == MPHX_KEYS_U64) {
+        uint64_t x = 0, y = 0;
+        HIP_TRY(hipMemcpyAsync(&x, k.keys + a, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&y, k.keys + b, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        eq = x == y;
+        return MPHX_OK;
+    }
+    uint64_t oa[2], ob[2];
+    HIP_TRY(hipMemcpyAsync(oa, k.offs + a, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(ob, k.offs + b, 16, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (oa[1] - oa[0] != ob[1] - ob[0]) {
+        eq = false;
+        return MPHX_OK;
+    }
+    std::vector<uint8_t> x(oa[1] - oa[0]), y(ob[1] - ob[0]);
+    if (!x.empty()) {
+        HIP_TRY(hipMemcpyAsync(x.data(), k.bytes + oa[0], x.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(y.data(), k.bytes + ob[0], y.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    eq = x == y;
+    return MPHX_OK;
+}
+
+// After the last failed try: do identical core edges come from equal keys?
+int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, bool& dup, hipStream_t s)
+{
+    dup = false;
+    std::vector<uint32_t> hm((n + 3) / 4);
+    std::vector<uint32_t> edges(3 * n);
+    HIP_TRY(hipMemcpyAsync(hm.data(), L.hmask32, hm.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(edges.data(), L.edges, edges.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<uint32_t> core;
+    for (uint64_t e = 0; e < n; e++)
+        if (((hm[e >> 2] >> (8 * (e & 3))) & 0xFF) == 0)
+            core.push_back((uint32_t)e);
+    std::sort(core.begin(), core.end(), [&](uint32_t a, uint32_t b) {
+        for (int q = 0; q < 3; q++)
+            if (edges[3ull * a + q] != edges[3ull * b + q]) return edges[3ull * a + q] < edges[3ull * b + q];
+        return a < b;
+    });
+    for (size_t i = 0; i + 1 < core.size() && !dup; i++) {
+        uint32_t a = core[i], b = core[i + 1];
+        if (edges[3ull * a] == edges[3ull * b] && edges[3ull * a + 1] == edges[3ull * b + 1] &&
+            edges[3ull * a + 2] == edges[3ull * b + 2]) {
+            bool eq = false;
+            int rc = keys_equal(k, a, b, eq, s);
+            if (rc) return rc;
+            dup = eq;
+        }
+    }
+    return MPHX_OK;
+}
+
+int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+               uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
+{
+    g_err.clear();
+    if (gnum == 0 || gden == 0) return fail(MPHX_EINVAL, "gamma must be a positive fraction");
+    if (max_tries == 0) return fail(MPHX_EINVAL, "max_tries must be >= 1");
+    if (n >= 0xFFFFFFFFull) return fail(MPHX_EINVAL, "n must be < 2^32 - 1");
+    const uint64_t P = mphx_part_size(n, gnum, gden);
+    const uint64_t m = 3 * P;
+    if (m > 0x100000000ull) return fail(MPHX_EINVAL, "3P = %llu vertices exceed 2^32", (unsigned long long)m);
+    if (n > 0) {
+        if (k.kind == MPHX_KEYS_U64 && !k.keys) return fail(MPHX_EINVAL, "null keys");
+        if (k.kind == MPHX_KEYS_STR && (!k.bytes || !k.offs)) return fail(MPHX_EINVAL, "null bytes/offs");
+        if (k.kind == MPHX_KEYS_STR && ((uintptr_t)k.bytes & 3)) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+        if (!codes || !rank) return fail(MPHX_EINVAL, "null output");
+    }
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    size_t need = mphx_mphf_workspace_bytes(n, gnum, gden, k.kind);
+    if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if (info) {
+        memset(info, 0, sizeof *info);
+        info->P = P;
+        info->m = m;
+        info->seed_used = seed;
+    }
+    if (n == 0) {
+        if (info) info->tries = 1;
+        return MPHX_OK;
+    }
+
+    Carve c(ws);
+    MphfLayout L;
+    layout_mphf(c, n, m, L);
+    const int record = g_opt.record.load();
+
+    PeelState st{};
+    st.edges = L.edges;
+    st.n = n;
+    st.m = m;
+    st.P = P;
+    st.tripartite = true;
+    st.record = record;
+    st.rec = L.rec;
+    st.front = L.front;
+    st.layer = L.layer;
+    st.hmask32 = L.hmask32;
+    st.fstart = L.fstart;
+    st.lstart = L.lstart;
+    st.round_out = nullptr;
+    st.ctrl = L.ctrl;
+    st.rcap = round_cap(n);
+
+    Ctrl h{};
+    uint32_t t = 0;
+    bool peeled = false;
+    for (t = 0; t < max_tries; t++) {
+        uint64_t sd = seed + t;
+        HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
+        HIP_TRY(launch_zero(L.hmask32, ((n + 3) / 4) * 4, s));
+        HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
+        if (k.kind == MPHX_KEYS_U64)
+            HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
+        else
+            HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
+        HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+        uint64_t f0 = 0;
+        int rc = check_build_errors(L.ctrl, s, f0);
+        if (rc) {
+            if (info) { info->tries = t + 1; info->seed_used = sd; }
+            return rc;
+        }
+        rc = run_rounds(st, h, f0, s);
+        if (rc) return rc;
+        if (info) {
+            info->tries = t + 1;
+            info->seed_used = sd;
+            info->n_rounds = h.nrounds;
+            info->n_core = n - h.ltail;
+        }
+        if (h.ltail == n) {
+            peeled = true;
+            break;
+        }
+    }
+    if (!peeled) {
+        bool dup = false;
+        int rc = detect_duplicates(k, L, n, dup, s);
+        if (rc) return rc;
+        if (dup) return fail(MPHX_EDUP, "duplicate keys: identical edges from equal keys stay in the 2-core");
+        return fail(MPHX_ECORE, "2-core of %llu edges after %u tries", (unsigned long long)(n - h.ltail), max_tries);
+    }
+
+    // Assignment in reverse round order with exact grids from the layer bounds.
+    std::vector<uint64_t> lb(h.nrounds + 1);
+    HIP_TRY(hipMemcpyAsync(lb.data(), L.lstart, lb.size() * 8, hipMemcpyDeviceToHost, s));
+    uint8_t* code8 = reinterpret_cast<uint8_t*>(L.front);
+    HIP_TRY(launch_zero(code8, m, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t r = (int64_t)h.nrounds - 1; r >= 0; r--) {
+        uint64_t cnt = lb[r + 1] - lb[r];
+        HIP_TRY(launch_assign_round(L.edges, L.layer, L.hmask32, L.lstart, (uint32_t)r, cnt, code8, 16384, s));
+    }
+    HIP_TRY(launch_pack_count(code8, m, codes, L.bcount, s));
+    uint64_t nblocks = (m + 511) / 512;
+    HIP_TRY(launch_scan_u32_to_u64(L.bcount, nblocks, rank, nblocks, L.scan, L.scan_bytes, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MPHX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mphx_mphf_build_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gamma_num, uint32_t gamma_den,
+                        uint32_t max_tries, uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, void* stream,
+                        mphx_mphf_info* info)
+{
+    KeySrc k{MPHX_KEYS_U64, keys, nullptr, nullptr};
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, codes, rank, ws, ws_bytes, (hipStream_t)stream,
+                      info);
+}
+
+int mphx_mphf_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint32_t gamma_num,
+                        uint32_t gamma_den, uint32_t max_tries, uint64_t* codes, uint64_t* rank, void* ws,
+                        size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    KeySrc k{MPHX_KEYS_STR, nullptr, bytes, offs};
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, codes, rank, ws, ws_bytes, (hipStream_t)stream,
+                      info);
+}
+
+int mphx_mphf_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed, const uint64_t* keys,
+                         uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!codes || !rank || !keys || !out || P == 0) return fail(MPHX_EINVAL, "null pointer or P = 0");
+    HIP_TRY(launch_lookup_u64(codes, rank, P, seed, keys, n, out, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_mphf_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed, const uint8_t* bytes,
+                         const uint64_t* offs, uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!codes || !rank || !bytes || !offs || !out || P == 0) return fail(MPHX_EINVAL, "null pointer or P = 0");
+    if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    HIP_TRY(launch_lookup_str(codes, rank, P, seed, bytes, offs, n, out, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!keys || !edges) return fail(MPHX_EINVAL, "null pointer");
+    if (P == 0 || 3 * P > 0x100000000ull) return fail(MPHX_EINVAL, "P out of range");
+    HIP_TRY(launch_hash_u64(keys, n, seed, P, edges, nullptr, nullptr, 0, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
+                  void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!bytes || !offs || !edges) return fail(MPHX_EINVAL, "null pointer");
+    if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    if (P == 0 || 3 * P > 0x100000000ull) return fail(MPHX_EINVAL, "P out of range");
+    HIP_TRY(launch_hash_str(bytes, offs, n, seed, P, edges, nullptr, nullptr, 0, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+size_t mphx_bijection_scratch_bytes(uint64_t n)
+{
+    uint64_t words = (n + 31) / 32;
+    return (size_t)(((words * 4 + 255) & ~255ull) + sizeof(Ctrl));
+}
+
+int mphx_check_bijection(const uint64_t* vals, uint64_t n, void* scratch, uint64_t* n_bad, void* stream)
+{
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (!n_bad) return fail(MPHX_EINVAL, "null n_bad");
+    *n_bad = 0;
+    if (n == 0) return MPHX_OK;
+    if (!vals || !scratch || !aligned256(scratch)) return fail(MPHX_EINVAL, "null or misaligned pointer");
+    // bitmap words first, then one control slot for the violation counter
+    uint64_t words = (n + 31) / 32;
+    uint32_t* bitmap = reinterpret_cast<uint32_t*>(scratch);
+    Ctrl* ctrl = reinterpret_cast<Ctrl*>(reinterpret_cast<uint8_t*>(scratch) + ((words * 4 + 255) & ~255ull));
+    HIP_TRY(launch_zero(bitmap, words * 4, s));
+    HIP_TRY(launch_zero(ctrl, sizeof(Ctrl), s));
+    HIP_TRY(launch_bijection(vals, n, bitmap, ctrl, s));
+    unsigned long long bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, &ctrl->aux, 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_bad = bad;
+    return MPHX_OK;
+}
+
+int mphx_gen_keys_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, void* stream)
+{
+    g_err.clear();
+    if (n && !keys) return fail(MPHX_EINVAL, "null keys");
+    HIP_TRY(launch_gen_u64(keys, n, gen_seed, start, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start, const uint16_t* qtable,
+                         void* stream)
+{
+    g_err.clear();
+    if (n && (!lens || !qtable)) return fail(MPHX_EINVAL, "null pointer");
+    HIP_TRY(launch_gen_str_lengths(lens, n, gen_seed, start, qtable, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+size_t mphx_scan_scratch_bytes(uint64_t count) { return scan_scratch_bytes(count); }
+
+int mphx_gen_str_offsets(const uint32_t* lens, uint64_t n, uint64_t* offs, void* scratch, size_t scratch_bytes,
+                         void* stream)
+{
+    g_err.clear();
+    if (!offs || (n && !lens) || !scratch) return fail(MPHX_EINVAL, "null pointer");
+    if (scratch_bytes < scan_scratch_bytes(n + 1)) return fail(MPHX_ENOMEM, "scan scratch too small");
+    HIP_TRY(launch_scan_u32_to_u64(lens, n, offs, n + 1, scratch, scratch_bytes, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t gen_seed, uint64_t start,
+                       void* stream)
+{
+    g_err.clear();
+    if (n && (!bytes || !offs)) return fail(MPHX_EINVAL, "null pointer");
+    if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    HIP_TRY(launch_gen_str_bytes(bytes, offs, n, gen_seed, start, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+}  // extern "C"

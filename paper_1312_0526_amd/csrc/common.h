@@ -1,0 +1,218 @@
+// Internal device helpers of the gfx950 MWHC build library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mphx {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+constexpr uint32_t kRoundCore = 0xFFFFFFFFu;
+constexpr uint32_t kMaxDegree = 255u;
+constexpr int kWave = 64;
+
+// Error bits raised by kernels into Ctrl::err.
+constexpr uint32_t kErrBadEdge = 1u;  // vertex id >= m or a repeated vertex in an edge
+constexpr uint32_t kErrDegree = 2u;   // a vertex reached degree 256
+
+// Device-side control block of one peeling run (lives in the workspace).
+struct Ctrl {
+    unsigned long long ftail;  // append cursor of the frontier array (all rounds back to back)
+    unsigned long long ltail;  // append cursor of the layer array (all rounds back to back)
+    uint32_t nrounds;          // first round whose layer was empty (UINT32_MAX while running)
+    uint32_t err;              // kErr* bits
+    unsigned long long aux;    // scratch counter (bijection check, duplicate scans)
+    uint64_t pad[28];
+};
+static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte slot");
+
+// SplitMix64 output function (Steele, Lea & Flood 2014; Stafford's Mix13 constants).
+__device__ __forceinline__ uint64_t fin(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// floor(z * p / 2^64), a uniform 64-bit value mapped into [0, p).
+__device__ __forceinline__ uint64_t range_reduce(uint64_t z, uint64_t p) { return __umul64hi(z, p); }
+
+// Tripartite edge of a key with digest (a, b): vertex k in part k.
+__device__ __forceinline__ void edge_of_digest(uint64_t a, uint64_t b, uint64_t P, uint32_t& v0,
+                                               uint32_t& v1, uint32_t& v2)
+{
+    v0 = (uint32_t)range_reduce(fin(a + kGamma), P);
+    v1 = (uint32_t)(P + range_reduce(fin(a + 2 * kGamma), P));
+    v2 = (uint32_t)(2 * P + range_reduce(fin(b + 3 * kGamma), P));
+}
+
+// ----- wave64 helpers ---------------------------------------------------------------------
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t wave_bcast64(uint64_t x, int lane)
+{
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Reserve slots in an append-only array for the active lanes of a wave: lane j asks for
+// c_j in {0, 1, 2} slots (bit0 = first slot, bit1 = second).  One atomic per wave.
+// Returns the first slot of this lane (meaningless if it asked for none).
+__device__ __forceinline__ uint64_t wave_append(unsigned long long* tail, bool want1, bool want2)
+{
+    uint64_t b1 = __ballot(want1);
+    uint64_t b2 = __ballot(want2);
+    uint32_t total = (uint32_t)(__popcll(b1) + __popcll(b2));
+    uint64_t base = 0;
+    if (total) {
+        uint64_t active = __ballot(1);
+        int leader = __ffsll((long long)active) - 1;
+        if ((int)__lane_id() == leader)
+            base = atomicAdd(tail, (unsigned long long)total);
+        base = wave_bcast64(base, leader);
+    }
+    return base + lanes_below(b1) + lanes_below(b2);
+}
+
+// ----- per-vertex packed incidence record (Section 4.1) ----------------------------------
+// Each vertex keeps its degree and a combination of the ids of its incident edges from which
+// the single remaining edge is read off when the degree is 1.
+//
+// RecXor: low 32 bits = XOR of incident edge ids, high 32 bits = degree; AddEdge/DeleteEdge
+//         are a 32-bit atomic XOR plus a 32-bit atomic add/sub on the two halves of one
+//         8-byte word (same cache line).
+// RecSum: bits [40, 64) = degree, bits [0, 40) = sum of incident edge ids; AddEdge/DeleteEdge
+//         are one 64-bit atomic add of +-(2^40 + e).  While the degree is <= 255 the sum stays
+//         below 2^40 and never carries into the degree.
+struct RecXor {
+    static constexpr int kind = 0;
+    __device__ static __forceinline__ uint32_t deg(uint64_t r) { return (uint32_t)(r >> 32); }
+    __device__ static __forceinline__ uint32_t edge(uint64_t r) { return (uint32_t)r; }
+    __device__ static __forceinline__ void add(uint64_t* rec, uint32_t v, uint32_t e)
+    {
+        uint32_t* p = reinterpret_cast<uint32_t*>(rec + v);
+        atomicXor(p, e);
+        atomicAdd(p + 1, 1u);
+    }
+    // returns the degree before the deletion
+    __device__ static __forceinline__ uint32_t del(uint64_t* rec, uint32_t v, uint32_t e)
+    {
+        uint32_t* p = reinterpret_cast<uint32_t*>(rec + v);
+        atomicXor(p, e);
+        return atomicSub(p + 1, 1u);
+    }
+};
+
+struct RecSum {
+    static constexpr int kind = 1;
+    static constexpr uint64_t kOne = 1ull << 40;
+    __device__ static __forceinline__ uint32_t deg(uint64_t r) { return (uint32_t)(r >> 40); }
+    __device__ static __forceinline__ uint32_t edge(uint64_t r) { return (uint32_t)(r & (kOne - 1)); }
+    // returns the degree before the addition (used to detect degree 256)
+    __device__ static __forceinline__ uint32_t add_ret(uint64_t* rec, uint32_t v, uint32_t e)
+    {
+        unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(rec + v),
+                                           (unsigned long long)(kOne + e));
+        return (uint32_t)(old >> 40);
+    }
+    __device__ static __forceinline__ uint32_t del(uint64_t* rec, uint32_t v, uint32_t e)
+    {
+        unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(rec + v),
+                                           (unsigned long long)(0ull - (kOne + e)));
+        return (uint32_t)(old >> 40);
+    }
+};
+
+// Part of a vertex in the tripartite layout.
+__device__ __forceinline__ uint32_t part_of(uint32_t v, uint64_t P)
+{
+    return (uint32_t)((uint64_t)v >= 2 * P ? 2 : ((uint64_t)v >= P ? 1 : 0));
+}
+
+// Claim mask of edge e: one byte per edge, bit k set when the vertex in position k had degree
+// 1 at the start of the edge's round.  Bytes are packed four per 32-bit word for atomicOr.
+__device__ __forceinline__ uint32_t claim_mask(const uint32_t* hmask32, uint32_t e)
+{
+    return (hmask32[e >> 2] >> (8 * (e & 3))) & 0xFFu;
+}
+
+// ---- byte-string keys --------------------------------------------------------------------
+// Aligned 32-bit read of dword q of the byte array; the dword holding the array's last byte
+// is assembled byte by byte so nothing past `total` is touched.
+__device__ __forceinline__ uint32_t load_dword(const uint8_t* bytes, uint64_t q, uint64_t total)
+{
+    uint64_t b = q * 4;
+    if (b + 4 <= total)
+        return *reinterpret_cast<const uint32_t*>(bytes + b);
+    uint32_t x = 0;
+    for (uint32_t t = 0; t < 4; t++)
+        if (b + t < total)
+            x |= (uint32_t)bytes[b + t] << (8 * t);
+    return x;
+}
+
+// 128-bit digest (a, b): per lane, sum of fin(w_j XOR (s_lane + j*GAMMA)) over the key's
+// little-endian 8-byte words (zero padded), then fin(sum XOR s_lane XOR len).  The key's words
+// are rebuilt from aligned dwords with a funnel shift.
+__device__ __forceinline__ void digest_str(const uint8_t* bytes, uint64_t off, uint64_t len, uint64_t total,
+                                           uint64_t sa, uint64_t sb, uint64_t& a, uint64_t& b)
+{
+    uint64_t A = 0, B = 0;
+    const uint64_t nw = (len + 7) >> 3;
+    const uint64_t q0 = off >> 2;
+    const uint32_t sh = (uint32_t)(off & 3) * 8;
+    uint32_t c0 = nw ? load_dword(bytes, q0, total) : 0u;
+    for (uint64_t j = 0; j < nw; j++) {
+        uint32_t c1 = load_dword(bytes, q0 + 2 * j + 1, total);
+        uint32_t c2 = (sh != 0 || j + 1 < nw) ? load_dword(bytes, q0 + 2 * j + 2, total) : 0u;
+        uint64_t lo = (uint64_t)c0 | ((uint64_t)c1 << 32);
+        uint64_t w = sh ? ((lo >> sh) | ((uint64_t)c2 << (64 - sh))) : lo;
+        uint64_t rem = len - 8 * j;
+        if (rem < 8)
+            w &= (1ull << (8 * rem)) - 1;
+        A += fin(w ^ (sa + j * kGamma));
+        B += fin(w ^ (sb + j * kGamma));
+        c0 = c2;
+    }
+    a = fin(A ^ sa ^ len);
+    b = fin(B ^ sb ^ len);
+}
+
+// ----- MPHF evaluation (Section 3 definition, Section 5 broadword ranking) -----------------
+__device__ __forceinline__ uint32_t nz_pairs(uint64_t w)
+{
+    return (uint32_t)__popcll((w | (w >> 1)) & 0x5555555555555555ull);
+}
+
+// One thread per output word: pack 32 codes, count the non-zero ones; 16 words (512
+// vertices) per rank block are summed across 16 lanes.
+__device__ __forceinline__ uint32_t code_at(const uint64_t* codes, uint32_t v)
+{
+    return (uint32_t)(codes[v >> 5] >> (2 * (v & 31))) & 3u;
+}
+
+__device__ __forceinline__ uint64_t rank_of(const uint64_t* codes, const uint64_t* rank, uint32_t h)
+{
+    uint64_t r = rank[h >> 9];
+    const uint64_t w1 = h >> 5;
+    for (uint64_t w = (uint64_t)(h >> 9) * 16; w < w1; w++)
+        r += nz_pairs(codes[w]);
+    uint32_t below = 2 * (h & 31);
+    uint64_t mask = below ? ((1ull << below) - 1) : 0ull;
+    return r + nz_pairs(codes[w1] & mask);
+}
+
+__device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,
+                                              uint32_t v2)
+{
+    uint32_t s = (code_at(codes, v0) % 3 + code_at(codes, v1) % 3 + code_at(codes, v2) % 3) % 3;
+    uint32_t h = s == 0 ? v0 : (s == 1 ? v1 : v2);
+    return rank_of(codes, rank, h);
+}
+
+}  // namespace mphx

@@ -1,0 +1,77 @@
+// Internal host-side launchers of the gfx950 kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace mphx {
+
+// Everything one peeling run needs on the device.
+struct PeelState {
+    const uint32_t* edges;  // n x 3
+    uint64_t n, m, P;       // P = part size when tripartite
+    bool tripartite;
+    int record;             // 0 = RecXor, 1 = RecSum
+    unsigned grid_cap;      // max blocks of the grid-stride round kernels
+    uint64_t* rec;          // m packed records
+    uint32_t* front;        // m: frontiers of all rounds back to back
+    uint32_t* layer;        // n: layers of all rounds back to back
+    uint32_t* hmask32;      // ceil(n/4) words of claim bytes
+    uint64_t* fstart;       // rcap + 2 frontier starts
+    uint64_t* lstart;       // rcap + 2 layer starts
+    uint32_t* round_out;    // nullable: per-edge round
+    Ctrl* ctrl;
+    uint64_t rcap;          // rounds the start arrays can hold
+};
+
+// utilities (scan.hip)
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
+hipError_t launch_ctrl_init(Ctrl* ctrl, uint64_t* fstart, uint64_t* lstart, hipStream_t s);
+size_t scan_scratch_bytes(uint64_t count);
+// exclusive scans; in and out may alias
+hipError_t launch_scan_u32(const uint32_t* in, uint64_t count, uint32_t* out, void* scratch, size_t scratch_bytes,
+                           hipStream_t s);
+// out has count_out entries; input entries past count_in read as 0
+hipError_t launch_scan_u32_to_u64(const uint32_t* in, uint64_t count_in, uint64_t* out, uint64_t count_out,
+                                  void* scratch, size_t scratch_bytes, hipStream_t s);
+
+// hashing and key generation (keys.hip); rec == nullptr hashes only
+hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
+                           uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s);
+hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
+                           uint32_t* edges, uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s);
+hipError_t launch_gen_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, hipStream_t s);
+hipError_t launch_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start,
+                                  const uint16_t* qtable, hipStream_t s);
+hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t gen_seed, uint64_t start,
+                                hipStream_t s);
+
+// peeling (peel.hip)
+hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl, int record,
+                              hipStream_t s);
+hipError_t launch_frontier_init(const uint64_t* rec, uint64_t m, uint32_t* front, Ctrl* ctrl, int record,
+                                hipStream_t s);
+hipError_t launch_round(const PeelState& st, uint32_t r, hipStream_t s);
+hipError_t launch_peel_finalize(const uint32_t* round, const uint32_t* hmask32, uint64_t n, uint8_t* core_mask,
+                                uint8_t* hinge, hipStream_t s);
+uint64_t sort_tiles(uint64_t n);
+hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds, uint32_t* order,
+                             uint32_t* scratch_ids, uint32_t* tilehist, void* scan_scratch, size_t scan_bytes,
+                             hipStream_t s);
+
+// assignment, ranking, lookup (solve.hip)
+hipError_t launch_assign_round(const uint32_t* edges, const uint32_t* layer, const uint32_t* hmask32,
+                               const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint8_t* code8,
+                               unsigned grid_cap, hipStream_t s);
+hipError_t launch_pack_count(const uint8_t* code8, uint64_t m, uint64_t* codes, uint32_t* bcount, hipStream_t s);
+hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                             const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                             const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_bijection(const uint64_t* vals, uint64_t n, uint32_t* bitmap, Ctrl* ctrl, hipStream_t s);
+
+}  // namespace mphx

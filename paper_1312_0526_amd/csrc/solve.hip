@@ -1,0 +1,168 @@
+// Assignment (Section 3, along the layers in reverse round order as in Section 4.3), code
+// packing + rank counts, MPHF evaluation (Section 5 broadword ranking) and the bijection check.
+#include "common.h"
+#include "launch.h"
+
+namespace mphx {
+
+// code8[v]: 0 = not a hinge, 1/2 = hinge with g = 1/2, 3 = hinge with g = 0.
+__device__ __forceinline__ uint32_t g_of_code(uint32_t c) { return c == 3 ? 0u : c; }
+
+// One layer: every edge solves g[v_k] = k - g[v_k+1] - g[v_k+2] (mod 3) for its hinge k.
+// Inside a layer no edge touches another edge's hinge (its only edge at round start), so the
+// edges of a layer are independent.
+__global__ __launch_bounds__(256) void k_assign_round(const uint32_t* __restrict__ edges,
+                                                      const uint32_t* __restrict__ layer,
+                                                      const uint32_t* __restrict__ hmask32,
+                                                      const uint64_t* __restrict__ lstart, uint32_t r,
+                                                      uint8_t* __restrict__ code8)
+{
+    const uint64_t lo = lstart[r], hi = lstart[r + 1];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride) {
+        uint32_t e = layer[i];
+        uint32_t k = __builtin_ctz(claim_mask(hmask32, e));
+        const uint32_t* t = edges + 3 * (uint64_t)e;
+        uint32_t v0 = t[0], v1 = t[1], v2 = t[2];
+        uint32_t vk = k == 0 ? v0 : (k == 1 ? v1 : v2);
+        uint32_t va = k == 0 ? v1 : (k == 1 ? v2 : v0);
+        uint32_t vb = k == 0 ? v2 : (k == 1 ? v0 : v1);
+        uint32_t g = (k + 6 - g_of_code(code8[va]) - g_of_code(code8[vb])) % 3;
+        code8[vk] = (uint8_t)(g ? g : 3);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pack_count(const uint8_t* __restrict__ code8, uint64_t m,
+                                                    uint64_t* __restrict__ codes, uint32_t* __restrict__ bcount,
+                                                    uint64_t nwords)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < nwords; base += stride) {
+        uint64_t w = base + threadIdx.x;
+        uint64_t x = 0;
+        if (w < nwords) {
+            uint64_t v0 = w * 32;
+            if (v0 + 32 <= m) {
+                const uint4* p = reinterpret_cast<const uint4*>(code8 + v0);
+                uint4 a = p[0], b = p[1];
+                uint32_t d[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+#pragma unroll
+                    for (int t = 0; t < 4; t++)
+                        x |= (uint64_t)((d[q] >> (8 * t)) & 3u) << (2 * (4 * q + t));
+                }
+            } else {
+                for (uint64_t t = 0; v0 + t < m && t < 32; t++)
+                    x |= (uint64_t)(code8[v0 + t] & 3u) << (2 * t);
+            }
+            codes[w] = x;
+        }
+        uint32_t c = nz_pairs(x);
+        c += __shfl_xor(c, 1, 16);
+        c += __shfl_xor(c, 2, 16);
+        c += __shfl_xor(c, 4, 16);
+        c += __shfl_xor(c, 8, 16);
+        if (w < nwords && (w & 15) == 0)
+            bcount[w >> 4] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lookup_u64(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ rank,
+                                                    uint64_t P, uint64_t seed, const uint64_t* __restrict__ keys,
+                                                    uint64_t n, uint64_t* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t s = keys[i] ^ seed;
+        uint32_t v0, v1, v2;
+        edge_of_digest(s, s, P, v0, v1, v2);
+        out[i] = eval_edge(codes, rank, v0, v1, v2);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_lookup_str(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ rank,
+                                                    uint64_t P, uint64_t seed, const uint8_t* __restrict__ bytes,
+                                                    const uint64_t* __restrict__ offs, uint64_t n,
+                                                    uint64_t* __restrict__ out)
+{
+    const uint64_t total = offs[n];
+    const uint64_t sa = fin(seed + kGamma);
+    const uint64_t sb = fin(seed + 2 * kGamma);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t o0 = offs[i], o1 = offs[i + 1];
+        uint64_t a, b;
+        digest_str(bytes, o0, o1 - o0, total, sa, sb, a, b);
+        uint32_t v0, v1, v2;
+        edge_of_digest(a, b, P, v0, v1, v2);
+        out[i] = eval_edge(codes, rank, v0, v1, v2);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bijection(const uint64_t* __restrict__ vals, uint64_t n,
+                                                   uint32_t* __restrict__ bitmap, Ctrl* ctrl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long bad = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t v = vals[i];
+        if (v >= n) {
+            bad++;
+            continue;
+        }
+        uint32_t bit = 1u << (v & 31);
+        uint32_t old = atomicOr(&bitmap[v >> 5], bit);
+        if (old & bit)
+            bad++;
+    }
+    if (bad)
+        atomicAdd(&ctrl->aux, bad);
+}
+
+static inline unsigned grid_cap(uint64_t count, unsigned cap)
+{
+    uint64_t g = (count + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+hipError_t launch_assign_round(const uint32_t* edges, const uint32_t* layer, const uint32_t* hmask32,
+                               const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint8_t* code8,
+                               unsigned grid_cap_blocks, hipStream_t s)
+{
+    k_assign_round<<<grid_cap(n_bound, grid_cap_blocks), 256, 0, s>>>(edges, layer, hmask32, lstart, r, code8);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_count(const uint8_t* code8, uint64_t m, uint64_t* codes, uint32_t* bcount, hipStream_t s)
+{
+    uint64_t nwords = (m + 31) / 32;
+    if (nwords == 0) return hipSuccess;
+    k_pack_count<<<grid_cap(nwords, 16384), 256, 0, s>>>(code8, m, codes, bcount, nwords);
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                             const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_lookup_u64<<<grid_cap(n, 16384), 256, 0, s>>>(codes, rank, P, seed, keys, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                             const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_lookup_str<<<grid_cap(n, 16384), 256, 0, s>>>(codes, rank, P, seed, bytes, offs, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bijection(const uint64_t* vals, uint64_t n, uint32_t* bitmap, Ctrl* ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_bijection<<<grid_cap(n, 8192), 256, 0, s>>>(vals, n, bitmap, ctrl);
+    return hipGetLastError();
+}
+
+}  // namespace mphx

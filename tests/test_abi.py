@@ -1,0 +1,81 @@
+"""The C-ABI library loads and exports every symbol include/mphx.h declares (CPU only; no
+compute calls).  Argument errors are reported before any device work."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mphx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"MPHX_API\s+[\w\s\*]+?\b(mphx_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def mx():
+    import paper_1312_0526_amd as mx
+
+    mx.lib()
+    return mx
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mphx_peel", "mphx_peel_workspace_bytes", "mphx_mphf_build_u64", "mphx_mphf_build_str",
+                     "mphx_mphf_workspace_bytes", "mphx_mphf_lookup_u64", "mphx_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(mx):
+    lib = C.CDLL(mx.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_part_size_matches_oracle(mx):
+    import oracle
+
+    o = oracle.Oracle()
+    for n in (0, 1, 2, 3, 1000, 10**6, 1 << 27, 1 << 31, (1 << 32) - 2):
+        for g in ((123, 100), (120, 100), (1, 1), (7, 3)):
+            assert mx.part_size(n, g) == o.part_size(n, *g)
+
+
+def test_options_roundtrip(mx):
+    old = mx.get_option("record")
+    mx.set_option("record", 0)
+    assert mx.get_option("record") == 0
+    mx.set_option("record", old)
+    with pytest.raises(mx.MphxError):
+        mx.set_option("record", 7)
+    with pytest.raises(mx.MphxError):
+        mx.set_option("no_such_option", 1)
+
+
+def test_argument_errors_need_no_device(mx):
+    lib = mx.lib()
+    info = mx._lib.PeelInfo()
+    # null workspace
+    assert lib.mphx_peel(None, 10, 30, None, None, None, None, None, 0, None, C.byref(info)) == mx.EINVAL
+    # n too large
+    assert lib.mphx_peel(None, 1 << 32, 30, None, None, None, None, None, 0, None, C.byref(info)) == mx.EINVAL
+    # workspace too small (a fake aligned pointer: rejected before use)
+    assert lib.mphx_peel(C.c_void_p(4096), 10, 30, C.c_void_p(4096), C.c_void_p(4096), C.c_void_p(4096), None,
+                         C.c_void_p(4096), 16, None, C.byref(info)) == mx.ENOMEM
+    minfo = mx._lib.MphfInfo()
+    assert lib.mphx_mphf_build_u64(None, 10, 0, 0, 100, 1, None, None, None, 0, None, C.byref(minfo)) == mx.EINVAL
+    assert lib.mphx_mphf_build_u64(None, 10, 0, 123, 100, 0, None, None, None, 0, None, C.byref(minfo)) == mx.EINVAL
+    msg = lib.mphx_last_error().decode()
+    assert "max_tries" in msg
+
+
+def test_workspace_sizes_scale_linearly(mx):
+    a = mx.mphf_workspace_bytes(1 << 20)
+    b = mx.mphf_workspace_bytes(1 << 21)
+    assert 1.9 < b / a < 2.1
+    # edges 12n + records 8m + frontier 4m + layer 4n + claim bytes n, m = 3.69n
+    assert 45 * (1 << 21) < b < 50 * (1 << 21)

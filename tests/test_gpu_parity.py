@@ -1,0 +1,281 @@
+"""HIP path against the oracle, element by element, through the C ABI (GPU only).
+
+Sizes span several tiles and ragged tails; the configuration-1 workload (10^6 u64 keys,
+gamma = 123/100) runs in full.  Integer work: the bar is bit-exact equality.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import pins
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+NONE = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def mx():
+    import torch
+
+    import paper_1312_0526_amd as mx
+
+    assert torch.cuda.is_available()
+    mx.lib()
+    return mx
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.Oracle()
+
+
+@pytest.fixture(params=[0, 1], ids=["xor-record", "sum-record"])
+def record(request, mx):
+    old = mx.get_option("record")
+    mx.set_option("record", request.param)
+    yield request.param
+    mx.set_option("record", old)
+
+
+def dev(a):
+    import torch
+
+    a = np.ascontiguousarray(a)
+    view = {np.dtype(np.uint64): np.int64, np.dtype(np.uint32): np.int32}.get(a.dtype)
+    if view is not None:
+        a = a.view(view)
+    return torch.from_numpy(a).to("cuda")
+
+
+def host(t, dtype):
+    return t.cpu().numpy().view(dtype)
+
+
+# ------------------------------------------------------------------------------------------
+# hashing and generators
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,seed,P", [(1, 0, 1), (1000, 0, 1 << 30), (1_000_000, 0, 410_000),
+                                      (300_001, 0xDEADBEEF, 123_457), (4099, (1 << 64) - 1, 7)])
+def test_hash_u64(mx, o, n, seed, P):
+    keys = workloads.u64_keys(n, gen_seed=11)
+    got = host(mx.hash_u64(dev(keys), seed, P), np.uint32).reshape(-1, 3)
+    assert np.array_equal(got, o.hash_u64(keys, seed, P))
+
+
+def test_hash_u64_known_answer(mx):
+    P = 1 << 30
+    got = host(mx.hash_u64(dev(np.zeros(1, np.uint64)), 0, P), np.uint32).tolist()
+    want = [pins.SPLITMIX0[0] >> 34, P + (pins.SPLITMIX0[1] >> 34), 2 * P + (pins.SPLITMIX0[2] >> 34)]
+    assert got == want
+
+
+def _str_cases():
+    rng = np.random.default_rng(5)
+    keys = [b"", b"a", b"ab", b"abc", b"abcd", b"abcdefg", b"abcdefgh", b"abcdefghi", bytes(range(256)),
+            b"\x00" * 9, b"x" * 512]
+    keys += [bytes(rng.integers(0, 256, size=int(l), dtype=np.uint8)) for l in rng.integers(0, 40, size=300)]
+    data = np.frombuffer(b"".join(keys), np.uint8).copy()
+    offs = np.zeros(len(keys) + 1, np.uint64)
+    offs[1:] = np.cumsum([len(k) for k in keys])
+    return data, offs
+
+
+@pytest.mark.parametrize("seed", [0, 1, 0x123456789ABCDEF])
+def test_hash_str_edge_cases(mx, o, seed):
+    data, offs = _str_cases()  # every alignment of start and end, empty keys, 512-byte keys
+    P = 1000003
+    got = host(mx.hash_str(dev(data), dev(offs), seed, P), np.uint32).reshape(-1, 3)
+    assert np.array_equal(got, o.hash_str(data, offs, seed, P))
+
+
+def test_hash_str_generated(mx, o):
+    data, offs = workloads.str_keys(100_003, gen_seed=2)
+    P = mx.part_size(100_003)
+    got = host(mx.hash_str(dev(data), dev(offs), 9, P), np.uint32).reshape(-1, 3)
+    assert np.array_equal(got, o.hash_str(data, offs, 9, P))
+
+
+def test_device_generators_match_host(mx):
+    import torch
+
+    k = host(mx.gen_keys_u64(70_001, gen_seed=3, start=5), np.uint64)
+    assert np.array_equal(k, workloads.u64_keys(70_001, gen_seed=3, start=5))
+    q = dev(workloads.quantile_table().view(np.int16))
+    for n, start in ((50_001, 0), (3, 123_456_789_012)):
+        data, offs = mx.gen_str_keys(n, q, gen_seed=4, start=start)
+        hd, ho = workloads.str_keys(n, gen_seed=4, start=start)
+        assert np.array_equal(host(offs, np.uint64), ho)
+        assert np.array_equal(data.cpu().numpy()[: int(ho[-1])], hd)
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------------------------------
+# peeling
+# ------------------------------------------------------------------------------------------
+def _peel_both(mx, o, edges, m):
+    rc, ref = o.peel(edges, m, 0)
+    assert rc == 0
+    got = mx.peel(dev(edges.astype(np.uint32)), m)
+    return got, ref
+
+
+def _assert_peel_equal(got, ref):
+    assert got["n_peeled"] == ref["n_peeled"]
+    assert got["n_rounds"] == ref["n_rounds"]
+    for key, dt in (("order", np.uint32), ("round", np.uint32), ("core_mask", np.uint8), ("hinge", np.uint8)):
+        g = host(got[key], dt)
+        assert np.array_equal(g, ref[key]), f"{key} differs"
+
+
+def test_peel_worked_examples(mx, o, record):
+    g = pins.golden()
+    for name in ("E1", "E2"):
+        ex = g[name]
+        edges = np.array(ex["edges"], np.uint32)
+        got = mx.peel(dev(edges), g["m"])
+        assert host(got["round"], np.uint32).tolist() == ex["round"]
+        assert host(got["order"], np.uint32).tolist() == ex["order"]
+        assert host(got["core_mask"], np.uint8).tolist() == ex["core_mask"]
+        h = host(got["hinge"], np.uint8).tolist()
+        assert h == ex["hinge"]
+        assert got["n_rounds"] == ex["n_rounds"]
+
+
+@pytest.mark.parametrize("n,gamma", [(1, 1.23), (2, 1.0), (5000, 1.23), (65_537, 1.23), (65_537, 1.18),
+                                     (200_000, 1.05), (1_000_000, 1.23), (1_000_000, 1.20)])
+def test_peel_tripartite(mx, o, record, n, gamma):
+    rng = np.random.default_rng(n)
+    P = max(1, int(np.ceil(gamma * n / 3)))
+    edges = pins.random_tripartite(n, P, rng)
+    got, ref = _peel_both(mx, o, edges, 3 * P)
+    _assert_peel_equal(got, ref)
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_peel_generic(mx, o, record, trial):
+    rng = np.random.default_rng(100 + trial)
+    n = int(rng.integers(1, 3000))
+    m = int(rng.integers(3, max(4, n)))
+    edges = pins.random_generic(n, m, rng)
+    if trial % 2:
+        edges = np.concatenate([edges, edges[: n // 10]])  # duplicates stay in the core
+    got, ref = _peel_both(mx, o, edges, m)
+    _assert_peel_equal(got, ref)
+
+
+def test_peel_long_chain(mx, o):
+    """A chain peels one edge per round from each end: about n/2 rounds."""
+    n = 3001
+    edges = np.array([[2 * i, 2 * i + 1, 2 * i + 2] for i in range(n)], np.uint32)
+    got, ref = _peel_both(mx, o, edges, 2 * n + 1)
+    assert ref["n_rounds"] > 1000
+    _assert_peel_equal(got, ref)
+
+
+def test_peel_empty(mx):
+    got = mx.peel(dev(np.zeros((0, 3), np.uint32)), 10)
+    assert got["n_peeled"] == 0 and got["n_rounds"] == 0
+
+
+def test_peel_errors(mx):
+    with pytest.raises(mx.MphxError) as ei:
+        mx.peel(dev(np.array([[0, 1, 5]], np.uint32)), 5)
+    assert ei.value.status == mx.EINVAL
+    with pytest.raises(mx.MphxError) as ei:
+        mx.peel(dev(np.array([[0, 1, 1]], np.uint32)), 5)
+    assert ei.value.status == mx.EINVAL
+    star = np.array([[0, 1 + i, 300 + i] for i in range(256)], np.uint32)
+    for rec in (0, 1):
+        mx.set_option("record", rec)
+        with pytest.raises(mx.MphxError) as ei:
+            mx.peel(dev(star), 600)
+        assert ei.value.status == mx.ERANGE
+        got = mx.peel(dev(star[:255]), 600)
+        assert got["n_peeled"] == 255
+    mx.set_option("record", 1)
+
+
+# ------------------------------------------------------------------------------------------
+# whole MPHF build
+# ------------------------------------------------------------------------------------------
+def _assert_mphf_equal(got, ref):
+    for key in ("P", "m", "seed_used", "tries", "n_rounds"):
+        assert got[key] == ref[key], key
+    assert np.array_equal(host(got["codes"], np.uint64), ref["words"])
+    assert np.array_equal(host(got["rank"], np.uint64), ref["rank"])
+
+
+def test_mphf_two_keys_one_vertex_per_part(mx, o):
+    """n = 2 gives P = 1: both edges are (0, 1, 2) and can never peel (distinct keys: ECORE)."""
+    keys = workloads.u64_keys(2)
+    rc, ref = o.mphf_build_u64(keys, max_tries=5)
+    assert rc == oracle.ECORE
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_u64(dev(keys), max_tries=5)
+    assert ei.value.status == mx.ECORE and ei.value.info["n_core"] == ref["n_core"] == 2
+
+
+@pytest.mark.parametrize("n,seed", [(1_000_000, 0), (12_345, 77), (1, 0), (7, 5)])
+def test_mphf_u64(mx, o, record, n, seed):
+    keys = workloads.u64_keys(n)
+    got = mx.mphf_build_u64(dev(keys), seed=seed)
+    rc, ref = o.mphf_build_u64(keys, seed=seed)
+    assert rc == 0
+    _assert_mphf_equal(got, ref)
+    f = mx.lookup_u64(got["codes"], got["rank"], got["P"], got["seed_used"], dev(keys))
+    assert np.array_equal(host(f, np.uint64), o.lookup_u64(ref["words"], ref["rank"], ref["P"], ref["seed_used"], keys))
+    assert mx.check_bijection(f) == 0
+
+
+def test_mphf_small_buckets_retry(mx, o):
+    """n = 100 fails often at gamma 1.23: tries and seeds must follow the oracle."""
+    retried = 0
+    for b in range(30):
+        keys = workloads.u64_keys(100, gen_seed=workloads.bucket_gen_seed(b))
+        got = mx.mphf_build_u64(dev(keys), seed=0)
+        rc, ref = o.mphf_build_u64(keys, seed=0)
+        assert rc == 0
+        _assert_mphf_equal(got, ref)
+        retried += got["tries"] > 1
+    assert retried > 5
+
+
+def test_mphf_str(mx, o, record):
+    data, offs = workloads.str_keys(200_000, gen_seed=1)
+    got = mx.mphf_build_str(dev(data), dev(offs), seed=4)
+    rc, ref = o.mphf_build_str(data, offs, seed=4)
+    assert rc == 0
+    _assert_mphf_equal(got, ref)
+    f = mx.lookup_str(got["codes"], got["rank"], got["P"], got["seed_used"], dev(data), dev(offs))
+    assert np.array_equal(host(f, np.uint64),
+                          o.lookup_str(ref["words"], ref["rank"], ref["P"], ref["seed_used"], data, offs))
+
+
+def test_mphf_core_and_duplicates(mx, o):
+    keys = workloads.u64_keys(50_000)
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_u64(dev(keys), gamma=(120, 100), max_tries=1)
+    assert ei.value.status == mx.ECORE
+    rc, ref = o.mphf_build_u64(keys, gnum=120, max_tries=1)
+    assert rc == oracle.ECORE and ei.value.info["n_core"] == ref["n_core"]
+    dup = np.concatenate([keys[:1000], keys[:2]])
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_u64(dev(dup), max_tries=2)
+    assert ei.value.status == mx.EDUP
+    assert o.mphf_build_u64(dup, max_tries=2)[0] == oracle.EDUP
+
+
+def test_mphf_deterministic_across_launch_shapes(mx):
+    keys = dev(workloads.u64_keys(300_000, gen_seed=9))
+    outs = []
+    for grid, batch in ((0, 8), (64, 1), (1000, 64), (0, 3)):
+        mx.set_option("grid", grid)
+        mx.set_option("round_batch", batch)
+        r = mx.mphf_build_u64(keys)
+        outs.append((host(r["codes"], np.uint64), host(r["rank"], np.uint64)))
+    mx.set_option("grid", 0)
+    mx.set_option("round_batch", 8)
+    for c, r in outs[1:]:
+        assert np.array_equal(c, outs[0][0]) and np.array_equal(r, outs[0][1])
