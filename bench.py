@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""MWHC minimal-perfect-hash build throughput on one MI355X.
+
+One step = one whole build over device-resident synthetic keys: hash the keys to a tripartite
+3-hypergraph, peel it in synchronous rounds, assign g by backward substitution along the
+layers in reverse round order, and build the rank table (retries included when a 2-core
+remains).  The reported value is keys (= hypergraph edges) per second.
+
+Default workload: 2^31 byte-string keys (printable ASCII, log-normal lengths with mean 60 B,
+clamped to 8..512 B, distinct by construction), gamma = 123/100, generated on the device
+before timing.  --config c1 / c2 select 10^6 / 2^27 u64 keys instead.
+
+Prints one JSON line (rank 0).  Per-kernel times come from HIP events the library records on
+the build's stream (option "timing"); the roofline object uses the algorithmic bytes of the
+dominant kernel (accounting below) divided by its measured time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published peak
+
+CONFIGS = {
+    "c1": dict(kind="u64", n=1_000_000, workload="mwhc_u64_n1e6_gamma1.23"),
+    "c2": dict(kind="u64", n=1 << 27, workload="mwhc_u64_n2^27_gamma1.23"),
+    "c3": dict(kind="str", n=1 << 31, workload="mwhc_str_n2^31_mean60B_gamma1.23"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(phase: str, st: dict) -> float:
+    """Bytes each phase must move at least once, at element size (not cache-line size).
+
+    n keys/edges, m = 3P vertices, key_bytes = total key bytes, F = frontier entries over all
+    rounds, F0 = initial frontier, C = claims (vertex had degree 1 at round start), R8 = 8-byte
+    per-vertex record, read-modify-write = 2 x its size.
+    """
+    n, m = st["n"], st["m"]
+    F, F0, C = st["frontier_total"], st["frontier0"], st["claims"]
+    if phase == "hash_build":
+        # key (u64: 8 B; strings: the bytes + one 8 B offset), edge write 12 B, 3 record RMW
+        key = 8 * n if st["kind"] == "u64" else st["key_bytes"] + 8 * n
+        return key + 12 * n + 3 * 16 * n
+    if phase == "frontier":
+        return 8 * m + 4 * F0
+    if phase == "claim":
+        # frontier entry 4 + record 8 per entry; claim byte RMW 2 per claim; layer append 4
+        return 12 * F + 2 * C + 4 * n
+    if phase == "apply":
+        # layer 4 + claim byte 1 + edge 12 per edge; record RMW 16 per non-claimer vertex;
+        # frontier push 4 per vertex that dropped to degree 1
+        return 17 * n + 16 * (3 * n - C) + 4 * (F - F0)
+    if phase == "assign":
+        # layer 4 + claim byte 1 + edge 12 + two code reads + one code write (1 B each)
+        return 20 * n
+    if phase == "rank":
+        # code bytes read, packed words written, per-512 counts written/read, rank written
+        return m + m / 4 + 16 * m / 512
+    return 0.0
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", choices=sorted(CONFIGS), default="c3")
+    ap.add_argument("--n", type=int, default=0, help="override the number of keys")
+    ap.add_argument("--record", type=int, default=-1, help="per-vertex record layout (0 xor, 1 sum)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="keys in the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
+              "of the peel is a design note, not built", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1312_0526_amd as mx
+    import workloads
+
+    cfg = dict(CONFIGS[args.config])
+    n = args.n or cfg["n"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.record >= 0:
+        mx.set_option("record", args.record)
+    gamma = (123, 100)
+
+    # ---- inputs, generated on the device before timing --------------------------------------
+    t0 = time.perf_counter()
+    if cfg["kind"] == "u64":
+        keys = mx.gen_keys_u64(n, gen_seed=0, device=dev)
+        key_bytes = 8 * n
+        kind = mx.KEYS_U64
+    else:
+        q = torch.from_numpy(workloads.quantile_table().view(np.int16)).to(dev)
+        data, offs = mx.gen_str_keys(n, q, gen_seed=0, device=dev)
+        key_bytes = int(offs[-1].item())
+        kind = mx.KEYS_STR
+    torch.cuda.synchronize()
+    log(f"[bench] {cfg['workload']} n={n}: keys generated on device in {time.perf_counter() - t0:.1f} s "
+        f"({key_bytes / 1e9:.2f} GB of key bytes)")
+
+    P = mx.part_size(n, gamma)
+    m = 3 * P
+    ws = torch.empty(mx.mphf_workspace_bytes(n, gamma, kind), dtype=torch.uint8, device=dev)
+    codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
+    rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
+    log(f"[bench] workspace {ws.numel() / 1e9:.2f} GB, device memory in use "
+        f"{torch.cuda.memory_allocated() / 1e9:.1f} GB")
+
+    def step():
+        if kind == mx.KEYS_U64:
+            return mx.mphf_build_u64(keys, seed=0, gamma=gamma, ws=ws, out=(codes, rank))
+        return mx.mphf_build_str(data, offs, seed=0, gamma=gamma, ws=ws, out=(codes, rank))
+
+    mx.set_option("timing", 1)
+    for i in range(args.warmup):
+        r = step()
+        log(f"[bench] warmup {i}: rounds={r['n_rounds']} tries={r['tries']}")
+    torch.cuda.synchronize()
+    mx.phase_times(reset=True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = n / (ms_per_step / 1000.0)
+    phases = mx.phase_times(reset=True)
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value / 1e9:.3f} G keys/s")
+
+    st = dict(n=n, m=m, kind=cfg["kind"], key_bytes=key_bytes, frontier_total=r["frontier_total"],
+              frontier0=r["frontier0"], claims=r["claims"])
+    phase_rows = {}
+    for name, (ms, launches) in phases.items():
+        if launches == 0:
+            continue
+        per_step_ms = ms / args.steps
+        b = algorithmic_bytes(name, st)
+        gbs = b / (per_step_ms / 1000.0) / 1e9 if per_step_ms > 0 else 0.0
+        phase_rows[name] = dict(ms=round(per_step_ms, 3), launches=launches // args.steps,
+                                alg_bytes=int(b), alg_GBps=round(gbs, 1))
+        log(f"[bench]   {name:10s} {per_step_ms:9.3f} ms/step  {launches // args.steps:5d} launches  "
+            f"{b / 1e9:8.2f} GB alg  {gbs:8.1f} GB/s")
+    dom = max(phase_rows, key=lambda k: phase_rows[k]["ms"])
+    ach = phase_rows[dom]["alg_GBps"]
+    roofline = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+
+    # ---- oracle on a bounded sample of the same workload ------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        o = oracle.Oracle()
+        ns = min(args.cpu_sample, n)
+        if cfg["kind"] == "u64":
+            hk = workloads.u64_keys(ns)
+            c0 = time.perf_counter()
+            rc, _ = o.mphf_build_u64(hk, seed=0)
+        else:
+            hd, ho = workloads.str_keys(ns)
+            c0 = time.perf_counter()
+            rc, _ = o.mphf_build_str(hd, ho, seed=0)
+        cs = time.perf_counter() - c0
+        cpu = dict(value=round(ns / cs, 1), unit="keys/s", cores=1, kind="oracle",
+                   sample=f"first {ns} keys of the same generator, single-threaded C oracle, "
+                          f"{cs:.1f} s (status {rc})")
+        log(f"[bench] oracle: {ns} keys in {cs:.2f} s = {ns / cs / 1e6:.3f} M keys/s")
+
+    out = {
+        "metric": "edges peeled/s (hash+peel+assign+rank), plain single-hypergraph build",
+        "value": round(value, 1),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": cfg["workload"], "n": n, "gamma": "123/100", "m": m,
+                   "key_bytes": key_bytes, "rounds": r["n_rounds"], "tries": r["tries"],
+                   "record": mx.get_option("record"), "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases": phase_rows,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

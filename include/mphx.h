@@ -58,9 +58,12 @@ extern "C" {
 #define MPHX_MAX_DEGREE 255u
 
 typedef struct mphx_peel_info {
-    uint64_t n_peeled;   /* edges removed; n - n_peeled edges form the 2-core */
-    uint32_t n_rounds;   /* number of non-empty layers */
+    uint64_t n_peeled;       /* edges removed; n - n_peeled edges form the 2-core */
+    uint32_t n_rounds;       /* number of non-empty layers */
     uint32_t reserved;
+    uint64_t frontier_total; /* frontier entries over all rounds (vertices that reached degree 1) */
+    uint64_t claims;         /* (vertex, edge) pairs where the vertex had degree 1 at round start */
+    uint64_t frontier0;      /* vertices of degree 1 before round 0 */
 } mphx_peel_info;
 
 typedef struct mphx_mphf_info {
@@ -70,6 +73,9 @@ typedef struct mphx_mphf_info {
     uint32_t tries;      /* tries made: seed, seed+1, ... */
     uint32_t n_rounds;   /* peeling rounds of the last try */
     uint64_t n_core;     /* 2-core edges left on the last try (0 on success) */
+    uint64_t frontier_total; /* last try: frontier entries over all rounds */
+    uint64_t claims;         /* last try: (vertex, edge) claims over all rounds */
+    uint64_t frontier0;      /* last try: vertices of degree 1 before round 0 */
 } mphx_mphf_info;
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -188,10 +194,19 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 incidence list over the group Z/2^40 instead of XOR).  Results identical.
  *   "grid"        blocks per launch of the grid-stride peeling kernels (0 = automatic).
  *   "round_batch" peeling rounds enqueued between two checks of the termination flag.
+ *   "timing"      1 = record a HIP event pair on the caller's stream around every kernel
+ *                 launch of mphx_peel / mphx_mphf_build_*, accumulated per phase.
  * Returns MPHX_EINVAL for an unknown key or value.
+ *
+ * mphx_phase_times copies the accumulated per-phase kernel time (ms) and launch counts of
+ * the calling thread (phases: hash_build, frontier, claim, apply, assign, rank, order,
+ * other; mphx_phase_name(i) names phase i) and optionally resets them; returns the number
+ * of phases.
  * --------------------------------------------------------------------------------------- */
 MPHX_API int mphx_set_option(const char* key, int64_t value);
 MPHX_API int64_t mphx_get_option(const char* key);
+MPHX_API int mphx_phase_times(double* ms, uint64_t* launches, int max_phases, int reset);
+MPHX_API const char* mphx_phase_name(int i);
 
 #ifdef __cplusplus
 }

@@ -27,12 +27,14 @@ class MphxError(RuntimeError):
 
 
 class PeelInfo(C.Structure):
-    _fields_ = [("n_peeled", C.c_uint64), ("n_rounds", C.c_uint32), ("reserved", C.c_uint32)]
+    _fields_ = [("n_peeled", C.c_uint64), ("n_rounds", C.c_uint32), ("reserved", C.c_uint32),
+                ("frontier_total", C.c_uint64), ("claims", C.c_uint64), ("frontier0", C.c_uint64)]
 
 
 class MphfInfo(C.Structure):
     _fields_ = [("P", C.c_uint64), ("m", C.c_uint64), ("seed_used", C.c_uint64), ("tries", C.c_uint32),
-                ("n_rounds", C.c_uint32), ("n_core", C.c_uint64)]
+                ("n_rounds", C.c_uint32), ("n_core", C.c_uint64), ("frontier_total", C.c_uint64),
+                ("claims", C.c_uint64), ("frontier0", C.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -61,6 +63,8 @@ _SIGS = {
     "mphx_gen_str_bytes": (_i32, [_vp, _vp, _u64, _u64, _u64, _vp]),
     "mphx_set_option": (_i32, [C.c_char_p, C.c_int64]),
     "mphx_get_option": (C.c_int64, [C.c_char_p]),
+    "mphx_phase_times": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_uint64), _i32, _i32]),
+    "mphx_phase_name": (C.c_char_p, [_i32]),
 }
 
 _lib = None
@@ -121,6 +125,14 @@ def get_option(key: str) -> int:
     return int(lib().mphx_get_option(key.encode()))
 
 
+def phase_times(reset: bool = False) -> dict:
+    """Accumulated per-phase kernel time (ms) and launch counts (needs option timing=1)."""
+    ms = (C.c_double * 16)()
+    cnt = (C.c_uint64 * 16)()
+    k = lib().mphx_phase_times(ms, cnt, 16, int(reset))
+    return {lib().mphx_phase_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
 def part_size(n: int, gamma=(123, 100)) -> int:
     return int(lib().mphx_part_size(n, gamma[0], gamma[1]))
 
@@ -144,15 +156,24 @@ def peel(edges: torch.Tensor, m: int, with_hinge: bool = True) -> dict:
     if rc:
         _err(rc)
     return dict(order=order, round=rnd, core_mask=core, hinge=hinge, n_peeled=int(info.n_peeled),
-                n_rounds=int(info.n_rounds))
+                n_rounds=int(info.n_rounds), frontier_total=int(info.frontier_total), claims=int(info.claims),
+                frontier0=int(info.frontier0))
 
 
-def _mphf_outputs(n, gamma, kind, dev):
+def _mphf_outputs(n, gamma, kind, dev, ws, out):
     P = part_size(n, gamma)
     m = 3 * P
-    codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
-    rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
-    ws = _workspace(lib().mphx_mphf_workspace_bytes(n, gamma[0], gamma[1], kind), dev)
+    if out is None:
+        codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
+        rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
+    else:
+        codes, rank = out
+        _check(codes, torch.int64, "codes")
+        _check(rank, torch.int64, "rank")
+        if codes.numel() < (m + 31) // 32 or rank.numel() < (m + 511) // 512:
+            raise ValueError("output buffers too small")
+    if ws is None:
+        ws = _workspace(lib().mphx_mphf_workspace_bytes(n, gamma[0], gamma[1], kind), dev)
     return P, m, codes, rank, ws
 
 
@@ -163,11 +184,12 @@ def _result(codes, rank, info, m):
     return d
 
 
-def mphf_build_u64(keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64, ws=None) -> dict:
+def mphf_build_u64(keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64, ws=None,
+                   out=None) -> dict:
+    """Build an MPHF of u64 keys (int64 view).  ws / out=(codes, rank) may be preallocated."""
     _check(keys, torch.int64, "keys")
     n = keys.numel()
-    P, m, codes, rank, ws_new = _mphf_outputs(n, gamma, KEYS_U64, keys.device)
-    ws = ws_new if ws is None else ws
+    P, m, codes, rank, ws = _mphf_outputs(n, gamma, KEYS_U64, keys.device, ws, out)
     info = MphfInfo()
     rc = lib().mphx_mphf_build_u64(_ptr(keys), n, seed, gamma[0], gamma[1], max_tries, _ptr(codes), _ptr(rank),
                                    _ptr(ws), ws.numel(), _stream(keys.device), C.byref(info))
@@ -177,12 +199,12 @@ def mphf_build_u64(keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_trie
 
 
 def mphf_build_str(data: torch.Tensor, offs: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64,
-                   ws=None) -> dict:
+                   ws=None, out=None) -> dict:
+    """Build an MPHF of byte-string keys (data + n+1 offsets).  ws / out may be preallocated."""
     _check(data, torch.uint8, "data")
     _check(offs, torch.int64, "offs")
     n = offs.numel() - 1
-    P, m, codes, rank, ws_new = _mphf_outputs(n, gamma, KEYS_STR, data.device)
-    ws = ws_new if ws is None else ws
+    P, m, codes, rank, ws = _mphf_outputs(n, gamma, KEYS_STR, data.device, ws, out)
     info = MphfInfo()
     rc = lib().mphx_mphf_build_str(_ptr(data), _ptr(offs), n, seed, gamma[0], gamma[1], max_tries, _ptr(codes),
                                    _ptr(rank), _ptr(ws), ws.numel(), _stream(data.device), C.byref(info))

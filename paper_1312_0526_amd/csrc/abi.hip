@@ -21,8 +21,75 @@ struct Options {
     std::atomic<int> record{1};        // 0 = XOR record, 1 = sum record
     std::atomic<int> grid{0};          // 0 = automatic
     std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
+    std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
 };
 Options g_opt;
+
+// ---- per-phase timing (HIP events on the caller's stream) ---------------------------------
+enum Phase { PH_HASH, PH_FRONTIER, PH_CLAIM, PH_APPLY, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_COUNT };
+const char* const kPhaseNames[PH_COUNT] = {"hash_build", "frontier", "claim", "apply",
+                                           "assign",     "rank",     "order", "other"};
+
+struct Timers {
+    struct Span { int phase; hipEvent_t a, b; };
+    std::vector<hipEvent_t> pool;
+    std::vector<Span> pending;
+    double ms[PH_COUNT] = {};
+    uint64_t launches[PH_COUNT] = {};
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Fold completed spans into the totals (the stream has been synchronised).
+    void harvest()
+    {
+        for (auto& sp : pending) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, sp.a, sp.b) == hipSuccess) {
+                ms[sp.phase] += t;
+                launches[sp.phase] += 1;
+            }
+            pool.push_back(sp.a);
+            pool.push_back(sp.b);
+        }
+        pending.clear();
+    }
+};
+thread_local Timers g_timers;
+
+struct Timed {
+    int phase;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Timed(int ph, hipStream_t st) : phase(ph), s(st)
+    {
+        if (g_opt.timing.load()) {
+            a = g_timers.get();
+            if (a && hipEventRecord(a, s) != hipSuccess) {
+                g_timers.pool.push_back(a);
+                a = nullptr;
+            }
+        }
+    }
+    ~Timed()
+    {
+        if (!a) return;
+        hipEvent_t b = g_timers.get();
+        if (b && hipEventRecord(b, s) == hipSuccess)
+            g_timers.pending.push_back({phase, a, b});
+        else {
+            g_timers.pool.push_back(a);
+            if (b) g_timers.pool.push_back(b);
+        }
+    }
+};
 
 int fail(int code, const char* fmt, ...)
 {
@@ -137,8 +204,14 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t first_front, hipStream_t s)
     for (;;) {
         uint64_t upto = std::min<uint64_t>((uint64_t)r + batch, st.rcap);
         st.grid_cap = auto_grid(last_front);
-        for (; r < upto; r++)
-            HIP_TRY(launch_round(st, r, s));
+        for (; r < upto; r++) {
+            {
+                Timed t(PH_CLAIM, s);
+                HIP_TRY(launch_claim(st, r, s));
+            }
+            Timed t(PH_APPLY, s);
+            HIP_TRY(launch_apply(st, r, s));
+        }
         uint64_t fs = 0;
         HIP_TRY(hipMemcpyAsync(&fs, st.fstart + r, sizeof fs, hipMemcpyDeviceToHost, s));
         int rc = read_ctrl(st.ctrl, h, s);
@@ -192,6 +265,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "round_batch")) {
         if (value < 1 || value > 4096) return fail(MPHX_EINVAL, "round_batch out of range");
         g_opt.round_batch = (int)value;
+    } else if (!strcmp(key, "timing")) {
+        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "timing must be 0 or 1");
+        g_opt.timing = (int)value;
     } else {
         return fail(MPHX_EINVAL, "unknown option '%s'", key);
     }
@@ -204,9 +280,28 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "record")) return g_opt.record;
     if (!strcmp(key, "grid")) return g_opt.grid;
     if (!strcmp(key, "round_batch")) return g_opt.round_batch;
+    if (!strcmp(key, "timing")) return g_opt.timing;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
+
+int mphx_phase_times(double* ms, uint64_t* launches, int max_phases, int reset)
+{
+    int k = std::min<int>(max_phases, PH_COUNT);
+    for (int i = 0; i < k; i++) {
+        if (ms) ms[i] = g_timers.ms[i];
+        if (launches) launches[i] = g_timers.launches[i];
+    }
+    if (reset) {
+        for (int i = 0; i < PH_COUNT; i++) {
+            g_timers.ms[i] = 0;
+            g_timers.launches[i] = 0;
+        }
+    }
+    return PH_COUNT;
+}
+
+const char* mphx_phase_name(int i) { return (i >= 0 && i < PH_COUNT) ? kPhaseNames[i] : ""; }
 
 size_t mphx_peel_workspace_bytes(uint64_t n, uint64_t m)
 {
@@ -241,8 +336,14 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     HIP_TRY(launch_zero(L.hmask32, ((n + 3) / 4) * 4, s));
     HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
     HIP_TRY(launch_fill_u32(round, n, kRoundCore, s));
-    HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, record, s));
-    HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+    {
+        Timed t(PH_HASH, s);
+        HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, record, s));
+    }
+    {
+        Timed t(PH_FRONTIER, s);
+        HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+    }
     uint64_t f0 = 0;
     int rc = check_build_errors(L.ctrl, s, f0);
     if (rc) return rc;
@@ -267,12 +368,19 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     rc = run_rounds(st, h, f0, s);
     if (rc) return rc;
 
-    HIP_TRY(launch_peel_finalize(round, L.hmask32, n, core_mask, hinge, s));
-    HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.layer, L.tilehist, L.scan, L.scan_bytes, s));
+    {
+        Timed t(PH_ORDER, s);
+        HIP_TRY(launch_peel_finalize(round, L.hmask32, n, core_mask, hinge, s));
+        HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.layer, L.tilehist, L.scan, L.scan_bytes, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
+    g_timers.harvest();
     if (info) {
         info->n_peeled = h.ltail;
         info->n_rounds = h.nrounds;
+        info->frontier_total = h.ftail;
+        info->claims = h.claims;
+        info->frontier0 = f0;
     }
     return MPHX_OK;
 }
@@ -418,11 +526,17 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
         HIP_TRY(launch_zero(L.hmask32, ((n + 3) / 4) * 4, s));
         HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
-        if (k.kind == MPHX_KEYS_U64)
-            HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
-        else
-            HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
-        HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+        {
+            Timed tm(PH_HASH, s);
+            if (k.kind == MPHX_KEYS_U64)
+                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
+            else
+                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
+        }
+        {
+            Timed tm(PH_FRONTIER, s);
+            HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+        }
         uint64_t f0 = 0;
         int rc = check_build_errors(L.ctrl, s, f0);
         if (rc) {
@@ -436,6 +550,9 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             info->seed_used = sd;
             info->n_rounds = h.nrounds;
             info->n_core = n - h.ltail;
+            info->frontier_total = h.ftail;
+            info->claims = h.claims;
+            info->frontier0 = f0;
         }
         if (h.ltail == n) {
             peeled = true;
@@ -458,12 +575,17 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     HIP_TRY(hipStreamSynchronize(s));
     for (int64_t r = (int64_t)h.nrounds - 1; r >= 0; r--) {
         uint64_t cnt = lb[r + 1] - lb[r];
+        Timed tm(PH_ASSIGN, s);
         HIP_TRY(launch_assign_round(L.edges, L.layer, L.hmask32, L.lstart, (uint32_t)r, cnt, code8, 16384, s));
     }
-    HIP_TRY(launch_pack_count(code8, m, codes, L.bcount, s));
-    uint64_t nblocks = (m + 511) / 512;
-    HIP_TRY(launch_scan_u32_to_u64(L.bcount, nblocks, rank, nblocks, L.scan, L.scan_bytes, s));
+    {
+        Timed tm(PH_RANK, s);
+        HIP_TRY(launch_pack_count(code8, m, codes, L.bcount, s));
+        uint64_t nblocks = (m + 511) / 512;
+        HIP_TRY(launch_scan_u32_to_u64(L.bcount, nblocks, rank, nblocks, L.scan, L.scan_bytes, s));
+    }
     HIP_TRY(hipStreamSynchronize(s));
+    g_timers.harvest();
     return MPHX_OK;
 }
 

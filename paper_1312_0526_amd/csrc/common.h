@@ -22,8 +22,9 @@ struct Ctrl {
     unsigned long long ltail;  // append cursor of the layer array (all rounds back to back)
     uint32_t nrounds;          // first round whose layer was empty (UINT32_MAX while running)
     uint32_t err;              // kErr* bits
-    unsigned long long aux;    // scratch counter (bijection check, duplicate scans)
-    uint64_t pad[28];
+    unsigned long long aux;    // scratch counter (bijection check)
+    unsigned long long claims; // (vertex, edge) claims made over all rounds
+    uint64_t pad[27];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte slot");
 

@@ -55,7 +55,8 @@ hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uin
                               hipStream_t s);
 hipError_t launch_frontier_init(const uint64_t* rec, uint64_t m, uint32_t* front, Ctrl* ctrl, int record,
                                 hipStream_t s);
-hipError_t launch_round(const PeelState& st, uint32_t r, hipStream_t s);
+hipError_t launch_claim(const PeelState& st, uint32_t r, hipStream_t s);
+hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s);
 hipError_t launch_peel_finalize(const uint32_t* round, const uint32_t* hmask32, uint64_t n, uint8_t* core_mask,
                                 uint8_t* hinge, hipStream_t s);
 uint64_t sort_tiles(uint64_t n);

@@ -86,12 +86,13 @@ __global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec,
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
-        bool first = false;
+        bool first = false, claimed = false;
         uint32_t e = 0;
         if (i < hi) {
             uint32_t v = front[i];
             uint64_t x = rec[v];
             if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
+                claimed = true;
                 e = Rec::edge(x);
                 uint32_t k;
                 if constexpr (kTri) {
@@ -108,6 +109,9 @@ __global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec,
         uint64_t pos = wave_append(&ctrl->ltail, first, false);
         if (first)
             layer[pos] = e;
+        uint64_t cb = __ballot(claimed);
+        if (cb && (int)__lane_id() == __ffsll((long long)__ballot(1)) - 1)
+            atomicAdd(&ctrl->claims, (unsigned long long)__popcll(cb));
     }
 }
 
@@ -295,29 +299,36 @@ hipError_t launch_frontier_init(const uint64_t* rec, uint64_t m, uint32_t* front
     return hipGetLastError();
 }
 
-hipError_t launch_round(const PeelState& st, uint32_t r, hipStream_t s)
+hipError_t launch_claim(const PeelState& st, uint32_t r, hipStream_t s)
 {
-    unsigned gc = grid_for(st.m, st.grid_cap);
-    unsigned ga = grid_for(st.n, st.grid_cap);
+    unsigned g = grid_for(st.m, st.grid_cap);
     if (st.record == 1) {
         if (st.tripartite)
-            k_claim<RecSum, true><<<gc, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                     st.ctrl, r, st.P, st.n);
+            k_claim<RecSum, true><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
+                                                    st.ctrl, r, st.P, st.n);
         else
-            k_claim<RecSum, false><<<gc, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                      st.ctrl, r, st.P, st.n);
-        k_apply<RecSum><<<ga, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.lstart,
-                                           st.round_out, st.ctrl, r);
+            k_claim<RecSum, false><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
+                                                     st.ctrl, r, st.P, st.n);
     } else {
         if (st.tripartite)
-            k_claim<RecXor, true><<<gc, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                     st.ctrl, r, st.P, st.n);
+            k_claim<RecXor, true><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
+                                                    st.ctrl, r, st.P, st.n);
         else
-            k_claim<RecXor, false><<<gc, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                      st.ctrl, r, st.P, st.n);
-        k_apply<RecXor><<<ga, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.lstart,
-                                           st.round_out, st.ctrl, r);
+            k_claim<RecXor, false><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
+                                                     st.ctrl, r, st.P, st.n);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s)
+{
+    unsigned g = grid_for(st.n, st.grid_cap);
+    if (st.record == 1)
+        k_apply<RecSum><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.lstart, st.round_out,
+                                          st.ctrl, r);
+    else
+        k_apply<RecXor><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.lstart, st.round_out,
+                                          st.ctrl, r);
     return hipGetLastError();
 }
 

@@ -66,7 +66,7 @@ def test_hash_u64(mx, o, n, seed, P):
 
 def test_hash_u64_known_answer(mx):
     P = 1 << 30
-    got = host(mx.hash_u64(dev(np.zeros(1, np.uint64)), 0, P), np.uint32).tolist()
+    got = host(mx.hash_u64(dev(np.zeros(1, np.uint64)), 0, P), np.uint32).reshape(-1).tolist()
     want = [pins.SPLITMIX0[0] >> 34, P + (pins.SPLITMIX0[1] >> 34), 2 * P + (pins.SPLITMIX0[2] >> 34)]
     assert got == want
 
@@ -166,10 +166,11 @@ def test_peel_generic(mx, o, record, trial):
 
 
 def test_peel_long_chain(mx, o):
-    """A chain peels one edge per round from each end: about n/2 rounds."""
+    """Overlapping triples (i, i+1, i+2): only the two ends have a degree-1 vertex, so the
+    chain peels one edge per round from each end, about n/2 rounds."""
     n = 3001
-    edges = np.array([[2 * i, 2 * i + 1, 2 * i + 2] for i in range(n)], np.uint32)
-    got, ref = _peel_both(mx, o, edges, 2 * n + 1)
+    edges = np.array([[i, i + 1, i + 2] for i in range(n)], np.uint32)
+    got, ref = _peel_both(mx, o, edges, n + 2)
     assert ref["n_rounds"] > 1000
     _assert_peel_equal(got, ref)
 
