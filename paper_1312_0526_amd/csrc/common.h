@@ -80,6 +80,69 @@ __device__ __forceinline__ uint64_t wave_append(unsigned long long* tail, bool w
     return base + lanes_below(b1) + lanes_below(b2);
 }
 
+// Block-wide append-only output with LDS staging.  Each call, every thread of the block offers
+// up to two values; they are packed into an LDS buffer (wave ballot + lane prefix, then a
+// prefix over the block's waves) and the buffer is copied out with a single atomicAdd on the
+// global cursor whenever the next call could overflow it, and once at the end.  Every thread
+// of the block must make the same sequence of calls (uniform loops only).
+template <int kBlock, int kCap>
+struct BlockAppender {
+    static_assert(kCap >= 4 * kBlock, "buffer must hold several calls");
+    uint32_t buf[kCap];
+    uint32_t wtot[kBlock / kWave];
+    uint32_t count;
+    unsigned long long base;
+
+    __device__ void init()
+    {
+        if (threadIdx.x == 0)
+            count = 0;
+        __syncthreads();
+    }
+
+    __device__ void flush(unsigned long long* tail, uint32_t* out)
+    {
+        if (threadIdx.x == 0 && count)
+            base = atomicAdd(tail, (unsigned long long)count);
+        __syncthreads();
+        const uint32_t c = count;
+        for (uint32_t i = threadIdx.x; i < c; i += kBlock)
+            out[base + i] = buf[i];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            count = 0;
+        __syncthreads();
+    }
+
+    __device__ void push(bool want1, uint32_t v1, bool want2, uint32_t v2, unsigned long long* tail, uint32_t* out)
+    {
+        const uint32_t w = threadIdx.x / kWave;
+        uint64_t b1 = __ballot(want1);
+        uint64_t b2 = __ballot(want2);
+        if ((threadIdx.x & (kWave - 1)) == 0)
+            wtot[w] = (uint32_t)(__popcll(b1) + __popcll(b2));
+        __syncthreads();
+        uint32_t off = count;
+        for (uint32_t q = 0; q < w; q++)
+            off += wtot[q];
+        off += lanes_below(b1) + lanes_below(b2);
+        if (want1)
+            buf[off++] = v1;
+        if (want2)
+            buf[off] = v2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (uint32_t q = 0; q < kBlock / kWave; q++)
+                t += wtot[q];
+            count += t;
+        }
+        __syncthreads();
+        if (count > kCap - 2 * kBlock)
+            flush(tail, out);
+    }
+};
+
 // ----- per-vertex packed incidence record (Section 4.1) ----------------------------------
 // Each vertex keeps its degree and a combination of the ids of its incident edges from which
 // the single remaining edge is read off when the degree is 1.

@@ -18,6 +18,9 @@
 
 namespace mphx {
 
+// LDS-staged appender of the frontier / layer arrays (16 KB per block).
+using Appender = BlockAppender<256, 4096>;
+
 // ------------------------------------------------------------------------------------------
 // Degree + label build from a caller-provided edge list, with validation.
 // ------------------------------------------------------------------------------------------
@@ -54,6 +57,8 @@ template <class Rec>
 __global__ __launch_bounds__(256) void k_frontier_init(const uint64_t* __restrict__ rec, uint64_t m,
                                                        uint32_t* __restrict__ front, Ctrl* ctrl)
 {
+    __shared__ Appender app;
+    app.init();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         uint64_t v = base + threadIdx.x;
@@ -64,10 +69,9 @@ __global__ __launch_bounds__(256) void k_frontier_init(const uint64_t* __restric
             if (d > kMaxDegree)
                 atomicOr(&ctrl->err, kErrDegree);
         }
-        uint64_t pos = wave_append(&ctrl->ftail, one, false);
-        if (one)
-            front[pos] = (uint32_t)v;
+        app.push(one, (uint32_t)v, false, 0u, &ctrl->ftail, front);
     }
+    app.flush(&ctrl->ftail, front);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -83,6 +87,14 @@ __global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec,
     const uint64_t hi = *(volatile unsigned long long*)&ctrl->ftail;  // no push during a claim
     if (blockIdx.x == 0 && threadIdx.x == 0)
         fstart[r + 1] = hi;
+    if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
+        return;  // whole block idle (uniform)
+    __shared__ Appender app;
+    __shared__ uint32_t nclaims;
+    if (threadIdx.x == 0)
+        nclaims = 0;
+    app.init();
+    uint32_t myclaims = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
@@ -106,13 +118,15 @@ __global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec,
                 first = ((old >> sh) & 0xFFu) == 0;
             }
         }
-        uint64_t pos = wave_append(&ctrl->ltail, first, false);
-        if (first)
-            layer[pos] = e;
-        uint64_t cb = __ballot(claimed);
-        if (cb && (int)__lane_id() == __ffsll((long long)__ballot(1)) - 1)
-            atomicAdd(&ctrl->claims, (unsigned long long)__popcll(cb));
+        myclaims += claimed;
+        app.push(first, e, false, 0u, &ctrl->ltail, layer);
     }
+    app.flush(&ctrl->ltail, layer);
+    if (myclaims)
+        atomicAdd(&nclaims, myclaims);
+    __syncthreads();
+    if (threadIdx.x == 0 && nclaims)
+        atomicAdd(&ctrl->claims, (unsigned long long)nclaims);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -132,6 +146,10 @@ __global__ __launch_bounds__(256) void k_apply(uint64_t* __restrict__ rec, uint3
         if (hi == lo)
             atomicMin(&ctrl->nrounds, r);
     }
+    if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
+        return;  // whole block idle (uniform)
+    __shared__ Appender app;
+    app.init();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
@@ -155,12 +173,9 @@ __global__ __launch_bounds__(256) void k_apply(uint64_t* __restrict__ rec, uint3
                 npush++;
             }
         }
-        uint64_t pos = wave_append(&ctrl->ftail, npush >= 1, npush >= 2);
-        if (npush >= 1)
-            front[pos] = push0;
-        if (npush >= 2)
-            front[pos + 1] = push1;
+        app.push(npush >= 1, push0, npush >= 2, push1, &ctrl->ftail, front);
     }
+    app.flush(&ctrl->ftail, front);
 }
 
 // ------------------------------------------------------------------------------------------
