@@ -33,6 +33,7 @@ CONFIGS = {
     "c2": dict(kind="u64", n=1 << 27, workload="mwhc_u64_n2^27_gamma1.23"),
     "c3": dict(kind="str", n=1 << 31, workload="mwhc_str_n2^31_mean60B_gamma1.23"),
 }
+BATCH_WORKLOAD = "mwhc_batched_65536_buckets_loguniform_100_1e6_u64_gamma1.23"
 
 
 def log(*a):
@@ -70,6 +71,61 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
     return 0.0
 
 
+def batched_leg(args, mx, torch, np, workloads) -> dict:
+    """65,536 independent u64 buckets, sizes floor(100 * 10^(4u)), one captured persistent
+    launch per step; beside it the plain path on a sample of the same buckets."""
+    dev = torch.device("cuda:0")
+    sizes = workloads.bucket_sizes(args.batch_buckets, 100, 1_000_000, seed=0)
+    off = np.zeros(len(sizes) + 1, np.uint64)
+    off[1:] = np.cumsum(sizes)
+    total = int(off[-1])
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).to(dev))
+    bb = mx.BatchBuild(off, block=args.batch_block, grid=args.batch_grid)
+    bb.capture(keys)
+    log(f"[batched] {len(sizes)} buckets, {total} keys ({total * 8 / 1e9:.1f} GB), slots "
+        f"{bb.ws.numel() / 1e9:.1f} GB, max bucket {bb.max_bucket}")
+    for _ in range(args.warmup):
+        bb.launch()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bb.launch()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    res = bb.bucket_results()
+    ok = res["status"] == 0
+    ok_keys = int(sizes[ok].sum())
+    sec = float(np.median(times))
+    extra_tries = int(res["tries"].sum() - len(res))
+    log(f"[batched] median {sec * 1000:.1f} ms/step, {ok_keys / sec / 1e9:.3f} G keys/s, "
+        f"{int((~ok).sum())} failed buckets, {extra_tries} retries")
+    # the plain path (one mphf_build_u64 per bucket) on a random sample of the same buckets
+    rng = np.random.default_rng(1)
+    sample = rng.choice(len(sizes), size=min(args.plain_sample, len(sizes)), replace=False)
+    plain_keys = plain_sec = 0
+    for b in sample:
+        kb = keys[int(off[b]):int(off[b + 1])]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mx.mphf_build_u64(kb, seed=0)
+        torch.cuda.synchronize()
+        plain_sec += time.perf_counter() - t0
+        plain_keys += int(sizes[b])
+    plain_rate = plain_keys / plain_sec
+    log(f"[batched] plain path on {len(sample)} sampled buckets: {plain_rate / 1e9:.3f} G keys/s")
+    bb.destroy_graph()
+    out = dict(workload=BATCH_WORKLOAD, buckets=len(sizes), keys=total, ms_per_step=round(sec * 1000, 3),
+               value=round(ok_keys / sec, 1), unit="edges/s", failed_buckets=int((~ok).sum()),
+               retries=extra_tries, block=bb.tuning.block, grid=bb.tuning.grid,
+               plain_same_buckets=dict(value=round(plain_rate, 1), unit="edges/s", buckets=len(sample)),
+               speedup_vs_plain=round(ok_keys / sec / plain_rate, 2))
+    del bb, keys
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +136,11 @@ def main() -> int:
     ap.add_argument("--record", type=int, default=-1, help="per-vertex record layout (0 xor, 1 sum)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="keys in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="plain,batched", help="comma list of: plain, batched")
+    ap.add_argument("--batch-buckets", type=int, default=65536)
+    ap.add_argument("--batch-block", type=int, default=0)
+    ap.add_argument("--batch-grid", type=int, default=0)
+    ap.add_argument("--plain-sample", type=int, default=256)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -186,6 +247,15 @@ def main() -> int:
                           f"{cs:.1f} s (status {rc})")
         log(f"[bench] oracle: {ns} keys in {cs:.2f} s = {ns / cs / 1e6:.3f} M keys/s")
 
+    legs = set(args.legs.split(","))
+    del ws, codes, rank
+    if cfg["kind"] == "u64":
+        del keys
+    else:
+        del data, offs
+    torch.cuda.empty_cache()
+    batched = batched_leg(args, mx, torch, np, workloads) if "batched" in legs else None
+
     out = {
         "metric": "edges peeled/s (hash+peel+assign+rank), plain single-hypergraph build",
         "value": round(value, 1),
@@ -205,6 +275,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phase_rows,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     return 0

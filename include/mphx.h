@@ -166,6 +166,61 @@ MPHX_API int mphx_check_bijection(const uint64_t* vals, uint64_t n, void* scratc
                          void* stream);
 
 /* ---------------------------------------------------------------------------------------
+ * Batched builds: B independent u64 key buckets (bucket b = keys[bucket_off[b],
+ * bucket_off[b+1])), each an MWHC MPHF of its own exactly as mphx_mphf_build_u64 would build
+ * it with the same seed, gamma and max_tries (Section 3 / 4.2 / 4.3 per bucket; independent
+ * buckets as in the HEM scheme of Section 3).  One persistent launch: every workgroup takes
+ * the next bucket from a device queue (the `order` array, largest first) and builds it alone,
+ * including the retries, so nothing returns to the host between buckets.
+ *
+ * mphx_batch_layout (all host arrays): from the B+1 bucket offsets, writes code_off / rank_off
+ * (B+1 entries each: where bucket b's ceil(m_b/32) code words and ceil(m_b/512) rank samples
+ * start in the concatenated outputs; the last entry is the total), order (B bucket ids by
+ * decreasing size) and *max_bucket.  Returns MPHX_EINVAL if offsets decrease or a bucket
+ * needs 3P > 2^32 vertices.
+ * mphx_build_batch_u64: device arrays keys, bucket_off, order, code_off, rank_off, codes,
+ * rank, results (B entries); ws (dev, 256-byte aligned) of mphx_batch_workspace_bytes(...)
+ * bytes for the same max_bucket and tuning.  Enqueues only (no synchronisation, no host
+ * read-back), so the call can be captured into a HIP graph.  A bucket larger than max_bucket
+ * gets status MPHX_EINVAL and is left untouched.  Per-bucket status: MPHX_OK, MPHX_ECORE
+ * (2-core after max_tries; duplicate keys also end here), MPHX_ERANGE (degree above 255).
+ * tuning may be NULL (block 1024, one workgroup per compute unit).
+ * mphx_graph_capture_batch_u64 records the same work into an instantiated graph (*graph);
+ * mphx_graph_launch replays it on a stream; mphx_graph_destroy frees it.
+ * --------------------------------------------------------------------------------------- */
+typedef struct mphx_bucket_result {
+    uint64_t seed_used;
+    uint32_t tries;
+    int32_t status;
+    uint32_t n_rounds;
+    uint32_t reserved;
+} mphx_bucket_result;
+
+typedef struct mphx_batch_tuning {
+    uint32_t block;  /* threads per workgroup: 256, 512 or 1024 (0 = 1024) */
+    uint32_t grid;   /* workgroups in the persistent launch (0 = one per compute unit) */
+} mphx_batch_tuning;
+
+MPHX_API int mphx_batch_layout(const uint64_t* bucket_off, uint32_t B, uint32_t gamma_num, uint32_t gamma_den,
+                               uint64_t* code_off, uint64_t* rank_off, uint32_t* order, uint64_t* max_bucket);
+MPHX_API size_t mphx_batch_workspace_bytes(uint64_t max_bucket, uint32_t gamma_num, uint32_t gamma_den,
+                                           const mphx_batch_tuning* tuning);
+MPHX_API int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order,
+                                  uint32_t B, uint64_t max_bucket, uint64_t seed, uint32_t gamma_num,
+                                  uint32_t gamma_den, uint32_t max_tries, const uint64_t* code_off,
+                                  const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                                  mphx_bucket_result* results, void* ws, size_t ws_bytes,
+                                  const mphx_batch_tuning* tuning, void* stream);
+MPHX_API int mphx_graph_capture_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order,
+                                          uint32_t B, uint64_t max_bucket, uint64_t seed, uint32_t gamma_num,
+                                          uint32_t gamma_den, uint32_t max_tries, const uint64_t* code_off,
+                                          const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                                          mphx_bucket_result* results, void* ws, size_t ws_bytes,
+                                          const mphx_batch_tuning* tuning, void** graph);
+MPHX_API int mphx_graph_launch(void* graph, void* stream);
+MPHX_API int mphx_graph_destroy(void* graph);
+
+/* ---------------------------------------------------------------------------------------
  * Synthetic key sets on the device (benchmark inputs; the same definitions as the host-side
  * generators that the tests use).  GAMMA and fin as above; S(s, t) = fin(s + t*GAMMA).
  *   u64 keys:     key_i = S(gen_seed, i + 1), i in [start, start + n).
@@ -177,6 +232,9 @@ MPHX_API int mphx_check_bijection(const uint64_t* vals, uint64_t n, void* scratc
  * mphx_gen_str_bytes then fills bytes (dev) from the offsets.  qtable (dev): 65536 uint16.
  * --------------------------------------------------------------------------------------- */
 MPHX_API int mphx_gen_keys_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, void* stream);
+/* Bucketed u64 key sets: bucket b (keys[off[b], off[b+1]), off (dev) B+1 entries) is the u64
+ * key set of generator seed S(0, b + 1). */
+MPHX_API int mphx_gen_buckets_u64(uint64_t* keys, const uint64_t* off, uint32_t B, void* stream);
 MPHX_API int mphx_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start,
                          const uint16_t* qtable, void* stream);
 MPHX_API size_t mphx_scan_scratch_bytes(uint64_t count);

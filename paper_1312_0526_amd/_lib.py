@@ -63,6 +63,15 @@ _SIGS = {
     "mphx_gen_str_bytes": (_i32, [_vp, _vp, _u64, _u64, _u64, _vp]),
     "mphx_set_option": (_i32, [C.c_char_p, C.c_int64]),
     "mphx_get_option": (C.c_int64, [C.c_char_p]),
+    "mphx_gen_buckets_u64": (_i32, [_vp, _vp, _u32, _vp]),
+    "mphx_batch_layout": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp, _vp, C.POINTER(C.c_uint64)]),
+    "mphx_batch_workspace_bytes": (_sz, [_u64, _u32, _u32, _vp]),
+    "mphx_build_batch_u64": (_i32, [_vp, _vp, _vp, _u32, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp,
+                                    _vp, _sz, _vp, _vp]),
+    "mphx_graph_capture_batch_u64": (_i32, [_vp, _vp, _vp, _u32, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp,
+                                            _vp, _vp, _sz, _vp, C.POINTER(C.c_void_p)]),
+    "mphx_graph_launch": (_i32, [_vp, _vp]),
+    "mphx_graph_destroy": (_i32, [_vp]),
     "mphx_phase_times": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_uint64), _i32, _i32]),
     "mphx_phase_name": (C.c_char_p, [_i32]),
 }
@@ -298,3 +307,118 @@ def gen_str_keys(n: int, qtable: torch.Tensor, gen_seed: int = 0, start: int = 0
     if rc:
         _err(rc)
     return data, offs
+
+
+# ------------------------------------------------------------------------------------------
+# batched builds
+# ------------------------------------------------------------------------------------------
+class BatchTuning(C.Structure):
+    _fields_ = [("block", C.c_uint32), ("grid", C.c_uint32)]
+
+
+BUCKET_RESULT = None
+
+
+def _bucket_dtype():
+    import numpy as np
+
+    return np.dtype([("seed_used", "<u8"), ("tries", "<u4"), ("status", "<i4"), ("n_rounds", "<u4"),
+                     ("reserved", "<u4")])
+
+
+def gen_buckets_u64(bucket_off: torch.Tensor) -> torch.Tensor:
+    """Device keys of every bucket (bucket b: generator seed S(0, b + 1))."""
+    _check(bucket_off, torch.int64, "bucket_off")
+    B = bucket_off.numel() - 1
+    total = int(bucket_off[-1].item())
+    keys = torch.empty(max(total, 1), dtype=torch.int64, device=bucket_off.device)
+    rc = lib().mphx_gen_buckets_u64(_ptr(keys), _ptr(bucket_off), B, _stream(bucket_off.device))
+    if rc:
+        _err(rc)
+    return keys
+
+
+class BatchBuild:
+    """A batched build plan: B buckets of u64 keys with host offsets `bucket_off` (B+1)."""
+
+    def __init__(self, bucket_off, device="cuda", gamma=(123, 100), max_tries=64, seed=0, block=0, grid=0):
+        import numpy as np
+
+        off = np.ascontiguousarray(bucket_off, dtype=np.uint64)
+        self.B = len(off) - 1
+        self.gamma, self.max_tries, self.seed = gamma, max_tries, seed
+        self.device = torch.device(device)
+        code_off = np.zeros(self.B + 1, np.uint64)
+        rank_off = np.zeros(self.B + 1, np.uint64)
+        order = np.zeros(max(self.B, 1), np.uint32)
+        mx = C.c_uint64(0)
+        rc = lib().mphx_batch_layout(off.ctypes.data, self.B, gamma[0], gamma[1], code_off.ctypes.data,
+                                     rank_off.ctypes.data, order.ctypes.data, C.byref(mx))
+        if rc:
+            _err(rc)
+        self.max_bucket = int(mx.value)
+        self.host_off, self.code_off_h, self.rank_off_h = off, code_off, rank_off
+        self.tuning = BatchTuning(block, grid)
+        dev = self.device
+        self.bucket_off = torch.from_numpy(off.view(np.int64)).to(dev)
+        self.order = torch.from_numpy(order.view(np.int32)).to(dev)
+        self.code_off = torch.from_numpy(code_off.view(np.int64)).to(dev)
+        self.rank_off = torch.from_numpy(rank_off.view(np.int64)).to(dev)
+        self.codes = torch.zeros(max(int(code_off[-1]), 1), dtype=torch.int64, device=dev)
+        self.rank = torch.zeros(max(int(rank_off[-1]), 1), dtype=torch.int64, device=dev)
+        self.results = torch.zeros(max(self.B, 1) * 24, dtype=torch.uint8, device=dev)
+        ws_bytes = lib().mphx_batch_workspace_bytes(self.max_bucket, gamma[0], gamma[1], C.byref(self.tuning))
+        if ws_bytes == 0:
+            _err(EINVAL)
+        self.ws = _workspace(ws_bytes, dev)
+        self.graph = None
+
+    def _args(self, keys):
+        _check(keys, torch.int64, "keys")
+        return (_ptr(keys), _ptr(self.bucket_off), _ptr(self.order), self.B, self.max_bucket, self.seed,
+                self.gamma[0], self.gamma[1], self.max_tries, _ptr(self.code_off), _ptr(self.rank_off),
+                _ptr(self.codes), _ptr(self.rank), _ptr(self.results), _ptr(self.ws), self.ws.numel(),
+                C.byref(self.tuning))
+
+    def run(self, keys, max_bucket=None):
+        """Enqueue the whole batch on the current stream (no synchronisation)."""
+        args = list(self._args(keys))
+        if max_bucket is not None:
+            args[4] = max_bucket
+        rc = lib().mphx_build_batch_u64(*args, _stream(self.device))
+        if rc:
+            _err(rc)
+
+    def capture(self, keys):
+        """Record the batch into a HIP graph (replayed by launch())."""
+        self.destroy_graph()
+        g = C.c_void_p()
+        rc = lib().mphx_graph_capture_batch_u64(*self._args(keys), C.byref(g))
+        if rc:
+            _err(rc)
+        self.graph = g
+
+    def launch(self):
+        rc = lib().mphx_graph_launch(self.graph, _stream(self.device))
+        if rc:
+            _err(rc)
+
+    def destroy_graph(self):
+        if self.graph is not None and self.graph.value:
+            lib().mphx_graph_destroy(self.graph)
+        self.graph = None
+
+    def __del__(self):
+        try:
+            self.destroy_graph()
+        except Exception:
+            pass
+
+    def bucket_results(self):
+        return self.results.cpu().numpy()[: self.B * 24].view(_bucket_dtype())
+
+    def bucket_codes(self, b):
+        return self.codes[int(self.code_off_h[b]):int(self.code_off_h[b + 1])]
+
+    def bucket_rank(self, b):
+        return self.rank[int(self.rank_off_h[b]):int(self.rank_off_h[b + 1])]

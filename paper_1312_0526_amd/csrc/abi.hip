@@ -690,6 +690,14 @@ int mphx_gen_keys_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t st
     return MPHX_OK;
 }
 
+int mphx_gen_buckets_u64(uint64_t* keys, const uint64_t* off, uint32_t B, void* stream)
+{
+    g_err.clear();
+    if (B && (!keys || !off)) return fail(MPHX_EINVAL, "null pointer");
+    HIP_TRY(launch_gen_buckets_u64(keys, off, B, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
 int mphx_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start, const uint16_t* qtable,
                          void* stream)
 {
@@ -718,6 +726,172 @@ int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_
     if (n && (!bytes || !offs)) return fail(MPHX_EINVAL, "null pointer");
     if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
     HIP_TRY(launch_gen_str_bytes(bytes, offs, n, gen_seed, start, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Batched builds
+// ------------------------------------------------------------------------------------------
+namespace {
+
+static_assert(sizeof(mphx_bucket_result) == sizeof(BucketResult), "bucket result layouts agree");
+
+int batch_tuning(const mphx_batch_tuning* t, unsigned& block, unsigned& grid)
+{
+    block = (t && t->block) ? t->block : 1024;
+    if (block != 256 && block != 512 && block != 1024)
+        return fail(MPHX_EINVAL, "batch block must be 256, 512 or 1024");
+    grid = t ? t->grid : 0;
+    if (grid == 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        grid = (unsigned)cus;
+    }
+    if (grid > (1u << 20))
+        return fail(MPHX_EINVAL, "batch grid too large");
+    return MPHX_OK;
+}
+
+int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order, uint32_t B,
+                  uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+                  const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                  mphx_bucket_result* results, void* ws, size_t ws_bytes, const mphx_batch_tuning* t,
+                  hipStream_t s)
+{
+    if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
+    if (B == 0) return MPHX_OK;
+    if (!keys || !bucket_off || !order || !code_off || !rank_off || !codes || !rank || !results)
+        return fail(MPHX_EINVAL, "null pointer argument");
+    if (max_bucket >= 0xFFFFFFFFull || 3 * mphx_part_size(max_bucket, gnum, gden) > 0x100000000ull)
+        return fail(MPHX_EINVAL, "max_bucket too large");
+    unsigned block = 0, grid = 0;
+    int rc = batch_tuning(t, block, grid);
+    if (rc) return rc;
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    size_t need = mphx_batch_workspace_bytes(max_bucket, gnum, gden, t);
+    if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    BatchLaunch L{};
+    L.keys = keys;
+    L.bucket_off = bucket_off;
+    L.order = order;
+    L.B = B;
+    L.seed = seed;
+    L.gnum = gnum;
+    L.gden = gden;
+    L.max_tries = max_tries;
+    L.code_off = code_off;
+    L.rank_off = rank_off;
+    L.codes = codes;
+    L.rank = rank;
+    L.results = reinterpret_cast<BucketResult*>(results);
+    L.next = reinterpret_cast<unsigned int*>(ws);
+    L.slots = reinterpret_cast<uint8_t*>(ws) + 256;
+    L.slot_bytes = batch_slot_bytes(max_bucket, gnum, gden);
+    L.max_n = max_bucket;
+    L.block = block;
+    L.grid = grid;
+    HIP_TRY(launch_batch(L, s));
+    return MPHX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mphx_batch_layout(const uint64_t* bucket_off, uint32_t B, uint32_t gnum, uint32_t gden, uint64_t* code_off,
+                      uint64_t* rank_off, uint32_t* order, uint64_t* max_bucket)
+{
+    g_err.clear();
+    if (!bucket_off || !code_off || !rank_off || !order || !max_bucket) return fail(MPHX_EINVAL, "null pointer");
+    if (gnum == 0 || gden == 0) return fail(MPHX_EINVAL, "bad gamma");
+    uint64_t cw = 0, cr = 0, mx = 0;
+    std::vector<std::pair<uint64_t, uint32_t>> sz(B);
+    for (uint32_t b = 0; b < B; b++) {
+        if (bucket_off[b + 1] < bucket_off[b]) return fail(MPHX_EINVAL, "bucket offsets decrease at %u", b);
+        uint64_t n = bucket_off[b + 1] - bucket_off[b];
+        uint64_t m = 3 * mphx_part_size(n, gnum, gden);
+        if (n >= 0xFFFFFFFFull || m > 0x100000000ull) return fail(MPHX_EINVAL, "bucket %u too large", b);
+        code_off[b] = cw;
+        rank_off[b] = cr;
+        cw += (m + 31) / 32;
+        cr += (m + 511) / 512;
+        mx = std::max(mx, n);
+        sz[b] = {n, b};
+    }
+    code_off[B] = cw;
+    rank_off[B] = cr;
+    std::stable_sort(sz.begin(), sz.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (uint32_t b = 0; b < B; b++) order[b] = sz[b].second;
+    *max_bucket = mx;
+    return MPHX_OK;
+}
+
+size_t mphx_batch_workspace_bytes(uint64_t max_bucket, uint32_t gnum, uint32_t gden, const mphx_batch_tuning* t)
+{
+    unsigned block = 0, grid = 0;
+    if (batch_tuning(t, block, grid)) return 0;
+    return 256 + (size_t)grid * batch_slot_bytes(max_bucket, gnum, gden);
+}
+
+int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order, uint32_t B,
+                         uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+                         const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                         mphx_bucket_result* results, void* ws, size_t ws_bytes, const mphx_batch_tuning* t,
+                         void* stream)
+{
+    g_err.clear();
+    return batch_enqueue(keys, bucket_off, order, B, max_bucket, seed, gnum, gden, max_tries, code_off, rank_off,
+                         codes, rank, results, ws, ws_bytes, t, (hipStream_t)stream);
+}
+
+int mphx_graph_capture_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order,
+                                 uint32_t B, uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden,
+                                 uint32_t max_tries, const uint64_t* code_off, const uint64_t* rank_off,
+                                 uint64_t* codes, uint64_t* rank, mphx_bucket_result* results, void* ws,
+                                 size_t ws_bytes, const mphx_batch_tuning* t, void** graph)
+{
+    g_err.clear();
+    if (!graph) return fail(MPHX_EINVAL, "null graph pointer");
+    *graph = nullptr;
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = MPHX_OK;
+    if (e == hipSuccess) {
+        rc = batch_enqueue(keys, bucket_off, order, B, max_bucket, seed, gnum, gden, max_tries, code_off, rank_off,
+                           codes, rank, results, ws, ws_bytes, t, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (rc == MPHX_OK && e2 != hipSuccess) e = e2;
+    }
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess && rc == MPHX_OK)
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(MPHX_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    *graph = ex;
+    return MPHX_OK;
+}
+
+int mphx_graph_launch(void* graph, void* stream)
+{
+    g_err.clear();
+    if (!graph) return fail(MPHX_EINVAL, "null graph");
+    HIP_TRY(hipGraphLaunch((hipGraphExec_t)graph, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_graph_destroy(void* graph)
+{
+    g_err.clear();
+    if (!graph) return MPHX_OK;
+    HIP_TRY(hipGraphExecDestroy((hipGraphExec_t)graph));
     return MPHX_OK;
 }
 

@@ -28,6 +28,16 @@ struct Ctrl {
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte slot");
 
+// Per-bucket outcome of a batched build (same layout as mphx_bucket_result).
+struct BucketResult {
+    uint64_t seed_used;
+    uint32_t tries;
+    int32_t status;  // 0 ok, 1 a 2-core remained after every try, -2 degree above 255
+    uint32_t n_rounds;
+    uint32_t reserved;
+};
+static_assert(sizeof(BucketResult) == 24, "BucketResult is 24 bytes");
+
 // SplitMix64 output function (Steele, Lea & Flood 2014; Stafford's Mix13 constants).
 __device__ __forceinline__ uint64_t fin(uint64_t z)
 {

@@ -72,6 +72,18 @@ __global__ __launch_bounds__(256) void k_gen_u64(uint64_t* __restrict__ keys, ui
         keys[i] = fin(gen_seed + (start + i + 1) * kGamma);
 }
 
+// Bucketed u64 key sets: bucket b uses generator seed S(0, b + 1); one block per bucket.
+__global__ __launch_bounds__(256) void k_gen_buckets_u64(uint64_t* __restrict__ keys, const uint64_t* __restrict__ off,
+                                                         uint32_t B)
+{
+    for (uint32_t b = blockIdx.x; b < B; b += gridDim.x) {
+        const uint64_t lo = off[b], n = off[b + 1] - lo;
+        const uint64_t gs = fin((uint64_t)(b + 1) * kGamma);
+        for (uint64_t j = threadIdx.x; j < n; j += blockDim.x)
+            keys[lo + j] = fin(gs + (j + 1) * kGamma);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_gen_str_len(uint32_t* __restrict__ lens, uint64_t n, uint64_t gen_seed,
                                                      uint64_t start, const uint16_t* __restrict__ qtable)
 {
@@ -172,6 +184,13 @@ hipError_t launch_gen_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_
 {
     if (n == 0) return hipSuccess;
     k_gen_u64<<<grid_cap(n, 16384), 256, 0, s>>>(keys, n, gen_seed, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_buckets_u64(uint64_t* keys, const uint64_t* off, uint32_t B, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    k_gen_buckets_u64<<<(B < 65536u ? B : 65536u), 256, 0, s>>>(keys, off, B);
     return hipGetLastError();
 }
 

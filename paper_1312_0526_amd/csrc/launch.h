@@ -27,6 +27,30 @@ struct PeelState {
     uint64_t rcap;          // rounds the start arrays can hold
 };
 
+// Everything one batched launch needs.
+struct BatchLaunch {
+    const uint64_t* keys;
+    const uint64_t* bucket_off;
+    const uint32_t* order;
+    uint32_t B;
+    uint64_t seed;
+    uint32_t gnum, gden, max_tries;
+    const uint64_t* code_off;
+    const uint64_t* rank_off;
+    uint64_t* codes;
+    uint64_t* rank;
+    BucketResult* results;
+    uint8_t* slots;
+    uint64_t slot_bytes;
+    uint64_t max_n;
+    unsigned int* next;
+    unsigned block, grid;
+};
+
+// batched builds (batch.hip)
+uint64_t batch_slot_bytes(uint64_t max_n, uint32_t gnum, uint32_t gden);
+hipError_t launch_batch(const BatchLaunch& L, hipStream_t s);
+
 // utilities (scan.hip)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
@@ -45,6 +69,7 @@ hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint
 hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
                            uint32_t* edges, uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s);
 hipError_t launch_gen_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, hipStream_t s);
+hipError_t launch_gen_buckets_u64(uint64_t* keys, const uint64_t* off, uint32_t B, hipStream_t s);
 hipError_t launch_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start,
                                   const uint16_t* qtable, hipStream_t s);
 hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t gen_seed, uint64_t start,

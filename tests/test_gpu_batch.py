@@ -1,0 +1,130 @@
+"""Batched builds (one persistent launch for many buckets) against the oracle, bucket by
+bucket, through the C ABI (GPU only).  Each bucket must equal the oracle's single build of
+the same keys with the same seed, including the retry count and the seed used."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mx():
+    import torch
+
+    import paper_1312_0526_amd as mx
+
+    assert torch.cuda.is_available()
+    mx.lib()
+    return mx
+
+
+@pytest.fixture(scope="module")
+def o():
+    return oracle.Oracle()
+
+
+def _offsets(sizes):
+    off = np.zeros(len(sizes) + 1, np.uint64)
+    off[1:] = np.cumsum(sizes)
+    return off
+
+
+def _host_keys(sizes):
+    return np.concatenate([workloads.u64_keys(int(s), gen_seed=workloads.bucket_gen_seed(b))
+                           for b, s in enumerate(sizes)]) if len(sizes) else np.zeros(0, np.uint64)
+
+
+def _check_buckets(mx, o, bb, keys_h, sizes, which=None):
+    res = bb.bucket_results()
+    off = _offsets(sizes)
+    which = range(len(sizes)) if which is None else which
+    for b in which:
+        kb = keys_h[int(off[b]):int(off[b + 1])]
+        rc, ref = o.mphf_build_u64(kb, seed=bb.seed, max_tries=bb.max_tries)
+        assert res[b]["status"] == rc, (b, sizes[b])
+        assert res[b]["tries"] == ref["tries"] and res[b]["seed_used"] == ref["seed_used"], b
+        if rc == 0:
+            assert res[b]["n_rounds"] == ref["n_rounds"], b
+            assert np.array_equal(bb.bucket_codes(b).cpu().numpy().view(np.uint64), ref["words"]), b
+            assert np.array_equal(bb.bucket_rank(b).cpu().numpy().view(np.uint64), ref["rank"]), b
+
+
+SIZES = np.concatenate([[1, 3, 7, 100, 101, 4096], workloads.bucket_sizes(250, 100, 30_000, seed=5)])
+
+
+@pytest.mark.parametrize("block,grid", [(256, 0), (512, 7), (1024, 3), (256, 1)])
+def test_batch_matches_oracle(mx, o, block, grid):
+    import torch
+
+    off = _offsets(SIZES)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    keys_h = _host_keys(SIZES)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64)[: len(keys_h)], keys_h)
+    bb = mx.BatchBuild(off, block=block, grid=grid)
+    bb.run(keys)
+    torch.cuda.synchronize()
+    _check_buckets(mx, o, bb, keys_h, SIZES)
+    res = bb.bucket_results()
+    assert (res["tries"] > 1).sum() > 20  # small buckets retry often at gamma 1.23
+
+
+def test_batch_large_buckets_sampled(mx, o):
+    import torch
+
+    sizes = workloads.bucket_sizes(64, 100, 1_000_000, seed=0)
+    off = _offsets(sizes)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    bb = mx.BatchBuild(off)
+    bb.run(keys)
+    torch.cuda.synchronize()
+    res = bb.bucket_results()
+    assert (res["status"] == 0).all()
+    keys_h = keys.cpu().numpy().view(np.uint64)
+    big = np.argsort(-sizes)[:2].tolist()
+    _check_buckets(mx, o, bb, keys_h, sizes, which=big + [5, 17, 40])
+
+
+def test_batch_graph_replays(mx, o):
+    """Capture once, replay several times with eager work and synchronisations between the
+    replays; every replay must reproduce the eager result."""
+    import torch
+
+    sizes = SIZES[:80]
+    off = _offsets(sizes)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    bb = mx.BatchBuild(off)
+    bb.run(keys)
+    torch.cuda.synchronize()
+    ref_codes, ref_rank, ref_res = bb.codes.clone(), bb.rank.clone(), bb.results.clone()
+    bb.capture(keys)
+    for rep in range(4):
+        bb.codes.zero_()
+        bb.rank.zero_()
+        bb.results.zero_()
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        bb.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(bb.codes, ref_codes), rep
+        assert torch.equal(bb.rank, ref_rank), rep
+        assert torch.equal(bb.results, ref_res), rep
+    bb.destroy_graph()
+    _check_buckets(mx, o, bb, _host_keys(sizes), sizes, which=range(0, 80, 7))
+
+
+def test_batch_rejects_oversize_bucket(mx):
+    import torch
+
+    sizes = np.array([50, 500, 60], np.int64)
+    off = _offsets(sizes)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    bb = mx.BatchBuild(off)
+    bb.results.fill_(0xAB)
+    bb.run(keys, max_bucket=100)  # slots sized for 500; the declared bound says 100
+    torch.cuda.synchronize()
+    res = bb.bucket_results()
+    assert res[1]["status"] == mx.EINVAL
+    assert res[0]["status"] in (0, 1) and res[2]["status"] in (0, 1)
