@@ -126,6 +126,78 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     return out
 
 
+SERVE_WORKLOAD = "mwhc_served_poisson_sizes_loguniform_1e3_1e8_u64_or_str_gamma1.23"
+
+
+def served_leg(args, mx, torch, np, workloads) -> dict:
+    """Poisson stream of builds (sizes log-uniform 1e3..1e8, u64 or string keys 50/50)
+    submitted to the build server at its arrival times; rates swept around saturation."""
+    dev = torch.device("cuda:0")
+    max_n = args.serve_max
+    keys = mx.gen_keys_u64(max_n, gen_seed=7, device=dev)
+    q = torch.from_numpy(workloads.quantile_table().view(np.int16)).to(dev)
+    data, offs = mx.gen_str_keys(max_n, q, gen_seed=8, device=dev)
+    torch.cuda.synchronize()
+    nreq = args.serve_requests
+    sizes = workloads.request_sizes(nreq, 1000, max_n, seed=1)
+    kinds = (workloads.stream(np.uint64(2), np.arange(1, nreq + 1, dtype=np.uint64)) & np.uint64(1)).astype(int)
+    offs_slices = {}
+
+    def submit(srv, i):
+        n = int(sizes[i])
+        if kinds[i] == 0:
+            return srv.submit_u64(keys[:n], seed=i)
+        if n not in offs_slices:
+            offs_slices[n] = offs[: n + 1]
+        return srv.submit_str(data, offs_slices[n], seed=i)
+
+    mean_n = float(sizes.mean())
+    # saturation estimate: everything submitted at once
+    srv = mx.Server(hbm_budget=args.serve_budget, slots=args.serve_slots)
+    warm = [submit(srv, i) for i in range(min(8, nreq))]
+    for t in warm:
+        srv.wait(t)
+        srv.release(t)
+    t0 = mx.Server.clock()
+    tickets = [submit(srv, i) for i in range(nreq)]
+    res = [srv.wait(t) for t in tickets]
+    for t in tickets:
+        srv.release(t)
+    span = max(r["t_done"] for r in res) - t0
+    sat_rate = nreq / span
+    log(f"[served] saturation: {nreq} builds in {span:.2f} s = {sat_rate:.1f} builds/s, "
+        f"{sizes.sum() / span / 1e9:.3f} G keys/s (mean size {mean_n:.0f})")
+    rows = []
+    for frac in args.serve_rates:
+        rate = frac * sat_rate
+        arr = workloads.poisson_arrivals(nreq, rate, seed=int(frac * 1000))
+        start = mx.Server.clock() + 0.01
+        tickets = []
+        for i in range(nreq):
+            while mx.Server.clock() < start + arr[i]:
+                pass
+            tickets.append(submit(srv, i))
+        res = [srv.wait(t) for t in tickets]
+        for t in tickets:
+            srv.release(t)
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        bad = sum(r["status"] != 0 for r in res)
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        row = dict(rate_frac=frac, offered_builds_per_s=round(rate, 2), builds_per_s=round(nreq / span, 2),
+                   edges_per_s=round(float(sizes.sum()) / span, 1), p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                   p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3), failed=int(bad))
+        rows.append(row)
+        log(f"[served] rate {frac:.2f}x = {rate:.1f}/s: p50 {row['p50_ms']:.2f} ms, p99 {row['p99_ms']:.2f} ms, "
+            f"{row['edges_per_s'] / 1e9:.3f} G keys/s, {bad} failed")
+    st = srv.stats()
+    srv.close()
+    del keys, data, offs
+    torch.cuda.empty_cache()
+    return dict(workload=SERVE_WORKLOAD, requests_per_rate=nreq, mean_keys=round(mean_n, 1),
+                slots=args.serve_slots, hbm_budget=args.serve_budget, peak_pool_in_use=st["peak_in_use"],
+                saturation_builds_per_s=round(sat_rate, 2), rates=rows)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,11 +208,16 @@ def main() -> int:
     ap.add_argument("--record", type=int, default=-1, help="per-vertex record layout (0 xor, 1 sum)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="keys in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="plain,batched", help="comma list of: plain, batched")
+    ap.add_argument("--legs", default="plain,batched,served", help="comma list of: plain, batched, served")
     ap.add_argument("--batch-buckets", type=int, default=65536)
     ap.add_argument("--batch-block", type=int, default=0)
     ap.add_argument("--batch-grid", type=int, default=0)
     ap.add_argument("--plain-sample", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-max", type=int, default=100_000_000)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget", type=int, default=64 << 30)
+    ap.add_argument("--serve-rates", type=lambda s: [float(x) for x in s.split(",")], default=[0.5, 0.9])
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -255,6 +332,7 @@ def main() -> int:
         del data, offs
     torch.cuda.empty_cache()
     batched = batched_leg(args, mx, torch, np, workloads) if "batched" in legs else None
+    served = served_leg(args, mx, torch, np, workloads) if "served" in legs else None
 
     out = {
         "metric": "edges peeled/s (hash+peel+assign+rank), plain single-hypergraph build",
@@ -276,6 +354,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "phases": phase_rows,
         "batched": batched,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
     return 0

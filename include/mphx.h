@@ -221,6 +221,61 @@ MPHX_API int mphx_graph_launch(void* graph, void* stream);
 MPHX_API int mphx_graph_destroy(void* graph);
 
 /* ---------------------------------------------------------------------------------------
+ * Build server: continuous admission of MPHF builds of mixed sizes under an HBM budget.
+ *
+ * mphx_server_create allocates one device pool of hbm_budget bytes on `device` (the only
+ * device allocation the library makes) and starts `slots` worker threads (1..64), each with its
+ * own HIP stream.  mphx_server_submit queues a request and returns a ticket at once; the
+ * request's keys and output buffers are caller-owned device memory that must stay valid until
+ * the ticket completes.  Requests are admitted in arrival order as workers and pool memory
+ * free up (a later request that fits may pass the queue head a bounded number of times);
+ * admitted builds run concurrently.  A request whose workspace exceeds the whole budget
+ * completes at once with MPHX_ENOMEM; smaller ones wait and never fail for lack of memory.
+ * Each result (status, tries, seed, codes, rank) is exactly what mphx_mphf_build_u64/_str
+ * returns for the request alone.  Times are seconds of mphx_server_clock() (steady clock):
+ * t_submit at submission, t_start at admission, t_done when the outputs are complete.
+ * mphx_server_poll returns 0 (done, *res filled) or 1 (pending); mphx_server_wait blocks.
+ * mphx_server_destroy finishes all queued work, then frees the pool.
+ * --------------------------------------------------------------------------------------- */
+typedef struct mphx_server mphx_server;
+
+typedef struct mphx_request {
+    int32_t key_kind;        /* MPHX_KEYS_U64 or MPHX_KEYS_STR */
+    uint32_t max_tries;
+    const uint64_t* keys;    /* dev, n u64 keys (MPHX_KEYS_U64) */
+    const uint8_t* bytes;    /* dev, 4-byte aligned (MPHX_KEYS_STR) */
+    const uint64_t* offs;    /* dev, n + 1 offsets into bytes (MPHX_KEYS_STR) */
+    uint64_t n;
+    uint64_t seed;
+    uint32_t gamma_num, gamma_den;
+    uint64_t* codes;         /* dev, ceil(m/32) words */
+    uint64_t* rank;          /* dev, ceil(m/512) entries */
+} mphx_request;
+
+typedef struct mphx_request_result {
+    int32_t status;
+    uint32_t tries;
+    uint32_t n_rounds;
+    uint32_t reserved;
+    uint64_t seed_used, P, m;
+    double t_submit, t_start, t_done;
+} mphx_request_result;
+
+typedef struct mphx_server_stats_t {
+    uint32_t pending, running;
+    uint64_t completed;
+    size_t budget, in_use, peak_in_use;
+} mphx_server_stats_t;
+
+MPHX_API int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, mphx_server** server);
+MPHX_API int mphx_server_submit(mphx_server* server, const mphx_request* req, uint64_t* ticket);
+MPHX_API int mphx_server_poll(mphx_server* server, uint64_t ticket, mphx_request_result* res);
+MPHX_API int mphx_server_wait(mphx_server* server, uint64_t ticket, mphx_request_result* res);
+MPHX_API int mphx_server_stats(mphx_server* server, mphx_server_stats_t* stats);
+MPHX_API double mphx_server_clock(void);
+MPHX_API int mphx_server_destroy(mphx_server* server);
+
+/* ---------------------------------------------------------------------------------------
  * Synthetic key sets on the device (benchmark inputs; the same definitions as the host-side
  * generators that the tests use).  GAMMA and fin as above; S(s, t) = fin(s + t*GAMMA).
  *   u64 keys:     key_i = S(gen_seed, i + 1), i in [start, start + n).

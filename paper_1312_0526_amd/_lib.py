@@ -72,6 +72,13 @@ _SIGS = {
                                             _vp, _vp, _sz, _vp, C.POINTER(C.c_void_p)]),
     "mphx_graph_launch": (_i32, [_vp, _vp]),
     "mphx_graph_destroy": (_i32, [_vp]),
+    "mphx_server_create": (_i32, [_i32, _sz, _u32, C.POINTER(C.c_void_p)]),
+    "mphx_server_submit": (_i32, [_vp, _vp, C.POINTER(C.c_uint64)]),
+    "mphx_server_poll": (_i32, [_vp, _u64, _vp]),
+    "mphx_server_wait": (_i32, [_vp, _u64, _vp]),
+    "mphx_server_stats": (_i32, [_vp, _vp]),
+    "mphx_server_clock": (C.c_double, []),
+    "mphx_server_destroy": (_i32, [_vp]),
     "mphx_phase_times": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_uint64), _i32, _i32]),
     "mphx_phase_name": (C.c_char_p, [_i32]),
 }
@@ -422,3 +429,118 @@ class BatchBuild:
 
     def bucket_rank(self, b):
         return self.rank[int(self.rank_off_h[b]):int(self.rank_off_h[b + 1])]
+
+
+# ------------------------------------------------------------------------------------------
+# build server
+# ------------------------------------------------------------------------------------------
+class Request(C.Structure):
+    _fields_ = [("key_kind", C.c_int32), ("max_tries", C.c_uint32), ("keys", C.c_void_p), ("bytes", C.c_void_p),
+                ("offs", C.c_void_p), ("n", C.c_uint64), ("seed", C.c_uint64), ("gamma_num", C.c_uint32),
+                ("gamma_den", C.c_uint32), ("codes", C.c_void_p), ("rank", C.c_void_p)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("tries", C.c_uint32), ("n_rounds", C.c_uint32), ("reserved", C.c_uint32),
+                ("seed_used", C.c_uint64), ("P", C.c_uint64), ("m", C.c_uint64), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if k.startswith("t_") else int(getattr(self, k)))
+                for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("pending", C.c_uint32), ("running", C.c_uint32), ("completed", C.c_uint64), ("budget", C.c_size_t),
+                ("in_use", C.c_size_t), ("peak_in_use", C.c_size_t)]
+
+
+class Server:
+    """Continuous-admission build server (see mphx_server_* in include/mphx.h).
+
+    submit_*() returns a ticket at once; the caller keeps the key tensors alive until the
+    ticket completes (the server holds references for it).  Outputs are allocated here."""
+
+    def __init__(self, hbm_budget: int, slots: int = 4, device="cuda"):
+        self.device = torch.device(device)
+        idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        h = C.c_void_p()
+        rc = lib().mphx_server_create(idx, int(hbm_budget), int(slots), C.byref(h))
+        if rc:
+            raise MphxError(rc, "server create failed")
+        self.h = h
+        self._live = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(lib().mphx_server_clock())
+
+    def _submit(self, req, hold, n, gamma):
+        P = part_size(n, gamma)
+        m = 3 * P
+        codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=self.device)
+        rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=self.device)
+        req.codes, req.rank = _ptr(codes), _ptr(rank)
+        torch.cuda.current_stream(self.device).synchronize()  # inputs/outputs exist before workers run
+        t = C.c_uint64(0)
+        rc = lib().mphx_server_submit(self.h, C.byref(req), C.byref(t))
+        if rc:
+            raise MphxError(rc, "submit failed")
+        self._live[t.value] = (hold, codes, rank)
+        return t.value
+
+    def submit_u64(self, keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64) -> int:
+        _check(keys, torch.int64, "keys")
+        req = Request(KEYS_U64, max_tries, _ptr(keys), None, None, keys.numel(), seed, gamma[0], gamma[1])
+        return self._submit(req, (keys,), keys.numel(), gamma)
+
+    def submit_str(self, data: torch.Tensor, offs: torch.Tensor, seed: int = 0, gamma=(123, 100),
+                   max_tries: int = 64) -> int:
+        _check(data, torch.uint8, "data")
+        _check(offs, torch.int64, "offs")
+        n = offs.numel() - 1
+        req = Request(KEYS_STR, max_tries, None, _ptr(data), _ptr(offs), n, seed, gamma[0], gamma[1])
+        return self._submit(req, (data, offs), n, gamma)
+
+    def poll(self, ticket: int):
+        r = RequestResult()
+        rc = lib().mphx_server_poll(self.h, ticket, C.byref(r))
+        if rc < 0:
+            raise MphxError(rc, "poll failed")
+        return None if rc == 1 else self._finish(ticket, r)
+
+    def wait(self, ticket: int) -> dict:
+        r = RequestResult()
+        rc = lib().mphx_server_wait(self.h, ticket, C.byref(r))
+        if rc:
+            raise MphxError(rc, "wait failed")
+        return self._finish(ticket, r)
+
+    def _finish(self, ticket, r):
+        d = r.as_dict()
+        hold, codes, rank = self._live.get(ticket, (None, None, None))
+        d["codes"], d["rank"] = codes, rank
+        if codes is not None and d["m"]:
+            d["codes"] = codes[: (d["m"] + 31) // 32]
+            d["rank"] = rank[: (d["m"] + 511) // 512]
+        return d
+
+    def release(self, ticket: int):
+        self._live.pop(ticket, None)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        lib().mphx_server_stats(self.h, C.byref(st))
+        return {k: int(getattr(st, k)) for k, _ in st._fields_}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().mphx_server_destroy(self.h)
+            self.h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,110 @@
+"""Build server: each result in a concurrent mix equals the same request built alone
+(bit-exact), small budgets queue instead of failing, and admitted builds overlap (GPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mx():
+    import torch
+
+    import paper_1312_0526_amd as mx
+
+    assert torch.cuda.is_available()
+    mx.lib()
+    return mx
+
+
+def _dev(a):
+    import torch
+
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a).cuda()
+
+
+def _requests():
+    reqs = []
+    for i, n in enumerate([1000, 5000, 200_000, 3_000_000, 777, 60_000]):
+        reqs.append(("u64", _dev(workloads.u64_keys(n, gen_seed=100 + i)), None, 10 + i))
+    for i, n in enumerate([2000, 150_000, 1_000_000]):
+        d, o = workloads.str_keys(n, gen_seed=200 + i)
+        reqs.append(("str", _dev(d), _dev(o), 20 + i))
+    return reqs
+
+
+def _alone(mx, r):
+    kind, a, b, seed = r
+    if kind == "u64":
+        return mx.mphf_build_u64(a, seed=seed)
+    return mx.mphf_build_str(a, b, seed=seed)
+
+
+def _submit(srv, r):
+    kind, a, b, seed = r
+    return srv.submit_u64(a, seed=seed) if kind == "u64" else srv.submit_str(a, b, seed=seed)
+
+
+def test_mix_equals_alone(mx):
+    import torch
+
+    reqs = _requests()
+    alone = [_alone(mx, r) for r in reqs]
+    srv = mx.Server(hbm_budget=8 << 30, slots=4)
+    tickets = [_submit(srv, r) for r in reqs]
+    res = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    for r, a in zip(res, alone):
+        assert r["status"] == 0
+        assert r["tries"] == a["tries"] and r["seed_used"] == a["seed_used"] and r["P"] == a["P"]
+        assert torch.equal(r["codes"], a["codes"]) and torch.equal(r["rank"], a["rank"])
+    # overlap: some admitted build started before another one finished
+    spans = sorted((r["t_start"], r["t_done"]) for r in res)
+    assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["in_use"] == 0 and st["peak_in_use"] > 0
+    srv.close()
+    # spot-check two results against the oracle
+    o = oracle.Oracle()
+    keys = workloads.u64_keys(5000, gen_seed=101)
+    rc, ref = o.mphf_build_u64(keys, seed=11)
+    assert np.array_equal(res[1]["codes"].cpu().numpy().view(np.uint64), ref["words"])
+
+
+def test_tiny_budget_queues_but_never_fails(mx):
+    import torch
+
+    reqs = _requests()[:4]
+    ws = [(mx.mphf_workspace_bytes(r[1].numel()) + 255) // 256 * 256 for r in reqs]
+    budget = max(ws) + 4096
+    srv = mx.Server(hbm_budget=budget, slots=4)
+    tickets = [_submit(srv, r) for r in reqs]
+    res = [srv.wait(t) for t in tickets]
+    assert all(r["status"] == 0 for r in res)
+    # the workspaces of the builds running at any instant fit in the budget
+    for r in res:
+        t = r["t_start"]
+        live = sum(w for q, w in zip(res, ws) if q["t_start"] <= t < q["t_done"])
+        assert live <= budget
+    assert srv.stats()["peak_in_use"] <= budget
+    alone = [_alone(mx, r) for r in reqs]
+    for r, a in zip(res, alone):
+        assert torch.equal(r["codes"], a["codes"])
+    srv.close()
+
+
+def test_over_budget_request_fails_fast(mx):
+    small = _dev(workloads.u64_keys(1000))
+    big = _dev(workloads.u64_keys(1_000_000))
+    srv = mx.Server(hbm_budget=mx.mphf_workspace_bytes(1000) + 4096, slots=2)
+    tb = srv.submit_u64(big)
+    ts = srv.submit_u64(small)
+    assert srv.wait(tb)["status"] == mx.ENOMEM
+    assert srv.wait(ts)["status"] == 0
+    srv.close()
