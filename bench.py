@@ -44,8 +44,7 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
     """Bytes each phase must move at least once, at element size (not cache-line size).
 
     n keys/edges, m = 3P vertices, key_bytes = total key bytes, F = frontier entries over all
-    rounds, F0 = initial frontier, C = claims (vertex had degree 1 at round start), R8 = 8-byte
-    per-vertex record, read-modify-write = 2 x its size.
+    rounds, F0 = initial frontier; an 8-byte per-vertex record read-modify-write counts 16 B.
     """
     n, m = st["n"], st["m"]
     F, F0, C = st["frontier_total"], st["frontier0"], st["claims"]
@@ -54,17 +53,18 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
         key = 8 * n if st["kind"] == "u64" else st["key_bytes"] + 8 * n
         return key + 12 * n + 3 * 16 * n
     if phase == "frontier":
-        return 8 * m + 4 * F0
+        # every record read, an 8 B (edge, position) entry per degree-1 vertex
+        return 8 * m + 8 * F0
     if phase == "claim":
-        # frontier entry 4 + record 8 per entry; claim byte RMW 2 per claim; layer append 4
-        return 12 * F + 2 * C + 4 * n
+        # entry read 8 B and edge-state RMW 8 B per entry; layer slot append 4 B per edge
+        return 16 * F + 4 * n
     if phase == "apply":
-        # layer 4 + claim byte 1 + edge 12 per edge; record RMW 16 per non-claimer vertex;
-        # frontier push 4 per vertex that dropped to degree 1
-        return 17 * n + 16 * (3 * n - C) + 4 * (F - F0)
+        # slot read 4 + state read 4 + edge read 12 + slot write 12 per edge; two record RMW
+        # (16 B each) per edge; 8 B entry per vertex that dropped to degree 1
+        return 32 * n + 32 * n + 8 * (F - F0)
     if phase == "assign":
-        # layer 4 + claim byte 1 + edge 12 + two code reads + one code write (1 B each)
-        return 20 * n
+        # 12 B slot read + two code reads + one code write (1 B each)
+        return 15 * n
     if phase == "rank":
         # code bytes read, packed words written, per-512 counts written/read, rank written
         return m + m / 4 + 16 * m / 512
@@ -205,7 +205,6 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", choices=sorted(CONFIGS), default="c3")
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
-    ap.add_argument("--record", type=int, default=-1, help="per-vertex record layout (0 xor, 1 sum)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="keys in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="plain,batched,served", help="comma list of: plain, batched, served")
@@ -235,8 +234,6 @@ def main() -> int:
     n = args.n or cfg["n"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.record >= 0:
-        mx.set_option("record", args.record)
     gamma = (123, 100)
 
     # ---- inputs, generated on the device before timing --------------------------------------
@@ -349,7 +346,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": cfg["workload"], "n": n, "gamma": "123/100", "m": m,
                    "key_bytes": key_bytes, "rounds": r["n_rounds"], "tries": r["tries"],
-                   "record": mx.get_option("record"), "parallelism": "single GPU"},
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phase_rows,

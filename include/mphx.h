@@ -301,10 +301,6 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
 /* ---------------------------------------------------------------------------------------
  * Tuning and diagnostics.
  * mphx_set_option / mphx_get_option (process-wide):
- *   "record"      0 = per-vertex record {XOR of incident edge ids, degree} updated with two
- *                 32-bit atomics (Section 4.1, labelled XOR trick); 1 = {degree, sum of
- *                 incident edge ids} updated with one 64-bit atomic add (the same packed
- *                 incidence list over the group Z/2^40 instead of XOR).  Results identical.
  *   "grid"        blocks per launch of the grid-stride peeling kernels (0 = automatic).
  *   "round_batch" peeling rounds enqueued between two checks of the termination flag.
  *   "timing"      1 = record a HIP event pair on the caller's stream around every kernel

@@ -18,7 +18,6 @@ namespace {
 thread_local std::string g_err;
 
 struct Options {
-    std::atomic<int> record{1};        // 0 = XOR record, 1 = sum record
     std::atomic<int> grid{0};          // 0 = automatic
     std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
@@ -130,8 +129,9 @@ struct Carve {
 
 struct PeelLayout {
     Ctrl* ctrl;
-    uint64_t *fstart, *lstart, *rec;
-    uint32_t *front, *layer, *hmask32, *tilehist;
+    uint64_t *fstart, *lstart, *rec, *front;
+    uint32_t *state, *tilehist, *ids;
+    uint3* slots;
     void* scan;
     size_t scan_bytes;
 };
@@ -143,9 +143,10 @@ void layout_peel(Carve& c, uint64_t n, uint64_t m, PeelLayout& L)
     L.fstart = c.take<uint64_t>(rcap + 2);
     L.lstart = c.take<uint64_t>(rcap + 2);
     L.rec = c.take<uint64_t>(m);
-    L.front = c.take<uint32_t>(m);
-    L.layer = c.take<uint32_t>(n);
-    L.hmask32 = c.take<uint32_t>((n + 3) / 4);
+    L.front = c.take<uint64_t>(m);
+    L.slots = c.take<uint3>(n);
+    L.state = c.take<uint32_t>(n);
+    L.ids = reinterpret_cast<uint32_t*>(L.slots);  // sort scratch once the peel is over
     uint64_t hist_entries = 256 * sort_tiles(n);
     L.tilehist = c.take<uint32_t>(hist_entries);
     L.scan_bytes = scan_scratch_bytes(hist_entries);
@@ -154,8 +155,9 @@ void layout_peel(Carve& c, uint64_t n, uint64_t m, PeelLayout& L)
 
 struct MphfLayout {
     Ctrl* ctrl;
-    uint64_t *fstart, *lstart, *rec;
-    uint32_t *edges, *front, *layer, *hmask32, *bcount;
+    uint64_t *fstart, *lstart, *rec, *front;
+    uint32_t *edges, *state, *bcount;
+    uint3* slots;
     void* scan;
     size_t scan_bytes;
 };
@@ -168,9 +170,9 @@ void layout_mphf(Carve& c, uint64_t n, uint64_t m, MphfLayout& L)
     L.lstart = c.take<uint64_t>(rcap + 2);
     L.edges = c.take<uint32_t>(3 * n);
     L.rec = c.take<uint64_t>(m);
-    L.front = c.take<uint32_t>(std::max<uint64_t>(m, (m + 3) / 4));  // also the byte codes after peeling
-    L.layer = c.take<uint32_t>(n);
-    L.hmask32 = c.take<uint32_t>((n + 3) / 4);
+    L.front = c.take<uint64_t>(m);  // also the byte codes after peeling
+    L.slots = c.take<uint3>(n);
+    L.state = c.take<uint32_t>(n);
     uint64_t nblocks = (m + 511) / 512;
     L.bcount = c.take<uint32_t>(nblocks);
     L.scan_bytes = scan_scratch_bytes(nblocks);
@@ -226,7 +228,7 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t first_front, hipStream_t s)
     }
 }
 
-int check_build_errors(Ctrl* dctrl, hipStream_t s, uint64_t& first_front)
+int check_build_errors(Ctrl* dctrl, uint64_t n, hipStream_t s, uint64_t& first_front)
 {
     Ctrl h;
     int rc = read_ctrl(dctrl, h, s);
@@ -234,7 +236,8 @@ int check_build_errors(Ctrl* dctrl, hipStream_t s, uint64_t& first_front)
     first_front = h.ftail;
     if (h.err & kErrBadEdge)
         return fail(MPHX_EINVAL, "edge with a vertex id >= m or a repeated vertex");
-    if (h.err & kErrDegree)
+    // every degree field at most 255 and their total exactly 3n: no field overflowed
+    if ((h.err & kErrDegree) || h.degsum != 3 * n)
         return fail(MPHX_ERANGE, "a vertex has degree above %u", MPHX_MAX_DEGREE);
     return MPHX_OK;
 }
@@ -256,10 +259,7 @@ uint64_t mphx_part_size(uint64_t n, uint32_t gamma_num, uint32_t gamma_den)
 int mphx_set_option(const char* key, int64_t value)
 {
     if (!key) return fail(MPHX_EINVAL, "null option key");
-    if (!strcmp(key, "record")) {
-        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "record must be 0 or 1");
-        g_opt.record = (int)value;
-    } else if (!strcmp(key, "grid")) {
+    if (!strcmp(key, "grid")) {
         if (value < 0 || value > (1 << 20)) return fail(MPHX_EINVAL, "grid out of range");
         g_opt.grid = (int)value;
     } else if (!strcmp(key, "round_batch")) {
@@ -277,7 +277,6 @@ int mphx_set_option(const char* key, int64_t value)
 int64_t mphx_get_option(const char* key)
 {
     if (!key) return MPHX_EINVAL;
-    if (!strcmp(key, "record")) return g_opt.record;
     if (!strcmp(key, "grid")) return g_opt.grid;
     if (!strcmp(key, "round_batch")) return g_opt.round_batch;
     if (!strcmp(key, "timing")) return g_opt.timing;
@@ -330,23 +329,6 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     Carve c(ws);
     PeelLayout L;
     layout_peel(c, n, m, L);
-    const int record = g_opt.record.load();
-
-    HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
-    HIP_TRY(launch_zero(L.hmask32, ((n + 3) / 4) * 4, s));
-    HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
-    HIP_TRY(launch_fill_u32(round, n, kRoundCore, s));
-    {
-        Timed t(PH_HASH, s);
-        HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, record, s));
-    }
-    {
-        Timed t(PH_FRONTIER, s);
-        HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
-    }
-    uint64_t f0 = 0;
-    int rc = check_build_errors(L.ctrl, s, f0);
-    if (rc) return rc;
 
     PeelState st{};
     st.edges = edges;
@@ -354,24 +336,38 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     st.m = m;
     st.P = 0;
     st.tripartite = false;
-    st.record = record;
     st.rec = L.rec;
     st.front = L.front;
-    st.layer = L.layer;
-    st.hmask32 = L.hmask32;
+    st.slots = L.slots;
+    st.state = L.state;
     st.fstart = L.fstart;
     st.lstart = L.lstart;
-    st.round_out = round;
     st.ctrl = L.ctrl;
     st.rcap = round_cap(n);
+
+    HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
+    HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
+    HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
+    {
+        Timed t(PH_HASH, s);
+        HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, s));
+    }
+    {
+        Timed t(PH_FRONTIER, s);
+        HIP_TRY(launch_frontier_init(st, s));
+    }
+    uint64_t f0 = 0;
+    int rc = check_build_errors(L.ctrl, n, s, f0);
+    if (rc) return rc;
+
     Ctrl h;
     rc = run_rounds(st, h, f0, s);
     if (rc) return rc;
 
     {
         Timed t(PH_ORDER, s);
-        HIP_TRY(launch_peel_finalize(round, L.hmask32, n, core_mask, hinge, s));
-        HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.layer, L.tilehist, L.scan, L.scan_bytes, s));
+        HIP_TRY(launch_peel_finalize(L.state, n, round, core_mask, hinge, s));
+        HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.ids, L.tilehist, L.scan, L.scan_bytes, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
     g_timers.harvest();
@@ -439,14 +435,14 @@ int keys_equal(const KeySrc& k, uint64_t a, uint64_t b, bool& eq, hipStream_t s)
 int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, bool& dup, hipStream_t s)
 {
     dup = false;
-    std::vector<uint32_t> hm((n + 3) / 4);
+    std::vector<uint32_t> state(n);
     std::vector<uint32_t> edges(3 * n);
-    HIP_TRY(hipMemcpyAsync(hm.data(), L.hmask32, hm.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(state.data(), L.state, state.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(edges.data(), L.edges, edges.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     std::vector<uint32_t> core;
     for (uint64_t e = 0; e < n; e++)
-        if (((hm[e >> 2] >> (8 * (e & 3))) & 0xFF) == 0)
+        if (state[e] == kUnclaimed)
             core.push_back((uint32_t)e);
     std::sort(core.begin(), core.end(), [&](uint32_t a, uint32_t b) {
         for (int q = 0; q < 3; q++)
@@ -499,7 +495,6 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     Carve c(ws);
     MphfLayout L;
     layout_mphf(c, n, m, L);
-    const int record = g_opt.record.load();
 
     PeelState st{};
     st.edges = L.edges;
@@ -507,14 +502,12 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     st.m = m;
     st.P = P;
     st.tripartite = true;
-    st.record = record;
     st.rec = L.rec;
     st.front = L.front;
-    st.layer = L.layer;
-    st.hmask32 = L.hmask32;
+    st.slots = L.slots;
+    st.state = L.state;
     st.fstart = L.fstart;
     st.lstart = L.lstart;
-    st.round_out = nullptr;
     st.ctrl = L.ctrl;
     st.rcap = round_cap(n);
 
@@ -524,21 +517,21 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     for (t = 0; t < max_tries; t++) {
         uint64_t sd = seed + t;
         HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
-        HIP_TRY(launch_zero(L.hmask32, ((n + 3) / 4) * 4, s));
+        HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
         HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
         {
             Timed tm(PH_HASH, s);
             if (k.kind == MPHX_KEYS_U64)
-                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
+                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, L.rec, s));
             else
-                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, L.rec, L.ctrl, record, s));
+                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, L.rec, s));
         }
         {
             Timed tm(PH_FRONTIER, s);
-            HIP_TRY(launch_frontier_init(L.rec, m, L.front, L.ctrl, record, s));
+            HIP_TRY(launch_frontier_init(st, s));
         }
         uint64_t f0 = 0;
-        int rc = check_build_errors(L.ctrl, s, f0);
+        int rc = check_build_errors(L.ctrl, n, s, f0);
         if (rc) {
             if (info) { info->tries = t + 1; info->seed_used = sd; }
             return rc;
@@ -576,7 +569,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     for (int64_t r = (int64_t)h.nrounds - 1; r >= 0; r--) {
         uint64_t cnt = lb[r + 1] - lb[r];
         Timed tm(PH_ASSIGN, s);
-        HIP_TRY(launch_assign_round(L.edges, L.layer, L.hmask32, L.lstart, (uint32_t)r, cnt, code8, 16384, s));
+        HIP_TRY(launch_assign_round(L.slots, L.lstart, (uint32_t)r, cnt, P, code8, 16384, s));
     }
     {
         Timed tm(PH_RANK, s);
@@ -638,7 +631,7 @@ int mphx_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, u
     if (n == 0) return MPHX_OK;
     if (!keys || !edges) return fail(MPHX_EINVAL, "null pointer");
     if (P == 0 || 3 * P > 0x100000000ull) return fail(MPHX_EINVAL, "P out of range");
-    HIP_TRY(launch_hash_u64(keys, n, seed, P, edges, nullptr, nullptr, 0, (hipStream_t)stream));
+    HIP_TRY(launch_hash_u64(keys, n, seed, P, edges, nullptr, (hipStream_t)stream));
     return MPHX_OK;
 }
 
@@ -650,7 +643,7 @@ int mphx_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64
     if (!bytes || !offs || !edges) return fail(MPHX_EINVAL, "null pointer");
     if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
     if (P == 0 || 3 * P > 0x100000000ull) return fail(MPHX_EINVAL, "P out of range");
-    HIP_TRY(launch_hash_str(bytes, offs, n, seed, P, edges, nullptr, nullptr, 0, (hipStream_t)stream));
+    HIP_TRY(launch_hash_str(bytes, offs, n, seed, P, edges, nullptr, (hipStream_t)stream));
     return MPHX_OK;
 }
 

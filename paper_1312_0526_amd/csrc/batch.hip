@@ -96,6 +96,12 @@ __device__ __forceinline__ uint32_t ld_l2(const uint32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// Returns the degree before the addition (the batched build checks degrees as it goes).
+__device__ __forceinline__ uint32_t rec_add_ret(uint64_t* rec, uint32_t v, uint32_t e)
+{
+    return Rec::deg(atomicAdd(reinterpret_cast<unsigned long long*>(rec + v), (unsigned long long)(Rec::kOne + e)));
+}
+
 __device__ __forceinline__ uint32_t claim_mask_l2(const uint32_t* claim, uint32_t e)
 {
     return (ld_l2(claim + (e >> 2)) >> (8 * (e & 3))) & 0xFFu;
@@ -201,9 +207,9 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
         for (uint32_t i = tid; i < n; i += kBlock) {
             uint32_t v0, v1, v2;
             edge_of_key(keys[i], sd, P, v0, v1, v2);
-            uint32_t d = RecSum::add_ret(L.rec, v0, i);
-            d = max(d, RecSum::add_ret(L.rec, v1, i));
-            d = max(d, RecSum::add_ret(L.rec, v2, i));
+            uint32_t d = rec_add_ret(L.rec, v0, i);
+            d = max(d, rec_add_ret(L.rec, v1, i));
+            d = max(d, rec_add_ret(L.rec, v2, i));
             if (d >= kMaxDegree)
                 s_err = 1;
         }
@@ -215,7 +221,7 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
         // round-0 frontier
         for (uint32_t base = 0; base < m; base += kBlock) {
             uint32_t v = base + tid;
-            bool one = v < m && RecSum::deg(ld_l2(L.rec + v)) == 1;
+            bool one = v < m && Rec::deg(ld_l2(L.rec + v)) == 1;
             uint32_t pos = block_append(&s_ftail, one, false);
             if (one)
                 L.front[pos] = v;
@@ -233,8 +239,8 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
                 if (i < fhi) {
                     uint32_t v = L.front[i];
                     uint64_t x = ld_l2(L.rec + v);
-                    if (RecSum::deg(x) == 1 && RecSum::edge(x) < n) {
-                        e = RecSum::edge(x);
+                    if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
+                        e = Rec::edge(x);
                         uint32_t k = part_of(v, P);
                         uint32_t sh = 8 * (e & 3);
                         uint32_t old = atomicOr(&L.claim[e >> 2], (1u << k) << sh);
@@ -262,7 +268,7 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
                     edge_of_key(keys[e], sd, P, v[0], v[1], v[2]);
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        if (!(mask & (1u << k)) && RecSum::del(L.rec, v[k], e) == 2) {
+                        if (!(mask & (1u << k)) && Rec::deg(Rec::del(L.rec, v[k], e)) == 2) {
                             if (np) p1 = v[k]; else p0 = v[k];
                             np++;
                         }

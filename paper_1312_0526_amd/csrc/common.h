@@ -24,7 +24,8 @@ struct Ctrl {
     uint32_t err;              // kErr* bits
     unsigned long long aux;    // scratch counter (bijection check)
     unsigned long long claims; // (vertex, edge) claims made over all rounds
-    uint64_t pad[27];
+    unsigned long long degsum; // sum of all degree fields (overflow check: must be 3n)
+    uint64_t pad[26];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte slot");
 
@@ -94,11 +95,12 @@ __device__ __forceinline__ uint64_t wave_append(unsigned long long* tail, bool w
 // up to two values; they are packed into an LDS buffer (wave ballot + lane prefix, then a
 // prefix over the block's waves) and the buffer is copied out with a single atomicAdd on the
 // global cursor whenever the next call could overflow it, and once at the end.  Every thread
-// of the block must make the same sequence of calls (uniform loops only).
-template <int kBlock, int kCap>
+// of the block must make the same sequence of calls (uniform loops only).  `out(i, v)` stores
+// value v at global position i.
+template <typename T, int kBlock, int kCap>
 struct BlockAppender {
     static_assert(kCap >= 4 * kBlock, "buffer must hold several calls");
-    uint32_t buf[kCap];
+    T buf[kCap];
     uint32_t wtot[kBlock / kWave];
     uint32_t count;
     unsigned long long base;
@@ -110,21 +112,23 @@ struct BlockAppender {
         __syncthreads();
     }
 
-    __device__ void flush(unsigned long long* tail, uint32_t* out)
+    template <class Out>
+    __device__ void flush(unsigned long long* tail, Out out)
     {
         if (threadIdx.x == 0 && count)
             base = atomicAdd(tail, (unsigned long long)count);
         __syncthreads();
         const uint32_t c = count;
         for (uint32_t i = threadIdx.x; i < c; i += kBlock)
-            out[base + i] = buf[i];
+            out(base + i, buf[i]);
         __syncthreads();
         if (threadIdx.x == 0)
             count = 0;
         __syncthreads();
     }
 
-    __device__ void push(bool want1, uint32_t v1, bool want2, uint32_t v2, unsigned long long* tail, uint32_t* out)
+    template <class Out>
+    __device__ void push(bool want1, T v1, bool want2, T v2, unsigned long long* tail, Out out)
     {
         const uint32_t w = threadIdx.x / kWave;
         uint64_t b1 = __ballot(want1);
@@ -155,64 +159,41 @@ struct BlockAppender {
 
 // ----- per-vertex packed incidence record (Section 4.1) ----------------------------------
 // Each vertex keeps its degree and a combination of the ids of its incident edges from which
-// the single remaining edge is read off when the degree is 1.
-//
-// RecXor: low 32 bits = XOR of incident edge ids, high 32 bits = degree; AddEdge/DeleteEdge
-//         are a 32-bit atomic XOR plus a 32-bit atomic add/sub on the two halves of one
-//         8-byte word (same cache line).
-// RecSum: bits [40, 64) = degree, bits [0, 40) = sum of incident edge ids; AddEdge/DeleteEdge
-//         are one 64-bit atomic add of +-(2^40 + e).  While the degree is <= 255 the sum stays
-//         below 2^40 and never carries into the degree.
-struct RecXor {
-    static constexpr int kind = 0;
-    __device__ static __forceinline__ uint32_t deg(uint64_t r) { return (uint32_t)(r >> 32); }
-    __device__ static __forceinline__ uint32_t edge(uint64_t r) { return (uint32_t)r; }
-    __device__ static __forceinline__ void add(uint64_t* rec, uint32_t v, uint32_t e)
-    {
-        uint32_t* p = reinterpret_cast<uint32_t*>(rec + v);
-        atomicXor(p, e);
-        atomicAdd(p + 1, 1u);
-    }
-    // returns the degree before the deletion
-    __device__ static __forceinline__ uint32_t del(uint64_t* rec, uint32_t v, uint32_t e)
-    {
-        uint32_t* p = reinterpret_cast<uint32_t*>(rec + v);
-        atomicXor(p, e);
-        return atomicSub(p + 1, 1u);
-    }
-};
-
-struct RecSum {
-    static constexpr int kind = 1;
+// the single remaining edge is read off when the degree is 1.  The paper combines the ids
+// with XOR; here they are summed, the same structure over the group Z/2^40 instead of
+// (Z/2)^32, so that AddEdge / DeleteEdge of edge e is ONE 64-bit atomic add of +-(2^40 + e)
+// that updates degree and label together and returns a consistent (degree, label) snapshot.
+// Layout: bits [40, 64) degree, bits [0, 40) sum of incident edge ids.  While the degree is
+// <= 255 the sum stays below 2^40 and never carries into the degree.
+struct Rec {
     static constexpr uint64_t kOne = 1ull << 40;
     __device__ static __forceinline__ uint32_t deg(uint64_t r) { return (uint32_t)(r >> 40); }
     __device__ static __forceinline__ uint32_t edge(uint64_t r) { return (uint32_t)(r & (kOne - 1)); }
-    // returns the degree before the addition (used to detect degree 256)
-    __device__ static __forceinline__ uint32_t add_ret(uint64_t* rec, uint32_t v, uint32_t e)
+    __device__ static __forceinline__ void add(uint64_t* rec, uint32_t v, uint32_t e)
     {
-        unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(rec + v),
-                                           (unsigned long long)(kOne + e));
-        return (uint32_t)(old >> 40);
+        atomicAdd(reinterpret_cast<unsigned long long*>(rec + v), (unsigned long long)(kOne + e));
     }
-    __device__ static __forceinline__ uint32_t del(uint64_t* rec, uint32_t v, uint32_t e)
+    // returns the record before the deletion
+    __device__ static __forceinline__ uint64_t del(uint64_t* rec, uint32_t v, uint32_t e)
     {
-        unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long*>(rec + v),
-                                           (unsigned long long)(0ull - (kOne + e)));
-        return (uint32_t)(old >> 40);
+        return atomicAdd(reinterpret_cast<unsigned long long*>(rec + v), (unsigned long long)(0ull - (kOne + e)));
     }
 };
+
+// Frontier entry: the only remaining edge of a vertex that reached degree 1, and that vertex's
+// position in the edge (its part, for tripartite edges).
+__device__ __forceinline__ uint64_t fentry(uint32_t e, uint32_t k) { return ((uint64_t)k << 32) | e; }
+__device__ __forceinline__ uint32_t fentry_edge(uint64_t f) { return (uint32_t)f; }
+__device__ __forceinline__ uint32_t fentry_pos(uint64_t f) { return (uint32_t)(f >> 32); }
+
+// Per-edge peel state: 0xFFFFFFFF until claimed, then (round << 2) | hinge position.  Claims
+// use atomicMin, so the lowest position among the edge's degree-1 vertices of that round wins.
+constexpr uint32_t kUnclaimed = 0xFFFFFFFFu;
 
 // Part of a vertex in the tripartite layout.
 __device__ __forceinline__ uint32_t part_of(uint32_t v, uint64_t P)
 {
     return (uint32_t)((uint64_t)v >= 2 * P ? 2 : ((uint64_t)v >= P ? 1 : 0));
-}
-
-// Claim mask of edge e: one byte per edge, bit k set when the vertex in position k had degree
-// 1 at the start of the edge's round.  Bytes are packed four per 32-bit word for atomicOr.
-__device__ __forceinline__ uint32_t claim_mask(const uint32_t* hmask32, uint32_t e)
-{
-    return (hmask32[e >> 2] >> (8 * (e & 3))) & 0xFFu;
 }
 
 // ---- byte-string keys --------------------------------------------------------------------

@@ -1,31 +1,15 @@
 // Key hashing (Section 3; tripartite layout of Section 4.3) fused with the packed-record build
-// (Section 4.1 AddEdge), and the device-side synthetic key generators.
+// (Section 4.1 AddEdge, non-returning atomics; degree overflow is checked by the frontier
+// scan), and the device-side synthetic key generators.
 #include "common.h"
 #include "launch.h"
 
 namespace mphx {
 
-template <class Rec>
-__device__ __forceinline__ void add_edge(uint64_t* rec, uint32_t v0, uint32_t v1, uint32_t v2, uint32_t e, Ctrl* ctrl)
-{
-    if constexpr (Rec::kind == 1) {
-        uint32_t d = Rec::add_ret(rec, v0, e);
-        d = max(d, Rec::add_ret(rec, v1, e));
-        d = max(d, Rec::add_ret(rec, v2, e));
-        if (d >= kMaxDegree)
-            atomicOr(&ctrl->err, kErrDegree);
-    } else {
-        Rec::add(rec, v0, e);
-        Rec::add(rec, v1, e);
-        Rec::add(rec, v2, e);
-    }
-}
-
 // ---- u64 keys: one thread per key, state a = b = key XOR seed -------------------------------
-template <class Rec, bool kBuild>
+template <bool kBuild>
 __global__ __launch_bounds__(256) void k_hash_u64(const uint64_t* __restrict__ keys, uint64_t n, uint64_t seed,
-                                                  uint64_t P, uint32_t* __restrict__ edges, uint64_t* __restrict__ rec,
-                                                  Ctrl* ctrl)
+                                                  uint64_t P, uint32_t* __restrict__ edges, uint64_t* __restrict__ rec)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -35,15 +19,18 @@ __global__ __launch_bounds__(256) void k_hash_u64(const uint64_t* __restrict__ k
         edges[3 * i] = v0;
         edges[3 * i + 1] = v1;
         edges[3 * i + 2] = v2;
-        if constexpr (kBuild)
-            add_edge<Rec>(rec, v0, v1, v2, (uint32_t)i, ctrl);
+        if constexpr (kBuild) {
+            Rec::add(rec, v0, (uint32_t)i);
+            Rec::add(rec, v1, (uint32_t)i);
+            Rec::add(rec, v2, (uint32_t)i);
+        }
     }
 }
 
-template <class Rec, bool kBuild>
+template <bool kBuild>
 __global__ __launch_bounds__(256) void k_hash_str(const uint8_t* __restrict__ bytes, const uint64_t* __restrict__ offs,
                                                   uint64_t n, uint64_t seed, uint64_t P, uint32_t* __restrict__ edges,
-                                                  uint64_t* __restrict__ rec, Ctrl* ctrl)
+                                                  uint64_t* __restrict__ rec)
 {
     const uint64_t total = offs[n];
     const uint64_t sa = fin(seed + kGamma);
@@ -58,8 +45,11 @@ __global__ __launch_bounds__(256) void k_hash_str(const uint8_t* __restrict__ by
         edges[3 * i] = v0;
         edges[3 * i + 1] = v1;
         edges[3 * i + 2] = v2;
-        if constexpr (kBuild)
-            add_edge<Rec>(rec, v0, v1, v2, (uint32_t)i, ctrl);
+        if constexpr (kBuild) {
+            Rec::add(rec, v0, (uint32_t)i);
+            Rec::add(rec, v1, (uint32_t)i);
+            Rec::add(rec, v2, (uint32_t)i);
+        }
     }
 }
 
@@ -153,30 +143,26 @@ static inline unsigned grid_cap(uint64_t count, unsigned cap)
 }
 
 hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
-                           uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s)
+                           uint64_t* rec, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     unsigned g = grid_cap(n, 16384);
     if (!rec)
-        k_hash_u64<RecXor, false><<<g, 256, 0, s>>>(keys, n, seed, P, edges, rec, ctrl);
-    else if (record == 1)
-        k_hash_u64<RecSum, true><<<g, 256, 0, s>>>(keys, n, seed, P, edges, rec, ctrl);
+        k_hash_u64<false><<<g, 256, 0, s>>>(keys, n, seed, P, edges, rec);
     else
-        k_hash_u64<RecXor, true><<<g, 256, 0, s>>>(keys, n, seed, P, edges, rec, ctrl);
+        k_hash_u64<true><<<g, 256, 0, s>>>(keys, n, seed, P, edges, rec);
     return hipGetLastError();
 }
 
 hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
-                           uint32_t* edges, uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s)
+                           uint32_t* edges, uint64_t* rec, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     unsigned g = grid_cap(n, 16384);
     if (!rec)
-        k_hash_str<RecXor, false><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec, ctrl);
-    else if (record == 1)
-        k_hash_str<RecSum, true><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec, ctrl);
+        k_hash_str<false><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec);
     else
-        k_hash_str<RecXor, true><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec, ctrl);
+        k_hash_str<true><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec);
     return hipGetLastError();
 }
 

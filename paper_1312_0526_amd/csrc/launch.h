@@ -14,15 +14,13 @@ struct PeelState {
     const uint32_t* edges;  // n x 3
     uint64_t n, m, P;       // P = part size when tripartite
     bool tripartite;
-    int record;             // 0 = RecXor, 1 = RecSum
     unsigned grid_cap;      // max blocks of the grid-stride round kernels
     uint64_t* rec;          // m packed records
-    uint32_t* front;        // m: frontiers of all rounds back to back
-    uint32_t* layer;        // n: layers of all rounds back to back
-    uint32_t* hmask32;      // ceil(n/4) words of claim bytes
+    uint64_t* front;        // m frontier entries (edge, position) of all rounds back to back
+    uint3* slots;           // n layer slots of all rounds back to back: edge id, then vertices
+    uint32_t* state;        // n edge states: unclaimed or (round << 2) | hinge
     uint64_t* fstart;       // rcap + 2 frontier starts
     uint64_t* lstart;       // rcap + 2 layer starts
-    uint32_t* round_out;    // nullable: per-edge round
     Ctrl* ctrl;
     uint64_t rcap;          // rounds the start arrays can hold
 };
@@ -65,9 +63,9 @@ hipError_t launch_scan_u32_to_u64(const uint32_t* in, uint64_t count_in, uint64_
 
 // hashing and key generation (keys.hip); rec == nullptr hashes only
 hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
-                           uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s);
+                           uint64_t* rec, hipStream_t s);
 hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
-                           uint32_t* edges, uint64_t* rec, Ctrl* ctrl, int record, hipStream_t s);
+                           uint32_t* edges, uint64_t* rec, hipStream_t s);
 hipError_t launch_gen_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, hipStream_t s);
 hipError_t launch_gen_buckets_u64(uint64_t* keys, const uint64_t* off, uint32_t B, hipStream_t s);
 hipError_t launch_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start,
@@ -76,13 +74,12 @@ hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
                                 hipStream_t s);
 
 // peeling (peel.hip)
-hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl, int record,
+hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl,
                               hipStream_t s);
-hipError_t launch_frontier_init(const uint64_t* rec, uint64_t m, uint32_t* front, Ctrl* ctrl, int record,
-                                hipStream_t s);
+hipError_t launch_frontier_init(const PeelState& st, hipStream_t s);
 hipError_t launch_claim(const PeelState& st, uint32_t r, hipStream_t s);
 hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s);
-hipError_t launch_peel_finalize(const uint32_t* round, const uint32_t* hmask32, uint64_t n, uint8_t* core_mask,
+hipError_t launch_peel_finalize(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask,
                                 uint8_t* hinge, hipStream_t s);
 uint64_t sort_tiles(uint64_t n);
 hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds, uint32_t* order,
@@ -90,9 +87,8 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
                              hipStream_t s);
 
 // assignment, ranking, lookup (solve.hip)
-hipError_t launch_assign_round(const uint32_t* edges, const uint32_t* layer, const uint32_t* hmask32,
-                               const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint8_t* code8,
-                               unsigned grid_cap, hipStream_t s);
+hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
+                               uint8_t* code8, unsigned grid_cap, hipStream_t s);
 hipError_t launch_pack_count(const uint8_t* code8, uint64_t m, uint64_t* codes, uint32_t* bcount, hipStream_t s);
 hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
                              const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s);

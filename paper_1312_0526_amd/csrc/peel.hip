@@ -1,16 +1,22 @@
-// Peeling kernels for gfx950: packed incidence lists built with device atomics, synchronous
+// Peeling kernels for gfx950: packed incidence records built with device atomics, synchronous
 // frontier rounds (Section 4.2 layered peeling), and the canonical order.
 //
+// Frontier entries carry (e, k): the only remaining edge e of a vertex that just reached
+// degree 1, and the vertex's position k in e.  The entry is written by the thread whose
+// atomic DeleteEdge took the vertex from degree 2 to 1 -- the value that atomic returned holds
+// the label sum of the two edges, so the remaining one is known at once.  Round 0's entries
+// come from a scan of all records.
+//
 // One round r is two launches:
-//   claim(r): every frontier vertex that still has degree 1 reads its only edge e off its
-//             packed record (Section 4.1 RetrieveEdge) and sets bit <its position> in e's
-//             claim byte.  The first claimer appends e to the layer array, so each edge of the
-//             layer appears once (the dedupe of Section 4.2).  Nothing else changes, so every
-//             claimer sees the degrees of the start of the round.
-//   apply(r): for each layer edge, hinge = lowest claimed position; the edge is deleted from
-//             the vertices that did not claim it (DeleteEdge); a vertex whose degree drops
-//             from 2 to 1 joins the next frontier.  Claimers had degree 1, so their only edge
-//             is this one and they simply die with it.
+//   claim(r): every entry does atomicMin(state[e], (r << 2) | k).  The first claimer (old value
+//             unclaimed) appends e to the layer, so each edge of the layer appears once (the
+//             dedupe of Section 4.2) and state[e] ends as (r << 2) | lowest claimed position.
+//             An entry whose vertex lost its last edge in the same round that gave it degree 1
+//             names an edge peeled in an earlier round: atomicMin leaves that state alone.
+//   apply(r): for each layer edge, hinge = state[e] & 3; DeleteEdge at the other two vertices;
+//             a vertex whose degree drops from 2 to 1 joins the next frontier with its
+//             remaining edge.  The hinge vertex has degree 1 and dies with the edge.  The edge's
+//             vertices, hinge first, are written back into its layer slot for the assignment.
 // Round bounds are read from device memory, so rounds are enqueued without host round trips;
 // a round after the last one finds an empty frontier and does nothing.
 #include "common.h"
@@ -18,15 +24,27 @@
 
 namespace mphx {
 
-// LDS-staged appender of the frontier / layer arrays (16 KB per block).
-using Appender = BlockAppender<256, 4096>;
+constexpr int kPeelBlock = 256;
+using FrontAppender = BlockAppender<uint64_t, kPeelBlock, 2048>;
+using LayerAppender = BlockAppender<uint32_t, kPeelBlock, 2048>;
+
+// Position of vertex v in edge e (generic edge lists; tripartite ones use the part).
+template <bool kTri>
+__device__ __forceinline__ uint32_t position_in(const uint32_t* edges, uint32_t e, uint32_t v, uint64_t P)
+{
+    if constexpr (kTri) {
+        return part_of(v, P);
+    } else {
+        const uint32_t* t = edges + 3 * (uint64_t)e;
+        return t[0] == v ? 0u : (t[1] == v ? 1u : 2u);
+    }
+}
 
 // ------------------------------------------------------------------------------------------
 // Degree + label build from a caller-provided edge list, with validation.
 // ------------------------------------------------------------------------------------------
-template <class Rec>
-__global__ __launch_bounds__(256) void k_edges_build(const uint32_t* __restrict__ edges, uint64_t n,
-                                                     uint64_t m, uint64_t* __restrict__ rec, Ctrl* ctrl)
+__global__ __launch_bounds__(256) void k_edges_build(const uint32_t* __restrict__ edges, uint64_t n, uint64_t m,
+                                                     uint64_t* __restrict__ rec, Ctrl* ctrl)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
@@ -36,52 +54,61 @@ __global__ __launch_bounds__(256) void k_edges_build(const uint32_t* __restrict_
             atomicOr(&ctrl->err, kErrBadEdge);
             continue;
         }
-        if constexpr (Rec::kind == 1) {
-            uint32_t d = Rec::add_ret(rec, t0, (uint32_t)e);
-            d = max(d, Rec::add_ret(rec, t1, (uint32_t)e));
-            d = max(d, Rec::add_ret(rec, t2, (uint32_t)e));
-            if (d >= kMaxDegree)
-                atomicOr(&ctrl->err, kErrDegree);
-        } else {
-            Rec::add(rec, t0, (uint32_t)e);
-            Rec::add(rec, t1, (uint32_t)e);
-            Rec::add(rec, t2, (uint32_t)e);
-        }
+        Rec::add(rec, t0, (uint32_t)e);
+        Rec::add(rec, t1, (uint32_t)e);
+        Rec::add(rec, t2, (uint32_t)e);
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// Round-0 frontier: every vertex of degree 1, compacted with one atomic per wave.
+// Round-0 frontier: every vertex of degree 1 with its edge.  Also checks the degrees: a field
+// above 255, or a total that differs from 3n (a wrapped field), means some degree exceeded 255.
 // ------------------------------------------------------------------------------------------
-template <class Rec>
-__global__ __launch_bounds__(256) void k_frontier_init(const uint64_t* __restrict__ rec, uint64_t m,
-                                                       uint32_t* __restrict__ front, Ctrl* ctrl)
+template <bool kTri>
+__global__ __launch_bounds__(kPeelBlock) void k_frontier_init(const uint64_t* __restrict__ rec, uint64_t m,
+                                                              const uint32_t* __restrict__ edges, uint64_t P,
+                                                              uint64_t* __restrict__ front, Ctrl* ctrl)
 {
-    __shared__ Appender app;
+    __shared__ FrontAppender app;
+    __shared__ unsigned long long s_deg;
+    if (threadIdx.x == 0)
+        s_deg = 0;
     app.init();
+    auto out = [front](uint64_t i, uint64_t v) { front[i] = v; };
+    unsigned long long mydeg = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         uint64_t v = base + threadIdx.x;
         bool one = false;
+        uint64_t ent = 0;
         if (v < m) {
-            uint32_t d = Rec::deg(rec[v]);
-            one = d == 1;
+            uint64_t x = rec[v];
+            uint32_t d = Rec::deg(x);
+            mydeg += d;
             if (d > kMaxDegree)
                 atomicOr(&ctrl->err, kErrDegree);
+            one = d == 1;
+            if (one) {
+                uint32_t e = Rec::edge(x);
+                ent = fentry(e, position_in<kTri>(edges, e, (uint32_t)v, P));
+            }
         }
-        app.push(one, (uint32_t)v, false, 0u, &ctrl->ftail, front);
+        app.push(one, ent, false, 0ull, &ctrl->ftail, out);
     }
-    app.flush(&ctrl->ftail, front);
+    app.flush(&ctrl->ftail, out);
+    if (mydeg)
+        atomicAdd(&s_deg, mydeg);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_deg)
+        atomicAdd(&ctrl->degsum, s_deg);
 }
 
 // ------------------------------------------------------------------------------------------
 // Claim phase of round r.
 // ------------------------------------------------------------------------------------------
-template <class Rec, bool kTri>
-__global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec, const uint32_t* __restrict__ front,
-                                               const uint32_t* __restrict__ edges, uint32_t* __restrict__ hmask32,
-                                               uint32_t* __restrict__ layer, uint64_t* __restrict__ fstart,
-                                               Ctrl* ctrl, uint32_t r, uint64_t P, uint64_t n)
+__global__ __launch_bounds__(kPeelBlock) void k_claim(const uint64_t* __restrict__ front, uint32_t* __restrict__ state,
+                                                      uint3* __restrict__ slots, uint64_t* __restrict__ fstart,
+                                                      Ctrl* ctrl, uint32_t r)
 {
     const uint64_t lo = fstart[r];
     const uint64_t hi = *(volatile unsigned long long*)&ctrl->ftail;  // no push during a claim
@@ -89,39 +116,29 @@ __global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec,
         fstart[r + 1] = hi;
     if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
         return;  // whole block idle (uniform)
-    __shared__ Appender app;
+    __shared__ LayerAppender app;
     __shared__ uint32_t nclaims;
     if (threadIdx.x == 0)
         nclaims = 0;
     app.init();
+    auto out = [slots](uint64_t i, uint32_t e) { slots[i].x = e; };
     uint32_t myclaims = 0;
+    const uint32_t rr = r << 2;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
-        bool first = false, claimed = false;
+        bool first = false;
         uint32_t e = 0;
         if (i < hi) {
-            uint32_t v = front[i];
-            uint64_t x = rec[v];
-            if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
-                claimed = true;
-                e = Rec::edge(x);
-                uint32_t k;
-                if constexpr (kTri) {
-                    k = part_of(v, P);
-                } else {
-                    const uint32_t* t = edges + 3 * (uint64_t)e;
-                    k = t[0] == v ? 0u : (t[1] == v ? 1u : 2u);
-                }
-                uint32_t sh = 8 * (e & 3);
-                uint32_t old = atomicOr(&hmask32[e >> 2], (1u << k) << sh);
-                first = ((old >> sh) & 0xFFu) == 0;
-            }
+            uint64_t f = front[i];
+            e = fentry_edge(f);
+            uint32_t old = atomicMin(&state[e], rr | fentry_pos(f));
+            first = old == kUnclaimed;
+            myclaims += (old == kUnclaimed || (old >> 2) == r) ? 1u : 0u;
         }
-        myclaims += claimed;
-        app.push(first, e, false, 0u, &ctrl->ltail, layer);
+        app.push(first, e, false, 0u, &ctrl->ltail, out);
     }
-    app.flush(&ctrl->ltail, layer);
+    app.flush(&ctrl->ltail, out);
     if (myclaims)
         atomicAdd(&nclaims, myclaims);
     __syncthreads();
@@ -130,14 +147,13 @@ __global__ __launch_bounds__(256) void k_claim(const uint64_t* __restrict__ rec,
 }
 
 // ------------------------------------------------------------------------------------------
-// Apply phase of round r.  round_out (nullable) receives r for every layer edge.
+// Apply phase of round r.
 // ------------------------------------------------------------------------------------------
-template <class Rec>
-__global__ __launch_bounds__(256) void k_apply(uint64_t* __restrict__ rec, uint32_t* __restrict__ front,
-                                               const uint32_t* __restrict__ edges,
-                                               const uint32_t* __restrict__ hmask32,
-                                               const uint32_t* __restrict__ layer, uint64_t* __restrict__ lstart,
-                                               uint32_t* __restrict__ round_out, Ctrl* ctrl, uint32_t r)
+template <bool kTri>
+__global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec, uint64_t* __restrict__ front,
+                                                      const uint32_t* __restrict__ edges,
+                                                      const uint32_t* __restrict__ state, uint3* __restrict__ slots,
+                                                      uint64_t* __restrict__ lstart, Ctrl* ctrl, uint32_t r, uint64_t P)
 {
     const uint64_t lo = lstart[r];
     const uint64_t hi = *(volatile unsigned long long*)&ctrl->ltail;  // no claim during an apply
@@ -148,51 +164,60 @@ __global__ __launch_bounds__(256) void k_apply(uint64_t* __restrict__ rec, uint3
     }
     if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
         return;  // whole block idle (uniform)
-    __shared__ Appender app;
+    __shared__ FrontAppender app;
     app.init();
+    auto out = [front](uint64_t i, uint64_t v) { front[i] = v; };
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
-        uint32_t push0 = 0, push1 = 0;
-        uint32_t npush = 0;
+        uint64_t p0 = 0, p1 = 0;
+        uint32_t np = 0;
         if (i < hi) {
-            uint32_t e = layer[i];
-            uint32_t mask = claim_mask(hmask32, e);
-            if (round_out)
-                round_out[e] = r;
+            uint32_t e = slots[i].x;
+            uint32_t h = state[e] & 3u;
             const uint32_t* t = edges + 3 * (uint64_t)e;
             uint32_t v0 = t[0], v1 = t[1], v2 = t[2];
-            if (!(mask & 1u) && Rec::del(rec, v0, e) == 2)
-                push0 = v0, npush = 1;
-            if (!(mask & 2u) && Rec::del(rec, v1, e) == 2) {
-                if (npush) push1 = v1; else push0 = v1;
-                npush++;
+            uint32_t vh = h == 0 ? v0 : (h == 1 ? v1 : v2);
+            uint32_t va = h == 0 ? v1 : (h == 1 ? v2 : v0);
+            uint32_t vb = h == 0 ? v2 : (h == 1 ? v0 : v1);
+            slots[i] = make_uint3(vh, va, vb);
+            uint64_t oa = Rec::del(rec, va, e);
+            uint64_t ob = Rec::del(rec, vb, e);
+            if (Rec::deg(oa) == 2) {
+                uint32_t rem = (uint32_t)(Rec::edge(oa) - e);
+                p0 = fentry(rem, position_in<kTri>(edges, rem, va, P));
+                np = 1;
             }
-            if (!(mask & 4u) && Rec::del(rec, v2, e) == 2) {
-                if (npush) push1 = v2; else push0 = v2;
-                npush++;
+            if (Rec::deg(ob) == 2) {
+                uint32_t rem = (uint32_t)(Rec::edge(ob) - e);
+                uint64_t ent = fentry(rem, position_in<kTri>(edges, rem, vb, P));
+                if (np)
+                    p1 = ent;
+                else
+                    p0 = ent;
+                np++;
             }
         }
-        app.push(npush >= 1, push0, npush >= 2, push1, &ctrl->ftail, front);
+        app.push(np >= 1, p0, np >= 2, p1, &ctrl->ftail, out);
     }
-    app.flush(&ctrl->ftail, front);
+    app.flush(&ctrl->ftail, out);
 }
 
 // ------------------------------------------------------------------------------------------
-// Per-edge outputs of mphx_peel: core mask and hinge from round[] and the claim bytes.
+// Per-edge outputs of mphx_peel from the edge states.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_peel_finalize(const uint32_t* __restrict__ round,
-                                                       const uint32_t* __restrict__ hmask32, uint64_t n,
-                                                       uint8_t* __restrict__ core_mask, uint8_t* __restrict__ hinge)
+__global__ __launch_bounds__(256) void k_peel_finalize(const uint32_t* __restrict__ state, uint64_t n,
+                                                       uint32_t* __restrict__ round, uint8_t* __restrict__ core_mask,
+                                                       uint8_t* __restrict__ hinge)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
-        bool core = round[e] == kRoundCore;
+        uint32_t s = state[e];
+        bool core = s == kUnclaimed;
+        round[e] = core ? kRoundCore : (s >> 2);
         core_mask[e] = core ? 1 : 0;
-        if (hinge) {
-            uint32_t mask = claim_mask(hmask32, (uint32_t)e);
-            hinge[e] = core ? 0xFF : (uint8_t)__builtin_ctz(mask);
-        }
+        if (hinge)
+            hinge[e] = core ? 0xFF : (uint8_t)(s & 3u);
     }
 }
 
@@ -290,68 +315,47 @@ static inline unsigned grid_for(uint64_t count, unsigned cap)
     return (unsigned)g;
 }
 
-hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl,
-                              int record, hipStream_t s)
+hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    unsigned g = grid_for(n, 8192);
-    if (record == 1)
-        k_edges_build<RecSum><<<g, 256, 0, s>>>(edges, n, m, rec, ctrl);
-    else
-        k_edges_build<RecXor><<<g, 256, 0, s>>>(edges, n, m, rec, ctrl);
+    k_edges_build<<<grid_for(n, 8192), 256, 0, s>>>(edges, n, m, rec, ctrl);
     return hipGetLastError();
 }
 
-hipError_t launch_frontier_init(const uint64_t* rec, uint64_t m, uint32_t* front, Ctrl* ctrl, int record,
-                                 hipStream_t s)
+hipError_t launch_frontier_init(const PeelState& st, hipStream_t s)
 {
-    if (m == 0) return hipSuccess;
-    unsigned g = grid_for(m, 8192);
-    if (record == 1)
-        k_frontier_init<RecSum><<<g, 256, 0, s>>>(rec, m, front, ctrl);
+    if (st.m == 0) return hipSuccess;
+    unsigned g = grid_for(st.m, 8192);
+    if (st.tripartite)
+        k_frontier_init<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.front, st.ctrl);
     else
-        k_frontier_init<RecXor><<<g, 256, 0, s>>>(rec, m, front, ctrl);
+        k_frontier_init<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.front, st.ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_claim(const PeelState& st, uint32_t r, hipStream_t s)
 {
-    unsigned g = grid_for(st.m, st.grid_cap);
-    if (st.record == 1) {
-        if (st.tripartite)
-            k_claim<RecSum, true><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                    st.ctrl, r, st.P, st.n);
-        else
-            k_claim<RecSum, false><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                     st.ctrl, r, st.P, st.n);
-    } else {
-        if (st.tripartite)
-            k_claim<RecXor, true><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                    st.ctrl, r, st.P, st.n);
-        else
-            k_claim<RecXor, false><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.fstart,
-                                                     st.ctrl, r, st.P, st.n);
-    }
+    k_claim<<<grid_for(st.m, st.grid_cap), kPeelBlock, 0, s>>>(st.front, st.state, st.slots, st.fstart, st.ctrl, r);
     return hipGetLastError();
 }
 
 hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s)
 {
     unsigned g = grid_for(st.n, st.grid_cap);
-    if (st.record == 1)
-        k_apply<RecSum><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.lstart, st.round_out,
-                                          st.ctrl, r);
+    if (st.tripartite)
+        k_apply<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.front, st.edges, st.state, st.slots, st.lstart, st.ctrl, r,
+                                               st.P);
     else
-        k_apply<RecXor><<<g, 256, 0, s>>>(st.rec, st.front, st.edges, st.hmask32, st.layer, st.lstart, st.round_out,
-                                          st.ctrl, r);
+        k_apply<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.front, st.edges, st.state, st.slots, st.lstart, st.ctrl, r,
+                                                st.P);
     return hipGetLastError();
 }
 
-hipError_t launch_peel_finalize(const uint32_t* round, const uint32_t* hmask32, uint64_t n, uint8_t* core_mask,
-                                uint8_t* hinge, hipStream_t s)
+hipError_t launch_peel_finalize(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask, uint8_t* hinge,
+                                hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    k_peel_finalize<<<grid_for(n, 8192), 256, 0, s>>>(round, hmask32, n, core_mask, hinge);
+    k_peel_finalize<<<grid_for(n, 8192), 256, 0, s>>>(state, n, round, core_mask, hinge);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ __global__ void k_ctrl_init(Ctrl* ctrl, uint64_t* fstart, uint64_t* lstart)
         ctrl->err = 0;
         ctrl->aux = 0;
         ctrl->claims = 0;
+        ctrl->degsum = 0;
         fstart[0] = 0;
         lstart[0] = 0;
     }

@@ -10,25 +10,19 @@ __device__ __forceinline__ uint32_t g_of_code(uint32_t c) { return c == 3 ? 0u :
 
 // One layer: every edge solves g[v_k] = k - g[v_k+1] - g[v_k+2] (mod 3) for its hinge k.
 // Inside a layer no edge touches another edge's hinge (its only edge at round start), so the
-// edges of a layer are independent.
-__global__ __launch_bounds__(256) void k_assign_round(const uint32_t* __restrict__ edges,
-                                                      const uint32_t* __restrict__ layer,
-                                                      const uint32_t* __restrict__ hmask32,
-                                                      const uint64_t* __restrict__ lstart, uint32_t r,
+// edges of a layer are independent.  Each layer slot holds the edge's vertices hinge first; the
+// hinge position is the hinge vertex's part.
+__global__ __launch_bounds__(256) void k_assign_round(const uint3* __restrict__ slots,
+                                                      const uint64_t* __restrict__ lstart, uint32_t r, uint64_t P,
                                                       uint8_t* __restrict__ code8)
 {
     const uint64_t lo = lstart[r], hi = lstart[r + 1];
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = lo + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride) {
-        uint32_t e = layer[i];
-        uint32_t k = __builtin_ctz(claim_mask(hmask32, e));
-        const uint32_t* t = edges + 3 * (uint64_t)e;
-        uint32_t v0 = t[0], v1 = t[1], v2 = t[2];
-        uint32_t vk = k == 0 ? v0 : (k == 1 ? v1 : v2);
-        uint32_t va = k == 0 ? v1 : (k == 1 ? v2 : v0);
-        uint32_t vb = k == 0 ? v2 : (k == 1 ? v0 : v1);
-        uint32_t g = (k + 6 - g_of_code(code8[va]) - g_of_code(code8[vb])) % 3;
-        code8[vk] = (uint8_t)(g ? g : 3);
+        uint3 t = slots[i];
+        uint32_t k = part_of(t.x, P);
+        uint32_t g = (k + 6 - g_of_code(code8[t.y]) - g_of_code(code8[t.z])) % 3;
+        code8[t.x] = (uint8_t)(g ? g : 3);
     }
 }
 
@@ -126,11 +120,10 @@ static inline unsigned grid_cap(uint64_t count, unsigned cap)
     return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
 }
 
-hipError_t launch_assign_round(const uint32_t* edges, const uint32_t* layer, const uint32_t* hmask32,
-                               const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint8_t* code8,
-                               unsigned grid_cap_blocks, hipStream_t s)
+hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
+                               uint8_t* code8, unsigned grid_cap_blocks, hipStream_t s)
 {
-    k_assign_round<<<grid_cap(n_bound, grid_cap_blocks), 256, 0, s>>>(edges, layer, hmask32, lstart, r, code8);
+    k_assign_round<<<grid_cap(n_bound, grid_cap_blocks), 256, 0, s>>>(slots, lstart, r, P, code8);
     return hipGetLastError();
 }
 

@@ -1,0 +1,117 @@
+"""Parity at the full workload sizes (GPU only; minutes of CPU for the oracle).
+
+* 2^27 u64 keys: the whole MPHF (codes + rank) equals the oracle's; at gamma = 120/100 (below
+  the threshold c_3 ~ 1.221, Section 1) the peel returns exactly the oracle's 2-core, rounds,
+  hinges and order, and a one-try build reports the same 2-core size.
+* 2^31 byte-string keys generated on the device (the configuration the benchmark times): the
+  oracle cannot build it, so the test checks what holds at any size -- the device keys equal
+  the generator's definition at sampled indices, the device hash equals the oracle's hash for
+  those keys, the MPHF is a bijection onto [0, n) over all keys, the rank samples equal the
+  prefix counts of the codes, and the oracle's evaluation of the GPU tables agrees with the
+  GPU lookup at sampled keys.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mx():
+    import torch
+
+    import paper_1312_0526_amd as mx
+
+    assert torch.cuda.is_available()
+    mx.lib()
+    return mx
+
+
+def host(t, dt):
+    return t.cpu().numpy().view(dt)
+
+
+@pytest.mark.timeout(1200)
+def test_config2_full_parity(mx):
+    import torch
+
+    n = 1 << 27
+    o = oracle.Oracle()
+    keys_h = workloads.u64_keys(n)
+    keys = mx.gen_keys_u64(n)
+    assert np.array_equal(host(keys[:1000], np.uint64), keys_h[:1000])
+    assert np.array_equal(host(keys[-1000:], np.uint64), keys_h[-1000:])
+    r = mx.mphf_build_u64(keys, seed=0)
+    rc, ref = o.mphf_build_u64(keys_h, seed=0)
+    assert rc == 0 and r["tries"] == ref["tries"] == 1 and r["n_rounds"] == ref["n_rounds"]
+    assert np.array_equal(host(r["codes"], np.uint64), ref["words"])
+    assert np.array_equal(host(r["rank"], np.uint64), ref["rank"])
+    del r
+    # below the threshold: the exact 2-core through the peel entry point
+    P = o.part_size(n, 120, 100)
+    edges = o.hash_u64(keys_h, 0, P)
+    rc, pref = o.peel(edges, 3 * P, P)
+    assert rc == 0 and abs((n - pref["n_peeled"]) / n - 0.4921) < 0.003
+    got = mx.peel(torch.from_numpy(edges.view(np.int32)).cuda(), 3 * P)
+    assert got["n_peeled"] == pref["n_peeled"] and got["n_rounds"] == pref["n_rounds"]
+    for key, dt in (("order", np.uint32), ("round", np.uint32), ("core_mask", np.uint8), ("hinge", np.uint8)):
+        assert np.array_equal(host(got[key], dt), pref[key]), key
+    del got
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_u64(keys, gamma=(120, 100), max_tries=1)
+    assert ei.value.status == mx.ECORE and ei.value.info["n_core"] == n - pref["n_peeled"]
+
+
+_POP8 = np.array([bin(i).count("1") for i in range(256)], np.uint8)
+
+
+def _nz_pairs(words):
+    """Non-zero 2-bit pairs per word, counted bit by bit through a byte table."""
+    x = (words | (words >> np.uint64(1))) & np.uint64(0x5555555555555555)
+    return _POP8[x.view(np.uint8)].reshape(-1, 8).sum(axis=1, dtype=np.int64)
+
+
+@pytest.mark.timeout(1200)
+def test_config3_sampled_parity(mx):
+    import torch
+
+    n = 1 << 31
+    o = oracle.Oracle()
+    q = torch.from_numpy(workloads.quantile_table().view(np.int16)).cuda()
+    data, offs = mx.gen_str_keys(n, q, gen_seed=0)
+    rng = np.random.default_rng(7)
+    sample = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, size=2000)])).astype(np.int64)
+    offs_h = host(offs, np.uint64)
+    # device keys equal the generator's definition at sampled indices
+    for i in sample[:300]:
+        lo, hi = int(offs_h[i]), int(offs_h[i + 1])
+        assert bytes(data[lo:hi].cpu().numpy()) == workloads.str_key(int(i)), i
+    r = mx.mphf_build_str(data, offs, seed=0)
+    assert r["tries"] == 1 and r["n_core"] == 0
+    P, seed = r["P"], r["seed_used"]
+    # device hash of the sampled keys equals the oracle's
+    skeys = [workloads.str_key(int(i)) for i in sample]
+    sd = np.frombuffer(b"".join(skeys), np.uint8).copy()
+    so = np.zeros(len(skeys) + 1, np.uint64)
+    so[1:] = np.cumsum([len(k) for k in skeys])
+    ge = host(mx.hash_str(torch.from_numpy(sd).cuda(), torch.from_numpy(so.view(np.int64)).cuda(), seed, P),
+              np.uint32).reshape(-1, 3)
+    assert np.array_equal(ge, o.hash_str(sd, so, seed, P))
+    # bijection over all 2^31 keys
+    f = mx.lookup_str(r["codes"], r["rank"], P, seed, data, offs)
+    assert mx.check_bijection(f) == 0
+    f_s = host(f[torch.from_numpy(sample).cuda()], np.uint64)
+    del f
+    codes = host(r["codes"], np.uint64)
+    rank = host(r["rank"], np.uint64)
+    # the oracle's evaluation of the GPU tables at the sampled keys
+    assert np.array_equal(o.lookup_str(codes, rank, P, seed, sd, so), f_s)
+    # rank samples are the prefix counts of non-zero codes; exactly n hinge vertices
+    nz = _nz_pairs(codes)
+    per_block = np.add.reduceat(nz, np.arange(0, len(nz), 16))
+    prefix = np.concatenate([[0], np.cumsum(per_block)[:-1]])
+    assert np.array_equal(rank.astype(np.int64), prefix)
+    assert int(nz.sum()) == n

@@ -31,12 +31,14 @@ def o():
     return oracle.Oracle()
 
 
-@pytest.fixture(params=[0, 1], ids=["xor-record", "sum-record"])
+@pytest.fixture(params=[(0, 8), (96, 1)], ids=["auto-grid", "small-grid-one-round-batches"])
 def record(request, mx):
-    old = mx.get_option("record")
-    mx.set_option("record", request.param)
+    """Launch shapes: automatic grids, and a small fixed grid with a check after every round."""
+    mx.set_option("grid", request.param[0])
+    mx.set_option("round_batch", request.param[1])
     yield request.param
-    mx.set_option("record", old)
+    mx.set_option("grid", 0)
+    mx.set_option("round_batch", 8)
 
 
 def dev(a):
@@ -188,14 +190,18 @@ def test_peel_errors(mx):
         mx.peel(dev(np.array([[0, 1, 1]], np.uint32)), 5)
     assert ei.value.status == mx.EINVAL
     star = np.array([[0, 1 + i, 300 + i] for i in range(256)], np.uint32)
-    for rec in (0, 1):
-        mx.set_option("record", rec)
-        with pytest.raises(mx.MphxError) as ei:
-            mx.peel(dev(star), 600)
-        assert ei.value.status == mx.ERANGE
-        got = mx.peel(dev(star[:255]), 600)
-        assert got["n_peeled"] == 255
-    mx.set_option("record", 1)
+    with pytest.raises(mx.MphxError) as ei:
+        mx.peel(dev(star), 600)
+    assert ei.value.status == mx.ERANGE
+    got = mx.peel(dev(star[:255]), 600)
+    assert got["n_peeled"] == 255
+    # a vertex in 2^24 + 1 edges wraps a 24-bit degree field: still caught (total != 3n)
+    big = 1 << 24
+    wrap = np.stack([np.zeros(big + 1, np.uint32), np.arange(1, big + 2, dtype=np.uint32),
+                     np.arange(big + 2, 2 * big + 3, dtype=np.uint32)], axis=1)
+    with pytest.raises(mx.MphxError) as ei:
+        mx.peel(dev(wrap), 2 * big + 3)
+    assert ei.value.status == mx.ERANGE
 
 
 # ------------------------------------------------------------------------------------------
