@@ -199,6 +199,9 @@ typedef struct mphx_bucket_result {
 typedef struct mphx_batch_tuning {
     uint32_t block;  /* threads per workgroup: 256, 512 or 1024 (0 = 1024) */
     uint32_t grid;   /* workgroups in the persistent launch (0 = one per compute unit) */
+    uint32_t scope;  /* atomics on a bucket's state: 0 = workgroup scope (one workgroup owns a
+                        bucket), 1 = device scope; results are identical */
+    uint32_t reserved;
 } mphx_batch_tuning;
 
 MPHX_API int mphx_batch_layout(const uint64_t* bucket_off, uint32_t B, uint32_t gamma_num, uint32_t gamma_den,

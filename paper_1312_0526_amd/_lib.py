@@ -320,7 +320,7 @@ def gen_str_keys(n: int, qtable: torch.Tensor, gen_seed: int = 0, start: int = 0
 # batched builds
 # ------------------------------------------------------------------------------------------
 class BatchTuning(C.Structure):
-    _fields_ = [("block", C.c_uint32), ("grid", C.c_uint32)]
+    _fields_ = [("block", C.c_uint32), ("grid", C.c_uint32), ("scope", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 BUCKET_RESULT = None
@@ -348,7 +348,7 @@ def gen_buckets_u64(bucket_off: torch.Tensor) -> torch.Tensor:
 class BatchBuild:
     """A batched build plan: B buckets of u64 keys with host offsets `bucket_off` (B+1)."""
 
-    def __init__(self, bucket_off, device="cuda", gamma=(123, 100), max_tries=64, seed=0, block=0, grid=0):
+    def __init__(self, bucket_off, device="cuda", gamma=(123, 100), max_tries=64, seed=0, block=0, grid=0, scope=0):
         import numpy as np
 
         off = np.ascontiguousarray(bucket_off, dtype=np.uint64)
@@ -365,7 +365,7 @@ class BatchBuild:
             _err(rc)
         self.max_bucket = int(mx.value)
         self.host_off, self.code_off_h, self.rank_off_h = off, code_off, rank_off
-        self.tuning = BatchTuning(block, grid)
+        self.tuning = BatchTuning(block, grid, scope, 0)
         dev = self.device
         self.bucket_off = torch.from_numpy(off.view(np.int64)).to(dev)
         self.order = torch.from_numpy(order.view(np.int32)).to(dev)

@@ -787,6 +787,7 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
     L.max_n = max_bucket;
     L.block = block;
     L.grid = grid;
+    L.wg_scope = !(t && t->scope == 1);
     HIP_TRY(launch_batch(L, s));
     return MPHX_OK;
 }

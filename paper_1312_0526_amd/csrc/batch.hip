@@ -86,26 +86,33 @@ uint64_t batch_slot_bytes(uint64_t max_n, uint32_t gnum, uint32_t gden)
     return slot_layout(nullptr, max_n, 3 * P, nullptr);
 }
 
-// Loads of words that other waves of the workgroup change with atomics earlier in the same
-// kernel: atomics execute in L2, so read through to L2 instead of a possibly stale L1 line.
-__device__ __forceinline__ uint64_t ld_l2(const uint64_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ld_l2(const uint32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-// Returns the degree before the addition (the batched build checks degrees as it goes).
-__device__ __forceinline__ uint32_t rec_add_ret(uint64_t* rec, uint32_t v, uint32_t e)
-{
-    return Rec::deg(atomicAdd(reinterpret_cast<unsigned long long*>(rec + v), (unsigned long long)(Rec::kOne + e)));
-}
-
-__device__ __forceinline__ uint32_t claim_mask_l2(const uint32_t* claim, uint32_t e)
-{
-    return (ld_l2(claim + (e >> 2)) >> (8 * (e & 3))) & 0xFFu;
-}
+// A bucket's state is read and written by exactly one workgroup, so its atomics and the loads
+// of atomically updated words may use workgroup scope (kScope = __HIP_MEMORY_SCOPE_WORKGROUP)
+// instead of agent scope; both are correct and give identical results.  Loads of atomically
+// updated words always go through these helpers, never a plain load that could hit a stale L1
+// line.
+template <int kScope>
+struct Sc {
+    __device__ static __forceinline__ uint64_t ld(const uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, kScope); }
+    __device__ static __forceinline__ uint32_t ld(const uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, kScope); }
+    // degree before adding edge e at v (the batched build checks degrees as it goes)
+    __device__ static __forceinline__ uint32_t rec_add(uint64_t* rec, uint32_t v, uint32_t e)
+    {
+        return Rec::deg(__hip_atomic_fetch_add(rec + v, Rec::kOne + e, __ATOMIC_RELAXED, kScope));
+    }
+    __device__ static __forceinline__ uint64_t rec_del(uint64_t* rec, uint32_t v, uint32_t e)
+    {
+        return __hip_atomic_fetch_add(rec + v, 0ull - (Rec::kOne + e), __ATOMIC_RELAXED, kScope);
+    }
+    __device__ static __forceinline__ uint32_t fetch_or(uint32_t* p, uint32_t x)
+    {
+        return __hip_atomic_fetch_or(p, x, __ATOMIC_RELAXED, kScope);
+    }
+    __device__ static __forceinline__ uint32_t claim_mask(const uint32_t* claim, uint32_t e)
+    {
+        return (ld(claim + (e >> 2)) >> (8 * (e & 3))) & 0xFFu;
+    }
+};
 
 // Workgroup-wide exclusive scan of count values (in place is not needed: in -> out).
 template <int kBlock>
@@ -163,7 +170,7 @@ __device__ __forceinline__ void edge_of_key(uint64_t key, uint64_t seed, uint64_
     edge_of_digest(s, s, P, v0, v1, v2);
 }
 
-template <int kBlock>
+template <int kBlock, int kScope>
 __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
 {
     __shared__ uint32_t s_ftail, s_ltail, s_err;
@@ -207,9 +214,9 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
         for (uint32_t i = tid; i < n; i += kBlock) {
             uint32_t v0, v1, v2;
             edge_of_key(keys[i], sd, P, v0, v1, v2);
-            uint32_t d = rec_add_ret(L.rec, v0, i);
-            d = max(d, rec_add_ret(L.rec, v1, i));
-            d = max(d, rec_add_ret(L.rec, v2, i));
+            uint32_t d = Sc<kScope>::rec_add(L.rec, v0, i);
+            d = max(d, Sc<kScope>::rec_add(L.rec, v1, i));
+            d = max(d, Sc<kScope>::rec_add(L.rec, v2, i));
             if (d >= kMaxDegree)
                 s_err = 1;
         }
@@ -221,7 +228,7 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
         // round-0 frontier
         for (uint32_t base = 0; base < m; base += kBlock) {
             uint32_t v = base + tid;
-            bool one = v < m && Rec::deg(ld_l2(L.rec + v)) == 1;
+            bool one = v < m && Rec::deg(Sc<kScope>::ld(L.rec + v)) == 1;
             uint32_t pos = block_append(&s_ftail, one, false);
             if (one)
                 L.front[pos] = v;
@@ -238,12 +245,12 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
                 uint32_t e = 0;
                 if (i < fhi) {
                     uint32_t v = L.front[i];
-                    uint64_t x = ld_l2(L.rec + v);
+                    uint64_t x = Sc<kScope>::ld(L.rec + v);
                     if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
                         e = Rec::edge(x);
                         uint32_t k = part_of(v, P);
                         uint32_t sh = 8 * (e & 3);
-                        uint32_t old = atomicOr(&L.claim[e >> 2], (1u << k) << sh);
+                        uint32_t old = Sc<kScope>::fetch_or(&L.claim[e >> 2], (1u << k) << sh);
                         first = ((old >> sh) & 0xFFu) == 0;
                     }
                 }
@@ -263,12 +270,12 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
                 uint32_t p0 = 0, p1 = 0, np = 0;
                 if (i < lhi) {
                     uint32_t e = L.layer[i];
-                    uint32_t mask = claim_mask_l2(L.claim, e);
+                    uint32_t mask = Sc<kScope>::claim_mask(L.claim, e);
                     uint32_t v[3];
                     edge_of_key(keys[e], sd, P, v[0], v[1], v[2]);
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        if (!(mask & (1u << k)) && Rec::deg(Rec::del(L.rec, v[k], e)) == 2) {
+                        if (!(mask & (1u << k)) && Rec::deg(Sc<kScope>::rec_del(L.rec, v[k], e)) == 2) {
                             if (np) p1 = v[k]; else p0 = v[k];
                             np++;
                         }
@@ -311,7 +318,7 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
         const uint32_t lo = L.lstart[r], hi = L.lstart[r + 1];
         for (uint32_t i = lo + tid; i < hi; i += kBlock) {
             uint32_t e = L.layer[i];
-            uint32_t k = __builtin_ctz(claim_mask_l2(L.claim, e));
+            uint32_t k = __builtin_ctz(Sc<kScope>::claim_mask(L.claim, e));
             uint32_t v[3];
             edge_of_key(keys[e], sd, P, v[0], v[1], v[2]);
             uint32_t va = v[(k + 1) % 3], vb = v[(k + 2) % 3];
@@ -363,7 +370,7 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
     __syncthreads();
 }
 
-template <int kBlock>
+template <int kBlock, int kScope>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
 {
     __shared__ uint32_t s_idx;
@@ -376,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
         __syncthreads();
         if (idx >= a.B)
             break;
-        build_bucket<kBlock>(a, a.order[idx], slot);
+        build_bucket<kBlock, kScope>(a, a.order[idx], slot);
     }
 }
 
@@ -402,10 +409,12 @@ hipError_t launch_batch(const BatchLaunch& L, hipStream_t s)
     a.next = L.next;
     hipError_t err = launch_zero(L.next, sizeof(unsigned int), s);
     if (err != hipSuccess) return err;
+    constexpr int W = __HIP_MEMORY_SCOPE_WORKGROUP, A = __HIP_MEMORY_SCOPE_AGENT;
+    const bool wg = L.wg_scope;
     switch (L.block) {
-    case 256: k_batch<256><<<L.grid, 256, 0, s>>>(a); break;
-    case 512: k_batch<512><<<L.grid, 512, 0, s>>>(a); break;
-    case 1024: k_batch<1024><<<L.grid, 1024, 0, s>>>(a); break;
+    case 256: wg ? k_batch<256, W><<<L.grid, 256, 0, s>>>(a) : k_batch<256, A><<<L.grid, 256, 0, s>>>(a); break;
+    case 512: wg ? k_batch<512, W><<<L.grid, 512, 0, s>>>(a) : k_batch<512, A><<<L.grid, 512, 0, s>>>(a); break;
+    case 1024: wg ? k_batch<1024, W><<<L.grid, 1024, 0, s>>>(a) : k_batch<1024, A><<<L.grid, 1024, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -43,6 +43,7 @@ struct BatchLaunch {
     uint64_t max_n;
     unsigned int* next;
     unsigned block, grid;
+    bool wg_scope;  // workgroup-scope atomics on the bucket state
 };
 
 // batched builds (batch.hip)

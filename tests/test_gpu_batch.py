@@ -55,15 +55,15 @@ def _check_buckets(mx, o, bb, keys_h, sizes, which=None):
 SIZES = np.concatenate([[1, 3, 7, 100, 101, 4096], workloads.bucket_sizes(250, 100, 30_000, seed=5)])
 
 
-@pytest.mark.parametrize("block,grid", [(256, 0), (512, 7), (1024, 3), (256, 1)])
-def test_batch_matches_oracle(mx, o, block, grid):
+@pytest.mark.parametrize("block,grid,scope", [(256, 0, 0), (512, 7, 0), (1024, 3, 1), (256, 1, 0), (1024, 0, 1)])
+def test_batch_matches_oracle(mx, o, block, grid, scope):
     import torch
 
     off = _offsets(SIZES)
     keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
     keys_h = _host_keys(SIZES)
     assert np.array_equal(keys.cpu().numpy().view(np.uint64)[: len(keys_h)], keys_h)
-    bb = mx.BatchBuild(off, block=block, grid=grid)
+    bb = mx.BatchBuild(off, block=block, grid=grid, scope=scope)
     bb.run(keys)
     torch.cuda.synchronize()
     _check_buckets(mx, o, bb, keys_h, SIZES)
