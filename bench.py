@@ -53,15 +53,13 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
         key = 8 * n if st["kind"] == "u64" else st["key_bytes"] + 8 * n
         return key + 12 * n + 3 * 16 * n
     if phase == "frontier":
-        # every record read, an 8 B (edge, position) entry per degree-1 vertex
-        return 8 * m + 8 * F0
-    if phase == "claim":
-        # entry read 8 B and edge-state RMW 8 B per entry; layer slot append 4 B per edge
-        return 16 * F + 4 * n
+        # round 0: every record read; per degree-1 vertex an edge-state RMW (8 B) and at most
+        # one 4 B layer append
+        return 8 * m + 12 * F0
     if phase == "apply":
-        # slot read 4 + state read 4 + edge read 12 + slot write 12 per edge; two record RMW
-        # (16 B each) per edge; 8 B entry per vertex that dropped to degree 1
-        return 32 * n + 32 * n + 8 * (F - F0)
+        # per edge: slot read 4 + state read 4 + edge read 12 + slot write 12, two record RMW
+        # (16 B each); per vertex taken to degree 1: edge-state RMW 8 + at most one 4 B append
+        return 64 * n + 12 * (F - F0)
     if phase == "assign":
         # 12 B slot read + two code reads + one code write (1 B each)
         return 15 * n

@@ -180,7 +180,7 @@ MPHX_API int mphx_check_bijection(const uint64_t* vals, uint64_t n, void* scratc
  * needs 3P > 2^32 vertices.
  * mphx_build_batch_u64: device arrays keys, bucket_off, order, code_off, rank_off, codes,
  * rank, results (B entries); ws (dev, 256-byte aligned) of mphx_batch_workspace_bytes(...)
- * bytes for the same max_bucket and tuning.  Enqueues only (no synchronisation, no host
+ * bytes for the same B, max_bucket and tuning.  Enqueues only (no synchronisation, no host
  * read-back), so the call can be captured into a HIP graph.  A bucket larger than max_bucket
  * gets status MPHX_EINVAL and is left untouched.  Per-bucket status: MPHX_OK, MPHX_ECORE
  * (2-core after max_tries; duplicate keys also end here), MPHX_ERANGE (degree above 255).
@@ -206,8 +206,8 @@ typedef struct mphx_batch_tuning {
 
 MPHX_API int mphx_batch_layout(const uint64_t* bucket_off, uint32_t B, uint32_t gamma_num, uint32_t gamma_den,
                                uint64_t* code_off, uint64_t* rank_off, uint32_t* order, uint64_t* max_bucket);
-MPHX_API size_t mphx_batch_workspace_bytes(uint64_t max_bucket, uint32_t gamma_num, uint32_t gamma_den,
-                                           const mphx_batch_tuning* tuning);
+MPHX_API size_t mphx_batch_workspace_bytes(uint32_t B, uint64_t max_bucket, uint32_t gamma_num,
+                                           uint32_t gamma_den, const mphx_batch_tuning* tuning);
 MPHX_API int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order,
                                   uint32_t B, uint64_t max_bucket, uint64_t seed, uint32_t gamma_num,
                                   uint32_t gamma_den, uint32_t max_tries, const uint64_t* code_off,
@@ -220,6 +220,27 @@ MPHX_API int mphx_graph_capture_batch_u64(const uint64_t* keys, const uint64_t* 
                                           const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
                                           mphx_bucket_result* results, void* ws, size_t ws_bytes,
                                           const mphx_batch_tuning* tuning, void** graph);
+/* The general form: B buckets described one by one (dev array `buckets`), each with its own
+ * keys (u64 `keys`, or 4-byte-aligned string `bytes` + n+1 `offs` with keys == NULL), seed,
+ * output buffers (codes ceil(m_b/32) words, rank ceil(m_b/512)) and result slot.  order (dev,
+ * nullable) gives the processing order (largest first is best).  ws (dev, 256-byte aligned):
+ * mphx_batch_desc_workspace_bytes(max_bucket, ...) bytes.  Enqueue only. */
+typedef struct mphx_bucket {
+    const uint64_t* keys;
+    const uint8_t* bytes;
+    const uint64_t* offs;
+    uint64_t n;
+    uint64_t seed;
+    uint64_t* codes;
+    uint64_t* rank;
+    mphx_bucket_result* result;
+} mphx_bucket;
+
+MPHX_API size_t mphx_batch_desc_workspace_bytes(uint64_t max_bucket, uint32_t gamma_num, uint32_t gamma_den,
+                                                const mphx_batch_tuning* tuning);
+MPHX_API int mphx_build_batch(const mphx_bucket* buckets, uint32_t B, const uint32_t* order, uint64_t max_bucket,
+                              uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, void* ws, size_t ws_bytes,
+                              const mphx_batch_tuning* tuning, void* stream);
 MPHX_API int mphx_graph_launch(void* graph, void* stream);
 MPHX_API int mphx_graph_destroy(void* graph);
 
@@ -228,7 +249,10 @@ MPHX_API int mphx_graph_destroy(void* graph);
  *
  * mphx_server_create allocates one device pool of hbm_budget bytes on `device` (the only
  * device allocation the library makes) and starts `slots` worker threads (1..64), each with its
- * own HIP stream.  mphx_server_submit queues a request and returns a ticket at once; the
+ * own HIP stream.  With batch_max_keys > 0 it also reserves, inside the pool, a workspace for
+ * batched launches (when the budget leaves room for it): requests of at most that many keys
+ * then go to one more worker that builds every such request waiting at that moment together,
+ * in one persistent batched launch (mphx_build_batch); the others take the plain path.  mphx_server_submit queues a request and returns a ticket at once; the
  * request's keys and output buffers are caller-owned device memory that must stay valid until
  * the ticket completes.  Requests are admitted in arrival order as workers and pool memory
  * free up (a later request that fits may pass the queue head a bounded number of times);
@@ -270,7 +294,8 @@ typedef struct mphx_server_stats_t {
     size_t budget, in_use, peak_in_use;
 } mphx_server_stats_t;
 
-MPHX_API int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, mphx_server** server);
+MPHX_API int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, uint64_t batch_max_keys,
+                                mphx_server** server);
 MPHX_API int mphx_server_submit(mphx_server* server, const mphx_request* req, uint64_t* ticket);
 MPHX_API int mphx_server_poll(mphx_server* server, uint64_t ticket, mphx_request_result* res);
 MPHX_API int mphx_server_wait(mphx_server* server, uint64_t ticket, mphx_request_result* res);

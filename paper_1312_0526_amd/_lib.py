@@ -65,14 +65,16 @@ _SIGS = {
     "mphx_get_option": (C.c_int64, [C.c_char_p]),
     "mphx_gen_buckets_u64": (_i32, [_vp, _vp, _u32, _vp]),
     "mphx_batch_layout": (_i32, [_vp, _u32, _u32, _u32, _vp, _vp, _vp, C.POINTER(C.c_uint64)]),
-    "mphx_batch_workspace_bytes": (_sz, [_u64, _u32, _u32, _vp]),
+    "mphx_batch_workspace_bytes": (_sz, [_u32, _u64, _u32, _u32, _vp]),
     "mphx_build_batch_u64": (_i32, [_vp, _vp, _vp, _u32, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp,
                                     _vp, _sz, _vp, _vp]),
     "mphx_graph_capture_batch_u64": (_i32, [_vp, _vp, _vp, _u32, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp,
                                             _vp, _vp, _sz, _vp, C.POINTER(C.c_void_p)]),
+    "mphx_batch_desc_workspace_bytes": (_sz, [_u64, _u32, _u32, _vp]),
+    "mphx_build_batch": (_i32, [_vp, _u32, _vp, _u64, _u32, _u32, _u32, _vp, _sz, _vp, _vp]),
     "mphx_graph_launch": (_i32, [_vp, _vp]),
     "mphx_graph_destroy": (_i32, [_vp]),
-    "mphx_server_create": (_i32, [_i32, _sz, _u32, C.POINTER(C.c_void_p)]),
+    "mphx_server_create": (_i32, [_i32, _sz, _u32, _u64, C.POINTER(C.c_void_p)]),
     "mphx_server_submit": (_i32, [_vp, _vp, C.POINTER(C.c_uint64)]),
     "mphx_server_poll": (_i32, [_vp, _u64, _vp]),
     "mphx_server_wait": (_i32, [_vp, _u64, _vp]),
@@ -374,7 +376,8 @@ class BatchBuild:
         self.codes = torch.zeros(max(int(code_off[-1]), 1), dtype=torch.int64, device=dev)
         self.rank = torch.zeros(max(int(rank_off[-1]), 1), dtype=torch.int64, device=dev)
         self.results = torch.zeros(max(self.B, 1) * 24, dtype=torch.uint8, device=dev)
-        ws_bytes = lib().mphx_batch_workspace_bytes(self.max_bucket, gamma[0], gamma[1], C.byref(self.tuning))
+        ws_bytes = lib().mphx_batch_workspace_bytes(self.B, self.max_bucket, gamma[0], gamma[1],
+                                                    C.byref(self.tuning))
         if ws_bytes == 0:
             _err(EINVAL)
         self.ws = _workspace(ws_bytes, dev)
@@ -461,11 +464,11 @@ class Server:
     submit_*() returns a ticket at once; the caller keeps the key tensors alive until the
     ticket completes (the server holds references for it).  Outputs are allocated here."""
 
-    def __init__(self, hbm_budget: int, slots: int = 4, device="cuda"):
+    def __init__(self, hbm_budget: int, slots: int = 4, batch_max_keys: int = 1 << 17, device="cuda"):
         self.device = torch.device(device)
         idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
         h = C.c_void_p()
-        rc = lib().mphx_server_create(idx, int(hbm_budget), int(slots), C.byref(h))
+        rc = lib().mphx_server_create(idx, int(hbm_budget), int(slots), int(batch_max_keys), C.byref(h))
         if rc:
             raise MphxError(rc, "server create failed")
         self.h = h
@@ -544,3 +547,57 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def build_batch(buckets, gamma=(123, 100), max_tries=64, block=0, grid=0, scope=0, device="cuda"):
+    """Batched builds of independent key sets given one by one.
+
+    buckets: list of ("u64", keys) or ("str", data, offs) device tensors with a seed, as
+    (kind, *tensors, seed).  Returns one dict per bucket (status, tries, seed_used, n_rounds,
+    codes, rank), built in one persistent launch."""
+    import numpy as np
+
+    dev = torch.device(device)
+    B = len(buckets)
+    descs = np.zeros(max(B, 1), dtype=np.dtype([("keys", "<u8"), ("bytes", "<u8"), ("offs", "<u8"), ("n", "<u8"),
+                                                 ("seed", "<u8"), ("codes", "<u8"), ("rank", "<u8"),
+                                                 ("result", "<u8")]))
+    results = torch.zeros(max(B, 1) * 24, dtype=torch.uint8, device=dev)
+    outs, sizes = [], []
+    for b, bk in enumerate(buckets):
+        kind, seed = bk[0], bk[-1]
+        if kind == "u64":
+            _check(bk[1], torch.int64, "keys")
+            n = bk[1].numel()
+            descs[b]["keys"] = _ptr(bk[1])
+        else:
+            _check(bk[1], torch.uint8, "data")
+            _check(bk[2], torch.int64, "offs")
+            n = bk[2].numel() - 1
+            descs[b]["bytes"], descs[b]["offs"] = _ptr(bk[1]), _ptr(bk[2])
+        m = 3 * part_size(n, gamma)
+        codes = torch.zeros(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
+        rank = torch.zeros(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
+        descs[b]["n"], descs[b]["seed"] = n, seed
+        descs[b]["codes"], descs[b]["rank"] = _ptr(codes), _ptr(rank)
+        descs[b]["result"] = _ptr(results) + 24 * b
+        outs.append((codes, rank, m))
+        sizes.append(n)
+    d_descs = torch.from_numpy(descs.view(np.uint8).copy()).to(dev)
+    order = np.argsort(-np.asarray(sizes, dtype=np.int64), kind="stable").astype(np.int32) if B else \
+        np.zeros(1, np.int32)
+    d_order = torch.from_numpy(order).to(dev)
+    tuning = BatchTuning(block, grid, scope, 0)
+    max_bucket = max(sizes) if sizes else 0
+    ws = _workspace(lib().mphx_batch_desc_workspace_bytes(max_bucket, gamma[0], gamma[1], C.byref(tuning)), dev)
+    rc = lib().mphx_build_batch(_ptr(d_descs), B, _ptr(d_order), max_bucket, gamma[0], gamma[1], max_tries, _ptr(ws),
+                                ws.numel(), C.byref(tuning), _stream(dev))
+    if rc:
+        _err(rc)
+    res = results.cpu().numpy()[: B * 24].view(_bucket_dtype())
+    out = []
+    for b in range(B):
+        codes, rank, m = outs[b]
+        out.append(dict(status=int(res[b]["status"]), tries=int(res[b]["tries"]), seed_used=int(res[b]["seed_used"]),
+                        n_rounds=int(res[b]["n_rounds"]), codes=codes[: (m + 31) // 32], rank=rank[: (m + 511) // 512]))
+    return out

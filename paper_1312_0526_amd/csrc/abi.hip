@@ -129,7 +129,8 @@ struct Carve {
 
 struct PeelLayout {
     Ctrl* ctrl;
-    uint64_t *fstart, *lstart, *rec, *front;
+    uint64_t *lstart, *rec;
+    unsigned long long* lcount;
     uint32_t *state, *tilehist, *ids;
     uint3* slots;
     void* scan;
@@ -140,10 +141,9 @@ void layout_peel(Carve& c, uint64_t n, uint64_t m, PeelLayout& L)
 {
     uint64_t rcap = round_cap(n);
     L.ctrl = c.take<Ctrl>(1);
-    L.fstart = c.take<uint64_t>(rcap + 2);
     L.lstart = c.take<uint64_t>(rcap + 2);
+    L.lcount = c.take<unsigned long long>(rcap + 2);
     L.rec = c.take<uint64_t>(m);
-    L.front = c.take<uint64_t>(m);
     L.slots = c.take<uint3>(n);
     L.state = c.take<uint32_t>(n);
     L.ids = reinterpret_cast<uint32_t*>(L.slots);  // sort scratch once the peel is over
@@ -155,7 +155,8 @@ void layout_peel(Carve& c, uint64_t n, uint64_t m, PeelLayout& L)
 
 struct MphfLayout {
     Ctrl* ctrl;
-    uint64_t *fstart, *lstart, *rec, *front;
+    uint64_t *lstart, *rec;
+    unsigned long long* lcount;
     uint32_t *edges, *state, *bcount;
     uint3* slots;
     void* scan;
@@ -166,11 +167,10 @@ void layout_mphf(Carve& c, uint64_t n, uint64_t m, MphfLayout& L)
 {
     uint64_t rcap = round_cap(n);
     L.ctrl = c.take<Ctrl>(1);
-    L.fstart = c.take<uint64_t>(rcap + 2);
     L.lstart = c.take<uint64_t>(rcap + 2);
+    L.lcount = c.take<unsigned long long>(rcap + 2);
     L.edges = c.take<uint32_t>(3 * n);
-    L.rec = c.take<uint64_t>(m);
-    L.front = c.take<uint64_t>(m);  // also the byte codes after peeling
+    L.rec = c.take<uint64_t>(m);  // also the byte codes after peeling
     L.slots = c.take<uint3>(n);
     L.state = c.take<uint32_t>(n);
     uint64_t nblocks = (m + 511) / 512;
@@ -197,33 +197,35 @@ unsigned auto_grid(uint64_t work)
 }
 
 // Enqueue rounds in growing batches until a round finds an empty layer.  On return
-// h.nrounds holds the number of non-empty layers and h.ltail the number of peeled edges.
-int run_rounds(PeelState& st, Ctrl& h, uint64_t first_front, hipStream_t s)
+// h.nrounds holds the number of non-empty layers and *peeled the number of peeled edges.
+int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
 {
     uint32_t r = 0;
     uint32_t batch = (uint32_t)std::max(1, g_opt.round_batch.load());
-    uint64_t last_front = first_front;
+    unsigned long long next_layer = 0;
+    HIP_TRY(hipMemcpyAsync(&next_layer, st.lcount, sizeof next_layer, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     for (;;) {
         uint64_t upto = std::min<uint64_t>((uint64_t)r + batch, st.rcap);
-        st.grid_cap = auto_grid(last_front);
+        // sized for the next layer; later rounds of the batch may be larger, which only costs
+        // them more grid-stride iterations
+        st.grid_cap = auto_grid(next_layer);
         for (; r < upto; r++) {
-            {
-                Timed t(PH_CLAIM, s);
-                HIP_TRY(launch_claim(st, r, s));
-            }
             Timed t(PH_APPLY, s);
             HIP_TRY(launch_apply(st, r, s));
         }
-        uint64_t fs = 0;
-        HIP_TRY(hipMemcpyAsync(&fs, st.fstart + r, sizeof fs, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&next_layer, st.lcount + r, sizeof next_layer, hipMemcpyDeviceToHost, s));
         int rc = read_ctrl(st.ctrl, h, s);
         if (rc) return rc;
-        if (h.nrounds != 0xFFFFFFFFu) return MPHX_OK;
+        if (h.nrounds != 0xFFFFFFFFu) {
+            uint64_t p = 0;
+            HIP_TRY(hipMemcpyAsync(&p, st.lstart + h.nrounds, sizeof p, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            *peeled = p;
+            return MPHX_OK;
+        }
         if (r >= st.rcap)
             return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
-        // size of the frontier the next round starts from; later rounds of the batch may be
-        // larger, which only costs them more grid-stride iterations
-        last_front = h.ftail - std::min<uint64_t>(fs, h.ftail);
         batch = std::min<uint32_t>(batch * 2, 64);
     }
 }
@@ -337,31 +339,32 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     st.P = 0;
     st.tripartite = false;
     st.rec = L.rec;
-    st.front = L.front;
     st.slots = L.slots;
     st.state = L.state;
-    st.fstart = L.fstart;
     st.lstart = L.lstart;
+    st.lcount = L.lcount;
     st.ctrl = L.ctrl;
     st.rcap = round_cap(n);
 
     HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
     HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
-    HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
+    HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
+    HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
     {
         Timed t(PH_HASH, s);
         HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, s));
     }
     {
         Timed t(PH_FRONTIER, s);
-        HIP_TRY(launch_frontier_init(st, s));
+        HIP_TRY(launch_round0(st, s));
     }
     uint64_t f0 = 0;
     int rc = check_build_errors(L.ctrl, n, s, f0);
     if (rc) return rc;
 
     Ctrl h;
-    rc = run_rounds(st, h, f0, s);
+    uint64_t peeled = 0;
+    rc = run_rounds(st, h, &peeled, s);
     if (rc) return rc;
 
     {
@@ -372,7 +375,7 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     HIP_TRY(hipStreamSynchronize(s));
     g_timers.harvest();
     if (info) {
-        info->n_peeled = h.ltail;
+        info->n_peeled = peeled;
         info->n_rounds = h.nrounds;
         info->frontier_total = h.ftail;
         info->claims = h.claims;
@@ -503,22 +506,23 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     st.P = P;
     st.tripartite = true;
     st.rec = L.rec;
-    st.front = L.front;
     st.slots = L.slots;
     st.state = L.state;
-    st.fstart = L.fstart;
     st.lstart = L.lstart;
+    st.lcount = L.lcount;
     st.ctrl = L.ctrl;
     st.rcap = round_cap(n);
 
     Ctrl h{};
+    uint64_t peeled = 0;
     uint32_t t = 0;
-    bool peeled = false;
+    bool done = false;
     for (t = 0; t < max_tries; t++) {
         uint64_t sd = seed + t;
         HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
         HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
-        HIP_TRY(launch_ctrl_init(L.ctrl, L.fstart, L.lstart, s));
+        HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
+        HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
         {
             Timed tm(PH_HASH, s);
             if (k.kind == MPHX_KEYS_U64)
@@ -528,7 +532,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         }
         {
             Timed tm(PH_FRONTIER, s);
-            HIP_TRY(launch_frontier_init(st, s));
+            HIP_TRY(launch_round0(st, s));
         }
         uint64_t f0 = 0;
         int rc = check_build_errors(L.ctrl, n, s, f0);
@@ -536,34 +540,34 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             if (info) { info->tries = t + 1; info->seed_used = sd; }
             return rc;
         }
-        rc = run_rounds(st, h, f0, s);
+        rc = run_rounds(st, h, &peeled, s);
         if (rc) return rc;
         if (info) {
             info->tries = t + 1;
             info->seed_used = sd;
             info->n_rounds = h.nrounds;
-            info->n_core = n - h.ltail;
+            info->n_core = n - peeled;
             info->frontier_total = h.ftail;
             info->claims = h.claims;
             info->frontier0 = f0;
         }
-        if (h.ltail == n) {
-            peeled = true;
+        if (peeled == n) {
+            done = true;
             break;
         }
     }
-    if (!peeled) {
+    if (!done) {
         bool dup = false;
         int rc = detect_duplicates(k, L, n, dup, s);
         if (rc) return rc;
         if (dup) return fail(MPHX_EDUP, "duplicate keys: identical edges from equal keys stay in the 2-core");
-        return fail(MPHX_ECORE, "2-core of %llu edges after %u tries", (unsigned long long)(n - h.ltail), max_tries);
+        return fail(MPHX_ECORE, "2-core of %llu edges after %u tries", (unsigned long long)(n - peeled), max_tries);
     }
 
     // Assignment in reverse round order with exact grids from the layer bounds.
     std::vector<uint64_t> lb(h.nrounds + 1);
     HIP_TRY(hipMemcpyAsync(lb.data(), L.lstart, lb.size() * 8, hipMemcpyDeviceToHost, s));
-    uint8_t* code8 = reinterpret_cast<uint8_t*>(L.front);
+    uint8_t* code8 = reinterpret_cast<uint8_t*>(L.rec);
     HIP_TRY(launch_zero(code8, m, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int64_t r = (int64_t)h.nrounds - 1; r >= 0; r--) {
@@ -730,6 +734,7 @@ int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_
 namespace {
 
 static_assert(sizeof(mphx_bucket_result) == sizeof(BucketResult), "bucket result layouts agree");
+static_assert(sizeof(mphx_bucket) == sizeof(BucketDesc), "bucket descriptor layouts agree");
 
 int batch_tuning(const mphx_batch_tuning* t, unsigned& block, unsigned& grid)
 {
@@ -749,6 +754,12 @@ int batch_tuning(const mphx_batch_tuning* t, unsigned& block, unsigned& grid)
     return MPHX_OK;
 }
 
+size_t batch_ws_bytes(uint32_t B, uint64_t max_bucket, uint32_t gnum, uint32_t gden, unsigned grid)
+{
+    return 256 + (((size_t)B * sizeof(BucketDesc) + 255) & ~(size_t)255) +
+           (size_t)grid * batch_slot_bytes(max_bucket, gnum, gden);
+}
+
 int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order, uint32_t B,
                   uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
                   const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
@@ -765,30 +776,24 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
     int rc = batch_tuning(t, block, grid);
     if (rc) return rc;
     if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
-    size_t need = mphx_batch_workspace_bytes(max_bucket, gnum, gden, t);
+    size_t need = batch_ws_bytes(B, max_bucket, gnum, gden, grid);
     if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
-    BatchLaunch L{};
-    L.keys = keys;
-    L.bucket_off = bucket_off;
-    L.order = order;
-    L.B = B;
-    L.seed = seed;
-    L.gnum = gnum;
-    L.gden = gden;
-    L.max_tries = max_tries;
-    L.code_off = code_off;
-    L.rank_off = rank_off;
-    L.codes = codes;
-    L.rank = rank;
-    L.results = reinterpret_cast<BucketResult*>(results);
-    L.next = reinterpret_cast<unsigned int*>(ws);
-    L.slots = reinterpret_cast<uint8_t*>(ws) + 256;
-    L.slot_bytes = batch_slot_bytes(max_bucket, gnum, gden);
-    L.max_n = max_bucket;
-    L.block = block;
-    L.grid = grid;
-    L.wg_scope = !(t && t->scope == 1);
-    HIP_TRY(launch_batch(L, s));
+    uint8_t* base = reinterpret_cast<uint8_t*>(ws);
+    BucketDesc* descs = reinterpret_cast<BucketDesc*>(base + 256);
+    BatchArgs a{};
+    a.descs = descs;
+    a.order = order;
+    a.B = B;
+    a.gnum = gnum;
+    a.gden = gden;
+    a.max_tries = max_tries;
+    a.next = reinterpret_cast<unsigned int*>(base);
+    a.slots = base + 256 + (((size_t)B * sizeof(BucketDesc) + 255) & ~(size_t)255);
+    a.slot_bytes = batch_slot_bytes(max_bucket, gnum, gden);
+    a.max_n = max_bucket;
+    HIP_TRY(launch_batch_descs(descs, keys, bucket_off, B, seed, code_off, rank_off, codes, rank,
+                               reinterpret_cast<BucketResult*>(results), s));
+    HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), s));
     return MPHX_OK;
 }
 
@@ -824,11 +829,12 @@ int mphx_batch_layout(const uint64_t* bucket_off, uint32_t B, uint32_t gnum, uin
     return MPHX_OK;
 }
 
-size_t mphx_batch_workspace_bytes(uint64_t max_bucket, uint32_t gnum, uint32_t gden, const mphx_batch_tuning* t)
+size_t mphx_batch_workspace_bytes(uint32_t B, uint64_t max_bucket, uint32_t gnum, uint32_t gden,
+                                  const mphx_batch_tuning* t)
 {
     unsigned block = 0, grid = 0;
     if (batch_tuning(t, block, grid)) return 0;
-    return 256 + (size_t)grid * batch_slot_bytes(max_bucket, gnum, gden);
+    return batch_ws_bytes(B, max_bucket, gnum, gden, grid);
 }
 
 int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order, uint32_t B,
@@ -840,6 +846,45 @@ int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const
     g_err.clear();
     return batch_enqueue(keys, bucket_off, order, B, max_bucket, seed, gnum, gden, max_tries, code_off, rank_off,
                          codes, rank, results, ws, ws_bytes, t, (hipStream_t)stream);
+}
+
+size_t mphx_batch_desc_workspace_bytes(uint64_t max_bucket, uint32_t gnum, uint32_t gden, const mphx_batch_tuning* t)
+{
+    unsigned block = 0, grid = 0;
+    if (batch_tuning(t, block, grid)) return 0;
+    return 256 + (size_t)grid * batch_slot_bytes(max_bucket, gnum, gden);
+}
+
+int mphx_build_batch(const mphx_bucket* buckets, uint32_t B, const uint32_t* order, uint64_t max_bucket,
+                     uint32_t gnum, uint32_t gden, uint32_t max_tries, void* ws, size_t ws_bytes,
+                     const mphx_batch_tuning* t, void* stream)
+{
+    g_err.clear();
+    if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
+    if (B == 0) return MPHX_OK;
+    if (!buckets) return fail(MPHX_EINVAL, "null buckets");
+    if (max_bucket >= 0xFFFFFFFFull || 3 * mphx_part_size(max_bucket, gnum, gden) > 0x100000000ull)
+        return fail(MPHX_EINVAL, "max_bucket too large");
+    unsigned block = 0, grid = 0;
+    int rc = batch_tuning(t, block, grid);
+    if (rc) return rc;
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    size_t need = mphx_batch_desc_workspace_bytes(max_bucket, gnum, gden, t);
+    if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    uint8_t* base = reinterpret_cast<uint8_t*>(ws);
+    BatchArgs a{};
+    a.descs = reinterpret_cast<const BucketDesc*>(buckets);
+    a.order = order;
+    a.B = B;
+    a.gnum = gnum;
+    a.gden = gden;
+    a.max_tries = max_tries;
+    a.next = reinterpret_cast<unsigned int*>(base);
+    a.slots = base + 256;
+    a.slot_bytes = batch_slot_bytes(max_bucket, gnum, gden);
+    a.max_n = max_bucket;
+    HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), (hipStream_t)stream));
+    return MPHX_OK;
 }
 
 int mphx_graph_capture_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order,

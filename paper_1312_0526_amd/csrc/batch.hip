@@ -1,39 +1,25 @@
-// Batched MWHC builds: many independent key buckets in one persistent launch.
+// Batched MWHC builds: many independent key sets ("buckets") in one persistent launch.
 //
 // Each workgroup repeatedly takes the next bucket from a device queue (buckets ordered by
-// decreasing size, so the longest jobs start first) and runs the whole build of that bucket
-// by itself: hash (Section 3, tripartite as in Section 4.3), degree/label records (Section
-// 4.1), synchronous peeling rounds (Section 4.2) separated by workgroup barriers, a new seed
-// while a 2-core remains, assignment along the layers in reverse round order (Section 4.3),
-// then the packed codes and rank samples (Section 5).  Buckets never wait for each other, so
-// the kernel needs no grid-wide synchronisation and ends when the queue is empty.
+// decreasing size, so the longest jobs start first) and runs the whole build of that bucket by
+// itself: hash (Section 3, tripartite as in Section 4.3), degree/label records (Section 4.1),
+// synchronous peeling rounds (Section 4.2) separated by workgroup barriers, a new seed while a
+// 2-core remains, assignment along the layers in reverse round order (Section 4.3), then the
+// packed codes and rank samples (Section 5).  Buckets never wait for each other, so the kernel
+// needs no grid-wide synchronisation and ends when the queue is empty.
 //
-// A bucket's state lives in a per-workgroup slot of global memory sized for the largest
-// bucket; a bucket of up to 10^6 keys keeps its state within a few tens of MB, which stays in
-// L2 / the MALL while the workgroup works on it.  Edges are recomputed from the key whenever
-// needed (three SplitMix64 finalisers) instead of being stored.
+// Every bucket is described by its own key pointers and output pointers, so a batch can be
+// one array split by offsets (mphx_build_batch_u64) or unrelated requests gathered by the
+// build server.  The rounds follow the plain path's design: the atomic that takes a vertex
+// from degree 2 to 1 returns the vertex's remaining edge, which is claimed for the next round
+// at once with atomicMin((round << 2) | position) on the edge's state word (a claim on an edge
+// that leaves in the current round cannot lower its state); layer slots are rewritten with
+// the edge's vertices hinge first for the assignment.  u64 keys recompute their edge from the
+// key when needed; string keys keep their edges in the slot.
 #include "common.h"
 #include "launch.h"
 
 namespace mphx {
-
-struct BatchArgs {
-    const uint64_t* keys;
-    const uint64_t* bucket_off;  // B + 1
-    const uint32_t* order;       // B bucket ids, processing order
-    uint32_t B;
-    uint64_t seed;
-    uint32_t gnum, gden, max_tries;
-    const uint64_t* code_off;    // B + 1 word offsets into codes
-    const uint64_t* rank_off;    // B + 1 offsets into rank
-    uint64_t* codes;
-    uint64_t* rank;
-    BucketResult* results;
-    uint8_t* slots;
-    uint64_t slot_bytes;
-    uint64_t max_n;              // largest bucket a slot can hold
-    unsigned int* next;          // queue cursor
-};
 
 __device__ __forceinline__ uint64_t part_size_dev(uint64_t n, uint32_t gnum, uint32_t gden)
 {
@@ -42,14 +28,14 @@ __device__ __forceinline__ uint64_t part_size_dev(uint64_t n, uint32_t gnum, uin
     return (num + den - 1) / den;
 }
 
-// Slot layout for a bucket of n keys and m vertices (offsets in bytes, 256-aligned pieces).
+// Slot layout for a bucket of n keys and m vertices (256-aligned pieces).
 struct SlotLayout {
-    uint64_t* rec;      // m
-    uint32_t* front;    // m (codes as bytes after peeling)
-    uint32_t* layer;    // n
-    uint32_t* claim;    // ceil(n/4) words of claim bytes
-    uint32_t* lstart;   // n + 2 layer starts
-    uint32_t* bcount;   // ceil(m/512)
+    uint64_t* rec;     // m records (codes as bytes after peeling)
+    uint3* slots;      // n layer slots
+    uint32_t* state;   // n edge states
+    uint32_t* lstart;  // n + 2 layer starts
+    uint32_t* bcount;  // ceil(m/512)
+    uint3* edges;      // n edges (string keys only)
 };
 
 __host__ __device__ __forceinline__ uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -63,18 +49,18 @@ __host__ __device__ inline uint64_t slot_layout(uint8_t* base, uint64_t n, uint6
         return p;
     };
     uint8_t* rec = take(8 * m);
-    uint8_t* front = take(4 * m);
-    uint8_t* layer = take(4 * n);
-    uint8_t* claim = take(4 * ((n + 3) / 4));
+    uint8_t* slots = take(12 * n);
+    uint8_t* state = take(4 * n);
     uint8_t* lstart = take(4 * (n + 2));
     uint8_t* bcount = take(4 * ((m + 511) / 512));
+    uint8_t* edges = take(12 * n);
     if (L) {
         L->rec = reinterpret_cast<uint64_t*>(rec);
-        L->front = reinterpret_cast<uint32_t*>(front);
-        L->layer = reinterpret_cast<uint32_t*>(layer);
-        L->claim = reinterpret_cast<uint32_t*>(claim);
+        L->slots = reinterpret_cast<uint3*>(slots);
+        L->state = reinterpret_cast<uint32_t*>(state);
         L->lstart = reinterpret_cast<uint32_t*>(lstart);
         L->bcount = reinterpret_cast<uint32_t*>(bcount);
+        L->edges = reinterpret_cast<uint3*>(edges);
     }
     return off;
 }
@@ -104,17 +90,13 @@ struct Sc {
     {
         return __hip_atomic_fetch_add(rec + v, 0ull - (Rec::kOne + e), __ATOMIC_RELAXED, kScope);
     }
-    __device__ static __forceinline__ uint32_t fetch_or(uint32_t* p, uint32_t x)
+    __device__ static __forceinline__ uint32_t fetch_min(uint32_t* p, uint32_t x)
     {
-        return __hip_atomic_fetch_or(p, x, __ATOMIC_RELAXED, kScope);
-    }
-    __device__ static __forceinline__ uint32_t claim_mask(const uint32_t* claim, uint32_t e)
-    {
-        return (ld(claim + (e >> 2)) >> (8 * (e & 3))) & 0xFFu;
+        return __hip_atomic_fetch_min(p, x, __ATOMIC_RELAXED, kScope);
     }
 };
 
-// Workgroup-wide exclusive scan of count values (in place is not needed: in -> out).
+// Workgroup-wide exclusive scan of count values (in -> out).
 template <int kBlock>
 __device__ void block_exclusive_scan(const uint32_t* in, uint64_t* out, uint32_t count)
 {
@@ -148,7 +130,8 @@ __device__ void block_exclusive_scan(const uint32_t* in, uint64_t* out, uint32_t
     }
 }
 
-// Workgroup-local append: one LDS atomic per wave.
+// Workgroup-local append: one LDS atomic per wave; lane j asks for want1 + want2 slots
+// (want2 implies want1).
 __device__ __forceinline__ uint32_t block_append(uint32_t* counter, bool want1, bool want2)
 {
     uint64_t b1 = __ballot(want1), b2 = __ballot(want2);
@@ -163,61 +146,78 @@ __device__ __forceinline__ uint32_t block_append(uint32_t* counter, bool want1, 
     return base + lanes_below(b1) + lanes_below(b2);
 }
 
-__device__ __forceinline__ void edge_of_key(uint64_t key, uint64_t seed, uint64_t P, uint32_t& v0, uint32_t& v1,
-                                            uint32_t& v2)
+// Edge of key i of a bucket: recomputed for u64 keys, stored for string keys.
+__device__ __forceinline__ uint3 bucket_edge(const BucketDesc& d, const SlotLayout& L, uint32_t i, uint64_t sd,
+                                             uint64_t P)
 {
-    uint64_t s = key ^ seed;
-    edge_of_digest(s, s, P, v0, v1, v2);
+    if (d.keys) {
+        uint64_t s = d.keys[i] ^ sd;
+        uint32_t v0, v1, v2;
+        edge_of_digest(s, s, P, v0, v1, v2);
+        return make_uint3(v0, v1, v2);
+    }
+    return L.edges[i];
+}
+
+__device__ __forceinline__ void write_result(BucketResult* r, uint64_t seed_used, uint32_t tries, int32_t status,
+                                             uint32_t rounds)
+{
+    r->seed_used = seed_used;
+    r->tries = tries;
+    r->status = status;
+    r->n_rounds = rounds;
 }
 
 template <int kBlock, int kScope>
-__device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
+__device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* slot)
 {
-    __shared__ uint32_t s_ftail, s_ltail, s_err;
-    const uint64_t k0 = a.bucket_off[b];
-    const uint64_t n64 = a.bucket_off[b + 1] - k0;
-    if (n64 > a.max_n) {  // larger than the slots were sized for: report, touch nothing
-        if (threadIdx.x == 0) {
-            a.results[b].seed_used = a.seed;
-            a.results[b].tries = 0;
-            a.results[b].status = -1;
-            a.results[b].n_rounds = 0;
-        }
+    using S = Sc<kScope>;
+    __shared__ uint32_t s_ltail, s_err;
+    const uint32_t tid = threadIdx.x;
+    if (d.n > a.max_n) {  // larger than the slots were sized for: report, touch nothing
+        if (tid == 0)
+            write_result(d.result, d.seed, 0, -1, 0);
         __syncthreads();
         return;
     }
-    const uint32_t n = (uint32_t)n64;
-    const uint64_t* keys = a.keys + k0;
+    const uint32_t n = (uint32_t)d.n;
     const uint64_t P = part_size_dev(n, a.gnum, a.gden);
     const uint32_t m = (uint32_t)(3 * P);
     SlotLayout L;
     slot_layout(slot, n, m, &L);
-    const uint32_t tid = threadIdx.x;
+    const uint64_t total = d.keys ? 0 : d.offs[n];
 
     uint32_t t = 0, nrounds = 0;
     bool ok = false;
     int status = 0;
-    uint64_t sd = a.seed;
+    uint64_t sd = d.seed;
     for (t = 0; t < a.max_tries; t++) {
-        sd = a.seed + t;
+        sd = d.seed + t;
         for (uint32_t v = tid; v < m; v += kBlock)
             L.rec[v] = 0;
-        for (uint32_t w = tid; w < (n + 3) / 4; w += kBlock)
-            L.claim[w] = 0;
+        for (uint32_t e = tid; e < n; e += kBlock)
+            L.state[e] = kUnclaimed;
         if (tid == 0) {
-            s_ftail = 0;
             s_ltail = 0;
             s_err = 0;
         }
         __syncthreads();
-        // records (AddEdge at the three vertices)
+        // hash + records (AddEdge at the three vertices)
+        const uint64_t sa = fin(sd + kGamma), sb = fin(sd + 2 * kGamma);
         for (uint32_t i = tid; i < n; i += kBlock) {
-            uint32_t v0, v1, v2;
-            edge_of_key(keys[i], sd, P, v0, v1, v2);
-            uint32_t d = Sc<kScope>::rec_add(L.rec, v0, i);
-            d = max(d, Sc<kScope>::rec_add(L.rec, v1, i));
-            d = max(d, Sc<kScope>::rec_add(L.rec, v2, i));
-            if (d >= kMaxDegree)
+            uint3 ev;
+            if (d.keys) {
+                ev = bucket_edge(d, L, i, sd, P);
+            } else {
+                uint64_t o0 = d.offs[i], o1 = d.offs[i + 1], ha, hb;
+                digest_str(d.bytes, o0, o1 - o0, total, sa, sb, ha, hb);
+                edge_of_digest(ha, hb, P, ev.x, ev.y, ev.z);
+                L.edges[i] = ev;
+            }
+            uint32_t dg = S::rec_add(L.rec, ev.x, i);
+            dg = max(dg, S::rec_add(L.rec, ev.y, i));
+            dg = max(dg, S::rec_add(L.rec, ev.z, i));
+            if (dg >= kMaxDegree)
                 s_err = 1;
         }
         __syncthreads();
@@ -225,112 +225,107 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
             status = -2;  // degree above 255: no seed helps a duplicate-heavy bucket
             break;
         }
-        // round-0 frontier
+        // round 0: every degree-1 vertex claims its edge; first claimers fill layer 0
         for (uint32_t base = 0; base < m; base += kBlock) {
             uint32_t v = base + tid;
-            bool one = v < m && Rec::deg(Sc<kScope>::ld(L.rec + v)) == 1;
-            uint32_t pos = block_append(&s_ftail, one, false);
-            if (one)
-                L.front[pos] = v;
+            bool first = false;
+            uint32_t e = 0;
+            if (v < m) {
+                uint64_t x = S::ld(L.rec + v);
+                if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
+                    e = Rec::edge(x);
+                    first = S::fetch_min(L.state + e, part_of(v, P)) == kUnclaimed;
+                }
+            }
+            uint32_t pos = block_append(&s_ltail, first, false);
+            if (first)
+                L.slots[pos].x = e;
         }
+        if (tid == 0)
+            L.lstart[0] = 0;
         __syncthreads();
-        uint32_t flo = 0, fhi = s_ftail, r = 0;
-        L.lstart[0] = 0;  // single writer is fine: every thread writes the same value
+        uint32_t r = 0, lo = 0;
         for (;;) {
-            const uint32_t llo = s_ltail;
-            // claim
-            for (uint32_t base = flo; base < fhi; base += kBlock) {
-                uint32_t i = base + tid;
-                bool first = false;
-                uint32_t e = 0;
-                if (i < fhi) {
-                    uint32_t v = L.front[i];
-                    uint64_t x = Sc<kScope>::ld(L.rec + v);
-                    if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
-                        e = Rec::edge(x);
-                        uint32_t k = part_of(v, P);
-                        uint32_t sh = 8 * (e & 3);
-                        uint32_t old = Sc<kScope>::fetch_or(&L.claim[e >> 2], (1u << k) << sh);
-                        first = ((old >> sh) & 0xFFu) == 0;
-                    }
-                }
-                uint32_t pos = block_append(&s_ltail, first, false);
-                if (first)
-                    L.layer[pos] = e;
-            }
+            // Layer r is [lo, hi).  Applying it claims round r + 1 at once: a vertex taken to
+            // degree 1 claims its remaining edge, which is final unless that edge also leaves
+            // in round r -- and then its state already holds round r, which the claim cannot
+            // lower.  Every thread reads hi before any thread appends (barrier below).
+            const uint32_t hi = s_ltail;
             __syncthreads();
-            const uint32_t lhi = s_ltail;
             if (tid == 0)
-                L.lstart[r + 1] = lhi;
-            if (lhi == llo)
+                L.lstart[r + 1] = hi;
+            if (lo == hi)
                 break;
-            // apply
-            for (uint32_t base = llo; base < lhi; base += kBlock) {
+            const uint32_t rr = (r + 1) << 2;
+            for (uint32_t base = lo; base < hi; base += kBlock) {
                 uint32_t i = base + tid;
-                uint32_t p0 = 0, p1 = 0, np = 0;
-                if (i < lhi) {
-                    uint32_t e = L.layer[i];
-                    uint32_t mask = Sc<kScope>::claim_mask(L.claim, e);
-                    uint32_t v[3];
-                    edge_of_key(keys[e], sd, P, v[0], v[1], v[2]);
-#pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        if (!(mask & (1u << k)) && Rec::deg(Sc<kScope>::rec_del(L.rec, v[k], e)) == 2) {
-                            if (np) p1 = v[k]; else p0 = v[k];
-                            np++;
-                        }
+                uint32_t c0 = 0, c1 = 0;
+                bool f0 = false, f1 = false;
+                if (i < hi) {
+                    uint32_t e = L.slots[i].x;
+                    uint32_t h = S::ld(L.state + e) & 3u;
+                    uint3 ev = bucket_edge(d, L, e, sd, P);
+                    uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
+                    uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
+                    uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
+                    L.slots[i] = make_uint3(vh, va, vb);
+                    uint64_t oa = S::rec_del(L.rec, va, e);
+                    uint64_t ob = S::rec_del(L.rec, vb, e);
+                    if (Rec::deg(oa) == 2) {
+                        c0 = (uint32_t)(Rec::edge(oa) - e);
+                        f0 = S::fetch_min(L.state + c0, rr | part_of(va, P)) == kUnclaimed;
+                    }
+                    if (Rec::deg(ob) == 2) {
+                        c1 = (uint32_t)(Rec::edge(ob) - e);
+                        f1 = S::fetch_min(L.state + c1, rr | part_of(vb, P)) == kUnclaimed;
+                    }
+                    if (!f0) {  // the first requested slot holds the first appended edge
+                        c0 = c1;
+                        f0 = f1;
+                        f1 = false;
                     }
                 }
-                uint32_t pos = block_append(&s_ftail, np >= 1, np >= 2);
-                if (np >= 1)
-                    L.front[pos] = p0;
-                if (np >= 2)
-                    L.front[pos + 1] = p1;
+                uint32_t pos = block_append(&s_ltail, f0, f1);
+                if (f0)
+                    L.slots[pos].x = c0;
+                if (f1)
+                    L.slots[pos + 1].x = c1;
             }
             __syncthreads();
-            flo = fhi;
-            fhi = s_ftail;
+            lo = hi;
             r++;
         }
         nrounds = r;
-        if (s_ltail == n) {
+        const bool all = s_ltail == n;
+        __syncthreads();
+        if (all) {
             ok = true;
             break;
         }
-        __syncthreads();
     }
     if (!ok) {
-        if (tid == 0) {
-            a.results[b].seed_used = sd;
-            a.results[b].tries = t < a.max_tries ? t + 1 : a.max_tries;
-            a.results[b].status = status ? status : 1;
-            a.results[b].n_rounds = nrounds;
-        }
+        if (tid == 0)
+            write_result(d.result, sd, t < a.max_tries ? t + 1 : a.max_tries, status ? status : 1, nrounds);
         __syncthreads();
         return;
     }
-    // assignment, last layer first; codes as bytes in the frontier area
-    uint8_t* code8 = reinterpret_cast<uint8_t*>(L.front);
+    // assignment, last layer first; codes as bytes in the record area
+    uint8_t* code8 = reinterpret_cast<uint8_t*>(L.rec);
     for (uint32_t v = tid; v < m; v += kBlock)
         code8[v] = 0;
     __syncthreads();
     for (int32_t r = (int32_t)nrounds - 1; r >= 0; r--) {
         const uint32_t lo = L.lstart[r], hi = L.lstart[r + 1];
         for (uint32_t i = lo + tid; i < hi; i += kBlock) {
-            uint32_t e = L.layer[i];
-            uint32_t k = __builtin_ctz(Sc<kScope>::claim_mask(L.claim, e));
-            uint32_t v[3];
-            edge_of_key(keys[e], sd, P, v[0], v[1], v[2]);
-            uint32_t va = v[(k + 1) % 3], vb = v[(k + 2) % 3];
-            uint32_t ca = code8[va], cb = code8[vb];
+            uint3 sl = L.slots[i];
+            uint32_t k = part_of(sl.x, P);
+            uint32_t ca = code8[sl.y], cb = code8[sl.z];
             uint32_t g = (k + 6 - (ca == 3 ? 0 : ca) - (cb == 3 ? 0 : cb)) % 3;
-            code8[v[k]] = (uint8_t)(g ? g : 3);
+            code8[sl.x] = (uint8_t)(g ? g : 3);
         }
         __syncthreads();
     }
     // pack codes, count per 512 vertices, exclusive scan into the rank samples
-    uint64_t* codes = a.codes + a.code_off[b];
-    uint64_t* rank = a.rank + a.rank_off[b];
     const uint32_t nwords = (m + 31) / 32, nblocks = (m + 511) / 512;
     for (uint32_t base = 0; base < nwords; base += kBlock) {
         uint32_t w = base + tid;
@@ -338,18 +333,18 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
         if (w < nwords) {
             if (32 * w + 32 <= m) {
                 const uint4* p = reinterpret_cast<const uint4*>(code8 + 32 * w);
-                uint4 c0 = p[0], c1 = p[1];
-                uint32_t d[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+                uint4 q0 = p[0], q1 = p[1];
+                uint32_t dw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
 #pragma unroll
                 for (int q = 0; q < 8; q++)
 #pragma unroll
                     for (int u = 0; u < 4; u++)
-                        x |= (uint64_t)((d[q] >> (8 * u)) & 3u) << (2 * (4 * q + u));
+                        x |= (uint64_t)((dw[q] >> (8 * u)) & 3u) << (2 * (4 * q + u));
             } else {
                 for (uint32_t q = 0; 32 * w + q < m; q++)
                     x |= (uint64_t)(code8[32 * w + q] & 3u) << (2 * q);
             }
-            codes[w] = x;
+            d.codes[w] = x;
         }
         uint32_t c = nz_pairs(x);
         c += __shfl_xor(c, 1, 16);
@@ -360,13 +355,9 @@ __device__ void build_bucket(const BatchArgs& a, uint32_t b, uint8_t* slot)
             L.bcount[w >> 4] = c;
     }
     __syncthreads();
-    block_exclusive_scan<kBlock>(L.bcount, rank, nblocks);
-    if (tid == 0) {
-        a.results[b].seed_used = sd;
-        a.results[b].tries = t + 1;
-        a.results[b].status = 0;
-        a.results[b].n_rounds = nrounds;
-    }
+    block_exclusive_scan<kBlock>(L.bcount, d.rank, nblocks);
+    if (tid == 0)
+        write_result(d.result, sd, t + 1, 0, nrounds);
     __syncthreads();
 }
 
@@ -383,38 +374,53 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
         __syncthreads();
         if (idx >= a.B)
             break;
-        build_bucket<kBlock, kScope>(a, a.order[idx], slot);
+        const BucketDesc d = a.descs[a.order ? a.order[idx] : idx];
+        build_bucket<kBlock, kScope>(a, d, slot);
     }
 }
 
-hipError_t launch_batch(const BatchLaunch& L, hipStream_t s)
+// Descriptors of the buckets of one u64 key array split by offsets, with outputs at offsets.
+__global__ __launch_bounds__(256) void k_batch_descs(BucketDesc* descs, const uint64_t* keys, const uint64_t* off,
+                                                     uint32_t B, uint64_t seed, const uint64_t* code_off,
+                                                     const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                                                     BucketResult* results)
 {
-    BatchArgs a;
-    a.keys = L.keys;
-    a.bucket_off = L.bucket_off;
-    a.order = L.order;
-    a.B = L.B;
-    a.seed = L.seed;
-    a.gnum = L.gnum;
-    a.gden = L.gden;
-    a.max_tries = L.max_tries;
-    a.code_off = L.code_off;
-    a.rank_off = L.rank_off;
-    a.codes = L.codes;
-    a.rank = L.rank;
-    a.results = L.results;
-    a.slots = L.slots;
-    a.slot_bytes = L.slot_bytes;
-    a.max_n = L.max_n;
-    a.next = L.next;
-    hipError_t err = launch_zero(L.next, sizeof(unsigned int), s);
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
+        BucketDesc d;
+        d.keys = keys + off[b];
+        d.bytes = nullptr;
+        d.offs = nullptr;
+        d.n = off[b + 1] - off[b];
+        d.seed = seed;
+        d.codes = codes + code_off[b];
+        d.rank = rank + rank_off[b];
+        d.result = results + b;
+        descs[b] = d;
+    }
+}
+
+hipError_t launch_batch_descs(BucketDesc* descs, const uint64_t* keys, const uint64_t* off, uint32_t B, uint64_t seed,
+                              const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                              BucketResult* results, hipStream_t s)
+{
+    if (B == 0) return hipSuccess;
+    unsigned g = (B + 255) / 256;
+    k_batch_descs<<<g < 4096 ? g : 4096, 256, 0, s>>>(descs, keys, off, B, seed, code_off, rank_off, codes, rank,
+                                                      results);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchArgs& a, unsigned block, unsigned grid, bool wg_scope, hipStream_t s)
+{
+    hipError_t err = launch_zero(a.next, sizeof(unsigned int), s);
     if (err != hipSuccess) return err;
     constexpr int W = __HIP_MEMORY_SCOPE_WORKGROUP, A = __HIP_MEMORY_SCOPE_AGENT;
-    const bool wg = L.wg_scope;
-    switch (L.block) {
-    case 256: wg ? k_batch<256, W><<<L.grid, 256, 0, s>>>(a) : k_batch<256, A><<<L.grid, 256, 0, s>>>(a); break;
-    case 512: wg ? k_batch<512, W><<<L.grid, 512, 0, s>>>(a) : k_batch<512, A><<<L.grid, 512, 0, s>>>(a); break;
-    case 1024: wg ? k_batch<1024, W><<<L.grid, 1024, 0, s>>>(a) : k_batch<1024, A><<<L.grid, 1024, 0, s>>>(a); break;
+    switch (block) {
+    case 256: wg_scope ? k_batch<256, W><<<grid, 256, 0, s>>>(a) : k_batch<256, A><<<grid, 256, 0, s>>>(a); break;
+    case 512: wg_scope ? k_batch<512, W><<<grid, 512, 0, s>>>(a) : k_batch<512, A><<<grid, 512, 0, s>>>(a); break;
+    case 1024:
+        wg_scope ? k_batch<1024, W><<<grid, 1024, 0, s>>>(a) : k_batch<1024, A><<<grid, 1024, 0, s>>>(a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

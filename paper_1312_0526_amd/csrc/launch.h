@@ -16,44 +16,50 @@ struct PeelState {
     bool tripartite;
     unsigned grid_cap;      // max blocks of the grid-stride round kernels
     uint64_t* rec;          // m packed records
-    uint64_t* front;        // m frontier entries (edge, position) of all rounds back to back
     uint3* slots;           // n layer slots of all rounds back to back: edge id, then vertices
     uint32_t* state;        // n edge states: unclaimed or (round << 2) | hinge
-    uint64_t* fstart;       // rcap + 2 frontier starts
     uint64_t* lstart;       // rcap + 2 layer starts
+    unsigned long long* lcount;  // rcap + 2 layer sizes (append cursors), zeroed per run
     Ctrl* ctrl;
     uint64_t rcap;          // rounds the start arrays can hold
 };
 
-// Everything one batched launch needs.
-struct BatchLaunch {
-    const uint64_t* keys;
-    const uint64_t* bucket_off;
-    const uint32_t* order;
-    uint32_t B;
+// One bucket of a batched launch: its keys (u64, or string bytes + offsets), its seed and
+// where its outputs go.
+struct BucketDesc {
+    const uint64_t* keys;    // u64 keys, or nullptr for string keys
+    const uint8_t* bytes;    // string bytes (4-byte aligned)
+    const uint64_t* offs;    // n + 1 string offsets
+    uint64_t n;
     uint64_t seed;
+    uint64_t* codes;         // ceil(m/32) words
+    uint64_t* rank;          // ceil(m/512) samples
+    BucketResult* result;
+};
+static_assert(sizeof(BucketDesc) == 64, "BucketDesc is 64 bytes");
+
+struct BatchArgs {
+    const BucketDesc* descs;
+    const uint32_t* order;   // processing order (nullable: descriptor order)
+    uint32_t B;
     uint32_t gnum, gden, max_tries;
-    const uint64_t* code_off;
-    const uint64_t* rank_off;
-    uint64_t* codes;
-    uint64_t* rank;
-    BucketResult* results;
     uint8_t* slots;
     uint64_t slot_bytes;
-    uint64_t max_n;
-    unsigned int* next;
-    unsigned block, grid;
-    bool wg_scope;  // workgroup-scope atomics on the bucket state
+    uint64_t max_n;          // largest bucket a slot can hold
+    unsigned int* next;      // queue cursor
 };
 
 // batched builds (batch.hip)
 uint64_t batch_slot_bytes(uint64_t max_n, uint32_t gnum, uint32_t gden);
-hipError_t launch_batch(const BatchLaunch& L, hipStream_t s);
+hipError_t launch_batch_descs(BucketDesc* descs, const uint64_t* keys, const uint64_t* off, uint32_t B, uint64_t seed,
+                              const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                              BucketResult* results, hipStream_t s);
+hipError_t launch_batch(const BatchArgs& a, unsigned block, unsigned grid, bool wg_scope, hipStream_t s);
 
 // utilities (scan.hip)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStream_t s);
-hipError_t launch_ctrl_init(Ctrl* ctrl, uint64_t* fstart, uint64_t* lstart, hipStream_t s);
+hipError_t launch_ctrl_init(Ctrl* ctrl, uint64_t* lstart, hipStream_t s);
 size_t scan_scratch_bytes(uint64_t count);
 // exclusive scans; in and out may alias
 hipError_t launch_scan_u32(const uint32_t* in, uint64_t count, uint32_t* out, void* scratch, size_t scratch_bytes,
@@ -77,8 +83,7 @@ hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
 // peeling (peel.hip)
 hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl,
                               hipStream_t s);
-hipError_t launch_frontier_init(const PeelState& st, hipStream_t s);
-hipError_t launch_claim(const PeelState& st, uint32_t r, hipStream_t s);
+hipError_t launch_round0(const PeelState& st, hipStream_t s);
 hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s);
 hipError_t launch_peel_finalize(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask,
                                 uint8_t* hinge, hipStream_t s);

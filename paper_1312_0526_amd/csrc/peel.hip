@@ -1,31 +1,29 @@
 // Peeling kernels for gfx950: packed incidence records built with device atomics, synchronous
 // frontier rounds (Section 4.2 layered peeling), and the canonical order.
 //
-// Frontier entries carry (e, k): the only remaining edge e of a vertex that just reached
-// degree 1, and the vertex's position k in e.  The entry is written by the thread whose
-// atomic DeleteEdge took the vertex from degree 2 to 1 -- the value that atomic returned holds
-// the label sum of the two edges, so the remaining one is known at once.  Round 0's entries
-// come from a scan of all records.
+// A vertex has degree 1 at the start of round r + 1 exactly when round r's deletions took it
+// from degree 2 to 1 (or, for round 0, when the build left it at 1).  The thread whose atomic
+// DeleteEdge takes a vertex from 2 to 1 gets the vertex's old record back, whose label sum holds
+// the two remaining edges, so it knows the vertex's last edge at once and claims it for the
+// next round on the spot: atomicMin(state[e], ((r + 1) << 2) | position).  The state word of an
+// edge is unclaimed until its round, then (round << 2) | lowest claimed position -- the hinge.
+// The first claimer (old value unclaimed) appends the edge to the next layer, so each edge
+// enters one layer once (the dedupe of Section 4.2).  A vertex that drops to 1 and then to 0 in
+// the same round claims an edge that leaves in that round; that edge's state already holds the
+// round, which the later claim cannot lower, so nothing changes.
 //
-// One round r is two launches:
-//   claim(r): every entry does atomicMin(state[e], (r << 2) | k).  The first claimer (old value
-//             unclaimed) appends e to the layer, so each edge of the layer appears once (the
-//             dedupe of Section 4.2) and state[e] ends as (r << 2) | lowest claimed position.
-//             An entry whose vertex lost its last edge in the same round that gave it degree 1
-//             names an edge peeled in an earlier round: atomicMin leaves that state alone.
-//   apply(r): for each layer edge, hinge = state[e] & 3; DeleteEdge at the other two vertices;
-//             a vertex whose degree drops from 2 to 1 joins the next frontier with its
-//             remaining edge.  The hinge vertex has degree 1 and dies with the edge.  The edge's
-//             vertices, hinge first, are written back into its layer slot for the assignment.
-// Round bounds are read from device memory, so rounds are enqueued without host round trips;
-// a round after the last one finds an empty frontier and does nothing.
+// One launch per round: apply(r) takes layer r = [lstart[r], lstart[r] + count[r]) -- count[r]
+// was final when apply(r - 1) ended -- writes each edge's vertices back into its layer slot
+// hinge first (for the assignment), deletes the edge at its two other vertices (the hinge has
+// degree 1 and dies with it) and appends the next layer through count[r + 1].  Round bounds
+// live in device memory, so rounds are enqueued without host round trips; a round after the
+// last one finds an empty layer and does nothing.
 #include "common.h"
 #include "launch.h"
 
 namespace mphx {
 
 constexpr int kPeelBlock = 256;
-using FrontAppender = BlockAppender<uint64_t, kPeelBlock, 2048>;
 using LayerAppender = BlockAppender<uint32_t, kPeelBlock, 2048>;
 
 // Position of vertex v in edge e (generic edge lists; tripartite ones use the part).
@@ -61,102 +59,68 @@ __global__ __launch_bounds__(256) void k_edges_build(const uint32_t* __restrict_
 }
 
 // ------------------------------------------------------------------------------------------
-// Round-0 frontier: every vertex of degree 1 with its edge.  Also checks the degrees: a field
-// above 255, or a total that differs from 3n (a wrapped field), means some degree exceeded 255.
+// Round 0: every vertex of degree 1 claims its edge; first claimers fill layer 0.  Also checks
+// the degrees: a field above 255, or a total that differs from 3n (a wrapped field), means some
+// degree exceeded 255.
 // ------------------------------------------------------------------------------------------
 template <bool kTri>
-__global__ __launch_bounds__(kPeelBlock) void k_frontier_init(const uint64_t* __restrict__ rec, uint64_t m,
-                                                              const uint32_t* __restrict__ edges, uint64_t P,
-                                                              uint64_t* __restrict__ front, Ctrl* ctrl)
+__global__ __launch_bounds__(kPeelBlock) void k_round0(const uint64_t* __restrict__ rec, uint64_t m,
+                                                       const uint32_t* __restrict__ edges, uint64_t P, uint64_t n,
+                                                       uint32_t* __restrict__ state, uint3* __restrict__ slots,
+                                                       unsigned long long* __restrict__ lcount, Ctrl* ctrl)
 {
-    __shared__ FrontAppender app;
-    __shared__ unsigned long long s_deg;
+    __shared__ LayerAppender app;
+    __shared__ unsigned long long s_deg, s_ones, s_claims;
     if (threadIdx.x == 0)
-        s_deg = 0;
+        s_deg = s_ones = s_claims = 0;
     app.init();
-    auto out = [front](uint64_t i, uint64_t v) { front[i] = v; };
-    unsigned long long mydeg = 0;
+    auto out = [slots](uint64_t i, uint32_t e) { slots[i].x = e; };
+    unsigned long long mydeg = 0, myones = 0, myclaims = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
         uint64_t v = base + threadIdx.x;
-        bool one = false;
-        uint64_t ent = 0;
+        bool first = false;
+        uint32_t e = 0;
         if (v < m) {
             uint64_t x = rec[v];
             uint32_t d = Rec::deg(x);
             mydeg += d;
             if (d > kMaxDegree)
                 atomicOr(&ctrl->err, kErrDegree);
-            one = d == 1;
-            if (one) {
-                uint32_t e = Rec::edge(x);
-                ent = fentry(e, position_in<kTri>(edges, e, (uint32_t)v, P));
+            if (d == 1 && Rec::edge(x) < n) {
+                e = Rec::edge(x);
+                uint32_t old = atomicMin(&state[e], position_in<kTri>(edges, e, (uint32_t)v, P));
+                first = old == kUnclaimed;
+                myones++;
+                myclaims++;
             }
         }
-        app.push(one, ent, false, 0ull, &ctrl->ftail, out);
+        app.push(first, e, false, 0u, &lcount[0], out);
     }
-    app.flush(&ctrl->ftail, out);
-    if (mydeg)
-        atomicAdd(&s_deg, mydeg);
+    app.flush(&lcount[0], out);
+    if (mydeg) atomicAdd(&s_deg, mydeg);
+    if (myones) atomicAdd(&s_ones, myones);
+    if (myclaims) atomicAdd(&s_claims, myclaims);
     __syncthreads();
-    if (threadIdx.x == 0 && s_deg)
-        atomicAdd(&ctrl->degsum, s_deg);
+    if (threadIdx.x == 0) {
+        if (s_deg) atomicAdd(&ctrl->degsum, s_deg);
+        if (s_ones) atomicAdd(&ctrl->ftail, s_ones);
+        if (s_claims) atomicAdd(&ctrl->claims, s_claims);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
-// Claim phase of round r.
-// ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kPeelBlock) void k_claim(const uint64_t* __restrict__ front, uint32_t* __restrict__ state,
-                                                      uint3* __restrict__ slots, uint64_t* __restrict__ fstart,
-                                                      Ctrl* ctrl, uint32_t r)
-{
-    const uint64_t lo = fstart[r];
-    const uint64_t hi = *(volatile unsigned long long*)&ctrl->ftail;  // no push during a claim
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        fstart[r + 1] = hi;
-    if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
-        return;  // whole block idle (uniform)
-    __shared__ LayerAppender app;
-    __shared__ uint32_t nclaims;
-    if (threadIdx.x == 0)
-        nclaims = 0;
-    app.init();
-    auto out = [slots](uint64_t i, uint32_t e) { slots[i].x = e; };
-    uint32_t myclaims = 0;
-    const uint32_t rr = r << 2;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
-        uint64_t i = base + threadIdx.x;
-        bool first = false;
-        uint32_t e = 0;
-        if (i < hi) {
-            uint64_t f = front[i];
-            e = fentry_edge(f);
-            uint32_t old = atomicMin(&state[e], rr | fentry_pos(f));
-            first = old == kUnclaimed;
-            myclaims += (old == kUnclaimed || (old >> 2) == r) ? 1u : 0u;
-        }
-        app.push(first, e, false, 0u, &ctrl->ltail, out);
-    }
-    app.flush(&ctrl->ltail, out);
-    if (myclaims)
-        atomicAdd(&nclaims, myclaims);
-    __syncthreads();
-    if (threadIdx.x == 0 && nclaims)
-        atomicAdd(&ctrl->claims, (unsigned long long)nclaims);
-}
-
-// ------------------------------------------------------------------------------------------
-// Apply phase of round r.
+// Round r: delete layer r's edges and claim round r + 1.
 // ------------------------------------------------------------------------------------------
 template <bool kTri>
-__global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec, uint64_t* __restrict__ front,
-                                                      const uint32_t* __restrict__ edges,
-                                                      const uint32_t* __restrict__ state, uint3* __restrict__ slots,
-                                                      uint64_t* __restrict__ lstart, Ctrl* ctrl, uint32_t r, uint64_t P)
+__global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec, const uint32_t* __restrict__ edges,
+                                                      uint32_t* __restrict__ state, uint3* __restrict__ slots,
+                                                      uint64_t* __restrict__ lstart,
+                                                      unsigned long long* __restrict__ lcount, Ctrl* ctrl, uint32_t r,
+                                                      uint64_t P)
 {
     const uint64_t lo = lstart[r];
-    const uint64_t hi = *(volatile unsigned long long*)&ctrl->ltail;  // no claim during an apply
+    const uint64_t hi = lo + lcount[r];  // final: appended during the previous launch
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         lstart[r + 1] = hi;
         if (hi == lo)
@@ -164,14 +128,19 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
     }
     if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
         return;  // whole block idle (uniform)
-    __shared__ FrontAppender app;
+    __shared__ LayerAppender app;
+    __shared__ unsigned long long s_push, s_claims;
+    if (threadIdx.x == 0)
+        s_push = s_claims = 0;
     app.init();
-    auto out = [front](uint64_t i, uint64_t v) { front[i] = v; };
+    auto out = [slots, hi](uint64_t i, uint32_t e) { slots[hi + i].x = e; };
+    unsigned long long mypush = 0, myclaims = 0;
+    const uint32_t rr = (r + 1) << 2;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
-        uint64_t p0 = 0, p1 = 0;
-        uint32_t np = 0;
+        uint32_t c0 = 0, c1 = 0;
+        bool f0 = false, f1 = false;
         if (i < hi) {
             uint32_t e = slots[i].x;
             uint32_t h = state[e] & 3u;
@@ -184,23 +153,35 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
             uint64_t oa = Rec::del(rec, va, e);
             uint64_t ob = Rec::del(rec, vb, e);
             if (Rec::deg(oa) == 2) {
-                uint32_t rem = (uint32_t)(Rec::edge(oa) - e);
-                p0 = fentry(rem, position_in<kTri>(edges, rem, va, P));
-                np = 1;
+                c0 = (uint32_t)(Rec::edge(oa) - e);
+                uint32_t old = atomicMin(&state[c0], rr | position_in<kTri>(edges, c0, va, P));
+                f0 = old == kUnclaimed;
+                mypush++;
+                myclaims += (f0 || (old >> 2) == r + 1) ? 1u : 0u;
             }
             if (Rec::deg(ob) == 2) {
-                uint32_t rem = (uint32_t)(Rec::edge(ob) - e);
-                uint64_t ent = fentry(rem, position_in<kTri>(edges, rem, vb, P));
-                if (np)
-                    p1 = ent;
-                else
-                    p0 = ent;
-                np++;
+                c1 = (uint32_t)(Rec::edge(ob) - e);
+                uint32_t old = atomicMin(&state[c1], rr | position_in<kTri>(edges, c1, vb, P));
+                f1 = old == kUnclaimed;
+                mypush++;
+                myclaims += (f1 || (old >> 2) == r + 1) ? 1u : 0u;
+            }
+            if (!f0) {  // the first requested slot holds the first appended edge
+                c0 = c1;
+                f0 = f1;
+                f1 = false;
             }
         }
-        app.push(np >= 1, p0, np >= 2, p1, &ctrl->ftail, out);
+        app.push(f0, c0, f1, c1, &lcount[r + 1], out);
     }
-    app.flush(&ctrl->ftail, out);
+    app.flush(&lcount[r + 1], out);
+    if (mypush) atomicAdd(&s_push, mypush);
+    if (myclaims) atomicAdd(&s_claims, myclaims);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_push) atomicAdd(&ctrl->ftail, s_push);
+        if (s_claims) atomicAdd(&ctrl->claims, s_claims);
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -322,20 +303,16 @@ hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uin
     return hipGetLastError();
 }
 
-hipError_t launch_frontier_init(const PeelState& st, hipStream_t s)
+hipError_t launch_round0(const PeelState& st, hipStream_t s)
 {
     if (st.m == 0) return hipSuccess;
     unsigned g = grid_for(st.m, 8192);
     if (st.tripartite)
-        k_frontier_init<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.front, st.ctrl);
+        k_round0<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots, st.lcount,
+                                                st.ctrl);
     else
-        k_frontier_init<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.front, st.ctrl);
-    return hipGetLastError();
-}
-
-hipError_t launch_claim(const PeelState& st, uint32_t r, hipStream_t s)
-{
-    k_claim<<<grid_for(st.m, st.grid_cap), kPeelBlock, 0, s>>>(st.front, st.state, st.slots, st.fstart, st.ctrl, r);
+        k_round0<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots, st.lcount,
+                                                 st.ctrl);
     return hipGetLastError();
 }
 
@@ -343,11 +320,11 @@ hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s)
 {
     unsigned g = grid_for(st.n, st.grid_cap);
     if (st.tripartite)
-        k_apply<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.front, st.edges, st.state, st.slots, st.lstart, st.ctrl, r,
+        k_apply<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, st.ctrl, r,
                                                st.P);
     else
-        k_apply<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.front, st.edges, st.state, st.slots, st.lstart, st.ctrl, r,
-                                                st.P);
+        k_apply<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, st.ctrl,
+                                                r, st.P);
     return hipGetLastError();
 }
 

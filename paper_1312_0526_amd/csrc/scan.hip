@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint64_t count, u
         p[i] = value;
 }
 
-__global__ void k_ctrl_init(Ctrl* ctrl, uint64_t* fstart, uint64_t* lstart)
+__global__ void k_ctrl_init(Ctrl* ctrl, uint64_t* lstart)
 {
     if (threadIdx.x == 0) {
         ctrl->ftail = 0;
@@ -39,7 +39,6 @@ __global__ void k_ctrl_init(Ctrl* ctrl, uint64_t* fstart, uint64_t* lstart)
         ctrl->aux = 0;
         ctrl->claims = 0;
         ctrl->degsum = 0;
-        fstart[0] = 0;
         lstart[0] = 0;
     }
 }
@@ -171,9 +170,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t count, uint32_t value, hipStrea
     return hipGetLastError();
 }
 
-hipError_t launch_ctrl_init(Ctrl* ctrl, uint64_t* fstart, uint64_t* lstart, hipStream_t s)
+hipError_t launch_ctrl_init(Ctrl* ctrl, uint64_t* lstart, hipStream_t s)
 {
-    k_ctrl_init<<<1, 64, 0, s>>>(ctrl, fstart, lstart);
+    k_ctrl_init<<<1, 64, 0, s>>>(ctrl, lstart);
     return hipGetLastError();
 }
 

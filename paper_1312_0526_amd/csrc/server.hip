@@ -6,7 +6,13 @@
 // small request may pass a large one that does not fit yet -- but only a bounded number of
 // times, after which the head of the queue blocks admission until it fits.  Admitted builds run
 // concurrently on their streams and overlap on the device; each frees its workspace when done.
-// Keys and outputs stay in caller-owned device memory; a build writes exactly what
+//
+// Requests of at most `batch_max_keys` keys take a separate lane: one more worker gathers every
+// such request waiting at that moment (same gamma and try limit, at most kLaneMax) and builds
+// them all in one persistent batched launch, from a workspace reserved in the pool when the
+// server starts.  Requests that arrive meanwhile form the next batch.
+//
+// Keys and outputs stay in caller-owned device memory; every build writes exactly what
 // mphx_mphf_build_{u64,str} writes for the same request alone.
 #include <chrono>
 #include <condition_variable>
@@ -82,7 +88,9 @@ struct Job {
     uint32_t skipped = 0;
 };
 
-constexpr uint32_t kMaxSkips = 8;  // times the queue head may be passed by later requests
+constexpr uint32_t kMaxSkips = 8;   // times the queue head may be passed by later requests
+constexpr uint32_t kLaneMax = 4096; // requests per batched launch
+constexpr uint32_t kLaneGrid = 128; // workgroups of the batched launch
 
 }  // namespace
 
@@ -101,6 +109,96 @@ struct mphx_server {
     uint64_t next_ticket = 1;
     uint32_t running = 0;
     size_t in_use = 0, peak_in_use = 0;
+
+    // batching lane
+    uint64_t lane_max = 0;                  // 0 = no lane
+    std::deque<Job> lane_pending;
+    uint8_t* lane_ws = nullptr;              // slots of the batched launch
+    size_t lane_ws_bytes = 0;
+    mphx_bucket* lane_descs = nullptr;       // device descriptors
+    mphx_bucket_result* lane_results = nullptr;
+    uint64_t lane_batches = 0;
+    mphx_batch_tuning lane_tuning{1024, kLaneGrid, 0, 0};
+
+    bool to_lane(const mphx_request& q) const { return lane_max && q.n <= lane_max; }
+
+    void lane_worker()
+    {
+        (void)hipSetDevice(device);
+        hipStream_t st = nullptr;
+        (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        std::vector<Job> batch;
+        std::vector<mphx_bucket> hd;
+        std::vector<mphx_bucket_result> hr;
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            while (lane_pending.empty() && !stopping)
+                cv_work.wait(lk);
+            if (lane_pending.empty() && stopping) break;
+            const mphx_request& h = lane_pending.front().req;
+            batch.clear();
+            for (auto it = lane_pending.begin(); it != lane_pending.end() && batch.size() < kLaneMax;) {
+                const mphx_request& q = it->req;
+                if (q.gamma_num == h.gamma_num && q.gamma_den == h.gamma_den && q.max_tries == h.max_tries) {
+                    batch.push_back(*it);
+                    it = lane_pending.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+            running++;
+            lk.unlock();
+
+            std::sort(batch.begin(), batch.end(), [](const Job& x, const Job& y) { return x.req.n > y.req.n; });
+            const uint32_t B = (uint32_t)batch.size();
+            hd.resize(B);
+            hr.assign(B, mphx_bucket_result{});
+            uint64_t mx = 0;
+            for (uint32_t i = 0; i < B; i++) {
+                const mphx_request& q = batch[i].req;
+                hd[i] = mphx_bucket{q.key_kind == MPHX_KEYS_U64 ? q.keys : nullptr,
+                                    q.key_kind == MPHX_KEYS_U64 ? nullptr : q.bytes,
+                                    q.key_kind == MPHX_KEYS_U64 ? nullptr : q.offs,
+                                    q.n, q.seed, q.codes, q.rank, lane_results + i};
+                mx = std::max(mx, q.n);
+            }
+            const double t_start = now_s();
+            int status = MPHX_OK;
+            if (hipMemcpyAsync(lane_descs, hd.data(), B * sizeof(mphx_bucket), hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                status = MPHX_EDEVICE;
+            if (status == MPHX_OK)
+                status = mphx_build_batch(lane_descs, B, nullptr, mx, batch[0].req.gamma_num, batch[0].req.gamma_den,
+                                          batch[0].req.max_tries, lane_ws, lane_ws_bytes, &lane_tuning, st);
+            if (status == MPHX_OK &&
+                (hipMemcpyAsync(hr.data(), lane_results, B * sizeof(mphx_bucket_result), hipMemcpyDeviceToHost, st) !=
+                     hipSuccess ||
+                 hipStreamSynchronize(st) != hipSuccess))
+                status = MPHX_EDEVICE;
+            const double t_done = now_s();
+
+            lk.lock();
+            for (uint32_t i = 0; i < B; i++) {
+                const mphx_request& q = batch[i].req;
+                mphx_request_result r{};
+                r.status = status == MPHX_OK ? hr[i].status : status;
+                r.tries = hr[i].tries;
+                r.n_rounds = hr[i].n_rounds;
+                r.seed_used = hr[i].seed_used;
+                r.P = mphx_part_size(q.n, q.gamma_num, q.gamma_den);
+                r.m = 3 * r.P;
+                r.t_submit = batch[i].t_submit;
+                r.t_start = t_start;
+                r.t_done = t_done;
+                done[batch[i].ticket] = r;
+            }
+            lane_batches++;
+            running--;
+            cv_done.notify_all();
+        }
+        lk.unlock();
+        (void)hipStreamDestroy(st);
+    }
 
     // Take the next admissible job (called with mu held); false if none fits now.
     bool admit(Job& out, size_t& off)
@@ -174,7 +272,7 @@ struct mphx_server {
 
 extern "C" {
 
-int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, mphx_server** out)
+int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, uint64_t batch_max_keys, mphx_server** out)
 {
     if (!out || slots == 0 || slots > 64 || hbm_budget < 256) return MPHX_EINVAL;
     *out = nullptr;
@@ -188,8 +286,26 @@ int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, mphx_serve
         return MPHX_ENOMEM;
     }
     s->alloc.init(s->budget);
+    if (batch_max_keys) {
+        // reserve the lane's workspace (sized for batch_max_keys keys at gamma 1.23),
+        // descriptors and results; without room for it the server has no lane
+        size_t ws = mphx_batch_desc_workspace_bytes(batch_max_keys, 123, 100, &s->lane_tuning);
+        size_t extra = (size_t)kLaneMax * (sizeof(mphx_bucket) + sizeof(mphx_bucket_result)) + 512;
+        size_t off = 0;
+        if (ws && ws + extra < s->budget / 2 && s->alloc.alloc(ws + extra, off)) {
+            s->lane_max = batch_max_keys;
+            s->lane_ws = s->pool + off;
+            s->lane_ws_bytes = ws;
+            s->lane_descs = reinterpret_cast<mphx_bucket*>(s->pool + off + ((ws + 255) & ~(size_t)255));
+            s->lane_results = reinterpret_cast<mphx_bucket_result*>(reinterpret_cast<uint8_t*>(s->lane_descs) +
+                                                                    (size_t)kLaneMax * sizeof(mphx_bucket));
+            s->in_use += ws + extra;
+        }
+    }
     for (uint32_t i = 0; i < slots; i++)
         s->workers.emplace_back([s] { s->worker(); });
+    if (s->lane_max)
+        s->workers.emplace_back([s] { s->lane_worker(); });
     *out = s;
     return MPHX_OK;
 }
@@ -216,8 +332,20 @@ int mphx_server_submit(mphx_server* s, const mphx_request* req, uint64_t* ticket
         s->cv_done.notify_all();
         return MPHX_OK;
     }
+    if (s->to_lane(j.req)) {
+        const mphx_request& q = j.req;
+        // only if the request's own slots (at its gamma) fit the lane's reserved workspace
+        size_t need = q.gamma_num && q.gamma_den && q.max_tries
+                          ? mphx_batch_desc_workspace_bytes(q.n, q.gamma_num, q.gamma_den, &s->lane_tuning)
+                          : 0;
+        if (need && need <= s->lane_ws_bytes && (q.key_kind == MPHX_KEYS_U64 || ((uintptr_t)q.bytes & 3) == 0)) {
+            s->lane_pending.push_back(j);
+            s->cv_work.notify_all();
+            return MPHX_OK;
+        }
+    }
     s->pending.push_back(j);
-    s->cv_work.notify_one();
+    s->cv_work.notify_all();
     return MPHX_OK;
 }
 
@@ -246,7 +374,7 @@ int mphx_server_stats(mphx_server* s, mphx_server_stats_t* st)
 {
     if (!s || !st) return MPHX_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
-    st->pending = (uint32_t)s->pending.size();
+    st->pending = (uint32_t)(s->pending.size() + s->lane_pending.size());
     st->running = s->running;
     st->completed = (uint64_t)s->done.size();
     st->budget = s->budget;

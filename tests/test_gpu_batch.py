@@ -128,3 +128,31 @@ def test_batch_rejects_oversize_bucket(mx):
     res = bb.bucket_results()
     assert res[1]["status"] == mx.EINVAL
     assert res[0]["status"] in (0, 1) and res[2]["status"] in (0, 1)
+
+
+def test_build_batch_descriptors_mixed_kinds(mx, o):
+    """The general entry point: unrelated u64 and string key sets, each with its own seed and
+    outputs, built in one launch; each equals the oracle's single build."""
+    import torch
+
+    def dev(a):
+        a = np.ascontiguousarray(a)
+        return torch.from_numpy(a.view(np.int64) if a.dtype == np.uint64 else a).cuda()
+
+    buckets, refs = [], []
+    for i, n in enumerate([1, 5, 100, 999, 5000, 30000, 70001]):
+        keys = workloads.u64_keys(n, gen_seed=300 + i)
+        buckets.append(("u64", dev(keys), 7 + i))
+        refs.append(o.mphf_build_u64(keys, seed=7 + i))
+        d, of = workloads.str_keys(n, gen_seed=400 + i)
+        buckets.append(("str", dev(d), dev(of), 9 + i))
+        refs.append(o.mphf_build_str(d, of, seed=9 + i))
+    for block, scope in ((1024, 0), (256, 1)):
+        out = mx.build_batch(buckets, block=block, grid=5, scope=scope)
+        for b, (got, (rc, ref)) in enumerate(zip(out, refs)):
+            assert got["status"] == rc, b
+            assert got["tries"] == ref["tries"] and got["seed_used"] == ref["seed_used"], b
+            if rc == 0:
+                assert got["n_rounds"] == ref["n_rounds"], b
+                assert np.array_equal(got["codes"].cpu().numpy().view(np.uint64), ref["words"]), b
+                assert np.array_equal(got["rank"].cpu().numpy().view(np.uint64), ref["rank"]), b

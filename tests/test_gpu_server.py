@@ -30,10 +30,11 @@ def _dev(a):
 
 
 def _requests():
+    """Sizes on both sides of the batching lane's limit (2^17 keys by default)."""
     reqs = []
-    for i, n in enumerate([1000, 5000, 200_000, 3_000_000, 777, 60_000]):
+    for i, n in enumerate([1000, 5000, 200_000, 3_000_000, 777, 60_000, 100, 131_072, 131_073]):
         reqs.append(("u64", _dev(workloads.u64_keys(n, gen_seed=100 + i)), None, 10 + i))
-    for i, n in enumerate([2000, 150_000, 1_000_000]):
+    for i, n in enumerate([2000, 150_000, 1_000_000, 30, 9000]):
         d, o = workloads.str_keys(n, gen_seed=200 + i)
         reqs.append(("str", _dev(d), _dev(o), 20 + i))
     return reqs
@@ -57,6 +58,8 @@ def test_mix_equals_alone(mx):
     reqs = _requests()
     alone = [_alone(mx, r) for r in reqs]
     srv = mx.Server(hbm_budget=8 << 30, slots=4)
+    base = srv.stats()["in_use"]  # the batching lane's reserved workspace
+    assert base > 0
     tickets = [_submit(srv, r) for r in reqs]
     res = [srv.wait(t) for t in tickets]
     torch.cuda.synchronize()
@@ -68,13 +71,16 @@ def test_mix_equals_alone(mx):
     spans = sorted((r["t_start"], r["t_done"]) for r in res)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
     st = srv.stats()
-    assert st["completed"] == len(reqs) and st["in_use"] == 0 and st["peak_in_use"] > 0
+    assert st["completed"] == len(reqs) and st["in_use"] == base and st["peak_in_use"] > base
     srv.close()
-    # spot-check two results against the oracle
+    # spot-check results against the oracle
     o = oracle.Oracle()
     keys = workloads.u64_keys(5000, gen_seed=101)
     rc, ref = o.mphf_build_u64(keys, seed=11)
     assert np.array_equal(res[1]["codes"].cpu().numpy().view(np.uint64), ref["words"])
+    d, of = workloads.str_keys(9000, gen_seed=204)
+    rc, ref = o.mphf_build_str(d, of, seed=24)
+    assert np.array_equal(res[-1]["codes"].cpu().numpy().view(np.uint64), ref["words"])
 
 
 def test_tiny_budget_queues_but_never_fails(mx):
@@ -84,6 +90,7 @@ def test_tiny_budget_queues_but_never_fails(mx):
     ws = [(mx.mphf_workspace_bytes(r[1].numel()) + 255) // 256 * 256 for r in reqs]
     budget = max(ws) + 4096
     srv = mx.Server(hbm_budget=budget, slots=4)
+    assert srv.stats()["in_use"] == 0  # no room for a batching lane at this budget
     tickets = [_submit(srv, r) for r in reqs]
     res = [srv.wait(t) for t in tickets]
     assert all(r["status"] == 0 for r in res)
