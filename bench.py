@@ -48,10 +48,13 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
     """
     n, m = st["n"], st["m"]
     F, F0, C = st["frontier_total"], st["frontier0"], st["claims"]
-    if phase == "hash_build":
-        # key (u64: 8 B; strings: the bytes + one 8 B offset), edge write 12 B, 3 record RMW
+    if phase == "hash":
+        # key (u64: 8 B; strings: the bytes + one 8 B offset) read, 12 B edge written
         key = 8 * n if st["kind"] == "u64" else st["key_bytes"] + 8 * n
-        return key + 12 * n + 3 * 16 * n
+        return key + 12 * n
+    if phase == "build":
+        # every edge read once, every 8 B vertex record written once
+        return 12 * n + 8 * m
     if phase == "frontier":
         # round 0: every record read; per degree-1 vertex an edge-state RMW (8 B) and at most
         # one 4 B layer append

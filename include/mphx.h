@@ -333,17 +333,50 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *   "round_batch" peeling rounds enqueued between two checks of the termination flag.
  *   "timing"      1 = record a HIP event pair on the caller's stream around every kernel
  *                 launch of mphx_peel / mphx_mphf_build_*, accumulated per phase.
+ *   "part_build"  1 (default) = mphx_mphf_build_* builds the vertex records by partitioning
+ *                 each part's (vertex, edge) incidences into buckets of 2^14 vertices and
+ *                 accumulating each bucket in LDS; 0 = device atomics straight into HBM.
+ *                 Both give identical records; mphx_peel always uses the atomics.
  * Returns MPHX_EINVAL for an unknown key or value.
  *
  * mphx_phase_times copies the accumulated per-phase kernel time (ms) and launch counts of
- * the calling thread (phases: hash_build, frontier, claim, apply, assign, rank, order,
- * other; mphx_phase_name(i) names phase i) and optionally resets them; returns the number
- * of phases.
+ * the calling thread (phases: hash, build, frontier, apply, assign, rank, order, other;
+ * mphx_phase_name(i) names phase i) and optionally resets them; returns the number of
+ * phases.
  * --------------------------------------------------------------------------------------- */
 MPHX_API int mphx_set_option(const char* key, int64_t value);
 MPHX_API int64_t mphx_get_option(const char* key);
 MPHX_API int mphx_phase_times(double* ms, uint64_t* launches, int max_phases, int reset);
 MPHX_API const char* mphx_phase_name(int i);
+
+/* ---------------------------------------------------------------------------------------
+ * Machine-ceiling probes (measurement only; none is on the build path).  The streaming copy
+ * gives the practical HBM ceiling the build's streaming phases are compared against; the
+ * random probes give the throughput of the access patterns that bound the degree build
+ * (non-returning 8-byte atomic add), the peeling rounds (returning 8-byte atomic add), the
+ * assignment (8-byte random loads, 1-byte random stores) and an LDS-resident build (8-byte
+ * LDS atomic add), as a function of the table's footprint.
+ *
+ * mphx_probe_copy: dst[0, bytes) = src[0, bytes); both 16-byte aligned, bytes a multiple
+ *   of 16 (else MPHX_EINVAL).  grid 0 = 8192 blocks of 256 threads.
+ * mphx_probe_random: `count` operations at indices uniform in [0, slots) drawn from the
+ *   SplitMix64 outputs of seed + (i+1)*0x9E3779B97F4A7C15.  The table (dev) holds `slots`
+ *   entries of 8 bytes (1 byte for MPHX_PROBE_STORE1); for MPHX_PROBE_LDS_ATOMIC_ADD each
+ *   workgroup keeps its own LDS table of `slots` <= 8192 entries and writes it to
+ *   table[block_index * slots + j] at the end, so the table holds grid * slots entries.
+ *   The table's contents afterwards are meaningless.  grid 0 = 8192; block a multiple of 64
+ *   up to 1024.  Returns MPHX_EINVAL for a bad argument, MPHX_EDEVICE if the launch failed.
+ * --------------------------------------------------------------------------------------- */
+#define MPHX_PROBE_ATOMIC_ADD 1
+#define MPHX_PROBE_ATOMIC_ADD_RET 2
+#define MPHX_PROBE_LOAD8 3
+#define MPHX_PROBE_STORE1 4
+#define MPHX_PROBE_LDS_ATOMIC_ADD 5
+#define MPHX_PROBE_ATOMIC_ADD32 6   /* 4-byte entries */
+#define MPHX_PROBE_ATOMIC_ADD_WG 7  /* workgroup-scope 8-byte add: atomic only within a workgroup */
+MPHX_API int mphx_probe_copy(const void* src, void* dst, uint64_t bytes, uint32_t grid, void* stream);
+MPHX_API int mphx_probe_random(int op, void* table, uint64_t slots, uint64_t count, uint64_t seed, uint32_t grid,
+                               uint32_t block, void* stream);
 
 #ifdef __cplusplus
 }

@@ -83,6 +83,8 @@ _SIGS = {
     "mphx_server_destroy": (_i32, [_vp]),
     "mphx_phase_times": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_uint64), _i32, _i32]),
     "mphx_phase_name": (C.c_char_p, [_i32]),
+    "mphx_probe_copy": (_i32, [_vp, _vp, _u64, _u32, _vp]),
+    "mphx_probe_random": (_i32, [_i32, _vp, _u64, _u64, _u64, _u32, _u32, _vp]),
 }
 
 _lib = None
@@ -286,6 +288,29 @@ def check_bijection(vals: torch.Tensor) -> int:
     if rc:
         _err(rc)
     return int(bad.value)
+
+
+PROBE_ATOMIC_ADD, PROBE_ATOMIC_ADD_RET, PROBE_LOAD8, PROBE_STORE1, PROBE_LDS_ATOMIC_ADD = 1, 2, 3, 4, 5
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, grid: int = 0):
+    """Streaming copy of src's bytes into dst (the practical HBM ceiling)."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda) or dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("probe_copy needs two device tensors, dst at least as large as src")
+    rc = lib().mphx_probe_copy(_ptr(src), _ptr(dst), nbytes, grid, _stream(src.device))
+    if rc:
+        _err(rc)
+
+
+def probe_random(op: int, table: torch.Tensor, slots: int, count: int, seed: int = 0, grid: int = 0,
+                 block: int = 256):
+    """`count` random operations of kind `op` over `slots` entries of `table` (see mphx.h)."""
+    if not table.is_cuda:
+        raise TypeError("table must be a device tensor")
+    rc = lib().mphx_probe_random(op, _ptr(table), slots, count, seed, grid, block, _stream(table.device))
+    if rc:
+        _err(rc)
 
 
 def gen_keys_u64(n: int, gen_seed: int = 0, start: int = 0, device="cuda") -> torch.Tensor:

@@ -21,13 +21,14 @@ struct Options {
     std::atomic<int> grid{0};          // 0 = automatic
     std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
+    std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
 };
 Options g_opt;
 
 // ---- per-phase timing (HIP events on the caller's stream) ---------------------------------
-enum Phase { PH_HASH, PH_FRONTIER, PH_CLAIM, PH_APPLY, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_COUNT };
-const char* const kPhaseNames[PH_COUNT] = {"hash_build", "frontier", "claim", "apply",
-                                           "assign",     "rank",     "order", "other"};
+enum Phase { PH_HASH, PH_BUILD, PH_FRONTIER, PH_APPLY, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_COUNT };
+const char* const kPhaseNames[PH_COUNT] = {"hash",   "build", "frontier", "apply",
+                                           "assign", "rank",  "order",    "other"};
 
 struct Timers {
     struct Span { int phase; hipEvent_t a, b; };
@@ -159,6 +160,8 @@ struct MphfLayout {
     unsigned long long* lcount;
     uint32_t *edges, *state, *bcount;
     uint3* slots;
+    uint2 *pairs1, *pairs2;  // the partitioned build's buffers, over slots and state
+    void* aux;               // the partitioned build's histograms and scan scratch
     void* scan;
     size_t scan_bytes;
 };
@@ -171,8 +174,14 @@ void layout_mphf(Carve& c, uint64_t n, uint64_t m, MphfLayout& L)
     L.lcount = c.take<unsigned long long>(rcap + 2);
     L.edges = c.take<uint32_t>(3 * n);
     L.rec = c.take<uint64_t>(m);  // also the byte codes after peeling
-    L.slots = c.take<uint3>(n);
-    L.state = c.take<uint32_t>(n);
+    // slots (12n) then state (4n) in one region of 16n bytes, which the partitioned build
+    // uses first as two buffers of n (vertex, edge) pairs
+    uint8_t* region = c.take<uint8_t>(16 * n);
+    L.slots = reinterpret_cast<uint3*>(region);
+    L.state = reinterpret_cast<uint32_t*>(region ? region + 12 * n : nullptr);
+    L.pairs1 = reinterpret_cast<uint2*>(region);
+    L.pairs2 = reinterpret_cast<uint2*>(region ? region + 8 * n : nullptr);
+    L.aux = c.take<uint8_t>(part_build_bytes(n, m / 3, nullptr));
     uint64_t nblocks = (m + 511) / 512;
     L.bcount = c.take<uint32_t>(nblocks);
     L.scan_bytes = scan_scratch_bytes(nblocks);
@@ -270,6 +279,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "timing")) {
         if (value != 0 && value != 1) return fail(MPHX_EINVAL, "timing must be 0 or 1");
         g_opt.timing = (int)value;
+    } else if (!strcmp(key, "part_build")) {
+        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "part_build must be 0 or 1");
+        g_opt.part_build = (int)value;
     } else {
         return fail(MPHX_EINVAL, "unknown option '%s'", key);
     }
@@ -282,6 +294,7 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "grid")) return g_opt.grid;
     if (!strcmp(key, "round_batch")) return g_opt.round_batch;
     if (!strcmp(key, "timing")) return g_opt.timing;
+    if (!strcmp(key, "part_build")) return g_opt.part_build;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
@@ -351,7 +364,7 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
     HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
     {
-        Timed t(PH_HASH, s);
+        Timed t(PH_BUILD, s);
         HIP_TRY(launch_edges_build(edges, n, m, L.rec, L.ctrl, s));
     }
     {
@@ -519,17 +532,25 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     bool done = false;
     for (t = 0; t < max_tries; t++) {
         uint64_t sd = seed + t;
-        HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
-        HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
+        const bool part = g_opt.part_build.load() != 0;
+        if (!part)
+            HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
         HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
         HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
         {
+            // with the partitioned build the hash only writes the edges
             Timed tm(PH_HASH, s);
+            uint64_t* fused = part ? nullptr : L.rec;
             if (k.kind == MPHX_KEYS_U64)
-                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, L.rec, s));
+                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, fused, s));
             else
-                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, L.rec, s));
+                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, fused, s));
         }
+        if (part) {
+            Timed tm(PH_BUILD, s);
+            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, L.ctrl, s));
+        }
+        HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));  // after the build: it shares the pair buffers
         {
             Timed tm(PH_FRONTIER, s);
             HIP_TRY(launch_round0(st, s));

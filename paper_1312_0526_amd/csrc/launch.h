@@ -92,6 +92,15 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
                              uint32_t* scratch_ids, uint32_t* tilehist, void* scan_scratch, size_t scan_bytes,
                              hipStream_t s);
 
+// partitioned record build of a tripartite edge list (part.hip): byte offsets of its
+// histograms, group table and scan scratch inside its auxiliary buffer
+struct PartBuildLayout {
+    size_t hist1_off, hist2_off, ginfo_off, scan_off, scan_bytes;
+};
+size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L);
+hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
+                             uint2* pairs2, void* aux, Ctrl* ctrl, hipStream_t s);
+
 // assignment, ranking, lookup (solve.hip)
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
                                uint8_t* code8, unsigned grid_cap, hipStream_t s);

@@ -286,3 +286,47 @@ def test_mphf_deterministic_across_launch_shapes(mx):
     mx.set_option("round_batch", 8)
     for c, r in outs[1:]:
         assert np.array_equal(c, outs[0][0]) and np.array_equal(r, outs[0][1])
+
+
+@pytest.fixture(params=[1, 0], ids=["partitioned-build", "atomic-build"])
+def build_mode(request, mx):
+    """The two record builds: radix-partitioned with LDS accumulation, and device atomics."""
+    mx.set_option("part_build", request.param)
+    yield request.param
+    mx.set_option("part_build", 1)
+
+
+@pytest.mark.parametrize("n", [12_000_000, 333_333])
+def test_mphf_record_builds_match_oracle(mx, o, build_mode, n):
+    """12e6 keys give P = 4.92e6 vertices per part: two partition groups (2^22 vertices each)
+    and 301 buckets of 2^14 vertices; 333,333 keys give one group and a ragged last bucket."""
+    keys = workloads.u64_keys(n, gen_seed=21)
+    got = mx.mphf_build_u64(dev(keys), seed=3)
+    rc, ref = o.mphf_build_u64(keys, seed=3)
+    assert rc == 0
+    _assert_mphf_equal(got, ref)
+
+
+def test_mphf_record_builds_agree_on_strings(mx):
+    data, offs = workloads.str_keys(700_000, gen_seed=2)
+    outs = []
+    for mode in (1, 0):
+        mx.set_option("part_build", mode)
+        r = mx.mphf_build_str(dev(data), dev(offs), seed=1)
+        outs.append((host(r["codes"], np.uint64), host(r["rank"], np.uint64), r["n_rounds"]))
+    mx.set_option("part_build", 1)
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("copies", [300, (1 << 24) + 1])
+def test_mphf_degree_overflow(mx, o, build_mode, copies):
+    """Equal keys give equal edges: their three vertices reach degree `copies`.  300 exceeds
+    the 255 limit directly; 2^24 + 1 wraps the 24-bit degree field to 1 (and the label sum
+    carries into it), which the total-degree check still catches."""
+    keys = np.full(copies, 0x1234_5678_9ABC_DEF0, dtype=np.uint64)
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_u64(dev(keys), max_tries=2)
+    assert ei.value.status == mx.ERANGE
+    if copies < 1000:
+        assert o.mphf_build_u64(keys, max_tries=2)[0] == oracle.ERANGE
