@@ -72,6 +72,112 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
     return 0.0
 
 
+# Phases, the kernels each is made of, and the sources those kernels are compiled from: HBM
+# counters taken on a kernel are reused only while its sources are unchanged.
+PHASE_KERNELS = {
+    "hash": ("k_hash_str_words", "k_hash_u64_tiles"),
+    "build": ("k_part_",),
+    "frontier": ("k_round0",),
+    "apply": ("k_apply",),
+    "assign": ("k_assign_round",),
+}
+PHASE_SOURCES = {
+    "hash": ("keys.hip",),
+    "build": ("part.hip", "scan.hip"),
+    "frontier": ("peel.hip",),
+    "apply": ("peel.hip",),
+    "assign": ("solve.hip",),
+}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_{workload}.json")
+
+
+def sources_digest(phase: str) -> str:
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1312_0526_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(PHASE_SOURCES[phase] + ("common.h", "launch.h")):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def counters_traffic(workload: str, phase: str):
+    """HBM bytes per launch of a phase from the committed counter summary, or None when there
+    is none or the phase's kernel sources changed since it was taken."""
+    path = COUNTERS_FILE.format(workload=workload.replace("^", ""))
+    if not os.path.exists(path) or phase not in PHASE_SOURCES:
+        return None
+    with open(path) as fh:
+        doc = json.load(fh)
+    row = doc.get("phases", {}).get(phase)
+    if not row or row.get("sources_digest") != sources_digest(phase) or not row.get("launches"):
+        return None
+    return (row["fetch_bytes"] + row["write_bytes"]) / row["launches"]
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
+                       workload: str, command: str) -> int:
+    """Writes profiles/hbm_counters_<workload>.{json,txt} from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE) of one build and two of the ceilings leg (copy calibration)."""
+    import csv
+    import glob
+
+    def per_kernel(d):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
+                name = name.split("(")[0].split("::")[-1].split("<")[0]
+                cur = out.setdefault(name, [0.0, 0])
+                cur[0] += float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
+                cur[1] += 1
+        return out
+
+    fk, wk = per_kernel(fetch_dir), per_kernel(write_dir)
+    cf, cw = per_kernel(copy_fetch_dir), per_kernel(copy_write_dir)
+    copy_bytes = float(4 << 30)  # the ceilings leg copies 4 GiB: reads and writes that much
+    f_scale = copy_bytes / (cf["k_copy"][0] / cf["k_copy"][1])
+    w_scale = copy_bytes / (cw["k_copy"][0] / cw["k_copy"][1])
+    doc = dict(workload=workload, command=command,
+               calibration=dict(kernel="k_copy", bytes=copy_bytes, fetch_per_dispatch=cf["k_copy"][0] / cf["k_copy"][1],
+                                write_per_dispatch=cw["k_copy"][0] / cw["k_copy"][1], fetch_scale=f_scale,
+                                write_scale=w_scale),
+               phases={}, kernels={})
+    for k in sorted(set(fk) | set(wk)):
+        doc["kernels"][k] = dict(dispatches=fk.get(k, [0, 0])[1], fetch_bytes=fk.get(k, [0, 0])[0] * f_scale,
+                                 write_bytes=wk.get(k, [0, 0])[0] * w_scale)
+    for ph, prefixes in PHASE_KERNELS.items():
+        ks = [k for k in doc["kernels"] if any(k.startswith(p) for p in prefixes)]
+        if not ks:
+            continue
+        doc["phases"][ph] = dict(kernels=ks, sources_digest=sources_digest(ph),
+                                 launches=sum(doc["kernels"][k]["dispatches"] for k in ks),
+                                 fetch_bytes=sum(doc["kernels"][k]["fetch_bytes"] for k in ks),
+                                 write_bytes=sum(doc["kernels"][k]["write_bytes"] for k in ks))
+    path = COUNTERS_FILE.format(workload=workload.replace("^", ""))
+    with open(path, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    lines = [f"# HBM traffic counters: {workload}", "", f"command: {command}", "",
+             f"Calibration: the ceilings leg's 4 GiB copy (k_copy) reads FETCH_SIZE = "
+             f"{doc['calibration']['fetch_per_dispatch'] / 2**30:.3f} GiB and WRITE_SIZE = "
+             f"{doc['calibration']['write_per_dispatch'] / 2**30:.3f} GiB per dispatch, so fetch figures are "
+             f"scaled by {f_scale:.3f} and write figures by {w_scale:.3f}.", "",
+             f"{'kernel':28s} {'disp':>5s} {'fetch_GB':>10s} {'write_GB':>10s}"]
+    for k, v in sorted(doc["kernels"].items(), key=lambda kv: -(kv[1]["fetch_bytes"] + kv[1]["write_bytes"])):
+        if v["fetch_bytes"] + v["write_bytes"] < 1e8:
+            continue
+        lines.append(f"{k:28s} {v['dispatches']:5d} {v['fetch_bytes'] / 1e9:10.2f} {v['write_bytes'] / 1e9:10.2f}")
+    lines += ["", "Per phase (the kernels bench.py's phase timers cover), bytes summed over dispatches:", ""]
+    for ph, v in doc["phases"].items():
+        lines.append(f"{ph:10s} launches {v['launches']:4d}  fetch {v['fetch_bytes'] / 1e9:9.2f} GB  "
+                     f"write {v['write_bytes'] / 1e9:9.2f} GB  sources {v['sources_digest']}")
+    with open(path[:-5] + ".txt", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
 def batched_leg(args, mx, torch, np, workloads) -> dict:
     """65,536 independent u64 buckets, sizes floor(100 * 10^(4u)), one captured persistent
     launch per step; beside it the plain path on a sample of the same buckets."""
@@ -127,6 +233,63 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     return out
 
 
+def ceilings_leg(mx, torch) -> dict:
+    """Machine ceilings of the access patterns the build is made of (the library's probe
+    kernels): a streaming copy, random 8-byte atomics / loads and 1-byte stores over a
+    16 GiB table (HBM-sized, far beyond the caches), and LDS-resident 8-byte atomics."""
+    dev = torch.device("cuda:0")
+
+    def best_ms(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            best = min(best, a.elapsed_time(b))
+        return best
+
+    out = {}
+    src = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    ms = best_ms(lambda: mx.probe_copy(src, dst))
+    out["copy_GBps"] = round(2 * src.numel() / ms / 1e6, 1)
+    del src, dst
+    table = torch.zeros(16 << 30, dtype=torch.uint8, device=dev)
+    count = 1 << 30
+    for name, op, esz in (("atomic_add_ret_Gops", mx.PROBE_ATOMIC_ADD_RET, 8), ("atomic_add_Gops", mx.PROBE_ATOMIC_ADD, 8),
+                          ("load8_Gops", mx.PROBE_LOAD8, 8), ("store1_Gops", mx.PROBE_STORE1, 1)):
+        ms = best_ms(lambda: mx.probe_random(op, table, table.numel() // esz, count, seed=op))
+        out[name] = round(count / ms / 1e6, 2)
+    del table
+    lds = torch.empty(4096 * 8192 * 8, dtype=torch.uint8, device=dev)
+    ms = best_ms(lambda: mx.probe_random(mx.PROBE_LDS_ATOMIC_ADD, lds, 8192, 1 << 32, grid=4096, block=1024))
+    out["lds_atomic_add_Gops"] = round((1 << 32) / ms / 1e6, 1)
+    del lds
+    torch.cuda.empty_cache()
+    out["footprint"] = "random ops over a 16 GiB table; copy of 4 GiB; LDS tables of 8192 x 8 B"
+    log(f"[ceilings] {out}")
+    return out
+
+
+def random_ops(phase: str, st: dict) -> dict:
+    """Random device-memory operations per step of a phase (atomics and gathers to arrays far
+    larger than the caches), the count its measured ceiling applies to."""
+    n, F, F0 = st["n"], st["frontier_total"], st["frontier0"]
+    if phase == "apply":
+        # per edge: state and edge-triple gathers, two returning deletes; per vertex taken to
+        # degree 1: one atomicMin claim
+        return dict(atomics=2 * n + (F - F0), loads=2 * n)
+    if phase == "frontier":
+        return dict(atomics=F0, loads=0)
+    if phase == "assign":
+        return dict(atomics=0, loads=2 * n, stores=n)
+    return {}
+
+
 SERVE_WORKLOAD = "mwhc_served_poisson_sizes_loguniform_1e3_1e8_u64_or_str_gamma1.23"
 
 
@@ -153,6 +316,24 @@ def served_leg(args, mx, torch, np, workloads) -> dict:
         return srv.submit_str(data, offs_slices[n], seed=i)
 
     mean_n = float(sizes.mean())
+    # the plain path on the same requests, one build after another on one stream
+    def plain(i):
+        n = int(sizes[i])
+        if kinds[i] == 0:
+            return mx.mphf_build_u64(keys[:n], seed=i)
+        return mx.mphf_build_str(data, offs[: n + 1], seed=i)
+
+    for i in range(min(4, nreq)):
+        plain(i)
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for i in range(nreq):
+        plain(i)
+    torch.cuda.synchronize()
+    plain_span = time.perf_counter() - p0
+    plain_rate = float(sizes.sum()) / plain_span
+    log(f"[served] plain path, same {nreq} requests back to back: {plain_span:.2f} s = "
+        f"{plain_rate / 1e9:.3f} G keys/s")
     # saturation estimate: everything submitted at once
     srv = mx.Server(hbm_budget=args.serve_budget, slots=args.serve_slots)
     warm = [submit(srv, i) for i in range(min(8, nreq))]
@@ -166,6 +347,7 @@ def served_leg(args, mx, torch, np, workloads) -> dict:
         srv.release(t)
     span = max(r["t_done"] for r in res) - t0
     sat_rate = nreq / span
+    sat_edges = float(sizes.sum()) / span
     log(f"[served] saturation: {nreq} builds in {span:.2f} s = {sat_rate:.1f} builds/s, "
         f"{sizes.sum() / span / 1e9:.3f} G keys/s (mean size {mean_n:.0f})")
     rows = []
@@ -196,7 +378,10 @@ def served_leg(args, mx, torch, np, workloads) -> dict:
     torch.cuda.empty_cache()
     return dict(workload=SERVE_WORKLOAD, requests_per_rate=nreq, mean_keys=round(mean_n, 1),
                 slots=args.serve_slots, hbm_budget=args.serve_budget, peak_pool_in_use=st["peak_in_use"],
-                saturation_builds_per_s=round(sat_rate, 2), rates=rows)
+                saturation_builds_per_s=round(sat_rate, 2), saturation_edges_per_s=round(sat_edges, 1),
+                plain_same_requests=dict(value=round(plain_rate, 1), unit="edges/s", requests=nreq,
+                                         note="one mphf_build after another on one stream"),
+                speedup_vs_plain=round(sat_edges / plain_rate, 2), rates=rows)
 
 
 def main() -> int:
@@ -208,7 +393,11 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
     ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="keys in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="plain,batched,served", help="comma list of: plain, batched, served")
+    ap.add_argument("--legs", default="ceilings,plain,batched,served",
+                    help="comma list of: ceilings, plain, batched, served")
+    ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
+    ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
     ap.add_argument("--batch-buckets", type=int, default=65536)
     ap.add_argument("--batch-block", type=int, default=0)
     ap.add_argument("--batch-grid", type=int, default=0)
@@ -219,6 +408,9 @@ def main() -> int:
     ap.add_argument("--serve-budget", type=int, default=64 << 30)
     ap.add_argument("--serve-rates", type=lambda s: [float(x) for x in s.split(",")], default=[0.5, 0.9])
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(*args.summarize_counters, workload=CONFIGS[args.config]["workload"],
+                                  command=args.counters_command)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding "
@@ -236,6 +428,11 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     gamma = (123, 100)
+    legs = set(args.legs.split(","))
+    ceilings = ceilings_leg(mx, torch) if "ceilings" in legs else None
+    if "plain" not in legs:
+        print(json.dumps({"ceilings": ceilings}), flush=True)
+        return 0
 
     # ---- inputs, generated on the device before timing --------------------------------------
     t0 = time.perf_counter()
@@ -298,8 +495,22 @@ def main() -> int:
             f"{b / 1e9:8.2f} GB alg  {gbs:8.1f} GB/s")
     dom = max(phase_rows, key=lambda k: phase_rows[k]["ms"])
     ach = phase_rows[dom]["alg_GBps"]
+    traffic = counters_traffic(cfg["workload"], dom) if n == cfg["n"] else None
     roofline = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None if traffic is None else round(traffic))
+    if traffic is not None:
+        roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roofline["traffic_GBps"] = round(traffic * phase_rows[dom]["launches"] / (phase_rows[dom]["ms"] / 1e3) / 1e9, 1)
+    # the dominant phase against the measured ceiling of the random operations it is made of
+    ops = random_ops(dom, st)
+    if ceilings and ops.get("atomics"):
+        sec = phase_rows[dom]["ms"] / 1e3
+        ach_ops = ops["atomics"] / sec / 1e9
+        roofline["secondary"] = dict(bound="device atomics", achieved=round(ach_ops, 2),
+                                     peak=ceilings["atomic_add_ret_Gops"], unit="G atomics/s",
+                                     frac=round(ach_ops / ceilings["atomic_add_ret_Gops"], 3),
+                                     atomics_per_step=int(ops["atomics"]), gathers_per_step=int(ops["loads"]),
+                                     note="peak = measured returning 8-byte atomic rate over a 16 GiB table")
 
     # ---- oracle on a bounded sample of the same workload ------------------------------------
     cpu = None
@@ -322,7 +533,6 @@ def main() -> int:
                           f"{cs:.1f} s (status {rc})")
         log(f"[bench] oracle: {ns} keys in {cs:.2f} s = {ns / cs / 1e6:.3f} M keys/s")
 
-    legs = set(args.legs.split(","))
     del ws, codes, rank
     if cfg["kind"] == "u64":
         del keys
@@ -350,6 +560,7 @@ def main() -> int:
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "ceilings": ceilings,
         "phases": phase_rows,
         "batched": batched,
         "served": served,

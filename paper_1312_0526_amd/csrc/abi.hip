@@ -541,14 +541,15 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             // with the partitioned build the hash only writes the edges
             Timed tm(PH_HASH, s);
             uint64_t* fused = part ? nullptr : L.rec;
+            const PartHist1 h1 = part ? part_hist1(L.aux, n, P) : PartHist1{nullptr, 0, 0};
             if (k.kind == MPHX_KEYS_U64)
-                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, fused, s));
+                HIP_TRY(launch_hash_u64(k.keys, n, sd, P, L.edges, fused, h1, s));
             else
-                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, fused, s));
+                HIP_TRY(launch_hash_str(k.bytes, k.offs, n, sd, P, L.edges, fused, h1, s));
         }
         if (part) {
             Timed tm(PH_BUILD, s);
-            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, L.ctrl, s));
+            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, L.ctrl, true, s));
         }
         HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));  // after the build: it shares the pair buffers
         {
@@ -656,7 +657,7 @@ int mphx_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, u
     if (n == 0) return MPHX_OK;
     if (!keys || !edges) return fail(MPHX_EINVAL, "null pointer");
     if (P == 0 || 3 * P > 0x100000000ull) return fail(MPHX_EINVAL, "P out of range");
-    HIP_TRY(launch_hash_u64(keys, n, seed, P, edges, nullptr, (hipStream_t)stream));
+    HIP_TRY(launch_hash_u64(keys, n, seed, P, edges, nullptr, PartHist1{nullptr, 0, 0}, (hipStream_t)stream));
     return MPHX_OK;
 }
 
@@ -668,7 +669,7 @@ int mphx_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64
     if (!bytes || !offs || !edges) return fail(MPHX_EINVAL, "null pointer");
     if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
     if (P == 0 || 3 * P > 0x100000000ull) return fail(MPHX_EINVAL, "P out of range");
-    HIP_TRY(launch_hash_str(bytes, offs, n, seed, P, edges, nullptr, (hipStream_t)stream));
+    HIP_TRY(launch_hash_str(bytes, offs, n, seed, P, edges, nullptr, PartHist1{nullptr, 0, 0}, (hipStream_t)stream));
     return MPHX_OK;
 }
 

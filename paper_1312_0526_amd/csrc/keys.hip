@@ -4,6 +4,8 @@
 #include "common.h"
 #include "launch.h"
 
+#include <algorithm>
+
 namespace mphx {
 
 // ---- u64 keys: one thread per key, state a = b = key XOR seed -------------------------------
@@ -51,6 +53,211 @@ __global__ __launch_bounds__(256) void k_hash_str(const uint8_t* __restrict__ by
             Rec::add(rec, v2, (uint32_t)i);
         }
     }
+}
+
+// ---- first-pass partition histograms, counted while hashing ----------------------------------
+// A block that hashes exactly one partition tile counts each part's group digits in LDS and
+// writes its column of the [3][NH][nt1] histogram at the end.
+struct TileHist {
+    uint32_t c[3 * kPartMaxGroups];
+    __device__ void clear()
+    {
+        for (uint32_t j = threadIdx.x; j < 3 * kPartMaxGroups; j += blockDim.x)
+            c[j] = 0;
+    }
+    __device__ void count(uint32_t v0, uint32_t v1, uint32_t v2, uint64_t P)
+    {
+        atomicAdd(&c[v0 >> kPartGrpShift], 1u);
+        atomicAdd(&c[kPartMaxGroups + ((uint32_t)(v1 - P) >> kPartGrpShift)], 1u);
+        atomicAdd(&c[2 * kPartMaxGroups + ((uint32_t)(v2 - 2 * P) >> kPartGrpShift)], 1u);
+    }
+    __device__ void store(const PartHist1& h, uint32_t tile)
+    {
+        for (uint32_t j = threadIdx.x; j < 3 * h.NH; j += blockDim.x) {
+            const uint32_t k = j / h.NH, g = j - k * h.NH;
+            h.hist[((uint64_t)k * h.NH + g) * h.nt1 + tile] = c[k * kPartMaxGroups + g];
+        }
+    }
+};
+
+// ---- u64 keys with the histograms: one block per partition tile ----------------------------
+constexpr uint32_t kHuBlock = 256;
+
+__global__ __launch_bounds__(kHuBlock) void k_hash_u64_tiles(const uint64_t* __restrict__ keys, uint64_t n,
+                                                             uint64_t seed, uint64_t P, uint32_t* __restrict__ edges,
+                                                             PartHist1 h1)
+{
+    __shared__ TileHist th;
+    th.clear();
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * kPartTile;
+    const uint64_t t1 = min<uint64_t>(t0 + kPartTile, n);
+    for (uint64_t i = t0 + threadIdx.x; i < t1; i += kHuBlock) {
+        uint64_t s = keys[i] ^ seed;
+        uint32_t v0, v1, v2;
+        edge_of_digest(s, s, P, v0, v1, v2);
+        edges[3 * i] = v0;
+        edges[3 * i + 1] = v1;
+        edges[3 * i + 2] = v2;
+        th.count(v0, v1, v2, P);
+    }
+    __syncthreads();
+    th.store(h1, blockIdx.x);
+}
+
+// ---- byte-string keys, word-parallel: the edge list alone ------------------------------------
+// Key lengths vary (the generated ones from 8 to 512 bytes, mean 60), so one thread per key
+// leaves most lanes of a wave idle while its longest key finishes.  Here a block takes 256
+// consecutive keys and spreads their 8-byte words over its lanes: word f of the block's flat
+// word list belongs to key owner[f] at word index j, adds its two mixed terms into that key's
+// LDS sums, and the key's thread finishes the digest.  The loads of consecutive words are
+// consecutive in memory; each lane has four words' loads in flight.  Keys longer than 512
+// bytes are digested by their own thread.  With histograms requested, block b hashes exactly
+// partition tile b.
+constexpr uint32_t kHsBlock = 256;
+constexpr uint32_t kHsMaxWords = 64;
+constexpr uint32_t kHsUnroll = 4;
+static_assert(kPartTile % kHsBlock == 0, "a partition tile is whole chunks");
+
+__device__ __forceinline__ uint64_t key_word(const uint8_t* bytes, uint64_t p, uint64_t total)
+{
+    const uint64_t q = p >> 2;
+    const uint32_t sh = (uint32_t)(p & 3) * 8;
+    const uint64_t lo = (uint64_t)load_dword(bytes, q, total) | ((uint64_t)load_dword(bytes, q + 1, total) << 32);
+    if (sh == 0)
+        return lo;
+    return (lo >> sh) | ((uint64_t)load_dword(bytes, q + 2, total) << (64 - sh));
+}
+
+__global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __restrict__ bytes,
+                                                             const uint64_t* __restrict__ offs, uint64_t n,
+                                                             uint64_t seed, uint64_t P, uint32_t* __restrict__ edges,
+                                                             PartHist1 h1)
+{
+    __shared__ uint64_t s_off[kHsBlock];
+    __shared__ uint32_t s_len[kHsBlock], s_wpre[kHsBlock], s_wtot[kHsBlock / kWave];
+    __shared__ unsigned long long s_A[kHsBlock], s_B[kHsBlock];
+    __shared__ uint8_t s_owner[kHsBlock * kHsMaxWords];
+    __shared__ TileHist th;
+    const uint64_t total = offs[n];
+    const uint64_t sa = fin(seed + kGamma);
+    const uint64_t sb = fin(seed + 2 * kGamma);
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const uint64_t nchunks = (n + kHsBlock - 1) / kHsBlock;
+    uint64_t c0 = blockIdx.x, c1 = nchunks, cstep = gridDim.x;
+    if (h1.hist) {
+        c0 = (uint64_t)blockIdx.x * (kPartTile / kHsBlock);
+        c1 = min<uint64_t>(c0 + kPartTile / kHsBlock, nchunks);
+        cstep = 1;
+        th.clear();
+    }
+    for (uint64_t c = c0; c < c1; c += cstep) {
+        const uint64_t i = c * kHsBlock + tid;
+        uint64_t o0 = 0, len = 0;
+        uint32_t nw = 0;
+        bool longkey = false;
+        if (i < n) {
+            o0 = offs[i];
+            len = offs[i + 1] - o0;
+            const uint64_t w = (len + 7) >> 3;
+            longkey = w > kHsMaxWords;
+            nw = longkey ? 0u : (uint32_t)w;
+        }
+        s_off[tid] = o0;
+        s_len[tid] = (uint32_t)(longkey ? 0 : len);
+        s_A[tid] = 0;
+        s_B[tid] = 0;
+        // exclusive prefix of the word counts over the block
+        uint32_t incl = nw;
+        for (uint32_t d = 1; d < kWave; d <<= 1) {
+            uint32_t y = __shfl_up(incl, d, kWave);
+            if (lane >= d)
+                incl += y;
+        }
+        if (lane == kWave - 1)
+            s_wtot[wv] = incl;
+        __syncthreads();
+        uint32_t pre = 0, W = 0;
+        for (uint32_t q = 0; q < kHsBlock / kWave; q++) {
+            pre += q < wv ? s_wtot[q] : 0u;
+            W += s_wtot[q];
+        }
+        pre += incl - nw;
+        s_wpre[tid] = pre;
+        for (uint32_t j = 0; j < nw; j++)
+            s_owner[pre + j] = (uint8_t)tid;
+        __syncthreads();
+        for (uint32_t f0 = tid; f0 < W; f0 += kHsUnroll * kHsBlock) {
+            uint32_t t[kHsUnroll], j[kHsUnroll];
+            uint64_t p[kHsUnroll], w[kHsUnroll];
+            bool fast = true;
+#pragma unroll
+            for (uint32_t u = 0; u < kHsUnroll; u++) {
+                const uint32_t f = f0 + u * kHsBlock;
+                t[u] = 0;
+                j[u] = 0;
+                p[u] = 0;
+                if (f < W) {
+                    t[u] = s_owner[f];
+                    j[u] = f - s_wpre[t[u]];
+                    p[u] = s_off[t[u]] + 8ull * j[u];
+                }
+                fast = fast && ((p[u] >> 2) + 3) * 4 <= total;
+            }
+            if (fast) {  // all three dwords of every word inside the array: plain loads
+                const uint32_t* d = reinterpret_cast<const uint32_t*>(bytes);
+                uint32_t x0[kHsUnroll], x1[kHsUnroll], x2[kHsUnroll];
+#pragma unroll
+                for (uint32_t u = 0; u < kHsUnroll; u++) {
+                    const uint64_t q = p[u] >> 2;
+                    x0[u] = d[q];
+                    x1[u] = d[q + 1];
+                    x2[u] = d[q + 2];
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kHsUnroll; u++) {
+                    const uint32_t sh = (uint32_t)(p[u] & 3) * 8;
+                    const uint64_t lo = (uint64_t)x0[u] | ((uint64_t)x1[u] << 32);
+                    w[u] = sh ? ((lo >> sh) | ((uint64_t)x2[u] << (64 - sh))) : lo;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t u = 0; u < kHsUnroll; u++)
+                    w[u] = f0 + u * kHsBlock < W ? key_word(bytes, p[u], total) : 0ull;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kHsUnroll; u++) {
+                if (f0 + u * kHsBlock < W) {
+                    const uint32_t rem = s_len[t[u]] - 8 * j[u];
+                    uint64_t x = w[u];
+                    if (rem < 8)
+                        x &= (1ull << (8 * rem)) - 1;
+                    atomicAdd(&s_A[t[u]], (unsigned long long)fin(x ^ (sa + j[u] * kGamma)));
+                    atomicAdd(&s_B[t[u]], (unsigned long long)fin(x ^ (sb + j[u] * kGamma)));
+                }
+            }
+        }
+        __syncthreads();
+        if (i < n) {
+            uint64_t a, b;
+            if (longkey) {
+                digest_str(bytes, o0, len, total, sa, sb, a, b);
+            } else {
+                a = fin(s_A[tid] ^ sa ^ len);
+                b = fin(s_B[tid] ^ sb ^ len);
+            }
+            uint32_t v0, v1, v2;
+            edge_of_digest(a, b, P, v0, v1, v2);
+            edges[3 * i] = v0;
+            edges[3 * i + 1] = v1;
+            edges[3 * i + 2] = v2;
+            if (h1.hist)
+                th.count(v0, v1, v2, P);
+        }
+        __syncthreads();  // the LDS arrays are reused by the next chunk
+    }
+    if (h1.hist)
+        th.store(h1, blockIdx.x);
 }
 
 // ---- synthetic key generators ------------------------------------------------------------
@@ -143,9 +350,13 @@ static inline unsigned grid_cap(uint64_t count, unsigned cap)
 }
 
 hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
-                           uint64_t* rec, hipStream_t s)
+                           uint64_t* rec, PartHist1 h1, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    if (!rec && h1.hist) {
+        k_hash_u64_tiles<<<(unsigned)h1.nt1, kHuBlock, 0, s>>>(keys, n, seed, P, edges, h1);
+        return hipGetLastError();
+    }
     unsigned g = grid_cap(n, 16384);
     if (!rec)
         k_hash_u64<false><<<g, 256, 0, s>>>(keys, n, seed, P, edges, rec);
@@ -155,14 +366,17 @@ hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint
 }
 
 hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
-                           uint32_t* edges, uint64_t* rec, hipStream_t s)
+                           uint32_t* edges, uint64_t* rec, PartHist1 h1, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    if (!rec) {
+        const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
+        const unsigned g = h1.hist ? (unsigned)h1.nt1 : (unsigned)std::min<uint64_t>(chunks, 65536);
+        k_hash_str_words<<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, edges, h1);
+        return hipGetLastError();
+    }
     unsigned g = grid_cap(n, 16384);
-    if (!rec)
-        k_hash_str<false><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec);
-    else
-        k_hash_str<true><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec);
+    k_hash_str<true><<<g, 256, 0, s>>>(bytes, offs, n, seed, P, edges, rec);
     return hipGetLastError();
 }
 

@@ -68,11 +68,35 @@ hipError_t launch_scan_u32(const uint32_t* in, uint64_t count, uint32_t* out, vo
 hipError_t launch_scan_u32_to_u64(const uint32_t* in, uint64_t count_in, uint64_t* out, uint64_t count_out,
                                   void* scratch, size_t scratch_bytes, hipStream_t s);
 
+// partitioned record build of a tripartite edge list (part.hip).  First-pass tiles are
+// kPartTile consecutive edges; the first-pass digit of part k's vertex v is
+// (v - kP) >> kPartGrpShift.  The key-hashing kernels can count those digits per tile while
+// they write the edges (PartHist1), which saves the build its own pass over the edges.
+constexpr uint32_t kPartTile = 8192;
+constexpr uint32_t kPartGrpShift = 22;
+constexpr uint32_t kPartMaxGroups = 512;
+
+struct PartHist1 {
+    uint32_t* hist;  // [3][NH][nt1] counts, or nullptr
+    uint32_t NH;
+    uint64_t nt1;
+};
+
+struct PartBuildLayout {
+    size_t hist1_off, hist2_off, ginfo_off, scan_off, scan_bytes;
+};
+size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L);
+PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P);
+// hist1_done: the hashing kernel already filled the first-pass histograms
+hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
+                             uint2* pairs2, void* aux, Ctrl* ctrl, bool hist1_done, hipStream_t s);
+
 // hashing and key generation (keys.hip); rec == nullptr hashes only
+// h1.hist != nullptr (with rec == nullptr): also count the first-pass partition digits
 hipError_t launch_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
-                           uint64_t* rec, hipStream_t s);
+                           uint64_t* rec, PartHist1 h1, hipStream_t s);
 hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t P,
-                           uint32_t* edges, uint64_t* rec, hipStream_t s);
+                           uint32_t* edges, uint64_t* rec, PartHist1 h1, hipStream_t s);
 hipError_t launch_gen_u64(uint64_t* keys, uint64_t n, uint64_t gen_seed, uint64_t start, hipStream_t s);
 hipError_t launch_gen_buckets_u64(uint64_t* keys, const uint64_t* off, uint32_t B, hipStream_t s);
 hipError_t launch_gen_str_lengths(uint32_t* lens, uint64_t n, uint64_t gen_seed, uint64_t start,
@@ -91,15 +115,6 @@ uint64_t sort_tiles(uint64_t n);
 hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds, uint32_t* order,
                              uint32_t* scratch_ids, uint32_t* tilehist, void* scan_scratch, size_t scan_bytes,
                              hipStream_t s);
-
-// partitioned record build of a tripartite edge list (part.hip): byte offsets of its
-// histograms, group table and scan scratch inside its auxiliary buffer
-struct PartBuildLayout {
-    size_t hist1_off, hist2_off, ginfo_off, scan_off, scan_bytes;
-};
-size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L);
-hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
-                             uint2* pairs2, void* aux, Ctrl* ctrl, hipStream_t s);
 
 // assignment, ranking, lookup (solve.hip)
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,

@@ -24,15 +24,18 @@ namespace {
 
 constexpr uint32_t kBkShift = 14;
 constexpr uint32_t kBkSize = 1u << kBkShift;
-constexpr uint32_t kGrpShift = 22;
-constexpr uint32_t kMaxGroups = 512;
+constexpr uint32_t kGrpShift = kPartGrpShift;
+constexpr uint32_t kMaxGroups = kPartMaxGroups;
 constexpr uint32_t kDigits = 256;
-constexpr uint32_t kPtBlock = 1024;
+constexpr uint32_t kPtBlock = 512;  // two blocks per CU: one loads while the other writes
 constexpr uint32_t kPtPer = 16;
 constexpr uint32_t kPtTile = kPtBlock * kPtPer;
 constexpr uint32_t kWaves = kPtBlock / kWave;
+constexpr uint32_t kAccBlock = 1024;
 
 static_assert((kBkShift + 8) == kGrpShift, "a group holds 256 buckets");
+static_assert(kPtTile == kPartTile, "first-pass tiles are the hashing kernels' tiles");
+static_assert(kPtBlock > 342 && kPtBlock >= kDigits, "one thread per group and per digit");
 
 // Exclusive prefix over the block (one value per thread); wtot is kWaves words of LDS.
 __device__ uint32_t block_exclusive(uint32_t x, uint32_t* wtot)
@@ -267,19 +270,19 @@ __device__ __forceinline__ uint64_t bucket_start(const GroupInfo& g, const uint3
 }
 
 // ---- per-bucket accumulation of part k's records in LDS ---------------------------------------
-__global__ __launch_bounds__(kPtBlock) void k_part_accum(const uint2* __restrict__ in, const uint32_t* __restrict__ ginfo,
+__global__ __launch_bounds__(kAccBlock) void k_part_accum(const uint2* __restrict__ in, const uint32_t* __restrict__ ginfo,
                                                          uint32_t NH, const uint32_t* __restrict__ off2, uint64_t n,
                                                          uint32_t k, uint64_t P, uint64_t* __restrict__ rec)
 {
     __shared__ unsigned long long lrec[kBkSize];
     const GroupInfo g(ginfo);
     const uint32_t b = blockIdx.x;
-    for (uint32_t j = threadIdx.x; j < kBkSize; j += kPtBlock)
+    for (uint32_t j = threadIdx.x; j < kBkSize; j += kAccBlock)
         lrec[j] = 0;
     const uint64_t lo = bucket_start(g, off2, NH, n, b);
     const uint64_t hi = bucket_start(g, off2, NH, n, b + 1);
     __syncthreads();
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kPtBlock) {
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kAccBlock) {
         const uint2 p = in[i];
         atomicAdd(&lrec[p.x & (kBkSize - 1)], (unsigned long long)(Rec::kOne + p.y));
     }
@@ -287,7 +290,7 @@ __global__ __launch_bounds__(kPtBlock) void k_part_accum(const uint2* __restrict
     const uint64_t v0 = (uint64_t)b * kBkSize;
     const uint32_t cnt = (uint32_t)min<uint64_t>(kBkSize, P - v0);
     uint64_t* dst = rec + (uint64_t)k * P + v0;
-    for (uint32_t j = threadIdx.x; j < cnt; j += kPtBlock)
+    for (uint32_t j = threadIdx.x; j < cnt; j += kAccBlock)
         dst[j] = lrec[j];
 }
 
@@ -320,8 +323,16 @@ size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L)
     return off;
 }
 
+PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P)
+{
+    PartBuildLayout L;
+    part_build_bytes(n, P, &L);
+    return PartHist1{reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(aux) + L.hist1_off), part_groups(P),
+                     part_tiles(n)};
+}
+
 hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
-                             uint2* pairs2, void* aux, Ctrl* ctrl, hipStream_t s)
+                             uint2* pairs2, void* aux, Ctrl* ctrl, bool hist1_done, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     PartBuildLayout L;
@@ -334,7 +345,8 @@ hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint
     const uint32_t NH = part_groups(P);
     const uint64_t nt1 = part_tiles(n), nt2 = nt1 + NH, nb = (P + kBkSize - 1) / kBkSize;
     if (NH > kMaxGroups || nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
-    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(edges, n, P, NH, nt1, hist1, ctrl);
+    if (!hist1_done)
+        k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(edges, n, P, NH, nt1, hist1, ctrl);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     for (uint32_t k = 0; k < 3; k++) {
@@ -349,7 +361,7 @@ hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint
         err = launch_scan_u32(hist2, nt2 * kDigits, hist2, scan, L.scan_bytes, s);
         if (err != hipSuccess) return err;
         k_part_scatter2<<<(unsigned)nt2, kPtBlock, 0, s>>>(pairs1, ginfo, NH, hist2, pairs2);
-        k_part_accum<<<(unsigned)nb, kPtBlock, 0, s>>>(pairs2, ginfo, NH, hist2, n, k, P, rec);
+        k_part_accum<<<(unsigned)nb, kAccBlock, 0, s>>>(pairs2, ginfo, NH, hist2, n, k, P, rec);
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }

@@ -78,6 +78,9 @@ def _str_cases():
     keys = [b"", b"a", b"ab", b"abc", b"abcd", b"abcdefg", b"abcdefgh", b"abcdefghi", bytes(range(256)),
             b"\x00" * 9, b"x" * 512]
     keys += [bytes(rng.integers(0, 256, size=int(l), dtype=np.uint8)) for l in rng.integers(0, 40, size=300)]
+    # longer than 512 bytes (digested by their own thread), between short keys of the same block
+    for pos, l in ((20, 513), (150, 1000), (400, 4099), (401, 520)):
+        keys.insert(pos, bytes(rng.integers(0, 256, size=l, dtype=np.uint8)))
     data = np.frombuffer(b"".join(keys), np.uint8).copy()
     offs = np.zeros(len(keys) + 1, np.uint64)
     offs[1:] = np.cumsum([len(k) for k in keys])
@@ -86,7 +89,7 @@ def _str_cases():
 
 @pytest.mark.parametrize("seed", [0, 1, 0x123456789ABCDEF])
 def test_hash_str_edge_cases(mx, o, seed):
-    data, offs = _str_cases()  # every alignment of start and end, empty keys, 512-byte keys
+    data, offs = _str_cases()  # every alignment of start and end, empty keys, 512-byte and longer keys
     P = 1000003
     got = host(mx.hash_str(dev(data), dev(offs), seed, P), np.uint32).reshape(-1, 3)
     assert np.array_equal(got, o.hash_str(data, offs, seed, P))
