@@ -147,12 +147,15 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
     for k in sorted(set(fk) | set(wk)):
         doc["kernels"][k] = dict(dispatches=fk.get(k, [0, 0])[1], fetch_bytes=fk.get(k, [0, 0])[0] * f_scale,
                                  write_bytes=wk.get(k, [0, 0])[0] * w_scale)
+    # the library times hash, build and frontier as one span per build, the rounds per launch
+    builds = doc["kernels"].get("k_round0", {}).get("dispatches", 1)
     for ph, prefixes in PHASE_KERNELS.items():
         ks = [k for k in doc["kernels"] if any(k.startswith(p) for p in prefixes)]
         if not ks:
             continue
+        per_launch = ph in ("apply", "assign")
         doc["phases"][ph] = dict(kernels=ks, sources_digest=sources_digest(ph),
-                                 launches=sum(doc["kernels"][k]["dispatches"] for k in ks),
+                                 launches=sum(doc["kernels"][k]["dispatches"] for k in ks) if per_launch else builds,
                                  fetch_bytes=sum(doc["kernels"][k]["fetch_bytes"] for k in ks),
                                  write_bytes=sum(doc["kernels"][k]["write_bytes"] for k in ks))
     path = COUNTERS_FILE.format(workload=workload.replace("^", ""))
@@ -173,6 +176,24 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
         lines.append(f"{ph:10s} launches {v['launches']:4d}  fetch {v['fetch_bytes'] / 1e9:9.2f} GB  "
                      f"write {v['write_bytes'] / 1e9:9.2f} GB  sources {v['sources_digest']}")
     with open(path[:-5] + ".txt", "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
+def summarize_kernel_stats(csv_path: str, out_path: str, title: str, command: str) -> int:
+    """Writes a text table of a rocprofv3 --stats kernel_stats.csv."""
+    import csv
+
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [f"# {title}", "", f"command: {command}", "",
+             f"{'kernel':36s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>11s} {'pct':>6s}"]
+    for r in rows:
+        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
+        name = name.split("::")[-1][:36]
+        lines.append(f"{name:36s} {r['Calls']:>6s} {int(r['TotalDurationNs']) / 1e6:10.3f} "
+                     f"{float(r['AverageNs']) / 1e3:11.2f} {float(r['Percentage']):6.2f}")
+    with open(out_path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
     return 0
@@ -398,6 +419,8 @@ def main() -> int:
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
+    ap.add_argument("--summarize-kernel-stats", nargs=3, metavar=("STATS_CSV", "OUT_TXT", "TITLE"),
+                    help="write a text table of a rocprofv3 kernel_stats.csv (command from --counters-command)")
     ap.add_argument("--batch-buckets", type=int, default=65536)
     ap.add_argument("--batch-block", type=int, default=0)
     ap.add_argument("--batch-grid", type=int, default=0)
@@ -408,6 +431,8 @@ def main() -> int:
     ap.add_argument("--serve-budget", type=int, default=64 << 30)
     ap.add_argument("--serve-rates", type=lambda s: [float(x) for x in s.split(",")], default=[0.5, 0.9])
     args = ap.parse_args()
+    if args.summarize_kernel_stats:
+        return summarize_kernel_stats(*args.summarize_kernel_stats, command=args.counters_command)
     if args.summarize_counters:
         return summarize_counters(*args.summarize_counters, workload=CONFIGS[args.config]["workload"],
                                   command=args.counters_command)
