@@ -55,14 +55,20 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
     if phase == "build":
         # every edge read once, every 8 B vertex record written once
         return 12 * n + 8 * m
+    lists = st.get("lists", False)
     if phase == "frontier":
         # round 0: every record read; per degree-1 vertex an edge-state RMW (8 B) and at most
-        # one 4 B layer append
-        return 8 * m + 12 * F0
+        # one 4 B layer append; with claim lists an 8 B claim written and read back
+        return 8 * m + (16 if lists else 12) * F0
     if phase == "apply":
-        # per edge: slot read 4 + state read 4 + edge read 12 + slot write 12, two record RMW
-        # (16 B each); per vertex taken to degree 1: edge-state RMW 8 + at most one 4 B append
-        return 64 * n + 12 * (F - F0)
+        # per edge: slot read 8 (edge + hinge, or edge + state read) + edge read 12 + slot
+        # write 12, two record RMW (16 B each); per vertex taken to degree 1: an edge-state
+        # RMW 8 + at most one 4 B append, or one 8 B claim written
+        return 64 * n + (8 if lists else 12) * (F - F0)
+    if phase == "resolve":
+        # claims of rounds 1.. read back (8 B each); per layer edge its state (4 B) and layer
+        # entry (8 B) written
+        return 8 * (F - F0) + 12 * n
     if phase == "assign":
         # 12 B slot read + two code reads + one code write (1 B each)
         return 15 * n
@@ -76,16 +82,18 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
 # counters taken on a kernel are reused only while its sources are unchanged.
 PHASE_KERNELS = {
     "hash": ("k_hash_str_words", "k_hash_u64_tiles"),
-    "build": ("k_part_",),
+    "build": ("k_part_accum",),
     "frontier": ("k_round0",),
     "apply": ("k_apply",),
+    "resolve": ("k_claims_resolve",),
     "assign": ("k_assign_round",),
 }
 PHASE_SOURCES = {
     "hash": ("keys.hip",),
     "build": ("part.hip", "scan.hip"),
-    "frontier": ("peel.hip",),
+    "frontier": ("peel.hip", "part.hip", "scan.hip"),
     "apply": ("peel.hip",),
+    "resolve": ("part.hip", "scan.hip"),
     "assign": ("solve.hip",),
 }
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_{workload}.json")
@@ -300,12 +308,15 @@ def random_ops(phase: str, st: dict) -> dict:
     """Random device-memory operations per step of a phase (atomics and gathers to arrays far
     larger than the caches), the count its measured ceiling applies to."""
     n, F, F0 = st["n"], st["frontier_total"], st["frontier0"]
+    lists = st.get("lists", False)
     if phase == "apply":
-        # per edge: state and edge-triple gathers, two returning deletes; per vertex taken to
-        # degree 1: one atomicMin claim
+        # per edge: edge-triple gather (and the state, without claim lists), two returning
+        # deletes; per vertex taken to degree 1: one atomicMin claim without claim lists
+        if lists:
+            return dict(atomics=2 * n, loads=n)
         return dict(atomics=2 * n + (F - F0), loads=2 * n)
     if phase == "frontier":
-        return dict(atomics=F0, loads=0)
+        return dict(atomics=0 if lists else F0, loads=0)
     if phase == "assign":
         return dict(atomics=0, loads=2 * n, stores=n)
     return {}
@@ -419,6 +430,8 @@ def main() -> int:
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="library option to set before timing (mphx_set_option), e.g. claim_lists=0")
     ap.add_argument("--summarize-kernel-stats", nargs=3, metavar=("STATS_CSV", "OUT_TXT", "TITLE"),
                     help="write a text table of a rocprofv3 kernel_stats.csv (command from --counters-command)")
     ap.add_argument("--batch-buckets", type=int, default=65536)
@@ -454,6 +467,11 @@ def main() -> int:
     torch.cuda.set_device(dev)
     gamma = (123, 100)
     legs = set(args.legs.split(","))
+    options = {}
+    for kv in args.set:
+        key, value = kv.split("=", 1)
+        mx.set_option(key, int(value))
+        options[key] = int(value)
     ceilings = ceilings_leg(mx, torch) if "ceilings" in legs else None
     if "plain" not in legs:
         print(json.dumps({"ceilings": ceilings}), flush=True)
@@ -505,8 +523,9 @@ def main() -> int:
     phases = mx.phase_times(reset=True)
     log(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value / 1e9:.3f} G keys/s")
 
+    lists_from = mx.get_option("claim_lists")
     st = dict(n=n, m=m, kind=cfg["kind"], key_bytes=key_bytes, frontier_total=r["frontier_total"],
-              frontier0=r["frontier0"], claims=r["claims"])
+              frontier0=r["frontier0"], claims=r["claims"], lists=lists_from > 0 and n >= (1 << lists_from))
     phase_rows = {}
     for name, (ms, launches) in phases.items():
         if launches == 0:
@@ -582,7 +601,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": cfg["workload"], "n": n, "gamma": "123/100", "m": m,
                    "key_bytes": key_bytes, "rounds": r["n_rounds"], "tries": r["tries"],
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", **({"options": options} if options else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ceilings": ceilings,

@@ -22,12 +22,20 @@ struct Options {
     std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
     std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
+    std::atomic<int> claim_lists{28};  // claim lists from n >= 2^claim_lists keys on (0 = never)
 };
+
 Options g_opt;
 
+bool use_claim_lists(uint64_t n)
+{
+    const int b = g_opt.claim_lists.load();
+    return b > 0 && n >= (1ull << b);
+}
+
 // ---- per-phase timing (HIP events on the caller's stream) ---------------------------------
-enum Phase { PH_HASH, PH_BUILD, PH_FRONTIER, PH_APPLY, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_COUNT };
-const char* const kPhaseNames[PH_COUNT] = {"hash",   "build", "frontier", "apply",
+enum Phase { PH_HASH, PH_BUILD, PH_FRONTIER, PH_APPLY, PH_RESOLVE, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_COUNT };
+const char* const kPhaseNames[PH_COUNT] = {"hash",   "build", "frontier", "apply", "resolve",
                                            "assign", "rank",  "order",    "other"};
 
 struct Timers {
@@ -161,12 +169,14 @@ struct MphfLayout {
     uint32_t *edges, *state, *bcount;
     uint3* slots;
     uint2 *pairs1, *pairs2;  // the partitioned build's buffers, over slots and state
-    void* aux;               // the partitioned build's histograms and scan scratch
+    void* aux;               // histograms and scan scratch of the partitions
+    uint2 *claims, *claims_tmp;  // claim lists (m each), when used
+    unsigned long long* ccount;  // claim counts per round
     void* scan;
     size_t scan_bytes;
 };
 
-void layout_mphf(Carve& c, uint64_t n, uint64_t m, MphfLayout& L)
+void layout_mphf(Carve& c, uint64_t n, uint64_t m, bool lists, MphfLayout& L)
 {
     uint64_t rcap = round_cap(n);
     L.ctrl = c.take<Ctrl>(1);
@@ -181,7 +191,10 @@ void layout_mphf(Carve& c, uint64_t n, uint64_t m, MphfLayout& L)
     L.state = reinterpret_cast<uint32_t*>(region ? region + 12 * n : nullptr);
     L.pairs1 = reinterpret_cast<uint2*>(region);
     L.pairs2 = reinterpret_cast<uint2*>(region ? region + 8 * n : nullptr);
-    L.aux = c.take<uint8_t>(part_build_bytes(n, m / 3, nullptr));
+    L.aux = c.take<uint8_t>(part_aux_bytes(n, m / 3, lists));
+    L.ccount = c.take<unsigned long long>(rcap + 2);
+    L.claims = lists ? c.take<uint2>(m) : nullptr;
+    L.claims_tmp = lists ? c.take<uint2>(m) : nullptr;
     uint64_t nblocks = (m + 511) / 512;
     L.bcount = c.take<uint32_t>(nblocks);
     L.scan_bytes = scan_scratch_bytes(nblocks);
@@ -221,7 +234,7 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
         st.grid_cap = auto_grid(next_layer);
         for (; r < upto; r++) {
             Timed t(PH_APPLY, s);
-            HIP_TRY(launch_apply(st, r, s));
+            HIP_TRY(launch_apply(st, r, false, false, s));
         }
         HIP_TRY(hipMemcpyAsync(&next_layer, st.lcount + r, sizeof next_layer, hipMemcpyDeviceToHost, s));
         int rc = read_ctrl(st.ctrl, h, s);
@@ -237,6 +250,47 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
             return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
         batch = std::min<uint32_t>(batch * 2, 64);
     }
+}
+
+// Claim-list rounds.  Layer 0 comes from round 0's atomic claims, which keep it in vertex
+// order (its hinges ascending, which the assignment's code writes profit from) and leave the
+// hinge in the edge state.  Every apply appends the next layer's claims and cancels to the
+// list, which is resolved into the next layer (the hinge lands in the slot).  One host read
+// per round sizes the resolve.  A round whose list resolves to nothing ends the peel.
+constexpr int kListOverflow = 1000;  // internal: a round's records exceeded the claim list
+
+int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
+{
+    for (uint32_t r = 0;; r++) {
+        if (r > st.rcap)
+            return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
+        unsigned long long est = 0;
+        if (r > 0) {
+            HIP_TRY(hipMemcpyAsync(&est, st.ccount + r, sizeof est, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (est > st.m)
+                return kListOverflow;  // the list holds m records; no layer of a large random graph comes near
+            Timed t(PH_RESOLVE, s);
+            HIP_TRY(launch_claims_resolve(st, r, est, s));
+        } else {
+            HIP_TRY(hipMemcpyAsync(&est, st.lcount, sizeof est, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        st.grid_cap = auto_grid(est);  // the records bound the layer
+        {
+            Timed t(PH_APPLY, s);
+            HIP_TRY(launch_apply(st, r, r > 0, true, s));
+        }
+        if (est == 0)
+            break;
+    }
+    int rc = read_ctrl(st.ctrl, h, s);
+    if (rc) return rc;
+    uint64_t p = 0;
+    HIP_TRY(hipMemcpyAsync(&p, st.lstart + h.nrounds, sizeof p, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *peeled = p;
+    return MPHX_OK;
 }
 
 int check_build_errors(Ctrl* dctrl, uint64_t n, hipStream_t s, uint64_t& first_front)
@@ -282,6 +336,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "part_build")) {
         if (value != 0 && value != 1) return fail(MPHX_EINVAL, "part_build must be 0 or 1");
         g_opt.part_build = (int)value;
+    } else if (!strcmp(key, "claim_lists")) {
+        if (value < 0 || value > 32) return fail(MPHX_EINVAL, "claim_lists must be in 0..32");
+        g_opt.claim_lists = (int)value;
     } else {
         return fail(MPHX_EINVAL, "unknown option '%s'", key);
     }
@@ -295,6 +352,7 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "round_batch")) return g_opt.round_batch;
     if (!strcmp(key, "timing")) return g_opt.timing;
     if (!strcmp(key, "part_build")) return g_opt.part_build;
+    if (!strcmp(key, "claim_lists")) return g_opt.claim_lists;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
@@ -403,7 +461,7 @@ size_t mphx_mphf_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_
     uint64_t m = 3 * mphx_part_size(n, gamma_num, gamma_den);
     Carve c(nullptr);
     MphfLayout L;
-    layout_mphf(c, n, m, L);
+    layout_mphf(c, n, m, use_claim_lists(n), L);
     return c.off;
 }
 
@@ -448,17 +506,21 @@ int keys_equal(const KeySrc& k, uint64_t a, uint64_t b, bool& eq, hipStream_t s)
 }
 
 // After the last failed try: do identical core edges come from equal keys?
-int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, bool& dup, hipStream_t s)
+int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, uint64_t m, bool& dup, hipStream_t s)
 {
+    // An edge is in the 2-core exactly when all three of its vertices still have degree >= 2:
+    // a peeled edge keeps its hinge at degree 1 (deletes skip the hinge), and a core vertex
+    // has lost every peeled edge and kept at least two core edges.
     dup = false;
-    std::vector<uint32_t> state(n);
+    std::vector<uint64_t> rec(m);
     std::vector<uint32_t> edges(3 * n);
-    HIP_TRY(hipMemcpyAsync(state.data(), L.state, state.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rec.data(), L.rec, rec.size() * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(edges.data(), L.edges, edges.size() * 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    auto deg = [&rec](uint32_t v) { return (uint32_t)(rec[v] >> 40); };
     std::vector<uint32_t> core;
     for (uint64_t e = 0; e < n; e++)
-        if (state[e] == kUnclaimed)
+        if (deg(edges[3 * e]) >= 2 && deg(edges[3 * e + 1]) >= 2 && deg(edges[3 * e + 2]) >= 2)
             core.push_back((uint32_t)e);
     std::sort(core.begin(), core.end(), [&](uint32_t a, uint32_t b) {
         for (int q = 0; q < 3; q++)
@@ -495,6 +557,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         if (!codes || !rank) return fail(MPHX_EINVAL, "null output");
     }
     if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    const bool lists = use_claim_lists(n);
     size_t need = mphx_mphf_workspace_bytes(n, gnum, gden, k.kind);
     if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
     if (info) {
@@ -510,7 +573,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
 
     Carve c(ws);
     MphfLayout L;
-    layout_mphf(c, n, m, L);
+    layout_mphf(c, n, m, lists, L);
 
     PeelState st{};
     st.edges = L.edges;
@@ -525,6 +588,11 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     st.lcount = L.lcount;
     st.ctrl = L.ctrl;
     st.rcap = round_cap(n);
+    st.lists = lists;
+    st.claims = L.claims;
+    st.claims_tmp = L.claims_tmp;
+    st.ccount = L.ccount;
+    st.aux = L.aux;
 
     Ctrl h{};
     uint64_t peeled = 0;
@@ -536,6 +604,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         if (!part)
             HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
         HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
+        HIP_TRY(launch_zero(L.ccount, (st.rcap + 2) * sizeof(unsigned long long), s));
         HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
         {
             // with the partitioned build the hash only writes the edges
@@ -549,7 +618,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         }
         if (part) {
             Timed tm(PH_BUILD, s);
-            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, L.ctrl, true, s));
+            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, s));
         }
         HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));  // after the build: it shares the pair buffers
         {
@@ -562,7 +631,12 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             if (info) { info->tries = t + 1; info->seed_used = sd; }
             return rc;
         }
-        rc = run_rounds(st, h, &peeled, s);
+        rc = st.lists ? run_rounds_lists(st, h, &peeled, s) : run_rounds(st, h, &peeled, s);
+        if (rc == kListOverflow) {  // redo this try with atomic claims
+            st.lists = false;
+            t--;
+            continue;
+        }
         if (rc) return rc;
         if (info) {
             info->tries = t + 1;
@@ -580,7 +654,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     }
     if (!done) {
         bool dup = false;
-        int rc = detect_duplicates(k, L, n, dup, s);
+        int rc = detect_duplicates(k, L, n, m, dup, s);
         if (rc) return rc;
         if (dup) return fail(MPHX_EDUP, "duplicate keys: identical edges from equal keys stay in the 2-core");
         return fail(MPHX_ECORE, "2-core of %llu edges after %u tries", (unsigned long long)(n - peeled), max_tries);

@@ -22,6 +22,14 @@ struct PeelState {
     unsigned long long* lcount;  // rcap + 2 layer sizes (append cursors), zeroed per run
     Ctrl* ctrl;
     uint64_t rcap;          // rounds the start arrays can hold
+    // Claim lists (tripartite only): instead of claiming an edge for the next round with a
+    // device atomic, a vertex reaching degree 1 appends (edge, position); the list is then
+    // partitioned by edge and resolved in LDS into the next layer.
+    bool lists;
+    uint2* claims;          // m (edge, position) claims of one round
+    uint2* claims_tmp;      // m, the partition's other buffer
+    unsigned long long* ccount;  // rcap + 2 claim counts: ccount[r] = claims that form layer r
+    void* aux;              // partition histograms and scan scratch (part_aux_bytes)
 };
 
 // One bucket of a batched launch: its keys (u64, or string bytes + offsets), its seed and
@@ -82,14 +90,18 @@ struct PartHist1 {
     uint64_t nt1;
 };
 
-struct PartBuildLayout {
-    size_t hist1_off, hist2_off, ginfo_off, scan_off, scan_bytes;
-};
-size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L);
+// Auxiliary buffer of the partition passes: sized for the record build of n edges with part
+// size P and, with claim lists, for resolving up to m = 3P claims.
+size_t part_aux_bytes(uint64_t n, uint64_t P, bool lists);
 PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P);
-// hist1_done: the hashing kernel already filled the first-pass histograms
+// the hashing kernel has filled the first-pass histograms (part_hist1)
 hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
-                             uint2* pairs2, void* aux, Ctrl* ctrl, bool hist1_done, hipStream_t s);
+                             uint2* pairs2, void* aux, hipStream_t s);
+// Layer r from the count claims in st.claims (ccount[r] of them, known to the host): the
+// claims are partitioned by edge, stale ones (edge already in a layer) dropped, each edge's
+// lowest claimed position kept as its hinge; winners set state and fill layer r's slots
+// (edge, hinge) through lcount[r].
+hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s);
 
 // hashing and key generation (keys.hip); rec == nullptr hashes only
 // h1.hist != nullptr (with rec == nullptr): also count the first-pass partition digits
@@ -108,7 +120,9 @@ hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
 hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl,
                               hipStream_t s);
 hipError_t launch_round0(const PeelState& st, hipStream_t s);
-hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s);
+// hinge_in_slot: layer r came from a resolved claim list; list_claims: append the next
+// layer's claims to st.claims (tripartite only) instead of claiming with atomics
+hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, bool list_claims, hipStream_t s);
 hipError_t launch_peel_finalize(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask,
                                 uint8_t* hinge, hipStream_t s);
 uint64_t sort_tiles(uint64_t n);

@@ -1,18 +1,22 @@
-// Vertex records of a tripartite hypergraph (Section 4.1: degree and the label sum of the
-// incident edges, packed as in Rec) built without device atomics.
+// Radix partitions of (key, value) pairs into LDS-sized buckets, and what is done per bucket:
 //
-// Part k holds the vertices [kP, (k+1)P) and exactly one vertex of every edge.  Its n
-// incidences (local vertex u, edge e) are partitioned by u into buckets of 2^14 consecutive
-// vertices in two passes -- first by the group digit u >> 22 (at most 342 groups, since
-// P < 2^32 / 3), then by the bucket digit (u >> 14) & 255 inside each group -- and each
-// bucket's 16384 records are then accumulated with LDS atomics and written out once.  Every
-// pass is a histogram / exclusive-scan / scatter over tiles of 16384 elements; a tile is
+// * Vertex records of a tripartite hypergraph (Section 4.1: degree and the label sum of the
+//   incident edges, packed as in Rec) built without device atomics.  Part k holds the vertices
+//   [kP, (k+1)P) and exactly one vertex of every edge.  Its n incidences (local vertex u,
+//   edge e) are partitioned by u into buckets of 2^14 consecutive vertices -- first by the
+//   group digit u >> 22 (at most 342 groups, since P < 2^32 / 3), then by the bucket digit
+//   (u >> 14) & 255 inside each group -- and each bucket's 16384 records are accumulated with
+//   LDS atomics and written out once.
+// * The claims of one peeling round (edge c, position p), partitioned by c into buckets of
+//   2^16 edges and resolved in LDS: the dedupe of Section 4.2 (an edge found from several
+//   degree-1 vertices enters the layer once) with the lowest claimed position as the hinge.
+//
+// Every pass is a histogram / exclusive-scan / scatter over tiles of 8192 elements; a tile is
 // ordered by digit in LDS before it is written, so the stores go out as runs of consecutive
-// addresses.  The order inside a bucket is not fixed, which the commutative sum does not see.
-//
-// Group and bucket offsets come from the scans: the scatter of the second pass lays out
-// tiles per group, and its scan is ordered (group, bucket digit, tile), so the scanned value
-// at (group, digit, tile 0) is where that bucket starts.
+// addresses.  The order inside a bucket is not fixed, which neither use depends on.  Group and
+// bucket offsets come from the scans: the second pass lays out its tiles per group, and its
+// scan is ordered (group, bucket digit, tile), so the scanned value at (group, digit, tile 0)
+// is where that bucket starts.
 #include "common.h"
 #include "launch.h"
 
@@ -22,20 +26,21 @@ namespace mphx {
 
 namespace {
 
-constexpr uint32_t kBkShift = 14;
-constexpr uint32_t kBkSize = 1u << kBkShift;
-constexpr uint32_t kGrpShift = kPartGrpShift;
+constexpr uint32_t kVxShift = 14;            // vertex buckets: 2^14 records = 128 KiB of LDS
+constexpr uint32_t kClShift = 16;            // claim buckets: 2^16 edges, a byte each = 64 KiB
 constexpr uint32_t kMaxGroups = kPartMaxGroups;
-constexpr uint32_t kDigits = 256;
-constexpr uint32_t kPtBlock = 512;  // two blocks per CU: one loads while the other writes
+constexpr uint32_t kDigits = 256;            // second-pass digit: (key >> bucket shift) & 255
+constexpr uint32_t kPtBlock = 512;           // two blocks per CU: one loads while the other writes
 constexpr uint32_t kPtPer = 16;
 constexpr uint32_t kPtTile = kPtBlock * kPtPer;
 constexpr uint32_t kWaves = kPtBlock / kWave;
 constexpr uint32_t kAccBlock = 1024;
+constexpr uint32_t kResBlock = 512;
 
-static_assert((kBkShift + 8) == kGrpShift, "a group holds 256 buckets");
+static_assert(kVxShift + 8 == kPartGrpShift, "a vertex group holds 256 buckets");
 static_assert(kPtTile == kPartTile, "first-pass tiles are the hashing kernels' tiles");
-static_assert(kPtBlock > 342 && kPtBlock >= kDigits, "one thread per group and per digit");
+static_assert(kPtBlock >= kDigits, "one thread per digit");
+static_assert(2 * kPtBlock >= kMaxGroups, "two groups per thread at most");
 
 // Exclusive prefix over the block (one value per thread); wtot is kWaves words of LDS.
 __device__ uint32_t block_exclusive(uint32_t x, uint32_t* wtot)
@@ -57,17 +62,38 @@ __device__ uint32_t block_exclusive(uint32_t x, uint32_t* wtot)
     return pre + incl - x;
 }
 
-// Local vertex of part k; an id outside the part is flagged and counted as vertex 0, so the
-// histograms and scatters stay consistent and the caller reports the error.
-__device__ __forceinline__ uint32_t local_of(uint32_t v, uint32_t k, uint64_t P, bool& bad)
+// Exclusive prefix of cnt[0, NH) into out[], NH <= 2 * kPtBlock (two entries per thread).
+__device__ void groups_exclusive(const uint32_t* cnt, uint32_t NH, uint32_t* out, uint32_t* wtot)
+{
+    const uint32_t j0 = 2 * threadIdx.x, j1 = j0 + 1;
+    const uint32_t a = j0 < NH ? cnt[j0] : 0u, b = j1 < NH ? cnt[j1] : 0u;
+    const uint32_t ex = block_exclusive(a + b, wtot);
+    if (j0 < NH)
+        out[j0] = ex;
+    if (j1 < NH)
+        out[j1] = ex + a;
+}
+
+// Local vertex of part k: an id outside the part cannot come from the hashing kernels, but is
+// counted as vertex 0 so that the passes stay consistent.
+__device__ __forceinline__ uint32_t local_of(uint32_t v, uint32_t k, uint64_t P)
 {
     uint64_t u = (uint64_t)v - (uint64_t)k * P;
-    if (u >= P) {
-        bad = true;
-        u = 0;
-    }
-    return (uint32_t)u;
+    return u < P ? (uint32_t)u : 0u;
 }
+
+// First-pass sources: part k's column of the edge list as (local vertex, edge) pairs, or a
+// list of (key, value) records.
+struct EdgeColumn {
+    const uint32_t* edges;
+    uint32_t k;
+    uint64_t P;
+    __device__ uint2 load(uint64_t i) const { return make_uint2(local_of(edges[3 * i + k], k, P), (uint32_t)i); }
+};
+struct Records {
+    const uint2* in;
+    __device__ uint2 load(uint64_t i) const { return in[i]; }
+};
 
 struct GroupInfo {
     const uint32_t* hstart;  // NH + 1 element offsets of the groups
@@ -75,39 +101,30 @@ struct GroupInfo {
     __device__ GroupInfo(const uint32_t* g) : hstart(g), tbase(g + kMaxGroups + 1) {}
 };
 
-// ---- pass 1 histograms, all three parts in one read of the edges ----------------------------
-__global__ __launch_bounds__(kPtBlock) void k_part_hist1(const uint32_t* __restrict__ edges, uint64_t n, uint64_t P,
-                                                         uint32_t NH, uint64_t nt1, uint32_t* __restrict__ hist1,
-                                                         Ctrl* ctrl)
+// ---- pass 1 histograms of a record list (the vertex build gets its own from hashing) -------
+__global__ __launch_bounds__(kPtBlock) void k_part_hist1(Records src, uint64_t n, uint32_t gsh, uint32_t NH,
+                                                         uint64_t nt1, uint32_t* __restrict__ hist1)
 {
-    __shared__ uint32_t c[3 * kMaxGroups];
-    for (uint32_t j = threadIdx.x; j < 3 * kMaxGroups; j += kPtBlock)
+    __shared__ uint32_t c[kMaxGroups];
+    for (uint32_t j = threadIdx.x; j < kMaxGroups; j += kPtBlock)
         c[j] = 0;
     __syncthreads();
     const uint64_t t0 = (uint64_t)blockIdx.x * kPtTile;
-    bool bad = false;
     for (uint32_t q = 0; q < kPtPer; q++) {
-        const uint64_t e = t0 + q * kPtBlock + threadIdx.x;
-        if (e < n) {
-            for (uint32_t k = 0; k < 3; k++) {
-                uint32_t u = local_of(edges[3 * e + k], k, P, bad);
-                atomicAdd(&c[k * kMaxGroups + (u >> kGrpShift)], 1u);
-            }
-        }
+        const uint64_t i = t0 + q * kPtBlock + threadIdx.x;
+        if (i < n)
+            atomicAdd(&c[src.load(i).x >> gsh], 1u);
     }
-    if (bad)
-        atomicOr(&ctrl->err, kErrBadEdge);
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < 3 * NH; j += kPtBlock) {
-        const uint32_t k = j / NH, h = j - k * NH;
-        hist1[((uint64_t)k * NH + h) * nt1 + blockIdx.x] = c[k * kMaxGroups + h];
-    }
+    for (uint32_t h = threadIdx.x; h < NH; h += kPtBlock)
+        hist1[(uint64_t)h * nt1 + blockIdx.x] = c[h];
 }
 
-// ---- pass 1 scatter of part k: (u, e) pairs grouped by u >> 22 ------------------------------
-__global__ __launch_bounds__(kPtBlock) void k_part_scatter1(const uint32_t* __restrict__ edges, uint64_t n, uint32_t k,
-                                                            uint64_t P, uint32_t NH, uint64_t nt1,
-                                                            const uint32_t* __restrict__ off1, uint2* __restrict__ out)
+// ---- pass 1 scatter: pairs grouped by key >> gsh -----------------------------------------------
+template <class Src>
+__global__ __launch_bounds__(kPtBlock) void k_part_scatter1(Src src, uint64_t n, uint32_t gsh, uint32_t NH,
+                                                            uint64_t nt1, const uint32_t* __restrict__ off1,
+                                                            uint2* __restrict__ out)
 {
     __shared__ uint2 buf[kPtTile];
     __shared__ uint32_t cnt[kMaxGroups], lst[kMaxGroups], gof[kMaxGroups], wtot[kWaves];
@@ -115,73 +132,70 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter1(const uint32_t* __re
         cnt[j] = 0;
     __syncthreads();
     const uint64_t t0 = (uint64_t)blockIdx.x * kPtTile;
-    uint32_t u[kPtPer], rk[kPtPer];
-    bool bad = false;
+    uint2 p[kPtPer];
+    uint32_t rk[kPtPer];
 #pragma unroll
     for (uint32_t q = 0; q < kPtPer; q++) {
-        const uint64_t e = t0 + q * kPtBlock + threadIdx.x;
-        if (e < n) {
-            u[q] = local_of(edges[3 * e + k], k, P, bad);
-            rk[q] = atomicAdd(&cnt[u[q] >> kGrpShift], 1u);
+        const uint64_t i = t0 + q * kPtBlock + threadIdx.x;
+        if (i < n) {
+            p[q] = src.load(i);
+            rk[q] = atomicAdd(&cnt[p[q].x >> gsh], 1u);
         }
     }
     __syncthreads();
-    const uint32_t x = threadIdx.x < NH ? cnt[threadIdx.x] : 0u;
-    const uint32_t ex = block_exclusive(x, wtot);
-    if (threadIdx.x < NH) {
-        lst[threadIdx.x] = ex;
-        gof[threadIdx.x] = off1[(uint64_t)threadIdx.x * nt1 + blockIdx.x];
-    }
+    groups_exclusive(cnt, NH, lst, wtot);
+    for (uint32_t h = threadIdx.x; h < NH; h += kPtBlock)
+        gof[h] = off1[(uint64_t)h * nt1 + blockIdx.x];
     __syncthreads();
 #pragma unroll
     for (uint32_t q = 0; q < kPtPer; q++) {
-        const uint64_t e = t0 + q * kPtBlock + threadIdx.x;
-        if (e < n)
-            buf[lst[u[q] >> kGrpShift] + rk[q]] = make_uint2(u[q], (uint32_t)e);
+        const uint64_t i = t0 + q * kPtBlock + threadIdx.x;
+        if (i < n)
+            buf[lst[p[q].x >> gsh] + rk[q]] = p[q];
     }
     __syncthreads();
     const uint32_t total = (uint32_t)min<uint64_t>(kPtTile, n - t0);
     for (uint32_t s = threadIdx.x; s < total; s += kPtBlock) {
-        const uint2 p = buf[s];
-        const uint32_t h = p.x >> kGrpShift;
-        out[(uint64_t)gof[h] + (s - lst[h])] = p;
+        const uint2 x = buf[s];
+        const uint32_t h = x.x >> gsh;
+        out[(uint64_t)gof[h] + (s - lst[h])] = x;
     }
 }
 
-// ---- group bounds and second-pass tile bases of part k (one block) ---------------------------
+// ---- group bounds and second-pass tile bases (one block) ---------------------------------------
 __global__ __launch_bounds__(kPtBlock) void k_part_groups(const uint32_t* __restrict__ off1, uint32_t NH, uint64_t nt1,
                                                           uint64_t n, uint32_t* __restrict__ ginfo)
 {
-    __shared__ uint32_t hs[kMaxGroups + 1], wtot[kWaves];
-    const uint32_t h = threadIdx.x;
-    if (h < NH)
+    __shared__ uint32_t hs[kMaxGroups + 1], tiles[kMaxGroups], tb[kMaxGroups], wtot[kWaves];
+    for (uint32_t h = threadIdx.x; h < NH; h += kPtBlock)
         hs[h] = off1[(uint64_t)h * nt1];
-    if (h == 0)
+    if (threadIdx.x == 0)
         hs[NH] = (uint32_t)n;
     __syncthreads();
-    const uint32_t tiles = h < NH ? (hs[h + 1] - hs[h] + kPtTile - 1) / kPtTile : 0u;
-    const uint32_t ex = block_exclusive(tiles, wtot);
-    if (h <= NH) {
+    for (uint32_t h = threadIdx.x; h < NH; h += kPtBlock)
+        tiles[h] = (hs[h + 1] - hs[h] + kPtTile - 1) / kPtTile;
+    __syncthreads();
+    groups_exclusive(tiles, NH, tb, wtot);
+    __syncthreads();
+    for (uint32_t h = threadIdx.x; h <= NH; h += kPtBlock) {
         ginfo[h] = hs[h];
-        if (h < NH)
-            ginfo[kMaxGroups + 1 + h] = ex;
+        ginfo[kMaxGroups + 1 + h] = h < NH ? tb[h] : tb[NH - 1] + tiles[NH - 1];
     }
-    if (h == NH - 1)
-        ginfo[kMaxGroups + 1 + NH] = ex + tiles;
 }
 
 // Group of second-pass tile b (the one group whose tile range holds b); s_h is LDS.
 __device__ __forceinline__ uint32_t group_of_tile(const GroupInfo& g, uint32_t NH, uint32_t b, uint32_t* s_h)
 {
-    if (threadIdx.x < NH && g.tbase[threadIdx.x] <= b && b < g.tbase[threadIdx.x + 1])
-        *s_h = threadIdx.x;
+    for (uint32_t h = threadIdx.x; h < NH; h += kPtBlock)
+        if (g.tbase[h] <= b && b < g.tbase[h + 1])
+            *s_h = h;
     __syncthreads();
     return *s_h;
 }
 
-// ---- pass 2 histograms of part k: bucket digits per (group, tile) -----------------------------
+// ---- pass 2 histograms: bucket digits per (group, tile) ----------------------------------------
 __global__ __launch_bounds__(kPtBlock) void k_part_hist2(const uint2* __restrict__ in, const uint32_t* __restrict__ ginfo,
-                                                         uint32_t NH, uint32_t* __restrict__ hist2)
+                                                         uint32_t NH, uint32_t bsh, uint32_t* __restrict__ hist2)
 {
     __shared__ uint32_t c[kDigits];
     __shared__ uint32_t s_h;
@@ -200,15 +214,15 @@ __global__ __launch_bounds__(kPtBlock) void k_part_hist2(const uint2* __restrict
     const uint64_t lo = (uint64_t)g.hstart[h] + (uint64_t)j * kPtTile;
     const uint64_t hi = min<uint64_t>(lo + kPtTile, g.hstart[h + 1]);
     for (uint64_t i = lo + threadIdx.x; i < hi; i += kPtBlock)
-        atomicAdd(&c[(in[i].x >> kBkShift) & (kDigits - 1)], 1u);
+        atomicAdd(&c[(in[i].x >> bsh) & (kDigits - 1)], 1u);
     __syncthreads();
     if (threadIdx.x < kDigits)
         hist2[(uint64_t)g.tbase[h] * kDigits + (uint64_t)threadIdx.x * tiles + j] = c[threadIdx.x];
 }
 
-// ---- pass 2 scatter of part k: pairs grouped by bucket ----------------------------------------
+// ---- pass 2 scatter: pairs grouped by bucket key >> bsh ----------------------------------------
 __global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const uint2* __restrict__ in, const uint32_t* __restrict__ ginfo,
-                                                            uint32_t NH, const uint32_t* __restrict__ off2,
+                                                            uint32_t NH, uint32_t bsh, const uint32_t* __restrict__ off2,
                                                             uint2* __restrict__ out)
 {
     __shared__ uint2 buf[kPtTile];
@@ -231,7 +245,7 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const uint2* __restr
         const uint32_t i = q * kPtBlock + threadIdx.x;
         if (i < total) {
             p[q] = in[lo + i];
-            rk[q] = atomicAdd(&cnt[(p[q].x >> kBkShift) & (kDigits - 1)], 1u);
+            rk[q] = atomicAdd(&cnt[(p[q].x >> bsh) & (kDigits - 1)], 1u);
         }
     }
     __syncthreads();
@@ -246,12 +260,12 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const uint2* __restr
     for (uint32_t q = 0; q < kPtPer; q++) {
         const uint32_t i = q * kPtBlock + threadIdx.x;
         if (i < total)
-            buf[lst[(p[q].x >> kBkShift) & (kDigits - 1)] + rk[q]] = p[q];
+            buf[lst[(p[q].x >> bsh) & (kDigits - 1)] + rk[q]] = p[q];
     }
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < total; s += kPtBlock) {
         const uint2 q = buf[s];
-        const uint32_t d = (q.x >> kBkShift) & (kDigits - 1);
+        const uint32_t d = (q.x >> bsh) & (kDigits - 1);
         out[(uint64_t)gof[d] + (s - lst[d])] = q;
     }
 }
@@ -274,35 +288,102 @@ __global__ __launch_bounds__(kAccBlock) void k_part_accum(const uint2* __restric
                                                          uint32_t NH, const uint32_t* __restrict__ off2, uint64_t n,
                                                          uint32_t k, uint64_t P, uint64_t* __restrict__ rec)
 {
-    __shared__ unsigned long long lrec[kBkSize];
+    __shared__ unsigned long long lrec[1u << kVxShift];
     const GroupInfo g(ginfo);
     const uint32_t b = blockIdx.x;
-    for (uint32_t j = threadIdx.x; j < kBkSize; j += kAccBlock)
+    for (uint32_t j = threadIdx.x; j < (1u << kVxShift); j += kAccBlock)
         lrec[j] = 0;
     const uint64_t lo = bucket_start(g, off2, NH, n, b);
     const uint64_t hi = bucket_start(g, off2, NH, n, b + 1);
     __syncthreads();
     for (uint64_t i = lo + threadIdx.x; i < hi; i += kAccBlock) {
         const uint2 p = in[i];
-        atomicAdd(&lrec[p.x & (kBkSize - 1)], (unsigned long long)(Rec::kOne + p.y));
+        atomicAdd(&lrec[p.x & ((1u << kVxShift) - 1)], (unsigned long long)(Rec::kOne + p.y));
     }
     __syncthreads();
-    const uint64_t v0 = (uint64_t)b * kBkSize;
-    const uint32_t cnt = (uint32_t)min<uint64_t>(kBkSize, P - v0);
+    const uint64_t v0 = (uint64_t)b << kVxShift;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(1u << kVxShift, P - v0);
     uint64_t* dst = rec + (uint64_t)k * P + v0;
     for (uint32_t j = threadIdx.x; j < cnt; j += kAccBlock)
         dst[j] = lrec[j];
 }
 
-}  // namespace
+// ---- resolve one round's claims, bucket by bucket of 2^16 edges -----------------------------
+// Every record is (edge c, position p) -- a claim from c's vertex in part p -- or
+// (c, 4 | p) -- a cancel from the same vertex, which marks its claim stale (the vertex lost
+// both its edges in one round).  Each (c, p) claims at most once and cancels at most once, so
+// an edge's byte in the LDS table collects its claim bits (0..2) and cancel bits (4..6); the
+// lowest position claimed and not cancelled is the hinge, and that claim is the winner and
+// appends (c, hinge) to the layer.  The grid is persistent: a block walks buckets b,
+// b + grid, ... so sparse rounds cost few launches.
+using ClaimAppender = BlockAppender<uint2, kResBlock, 4 * kResBlock>;
+constexpr uint32_t kResGridPerCU = 2;  // 64 KiB table + 16 KiB appender per block
 
-uint32_t part_groups(uint64_t P) { return (uint32_t)((P + (1ull << kGrpShift) - 1) >> kGrpShift); }
-uint64_t part_tiles(uint64_t n) { return (n + kPtTile - 1) / kPtTile; }
-
-size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L)
+__global__ __launch_bounds__(kResBlock) void k_claims_resolve(const uint2* __restrict__ in,
+                                                              const uint32_t* __restrict__ ginfo, uint32_t NH,
+                                                              const uint32_t* __restrict__ off2, uint64_t count,
+                                                              uint32_t nbuckets, uint3* __restrict__ slots,
+                                                              const uint64_t* __restrict__ lstart,
+                                                              unsigned long long* __restrict__ lcount, uint32_t r,
+                                                              Ctrl* ctrl)
 {
-    const uint64_t NH = part_groups(P), nt1 = part_tiles(n);
-    const uint64_t h1 = 3 * NH * nt1, h2 = (nt1 + NH) * kDigits;
+    __shared__ uint32_t tab[(1u << kClShift) / 4];
+    __shared__ ClaimAppender app;
+    __shared__ unsigned long long s_fresh;
+    constexpr uint32_t kMask = (1u << kClShift) - 1;
+    const GroupInfo g(ginfo);
+    const uint64_t base = lstart[r];
+    auto out = [slots, base](uint64_t i, uint2 v) { slots[base + i] = make_uint3(v.x, v.y, 0u); };
+    if (threadIdx.x == 0)
+        s_fresh = 0;
+    app.init();
+    unsigned long long fresh = 0;
+    for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
+        const uint64_t lo = bucket_start(g, off2, NH, count, b);
+        const uint64_t hi = bucket_start(g, off2, NH, count, b + 1);
+        if (lo == hi)
+            continue;  // uniform per block
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += kResBlock)
+            tab[(in[i].x & kMask) >> 2] = 0u;
+        __syncthreads();
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += kResBlock) {
+            const uint2 c = in[i];
+            atomicOr(&tab[(c.x & kMask) >> 2], 1u << (8 * (c.x & 3) + c.y));
+        }
+        __syncthreads();
+        for (uint64_t i0 = lo; i0 < hi; i0 += kResBlock) {
+            const uint64_t i = i0 + threadIdx.x;
+            bool win = false;
+            uint2 c = make_uint2(0u, 0u);
+            if (i < hi) {
+                c = in[i];
+                const uint32_t t = tab[(c.x & kMask) >> 2] >> (8 * (c.x & 3));
+                const uint32_t live = t & ~(t >> 4) & 7u;
+                win = c.y < 4 && live != 0 && (uint32_t)__builtin_ctz(live) == c.y;
+                fresh += (c.y < 4 && ((live >> c.y) & 1u)) ? 1u : 0u;
+            }
+            app.push(win, c, false, c, &lcount[r], out);
+        }
+        __syncthreads();  // the table is reused by the next bucket
+    }
+    app.flush(&lcount[r], out);
+    if (fresh)
+        atomicAdd(&s_fresh, fresh);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_fresh)
+        atomicAdd(&ctrl->claims, s_fresh);
+}
+
+// Byte offsets inside the auxiliary buffer of one partition: first-pass histograms
+// [NH][nt1], second-pass histograms [(nt1 + NH) * 256], group table, scan scratch.
+struct AuxLayout {
+    size_t hist1, hist2, ginfo, scan, scan_bytes, total;
+};
+
+AuxLayout aux_layout(uint64_t h1_entries, uint64_t n, uint32_t NH)
+{
+    const uint64_t nt1 = (n + kPtTile - 1) / kPtTile, h2 = (nt1 + NH) * kDigits;
+    AuxLayout L{};
     size_t off = 0;
     auto take = [&off](size_t bytes) {
         off = (off + 255) & ~(size_t)255;
@@ -310,62 +391,122 @@ size_t part_build_bytes(uint64_t n, uint64_t P, PartBuildLayout* L)
         off += bytes;
         return at;
     };
-    size_t o_h1 = take(h1 * 4), o_h2 = take(h2 * 4), o_gi = take((2 * kMaxGroups + 2) * 4);
-    size_t sb = std::max(scan_scratch_bytes(NH * nt1), scan_scratch_bytes(h2));
-    size_t o_sc = take(sb);
-    if (L) {
-        L->hist1_off = o_h1;
-        L->hist2_off = o_h2;
-        L->ginfo_off = o_gi;
-        L->scan_off = o_sc;
-        L->scan_bytes = sb;
-    }
-    return off;
+    L.hist1 = take(h1_entries * 4);
+    L.hist2 = take(h2 * 4);
+    L.ginfo = take((2 * kMaxGroups + 2) * 4);
+    L.scan_bytes = std::max(scan_scratch_bytes(h1_entries), scan_scratch_bytes(h2));
+    L.scan = take(L.scan_bytes);
+    L.total = off;
+    return L;
+}
+
+uint32_t groups_of(uint64_t keys, uint32_t gsh) { return (uint32_t)((keys + (1ull << gsh) - 1) >> gsh); }
+uint64_t tiles_of(uint64_t n) { return (n + kPtTile - 1) / kPtTile; }
+
+// Build aux: three parts' first-pass histograms of n edges over P vertices.
+AuxLayout build_aux(uint64_t n, uint64_t P)
+{
+    const uint32_t NH = groups_of(P, kPartGrpShift);
+    return aux_layout(3ull * NH * tiles_of(n), n, NH);
+}
+
+// Claims aux: up to m claims keyed by edge ids below n.
+AuxLayout claims_aux(uint64_t m, uint64_t n)
+{
+    const uint32_t NH = groups_of(n, kClShift + 8);
+    return aux_layout((uint64_t)NH * tiles_of(m), m, NH);
+}
+
+// Second pass + per-bucket kernel shared by both uses, after the first-pass scan.
+template <class Src, class Last>
+hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32_t* off1, uint2* mid, uint2* out,
+                          const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
+{
+    const uint64_t nt1 = tiles_of(n), nt2 = nt1 + NH;
+    uint32_t* hist2 = reinterpret_cast<uint32_t*>(base + L.hist2);
+    uint32_t* ginfo = reinterpret_cast<uint32_t*>(base + L.ginfo);
+    void* scan = base + L.scan;
+    hipError_t err = launch_scan_u32(off1, (uint64_t)NH * nt1, off1, scan, L.scan_bytes, s);
+    if (err != hipSuccess) return err;
+    k_part_scatter1<Src><<<(unsigned)nt1, kPtBlock, 0, s>>>(src, n, gsh, NH, nt1, off1, mid);
+    k_part_groups<<<1, kPtBlock, 0, s>>>(off1, NH, nt1, n, ginfo);
+    k_part_hist2<<<(unsigned)nt2, kPtBlock, 0, s>>>(mid, ginfo, NH, gsh - 8, hist2);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    err = launch_scan_u32(hist2, nt2 * kDigits, hist2, scan, L.scan_bytes, s);
+    if (err != hipSuccess) return err;
+    k_part_scatter2<<<(unsigned)nt2, kPtBlock, 0, s>>>(mid, ginfo, NH, gsh - 8, hist2, out);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return last(ginfo, hist2);
+}
+
+}  // namespace
+
+size_t part_aux_bytes(uint64_t n, uint64_t P, bool lists)
+{
+    size_t b = build_aux(n, P).total;
+    if (lists)
+        b = std::max(b, claims_aux(3 * P, n).total);
+    return b;
 }
 
 PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P)
 {
-    PartBuildLayout L;
-    part_build_bytes(n, P, &L);
-    return PartHist1{reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(aux) + L.hist1_off), part_groups(P),
-                     part_tiles(n)};
+    const AuxLayout L = build_aux(n, P);
+    return PartHist1{reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(aux) + L.hist1),
+                     groups_of(P, kPartGrpShift), tiles_of(n)};
 }
 
 hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
-                             uint2* pairs2, void* aux, Ctrl* ctrl, bool hist1_done, hipStream_t s)
+                             uint2* pairs2, void* aux, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    PartBuildLayout L;
-    part_build_bytes(n, P, &L);
+    const AuxLayout L = build_aux(n, P);
     uint8_t* base = reinterpret_cast<uint8_t*>(aux);
-    uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1_off);
-    uint32_t* hist2 = reinterpret_cast<uint32_t*>(base + L.hist2_off);
-    uint32_t* ginfo = reinterpret_cast<uint32_t*>(base + L.ginfo_off);
-    void* scan = base + L.scan_off;
-    const uint32_t NH = part_groups(P);
-    const uint64_t nt1 = part_tiles(n), nt2 = nt1 + NH, nb = (P + kBkSize - 1) / kBkSize;
+    uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
+    const uint32_t NH = groups_of(P, kPartGrpShift);
+    const uint64_t nt1 = tiles_of(n), nb = (P + (1ull << kVxShift) - 1) >> kVxShift;
     if (NH > kMaxGroups || nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
-    if (!hist1_done)
-        k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(edges, n, P, NH, nt1, hist1, ctrl);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
     for (uint32_t k = 0; k < 3; k++) {
         uint32_t* off1 = hist1 + (uint64_t)k * NH * nt1;
-        err = launch_scan_u32(off1, (uint64_t)NH * nt1, off1, scan, L.scan_bytes, s);
-        if (err != hipSuccess) return err;
-        k_part_scatter1<<<(unsigned)nt1, kPtBlock, 0, s>>>(edges, n, k, P, NH, nt1, off1, pairs1);
-        k_part_groups<<<1, kPtBlock, 0, s>>>(off1, NH, nt1, n, ginfo);
-        k_part_hist2<<<(unsigned)nt2, kPtBlock, 0, s>>>(pairs1, ginfo, NH, hist2);
-        err = hipGetLastError();
-        if (err != hipSuccess) return err;
-        err = launch_scan_u32(hist2, nt2 * kDigits, hist2, scan, L.scan_bytes, s);
-        if (err != hipSuccess) return err;
-        k_part_scatter2<<<(unsigned)nt2, kPtBlock, 0, s>>>(pairs1, ginfo, NH, hist2, pairs2);
-        k_part_accum<<<(unsigned)nb, kAccBlock, 0, s>>>(pairs2, ginfo, NH, hist2, n, k, P, rec);
-        err = hipGetLastError();
+        hipError_t err = partition_then(
+            EdgeColumn{edges, k, P}, n, kPartGrpShift, NH, off1, pairs1, pairs2, L, base,
+            [&](const uint32_t* ginfo, const uint32_t* off2) {
+                k_part_accum<<<(unsigned)nb, kAccBlock, 0, s>>>(pairs2, ginfo, NH, off2, n, k, P, rec);
+                return hipGetLastError();
+            },
+            s);
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const uint32_t gsh = kClShift + 8;
+    const AuxLayout L = claims_aux(st.m, st.n);
+    uint8_t* base = reinterpret_cast<uint8_t*>(st.aux);
+    uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
+    const uint32_t NH = groups_of(st.n, gsh);
+    const uint64_t nt1 = tiles_of(count), nb = (st.n + (1ull << kClShift) - 1) >> kClShift;
+    if (count > st.m || NH > kMaxGroups || nt1 > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{st.claims}, count, gsh, NH, nt1, hist1);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return partition_then(
+        Records{st.claims}, count, gsh, NH, hist1, st.claims_tmp, st.claims, L, base,
+        [&](const uint32_t* ginfo, const uint32_t* off2) {
+            int dev = 0, cus = 256;
+            if (hipGetDevice(&dev) == hipSuccess)
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            const uint64_t grid = std::min<uint64_t>(nb, (uint64_t)kResGridPerCU * (uint64_t)std::max(cus, 1));
+            k_claims_resolve<<<(unsigned)grid, kResBlock, 0, s>>>(st.claims, ginfo, NH, off2, count, (uint32_t)nb,
+                                                                st.slots, st.lstart, st.lcount, r, st.ctrl);
+            return hipGetLastError();
+        },
+        s);
 }
 
 }  // namespace mphx

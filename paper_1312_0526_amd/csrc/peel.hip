@@ -18,13 +18,24 @@
 // degree 1 and dies with it) and appends the next layer through count[r + 1].  Round bounds
 // live in device memory, so rounds are enqueued without host round trips; a round after the
 // last one finds an empty layer and does nothing.
+//
+// With claim lists (tripartite graphs), apply(r) appends (edge, position) claims instead of
+// the atomicMin, and a deletion that takes a vertex from 1 to 0 appends a cancel for its own
+// edge: if that vertex reached degree 1 earlier in the same round, its claim named exactly
+// this edge, which leaves in this round, so the pair marks the claim stale.  The lists are
+// then resolved bucket by bucket in LDS (part.hip); a resolved layer carries its hinge in the
+// slot.
 #include "common.h"
 #include "launch.h"
+
+#include <type_traits>
 
 namespace mphx {
 
 constexpr int kPeelBlock = 256;
 using LayerAppender = BlockAppender<uint32_t, kPeelBlock, 2048>;
+using ClaimListAppender = BlockAppender<uint2, kPeelBlock, 2048>;
+constexpr uint32_t kCancel = 4;  // claim-list record (edge, kCancel | position): a stale claim
 
 // Position of vertex v in edge e (generic edge lists; tripartite ones use the part).
 template <bool kTri>
@@ -112,15 +123,16 @@ __global__ __launch_bounds__(kPeelBlock) void k_round0(const uint64_t* __restric
 // ------------------------------------------------------------------------------------------
 // Round r: delete layer r's edges and claim round r + 1.
 // ------------------------------------------------------------------------------------------
-template <bool kTri>
+template <bool kTri, bool kList>
 __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec, const uint32_t* __restrict__ edges,
                                                       uint32_t* __restrict__ state, uint3* __restrict__ slots,
                                                       uint64_t* __restrict__ lstart,
-                                                      unsigned long long* __restrict__ lcount, Ctrl* ctrl, uint32_t r,
-                                                      uint64_t P)
+                                                      unsigned long long* __restrict__ lcount, uint2* __restrict__ claims,
+                                                      unsigned long long* __restrict__ ccount, uint64_t ccap,
+                                                      Ctrl* ctrl, uint32_t r, uint64_t P, bool hinge_in_slot)
 {
     const uint64_t lo = lstart[r];
-    const uint64_t hi = lo + lcount[r];  // final: appended during the previous launch
+    const uint64_t hi = lo + lcount[r];  // final: appended before this launch
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         lstart[r + 1] = hi;
         if (hi == lo)
@@ -128,22 +140,24 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
     }
     if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
         return;  // whole block idle (uniform)
-    __shared__ LayerAppender app;
+    using App = std::conditional_t<kList, ClaimListAppender, LayerAppender>;
+    __shared__ App app;
     __shared__ unsigned long long s_push, s_claims;
     if (threadIdx.x == 0)
         s_push = s_claims = 0;
     app.init();
-    auto out = [slots, hi](uint64_t i, uint32_t e) { slots[hi + i].x = e; };
     unsigned long long mypush = 0, myclaims = 0;
     const uint32_t rr = (r + 1) << 2;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
-        uint32_t c0 = 0, c1 = 0;
+        uint32_t c0 = 0, c1 = 0, p0 = 0, p1 = 0;
         bool f0 = false, f1 = false;
         if (i < hi) {
-            uint32_t e = slots[i].x;
-            uint32_t h = state[e] & 3u;
+            const uint3 sl = slots[i];
+            const uint32_t e = sl.x;
+            // a resolved claim list leaves the hinge in the slot, atomic claims in the state
+            const uint32_t h = hinge_in_slot ? sl.y : (state[e] & 3u);
             const uint32_t* t = edges + 3 * (uint64_t)e;
             uint32_t v0 = t[0], v1 = t[1], v2 = t[2];
             uint32_t vh = h == 0 ? v0 : (h == 1 ? v1 : v2);
@@ -154,27 +168,62 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
             uint64_t ob = Rec::del(rec, vb, e);
             if (Rec::deg(oa) == 2) {
                 c0 = (uint32_t)(Rec::edge(oa) - e);
-                uint32_t old = atomicMin(&state[c0], rr | position_in<kTri>(edges, c0, va, P));
-                f0 = old == kUnclaimed;
+                p0 = position_in<kTri>(edges, c0, va, P);
                 mypush++;
-                myclaims += (f0 || (old >> 2) == r + 1) ? 1u : 0u;
+                if constexpr (kList) {
+                    f0 = true;
+                } else {
+                    uint32_t old = atomicMin(&state[c0], rr | p0);
+                    f0 = old == kUnclaimed;
+                    myclaims += (f0 || (old >> 2) == r + 1) ? 1u : 0u;
+                }
+            } else if (kList && Rec::deg(oa) == 1) {
+                // va leaves with this edge; if it reached degree 1 earlier in this round, its
+                // claim named this edge and is stale: cancel it
+                c0 = e;
+                p0 = kCancel | part_of(va, P);
+                f0 = true;
             }
             if (Rec::deg(ob) == 2) {
                 c1 = (uint32_t)(Rec::edge(ob) - e);
-                uint32_t old = atomicMin(&state[c1], rr | position_in<kTri>(edges, c1, vb, P));
-                f1 = old == kUnclaimed;
+                p1 = position_in<kTri>(edges, c1, vb, P);
                 mypush++;
-                myclaims += (f1 || (old >> 2) == r + 1) ? 1u : 0u;
+                if constexpr (kList) {
+                    f1 = true;
+                } else {
+                    uint32_t old = atomicMin(&state[c1], rr | p1);
+                    f1 = old == kUnclaimed;
+                    myclaims += (f1 || (old >> 2) == r + 1) ? 1u : 0u;
+                }
+            } else if (kList && Rec::deg(ob) == 1) {
+                c1 = e;
+                p1 = kCancel | part_of(vb, P);
+                f1 = true;
             }
-            if (!f0) {  // the first requested slot holds the first appended edge
+            if (!f0) {  // the first requested slot holds the first appended entry
                 c0 = c1;
+                p0 = p1;
                 f0 = f1;
                 f1 = false;
             }
         }
-        app.push(f0, c0, f1, c1, &lcount[r + 1], out);
+        if constexpr (kList) {
+            // records past the list's capacity are counted, not stored; the host then redoes
+            // the build with atomic claims
+            app.push(f0, make_uint2(c0, p0), f1, make_uint2(c1, p1), &ccount[r + 1], [claims, ccap](uint64_t j, uint2 c) {
+                if (j < ccap) claims[j] = c;
+            });
+        } else {
+            app.push(f0, c0, f1, c1, &lcount[r + 1], [slots, hi](uint64_t j, uint32_t x) { slots[hi + j].x = x; });
+        }
     }
-    app.flush(&lcount[r + 1], out);
+    if constexpr (kList) {
+        app.flush(&ccount[r + 1], [claims, ccap](uint64_t j, uint2 c) {
+            if (j < ccap) claims[j] = c;
+        });
+    } else {
+        app.flush(&lcount[r + 1], [slots, hi](uint64_t j, uint32_t x) { slots[hi + j].x = x; });
+    }
     if (mypush) atomicAdd(&s_push, mypush);
     if (myclaims) atomicAdd(&s_claims, myclaims);
     __syncthreads();
@@ -316,15 +365,18 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const PeelState& st, uint32_t r, hipStream_t s)
+hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, bool list_claims, hipStream_t s)
 {
     unsigned g = grid_for(st.n, st.grid_cap);
-    if (st.tripartite)
-        k_apply<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, st.ctrl, r,
-                                               st.P);
+    if (st.tripartite && list_claims)
+        k_apply<true, true><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount,
+                                                     st.claims, st.ccount, st.m, st.ctrl, r, st.P, hinge_in_slot);
+    else if (st.tripartite)
+        k_apply<true, false><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount,
+                                                      st.claims, st.ccount, st.m, st.ctrl, r, st.P, hinge_in_slot);
     else
-        k_apply<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, st.ctrl,
-                                                r, st.P);
+        k_apply<false, false><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount,
+                                                       st.claims, st.ccount, st.m, st.ctrl, r, st.P, false);
     return hipGetLastError();
 }
 

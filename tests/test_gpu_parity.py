@@ -333,3 +333,53 @@ def test_mphf_degree_overflow(mx, o, build_mode, copies):
     assert ei.value.status == mx.ERANGE
     if copies < 1000:
         assert o.mphf_build_u64(keys, max_tries=2)[0] == oracle.ERANGE
+
+
+@pytest.fixture(params=[1, 0], ids=["claim-lists", "atomic-claims"])
+def claim_mode(request, mx):
+    """Next-layer claims: partitioned lists resolved in LDS (forced on at every size), or one
+    device atomic per claim."""
+    mx.set_option("claim_lists", request.param)
+    yield request.param
+    mx.set_option("claim_lists", 28)
+
+
+@pytest.mark.parametrize("n,seed", [(1_000_000, 0), (12_000_000, 4), (1, 0), (7, 5)])
+def test_mphf_claim_modes_match_oracle(mx, o, claim_mode, n, seed):
+    """12e6 keys span one claim group of 2^24 edges and 184 buckets of 2^16."""
+    keys = workloads.u64_keys(n, gen_seed=41)
+    got = mx.mphf_build_u64(dev(keys), seed=seed)
+    rc, ref = o.mphf_build_u64(keys, seed=seed)
+    assert rc == 0
+    _assert_mphf_equal(got, ref)
+
+
+def test_mphf_claim_lists_strings_retries_and_failures(mx, o):
+    mx.set_option("claim_lists", 1)
+    try:
+        data, offs = workloads.str_keys(300_000, gen_seed=43)
+        got = mx.mphf_build_str(dev(data), dev(offs), seed=6)
+        rc, ref = o.mphf_build_str(data, offs, seed=6)
+        assert rc == 0
+        _assert_mphf_equal(got, ref)
+        retried = 0
+        for b in range(20):
+            keys = workloads.u64_keys(100, gen_seed=workloads.bucket_gen_seed(b))
+            got = mx.mphf_build_u64(dev(keys), seed=0)
+            rc, ref = o.mphf_build_u64(keys, seed=0)
+            assert rc == 0
+            _assert_mphf_equal(got, ref)
+            retried += got["tries"] > 1
+        assert retried > 3
+        keys = workloads.u64_keys(50_000)
+        with pytest.raises(mx.MphxError) as ei:
+            mx.mphf_build_u64(dev(keys), gamma=(120, 100), max_tries=1)
+        rc, ref = o.mphf_build_u64(keys, gnum=120, max_tries=1)
+        assert ei.value.status == mx.ECORE and rc == oracle.ECORE
+        assert ei.value.info["n_core"] == ref["n_core"] and ei.value.info["n_rounds"] == ref["n_rounds"]
+        dup = np.concatenate([keys[:1000], keys[:2]])
+        with pytest.raises(mx.MphxError) as ei:
+            mx.mphf_build_u64(dev(dup), max_tries=2)
+        assert ei.value.status == mx.EDUP
+    finally:
+        mx.set_option("claim_lists", 28)
