@@ -314,7 +314,7 @@ __global__ __launch_bounds__(kAccBlock) void k_part_accum(const uint2* __restric
 // both its edges in one round).  Each (c, p) claims at most once and cancels at most once, so
 // an edge's byte in the LDS table collects its claim bits (0..2) and cancel bits (4..6); the
 // lowest position claimed and not cancelled is the hinge, and that claim is the winner and
-// appends (c, hinge) to the layer.  The grid is persistent: a block walks buckets b,
+// appends (c, hinge | live positions << 8) to the layer.  The grid is persistent: a block walks buckets b,
 // b + grid, ... so sparse rounds cost few launches.
 using ClaimAppender = BlockAppender<uint2, kResBlock, 4 * kResBlock>;
 constexpr uint32_t kResGridPerCU = 2;  // 64 KiB table + 16 KiB appender per block
@@ -361,6 +361,7 @@ __global__ __launch_bounds__(kResBlock) void k_claims_resolve(const uint2* __res
                 const uint32_t live = t & ~(t >> 4) & 7u;
                 win = c.y < 4 && live != 0 && (uint32_t)__builtin_ctz(live) == c.y;
                 fresh += (c.y < 4 && ((live >> c.y) & 1u)) ? 1u : 0u;
+                c.y |= live << 8;  // the layer entry also names every position at degree 1
             }
             app.push(win, c, false, c, &lcount[r], out);
         }

@@ -156,16 +156,22 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
         if (i < hi) {
             const uint3 sl = slots[i];
             const uint32_t e = sl.x;
-            // a resolved claim list leaves the hinge in the slot, atomic claims in the state
-            const uint32_t h = hinge_in_slot ? sl.y : (state[e] & 3u);
+            // a resolved claim list leaves the hinge in the slot, with the positions of all the
+            // edge's vertices that had degree 1 when the round began; atomic claims leave the
+            // hinge in the state
+            const uint32_t h = hinge_in_slot ? (sl.y & 3u) : (state[e] & 3u);
+            const uint32_t ones = hinge_in_slot ? (sl.y >> 8) & 7u : 0u;
             const uint32_t* t = edges + 3 * (uint64_t)e;
             uint32_t v0 = t[0], v1 = t[1], v2 = t[2];
             uint32_t vh = h == 0 ? v0 : (h == 1 ? v1 : v2);
             uint32_t va = h == 0 ? v1 : (h == 1 ? v2 : v0);
             uint32_t vb = h == 0 ? v2 : (h == 1 ? v0 : v1);
             slots[i] = make_uint3(vh, va, vb);
-            uint64_t oa = Rec::del(rec, va, e);
-            uint64_t ob = Rec::del(rec, vb, e);
+            // a vertex that had degree 1 when the round began drops to 0 with this edge and is
+            // never read again: its delete can be skipped (old degree reads as 1, no record)
+            const uint32_t pa = h == 2 ? 0u : h + 1, pb = h == 0 ? 2u : h - 1;
+            uint64_t oa = ((ones >> pa) & 1u) ? Rec::kOne : Rec::del(rec, va, e);
+            uint64_t ob = ((ones >> pb) & 1u) ? Rec::kOne : Rec::del(rec, vb, e);
             if (Rec::deg(oa) == 2) {
                 c0 = (uint32_t)(Rec::edge(oa) - e);
                 p0 = position_in<kTri>(edges, c0, va, P);
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
                     f0 = old == kUnclaimed;
                     myclaims += (f0 || (old >> 2) == r + 1) ? 1u : 0u;
                 }
-            } else if (kList && Rec::deg(oa) == 1) {
+            } else if (kList && Rec::deg(oa) == 1 && !((ones >> pa) & 1u)) {
                 // va leaves with this edge; if it reached degree 1 earlier in this round, its
                 // claim named this edge and is stale: cancel it
                 c0 = e;
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
                     f1 = old == kUnclaimed;
                     myclaims += (f1 || (old >> 2) == r + 1) ? 1u : 0u;
                 }
-            } else if (kList && Rec::deg(ob) == 1) {
+            } else if (kList && Rec::deg(ob) == 1 && !((ones >> pb) & 1u)) {
                 c1 = e;
                 p1 = kCancel | part_of(vb, P);
                 f1 = true;
