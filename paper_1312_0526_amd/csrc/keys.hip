@@ -110,13 +110,14 @@ __global__ __launch_bounds__(kHuBlock) void k_hash_u64_tiles(const uint64_t* __r
 // leaves most lanes of a wave idle while its longest key finishes.  Here a block takes 256
 // consecutive keys and spreads their 8-byte words over its lanes: word f of the block's flat
 // word list belongs to key owner[f] at word index j, adds its two mixed terms into that key's
-// LDS sums, and the key's thread finishes the digest.  The loads of consecutive words are
-// consecutive in memory; each lane has four words' loads in flight.  Keys longer than 512
-// bytes are digested by their own thread.  With histograms requested, block b hashes exactly
-// partition tile b.
+// LDS sums, and the key's thread finishes the digest.  The owner table covers a window of
+// kHsWindow words at a time (the block walks as many windows as its keys need, so a key of
+// any length is spread too); it is small, so eight blocks fit on a CU.  The loads of
+// consecutive words are consecutive in memory; each lane has two words' loads in flight.
+// With histograms requested, block b hashes exactly partition tile b.
 constexpr uint32_t kHsBlock = 256;
-constexpr uint32_t kHsMaxWords = 64;
-constexpr uint32_t kHsUnroll = 4;
+constexpr uint32_t kHsWindow = 2048;
+constexpr uint32_t kHsUnroll = 2;
 static_assert(kPartTile % kHsBlock == 0, "a partition tile is whole chunks");
 
 __device__ __forceinline__ uint64_t key_word(const uint8_t* bytes, uint64_t p, uint64_t total)
@@ -134,10 +135,9 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
                                                              uint64_t seed, uint64_t P, uint32_t* __restrict__ edges,
                                                              PartHist1 h1)
 {
-    __shared__ uint64_t s_off[kHsBlock];
-    __shared__ uint32_t s_len[kHsBlock], s_wpre[kHsBlock], s_wtot[kHsBlock / kWave];
+    __shared__ uint64_t s_off[kHsBlock], s_len[kHsBlock], s_wpre[kHsBlock], s_wtot[kHsBlock / kWave];
     __shared__ unsigned long long s_A[kHsBlock], s_B[kHsBlock];
-    __shared__ uint8_t s_owner[kHsBlock * kHsMaxWords];
+    __shared__ uint8_t s_owner[kHsWindow];
     __shared__ TileHist th;
     const uint64_t total = offs[n];
     const uint64_t sa = fin(seed + kGamma);
@@ -154,98 +154,93 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
     for (uint64_t c = c0; c < c1; c += cstep) {
         const uint64_t i = c * kHsBlock + tid;
         uint64_t o0 = 0, len = 0;
-        uint32_t nw = 0;
-        bool longkey = false;
         if (i < n) {
             o0 = offs[i];
             len = offs[i + 1] - o0;
-            const uint64_t w = (len + 7) >> 3;
-            longkey = w > kHsMaxWords;
-            nw = longkey ? 0u : (uint32_t)w;
         }
+        const uint64_t nw = (len + 7) >> 3;
         s_off[tid] = o0;
-        s_len[tid] = (uint32_t)(longkey ? 0 : len);
+        s_len[tid] = len;
         s_A[tid] = 0;
         s_B[tid] = 0;
         // exclusive prefix of the word counts over the block
-        uint32_t incl = nw;
+        uint64_t incl = nw;
         for (uint32_t d = 1; d < kWave; d <<= 1) {
-            uint32_t y = __shfl_up(incl, d, kWave);
+            uint64_t y = __shfl_up(incl, d, kWave);
             if (lane >= d)
                 incl += y;
         }
         if (lane == kWave - 1)
             s_wtot[wv] = incl;
         __syncthreads();
-        uint32_t pre = 0, W = 0;
+        uint64_t pre = 0, W = 0;
         for (uint32_t q = 0; q < kHsBlock / kWave; q++) {
-            pre += q < wv ? s_wtot[q] : 0u;
+            pre += q < wv ? s_wtot[q] : 0ull;
             W += s_wtot[q];
         }
         pre += incl - nw;
         s_wpre[tid] = pre;
-        for (uint32_t j = 0; j < nw; j++)
-            s_owner[pre + j] = (uint8_t)tid;
-        __syncthreads();
-        for (uint32_t f0 = tid; f0 < W; f0 += kHsUnroll * kHsBlock) {
-            uint32_t t[kHsUnroll], j[kHsUnroll];
-            uint64_t p[kHsUnroll], w[kHsUnroll];
-            bool fast = true;
-#pragma unroll
-            for (uint32_t u = 0; u < kHsUnroll; u++) {
-                const uint32_t f = f0 + u * kHsBlock;
-                t[u] = 0;
-                j[u] = 0;
-                p[u] = 0;
-                if (f < W) {
-                    t[u] = s_owner[f];
-                    j[u] = f - s_wpre[t[u]];
-                    p[u] = s_off[t[u]] + 8ull * j[u];
-                }
-                fast = fast && ((p[u] >> 2) + 3) * 4 <= total;
-            }
-            if (fast) {  // all three dwords of every word inside the array: plain loads
-                const uint32_t* d = reinterpret_cast<const uint32_t*>(bytes);
-                uint32_t x0[kHsUnroll], x1[kHsUnroll], x2[kHsUnroll];
+        for (uint64_t w0 = 0; w0 < W; w0 += kHsWindow) {
+            const uint64_t w1 = min<uint64_t>(w0 + kHsWindow, W);
+            // this key's words inside the window [w0, w1)
+            for (uint64_t f = max<uint64_t>(pre, w0); f < min<uint64_t>(pre + nw, w1); f++)
+                s_owner[f - w0] = (uint8_t)tid;
+            __syncthreads();
+            for (uint64_t f0 = w0 + tid; f0 < w1; f0 += kHsUnroll * kHsBlock) {
+                uint32_t t[kHsUnroll], j[kHsUnroll];
+                uint64_t p[kHsUnroll], w[kHsUnroll];
+                bool fast = true;
 #pragma unroll
                 for (uint32_t u = 0; u < kHsUnroll; u++) {
-                    const uint64_t q = p[u] >> 2;
-                    x0[u] = d[q];
-                    x1[u] = d[q + 1];
-                    x2[u] = d[q + 2];
+                    const uint64_t f = f0 + u * kHsBlock;
+                    t[u] = 0;
+                    j[u] = 0;
+                    p[u] = 0;
+                    if (f < w1) {
+                        t[u] = s_owner[f - w0];
+                        j[u] = (uint32_t)(f - s_wpre[t[u]]);
+                        p[u] = s_off[t[u]] + 8ull * j[u];
+                    }
+                    fast = fast && ((p[u] >> 2) + 3) * 4 <= total;
+                }
+                if (fast) {  // all three dwords of every word inside the array: plain loads
+                    const uint32_t* d = reinterpret_cast<const uint32_t*>(bytes);
+                    uint32_t x0[kHsUnroll], x1[kHsUnroll], x2[kHsUnroll];
+#pragma unroll
+                    for (uint32_t u = 0; u < kHsUnroll; u++) {
+                        const uint64_t q = p[u] >> 2;
+                        x0[u] = d[q];
+                        x1[u] = d[q + 1];
+                        x2[u] = d[q + 2];
+                    }
+#pragma unroll
+                    for (uint32_t u = 0; u < kHsUnroll; u++) {
+                        const uint32_t sh = (uint32_t)(p[u] & 3) * 8;
+                        const uint64_t lo = (uint64_t)x0[u] | ((uint64_t)x1[u] << 32);
+                        w[u] = sh ? ((lo >> sh) | ((uint64_t)x2[u] << (64 - sh))) : lo;
+                    }
+                } else {
+#pragma unroll
+                    for (uint32_t u = 0; u < kHsUnroll; u++)
+                        w[u] = f0 + u * kHsBlock < w1 ? key_word(bytes, p[u], total) : 0ull;
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kHsUnroll; u++) {
-                    const uint32_t sh = (uint32_t)(p[u] & 3) * 8;
-                    const uint64_t lo = (uint64_t)x0[u] | ((uint64_t)x1[u] << 32);
-                    w[u] = sh ? ((lo >> sh) | ((uint64_t)x2[u] << (64 - sh))) : lo;
-                }
-            } else {
-#pragma unroll
-                for (uint32_t u = 0; u < kHsUnroll; u++)
-                    w[u] = f0 + u * kHsBlock < W ? key_word(bytes, p[u], total) : 0ull;
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < kHsUnroll; u++) {
-                if (f0 + u * kHsBlock < W) {
-                    const uint32_t rem = s_len[t[u]] - 8 * j[u];
-                    uint64_t x = w[u];
-                    if (rem < 8)
-                        x &= (1ull << (8 * rem)) - 1;
-                    atomicAdd(&s_A[t[u]], (unsigned long long)fin(x ^ (sa + j[u] * kGamma)));
-                    atomicAdd(&s_B[t[u]], (unsigned long long)fin(x ^ (sb + j[u] * kGamma)));
+                    if (f0 + u * kHsBlock < w1) {
+                        const uint64_t rem = s_len[t[u]] - 8ull * j[u];
+                        uint64_t x = w[u];
+                        if (rem < 8)
+                            x &= (1ull << (8 * rem)) - 1;
+                        atomicAdd(&s_A[t[u]], (unsigned long long)fin(x ^ (sa + j[u] * kGamma)));
+                        atomicAdd(&s_B[t[u]], (unsigned long long)fin(x ^ (sb + j[u] * kGamma)));
+                    }
                 }
             }
+            __syncthreads();  // the owner window is rewritten next
         }
-        __syncthreads();
         if (i < n) {
-            uint64_t a, b;
-            if (longkey) {
-                digest_str(bytes, o0, len, total, sa, sb, a, b);
-            } else {
-                a = fin(s_A[tid] ^ sa ^ len);
-                b = fin(s_B[tid] ^ sb ^ len);
-            }
+            const uint64_t a = fin(s_A[tid] ^ sa ^ len);
+            const uint64_t b = fin(s_B[tid] ^ sb ^ len);
             uint32_t v0, v1, v2;
             edge_of_digest(a, b, P, v0, v1, v2);
             edges[3 * i] = v0;
@@ -254,7 +249,7 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
             if (h1.hist)
                 th.count(v0, v1, v2, P);
         }
-        __syncthreads();  // the LDS arrays are reused by the next chunk
+        __syncthreads();  // the per-key LDS arrays are reused by the next chunk
     }
     if (h1.hist)
         th.store(h1, blockIdx.x);
