@@ -135,8 +135,8 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
         out = {}
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
-                name = r["Kernel_Name"].replace("(anonymous namespace)::", "")
-                name = name.split("(")[0].split("::")[-1].split("<")[0]
+                name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+                name = name.split("(")[0].split("<")[0].split("::")[-1]
                 cur = out.setdefault(name, [0.0, 0])
                 cur[0] += float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
                 cur[1] += 1
@@ -197,8 +197,8 @@ def summarize_kernel_stats(csv_path: str, out_path: str, title: str, command: st
     lines = [f"# {title}", "", f"command: {command}", "",
              f"{'kernel':36s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>11s} {'pct':>6s}"]
     for r in rows:
-        name = r["Name"].replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")
-        name = name.split("::")[-1][:36]
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        name = name.replace("mphx::", "").replace("HIP_vector_type<unsigned int, 2u>", "uint2")[:36]
         lines.append(f"{name:36s} {r['Calls']:>6s} {int(r['TotalDurationNs']) / 1e6:10.3f} "
                      f"{float(r['AverageNs']) / 1e3:11.2f} {float(r['Percentage']):6.2f}")
     with open(out_path, "w") as fh:
