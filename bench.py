@@ -473,8 +473,13 @@ def main() -> int:
         mx.set_option(key, int(value))
         options[key] = int(value)
     ceilings = ceilings_leg(mx, torch) if "ceilings" in legs else None
-    if "plain" not in legs:
-        print(json.dumps({"ceilings": ceilings}), flush=True)
+    if "plain" not in legs:  # side legs only: no headline line
+        side = {"ceilings": ceilings}
+        if "batched" in legs:
+            side["batched"] = batched_leg(args, mx, torch, np, workloads)
+        if "served" in legs:
+            side["served"] = served_leg(args, mx, torch, np, workloads)
+        print(json.dumps(side), flush=True)
         return 0
 
     # ---- inputs, generated on the device before timing --------------------------------------

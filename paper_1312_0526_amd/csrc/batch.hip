@@ -146,6 +146,57 @@ __device__ __forceinline__ uint32_t block_append(uint32_t* counter, bool want1, 
     return base + lanes_below(b1) + lanes_below(b2);
 }
 
+// In-place exclusive scan of count <= kBatchMaxBuckets LDS words; returns the total.
+template <int kBlock>
+__device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t count, uint32_t* wtot)
+{
+    const uint32_t per = (count + kBlock - 1) / kBlock;
+    const uint32_t b0 = threadIdx.x * per, b1 = min(b0 + per, count);
+    uint32_t sum = 0;
+    for (uint32_t j = b0; j < b1; j++)
+        sum += a[j];
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t incl = sum;
+    for (uint32_t d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(incl, d, kWave);
+        if (lane >= d)
+            incl += y;
+    }
+    if (lane == kWave - 1)
+        wtot[w] = incl;
+    __syncthreads();
+    uint32_t pre = 0, total = 0;
+    for (uint32_t q = 0; q < kBlock / kWave; q++) {
+        pre += q < w ? wtot[q] : 0u;
+        total += wtot[q];
+    }
+    pre += incl - sum;
+    for (uint32_t j = b0; j < b1; j++) {
+        const uint32_t x = a[j];
+        a[j] = pre;
+        pre += x;
+    }
+    __syncthreads();
+    return total;
+}
+
+// The partitioned record build works on tiles of kBatchTile vertices (64 KiB of records in
+// LDS) and parts of at most kBatchMaxBuckets tiles; larger parts fall back to atomics.
+constexpr uint32_t kBatchTile = 8192;
+constexpr uint32_t kBatchMaxBuckets = 2048;
+
+// Part-k local vertex of key i: recomputed from a u64 key, read from the stored edge else.
+__device__ __forceinline__ uint32_t bucket_local(const BucketDesc& d, const SlotLayout& L, uint32_t i, uint64_t sd,
+                                                 uint64_t P, uint32_t k)
+{
+    if (d.keys) {
+        const uint64_t s = d.keys[i] ^ sd;
+        return (uint32_t)range_reduce(fin(s + (uint64_t)(k + 1) * kGamma), P);
+    }
+    const uint3 ev = L.edges[i];
+    return (k == 0 ? ev.x : (k == 1 ? ev.y : ev.z)) - (uint32_t)(k * P);
+}
+
 // Edge of key i of a bucket: recomputed for u64 keys, stored for string keys.
 __device__ __forceinline__ uint3 bucket_edge(const BucketDesc& d, const SlotLayout& L, uint32_t i, uint64_t sd,
                                              uint64_t P)
@@ -172,7 +223,11 @@ template <int kBlock, int kScope>
 __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* slot)
 {
     using S = Sc<kScope>;
-    __shared__ uint32_t s_ltail, s_err;
+    __shared__ uint32_t s_ltail, s_err, s_degsum;
+    __shared__ uint32_t s_cnt[kBatchMaxBuckets], s_bnd[kBatchMaxBuckets + 1], s_wtot[kBlock / kWave];
+    __shared__ unsigned long long s_tab[kBatchTile];
+    if (threadIdx.x == 0)
+        s_degsum = 0;
     const uint32_t tid = threadIdx.x;
     if (d.n > a.max_n) {  // larger than the slots were sized for: report, touch nothing
         if (tid == 0)
@@ -193,53 +248,146 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
     uint64_t sd = d.seed;
     for (t = 0; t < a.max_tries; t++) {
         sd = d.seed + t;
-        for (uint32_t v = tid; v < m; v += kBlock)
-            L.rec[v] = 0;
         for (uint32_t e = tid; e < n; e += kBlock)
             L.state[e] = kUnclaimed;
         if (tid == 0) {
             s_ltail = 0;
             s_err = 0;
         }
-        __syncthreads();
-        // hash + records (AddEdge at the three vertices)
         const uint64_t sa = fin(sd + kGamma), sb = fin(sd + 2 * kGamma);
-        for (uint32_t i = tid; i < n; i += kBlock) {
-            uint3 ev;
-            if (d.keys) {
-                ev = bucket_edge(d, L, i, sd, P);
-            } else {
+        if (!d.keys) {  // string keys: digest once, keep the edges
+            for (uint32_t i = tid; i < n; i += kBlock) {
                 uint64_t o0 = d.offs[i], o1 = d.offs[i + 1], ha, hb;
                 digest_str(d.bytes, o0, o1 - o0, total, sa, sb, ha, hb);
+                uint3 ev;
                 edge_of_digest(ha, hb, P, ev.x, ev.y, ev.z);
                 L.edges[i] = ev;
             }
-            uint32_t dg = S::rec_add(L.rec, ev.x, i);
-            dg = max(dg, S::rec_add(L.rec, ev.y, i));
-            dg = max(dg, S::rec_add(L.rec, ev.z, i));
-            if (dg >= kMaxDegree)
-                s_err = 1;
+        }
+        __syncthreads();
+        const uint32_t nbk = (uint32_t)((P + kBatchTile - 1) / kBatchTile);
+        if (nbk <= kBatchMaxBuckets) {
+            // Records part by part without device atomics: the part's (vertex, key) pairs are
+            // grouped by tile of kBatchTile vertices (LDS counts, one scatter into the slot
+            // area), each tile accumulated in LDS and written once.  Round 0 rides along: a
+            // vertex of degree 1 in part k claims its edge unless a lower part already did, so
+            // the hinge is the lowest part and each edge enters layer 0 once.
+            // The slot area (12n bytes) holds the pairs (8n) and, behind them, layer 0 (4n).
+            uint2* pairs = reinterpret_cast<uint2*>(L.slots);
+            uint32_t* stage = reinterpret_cast<uint32_t*>(pairs + n);
+            for (uint32_t k = 0; k < 3; k++) {
+                for (uint32_t b = tid; b < nbk; b += kBlock)
+                    s_cnt[b] = 0;
+                __syncthreads();
+                for (uint32_t i = tid; i < n; i += kBlock)
+                    atomicAdd(&s_cnt[bucket_local(d, L, i, sd, P, k) / kBatchTile], 1u);
+                __syncthreads();
+                lds_exclusive_scan<kBlock>(s_cnt, nbk, s_wtot);
+                for (uint32_t b = tid; b < nbk; b += kBlock)
+                    s_bnd[b] = s_cnt[b];
+                if (tid == 0)
+                    s_bnd[nbk] = n;
+                __syncthreads();
+                for (uint32_t i = tid; i < n; i += kBlock) {
+                    const uint32_t u = bucket_local(d, L, i, sd, P, k);
+                    const uint32_t pos = atomicAdd(&s_cnt[u / kBatchTile], 1u);
+                    pairs[pos] = make_uint2(u % kBatchTile, i);
+                }
+                __syncthreads();
+                uint32_t degsum = 0;
+                for (uint32_t b = 0; b < nbk; b++) {
+                    for (uint32_t v = tid; v < kBatchTile; v += kBlock)
+                        s_tab[v] = 0;
+                    __syncthreads();
+                    for (uint32_t j = s_bnd[b] + tid; j < s_bnd[b + 1]; j += kBlock) {
+                        const uint2 pr = pairs[j];
+                        atomicAdd(&s_tab[pr.x], (unsigned long long)(Rec::kOne + pr.y));
+                    }
+                    __syncthreads();
+                    const uint64_t v0 = (uint64_t)b * kBatchTile;
+                    const uint32_t cnt = (uint32_t)min<uint64_t>(kBatchTile, P - v0);
+                    for (uint32_t base = 0; base < cnt; base += kBlock) {
+                        const uint32_t v = base + tid;
+                        bool first = false;
+                        uint32_t e = 0;
+                        if (v < cnt) {
+                            const uint64_t x = s_tab[v];
+                            const uint32_t dg = Rec::deg(x);
+                            degsum += dg;
+                            if (dg > kMaxDegree)
+                                s_err = 1;
+                            L.rec[(uint64_t)k * P + v0 + v] = x;
+                            if (dg == 1 && Rec::edge(x) < n) {
+                                e = Rec::edge(x);
+                                first = k == 0 || L.state[e] == kUnclaimed;
+                                if (first)
+                                    L.state[e] = k;
+                            }
+                        }
+                        const uint32_t pos = block_append(&s_ltail, first, false);
+                        if (first && pos < n)  // more only from wrapped records, flagged below
+                            stage[pos] = e;
+                    }
+                    __syncthreads();
+                }
+                // every degree field at most 255 and their total n (no field wrapped)
+                if (degsum)
+                    atomicAdd(&s_degsum, degsum);
+                __syncthreads();
+                if (tid == 0) {
+                    if (s_degsum != n)
+                        s_err = 1;
+                    s_degsum = 0;
+                }
+                __syncthreads();
+            }
+            // Layer 0 moves to the front of the slots.  Slot j overwrites staged entries at
+            // most j, so a block-wide chunk is read in full before any of it is written.
+            const uint32_t l0 = min(s_ltail, n);
+            for (uint32_t base = 0; base < l0; base += kBlock) {
+                const uint32_t j = base + tid;
+                const uint32_t e = j < l0 ? stage[j] : 0u;
+                __syncthreads();
+                if (j < l0)
+                    L.slots[j].x = e;
+                __syncthreads();
+            }
+        } else {
+            // very large bucket: records with device atomics, round 0 with atomicMin
+            for (uint32_t v = tid; v < m; v += kBlock)
+                L.rec[v] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += kBlock) {
+                const uint3 ev = bucket_edge(d, L, i, sd, P);
+                uint32_t dg = S::rec_add(L.rec, ev.x, i);
+                dg = max(dg, S::rec_add(L.rec, ev.y, i));
+                dg = max(dg, S::rec_add(L.rec, ev.z, i));
+                if (dg >= kMaxDegree)
+                    s_err = 1;
+            }
+            __syncthreads();
+            if (!s_err) {
+                for (uint32_t base = 0; base < m; base += kBlock) {
+                    uint32_t v = base + tid;
+                    bool first = false;
+                    uint32_t e = 0;
+                    if (v < m) {
+                        uint64_t x = S::ld(L.rec + v);
+                        if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
+                            e = Rec::edge(x);
+                            first = S::fetch_min(L.state + e, part_of(v, P)) == kUnclaimed;
+                        }
+                    }
+                    uint32_t pos = block_append(&s_ltail, first, false);
+                    if (first)
+                        L.slots[pos].x = e;
+                }
+            }
         }
         __syncthreads();
         if (s_err) {
             status = -2;  // degree above 255: no seed helps a duplicate-heavy bucket
             break;
-        }
-        // round 0: every degree-1 vertex claims its edge; first claimers fill layer 0
-        for (uint32_t base = 0; base < m; base += kBlock) {
-            uint32_t v = base + tid;
-            bool first = false;
-            uint32_t e = 0;
-            if (v < m) {
-                uint64_t x = S::ld(L.rec + v);
-                if (Rec::deg(x) == 1 && Rec::edge(x) < n) {
-                    e = Rec::edge(x);
-                    first = S::fetch_min(L.state + e, part_of(v, P)) == kUnclaimed;
-                }
-            }
-            uint32_t pos = block_append(&s_ltail, first, false);
-            if (first)
-                L.slots[pos].x = e;
         }
         if (tid == 0)
             L.lstart[0] = 0;

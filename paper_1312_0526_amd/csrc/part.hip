@@ -499,9 +499,10 @@ hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count
     return partition_then(
         Records{st.claims}, count, gsh, NH, hist1, st.claims_tmp, st.claims, L, base,
         [&](const uint32_t* ginfo, const uint32_t* off2) {
-            int dev = 0, cus = 256;
-            if (hipGetDevice(&dev) == hipSuccess)
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                cus = 256;
             const uint64_t grid = std::min<uint64_t>(nb, (uint64_t)kResGridPerCU * (uint64_t)std::max(cus, 1));
             k_claims_resolve<<<(unsigned)grid, kResBlock, 0, s>>>(st.claims, ginfo, NH, off2, count, (uint32_t)nb,
                                                                 st.slots, st.lstart, st.lcount, r, st.ctrl);
