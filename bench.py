@@ -56,15 +56,22 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
         # every edge read once, every 8 B vertex record written once
         return 12 * n + 8 * m
     lists = st.get("lists", False)
+    U, T = st.get("update_deletes", 0), st.get("update_records", 0)
     if phase == "frontier":
         # round 0: every record read; per degree-1 vertex an edge-state RMW (8 B) and at most
-        # one 4 B layer append; with claim lists an 8 B claim written and read back
-        return 8 * m + (16 if lists else 12) * F0
+        # one 4 B layer append; with claim lists, the hinge test instead: the edge's lower-part
+        # vertices (about 4 B) and their records (about 8 B), and an 8 B layer entry
+        return 8 * m + (20 if lists else 12) * F0
     if phase == "apply":
         # per edge: slot read 8 (edge + hinge, or edge + state read) + edge read 12 + slot
-        # write 12, two record RMW (16 B each); per vertex taken to degree 1: an edge-state
+        # write 12; per delete a record RMW (16 B), or an 8 B update-list entry in rounds that
+        # use update lists; per vertex taken to degree 1 by an atomic delete: an edge-state
         # RMW 8 + at most one 4 B append, or one 8 B claim written
-        return 64 * n + (8 if lists else 12) * (F - F0)
+        return 32 * n + 16 * (2 * n - U) + 8 * U + (8 if lists else 12) * (F - F0)
+    if phase == "update":
+        # update lists: every delete read back once (8 B), every record it changes read and
+        # written once (16 B)
+        return 8 * U + 16 * T
     if phase == "resolve":
         # claims of rounds 1.. read back (8 B each); per layer edge its state (4 B) and layer
         # entry (8 B) written
@@ -86,6 +93,7 @@ PHASE_KERNELS = {
     "frontier": ("k_round0",),
     "apply": ("k_apply",),
     "resolve": ("k_claims_resolve",),
+    "update": ("k_update_accum",),
     "assign": ("k_assign_round",),
 }
 PHASE_SOURCES = {
@@ -94,6 +102,7 @@ PHASE_SOURCES = {
     "frontier": ("peel.hip", "part.hip", "scan.hip"),
     "apply": ("peel.hip",),
     "resolve": ("part.hip", "scan.hip"),
+    "update": ("part.hip", "scan.hip"),
     "assign": ("solve.hip",),
 }
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "hbm_counters_{workload}.json")
@@ -309,14 +318,17 @@ def random_ops(phase: str, st: dict) -> dict:
     larger than the caches), the count its measured ceiling applies to."""
     n, F, F0 = st["n"], st["frontier_total"], st["frontier0"]
     lists = st.get("lists", False)
+    U = st.get("update_deletes", 0)
     if phase == "apply":
         # per edge: edge-triple gather (and the state, without claim lists), two returning
-        # deletes; per vertex taken to degree 1: one atomicMin claim without claim lists
+        # deletes unless they went to an update list; per vertex taken to degree 1: one
+        # atomicMin claim without claim lists
         if lists:
-            return dict(atomics=2 * n, loads=n)
+            return dict(atomics=2 * n - U, loads=n)
         return dict(atomics=2 * n + (F - F0), loads=2 * n)
     if phase == "frontier":
-        return dict(atomics=0 if lists else F0, loads=0)
+        # with claim lists the hinge test gathers the lower-part vertices and their records
+        return dict(atomics=0, loads=F0) if lists else dict(atomics=F0, loads=0)
     if phase == "assign":
         return dict(atomics=0, loads=2 * n, stores=n)
     return {}
@@ -530,7 +542,8 @@ def main() -> int:
 
     lists_from = mx.get_option("claim_lists")
     st = dict(n=n, m=m, kind=cfg["kind"], key_bytes=key_bytes, frontier_total=r["frontier_total"],
-              frontier0=r["frontier0"], claims=r["claims"], lists=lists_from > 0 and n >= (1 << lists_from))
+              frontier0=r["frontier0"], claims=r["claims"], lists=lists_from > 0 and n >= (1 << lists_from),
+              update_deletes=r["update_deletes"], update_records=r["update_records"])
     phase_rows = {}
     for name, (ms, launches) in phases.items():
         if launches == 0:

@@ -76,6 +76,8 @@ typedef struct mphx_mphf_info {
     uint64_t frontier_total; /* last try: frontier entries over all rounds */
     uint64_t claims;         /* last try: (vertex, edge) claims over all rounds */
     uint64_t frontier0;      /* last try: vertices of degree 1 before round 0 */
+    uint64_t update_deletes; /* last try: deletes applied through update lists */
+    uint64_t update_records; /* last try: vertex records those deletes changed */
 } mphx_mphf_info;
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -343,11 +345,18 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 device atomic per claim, and reads one count back per round.  0 = never.
  *                 The same codes either way; the workspace grows by 16 bytes per vertex, so
  *                 query mphx_mphf_workspace_bytes after setting it.
+ *   "update_lists" p in 0..100 (default 16): in a claim-list build, a round whose claim count
+ *                 c has 2c >= p% of the vertex count (and 2c <= m) deletes its layer through
+ *                 a degree update list -- one (vertex, edge) record per delete, radix-
+ *                 partitioned by vertex and applied per bucket of 2^14 records in LDS, the
+ *                 sort-based round update of Section 4.2 -- instead of device atomics; the
+ *                 claims of the next round then come from the updated records.  0 = never.
+ *                 The same codes either way.
  * Returns MPHX_EINVAL for an unknown key or value.
  *
  * mphx_phase_times copies the accumulated per-phase kernel time (ms) and launch counts of
- * the calling thread (phases: hash, build, frontier, apply, resolve, assign, rank, order, other;
- * mphx_phase_name(i) names phase i) and optionally resets them; returns the number of
+ * the calling thread (phases: hash, build, frontier, apply, resolve, assign, rank, order, other,
+ * update; mphx_phase_name(i) names phase i) and optionally resets them; returns the number of
  * phases.
  * --------------------------------------------------------------------------------------- */
 MPHX_API int mphx_set_option(const char* key, int64_t value);

@@ -34,7 +34,8 @@ class PeelInfo(C.Structure):
 class MphfInfo(C.Structure):
     _fields_ = [("P", C.c_uint64), ("m", C.c_uint64), ("seed_used", C.c_uint64), ("tries", C.c_uint32),
                 ("n_rounds", C.c_uint32), ("n_core", C.c_uint64), ("frontier_total", C.c_uint64),
-                ("claims", C.c_uint64), ("frontier0", C.c_uint64)]
+                ("claims", C.c_uint64), ("frontier0", C.c_uint64), ("update_deletes", C.c_uint64),
+                ("update_records", C.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -23,6 +23,8 @@ struct Options {
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
     std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
     std::atomic<int> claim_lists{28};  // claim lists from n >= 2^claim_lists keys on (0 = never)
+    std::atomic<int> update_lists{16}; // claim-list rounds with 2 * layer >= m * update_lists / 100
+                                       // delete through a sorted update list (0 = never)
 };
 
 Options g_opt;
@@ -34,9 +36,11 @@ bool use_claim_lists(uint64_t n)
 }
 
 // ---- per-phase timing (HIP events on the caller's stream) ---------------------------------
-enum Phase { PH_HASH, PH_BUILD, PH_FRONTIER, PH_APPLY, PH_RESOLVE, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_COUNT };
+enum Phase {
+    PH_HASH, PH_BUILD, PH_FRONTIER, PH_APPLY, PH_RESOLVE, PH_ASSIGN, PH_RANK, PH_ORDER, PH_OTHER, PH_UPDATE, PH_COUNT
+};
 const char* const kPhaseNames[PH_COUNT] = {"hash",   "build", "frontier", "apply", "resolve",
-                                           "assign", "rank",  "order",    "other"};
+                                           "assign", "rank",  "order",    "other", "update"};
 
 struct Timers {
     struct Span { int phase; hipEvent_t a, b; };
@@ -172,6 +176,7 @@ struct MphfLayout {
     void* aux;               // histograms and scan scratch of the partitions
     uint2 *claims, *claims_tmp;  // claim lists (m each), when used
     unsigned long long* ccount;  // claim counts per round
+    unsigned long long* dcount;  // update-list counts per round
     void* scan;
     size_t scan_bytes;
 };
@@ -192,7 +197,8 @@ void layout_mphf(Carve& c, uint64_t n, uint64_t m, bool lists, MphfLayout& L)
     L.pairs1 = reinterpret_cast<uint2*>(region);
     L.pairs2 = reinterpret_cast<uint2*>(region ? region + 8 * n : nullptr);
     L.aux = c.take<uint8_t>(part_aux_bytes(n, m / 3, lists));
-    L.ccount = c.take<unsigned long long>(rcap + 2);
+    L.ccount = c.take<unsigned long long>(2 * (rcap + 2));
+    L.dcount = L.ccount ? L.ccount + rcap + 2 : nullptr;
     L.claims = lists ? c.take<uint2>(m) : nullptr;
     L.claims_tmp = lists ? c.take<uint2>(m) : nullptr;
     uint64_t nblocks = (m + 511) / 512;
@@ -234,7 +240,7 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
         st.grid_cap = auto_grid(next_layer);
         for (; r < upto; r++) {
             Timed t(PH_APPLY, s);
-            HIP_TRY(launch_apply(st, r, false, false, s));
+            HIP_TRY(launch_apply(st, r, false, ApplyMode::kAtomicClaims, s));
         }
         HIP_TRY(hipMemcpyAsync(&next_layer, st.lcount + r, sizeof next_layer, hipMemcpyDeviceToHost, s));
         int rc = read_ctrl(st.ctrl, h, s);
@@ -259,8 +265,16 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
 // per round sizes the resolve.  A round whose list resolves to nothing ends the peel.
 constexpr int kListOverflow = 1000;  // internal: a round's records exceeded the claim list
 
+// Claim-list rounds.  Round r's layer comes from round r - 1's claims (resolve), then
+// apply(r) deletes it.  A dense round -- twice its claim count, which bounds its deletes, at
+// least update_lists percent of m -- appends its deletes to an update list applied per vertex
+// bucket (Section 4.2's sort-based round update), which leaves the next claims in
+// st.claims_tmp; a sparse round deletes with atomics and appends claims and cancels to
+// st.claims.
 int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
 {
+    const uint64_t upd = (uint64_t)g_opt.update_lists.load();
+    bool in_tmp = false;  // round r's claims sit in st.claims_tmp
     for (uint32_t r = 0;; r++) {
         if (r > st.rcap)
             return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
@@ -271,15 +285,28 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
             if (est > st.m)
                 return kListOverflow;  // the list holds m records; no layer of a large random graph comes near
             Timed t(PH_RESOLVE, s);
-            HIP_TRY(launch_claims_resolve(st, r, est, s));
+            HIP_TRY(launch_claims_resolve(st, r, est, in_tmp, s));
         } else {
             HIP_TRY(hipMemcpyAsync(&est, st.lcount, sizeof est, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
         }
         st.grid_cap = auto_grid(est);  // the records bound the layer
+        // a layer of at most est edges deletes at most 2 est times, which the list must hold
+        const bool updates = upd > 0 && 2 * est <= st.m && 200 * (unsigned __int128)est >= (unsigned __int128)upd * st.m;
         {
             Timed t(PH_APPLY, s);
-            HIP_TRY(launch_apply(st, r, r > 0, true, s));
+            HIP_TRY(launch_apply(st, r, true, updates ? ApplyMode::kUpdateList : ApplyMode::kClaimList, s));
+        }
+        in_tmp = false;
+        if (updates) {
+            unsigned long long dels = 0;
+            HIP_TRY(hipMemcpyAsync(&dels, st.dcount + r, sizeof dels, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (dels > st.m)
+                return fail(MPHX_ERANGE, "update list of round %u overflowed (%llu deletes)", r, dels);
+            Timed t(PH_UPDATE, s);
+            HIP_TRY(launch_update_apply(st, r, dels, s));
+            in_tmp = true;
         }
         if (est == 0)
             break;
@@ -339,6 +366,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "claim_lists")) {
         if (value < 0 || value > 32) return fail(MPHX_EINVAL, "claim_lists must be in 0..32");
         g_opt.claim_lists = (int)value;
+    } else if (!strcmp(key, "update_lists")) {
+        if (value < 0 || value > 100) return fail(MPHX_EINVAL, "update_lists must be in 0..100");
+        g_opt.update_lists = (int)value;
     } else {
         return fail(MPHX_EINVAL, "unknown option '%s'", key);
     }
@@ -353,6 +383,7 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "timing")) return g_opt.timing;
     if (!strcmp(key, "part_build")) return g_opt.part_build;
     if (!strcmp(key, "claim_lists")) return g_opt.claim_lists;
+    if (!strcmp(key, "update_lists")) return g_opt.update_lists;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
@@ -592,6 +623,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     st.claims = L.claims;
     st.claims_tmp = L.claims_tmp;
     st.ccount = L.ccount;
+    st.dcount = L.dcount;
     st.aux = L.aux;
 
     Ctrl h{};
@@ -604,7 +636,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         if (!part)
             HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
         HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
-        HIP_TRY(launch_zero(L.ccount, (st.rcap + 2) * sizeof(unsigned long long), s));
+        HIP_TRY(launch_zero(L.ccount, 2 * (st.rcap + 2) * sizeof(unsigned long long), s));
         HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
         {
             // with the partitioned build the hash only writes the edges
@@ -620,7 +652,10 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             Timed tm(PH_BUILD, s);
             HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, s));
         }
-        HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));  // after the build: it shares the pair buffers
+        // atomic claims keep per-edge states (after the build: they share the pair buffers);
+        // claim lists carry the hinge in the layer slots from round 0 on
+        if (!st.lists)
+            HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
         {
             Timed tm(PH_FRONTIER, s);
             HIP_TRY(launch_round0(st, s));
@@ -646,6 +681,8 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             info->frontier_total = h.ftail;
             info->claims = h.claims;
             info->frontier0 = f0;
+            info->update_deletes = h.updates;
+            info->update_records = h.touched;
         }
         if (peeled == n) {
             done = true;
@@ -830,6 +867,7 @@ int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_
 namespace {
 
 static_assert(sizeof(mphx_bucket_result) == sizeof(BucketResult), "bucket result layouts agree");
+static_assert(sizeof(mphx_mphf_info) == 80 && sizeof(mphx_peel_info) == 40, "info layouts as documented");
 static_assert(sizeof(mphx_bucket) == sizeof(BucketDesc), "bucket descriptor layouts agree");
 
 int batch_tuning(const mphx_batch_tuning* t, unsigned& block, unsigned& grid)

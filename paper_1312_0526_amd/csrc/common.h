@@ -25,7 +25,9 @@ struct Ctrl {
     unsigned long long aux;    // scratch counter (bijection check)
     unsigned long long claims; // (vertex, edge) claims made over all rounds
     unsigned long long degsum; // sum of all degree fields (overflow check: must be 3n)
-    uint64_t pad[26];
+    unsigned long long updates;  // deletes applied through update lists
+    unsigned long long touched;  // records those deletes changed
+    uint64_t pad[24];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte slot");
 

@@ -29,6 +29,11 @@ struct PeelState {
     uint2* claims;          // m (edge, position) claims of one round
     uint2* claims_tmp;      // m, the partition's other buffer
     unsigned long long* ccount;  // rcap + 2 claim counts: ccount[r] = claims that form layer r
+    // Sorted update lists (dense rounds of a claim-list run): apply(r) appends one (vertex,
+    // edge) delete per non-hinge vertex to st.claims instead of deleting with atomics; the
+    // list is partitioned by vertex and applied bucket by bucket in LDS, which also yields
+    // the next round's claims (into st.claims_tmp).
+    unsigned long long* dcount;  // rcap + 2 update counts: dcount[r] = deletes of round r
     void* aux;              // partition histograms and scan scratch (part_aux_bytes)
 };
 
@@ -97,11 +102,17 @@ PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P);
 // the hashing kernel has filled the first-pass histograms (part_hist1)
 hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
                              uint2* pairs2, void* aux, hipStream_t s);
-// Layer r from the count claims in st.claims (ccount[r] of them, known to the host): the
-// claims are partitioned by edge, stale ones (edge already in a layer) dropped, each edge's
-// lowest claimed position kept as its hinge; winners set state and fill layer r's slots
-// (edge, hinge) through lcount[r].
-hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s);
+// Layer r from the count claims of round r - 1 (ccount[r] of them, known to the host), held in
+// st.claims, or in st.claims_tmp when round r - 1 used update lists (in_tmp): the claims are
+// partitioned by edge, cancelled ones dropped, each edge's lowest claimed position kept as its
+// hinge; each winner fills a slot of layer r, (edge, hinge | positions at degree 1 << 8),
+// through lcount[r].
+hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count, bool in_tmp, hipStream_t s);
+// Round r's count deletes (vertex, edge) in st.claims, appended by apply(r) in update mode:
+// partitioned by vertex into buckets of 2^14 records, each bucket's deletes summed in LDS and
+// subtracted from its records once; a record left at degree 1 claims its last edge for round
+// r + 1 into st.claims_tmp through ccount[r + 1].
+hipError_t launch_update_apply(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s);
 
 // hashing and key generation (keys.hip); rec == nullptr hashes only
 // h1.hist != nullptr (with rec == nullptr): also count the first-pass partition digits
@@ -119,10 +130,16 @@ hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
 // peeling (peel.hip)
 hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl,
                               hipStream_t s);
+// Round 0: layer 0 from the degree-1 vertices -- atomicMin claims on the edge states, or with
+// st.lists the hinge test on the records, which leaves (edge, hinge) in the slots.
 hipError_t launch_round0(const PeelState& st, hipStream_t s);
-// hinge_in_slot: layer r came from a resolved claim list; list_claims: append the next
-// layer's claims to st.claims (tripartite only) instead of claiming with atomics
-hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, bool list_claims, hipStream_t s);
+// How apply(r) deletes layer r and finds round r + 1: atomic deletes with atomicMin claims on
+// the edge states; atomic deletes with claims appended to st.claims (tripartite only); or
+// deletes appended to st.claims as an update list (tripartite only), applied afterwards by
+// launch_update_apply.
+enum class ApplyMode { kAtomicClaims, kClaimList, kUpdateList };
+// hinge_in_slot: layer r came from a resolved claim list
+hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, ApplyMode mode, hipStream_t s);
 hipError_t launch_peel_finalize(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask,
                                 uint8_t* hinge, hipStream_t s);
 uint64_t sort_tiles(uint64_t n);

@@ -28,7 +28,7 @@ namespace {
 
 constexpr uint32_t kVxShift = 14;            // vertex buckets: 2^14 records = 128 KiB of LDS
 constexpr uint32_t kClShift = 16;            // claim buckets: 2^16 edges, a byte each = 64 KiB
-constexpr uint32_t kMaxGroups = kPartMaxGroups;
+constexpr uint32_t kMaxGroups = 1024;        // first-pass digits: m >> kPartGrpShift < 1024 for m < 2^32
 constexpr uint32_t kDigits = 256;            // second-pass digit: (key >> bucket shift) & 255
 constexpr uint32_t kPtBlock = 512;           // two blocks per CU: one loads while the other writes
 constexpr uint32_t kPtPer = 16;
@@ -36,13 +36,17 @@ constexpr uint32_t kPtTile = kPtBlock * kPtPer;
 constexpr uint32_t kWaves = kPtBlock / kWave;
 constexpr uint32_t kAccBlock = 1024;
 constexpr uint32_t kResBlock = 512;
+constexpr uint32_t kUpdPer = (1u << kVxShift) / kAccBlock;  // records per thread of an update bucket
 
 static_assert(kVxShift + 8 == kPartGrpShift, "a vertex group holds 256 buckets");
 static_assert(kPtTile == kPartTile, "first-pass tiles are the hashing kernels' tiles");
 static_assert(kPtBlock >= kDigits, "one thread per digit");
 static_assert(2 * kPtBlock >= kMaxGroups, "two groups per thread at most");
+static_assert(kPartMaxGroups <= kMaxGroups, "the hashing kernels' digits fit the group tables");
 
-// Exclusive prefix over the block (one value per thread); wtot is kWaves words of LDS.
+// Exclusive prefix over a block of kB threads (one value per thread); wtot is kB / 64 words
+// of LDS.
+template <uint32_t kB = kPtBlock>
 __device__ uint32_t block_exclusive(uint32_t x, uint32_t* wtot)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -308,6 +312,86 @@ __global__ __launch_bounds__(kAccBlock) void k_part_accum(const uint2* __restric
         dst[j] = lrec[j];
 }
 
+// ---- one round's update list applied per bucket of 2^14 vertices ---------------------------
+// The bucket's deletes (vertex v, edge e) are summed per vertex in LDS -- degree and label sum
+// are both additive -- and each touched record is read, reduced by its sum and written back
+// once.  A record left at degree 1 had at least two edges when the round began, so its last
+// edge is alive and not in this round's layer (an edge of the layer that had it as a non-hinge
+// vertex sent a delete here, and it cannot be that edge's hinge, whose degree was 1): the
+// record claims that edge for the next round, from its part.  A record left at 0 needs nothing.
+__global__ __launch_bounds__(kAccBlock) void k_update_accum(const uint2* __restrict__ in,
+                                                           const uint32_t* __restrict__ ginfo, uint32_t NH,
+                                                           const uint32_t* __restrict__ off2, uint64_t count,
+                                                           uint64_t m, uint64_t P, uint64_t* __restrict__ rec,
+                                                           uint2* __restrict__ claims, uint64_t ccap,
+                                                           unsigned long long* __restrict__ ccount, Ctrl* ctrl)
+{
+    __shared__ unsigned long long tab[1u << kVxShift];
+    __shared__ uint32_t wtot[kAccBlock / kWave];
+    __shared__ unsigned long long s_base;
+    constexpr uint32_t kMask = (1u << kVxShift) - 1;
+    const GroupInfo g(ginfo);
+    const uint32_t b = blockIdx.x;
+    const uint64_t lo = bucket_start(g, off2, NH, count, b);
+    const uint64_t hi = bucket_start(g, off2, NH, count, b + 1);
+    if (lo == hi)
+        return;  // uniform per block
+    for (uint32_t j = threadIdx.x; j < (1u << kVxShift); j += kAccBlock)
+        tab[j] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kAccBlock) {
+        const uint2 d = in[i];
+        atomicAdd(&tab[d.x & kMask], (unsigned long long)(Rec::kOne + d.y));
+    }
+    __syncthreads();
+    // Each thread takes kUpdPer records, kAccBlock apart (coalesced), and has all their loads
+    // in flight before it uses any; one device atomic places the bucket's claims.
+    const uint64_t v0 = (uint64_t)b << kVxShift;
+    const uint32_t cnt = (uint32_t)min<uint64_t>(1u << kVxShift, m - v0);
+    unsigned long long d[kUpdPer];
+    uint64_t x[kUpdPer];
+#pragma unroll
+    for (uint32_t q = 0; q < kUpdPer; q++) {
+        const uint32_t j = q * kAccBlock + threadIdx.x;
+        d[q] = j < cnt ? tab[j] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kUpdPer; q++)
+        x[q] = d[q] ? rec[v0 + q * kAccBlock + threadIdx.x] : 0ull;
+    uint32_t mine = 0, changed = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kUpdPer; q++) {
+        if (d[q]) {
+            changed++;
+            x[q] -= d[q];
+            rec[v0 + q * kAccBlock + threadIdx.x] = x[q];
+            mine += Rec::deg(x[q]) == 1 ? 1u : 0u;
+        }
+    }
+    // claims and changed records in one scan: claims in the low 16 bits (at most 2^14 each)
+    const uint32_t pre = block_exclusive<kAccBlock>(mine | changed << 16, wtot);
+    const uint32_t rank = pre & 0xFFFFu;
+    if (threadIdx.x == kAccBlock - 1) {
+        const uint32_t total = rank + mine, all = (pre >> 16) + changed;
+        s_base = total ? atomicAdd(ccount, (unsigned long long)total) : 0ull;
+        if (total)
+            atomicAdd(&ctrl->ftail, (unsigned long long)total);
+        atomicAdd(&ctrl->updates, (unsigned long long)(hi - lo));
+        atomicAdd(&ctrl->touched, (unsigned long long)all);
+    }
+    __syncthreads();
+    uint64_t at = s_base + rank;
+#pragma unroll
+    for (uint32_t q = 0; q < kUpdPer; q++) {
+        if (d[q] && Rec::deg(x[q]) == 1) {
+            const uint32_t v = (uint32_t)(v0 + q * kAccBlock + threadIdx.x);
+            if (at < ccap)
+                claims[at] = make_uint2((uint32_t)Rec::edge(x[q]), part_of(v, P));
+            at++;
+        }
+    }
+}
+
 // ---- resolve one round's claims, bucket by bucket of 2^16 edges -----------------------------
 // Every record is (edge c, position p) -- a claim from c's vertex in part p -- or
 // (c, 4 | p) -- a cancel from the same vertex, which marks its claim stale (the vertex lost
@@ -418,6 +502,13 @@ AuxLayout claims_aux(uint64_t m, uint64_t n)
     return aux_layout((uint64_t)NH * tiles_of(m), m, NH);
 }
 
+// Update-list aux: up to m deletes keyed by vertex ids below m.
+AuxLayout updates_aux(uint64_t m)
+{
+    const uint32_t NH = groups_of(m, kPartGrpShift);
+    return aux_layout((uint64_t)NH * tiles_of(m), m, NH);
+}
+
 // Second pass + per-bucket kernel shared by both uses, after the first-pass scan.
 template <class Src, class Last>
 hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32_t* off1, uint2* mid, uint2* out,
@@ -448,7 +539,7 @@ size_t part_aux_bytes(uint64_t n, uint64_t P, bool lists)
 {
     size_t b = build_aux(n, P).total;
     if (lists)
-        b = std::max(b, claims_aux(3 * P, n).total);
+        b = std::max({b, claims_aux(3 * P, n).total, updates_aux(3 * P).total});
     return b;
 }
 
@@ -468,7 +559,7 @@ hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint
     uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
     const uint32_t NH = groups_of(P, kPartGrpShift);
     const uint64_t nt1 = tiles_of(n), nb = (P + (1ull << kVxShift) - 1) >> kVxShift;
-    if (NH > kMaxGroups || nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
+    if (NH > kPartMaxGroups || nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
     for (uint32_t k = 0; k < 3; k++) {
         uint32_t* off1 = hist1 + (uint64_t)k * NH * nt1;
         hipError_t err = partition_then(
@@ -483,7 +574,20 @@ hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint
     return hipSuccess;
 }
 
-hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s)
+namespace {
+
+unsigned resident_blocks(uint32_t per_cu)
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return per_cu * (unsigned)cus;
+}
+
+}  // namespace
+
+hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count, bool in_tmp, hipStream_t s)
 {
     if (count == 0) return hipSuccess;
     const uint32_t gsh = kClShift + 8;
@@ -493,19 +597,41 @@ hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count
     const uint32_t NH = groups_of(st.n, gsh);
     const uint64_t nt1 = tiles_of(count), nb = (st.n + (1ull << kClShift) - 1) >> kClShift;
     if (count > st.m || NH > kMaxGroups || nt1 > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{st.claims}, count, gsh, NH, nt1, hist1);
+    uint2* list = in_tmp ? st.claims_tmp : st.claims;
+    uint2* other = in_tmp ? st.claims : st.claims_tmp;
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{list}, count, gsh, NH, nt1, hist1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     return partition_then(
-        Records{st.claims}, count, gsh, NH, hist1, st.claims_tmp, st.claims, L, base,
+        Records{list}, count, gsh, NH, hist1, other, list, L, base,
         [&](const uint32_t* ginfo, const uint32_t* off2) {
-            int dev = 0, cus = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-                cus = 256;
-            const uint64_t grid = std::min<uint64_t>(nb, (uint64_t)kResGridPerCU * (uint64_t)std::max(cus, 1));
-            k_claims_resolve<<<(unsigned)grid, kResBlock, 0, s>>>(st.claims, ginfo, NH, off2, count, (uint32_t)nb,
+            const uint64_t grid = std::min<uint64_t>(nb, resident_blocks(kResGridPerCU));
+            k_claims_resolve<<<(unsigned)grid, kResBlock, 0, s>>>(list, ginfo, NH, off2, count, (uint32_t)nb,
                                                                 st.slots, st.lstart, st.lcount, r, st.ctrl);
+            return hipGetLastError();
+        },
+        s);
+}
+
+hipError_t launch_update_apply(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const AuxLayout L = updates_aux(st.m);
+    uint8_t* base = reinterpret_cast<uint8_t*>(st.aux);
+    uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
+    const uint32_t NH = groups_of(st.m, kPartGrpShift);
+    const uint64_t nt1 = tiles_of(count), nb = (st.m + (1ull << kVxShift) - 1) >> kVxShift;
+    if (count > st.m || NH > kMaxGroups || nt1 > 0x7FFFFFFFull || nb > 0x7FFFFFFFull || !st.tripartite)
+        return hipErrorInvalidValue;
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{st.claims}, count, kPartGrpShift, NH, nt1, hist1);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return partition_then(
+        Records{st.claims}, count, kPartGrpShift, NH, hist1, st.claims_tmp, st.claims, L, base,
+        [&](const uint32_t* ginfo, const uint32_t* off2) {
+            k_update_accum<<<(unsigned)nb, kAccBlock, 0, s>>>(st.claims, ginfo, NH, off2, count, st.m, st.P,
+                                                              st.rec, st.claims_tmp, st.m, st.ccount + r + 1,
+                                                              st.ctrl);
             return hipGetLastError();
         },
         s);

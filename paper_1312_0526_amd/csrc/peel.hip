@@ -24,7 +24,9 @@
 // edge: if that vertex reached degree 1 earlier in the same round, its claim named exactly
 // this edge, which leaves in this round, so the pair marks the claim stale.  The lists are
 // then resolved bucket by bucket in LDS (part.hip); a resolved layer carries its hinge in the
-// slot.
+// slot.  In a dense round apply(r) may instead append the deletes themselves (the degree update
+// list of the sort-based round update of Section 4.2), which part.hip applies per vertex
+// bucket.
 #include "common.h"
 #include "launch.h"
 
@@ -121,16 +123,78 @@ __global__ __launch_bounds__(kPeelBlock) void k_round0(const uint64_t* __restric
 }
 
 // ------------------------------------------------------------------------------------------
+// Round 0 of a claim-list run (tripartite), without atomics and without edge states: the
+// hinge of an edge is its lowest part at degree 1, so a degree-1 vertex of part k is the hinge
+// exactly when the edge's vertices in parts below k have higher degrees -- read from the edge
+// and from at most two records, all unchanged during the round.  The hinge alone appends the
+// edge to layer 0, in vertex order, as (edge, part).  Same degree checks as k_round0.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(kPeelBlock) void k_round0_lists(const uint64_t* __restrict__ rec, uint64_t m,
+                                                             const uint32_t* __restrict__ edges, uint64_t P,
+                                                             uint64_t n, uint3* __restrict__ slots,
+                                                             unsigned long long* __restrict__ lcount, Ctrl* ctrl)
+{
+    __shared__ ClaimListAppender app;
+    __shared__ unsigned long long s_deg, s_ones;
+    if (threadIdx.x == 0)
+        s_deg = s_ones = 0;
+    app.init();
+    auto out = [slots](uint64_t i, uint2 c) { slots[i] = make_uint3(c.x, c.y, 0u); };
+    unsigned long long mydeg = 0, myones = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const uint64_t v = base + threadIdx.x;
+        bool hinge = false;
+        uint32_t e = 0, k = 0;
+        if (v < m) {
+            const uint64_t x = rec[v];
+            const uint32_t d = Rec::deg(x);
+            mydeg += d;
+            if (d > kMaxDegree)
+                atomicOr(&ctrl->err, kErrDegree);
+            if (d == 1 && Rec::edge(x) < n) {
+                e = (uint32_t)Rec::edge(x);
+                k = part_of((uint32_t)v, P);
+                myones++;
+                hinge = true;
+                if (k > 0) {
+                    const uint32_t* t = edges + 3 * (uint64_t)e;
+                    const uint32_t u0 = t[0], u1 = k == 2 ? t[1] : 0u;
+                    const uint64_t x0 = u0 < m ? rec[u0] : 0ull;
+                    const uint64_t x1 = (k == 2 && u1 < m) ? rec[u1] : 0ull;
+                    hinge = Rec::deg(x0) != 1 && (k == 1 || Rec::deg(x1) != 1);
+                }
+            }
+        }
+        app.push(hinge, make_uint2(e, k), false, make_uint2(e, k), &lcount[0], out);
+    }
+    app.flush(&lcount[0], out);
+    if (mydeg) atomicAdd(&s_deg, mydeg);
+    if (myones) atomicAdd(&s_ones, myones);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_deg) atomicAdd(&ctrl->degsum, s_deg);
+        if (s_ones) {
+            atomicAdd(&ctrl->ftail, s_ones);
+            atomicAdd(&ctrl->claims, s_ones);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // Round r: delete layer r's edges and claim round r + 1.
 // ------------------------------------------------------------------------------------------
-template <bool kTri, bool kList>
+template <bool kTri, ApplyMode kMode>
 __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec, const uint32_t* __restrict__ edges,
                                                       uint32_t* __restrict__ state, uint3* __restrict__ slots,
                                                       uint64_t* __restrict__ lstart,
                                                       unsigned long long* __restrict__ lcount, uint2* __restrict__ claims,
-                                                      unsigned long long* __restrict__ ccount, uint64_t ccap,
+                                                      unsigned long long* __restrict__ ccount,
+                                                      unsigned long long* __restrict__ dcount, uint64_t ccap,
                                                       Ctrl* ctrl, uint32_t r, uint64_t P, bool hinge_in_slot)
 {
+    constexpr bool kList = kMode != ApplyMode::kAtomicClaims;
+    constexpr bool kUpdates = kMode == ApplyMode::kUpdateList;
     const uint64_t lo = lstart[r];
     const uint64_t hi = lo + lcount[r];  // final: appended before this launch
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -149,6 +213,11 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
     unsigned long long mypush = 0, myclaims = 0;
     const uint32_t rr = (r + 1) << 2;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    // list records past the capacity are counted, not stored; the host checks the count
+    unsigned long long* const tail = kUpdates ? &dcount[r] : &ccount[r + 1];
+    auto to_list = [claims, ccap](uint64_t j, uint2 c) {
+        if (j < ccap) claims[j] = c;
+    };
     for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
         uint64_t i = base + threadIdx.x;
         uint32_t c0 = 0, c1 = 0, p0 = 0, p1 = 0;
@@ -170,41 +239,51 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
             // a vertex that had degree 1 when the round began drops to 0 with this edge and is
             // never read again: its delete can be skipped (old degree reads as 1, no record)
             const uint32_t pa = h == 2 ? 0u : h + 1, pb = h == 0 ? 2u : h - 1;
-            uint64_t oa = ((ones >> pa) & 1u) ? Rec::kOne : Rec::del(rec, va, e);
-            uint64_t ob = ((ones >> pb) & 1u) ? Rec::kOne : Rec::del(rec, vb, e);
-            if (Rec::deg(oa) == 2) {
-                c0 = (uint32_t)(Rec::edge(oa) - e);
-                p0 = position_in<kTri>(edges, c0, va, P);
-                mypush++;
-                if constexpr (kList) {
+            if constexpr (kUpdates) {
+                // the deletes themselves go to the update list
+                f0 = !((ones >> pa) & 1u);
+                f1 = !((ones >> pb) & 1u);
+                c0 = va;
+                p0 = e;
+                c1 = vb;
+                p1 = e;
+            } else {
+                uint64_t oa = ((ones >> pa) & 1u) ? Rec::kOne : Rec::del(rec, va, e);
+                uint64_t ob = ((ones >> pb) & 1u) ? Rec::kOne : Rec::del(rec, vb, e);
+                if (Rec::deg(oa) == 2) {
+                    c0 = (uint32_t)(Rec::edge(oa) - e);
+                    p0 = position_in<kTri>(edges, c0, va, P);
+                    mypush++;
+                    if constexpr (kList) {
+                        f0 = true;
+                    } else {
+                        uint32_t old = atomicMin(&state[c0], rr | p0);
+                        f0 = old == kUnclaimed;
+                        myclaims += (f0 || (old >> 2) == r + 1) ? 1u : 0u;
+                    }
+                } else if (kList && Rec::deg(oa) == 1 && !((ones >> pa) & 1u)) {
+                    // va leaves with this edge; if it reached degree 1 earlier in this round, its
+                    // claim named this edge and is stale: cancel it
+                    c0 = e;
+                    p0 = kCancel | part_of(va, P);
                     f0 = true;
-                } else {
-                    uint32_t old = atomicMin(&state[c0], rr | p0);
-                    f0 = old == kUnclaimed;
-                    myclaims += (f0 || (old >> 2) == r + 1) ? 1u : 0u;
                 }
-            } else if (kList && Rec::deg(oa) == 1 && !((ones >> pa) & 1u)) {
-                // va leaves with this edge; if it reached degree 1 earlier in this round, its
-                // claim named this edge and is stale: cancel it
-                c0 = e;
-                p0 = kCancel | part_of(va, P);
-                f0 = true;
-            }
-            if (Rec::deg(ob) == 2) {
-                c1 = (uint32_t)(Rec::edge(ob) - e);
-                p1 = position_in<kTri>(edges, c1, vb, P);
-                mypush++;
-                if constexpr (kList) {
+                if (Rec::deg(ob) == 2) {
+                    c1 = (uint32_t)(Rec::edge(ob) - e);
+                    p1 = position_in<kTri>(edges, c1, vb, P);
+                    mypush++;
+                    if constexpr (kList) {
+                        f1 = true;
+                    } else {
+                        uint32_t old = atomicMin(&state[c1], rr | p1);
+                        f1 = old == kUnclaimed;
+                        myclaims += (f1 || (old >> 2) == r + 1) ? 1u : 0u;
+                    }
+                } else if (kList && Rec::deg(ob) == 1 && !((ones >> pb) & 1u)) {
+                    c1 = e;
+                    p1 = kCancel | part_of(vb, P);
                     f1 = true;
-                } else {
-                    uint32_t old = atomicMin(&state[c1], rr | p1);
-                    f1 = old == kUnclaimed;
-                    myclaims += (f1 || (old >> 2) == r + 1) ? 1u : 0u;
                 }
-            } else if (kList && Rec::deg(ob) == 1 && !((ones >> pb) & 1u)) {
-                c1 = e;
-                p1 = kCancel | part_of(vb, P);
-                f1 = true;
             }
             if (!f0) {  // the first requested slot holds the first appended entry
                 c0 = c1;
@@ -214,19 +293,13 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
             }
         }
         if constexpr (kList) {
-            // records past the list's capacity are counted, not stored; the host then redoes
-            // the build with atomic claims
-            app.push(f0, make_uint2(c0, p0), f1, make_uint2(c1, p1), &ccount[r + 1], [claims, ccap](uint64_t j, uint2 c) {
-                if (j < ccap) claims[j] = c;
-            });
+            app.push(f0, make_uint2(c0, p0), f1, make_uint2(c1, p1), tail, to_list);
         } else {
             app.push(f0, c0, f1, c1, &lcount[r + 1], [slots, hi](uint64_t j, uint32_t x) { slots[hi + j].x = x; });
         }
     }
     if constexpr (kList) {
-        app.flush(&ccount[r + 1], [claims, ccap](uint64_t j, uint2 c) {
-            if (j < ccap) claims[j] = c;
-        });
+        app.flush(tail, to_list);
     } else {
         app.flush(&lcount[r + 1], [slots, hi](uint64_t j, uint32_t x) { slots[hi + j].x = x; });
     }
@@ -362,7 +435,10 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
 {
     if (st.m == 0) return hipSuccess;
     unsigned g = grid_for(st.m, 8192);
-    if (st.tripartite)
+    if (st.lists) {
+        if (!st.tripartite) return hipErrorInvalidValue;
+        k_round0_lists<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount, st.ctrl);
+    } else if (st.tripartite)
         k_round0<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots, st.lcount,
                                                 st.ctrl);
     else
@@ -371,18 +447,23 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, bool list_claims, hipStream_t s)
+hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, ApplyMode mode, hipStream_t s)
 {
     unsigned g = grid_for(st.n, st.grid_cap);
-    if (st.tripartite && list_claims)
-        k_apply<true, true><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount,
-                                                     st.claims, st.ccount, st.m, st.ctrl, r, st.P, hinge_in_slot);
-    else if (st.tripartite)
-        k_apply<true, false><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount,
-                                                      st.claims, st.ccount, st.m, st.ctrl, r, st.P, hinge_in_slot);
-    else
-        k_apply<false, false><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount,
-                                                       st.claims, st.ccount, st.m, st.ctrl, r, st.P, false);
+    if (mode != ApplyMode::kAtomicClaims && !st.tripartite) return hipErrorInvalidValue;
+#define MPHX_APPLY(TRI, MODE, HINGE)                                                                        \
+    k_apply<TRI, MODE><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, \
+                                                st.claims, st.ccount, st.dcount, st.m, st.ctrl, r, st.P, HINGE)
+    switch (mode) {
+    case ApplyMode::kClaimList: MPHX_APPLY(true, ApplyMode::kClaimList, hinge_in_slot); break;
+    case ApplyMode::kUpdateList: MPHX_APPLY(true, ApplyMode::kUpdateList, hinge_in_slot); break;
+    default:
+        if (st.tripartite)
+            MPHX_APPLY(true, ApplyMode::kAtomicClaims, hinge_in_slot);
+        else
+            MPHX_APPLY(false, ApplyMode::kAtomicClaims, false);
+    }
+#undef MPHX_APPLY
     return hipGetLastError();
 }
 

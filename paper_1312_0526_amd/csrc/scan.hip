@@ -39,6 +39,8 @@ __global__ void k_ctrl_init(Ctrl* ctrl, uint64_t* lstart)
         ctrl->aux = 0;
         ctrl->claims = 0;
         ctrl->degsum = 0;
+        ctrl->updates = 0;
+        ctrl->touched = 0;
         lstart[0] = 0;
     }
 }

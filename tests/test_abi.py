@@ -56,6 +56,23 @@ def test_options_roundtrip(mx):
         mx.set_option("no_such_option", 1)
 
 
+def test_info_struct_mirrors_match_the_header(mx):
+    # the C side asserts the same sizes (80 and 40 bytes)
+    assert C.sizeof(mx._lib.MphfInfo) == 80 and C.sizeof(mx._lib.PeelInfo) == 40
+    names = [f for f, _ in mx._lib.MphfInfo._fields_]
+    assert names[-2:] == ["update_deletes", "update_records"]
+
+
+def test_update_lists_option_range(mx):
+    assert mx.get_option("update_lists") == 16
+    for bad in (-1, 101):
+        with pytest.raises(mx.MphxError):
+            mx.set_option("update_lists", bad)
+    mx.set_option("update_lists", 0)
+    assert mx.get_option("update_lists") == 0
+    mx.set_option("update_lists", 16)
+
+
 def test_argument_errors_need_no_device(mx):
     lib = mx.lib()
     info = mx._lib.PeelInfo()

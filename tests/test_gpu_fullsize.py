@@ -1,6 +1,7 @@
 """Parity at the full workload sizes (GPU only; minutes of CPU for the oracle).
 
-* 2^27 u64 keys: the whole MPHF (codes + rank) equals the oracle's; at gamma = 120/100 (below
+* 2^27 u64 keys: the whole MPHF (codes + rank) equals the oracle's, with atomic claims and
+  with claim and update lists; at gamma = 120/100 (below
   the threshold c_3 ~ 1.221, Section 1) the peel returns exactly the oracle's 2-core, rounds,
   hinges and order, and a one-try build reports the same 2-core size.
 * 2^31 byte-string keys generated on the device (the configuration the benchmark times): the
@@ -63,6 +64,26 @@ def test_config2_full_parity(mx):
     with pytest.raises(mx.MphxError) as ei:
         mx.mphf_build_u64(keys, gamma=(120, 100), max_tries=1)
     assert ei.value.status == mx.ECORE and ei.value.info["n_core"] == n - pref["n_peeled"]
+
+
+@pytest.mark.timeout(1200)
+def test_config2_full_parity_claim_and_update_lists(mx):
+    """2^27 keys through the path the largest builds take by default: claim lists from round 1,
+    the dense rounds' deletes through sorted update lists."""
+    n = 1 << 27
+    o = oracle.Oracle()
+    keys_h = workloads.u64_keys(n)
+    keys = mx.gen_keys_u64(n)
+    mx.set_option("claim_lists", 27)
+    try:
+        assert mx.get_option("update_lists") == 16
+        r = mx.mphf_build_u64(keys, seed=0)
+    finally:
+        mx.set_option("claim_lists", 28)
+    rc, ref = o.mphf_build_u64(keys_h, seed=0)
+    assert rc == 0 and r["tries"] == ref["tries"] == 1 and r["n_rounds"] == ref["n_rounds"]
+    assert np.array_equal(host(r["codes"], np.uint64), ref["words"])
+    assert np.array_equal(host(r["rank"], np.uint64), ref["rank"])
 
 
 _POP8 = np.array([bin(i).count("1") for i in range(256)], np.uint8)

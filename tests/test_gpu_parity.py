@@ -335,18 +335,25 @@ def test_mphf_degree_overflow(mx, o, build_mode, copies):
         assert o.mphf_build_u64(keys, max_tries=2)[0] == oracle.ERANGE
 
 
-@pytest.fixture(params=[1, 0], ids=["claim-lists", "atomic-claims"])
+@pytest.fixture(params=[(1, 0), (1, 1), (1, 16), (0, 0)],
+                ids=["claim-lists", "update-lists-most-rounds", "update-lists-dense-rounds", "atomic-claims"])
 def claim_mode(request, mx):
-    """Next-layer claims: partitioned lists resolved in LDS (forced on at every size), or one
+    """Next-layer claims: partitioned lists resolved in LDS (forced on at every size), with the
+    deletes of rounds whose claim count c has 200 c >= p m going through sorted update lists
+    (p = 1: nearly every round, p = 16: the dense ones, which the default picks), or one
     device atomic per claim."""
-    mx.set_option("claim_lists", request.param)
+    lists, upd = request.param
+    mx.set_option("claim_lists", lists)
+    mx.set_option("update_lists", upd)
     yield request.param
     mx.set_option("claim_lists", 28)
+    mx.set_option("update_lists", 16)
 
 
 @pytest.mark.parametrize("n,seed", [(1_000_000, 0), (12_000_000, 4), (1, 0), (7, 5)])
 def test_mphf_claim_modes_match_oracle(mx, o, claim_mode, n, seed):
-    """12e6 keys span one claim group of 2^24 edges and 184 buckets of 2^16."""
+    """12e6 keys span one claim group of 2^24 edges and 184 buckets of 2^16, and 2^14-vertex
+    update buckets in three first-pass groups."""
     keys = workloads.u64_keys(n, gen_seed=41)
     got = mx.mphf_build_u64(dev(keys), seed=seed)
     rc, ref = o.mphf_build_u64(keys, seed=seed)
@@ -354,8 +361,10 @@ def test_mphf_claim_modes_match_oracle(mx, o, claim_mode, n, seed):
     _assert_mphf_equal(got, ref)
 
 
-def test_mphf_claim_lists_strings_retries_and_failures(mx, o):
+@pytest.mark.parametrize("upd", [0, 1], ids=["claims", "update-lists"])
+def test_mphf_claim_lists_strings_retries_and_failures(mx, o, upd):
     mx.set_option("claim_lists", 1)
+    mx.set_option("update_lists", upd)
     try:
         data, offs = workloads.str_keys(300_000, gen_seed=43)
         got = mx.mphf_build_str(dev(data), dev(offs), seed=6)
@@ -383,3 +392,4 @@ def test_mphf_claim_lists_strings_retries_and_failures(mx, o):
         assert ei.value.status == mx.EDUP
     finally:
         mx.set_option("claim_lists", 28)
+        mx.set_option("update_lists", 16)
