@@ -650,7 +650,8 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         }
         if (part) {
             Timed tm(PH_BUILD, s);
-            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.aux, s));
+            // the claim buffers (m >= n pairs each) are free until the rounds
+            HIP_TRY(launch_part_build(L.edges, n, P, L.rec, L.pairs1, L.pairs2, L.claims, L.claims_tmp, L.aux, s));
         }
         // atomic claims keep per-edge states (after the build: they share the pair buffers);
         // claim lists carry the hinge in the layer slots from round 0 on

@@ -100,8 +100,9 @@ struct PartHist1 {
 size_t part_aux_bytes(uint64_t n, uint64_t P, bool lists);
 PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P);
 // the hashing kernel has filled the first-pass histograms (part_hist1)
+// extra1/extra2 (n pairs each, nullable): with both, one first pass serves all three parts
 hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
-                             uint2* pairs2, void* aux, hipStream_t s);
+                             uint2* pairs2, uint2* extra1, uint2* extra2, void* aux, hipStream_t s);
 // Layer r from the count claims of round r - 1 (ccount[r] of them, known to the host), held in
 // st.claims, or in st.claims_tmp when round r - 1 used update lists (in_tmp): the claims are
 // partitioned by edge, cancelled ones dropped, each edge's lowest claimed position kept as its

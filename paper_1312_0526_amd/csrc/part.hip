@@ -166,6 +166,66 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter1(Src src, uint64_t n,
     }
 }
 
+// ---- pass 1 scatter of all three parts from one read of the edges -------------------------------
+// The same as k_part_scatter1 on EdgeColumn k = 0, 1, 2, with the tile's edges loaded once;
+// off1 holds the three parts' scanned histograms back to back ([3][NH][nt1]).
+__global__ __launch_bounds__(kPtBlock) void k_part_scatter1_x3(const uint32_t* __restrict__ edges, uint64_t n,
+                                                               uint64_t P, uint32_t NH, uint64_t nt1,
+                                                               const uint32_t* __restrict__ off1, uint2* __restrict__ out0,
+                                                               uint2* __restrict__ out1, uint2* __restrict__ out2)
+{
+    __shared__ uint2 buf[kPtTile];
+    __shared__ uint32_t cnt[kMaxGroups], lst[kMaxGroups], gof[kMaxGroups], wtot[kWaves];
+    const uint64_t t0 = (uint64_t)blockIdx.x * kPtTile;
+    uint32_t v[kPtPer][3];
+#pragma unroll
+    for (uint32_t q = 0; q < kPtPer; q++) {
+        const uint64_t i = t0 + q * kPtBlock + threadIdx.x;
+        if (i < n) {
+            const uint32_t* t = edges + 3 * i;
+            v[q][0] = t[0];
+            v[q][1] = t[1];
+            v[q][2] = t[2];
+        }
+    }
+    const uint32_t total = (uint32_t)min<uint64_t>(kPtTile, n - t0);
+#pragma unroll
+    for (uint32_t k = 0; k < 3; k++) {
+        for (uint32_t j = threadIdx.x; j < kMaxGroups; j += kPtBlock)
+            cnt[j] = 0;
+        __syncthreads();
+        uint32_t rk[kPtPer];
+#pragma unroll
+        for (uint32_t q = 0; q < kPtPer; q++) {
+            const uint64_t i = t0 + q * kPtBlock + threadIdx.x;
+            if (i < n) {
+                v[q][k] = local_of(v[q][k], k, P);
+                rk[q] = atomicAdd(&cnt[v[q][k] >> kPartGrpShift], 1u);
+            }
+        }
+        __syncthreads();
+        groups_exclusive(cnt, NH, lst, wtot);
+        const uint32_t* off = off1 + (uint64_t)k * NH * nt1;
+        for (uint32_t h = threadIdx.x; h < NH; h += kPtBlock)
+            gof[h] = off[(uint64_t)h * nt1 + blockIdx.x];
+        __syncthreads();
+#pragma unroll
+        for (uint32_t q = 0; q < kPtPer; q++) {
+            const uint64_t i = t0 + q * kPtBlock + threadIdx.x;
+            if (i < n)
+                buf[lst[v[q][k] >> kPartGrpShift] + rk[q]] = make_uint2(v[q][k], (uint32_t)i);
+        }
+        __syncthreads();
+        uint2* out = k == 0 ? out0 : (k == 1 ? out1 : out2);
+        for (uint32_t s = threadIdx.x; s < total; s += kPtBlock) {
+            const uint2 x = buf[s];
+            const uint32_t h = x.x >> kPartGrpShift;
+            out[(uint64_t)gof[h] + (s - lst[h])] = x;
+        }
+        __syncthreads();  // buf, cnt and lst are reused by the next part
+    }
+}
+
 // ---- group bounds and second-pass tile bases (one block) ---------------------------------------
 __global__ __launch_bounds__(kPtBlock) void k_part_groups(const uint32_t* __restrict__ off1, uint32_t NH, uint64_t nt1,
                                                           uint64_t n, uint32_t* __restrict__ ginfo)
@@ -509,18 +569,16 @@ AuxLayout updates_aux(uint64_t m)
     return aux_layout((uint64_t)NH * tiles_of(m), m, NH);
 }
 
-// Second pass + per-bucket kernel shared by both uses, after the first-pass scan.
-template <class Src, class Last>
-hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32_t* off1, uint2* mid, uint2* out,
-                          const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
+// Second pass + per-bucket kernel, after the first pass left the pairs grouped in mid.
+template <class Last>
+hipError_t second_pass_then(uint64_t n, uint32_t gsh, uint32_t NH, const uint32_t* off1, uint2* mid, uint2* out,
+                            const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
 {
     const uint64_t nt1 = tiles_of(n), nt2 = nt1 + NH;
     uint32_t* hist2 = reinterpret_cast<uint32_t*>(base + L.hist2);
     uint32_t* ginfo = reinterpret_cast<uint32_t*>(base + L.ginfo);
     void* scan = base + L.scan;
-    hipError_t err = launch_scan_u32(off1, (uint64_t)NH * nt1, off1, scan, L.scan_bytes, s);
-    if (err != hipSuccess) return err;
-    k_part_scatter1<Src><<<(unsigned)nt1, kPtBlock, 0, s>>>(src, n, gsh, NH, nt1, off1, mid);
+    hipError_t err;
     k_part_groups<<<1, kPtBlock, 0, s>>>(off1, NH, nt1, n, ginfo);
     k_part_hist2<<<(unsigned)nt2, kPtBlock, 0, s>>>(mid, ginfo, NH, gsh - 8, hist2);
     err = hipGetLastError();
@@ -531,6 +589,18 @@ hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     return last(ginfo, hist2);
+}
+
+// Both passes + per-bucket kernel, after the first-pass histograms (off1, scanned here).
+template <class Src, class Last>
+hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32_t* off1, uint2* mid, uint2* out,
+                          const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
+{
+    const uint64_t nt1 = tiles_of(n);
+    hipError_t err = launch_scan_u32(off1, (uint64_t)NH * nt1, off1, base + L.scan, L.scan_bytes, s);
+    if (err != hipSuccess) return err;
+    k_part_scatter1<Src><<<(unsigned)nt1, kPtBlock, 0, s>>>(src, n, gsh, NH, nt1, off1, mid);
+    return second_pass_then(n, gsh, NH, off1, mid, out, L, base, last, s);
 }
 
 }  // namespace
@@ -551,7 +621,7 @@ PartHist1 part_hist1(void* aux, uint64_t n, uint64_t P)
 }
 
 hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint64_t* rec, uint2* pairs1,
-                             uint2* pairs2, void* aux, hipStream_t s)
+                             uint2* pairs2, uint2* extra1, uint2* extra2, void* aux, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const AuxLayout L = build_aux(n, P);
@@ -560,6 +630,29 @@ hipError_t launch_part_build(const uint32_t* edges, uint64_t n, uint64_t P, uint
     const uint32_t NH = groups_of(P, kPartGrpShift);
     const uint64_t nt1 = tiles_of(n), nb = (P + (1ull << kVxShift) - 1) >> kVxShift;
     if (NH > kPartMaxGroups || nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
+    if (extra1 && extra2) {
+        // one first pass for the three parts, then each part's second pass and accumulation
+        for (uint32_t k = 0; k < 3; k++) {
+            uint32_t* off1 = hist1 + (uint64_t)k * NH * nt1;
+            hipError_t err = launch_scan_u32(off1, (uint64_t)NH * nt1, off1, base + L.scan, L.scan_bytes, s);
+            if (err != hipSuccess) return err;
+        }
+        k_part_scatter1_x3<<<(unsigned)nt1, kPtBlock, 0, s>>>(edges, n, P, NH, nt1, hist1, pairs1, extra1, extra2);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+        uint2* const first[3] = {pairs1, extra1, extra2};
+        for (uint32_t k = 0; k < 3; k++) {
+            err = second_pass_then(
+                n, kPartGrpShift, NH, hist1 + (uint64_t)k * NH * nt1, first[k], pairs2, L, base,
+                [&](const uint32_t* ginfo, const uint32_t* off2) {
+                    k_part_accum<<<(unsigned)nb, kAccBlock, 0, s>>>(pairs2, ginfo, NH, off2, n, k, P, rec);
+                    return hipGetLastError();
+                },
+                s);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
     for (uint32_t k = 0; k < 3; k++) {
         uint32_t* off1 = hist1 + (uint64_t)k * NH * nt1;
         hipError_t err = partition_then(
