@@ -112,13 +112,16 @@ __global__ __launch_bounds__(kHuBlock) void k_hash_u64_tiles(const uint64_t* __r
 // word list belongs to key owner[f] at word index j, adds its two mixed terms into that key's
 // LDS sums, and the key's thread finishes the digest.  The owner table covers a window of
 // kHsWindow words at a time (the block walks as many windows as its keys need, so a key of
-// any length is spread too); it is small, so eight blocks fit on a CU.  The loads of
-// consecutive words are consecutive in memory; each lane has two words' loads in flight.
+// any length is spread too); it is filled by one mark per key and a block-wide running
+// maximum, so no thread loops over a long key's words.  The loads of consecutive words are
+// consecutive in memory; each lane has two words' loads in flight.
 // With histograms requested, block b hashes exactly partition tile b.
 constexpr uint32_t kHsBlock = 256;
 constexpr uint32_t kHsWindow = 2048;
 constexpr uint32_t kHsUnroll = 2;
+constexpr uint32_t kHsSub = 2;
 static_assert(kPartTile % kHsBlock == 0, "a partition tile is whole chunks");
+static_assert(kHsWindow == 8 * kHsBlock, "each thread scans eight owner entries");
 
 __device__ __forceinline__ uint64_t key_word(const uint8_t* bytes, uint64_t p, uint64_t total)
 {
@@ -135,13 +138,23 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
                                                              uint64_t seed, uint64_t P, uint32_t* __restrict__ edges,
                                                              PartHist1 h1)
 {
-    __shared__ uint64_t s_off[kHsBlock], s_len[kHsBlock], s_wpre[kHsBlock], s_wtot[kHsBlock / kWave];
-    __shared__ unsigned long long s_A[kHsBlock], s_B[kHsBlock];
-    __shared__ uint8_t s_owner[kHsWindow];
+    // Per key t of the chunk, with pre its first word in the chunk's flat word list: word f of
+    // the key (index j = f - pre) starts at byte base[t] + 8f and its lane-A salt is
+    // salt[t] + f * GAMMA (lane B adds sb - sa), so both follow from f by additions; end[t]
+    // is the key's end byte.
+    __shared__ uint64_t s_base[kHsBlock], s_end[kHsBlock], s_salt[kHsBlock], s_wtot[kHsBlock / kWave];
+    // each key's two sums are split over kHsSub partial sums (lane & (kHsSub - 1)), so that
+    // the neighbouring lanes that add words of one key hit different LDS addresses
+    __shared__ unsigned long long s_A[kHsBlock * kHsSub], s_B[kHsBlock * kHsSub];
+    __shared__ uint4 s_owner4[kHsWindow / 8];  // kHsWindow u16 entries: owner + 1 of each word
+    __shared__ uint32_t s_wmax[kHsBlock / kWave];
     __shared__ TileHist th;
+    uint16_t* const s_owner = reinterpret_cast<uint16_t*>(s_owner4);
     const uint64_t total = offs[n];
     const uint64_t sa = fin(seed + kGamma);
     const uint64_t sb = fin(seed + 2 * kGamma);
+    const uint64_t dba = sb - sa;
+    constexpr uint64_t kStep = (uint64_t)kHsUnroll * kHsBlock;
     const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const uint64_t nchunks = (n + kHsBlock - 1) / kHsBlock;
     uint64_t c0 = blockIdx.x, c1 = nchunks, cstep = gridDim.x;
@@ -159,10 +172,11 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
             len = offs[i + 1] - o0;
         }
         const uint64_t nw = (len + 7) >> 3;
-        s_off[tid] = o0;
-        s_len[tid] = len;
-        s_A[tid] = 0;
-        s_B[tid] = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kHsSub; k++) {
+            s_A[tid * kHsSub + k] = 0;
+            s_B[tid * kHsSub + k] = 0;
+        }
         // exclusive prefix of the word counts over the block
         uint64_t incl = nw;
         for (uint32_t d = 1; d < kWave; d <<= 1) {
@@ -179,27 +193,59 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
             W += s_wtot[q];
         }
         pre += incl - nw;
-        s_wpre[tid] = pre;
+        s_base[tid] = o0 - 8 * pre;
+        s_end[tid] = o0 + len;
+        s_salt[tid] = sa - pre * kGamma;
         for (uint64_t w0 = 0; w0 < W; w0 += kHsWindow) {
             const uint64_t w1 = min<uint64_t>(w0 + kHsWindow, W);
-            // this key's words inside the window [w0, w1)
-            for (uint64_t f = max<uint64_t>(pre, w0); f < min<uint64_t>(pre + nw, w1); f++)
-                s_owner[f - w0] = (uint8_t)tid;
+            // Owners of the window's words: every key with words in [w0, w1) marks its first
+            // one there with its index + 1, and a running maximum over the window carries
+            // each mark to the key's later words (keys own consecutive, increasing ranges).
+            s_owner4[tid] = make_uint4(0u, 0u, 0u, 0u);
             __syncthreads();
-            for (uint64_t f0 = w0 + tid; f0 < w1; f0 += kHsUnroll * kHsBlock) {
-                uint32_t t[kHsUnroll], j[kHsUnroll];
+            if (nw && pre < w1 && pre + nw > w0)
+                s_owner[max<uint64_t>(pre, w0) - w0] = (uint16_t)(tid + 1);
+            __syncthreads();
+            {
+                const uint4 m4 = s_owner4[tid];
+                uint32_t e[8] = {m4.x & 0xFFFFu, m4.x >> 16, m4.y & 0xFFFFu, m4.y >> 16,
+                                 m4.z & 0xFFFFu, m4.z >> 16, m4.w & 0xFFFFu, m4.w >> 16};
+#pragma unroll
+                for (uint32_t k = 1; k < 8; k++)
+                    e[k] = max(e[k], e[k - 1]);
+                uint32_t run = e[7];
+                for (uint32_t d = 1; d < kWave; d <<= 1) {
+                    const uint32_t y = __shfl_up(run, d, kWave);
+                    if (lane >= d)
+                        run = max(run, y);
+                }
+                if (lane == kWave - 1)
+                    s_wmax[wv] = run;
+                uint32_t carry = __shfl_up(run, 1, kWave);
+                if (lane == 0)
+                    carry = 0;
+                __syncthreads();
+                for (uint32_t q = 0; q < wv; q++)
+                    carry = max(carry, s_wmax[q]);
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    e[k] = max(e[k], carry);
+                s_owner4[tid] = make_uint4(e[0] | e[1] << 16, e[2] | e[3] << 16, e[4] | e[5] << 16, e[6] | e[7] << 16);
+            }
+            __syncthreads();
+            uint64_t fg = (w0 + tid) * kGamma;  // f0 * GAMMA
+            for (uint64_t f0 = w0 + tid; f0 < w1; f0 += kStep, fg += kStep * kGamma) {
+                uint32_t t[kHsUnroll];
                 uint64_t p[kHsUnroll], w[kHsUnroll];
                 bool fast = true;
 #pragma unroll
                 for (uint32_t u = 0; u < kHsUnroll; u++) {
                     const uint64_t f = f0 + u * kHsBlock;
                     t[u] = 0;
-                    j[u] = 0;
                     p[u] = 0;
                     if (f < w1) {
-                        t[u] = s_owner[f - w0];
-                        j[u] = (uint32_t)(f - s_wpre[t[u]]);
-                        p[u] = s_off[t[u]] + 8ull * j[u];
+                        t[u] = s_owner[f - w0] - 1u;
+                        p[u] = s_base[t[u]] + 8 * f;
                     }
                     fast = fast && ((p[u] >> 2) + 3) * 4 <= total;
                 }
@@ -213,11 +259,13 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
                         x1[u] = d[q + 1];
                         x2[u] = d[q + 2];
                     }
+                    // the 8 bytes from p: alignbyte shifts a dword pair right by (p & 3) bytes
 #pragma unroll
                     for (uint32_t u = 0; u < kHsUnroll; u++) {
-                        const uint32_t sh = (uint32_t)(p[u] & 3) * 8;
-                        const uint64_t lo = (uint64_t)x0[u] | ((uint64_t)x1[u] << 32);
-                        w[u] = sh ? ((lo >> sh) | ((uint64_t)x2[u] << (64 - sh))) : lo;
+                        const uint32_t sh = (uint32_t)p[u];
+                        const uint32_t lo = __builtin_amdgcn_alignbyte(x1[u], x0[u], sh);
+                        const uint32_t hi = __builtin_amdgcn_alignbyte(x2[u], x1[u], sh);
+                        w[u] = (uint64_t)lo | ((uint64_t)hi << 32);
                     }
                 } else {
 #pragma unroll
@@ -227,20 +275,28 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
 #pragma unroll
                 for (uint32_t u = 0; u < kHsUnroll; u++) {
                     if (f0 + u * kHsBlock < w1) {
-                        const uint64_t rem = s_len[t[u]] - 8ull * j[u];
-                        uint64_t x = w[u];
-                        if (rem < 8)
-                            x &= (1ull << (8 * rem)) - 1;
-                        atomicAdd(&s_A[t[u]], (unsigned long long)fin(x ^ (sa + j[u] * kGamma)));
-                        atomicAdd(&s_B[t[u]], (unsigned long long)fin(x ^ (sb + j[u] * kGamma)));
+                        // bytes past the key's end count as zero: shift them out and back
+                        const uint64_t rem = s_end[t[u]] - p[u];
+                        const uint32_t sh = rem < 8 ? 64u - 8u * (uint32_t)rem : 0u;
+                        const uint64_t x = (w[u] << sh) >> sh;
+                        const uint64_t salt = s_salt[t[u]] + fg + (uint64_t)u * kHsBlock * kGamma;
+                        const uint32_t slot = t[u] * kHsSub + (lane & (kHsSub - 1));
+                        atomicAdd(&s_A[slot], (unsigned long long)fin(x ^ salt));
+                        atomicAdd(&s_B[slot], (unsigned long long)fin(x ^ (salt + dba)));
                     }
                 }
             }
             __syncthreads();  // the owner window is rewritten next
         }
         if (i < n) {
-            const uint64_t a = fin(s_A[tid] ^ sa ^ len);
-            const uint64_t b = fin(s_B[tid] ^ sb ^ len);
+            uint64_t A = 0, B = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kHsSub; k++) {
+                A += s_A[tid * kHsSub + k];
+                B += s_B[tid * kHsSub + k];
+            }
+            const uint64_t a = fin(A ^ sa ^ len);
+            const uint64_t b = fin(B ^ sb ^ len);
             uint32_t v0, v1, v2;
             edge_of_digest(a, b, P, v0, v1, v2);
             edges[3 * i] = v0;
