@@ -205,8 +205,18 @@ def summarize_kernel_stats(csv_path: str, out_path: str, title: str, command: st
     rows = list(csv.DictReader(open(csv_path)))
     lines = [f"# {title}", "", f"command: {command}", "",
              f"{'kernel':36s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>11s} {'pct':>6s}"]
+    modes = {"(mphx::ApplyMode)0": "atomic", "(mphx::ApplyMode)1": "claim list", "(mphx::ApplyMode)2": "update list"}
     for r in rows:
-        name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        for k, v in modes.items():
+            name = name.replace(k, v)
+        depth = 0
+        for j, ch in enumerate(name):  # drop the parameter list: the first '(' outside <...>
+            depth += ch == "<"
+            depth -= ch == ">"
+            if ch == "(" and depth == 0:
+                name = name[:j]
+                break
         name = name.replace("mphx::", "").replace("HIP_vector_type<unsigned int, 2u>", "uint2")[:36]
         lines.append(f"{name:36s} {r['Calls']:>6s} {int(r['TotalDurationNs']) / 1e6:10.3f} "
                      f"{float(r['AverageNs']) / 1e3:11.2f} {float(r['Percentage']):6.2f}")
@@ -435,7 +445,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", choices=sorted(CONFIGS), default="c3")
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 22, help="keys in the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="ceilings,plain,batched,served",
                     help="comma list of: ceilings, plain, batched, served")

@@ -90,43 +90,58 @@ def str_lengths(n: int, gen_seed: int = 0, start: int = 0) -> np.ndarray:
     return _qtable()[(r0 >> np.uint64(64 - QTABLE_BITS)).astype(np.int64)].astype(np.int64)
 
 
+_STR_CHUNK = 1 << 19  # keys per vectorised pass: bounds the per-byte index arrays
+
+
 def str_keys(n: int, gen_seed: int = 0, start: int = 0):
     """Byte-string keys ``start .. start+n-1``.
 
     Returns ``(data, offs)``: ``data`` is a uint8 array with all keys back to back and
     ``offs`` a uint64 array of n + 1 offsets (key i is ``data[offs[i]:offs[i+1]]``).
     """
+    if n <= _STR_CHUNK:
+        return _str_keys_chunk(n, gen_seed, start)
+    lens = str_lengths(n, gen_seed, start)
+    offs = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offs[1:])
+    data = np.empty(int(offs[-1]), dtype=np.uint8)
+    for c0 in range(0, n, _STR_CHUNK):
+        c1 = min(c0 + _STR_CHUNK, n)
+        d, _ = _str_keys_chunk(c1 - c0, gen_seed, start + c0)
+        data[int(offs[c0]):int(offs[c1])] = d
+    return data, offs
+
+
+def _str_keys_chunk(n: int, gen_seed: int, start: int):
     base = u64_keys(n, gen_seed, start)
     lens = str_lengths(n, gen_seed, start)
     offs = np.zeros(n + 1, dtype=np.uint64)
     np.cumsum(lens, out=offs[1:])
-    total = int(offs[-1])
-    data = np.empty(total, dtype=np.uint8)
     if n == 0:
-        return data, offs
-    # prefix: base-95 digits of the global index
-    gidx = np.arange(start, start + n, dtype=np.int64)
-    o = offs[:-1].astype(np.int64)
-    for d in range(STR_PREFIX):
-        data[o + d] = (0x20 + (gidx // (95 ** d)) % 95).astype(np.uint8)
-    # body: words 2.. of each key's stream, little-endian bytes, printable map
+        return np.empty(0, dtype=np.uint8), offs
+    # Each key laid out in a row of the longest key's width: the prefix, then the mapped bytes
+    # of its stream words; the keys are the rows' first len bytes, read in row order.
     body = lens - STR_PREFIX
     nwords = (body + 7) // 8
+    wmax = int(nwords.max())
+    have = np.arange(wmax, dtype=np.int64)[None, :] < nwords[:, None]
     key_of_word = np.repeat(np.arange(n, dtype=np.int64), nwords)
     wstart = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(nwords, out=wstart[1:])
     t = np.arange(wstart[-1], dtype=np.int64) - wstart[key_of_word]
-    words = stream(base[key_of_word], (t + 2).astype(np.uint64))
-    wbytes = words.astype("<u8").view(np.uint8).reshape(-1, 8)
-    mapped = (0x20 + ((wbytes.astype(np.uint32) * 95) >> 8)).astype(np.uint8)
-    # byte p (0-based within the body) of the key sits at word p // 8, lane p % 8
-    key_of_byte = np.repeat(np.arange(n, dtype=np.int64), body)
-    bstart = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(body, out=bstart[1:])
-    p = np.arange(bstart[-1], dtype=np.int64) - bstart[key_of_byte]
-    src_word = wstart[key_of_byte] + p // 8
-    data[o[key_of_byte] + STR_PREFIX + p] = mapped[src_word, p % 8]
-    return data, offs
+    raw = stream(base[key_of_word], (t + 2).astype(np.uint64)).astype("<u8")
+    printable = (0x20 + ((np.arange(256, dtype=np.uint32) * 95) >> 8)).astype(np.uint8)
+    words = np.zeros((n, wmax), dtype="<u8")
+    words[have] = printable[raw.view(np.uint8)].view("<u8")
+    rows = np.empty((n, STR_PREFIX + 8 * wmax), dtype=np.uint8)
+    gidx = np.arange(start, start + n, dtype=np.int64)
+    digits = np.empty((n, STR_PREFIX), dtype=np.uint8)
+    for d in range(STR_PREFIX):  # base-95 digits of the global index
+        digits[:, d] = 0x20 + (gidx // (95 ** d)) % 95
+    rows[:, :STR_PREFIX] = digits
+    rows[:, STR_PREFIX:] = words.view(np.uint8).reshape(n, 8 * wmax)
+    keep = np.arange(rows.shape[1], dtype=np.int64)[None, :] < lens[:, None]
+    return rows[keep], offs
 
 
 def str_key(i: int, gen_seed: int = 0) -> bytes:
