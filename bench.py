@@ -60,7 +60,8 @@ def algorithmic_bytes(phase: str, st: dict) -> float:
     if phase == "frontier":
         # round 0: every record read; per degree-1 vertex an edge-state RMW (8 B) and at most
         # one 4 B layer append; with claim lists, the hinge test instead: the edge's lower-part
-        # vertices (about 4 B) and their records (about 8 B), and an 8 B layer entry
+        # vertices (about 4 B) and their records (about 8 B), and an 8 B layer entry (when
+        # round 0 also writes its hinge-first slots and deletes, those are counted under apply)
         return 8 * m + (20 if lists else 12) * F0
     if phase == "apply":
         # per edge: slot read 8 (edge + hinge, or edge + state read) + edge read 12 + slot

@@ -291,6 +291,21 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
             HIP_TRY(hipStreamSynchronize(s));
         }
         st.grid_cap = auto_grid(est);  // the records bound the layer
+        if (r == 0 && st.round0_updates) {
+            // round 0 already wrote layer 0's slots and its update list
+            HIP_TRY(launch_close_layer(st, 0, s));
+            unsigned long long dels = 0;
+            HIP_TRY(hipMemcpyAsync(&dels, st.dcount, sizeof dels, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (dels > st.m)
+                return kListOverflow;  // layer 0 larger than m/2 edges: redo with atomic claims
+            Timed t(PH_UPDATE, s);
+            HIP_TRY(launch_update_apply(st, 0, dels, s));
+            in_tmp = true;
+            if (est == 0)
+                break;
+            continue;
+        }
         // a layer of at most est edges deletes at most 2 est times, which the list must hold
         const bool updates = upd > 0 && 2 * est <= st.m && 200 * (unsigned __int128)est >= (unsigned __int128)upd * st.m;
         {
@@ -657,6 +672,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         // claim lists carry the hinge in the layer slots from round 0 on
         if (!st.lists)
             HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
+        st.round0_updates = st.lists && g_opt.update_lists.load() > 0;
         {
             Timed tm(PH_FRONTIER, s);
             HIP_TRY(launch_round0(st, s));

@@ -34,6 +34,8 @@ struct PeelState {
     // list is partitioned by vertex and applied bucket by bucket in LDS, which also yields
     // the next round's claims (into st.claims_tmp).
     unsigned long long* dcount;  // rcap + 2 update counts: dcount[r] = deletes of round r
+    // round 0 writes layer 0's slots hinge first and its update list itself (claim lists only)
+    bool round0_updates;
     void* aux;              // partition histograms and scan scratch (part_aux_bytes)
 };
 
@@ -132,8 +134,11 @@ hipError_t launch_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
 hipError_t launch_edges_build(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t* rec, Ctrl* ctrl,
                               hipStream_t s);
 // Round 0: layer 0 from the degree-1 vertices -- atomicMin claims on the edge states, or with
-// st.lists the hinge test on the records, which leaves (edge, hinge) in the slots.
+// st.lists the hinge test on the records, which leaves (edge, hinge) in the slots -- or, with
+// st.round0_updates, the hinge-first slots and round 0's update list (count in dcount[0]);
+// layer 0 is then closed by launch_close_layer instead of an apply.
 hipError_t launch_round0(const PeelState& st, hipStream_t s);
+hipError_t launch_close_layer(const PeelState& st, uint32_t r, hipStream_t s);
 // How apply(r) deletes layer r and finds round r + 1: atomic deletes with atomicMin claims on
 // the edge states; atomic deletes with claims appended to st.claims (tripartite only); or
 // deletes appended to st.claims as an update list (tripartite only), applied afterwards by

@@ -181,6 +181,84 @@ __global__ __launch_bounds__(kPeelBlock) void k_round0_lists(const uint64_t* __r
     }
 }
 
+// Round 0 of a claim-list run whose round 0 deletes through an update list: the same hinge
+// test, and the hinge then does what apply(0) would do -- it writes the edge's slot hinge
+// first (vh, va, vb) to layer 0 and appends the deletes (va, e) and (vb, e) -- so layer 0 is
+// read once, here.
+using SlotAppender = BlockAppender<uint3, kPeelBlock, 4 * kPeelBlock>;
+__global__ __launch_bounds__(kPeelBlock) void k_round0_updates(const uint64_t* __restrict__ rec, uint64_t m,
+                                                               const uint32_t* __restrict__ edges, uint64_t P,
+                                                               uint64_t n, uint3* __restrict__ slots,
+                                                               unsigned long long* __restrict__ lcount,
+                                                               uint2* __restrict__ dels,
+                                                               unsigned long long* __restrict__ dcount, uint64_t dcap,
+                                                               Ctrl* ctrl)
+{
+    __shared__ SlotAppender lapp;
+    __shared__ ClaimListAppender dapp;
+    __shared__ unsigned long long s_deg, s_ones;
+    if (threadIdx.x == 0)
+        s_deg = s_ones = 0;
+    lapp.init();
+    dapp.init();
+    auto slot_out = [slots](uint64_t i, uint3 t) { slots[i] = t; };
+    auto del_out = [dels, dcap](uint64_t j, uint2 d) {
+        if (j < dcap) dels[j] = d;  // past the capacity: counted, not stored; the host checks
+    };
+    unsigned long long mydeg = 0, myones = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const uint64_t v = base + threadIdx.x;
+        bool hinge = false;
+        uint32_t e = 0, vh = 0, va = 0, vb = 0;
+        if (v < m) {
+            const uint64_t x = rec[v];
+            const uint32_t d = Rec::deg(x);
+            mydeg += d;
+            if (d > kMaxDegree)
+                atomicOr(&ctrl->err, kErrDegree);
+            if (d == 1 && Rec::edge(x) < n) {
+                e = (uint32_t)Rec::edge(x);
+                const uint32_t k = part_of((uint32_t)v, P);
+                myones++;
+                const uint32_t* t = edges + 3 * (uint64_t)e;
+                const uint32_t u0 = t[0], u1 = t[1], u2 = t[2];
+                const uint64_t x0 = (k >= 1 && u0 < m) ? rec[u0] : 0ull;
+                const uint64_t x1 = (k == 2 && u1 < m) ? rec[u1] : 0ull;
+                hinge = (k == 0 || Rec::deg(x0) != 1) && (k < 2 || Rec::deg(x1) != 1);
+                vh = k == 0 ? u0 : (k == 1 ? u1 : u2);
+                va = k == 0 ? u1 : (k == 1 ? u2 : u0);
+                vb = k == 0 ? u2 : (k == 1 ? u0 : u1);
+            }
+        }
+        lapp.push(hinge, make_uint3(vh, va, vb), false, make_uint3(0u, 0u, 0u), &lcount[0], slot_out);
+        dapp.push(hinge, make_uint2(va, e), hinge, make_uint2(vb, e), &dcount[0], del_out);
+    }
+    lapp.flush(&lcount[0], slot_out);
+    dapp.flush(&dcount[0], del_out);
+    if (mydeg) atomicAdd(&s_deg, mydeg);
+    if (myones) atomicAdd(&s_ones, myones);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_deg) atomicAdd(&ctrl->degsum, s_deg);
+        if (s_ones) {
+            atomicAdd(&ctrl->ftail, s_ones);
+            atomicAdd(&ctrl->claims, s_ones);
+        }
+    }
+}
+
+// Closes layer r without an apply (its slots were written by k_round0_updates).
+__global__ void k_close_layer(uint64_t* __restrict__ lstart, const unsigned long long* __restrict__ lcount, Ctrl* ctrl,
+                              uint32_t r)
+{
+    if (threadIdx.x == 0) {
+        lstart[r + 1] = lstart[r] + lcount[r];
+        if (lcount[r] == 0)
+            atomicMin(&ctrl->nrounds, r);
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Round r: delete layer r's edges and claim round r + 1.
 // ------------------------------------------------------------------------------------------
@@ -437,7 +515,11 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
     unsigned g = grid_for(st.m, 8192);
     if (st.lists) {
         if (!st.tripartite) return hipErrorInvalidValue;
-        k_round0_lists<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount, st.ctrl);
+        if (st.round0_updates)
+            k_round0_updates<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount,
+                                                      st.claims, st.dcount, st.m, st.ctrl);
+        else
+            k_round0_lists<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount, st.ctrl);
     } else if (st.tripartite)
         k_round0<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots, st.lcount,
                                                 st.ctrl);
@@ -464,6 +546,12 @@ hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, App
             MPHX_APPLY(false, ApplyMode::kAtomicClaims, false);
     }
 #undef MPHX_APPLY
+    return hipGetLastError();
+}
+
+hipError_t launch_close_layer(const PeelState& st, uint32_t r, hipStream_t s)
+{
+    k_close_layer<<<1, 64, 0, s>>>(st.lstart, st.lcount, st.ctrl, r);
     return hipGetLastError();
 }
 
