@@ -345,6 +345,69 @@ def random_ops(phase: str, st: dict) -> dict:
     return {}
 
 
+LOOKUP_KEYS = 10_000_000
+LOOKUP_BATCH = 1 << 16
+LOOKUP_REPEATS = 10
+
+
+def lookup_leg(mx, torch, r: dict, n: int, kind: int, keys=None, data=None, offs=None,
+               ceilings=None) -> dict:
+    """Evaluation of the MPHF just built, in the paper's lookup-experiment shape (Section 5,
+    Table 2): 10^7 distinct keys of the set (its first ones), in batches of 2^16 keys, all
+    batches repeated 10 times back to back on the stream; per-batch time from HIP events."""
+    nk = min(LOOKUP_KEYS, n)
+    dev = torch.device("cuda:0")
+    out = torch.empty(nk, dtype=torch.int64, device=dev)
+    codes, rank, P, seed = r["codes"], r["rank"], r["P"], r["seed_used"]
+
+    def run(b0, b1):
+        if kind == mx.KEYS_U64:
+            mx.lookup_u64(codes, rank, P, seed, keys[b0:b1], out=out[b0:b1])
+        else:
+            mx.lookup_str(codes, rank, P, seed, data, offs[b0:b1 + 1], out=out[b0:b1])
+
+    batches = [(b, min(b + LOOKUP_BATCH, nk)) for b in range(0, nk, LOOKUP_BATCH)]
+    run(0, nk)
+    torch.cuda.synchronize()
+    # the values of distinct keys are distinct and below n
+    distinct = int(torch.unique(out).numel())
+    ok = distinct == nk and int(out.min().item()) >= 0 and int(out.max().item()) < n
+    whole = out.clone()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(LOOKUP_REPEATS * len(batches) + 1)]
+    ev[0].record()
+    j = 1
+    for _ in range(LOOKUP_REPEATS):
+        for b0, b1 in batches:
+            run(b0, b1)
+            ev[j].record()
+            j += 1
+    torch.cuda.synchronize()
+    ok = ok and bool(torch.equal(out, whole))  # batched evaluation equals one call over all keys
+    per_key = []
+    for k in range(1, j):
+        b0, b1 = batches[(k - 1) % len(batches)]
+        per_key.append(ev[k - 1].elapsed_time(ev[k]) * 1e6 / (b1 - b0))  # ns per key
+    total_ms = ev[0].elapsed_time(ev[j - 1])
+    mean = sum(per_key) / len(per_key)
+    sd = (sum((x - mean) ** 2 for x in per_key) / len(per_key)) ** 0.5
+    lookups = LOOKUP_REPEATS * nk
+    rate = lookups / (total_ms / 1e3)
+    # each lookup gathers three code words, one rank sample and the hinge's rank block: about
+    # four random lines besides the streamed key
+    res = dict(workload=f"lookup_{nk}_keys_batches_of_{LOOKUP_BATCH}", keys=nk, batch=LOOKUP_BATCH,
+               batches=len(batches) * LOOKUP_REPEATS, ns_per_key=round(mean, 4), rel_std=round(sd / mean, 4),
+               lookups_per_s=round(rate, 1), values_distinct_and_in_range=ok,
+               paper_ns_per_key_one_core="199-415 (Table 2, three CPUs, one thread)")
+    if ceilings and ceilings.get("load8_Gops"):
+        res["roofline"] = dict(bound="random gathers", achieved=round(4 * rate / 1e9, 2),
+                               peak=ceilings["load8_Gops"], unit="G gathers/s",
+                               frac=round(4 * rate / 1e9 / ceilings["load8_Gops"], 3))
+    log(f"[lookup] {nk} keys in {len(batches)} batches of {LOOKUP_BATCH} x {LOOKUP_REPEATS}: "
+        f"{mean:.3f} ns/key per batch (rel. sd {sd / mean:.3f}), {rate / 1e9:.2f} G lookups/s, ok={ok}")
+    del out, whole
+    return res
+
+
 SERVE_WORKLOAD = "mwhc_served_poisson_sizes_loguniform_1e3_1e8_u64_or_str_gamma1.23"
 
 
@@ -448,8 +511,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="ceilings,plain,batched,served",
-                    help="comma list of: ceilings, plain, batched, served")
+    ap.add_argument("--legs", default="ceilings,plain,lookup,batched,served",
+                    help="comma list of: ceilings, plain, lookup (needs plain), batched, served")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
@@ -574,16 +637,26 @@ def main() -> int:
     if traffic is not None:
         roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roofline["traffic_GBps"] = round(traffic * phase_rows[dom]["launches"] / (phase_rows[dom]["ms"] / 1e3) / 1e9, 1)
-    # the dominant phase against the measured ceiling of the random operations it is made of
+    # the dominant phase against the measured ceilings of the random operations it is made of:
+    # each class's rate over the phase time, against the probe's rate for that class alone
     ops = random_ops(dom, st)
-    if ceilings and ops.get("atomics"):
+    if ceilings and ops:
         sec = phase_rows[dom]["ms"] / 1e3
-        ach_ops = ops["atomics"] / sec / 1e9
-        roofline["secondary"] = dict(bound="device atomics", achieved=round(ach_ops, 2),
-                                     peak=ceilings["atomic_add_ret_Gops"], unit="G atomics/s",
-                                     frac=round(ach_ops / ceilings["atomic_add_ret_Gops"], 3),
-                                     atomics_per_step=int(ops["atomics"]), gathers_per_step=int(ops["loads"]),
-                                     note="peak = measured returning 8-byte atomic rate over a 16 GiB table")
+        classes = {"atomics": ("atomic_add_ret_Gops", "returning 8-byte atomics"),
+                   "loads": ("load8_Gops", "8-byte gathers"), "stores": ("store1_Gops", "1-byte scattered stores")}
+        per = {}
+        for k, (ck, what) in classes.items():
+            if ops.get(k):
+                ach_ops = ops[k] / sec / 1e9
+                per[k] = dict(what=what, per_step=int(ops[k]), achieved=round(ach_ops, 2), peak=ceilings[ck],
+                              unit="G/s", frac=round(ach_ops / ceilings[ck], 3))
+        if per:
+            top = max(per.values(), key=lambda x: x["frac"])
+            roofline["secondary"] = dict(bound="random device-memory operations: " + top["what"],
+                                         achieved=top["achieved"], peak=top["peak"], unit="G/s", frac=top["frac"],
+                                         classes=per,
+                                         note="peaks = the probe kernels' rates over a 16 GiB table, each class "
+                                              "alone; the phase runs its classes concurrently")
 
     # ---- oracle on a bounded sample of the same workload ------------------------------------
     cpu = None
@@ -605,6 +678,12 @@ def main() -> int:
                    sample=f"first {ns} keys of the same generator, single-threaded C oracle, "
                           f"{cs:.1f} s (status {rc})")
         log(f"[bench] oracle: {ns} keys in {cs:.2f} s = {ns / cs / 1e6:.3f} M keys/s")
+
+    lookup = None
+    if "lookup" in legs:
+        lookup = lookup_leg(mx, torch, r, n, kind, keys=keys if kind == mx.KEYS_U64 else None,
+                            data=None if kind == mx.KEYS_U64 else data,
+                            offs=None if kind == mx.KEYS_U64 else offs, ceilings=ceilings)
 
     del ws, codes, rank
     if cfg["kind"] == "u64":
@@ -635,6 +714,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "ceilings": ceilings,
         "phases": phase_rows,
+        "lookup": lookup,
         "batched": batched,
         "served": served,
     }

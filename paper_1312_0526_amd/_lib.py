@@ -238,9 +238,12 @@ def mphf_workspace_bytes(n: int, gamma=(123, 100), kind: int = KEYS_U64) -> int:
     return int(lib().mphx_mphf_workspace_bytes(n, gamma[0], gamma[1], kind))
 
 
-def lookup_u64(codes, rank, P: int, seed: int, keys: torch.Tensor) -> torch.Tensor:
+def lookup_u64(codes, rank, P: int, seed: int, keys: torch.Tensor, out=None) -> torch.Tensor:
+    """MPHF values of keys; out (int64, one per key) may be preallocated."""
     _check(keys, torch.int64, "keys")
-    out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    _check(out, torch.int64, "out", keys.numel())
     rc = lib().mphx_mphf_lookup_u64(_ptr(codes), _ptr(rank), P, seed, _ptr(keys), keys.numel(), _ptr(out),
                                     _stream(keys.device))
     if rc:
@@ -248,11 +251,15 @@ def lookup_u64(codes, rank, P: int, seed: int, keys: torch.Tensor) -> torch.Tens
     return out
 
 
-def lookup_str(codes, rank, P: int, seed: int, data: torch.Tensor, offs: torch.Tensor) -> torch.Tensor:
+def lookup_str(codes, rank, P: int, seed: int, data: torch.Tensor, offs: torch.Tensor, out=None) -> torch.Tensor:
+    """MPHF values of the string keys data[offs[i]:offs[i+1]] (offs may be a slice of a larger
+    offset array: offsets are absolute in data); out may be preallocated."""
     _check(data, torch.uint8, "data")
     _check(offs, torch.int64, "offs")
     n = offs.numel() - 1
-    out = torch.empty(n, dtype=torch.int64, device=data.device)
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=data.device)
+    _check(out, torch.int64, "out", n)
     rc = lib().mphx_mphf_lookup_str(_ptr(codes), _ptr(rank), P, seed, _ptr(data), _ptr(offs), n, _ptr(out),
                                     _stream(data.device))
     if rc:

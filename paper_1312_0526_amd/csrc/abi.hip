@@ -775,7 +775,7 @@ int mphx_mphf_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P
     if (n == 0) return MPHX_OK;
     if (!codes || !rank || !bytes || !offs || !out || P == 0) return fail(MPHX_EINVAL, "null pointer or P = 0");
     if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
-    HIP_TRY(launch_lookup_str(codes, rank, P, seed, bytes, offs, n, out, (hipStream_t)stream));
+    HIP_TRY(launch_lookup_str_words(codes, rank, P, seed, bytes, offs, n, out, (hipStream_t)stream));
     return MPHX_OK;
 }
 

@@ -223,18 +223,26 @@ __device__ __forceinline__ void digest_str(const uint8_t* bytes, uint64_t off, u
     const uint64_t nw = (len + 7) >> 3;
     const uint64_t q0 = off >> 2;
     const uint32_t sh = (uint32_t)(off & 3) * 8;
-    uint32_t c0 = nw ? load_dword(bytes, q0, total) : 0u;
-    for (uint64_t j = 0; j < nw; j++) {
-        uint32_t c1 = load_dword(bytes, q0 + 2 * j + 1, total);
-        uint32_t c2 = (sh != 0 || j + 1 < nw) ? load_dword(bytes, q0 + 2 * j + 2, total) : 0u;
-        uint64_t lo = (uint64_t)c0 | ((uint64_t)c1 << 32);
-        uint64_t w = sh ? ((lo >> sh) | ((uint64_t)c2 << (64 - sh))) : lo;
-        uint64_t rem = len - 8 * j;
-        if (rem < 8)
-            w &= (1ull << (8 * rem)) - 1;
-        A += fin(w ^ (sa + j * kGamma));
-        B += fin(w ^ (sb + j * kGamma));
-        c0 = c2;
+    // four words per step, their nine dwords loaded before any is used (one round trip)
+    constexpr uint32_t kStep = 4;
+    for (uint64_t j0 = 0; j0 < nw; j0 += kStep) {
+        uint32_t c[2 * kStep + 1];
+#pragma unroll
+        for (uint32_t k = 0; k < 2 * kStep + 1; k++)
+            c[k] = 2 * j0 + k <= 2 * nw ? load_dword(bytes, q0 + 2 * j0 + k, total) : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < kStep; u++) {
+            const uint64_t j = j0 + u;
+            if (j < nw) {
+                const uint64_t lo = (uint64_t)c[2 * u] | ((uint64_t)c[2 * u + 1] << 32);
+                uint64_t w = sh ? ((lo >> sh) | ((uint64_t)c[2 * u + 2] << (64 - sh))) : lo;
+                const uint64_t rem = len - 8 * j;
+                if (rem < 8)
+                    w &= (1ull << (8 * rem)) - 1;
+                A += fin(w ^ (sa + j * kGamma));
+                B += fin(w ^ (sb + j * kGamma));
+            }
+        }
     }
     a = fin(A ^ sa ^ len);
     b = fin(B ^ sb ^ len);
@@ -255,13 +263,22 @@ __device__ __forceinline__ uint32_t code_at(const uint64_t* codes, uint32_t v)
 
 __device__ __forceinline__ uint64_t rank_of(const uint64_t* codes, const uint64_t* rank, uint32_t h)
 {
-    uint64_t r = rank[h >> 9];
-    const uint64_t w1 = h >> 5;
-    for (uint64_t w = (uint64_t)(h >> 9) * 16; w < w1; w++)
-        r += nz_pairs(codes[w]);
-    uint32_t below = 2 * (h & 31);
-    uint64_t mask = below ? ((1ull << below) - 1) : 0ull;
-    return r + nz_pairs(codes[w1] & mask);
+    // the rank sample and the block's words up to h's own, all loads issued together (the
+    // words past h's are not read: they may lie past the end of the code array)
+    const uint64_t r = rank[h >> 9];
+    const uint32_t w0 = (h >> 9) * 16, w1 = h >> 5;
+    const uint32_t below = 2 * (h & 31);
+    const uint64_t mask = below ? ((1ull << below) - 1) : 0ull;
+    uint32_t acc = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 16; k++) {
+        const uint32_t w = w0 + k;
+        uint64_t x = w <= w1 ? codes[w] : 0ull;
+        if (w == w1)
+            x &= mask;
+        acc += nz_pairs(x);
+    }
+    return r + acc;
 }
 
 __device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,

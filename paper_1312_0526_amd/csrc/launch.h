@@ -159,8 +159,10 @@ hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint3
 hipError_t launch_pack_count(const uint8_t* code8, uint64_t m, uint64_t* codes, uint32_t* bcount, hipStream_t s);
 hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
                              const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s);
-hipError_t launch_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
-                             const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out, hipStream_t s);
+// string keys: the word-parallel digest of the hashing kernel, then the evaluation (keys.hip)
+hipError_t launch_lookup_str_words(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                                   const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
+                                   hipStream_t s);
 hipError_t launch_bijection(const uint64_t* vals, uint64_t n, uint32_t* bitmap, Ctrl* ctrl, hipStream_t s);
 
 }  // namespace mphx

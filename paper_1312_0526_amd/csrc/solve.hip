@@ -79,25 +79,6 @@ __global__ __launch_bounds__(256) void k_lookup_u64(const uint64_t* __restrict__
     }
 }
 
-__global__ __launch_bounds__(256) void k_lookup_str(const uint64_t* __restrict__ codes, const uint64_t* __restrict__ rank,
-                                                    uint64_t P, uint64_t seed, const uint8_t* __restrict__ bytes,
-                                                    const uint64_t* __restrict__ offs, uint64_t n,
-                                                    uint64_t* __restrict__ out)
-{
-    const uint64_t total = offs[n];
-    const uint64_t sa = fin(seed + kGamma);
-    const uint64_t sb = fin(seed + 2 * kGamma);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        uint64_t o0 = offs[i], o1 = offs[i + 1];
-        uint64_t a, b;
-        digest_str(bytes, o0, o1 - o0, total, sa, sb, a, b);
-        uint32_t v0, v1, v2;
-        edge_of_digest(a, b, P, v0, v1, v2);
-        out[i] = eval_edge(codes, rank, v0, v1, v2);
-    }
-}
-
 __global__ __launch_bounds__(256) void k_bijection(const uint64_t* __restrict__ vals, uint64_t n,
                                                    uint32_t* __restrict__ bitmap, Ctrl* ctrl)
 {
@@ -144,14 +125,6 @@ hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64
 {
     if (n == 0) return hipSuccess;
     k_lookup_u64<<<grid_cap(n, 16384), 256, 0, s>>>(codes, rank, P, seed, keys, n, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_lookup_str(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
-                             const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out, hipStream_t s)
-{
-    if (n == 0) return hipSuccess;
-    k_lookup_str<<<grid_cap(n, 16384), 256, 0, s>>>(codes, rank, P, seed, bytes, offs, n, out);
     return hipGetLastError();
 }
 

@@ -263,6 +263,36 @@ def test_mphf_str(mx, o, record):
                           o.lookup_str(ref["words"], ref["rank"], ref["P"], ref["seed_used"], data, offs))
 
 
+def test_lookup_in_batches_of_2_16(mx, o):
+    """The lookup experiment's shape (Section 5, Table 2): keys evaluated in batches of 2^16,
+    each batch one call on a slice of the offsets (absolute in the byte array) writing a slice
+    of a preallocated output; the batches, with a ragged last one, equal the oracle's values."""
+    import torch
+
+    n = 3 * (1 << 16) + 4321
+    data, offs = workloads.str_keys(n, gen_seed=9)
+    got = mx.mphf_build_str(dev(data), dev(offs), seed=2)
+    rc, ref = o.mphf_build_str(data, offs, seed=2)
+    assert rc == 0
+    d_data, d_offs = dev(data), dev(offs)
+    out = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    for b0 in range(0, n, 1 << 16):
+        b1 = min(b0 + (1 << 16), n)
+        mx.lookup_str(got["codes"], got["rank"], got["P"], got["seed_used"], d_data, d_offs[b0:b1 + 1], out=out[b0:b1])
+    want = o.lookup_str(ref["words"], ref["rank"], ref["P"], ref["seed_used"], data, offs)
+    assert np.array_equal(host(out, np.uint64), want)
+    keys = workloads.u64_keys(n, gen_seed=10)
+    got = mx.mphf_build_u64(dev(keys), seed=3)
+    rc, ref = o.mphf_build_u64(keys, seed=3)
+    assert rc == 0
+    d_keys = dev(keys)
+    out.fill_(-1)
+    for b0 in range(0, n, 1 << 16):
+        b1 = min(b0 + (1 << 16), n)
+        mx.lookup_u64(got["codes"], got["rank"], got["P"], got["seed_used"], d_keys[b0:b1], out=out[b0:b1])
+    assert np.array_equal(host(out, np.uint64), o.lookup_u64(ref["words"], ref["rank"], ref["P"], ref["seed_used"], keys))
+
+
 def test_mphf_core_and_duplicates(mx, o):
     keys = workloads.u64_keys(50_000)
     with pytest.raises(mx.MphxError) as ei:
