@@ -49,6 +49,15 @@ def _bind(lib):
                                          C.c_uint32, _u64p, _u64p, _u64p]),
         "orc_mphf_build_str": (C.c_int, [_u8p, _u64p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
                                          C.c_uint32, _u64p, _u64p, _u64p]),
+        "orc_sf_bits": (C.c_uint32, [C.c_uint64]),
+        "orc_sf_assign": (C.c_int, [_u32p, C.c_uint64, C.c_uint64, _u32p, _u32p, _u8p, _u32p, C.c_uint64, _u32p]),
+        "orc_sf_pack": (None, [_u32p, C.c_uint64, C.c_uint32, _u64p]),
+        "orc_sf_build_u64": (C.c_int, [_u64p, _u32p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
+                                       C.c_uint32, _u64p, _u64p]),
+        "orc_sf_build_str": (C.c_int, [_u8p, _u64p, _u32p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32,
+                                       C.c_uint32, C.c_uint32, _u64p, _u64p]),
+        "orc_sf_lookup_u64": (None, [_u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u64p, C.c_uint64, _u64p]),
+        "orc_sf_lookup_str": (None, [_u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u8p, _u64p, C.c_uint64, _u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -199,6 +208,89 @@ class Oracle:
         r = np.ascontiguousarray(rank, dtype=np.uint64) if len(rank) else np.zeros(1, np.uint64)
         self.lib.orc_lookup_str(_p(w, _u64p), _p(r, _u64p), P, seed, _p(data, _u8p), _p(offs, _u64p), n,
                                 _p(out, _u64p))
+        return out
+
+
+    # --- static functions (Section 3: f(x) = u[h0] + u[h1] + u[h2] mod sigma) -------------------
+    def sf_bits(self, sigma: int) -> int:
+        return int(self.lib.orc_sf_bits(sigma))
+
+    def sf_words(self, m: int, sigma: int) -> int:
+        return (m * self.sf_bits(sigma) + 63) // 64
+
+    def sf_assign(self, edges, m, order, rnd, hinge, values, sigma):
+        """u (uint32, one per vertex) from a complete peel (orc_peel's outputs)."""
+        n = len(order)
+        u = np.zeros(max(m, 1), np.uint32)
+        e = np.ascontiguousarray(edges, dtype=np.uint32).reshape(-1) if n else np.zeros(3, np.uint32)
+        o = np.ascontiguousarray(order, dtype=np.uint32) if n else np.zeros(1, np.uint32)
+        r = np.ascontiguousarray(rnd, dtype=np.uint32) if n else np.zeros(1, np.uint32)
+        h = np.ascontiguousarray(hinge, dtype=np.uint8) if n else np.zeros(1, np.uint8)
+        v = np.ascontiguousarray(values, dtype=np.uint32) if n else np.zeros(1, np.uint32)
+        rc = self.lib.orc_sf_assign(_p(e, _u32p), n, m, _p(o, _u32p), _p(r, _u32p), _p(h, _u8p), _p(v, _u32p),
+                                    sigma, _p(u, _u32p))
+        return int(rc), u[:m]
+
+    def sf_pack(self, u, sigma):
+        m = len(u)
+        b = self.sf_bits(sigma)
+        words = np.zeros(max((m * b + 63) // 64, 1), np.uint64)
+        uu = np.ascontiguousarray(u, dtype=np.uint32) if m else np.zeros(1, np.uint32)
+        self.lib.orc_sf_pack(_p(uu, _u32p), m, b, _p(words, _u64p))
+        return words[: (m * b + 63) // 64]
+
+    def sf_build_u64(self, keys, values, sigma, seed=0, gnum=123, gden=100, max_tries=64):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        values = np.ascontiguousarray(values, dtype=np.uint32)
+        n = len(keys)
+        P = self.part_size(n, gnum, gden)
+        nw = self.sf_words(3 * P, sigma) if sigma else 0
+        words = np.zeros(max(nw, 1), np.uint64)
+        info = np.zeros(6, np.uint64)
+        k = keys if n else np.zeros(1, np.uint64)
+        v = values if n else np.zeros(1, np.uint32)
+        rc = self.lib.orc_sf_build_u64(_p(k, _u64p), _p(v, _u32p), n, sigma, seed, gnum, gden, max_tries,
+                                       _p(words, _u64p), _p(info, _u64p))
+        return int(rc), self._sf_result(words[:nw], info)
+
+    def sf_build_str(self, data, offs, values, sigma, seed=0, gnum=123, gden=100, max_tries=64):
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        if data.size == 0:
+            data = np.zeros(1, np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        values = np.ascontiguousarray(values, dtype=np.uint32)
+        n = len(offs) - 1
+        P = self.part_size(n, gnum, gden)
+        nw = self.sf_words(3 * P, sigma) if sigma else 0
+        words = np.zeros(max(nw, 1), np.uint64)
+        info = np.zeros(6, np.uint64)
+        v = values if n else np.zeros(1, np.uint32)
+        rc = self.lib.orc_sf_build_str(_p(data, _u8p), _p(offs, _u64p), _p(v, _u32p), n, sigma, seed, gnum, gden,
+                                       max_tries, _p(words, _u64p), _p(info, _u64p))
+        return int(rc), self._sf_result(words[:nw], info)
+
+    @staticmethod
+    def _sf_result(words, info):
+        return dict(words=words, P=int(info[0]), m=int(info[1]), seed_used=int(info[2]), tries=int(info[3]),
+                    n_rounds=int(info[4]), n_core=int(info[5]))
+
+    def sf_lookup_u64(self, words, sigma, P, seed, keys):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.empty(len(keys), np.uint64)
+        w = np.ascontiguousarray(words, dtype=np.uint64) if len(words) else np.zeros(1, np.uint64)
+        self.lib.orc_sf_lookup_u64(_p(w, _u64p), sigma, P, seed, _p(keys, _u64p), len(keys), _p(out, _u64p))
+        return out
+
+    def sf_lookup_str(self, words, sigma, P, seed, data, offs):
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        if data.size == 0:
+            data = np.zeros(1, np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        n = len(offs) - 1
+        out = np.empty(n, np.uint64)
+        w = np.ascontiguousarray(words, dtype=np.uint64) if len(words) else np.zeros(1, np.uint64)
+        self.lib.orc_sf_lookup_str(_p(w, _u64p), sigma, P, seed, _p(data, _u8p), _p(offs, _u64p), n,
+                                   _p(out, _u64p))
         return out
 
 

@@ -40,7 +40,11 @@
  *    1 / 2 = hinge with g = 1 / 2, 3 = hinge with g = 0;
  *  - rank table: one u64 per 512 vertices holding the number of hinge vertices strictly
  *    before the block (exclusive rank), so the MPHF maps onto [0, n);
- *  - retries: seed, seed+1, ... up to max_tries; degree above 255 is an error.
+ *  - retries: seed, seed+1, ... up to max_tries; degree above 255 is an error;
+ *  - static functions (Section 3, any sigma in [1, 2^32]): values must lie in [0, sigma);
+ *    u = 0 on vertices that are no hinge; each u is stored in b = (bits of sigma - 1) bits,
+ *    vertex v's field at bits [v*b, v*b + b) of the little-endian bit string of the u64
+ *    words (b = 0 when sigma = 1: nothing is stored and every lookup is 0).
  *
  * No floating point anywhere.  All arithmetic is on unsigned integers.
  */
@@ -414,6 +418,97 @@ void orc_lookup_str(const uint64_t* words, const uint64_t* rank, uint64_t P, uin
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Static function (Section 3): u in [sigma]^m with f(x) = u[h0(x)] + u[h1(x)] + u[h2(x)]
+ * (mod sigma) for every key, solved like the MPHF's g along the layers in reverse round order:
+ * the hinge vertex of x's edge takes f(x) minus the other two vertices' values.
+ * ------------------------------------------------------------------------------------------ */
+uint32_t orc_sf_bits(uint64_t sigma)
+{
+    uint32_t b = 0;
+    while (b < 64 && ((sigma - 1) >> b) != 0)
+        b++;
+    return b;
+}
+
+int orc_sf_assign(const uint32_t* edges, uint64_t n, uint64_t m, const uint32_t* order, const uint32_t* round,
+                  const uint8_t* hinge, const uint32_t* values, uint64_t sigma, uint32_t* u)
+{
+    for (uint64_t v = 0; v < m; v++)
+        u[v] = 0;
+    uint64_t end = n;
+    while (end > 0) {
+        uint32_t rr = round[order[end - 1]];
+        if (rr == ORC_NONE)
+            return ORC_ECORE;
+        uint64_t begin = end;
+        while (begin > 0 && round[order[begin - 1]] == rr)
+            begin--;
+        for (uint64_t i = begin; i < end; i++) {
+            uint64_t e = order[i];
+            uint32_t k = hinge[e];
+            uint32_t vk = edges[3 * e + k];
+            uint32_t v1 = edges[3 * e + (k + 1) % 3];
+            uint32_t v2 = edges[3 * e + (k + 2) % 3];
+            /* f(x) = u[vk] + u[v1] + u[v2] (mod sigma) */
+            u[vk] = (uint32_t)((values[e] + 2 * sigma - u[v1] - u[v2]) % sigma);
+        }
+        end = begin;
+    }
+    return ORC_OK;
+}
+
+/* Fields of b bits, vertex v at bit v*b of the little-endian bit string of the words. */
+void orc_sf_pack(const uint32_t* u, uint64_t m, uint32_t b, uint64_t* words)
+{
+    uint64_t nwords = (m * b + 63) / 64;
+    for (uint64_t w = 0; w < nwords; w++)
+        words[w] = 0;
+    for (uint64_t v = 0; v < m; v++)
+        for (uint32_t t = 0; t < b; t++) {
+            uint64_t bit = v * b + t;
+            words[bit / 64] |= (uint64_t)((u[v] >> t) & 1u) << (bit % 64);
+        }
+}
+
+static uint64_t orc_sf_field(const uint64_t* words, uint32_t b, uint64_t v)
+{
+    uint64_t x = 0;
+    for (uint32_t t = 0; t < b; t++) {
+        uint64_t bit = v * b + t;
+        x |= ((words[bit / 64] >> (bit % 64)) & 1u) << t;
+    }
+    return x;
+}
+
+static uint64_t orc_sf_eval_edge(const uint64_t* words, uint64_t sigma, const uint32_t t[3])
+{
+    uint32_t b = orc_sf_bits(sigma);
+    return (orc_sf_field(words, b, t[0]) + orc_sf_field(words, b, t[1]) + orc_sf_field(words, b, t[2])) % sigma;
+}
+
+void orc_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed, const uint64_t* keys,
+                       uint64_t n, uint64_t* out)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t t[3];
+        orc_hash_u64(keys + i, 1, seed, P, t);
+        out[i] = orc_sf_eval_edge(words, sigma, t);
+    }
+}
+
+void orc_sf_lookup_str(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed, const uint8_t* bytes,
+                       const uint64_t* offs, uint64_t n, uint64_t* out)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t a, b;
+        uint32_t t[3];
+        orc_digest_str(bytes + offs[i], offs[i + 1] - offs[i], seed, &a, &b);
+        orc_edge_of_digest(a, b, P, t);
+        out[i] = orc_sf_eval_edge(words, sigma, t);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------
  * Whole MPHF build: hash (Section 3 / 4.3), peel (Section 4.2), retry with the next seed
  * while a 2-core remains, assign (Section 3 / 4.3), pack and rank (Section 5).
  * info[0] = P, info[1] = m, info[2] = seed used, info[3] = tries, info[4] = rounds,
@@ -441,12 +536,21 @@ static int orc_cmp_triple(const void* pa, const void* pb)
     return a < b ? -1 : (a > b);
 }
 
-static int orc_mphf_build(int kind, const void* keys, const uint64_t* offs, uint64_t n, uint64_t seed,
-                          uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* words,
-                          uint64_t* rank, uint64_t* info)
+/* values == NULL: the MPHF (words = 2-bit codes, rank = samples); else the static function
+ * with those values in [0, sigma) (words = packed u, rank unused). */
+static int orc_build(int kind, const void* keys, const uint64_t* offs, uint64_t n, const uint32_t* values,
+                     uint64_t sigma, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+                     uint64_t* words, uint64_t* rank, uint64_t* info)
 {
     if (gden == 0 || gnum == 0 || max_tries == 0 || n > 0xFFFFFFFFull)
         return ORC_EINVAL;
+    if (values) {
+        if (sigma == 0 || sigma > 0x100000000ull)
+            return ORC_EINVAL;
+        for (uint64_t i = 0; i < n; i++)
+            if (values[i] >= sigma)
+                return ORC_EINVAL;
+    }
     uint64_t P = orc_part_size(n, gnum, gden);
     uint64_t m = 3 * P;
     if (m > 0x100000000ull)
@@ -476,13 +580,22 @@ static int orc_mphf_build(int kind, const void* keys, const uint64_t* offs, uint
             break;
         }
         if (pinfo[0] == n) {
-            rc = orc_assign(edges, n, m, order, round, hinge, codes8);
-            if (rc != ORC_OK) {
-                status = rc;
-                break;
+            if (values) {
+                uint32_t* u = malloc((m ? m : 1) * sizeof(uint32_t));
+                if (!u) {
+                    status = ORC_ENOMEM;
+                    break;
+                }
+                rc = orc_sf_assign(edges, n, m, order, round, hinge, values, sigma, u);
+                if (rc == ORC_OK)
+                    orc_sf_pack(u, m, orc_sf_bits(sigma), words);
+                free(u);
+            } else {
+                rc = orc_assign(edges, n, m, order, round, hinge, codes8);
+                if (rc == ORC_OK)
+                    orc_pack_rank(codes8, m, words, rank);
             }
-            orc_pack_rank(codes8, m, words, rank);
-            status = ORC_OK;
+            status = rc;
             break;
         }
     }
@@ -524,12 +637,25 @@ static int orc_mphf_build(int kind, const void* keys, const uint64_t* offs, uint
 int orc_mphf_build_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gnum, uint32_t gden,
                        uint32_t max_tries, uint64_t* words, uint64_t* rank, uint64_t* info)
 {
-    return orc_mphf_build(0, keys, NULL, n, seed, gnum, gden, max_tries, words, rank, info);
+    return orc_build(0, keys, NULL, n, NULL, 0, seed, gnum, gden, max_tries, words, rank, info);
 }
 
 int orc_mphf_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed,
                        uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* words,
                        uint64_t* rank, uint64_t* info)
 {
-    return orc_mphf_build(1, bytes, offs, n, seed, gnum, gden, max_tries, words, rank, info);
+    return orc_build(1, bytes, offs, n, NULL, 0, seed, gnum, gden, max_tries, words, rank, info);
+}
+
+int orc_sf_build_u64(const uint64_t* keys, const uint32_t* values, uint64_t n, uint64_t sigma, uint64_t seed,
+                     uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* words, uint64_t* info)
+{
+    return orc_build(0, keys, NULL, n, values, sigma, seed, gnum, gden, max_tries, words, NULL, info);
+}
+
+int orc_sf_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t* values, uint64_t n,
+                     uint64_t sigma, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+                     uint64_t* words, uint64_t* info)
+{
+    return orc_build(1, bytes, offs, n, values, sigma, seed, gnum, gden, max_tries, words, NULL, info);
 }

@@ -417,9 +417,72 @@ def pin_string_digest(o) -> list:
     return bad
 
 
+def pin_static_function(o, seed=6) -> list:
+    """Static functions (Section 3): the lookup returns every key's value for several sigma;
+    u is zero off the hinges; with sigma = 3 and the hinge positions as values, u is the MPHF's
+    g (two separate assignments); the packed layout equals the closed form sum of u[v] << b*v."""
+    bad = []
+    rng = np.random.default_rng(seed)
+    n = 20000
+    keys = workloads.u64_keys(n, gen_seed=seed)
+    for sigma in (1, 2, 3, 7, 256, 1_000_003, 1 << 32):
+        values = (rng.integers(0, sigma, n, dtype=np.uint64)).astype(np.uint32)
+        rc, r = o.sf_build_u64(keys, values, sigma, seed=1)
+        if rc != 0:
+            bad.append(f"sf u64 sigma={sigma}: status {rc}")
+            continue
+        b = o.sf_bits(sigma)
+        if b != (sigma - 1).bit_length() or len(r["words"]) != (r["m"] * b + 63) // 64:
+            bad.append(f"sf sigma={sigma}: {b} bits, {len(r['words'])} words")
+        f = o.sf_lookup_u64(r["words"], sigma, r["P"], r["seed_used"], keys)
+        if not np.array_equal(f, values.astype(np.uint64)):
+            bad.append(f"sf u64 sigma={sigma}: lookup differs from the values at {int((f != values).sum())} keys")
+    data, offs = workloads.str_keys(7000, gen_seed=seed)
+    values = rng.integers(0, 1000, 7000).astype(np.uint32)
+    rc, r = o.sf_build_str(data, offs, values, 1000, seed=2)
+    f = o.sf_lookup_str(r["words"], 1000, r["P"], r["seed_used"], data, offs) if rc == 0 else None
+    if rc != 0 or not np.array_equal(f, values.astype(np.uint64)):
+        bad.append(f"sf str: status {rc} or lookup differs from the values")
+    # zero off the hinges; the MPHF is the case sigma = 3, f = hinge position
+    P = o.part_size(5000)
+    for hseed in range(20):  # the first hash seed whose graph peels completely
+        edges = o.hash_u64(workloads.u64_keys(5000, gen_seed=seed + 1), hseed, P)
+        rc, pr = o.peel(edges, 3 * P, P)
+        if rc == 0 and pr["n_peeled"] == 5000:
+            break
+    if rc == 0 and pr["n_peeled"] == 5000:
+        vals = rng.integers(0, 97, 5000).astype(np.uint32)
+        rc1, u = o.sf_assign(edges, 3 * P, pr["order"], pr["round"], pr["hinge"], vals, 97)
+        hinges = np.zeros(3 * P, bool)
+        hinges[edges[np.arange(5000), pr["hinge"].astype(np.int64)]] = True
+        if rc1 != 0 or (u[~hinges] != 0).any() or (u >= 97).any():
+            bad.append("sf: u not zero off the hinges or not below sigma")
+        rc2, u3 = o.sf_assign(edges, 3 * P, pr["order"], pr["round"], pr["hinge"], pr["hinge"].astype(np.uint32), 3)
+        rc3, codes8 = o.assign(edges, 3 * P, pr["order"], pr["round"], pr["hinge"])
+        if rc2 != 0 or rc3 != 0 or not np.array_equal(u3, (codes8 % 3).astype(np.uint32)):
+            bad.append("sf: sigma = 3 with the hinge positions does not give the MPHF's g")
+    else:
+        bad.append("sf: the 5000-edge test graph did not peel")
+    # packing: v's b bits at bit b*v of the little-endian bit string (straddling word ends)
+    for b_sigma, count in ((32, 5), (128, 10), (1 << 20, 7), (1 << 32, 3)):
+        u = rng.integers(0, b_sigma, count, dtype=np.uint64).astype(np.uint32)
+        b = (b_sigma - 1).bit_length()
+        big = sum(int(x) << (b * v) for v, x in enumerate(u))
+        nw = (count * b + 63) // 64
+        want = np.array([(big >> (64 * w)) & ((1 << 64) - 1) for w in range(nw)], np.uint64)
+        if not np.array_equal(o.sf_pack(u, b_sigma), want):
+            bad.append(f"sf pack b={b}: differs from the closed form")
+    # values outside [0, sigma) and sigma = 0 are rejected
+    rc, _ = o.sf_build_u64(keys[:100], np.full(100, 7, np.uint32), 7)
+    rc0, _ = o.sf_build_u64(keys[:100], np.zeros(100, np.uint32), 0)
+    if rc != -1 or rc0 != -1:
+        bad.append(f"sf: value >= sigma gave {rc}, sigma = 0 gave {rc0} (EINVAL expected)")
+    return bad
+
+
 ALL_PINS = [pin_splitmix, pin_hash_closed_form, pin_part_size, pin_worked_examples,
             pin_bruteforce_tripartite, pin_bruteforce_generic, pin_invariants, pin_mphf, pin_errors,
-            pin_string_digest]
+            pin_string_digest, pin_static_function]
 
 
 def run_all(o, pins=None) -> list:
