@@ -446,11 +446,11 @@ int orc_sf_assign(const uint32_t* edges, uint64_t n, uint64_t m, const uint32_t*
         for (uint64_t i = begin; i < end; i++) {
             uint64_t e = order[i];
             uint32_t k = hinge[e];
-            uint32_t vk = edges[3 * e + k];
-            uint32_t v1 = edges[3 * e + (k + 1) % 3];
-            uint32_t v2 = edges[3 * e + (k + 2) % 3];
-            /* f(x) = u[vk] + u[v1] + u[v2] (mod sigma) */
-            u[vk] = (uint32_t)((values[e] + 2 * sigma - u[v1] - u[v2]) % sigma);
+            uint32_t vh = edges[3 * e + k];
+            uint32_t va = edges[3 * e + (k + 1) % 3];
+            uint32_t vb = edges[3 * e + (k + 2) % 3];
+            /* f(x) = u[vh] + u[va] + u[vb] (mod sigma) */
+            u[vh] = (uint32_t)((values[e] + 2 * sigma - u[va] - u[vb]) % sigma);
         }
         end = begin;
     }

@@ -35,7 +35,7 @@ MUTANTS = {
     "duplicates reported as core": ("status = ORC_EDUP;", "status = ORC_ECORE;"),
     "part size rounds down": ("return (uint64_t)((num + den - 1) / den);", "return (uint64_t)(num / den);"),
     "rank counts only g = 0": ("count += codes8[v] != 0;", "count += codes8[v] == 3;"),
-    "static function sign flipped": ("(values[e] + 2 * sigma - u[v1] - u[v2]) % sigma", "(values[e] + u[v1] + u[v2]) % sigma"),
+    "static function sign flipped": ("(values[e] + 2 * sigma - u[va] - u[vb]) % sigma", "(values[e] + u[va] + u[vb]) % sigma"),
     "static function field one bit short": ("while (b < 64 && ((sigma - 1) >> b) != 0)", "while (b < 64 && ((sigma - 1) >> (b + 1)) != 0)"),
     "static function packing shifted": ("|= (uint64_t)((u[v] >> t) & 1u) << (bit % 64);", "|= (uint64_t)((u[v] >> t) & 1u) << ((bit + 1) % 64);"),
     "static function lookup drops a vertex": ("+ orc_sf_field(words, b, t[2])) % sigma", ") % sigma"),
