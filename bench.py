@@ -408,6 +408,64 @@ def lookup_leg(mx, torch, r: dict, n: int, kind: int, keys=None, data=None, offs
     return res
 
 
+SF_SIGMA = 256
+
+
+def sf_leg(args, mx, torch, n: int, kind: int, ws, keys=None, data=None, offs=None) -> dict:
+    """Static function (Section 3) of the same keys: sigma = 256, key i's value a byte of
+    SplitMix64 output i + 1 at state 7 (made on the device); builds timed like the plain leg,
+    with the first 10^7 keys' lookups checked against their values."""
+    dev = torch.device("cuda:0")
+    gamma = (123, 100)
+    vals = torch.empty(n, dtype=torch.int32, device=dev)
+    G, M1, M2 = 0x9E3779B97F4A7C15, 0xBF58476D1CE4E5B9, 0x94D049BB133111EB
+
+    def to_i64(x):
+        return x - (1 << 64) if x >= 1 << 63 else x
+
+    chunk = 1 << 27
+    for c0 in range(0, n, chunk):
+        c1 = min(c0 + chunk, n)
+        z = (torch.arange(c0 + 1, c1 + 1, dtype=torch.int64, device=dev) * to_i64(G)) + 7
+        z = (z ^ ((z >> 30) & ((1 << 34) - 1))) * to_i64(M1)
+        z = (z ^ ((z >> 27) & ((1 << 37) - 1))) * to_i64(M2)
+        z = z ^ ((z >> 31) & ((1 << 33) - 1))
+        vals[c0:c1] = (z & (SF_SIGMA - 1)).to(torch.int32)
+        del z
+    words = torch.empty(max(mx.sf_words(n, SF_SIGMA, gamma), 1), dtype=torch.int64, device=dev)
+    if ws.numel() < mx.sf_workspace_bytes(n, gamma, kind):  # without claim lists the values need 4n more
+        ws = torch.empty(mx.sf_workspace_bytes(n, gamma, kind), dtype=torch.uint8, device=dev)
+
+    def step():
+        if kind == mx.KEYS_U64:
+            return mx.sf_build_u64(keys, vals, SF_SIGMA, seed=0, gamma=gamma, ws=ws, words=words)
+        return mx.sf_build_str(data, offs, vals, SF_SIGMA, seed=0, gamma=gamma, ws=ws, words=words)
+
+    r = step()
+    torch.cuda.synchronize()
+    mx.phase_times(reset=True)
+    t0 = time.perf_counter()
+    steps = max(1, min(args.steps, 3))
+    for _ in range(steps):
+        r = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    phases = {k: round(v[0] / steps, 3) for k, v in mx.phase_times(reset=True).items() if v[1]}
+    nk = min(LOOKUP_KEYS, n)
+    if kind == mx.KEYS_U64:
+        f = mx.sf_lookup_u64(r["words"], SF_SIGMA, r["P"], r["seed_used"], keys[:nk])
+    else:
+        f = mx.sf_lookup_str(r["words"], SF_SIGMA, r["P"], r["seed_used"], data, offs[: nk + 1])
+    ok = bool(torch.equal(f, vals[:nk].to(torch.int64)))
+    res = dict(workload=f"static_function_sigma{SF_SIGMA}_same_keys", sigma=SF_SIGMA, bits=mx.sf_bits(SF_SIGMA),
+               ms_per_build=round(sec * 1e3, 3), keys_per_s=round(n / sec, 1), tries=r["tries"],
+               rounds=r["n_rounds"], bits_per_key=round(mx.sf_bits(SF_SIGMA) * r["m"] / n, 3),
+               lookups_equal_values=ok, phases_ms=phases)
+    log(f"[sf] sigma {SF_SIGMA}: {sec * 1e3:.1f} ms/build, {n / sec / 1e9:.3f} G keys/s, lookups ok={ok}")
+    del vals, words, f
+    return res
+
+
 SERVE_WORKLOAD = "mwhc_served_poisson_sizes_loguniform_1e3_1e8_u64_or_str_gamma1.23"
 
 
@@ -511,8 +569,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="ceilings,plain,lookup,batched,served",
-                    help="comma list of: ceilings, plain, lookup (needs plain), batched, served")
+    ap.add_argument("--legs", default="ceilings,plain,lookup,sf,batched,served",
+                    help="comma list of: ceilings, plain, lookup and sf (need plain), batched, served")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
@@ -685,6 +743,15 @@ def main() -> int:
                             data=None if kind == mx.KEYS_U64 else data,
                             offs=None if kind == mx.KEYS_U64 else offs, ceilings=ceilings)
 
+    sf = None
+    if "sf" in legs:  # the MPHF's tables go; its counts stay for the headline line
+        r = {k: v for k, v in r.items() if not isinstance(v, torch.Tensor)}
+        del codes, rank
+        codes = rank = None
+        torch.cuda.empty_cache()
+        sf = sf_leg(args, mx, torch, n, kind, ws, keys=keys if kind == mx.KEYS_U64 else None,
+                    data=None if kind == mx.KEYS_U64 else data, offs=None if kind == mx.KEYS_U64 else offs)
+
     del ws, codes, rank
     if cfg["kind"] == "u64":
         del keys
@@ -715,6 +782,7 @@ def main() -> int:
         "ceilings": ceilings,
         "phases": phase_rows,
         "lookup": lookup,
+        "static_function": sf,
         "batched": batched,
         "served": served,
     }

@@ -153,6 +153,38 @@ MPHX_API int mphx_mphf_lookup_str(const uint64_t* codes, const uint64_t* rank, u
                          const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
                          void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Static functions (Section 3: MWHC stores any f: S -> [sigma]).  Keys are hashed, built and
+ * peeled exactly as for the MPHF; then u in [sigma]^m is solved along the layers in reverse
+ * round order so that f(x) = u[v0] + u[v1] + u[v2] (mod sigma) for every key, with u = 0 on
+ * vertices that are no hinge.  Each u is stored in b = mphx_sf_bits(sigma) bits (the bits of
+ * sigma - 1; 0 when sigma = 1): vertex v's field at bits [v*b, v*b + b) of the little-endian
+ * bit string of the uint64 words.
+ *   values (dev) n uint32, each below sigma (key i's value); sigma in [1, 2^32].
+ *   words  (dev, caller-allocated) mphx_sf_words(n, gamma_num, gamma_den, sigma) uint64
+ *          (may be null when that is 0).
+ *   ws     (dev) at least mphx_sf_workspace_bytes(n, ...) bytes, 256-byte aligned.
+ *   info   as for the MPHF (P and seed_used are needed for lookups).
+ * Errors: as mphx_mphf_build_*, plus MPHX_EINVAL for sigma outside [1, 2^32] or a value not
+ * below sigma (checked on the device before any try).  Synchronises the stream.
+ * mphx_sf_lookup_*: out[i] = f(key i) (dev, n uint64).  Enqueue only.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API uint32_t mphx_sf_bits(uint64_t sigma);
+MPHX_API uint64_t mphx_sf_words(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, uint64_t sigma);
+MPHX_API size_t mphx_sf_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, int key_kind);
+MPHX_API int mphx_sf_build_u64(const uint64_t* keys, const uint32_t* values, uint64_t n, uint64_t sigma,
+                               uint64_t seed, uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries,
+                               uint64_t* words, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_sf_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t* values, uint64_t n,
+                               uint64_t sigma, uint64_t seed, uint32_t gamma_num, uint32_t gamma_den,
+                               uint32_t max_tries, uint64_t* words, void* ws, size_t ws_bytes, void* stream,
+                               mphx_mphf_info* info);
+MPHX_API int mphx_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed,
+                                const uint64_t* keys, uint64_t n, uint64_t* out, void* stream);
+MPHX_API int mphx_sf_lookup_str(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed,
+                                const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
+                                void* stream);
+
 /* Hash keys to edges (Section 3 / Section 4.3), edges (dev) n x 3 uint32.  Enqueue only. */
 MPHX_API int mphx_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
                   void* stream);

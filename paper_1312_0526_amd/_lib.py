@@ -51,6 +51,14 @@ _SIGS = {
     "mphx_mphf_build_u64": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
     "mphx_mphf_build_str": (_i32, [_vp, _vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp,
                                    C.POINTER(MphfInfo)]),
+    "mphx_sf_bits": (_u32, [_u64]),
+    "mphx_sf_words": (_u64, [_u64, _u32, _u32, _u64]),
+    "mphx_sf_workspace_bytes": (_sz, [_u64, _u32, _u32, _i32]),
+    "mphx_sf_build_u64": (_i32, [_vp, _vp, _u64, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
+    "mphx_sf_build_str": (_i32, [_vp, _vp, _vp, _u64, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _sz, _vp,
+                                 C.POINTER(MphfInfo)]),
+    "mphx_sf_lookup_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _u64, _vp, _vp]),
+    "mphx_sf_lookup_str": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
     "mphx_mphf_lookup_u64": (_i32, [_vp, _vp, _u64, _u64, _vp, _u64, _vp, _vp]),
     "mphx_mphf_lookup_str": (_i32, [_vp, _vp, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
     "mphx_hash_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp]),
@@ -262,6 +270,86 @@ def lookup_str(codes, rank, P: int, seed: int, data: torch.Tensor, offs: torch.T
     _check(out, torch.int64, "out", n)
     rc = lib().mphx_mphf_lookup_str(_ptr(codes), _ptr(rank), P, seed, _ptr(data), _ptr(offs), n, _ptr(out),
                                     _stream(data.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+# ---- static functions (Section 3: f(x) = u[v0] + u[v1] + u[v2] mod sigma) ----------------------
+def sf_bits(sigma: int) -> int:
+    return int(lib().mphx_sf_bits(sigma))
+
+
+def sf_words(n: int, sigma: int, gamma=(123, 100)) -> int:
+    return int(lib().mphx_sf_words(n, gamma[0], gamma[1], sigma))
+
+
+def sf_workspace_bytes(n: int, gamma=(123, 100), kind: int = KEYS_U64) -> int:
+    return int(lib().mphx_sf_workspace_bytes(n, gamma[0], gamma[1], kind))
+
+
+def _sf_finish(rc, info, words):
+    if rc:
+        _err(rc, info.as_dict())
+    d = info.as_dict()
+    d["words"] = words
+    return d
+
+
+def sf_build_u64(keys: torch.Tensor, values: torch.Tensor, sigma: int, seed: int = 0, gamma=(123, 100),
+                 max_tries: int = 64, ws=None, words=None) -> dict:
+    """Static function of u64 keys: values (int32 tensor holding uint32 values, one per key,
+    each below sigma).  Returns info and the packed fields (int64 tensor of uint64 words)."""
+    _check(keys, torch.int64, "keys")
+    n = keys.numel()
+    _check(values, torch.int32, "values", n)
+    nw = sf_words(n, sigma, gamma)
+    if words is None:
+        words = torch.empty(max(nw, 1), dtype=torch.int64, device=keys.device)
+    ws = ws if ws is not None else _workspace(sf_workspace_bytes(n, gamma, KEYS_U64), keys.device)
+    info = MphfInfo()
+    rc = lib().mphx_sf_build_u64(_ptr(keys), _ptr(values), n, sigma, seed, gamma[0], gamma[1], max_tries,
+                                 _ptr(words), _ptr(ws), ws.numel(), _stream(keys.device), C.byref(info))
+    return _sf_finish(rc, info, words[:nw])
+
+
+def sf_build_str(data: torch.Tensor, offs: torch.Tensor, values: torch.Tensor, sigma: int, seed: int = 0,
+                 gamma=(123, 100), max_tries: int = 64, ws=None, words=None) -> dict:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    _check(values, torch.int32, "values", n)
+    nw = sf_words(n, sigma, gamma)
+    if words is None:
+        words = torch.empty(max(nw, 1), dtype=torch.int64, device=data.device)
+    ws = ws if ws is not None else _workspace(sf_workspace_bytes(n, gamma, KEYS_STR), data.device)
+    info = MphfInfo()
+    rc = lib().mphx_sf_build_str(_ptr(data), _ptr(offs), _ptr(values), n, sigma, seed, gamma[0], gamma[1],
+                                 max_tries, _ptr(words), _ptr(ws), ws.numel(), _stream(data.device), C.byref(info))
+    return _sf_finish(rc, info, words[:nw])
+
+
+def sf_lookup_u64(words, sigma: int, P: int, seed: int, keys: torch.Tensor, out=None) -> torch.Tensor:
+    _check(keys, torch.int64, "keys")
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    _check(out, torch.int64, "out", keys.numel())
+    rc = lib().mphx_sf_lookup_u64(_ptr(words) if words.numel() else None, sigma, P, seed, _ptr(keys), keys.numel(),
+                                  _ptr(out), _stream(keys.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+def sf_lookup_str(words, sigma: int, P: int, seed: int, data: torch.Tensor, offs: torch.Tensor, out=None) -> torch.Tensor:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=data.device)
+    _check(out, torch.int64, "out", n)
+    rc = lib().mphx_sf_lookup_str(_ptr(words) if words.numel() else None, sigma, P, seed, _ptr(data), _ptr(offs), n,
+                                  _ptr(out), _stream(data.device))
     if rc:
         _err(rc)
     return out

@@ -177,11 +177,14 @@ struct MphfLayout {
     uint2 *claims, *claims_tmp;  // claim lists (m each), when used
     unsigned long long* ccount;  // claim counts per round
     unsigned long long* dcount;  // update-list counts per round
+    uint32_t* vals;              // static functions without claim lists: the values in layer order
     void* scan;
     size_t scan_bytes;
 };
 
-void layout_mphf(Carve& c, uint64_t n, uint64_t m, bool lists, MphfLayout& L)
+// sf: a static-function build, whose values reach the assignment in layer order through n
+// u32: the edge states with claim lists (unused there), else an array of their own.
+void layout_mphf(Carve& c, uint64_t n, uint64_t m, bool lists, MphfLayout& L, bool sf = false)
 {
     uint64_t rcap = round_cap(n);
     L.ctrl = c.take<Ctrl>(1);
@@ -205,6 +208,7 @@ void layout_mphf(Carve& c, uint64_t n, uint64_t m, bool lists, MphfLayout& L)
     L.bcount = c.take<uint32_t>(nblocks);
     L.scan_bytes = scan_scratch_bytes(nblocks);
     L.scan = c.take<uint8_t>(L.scan_bytes);
+    L.vals = (sf && !lists) ? c.take<uint32_t>(n) : nullptr;
 }
 
 bool aligned256(const void* p) { return ((uintptr_t)p & 255) == 0; }
@@ -511,6 +515,29 @@ size_t mphx_mphf_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_
     return c.off;
 }
 
+size_t mphx_sf_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, int key_kind)
+{
+    (void)key_kind;
+    uint64_t m = 3 * mphx_part_size(n, gamma_num, gamma_den);
+    Carve c(nullptr);
+    MphfLayout L;
+    layout_mphf(c, n, m, use_claim_lists(n), L, true);
+    return c.off;
+}
+
+uint32_t mphx_sf_bits(uint64_t sigma)
+{
+    uint32_t b = 0;
+    while (b < 64 && sigma > 0 && ((sigma - 1) >> b) != 0)
+        b++;
+    return b;
+}
+
+uint64_t mphx_sf_words(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, uint64_t sigma)
+{
+    return (3 * mphx_part_size(n, gamma_num, gamma_den) * mphx_sf_bits(sigma) + 63) / 64;
+}
+
 }  // extern "C"
 
 namespace {
@@ -586,8 +613,16 @@ int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, uint64_t
     return MPHX_OK;
 }
 
+// A static function's values and sigma (Section 3); absent for the MPHF.
+struct SfArgs {
+    const uint32_t* values;
+    uint64_t sigma;
+};
+
+// The MPHF (codes + rank) or, with sf, the static function (codes = its packed fields).
 int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
-               uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
+               uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info,
+               const SfArgs* sf = nullptr)
 {
     g_err.clear();
     if (gnum == 0 || gden == 0) return fail(MPHX_EINVAL, "gamma must be a positive fraction");
@@ -600,11 +635,13 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         if (k.kind == MPHX_KEYS_U64 && !k.keys) return fail(MPHX_EINVAL, "null keys");
         if (k.kind == MPHX_KEYS_STR && (!k.bytes || !k.offs)) return fail(MPHX_EINVAL, "null bytes/offs");
         if (k.kind == MPHX_KEYS_STR && ((uintptr_t)k.bytes & 3)) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
-        if (!codes || !rank) return fail(MPHX_EINVAL, "null output");
+        if (sf ? (!sf->values || (!codes && mphx_sf_bits(sf->sigma) > 0)) : (!codes || !rank))
+            return fail(MPHX_EINVAL, "null values or output");
     }
+    if (sf && (sf->sigma == 0 || sf->sigma > 0x100000000ull)) return fail(MPHX_EINVAL, "sigma must be in [1, 2^32]");
     if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
     const bool lists = use_claim_lists(n);
-    size_t need = mphx_mphf_workspace_bytes(n, gnum, gden, k.kind);
+    size_t need = sf ? mphx_sf_workspace_bytes(n, gnum, gden, k.kind) : mphx_mphf_workspace_bytes(n, gnum, gden, k.kind);
     if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
     if (info) {
         memset(info, 0, sizeof *info);
@@ -619,7 +656,15 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
 
     Carve c(ws);
     MphfLayout L;
-    layout_mphf(c, n, m, lists, L);
+    layout_mphf(c, n, m, lists, L, sf != nullptr);
+    if (sf) {  // every value below sigma
+        HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
+        HIP_TRY(launch_sf_check(sf->values, n, sf->sigma, L.ctrl, s));
+        Ctrl hc;
+        int rc = read_ctrl(L.ctrl, hc, s);
+        if (rc) return rc;
+        if (hc.err & kErrValue) return fail(MPHX_EINVAL, "a value is not below sigma = %llu", (unsigned long long)sf->sigma);
+    }
 
     PeelState st{};
     st.edges = L.edges;
@@ -673,6 +718,12 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         if (!st.lists)
             HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
         st.round0_updates = st.lists && g_opt.update_lists.load() > 0;
+        if (sf) {
+            // the values in layer order: over the edge states with claim lists; over the idle
+            // claim buffers when a try fell back to atomic claims; else their own array
+            st.vin = sf->values;
+            st.vout = st.lists ? L.state : (L.claims ? reinterpret_cast<uint32_t*>(L.claims) : L.vals);
+        }
         {
             Timed tm(PH_FRONTIER, s);
             HIP_TRY(launch_round0(st, s));
@@ -717,6 +768,24 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     // Assignment in reverse round order with exact grids from the layer bounds.
     std::vector<uint64_t> lb(h.nrounds + 1);
     HIP_TRY(hipMemcpyAsync(lb.data(), L.lstart, lb.size() * 8, hipMemcpyDeviceToHost, s));
+    if (sf) {
+        // u (one narrow element per vertex, over the records) solved layer by layer, then packed
+        const uint32_t b = mphx_sf_bits(sf->sigma);
+        void* u = L.rec;
+        HIP_TRY(launch_zero(u, m * sf_elem_bytes(b), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int64_t r = (int64_t)h.nrounds - 1; r >= 0; r--) {
+            Timed tm(PH_ASSIGN, s);
+            HIP_TRY(launch_sf_assign_round(L.slots + lb[r], st.vout + lb[r], lb[r + 1] - lb[r], sf->sigma, b, u, s));
+        }
+        {
+            Timed tm(PH_RANK, s);
+            HIP_TRY(launch_sf_pack(u, m, b, codes, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        g_timers.harvest();
+        return MPHX_OK;
+    }
     uint8_t* code8 = reinterpret_cast<uint8_t*>(L.rec);
     HIP_TRY(launch_zero(code8, m, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -756,6 +825,51 @@ int mphx_mphf_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, 
     KeySrc k{MPHX_KEYS_STR, nullptr, bytes, offs};
     return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, codes, rank, ws, ws_bytes, (hipStream_t)stream,
                       info);
+}
+
+int mphx_sf_build_u64(const uint64_t* keys, const uint32_t* values, uint64_t n, uint64_t sigma, uint64_t seed,
+                      uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* words, void* ws,
+                      size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    KeySrc k{MPHX_KEYS_U64, keys, nullptr, nullptr};
+    SfArgs sf{values, sigma};
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, words, nullptr, ws, ws_bytes, (hipStream_t)stream,
+                      info, &sf);
+}
+
+int mphx_sf_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t* values, uint64_t n, uint64_t sigma,
+                      uint64_t seed, uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* words,
+                      void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    KeySrc k{MPHX_KEYS_STR, nullptr, bytes, offs};
+    SfArgs sf{values, sigma};
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, words, nullptr, ws, ws_bytes, (hipStream_t)stream,
+                      info, &sf);
+}
+
+int mphx_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed, const uint64_t* keys,
+                       uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    const uint32_t b = mphx_sf_bits(sigma);
+    if ((!words && b > 0) || !keys || !out || P == 0 || sigma == 0 || sigma > 0x100000000ull)
+        return fail(MPHX_EINVAL, "null pointer, P = 0 or sigma out of [1, 2^32]");
+    HIP_TRY(launch_sf_lookup_u64(words, sigma, b, P, seed, keys, n, out, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_sf_lookup_str(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed, const uint8_t* bytes,
+                       const uint64_t* offs, uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    const uint32_t b = mphx_sf_bits(sigma);
+    if ((!words && b > 0) || !bytes || !offs || !out || P == 0 || sigma == 0 || sigma > 0x100000000ull)
+        return fail(MPHX_EINVAL, "null pointer, P = 0 or sigma out of [1, 2^32]");
+    if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    HIP_TRY(launch_sf_lookup_str_words(words, sigma, b, P, seed, bytes, offs, n, out, (hipStream_t)stream));
+    return MPHX_OK;
 }
 
 int mphx_mphf_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed, const uint64_t* keys,

@@ -15,6 +15,7 @@ constexpr int kWave = 64;
 // Error bits raised by kernels into Ctrl::err.
 constexpr uint32_t kErrBadEdge = 1u;  // vertex id >= m or a repeated vertex in an edge
 constexpr uint32_t kErrDegree = 2u;   // a vertex reached degree 256
+constexpr uint32_t kErrValue = 4u;    // a static-function value outside [0, sigma)
 
 // Device-side control block of one peeling run (lives in the workspace).
 struct Ctrl {
@@ -279,6 +280,28 @@ __device__ __forceinline__ uint64_t rank_of(const uint64_t* codes, const uint64_
         acc += nz_pairs(x);
     }
     return r + acc;
+}
+
+// ----- static functions (Section 3): f(x) = u[v0] + u[v1] + u[v2] mod sigma ---------------
+// u[v] is a field of b bits at bit v*b of the little-endian bit string of the u64 words.
+__device__ __forceinline__ uint64_t sf_field(const uint64_t* words, uint32_t b, uint32_t v)
+{
+    if (b == 0)
+        return 0;
+    const uint64_t bit = (uint64_t)v * b;
+    const uint64_t w = bit >> 6;
+    const uint32_t off = (uint32_t)(bit & 63);
+    uint64_t x = words[w] >> off;
+    if (off + b > 64)  // the field runs into the next word
+        x |= words[w + 1] << (64 - off);
+    return x & ((1ull << b) - 1);
+}
+
+__device__ __forceinline__ uint64_t sf_eval_edge(const uint64_t* words, uint64_t sigma, uint32_t b, uint32_t v0,
+                                                 uint32_t v1, uint32_t v2)
+{
+    const uint64_t s = sf_field(words, b, v0) + sf_field(words, b, v1) + sf_field(words, b, v2);
+    return s % sigma;
 }
 
 __device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,

@@ -133,19 +133,23 @@ __device__ __forceinline__ uint64_t key_word(const uint8_t* bytes, uint64_t p, u
     return (lo >> sh) | ((uint64_t)load_dword(bytes, q + 2, total) << (64 - sh));
 }
 
-// With kEval the kernel evaluates a built MPHF instead (Section 3 lookup): each key's edge
-// gives out[i] = f(key i) from the codes and rank samples, and nothing else is written.
-struct MphfTables {
-    const uint64_t* codes;
+// With kMode = kHsEvalMphf / kHsEvalSf the kernel evaluates a built function instead (Section 3
+// lookups): each key's edge gives out[i] = f(key i), from the MPHF's codes and rank samples or
+// from a static function's packed values, and nothing else is written.
+struct EvalTables {
+    const uint64_t* codes;  // MPHF codes, or a static function's packed fields
     const uint64_t* rank;
     uint64_t* out;
+    uint64_t sigma;
+    uint32_t bits;
 };
+constexpr int kHsEdges = 0, kHsEvalMphf = 1, kHsEvalSf = 2;
 
-template <bool kEval>
+template <int kMode>
 __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __restrict__ bytes,
                                                              const uint64_t* __restrict__ offs, uint64_t n,
                                                              uint64_t seed, uint64_t P, uint32_t* __restrict__ edges,
-                                                             PartHist1 h1, MphfTables mt)
+                                                             PartHist1 h1, EvalTables mt)
 {
     // Per key t of the chunk, with pre its first word in the chunk's flat word list: word f of
     // the key (index j = f - pre) starts at byte base[t] + 8f and its lane-A salt is
@@ -308,8 +312,10 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
             const uint64_t b = fin(B ^ sb ^ len);
             uint32_t v0, v1, v2;
             edge_of_digest(a, b, P, v0, v1, v2);
-            if constexpr (kEval) {
+            if constexpr (kMode == kHsEvalMphf) {
                 mt.out[i] = eval_edge(mt.codes, mt.rank, v0, v1, v2);
+            } else if constexpr (kMode == kHsEvalSf) {
+                mt.out[i] = sf_eval_edge(mt.codes, mt.sigma, mt.bits, v0, v1, v2);
             } else {
                 edges[3 * i] = v0;
                 edges[3 * i + 1] = v1;
@@ -436,7 +442,7 @@ hipError_t launch_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t 
     if (!rec) {
         const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
         const unsigned g = h1.hist ? (unsigned)h1.nt1 : (unsigned)std::min<uint64_t>(chunks, 65536);
-        k_hash_str_words<false><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, edges, h1, MphfTables{});
+        k_hash_str_words<kHsEdges><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, edges, h1, EvalTables{});
         return hipGetLastError();
     }
     unsigned g = grid_cap(n, 16384);
@@ -451,8 +457,20 @@ hipError_t launch_lookup_str_words(const uint64_t* codes, const uint64_t* rank, 
     if (n == 0) return hipSuccess;
     const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
     const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
-    k_hash_str_words<true><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
-                                                  MphfTables{codes, rank, out});
+    k_hash_str_words<kHsEvalMphf><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
+                                                         EvalTables{codes, rank, out, 0, 0});
+    return hipGetLastError();
+}
+
+hipError_t launch_sf_lookup_str_words(const uint64_t* words, uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed,
+                                      const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
+                                      hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
+    const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
+    k_hash_str_words<kHsEvalSf><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
+                                                       EvalTables{words, nullptr, out, sigma, b});
     return hipGetLastError();
 }
 

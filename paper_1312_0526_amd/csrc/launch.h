@@ -36,6 +36,10 @@ struct PeelState {
     unsigned long long* dcount;  // rcap + 2 update counts: dcount[r] = deletes of round r
     // round 0 writes layer 0's slots hinge first and its update list itself (claim lists only)
     bool round0_updates;
+    // static functions: vin[e] = key e's value (nullable); whoever writes a layer slot hinge
+    // first also writes vout[slot] = vin[edge], so the values reach the assignment in layer order
+    const uint32_t* vin;
+    uint32_t* vout;
     void* aux;              // partition histograms and scan scratch (part_aux_bytes)
 };
 
@@ -156,6 +160,18 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
 // assignment, ranking, lookup (solve.hip)
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
                                uint8_t* code8, unsigned grid_cap, hipStream_t s);
+// static functions (solve.hip; string lookups in keys.hip)
+hipError_t launch_sf_lookup_str_words(const uint64_t* words, uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed,
+                                      const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
+                                      hipStream_t s);
+// u holds m elements of sf_elem_bytes(b) bytes (u8 up to 8 bits, u16 up to 16, else u32)
+uint32_t sf_elem_bytes(uint32_t b);
+hipError_t launch_sf_assign_round(const uint3* slots, const uint32_t* vals, uint64_t count, uint64_t sigma,
+                                  uint32_t b, void* u, hipStream_t s);
+hipError_t launch_sf_pack(const void* u, uint64_t m, uint32_t b, uint64_t* words, hipStream_t s);
+hipError_t launch_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed,
+                                const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_sf_check(const uint32_t* vals, uint64_t n, uint64_t sigma, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_pack_count(const uint8_t* code8, uint64_t m, uint64_t* codes, uint32_t* bcount, hipStream_t s);
 hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
                              const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s);

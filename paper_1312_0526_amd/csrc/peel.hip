@@ -185,14 +185,15 @@ __global__ __launch_bounds__(kPeelBlock) void k_round0_lists(const uint64_t* __r
 // test, and the hinge then does what apply(0) would do -- it writes the edge's slot hinge
 // first (vh, va, vb) to layer 0 and appends the deletes (va, e) and (vb, e) -- so layer 0 is
 // read once, here.
-using SlotAppender = BlockAppender<uint3, kPeelBlock, 4 * kPeelBlock>;
+using SlotAppender = BlockAppender<uint4, kPeelBlock, 4 * kPeelBlock>;
 __global__ __launch_bounds__(kPeelBlock) void k_round0_updates(const uint64_t* __restrict__ rec, uint64_t m,
                                                                const uint32_t* __restrict__ edges, uint64_t P,
                                                                uint64_t n, uint3* __restrict__ slots,
                                                                unsigned long long* __restrict__ lcount,
                                                                uint2* __restrict__ dels,
                                                                unsigned long long* __restrict__ dcount, uint64_t dcap,
-                                                               Ctrl* ctrl)
+                                                               Ctrl* ctrl, const uint32_t* __restrict__ vin,
+                                                               uint32_t* __restrict__ vout)
 {
     __shared__ SlotAppender lapp;
     __shared__ ClaimListAppender dapp;
@@ -201,7 +202,11 @@ __global__ __launch_bounds__(kPeelBlock) void k_round0_updates(const uint64_t* _
         s_deg = s_ones = 0;
     lapp.init();
     dapp.init();
-    auto slot_out = [slots](uint64_t i, uint3 t) { slots[i] = t; };
+    auto slot_out = [slots, vout](uint64_t i, uint4 t) {
+        slots[i] = make_uint3(t.x, t.y, t.z);
+        if (vout)
+            vout[i] = t.w;  // a static function's value travels with the slot
+    };
     auto del_out = [dels, dcap](uint64_t j, uint2 d) {
         if (j < dcap) dels[j] = d;  // past the capacity: counted, not stored; the host checks
     };
@@ -231,7 +236,8 @@ __global__ __launch_bounds__(kPeelBlock) void k_round0_updates(const uint64_t* _
                 vb = k == 0 ? u2 : (k == 1 ? u0 : u1);
             }
         }
-        lapp.push(hinge, make_uint3(vh, va, vb), false, make_uint3(0u, 0u, 0u), &lcount[0], slot_out);
+        const uint32_t val = (hinge && vin) ? vin[e] : 0u;
+        lapp.push(hinge, make_uint4(vh, va, vb, val), false, make_uint4(0u, 0u, 0u, 0u), &lcount[0], slot_out);
         dapp.push(hinge, make_uint2(va, e), hinge, make_uint2(vb, e), &dcount[0], del_out);
     }
     lapp.flush(&lcount[0], slot_out);
@@ -269,7 +275,8 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
                                                       unsigned long long* __restrict__ lcount, uint2* __restrict__ claims,
                                                       unsigned long long* __restrict__ ccount,
                                                       unsigned long long* __restrict__ dcount, uint64_t ccap,
-                                                      Ctrl* ctrl, uint32_t r, uint64_t P, bool hinge_in_slot)
+                                                      Ctrl* ctrl, uint32_t r, uint64_t P, bool hinge_in_slot,
+                                                      const uint32_t* __restrict__ vin, uint32_t* __restrict__ vout)
 {
     constexpr bool kList = kMode != ApplyMode::kAtomicClaims;
     constexpr bool kUpdates = kMode == ApplyMode::kUpdateList;
@@ -314,6 +321,8 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
             uint32_t va = h == 0 ? v1 : (h == 1 ? v2 : v0);
             uint32_t vb = h == 0 ? v2 : (h == 1 ? v0 : v1);
             slots[i] = make_uint3(vh, va, vb);
+            if (vin)  // a static function's value travels with the slot
+                vout[i] = vin[e];
             // a vertex that had degree 1 when the round began drops to 0 with this edge and is
             // never read again: its delete can be skipped (old degree reads as 1, no record)
             const uint32_t pa = h == 2 ? 0u : h + 1, pb = h == 0 ? 2u : h - 1;
@@ -517,7 +526,7 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
         if (!st.tripartite) return hipErrorInvalidValue;
         if (st.round0_updates)
             k_round0_updates<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount,
-                                                      st.claims, st.dcount, st.m, st.ctrl);
+                                                      st.claims, st.dcount, st.m, st.ctrl, st.vin, st.vout);
         else
             k_round0_lists<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount, st.ctrl);
     } else if (st.tripartite)
@@ -535,7 +544,8 @@ hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, App
     if (mode != ApplyMode::kAtomicClaims && !st.tripartite) return hipErrorInvalidValue;
 #define MPHX_APPLY(TRI, MODE, HINGE)                                                                        \
     k_apply<TRI, MODE><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, \
-                                                st.claims, st.ccount, st.dcount, st.m, st.ctrl, r, st.P, HINGE)
+                                                st.claims, st.ccount, st.dcount, st.m, st.ctrl, r, st.P, HINGE,   \
+                                                st.vin, st.vout)
     switch (mode) {
     case ApplyMode::kClaimList: MPHX_APPLY(true, ApplyMode::kClaimList, hinge_in_slot); break;
     case ApplyMode::kUpdateList: MPHX_APPLY(true, ApplyMode::kUpdateList, hinge_in_slot); break;

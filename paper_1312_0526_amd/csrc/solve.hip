@@ -30,6 +30,69 @@ __global__ __launch_bounds__(256) void k_assign_round(const uint3* __restrict__ 
     }
 }
 
+// Static-function layer: the hinge takes f(x) - u[v_a] - u[v_b] (mod sigma); the value of slot
+// i's key travels in vals[i].  Every term is below sigma <= 2^32, so two conditional
+// subtractions replace the division.  u is kept in the narrowest of u8 / u16 / u32 that holds
+// b bits, which keeps its random accesses' footprint small.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sf_assign_round(const uint3* __restrict__ slots,
+                                                         const uint32_t* __restrict__ vals, uint64_t count,
+                                                         uint64_t sigma, T* __restrict__ u)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        const uint3 t = slots[i];
+        uint64_t x = (uint64_t)vals[i] + 2 * sigma - __builtin_nontemporal_load(&u[t.y]) -
+                     __builtin_nontemporal_load(&u[t.z]);
+        x = x >= sigma ? x - sigma : x;
+        x = x >= sigma ? x - sigma : x;
+        u[t.x] = (T)x;
+    }
+}
+
+// One thread per output word w: the fields overlapping bits [64w, 64w + 64).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sf_pack(const T* __restrict__ u, uint64_t m, uint32_t b,
+                                                 uint64_t nwords, uint64_t* __restrict__ words)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride) {
+        const uint64_t lo = 64 * w, hi = lo + 64;
+        uint64_t x = 0;
+        for (uint64_t v = lo / b; v * b < hi && v < m; v++) {
+            const uint64_t f = u[v];
+            const int64_t sh = (int64_t)(v * b) - (int64_t)lo;  // in (-b, 64)
+            x |= sh >= 0 ? f << sh : f >> (-sh);
+        }
+        words[w] = x;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sf_lookup_u64(const uint64_t* __restrict__ words, uint64_t sigma, uint32_t b,
+                                                       uint64_t P, uint64_t seed, const uint64_t* __restrict__ keys,
+                                                       uint64_t n, uint64_t* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t s = keys[i] ^ seed;
+        uint32_t v0, v1, v2;
+        edge_of_digest(s, s, P, v0, v1, v2);
+        out[i] = sf_eval_edge(words, sigma, b, v0, v1, v2);
+    }
+}
+
+// Flags a value outside [0, sigma) in ctrl->err.
+__global__ __launch_bounds__(256) void k_sf_check(const uint32_t* __restrict__ vals, uint64_t n, uint64_t sigma,
+                                                  Ctrl* ctrl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        bad |= vals[i] >= sigma;
+    if (__ballot(bad) && (threadIdx.x & (kWave - 1)) == 0)
+        atomicOr(&ctrl->err, kErrValue);
+}
+
 __global__ __launch_bounds__(256) void k_pack_count(const uint8_t* __restrict__ code8, uint64_t m,
                                                     uint64_t* __restrict__ codes, uint32_t* __restrict__ bcount,
                                                     uint64_t nwords)
@@ -109,6 +172,49 @@ hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint3
                                uint8_t* code8, unsigned grid_cap_blocks, hipStream_t s)
 {
     k_assign_round<<<grid_cap(n_bound, grid_cap_blocks), 256, 0, s>>>(slots, lstart, r, P, code8);
+    return hipGetLastError();
+}
+
+uint32_t sf_elem_bytes(uint32_t b) { return b <= 8 ? 1u : (b <= 16 ? 2u : 4u); }
+
+hipError_t launch_sf_assign_round(const uint3* slots, const uint32_t* vals, uint64_t count, uint64_t sigma,
+                                  uint32_t b, void* u, hipStream_t s)
+{
+    if (count == 0) return hipSuccess;
+    const unsigned g = grid_cap(count, 16384);
+    switch (sf_elem_bytes(b)) {
+    case 1: k_sf_assign_round<uint8_t><<<g, 256, 0, s>>>(slots, vals, count, sigma, (uint8_t*)u); break;
+    case 2: k_sf_assign_round<uint16_t><<<g, 256, 0, s>>>(slots, vals, count, sigma, (uint16_t*)u); break;
+    default: k_sf_assign_round<uint32_t><<<g, 256, 0, s>>>(slots, vals, count, sigma, (uint32_t*)u);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sf_pack(const void* u, uint64_t m, uint32_t b, uint64_t* words, hipStream_t s)
+{
+    const uint64_t nwords = (m * b + 63) / 64;
+    if (nwords == 0) return hipSuccess;
+    const unsigned g = grid_cap(nwords, 16384);
+    switch (sf_elem_bytes(b)) {
+    case 1: k_sf_pack<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)u, m, b, nwords, words); break;
+    case 2: k_sf_pack<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)u, m, b, nwords, words); break;
+    default: k_sf_pack<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)u, m, b, nwords, words);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed,
+                                const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_sf_lookup_u64<<<grid_cap(n, 16384), 256, 0, s>>>(words, sigma, b, P, seed, keys, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sf_check(const uint32_t* vals, uint64_t n, uint64_t sigma, Ctrl* ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_sf_check<<<grid_cap(n, 4096), 256, 0, s>>>(vals, n, sigma, ctrl);
     return hipGetLastError();
 }
 

@@ -63,6 +63,22 @@ def test_info_struct_mirrors_match_the_header(mx):
     assert names[-2:] == ["update_deletes", "update_records"]
 
 
+def test_static_function_sizes(mx):
+    import oracle
+
+    o = oracle.Oracle()
+    for sigma in (1, 2, 3, 4, 255, 256, 257, 65_535, 65_536, 65_537, 1_000_003, (1 << 32) - 1, 1 << 32):
+        assert mx.sf_bits(sigma) == o.sf_bits(sigma) == (sigma - 1).bit_length()
+        assert mx.sf_words(12_345, sigma) == o.sf_words(3 * o.part_size(12_345), sigma)
+    # without claim lists the values in layer order take n more u32; with them, the edge states
+    assert mx.sf_workspace_bytes(1 << 20) - mx.mphf_workspace_bytes(1 << 20) >= 4 << 20
+    mx.set_option("claim_lists", 20)
+    try:
+        assert mx.sf_workspace_bytes(1 << 20) == mx.mphf_workspace_bytes(1 << 20)
+    finally:
+        mx.set_option("claim_lists", 28)
+
+
 def test_update_lists_option_range(mx):
     assert mx.get_option("update_lists") == 16
     for bad in (-1, 101):
