@@ -41,6 +41,14 @@
  *  - rank table: one u64 per 512 vertices holding the number of hinge vertices strictly
  *    before the block (exclusive rank), so the MPHF maps onto [0, n);
  *  - retries: seed, seed+1, ... up to max_tries; degree above 255 is an error;
+ *  - HEM split (Section 3, "Practical workarounds"): a key's 64-bit signature is
+ *    fin(s + 4*GAMMA) for u64 keys (s = key XOR seed, a bijection: no two keys collide) and
+ *    fin(a XOR fin(b)) of the string digest (a, b); the top k bits pick one of 2^k buckets,
+ *    the signature with its two 32-bit halves swapped is the key inside the bucket, and each
+ *    bucket gets the MWHC MPHF of its keys (hash seed = the build's seed, retries seed+1, ...);
+ *    f(x) = (keys in earlier buckets) + the bucket MPHF's value; a bucket that fails (two keys
+ *    with one signature, or max_tries 2-cores) fails the build, which the caller redoes with
+ *    another seed;
  *  - static functions (Section 3, any sigma in [1, 2^32]): values must lie in [0, sigma);
  *    u = 0 on vertices that are no hinge; each u is stored in b = (bits of sigma - 1) bits,
  *    vertex v's field at bits [v*b, v*b + b) of the little-endian bit string of the u64
@@ -658,4 +666,88 @@ int orc_sf_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t*
                      uint64_t* words, uint64_t* info)
 {
     return orc_build(1, bytes, offs, n, values, sigma, seed, gnum, gden, max_tries, words, NULL, info);
+}
+
+/* ------------------------------------------------------------------------------------------
+ * HEM split (Section 3): signatures, buckets by their top bits, one MWHC MPHF per bucket.
+ * ------------------------------------------------------------------------------------------ */
+uint64_t orc_hem_signature_u64(uint64_t key, uint64_t seed) { return orc_fin((key ^ seed) + 4 * ORC_GAMMA); }
+
+uint64_t orc_hem_signature_str(const uint8_t* x, uint64_t len, uint64_t seed)
+{
+    uint64_t a, b;
+    orc_digest_str(x, len, seed, &a, &b);
+    return orc_fin(a ^ orc_fin(b));
+}
+
+/* The key a signature stands for inside its bucket: its two 32-bit halves swapped. */
+static uint64_t orc_hem_bucket_key(uint64_t sig) { return (sig << 32) | (sig >> 32); }
+
+/* sigs: the n signatures.  k in [0, 32].  Outputs: bucket_off (2^k + 1 key offsets), code_off
+ * and rank_off (2^k + 1: where bucket b's ceil(m_b/32) codes and ceil(m_b/512) rank samples
+ * start), seeds (2^k: each bucket's seed used), codes and rank (sized by code_off[2^k] and
+ * rank_off[2^k]: the caller calls with codes == NULL first to learn them).  Returns ORC_OK,
+ * or the first failing bucket's status (ORC_ECORE / ORC_EDUP / ORC_ERANGE). */
+int orc_hem_build(const uint64_t* sigs, uint64_t n, uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden,
+                  uint32_t max_tries, uint64_t* bucket_off, uint64_t* code_off, uint64_t* rank_off,
+                  uint64_t* seeds, uint64_t* codes, uint64_t* rank)
+{
+    if (k > 32 || gnum == 0 || gden == 0 || max_tries == 0)
+        return ORC_EINVAL;
+    const uint64_t B = 1ull << k;
+    for (uint64_t b = 0; b <= B; b++)
+        bucket_off[b] = 0;
+    for (uint64_t i = 0; i < n; i++)
+        bucket_off[(k ? sigs[i] >> (64 - k) : 0) + 1]++;
+    for (uint64_t b = 0; b < B; b++)
+        bucket_off[b + 1] += bucket_off[b];
+    code_off[0] = rank_off[0] = 0;
+    for (uint64_t b = 0; b < B; b++) {
+        uint64_t m = 3 * orc_part_size(bucket_off[b + 1] - bucket_off[b], gnum, gden);
+        code_off[b + 1] = code_off[b] + (m + 31) / 32;
+        rank_off[b + 1] = rank_off[b] + (m + 511) / 512;
+    }
+    if (!codes)
+        return ORC_OK;
+    /* counting sort of the bucket keys by bucket, stable in key order */
+    uint64_t* keys = malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t* fill = malloc(B * sizeof(uint64_t));
+    if (!keys || !fill) {
+        free(keys); free(fill);
+        return ORC_ENOMEM;
+    }
+    for (uint64_t b = 0; b < B; b++)
+        fill[b] = bucket_off[b];
+    for (uint64_t i = 0; i < n; i++)
+        keys[fill[k ? sigs[i] >> (64 - k) : 0]++] = orc_hem_bucket_key(sigs[i]);
+    int status = ORC_OK;
+    for (uint64_t b = 0; b < B && status == ORC_OK; b++) {
+        uint64_t info[6];
+        status = orc_mphf_build_u64(keys + bucket_off[b], bucket_off[b + 1] - bucket_off[b], seed, gnum, gden,
+                                    max_tries, codes + code_off[b], rank + rank_off[b], info);
+        seeds[b] = info[2];
+    }
+    free(keys);
+    free(fill);
+    return status;
+}
+
+/* f(x) for a key with signature sig. */
+static uint64_t orc_hem_eval(uint64_t sig, uint32_t k, const uint64_t* bucket_off, const uint64_t* code_off,
+                             const uint64_t* rank_off, const uint64_t* seeds, const uint64_t* codes,
+                             const uint64_t* rank, uint32_t gnum, uint32_t gden)
+{
+    uint64_t b = k ? sig >> (64 - k) : 0;
+    uint64_t nb = bucket_off[b + 1] - bucket_off[b];
+    uint64_t key = orc_hem_bucket_key(sig), f;
+    orc_lookup_u64(codes + code_off[b], rank + rank_off[b], orc_part_size(nb, gnum, gden), seeds[b], &key, 1, &f);
+    return bucket_off[b] + f;
+}
+
+void orc_hem_lookup(const uint64_t* sigs, uint64_t n, uint32_t k, const uint64_t* bucket_off,
+                    const uint64_t* code_off, const uint64_t* rank_off, const uint64_t* seeds,
+                    const uint64_t* codes, const uint64_t* rank, uint32_t gnum, uint32_t gden, uint64_t* out)
+{
+    for (uint64_t i = 0; i < n; i++)
+        out[i] = orc_hem_eval(sigs[i], k, bucket_off, code_off, rank_off, seeds, codes, rank, gnum, gden);
 }

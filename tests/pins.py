@@ -480,9 +480,57 @@ def pin_static_function(o, seed=6) -> list:
     return bad
 
 
+def pin_hem(o) -> list:
+    """HEM split (Section 3): the u64 signature is SplitMix64 output 4 at state key XOR seed
+    (published outputs: state -(4-t)*GAMMA gives output t of state 0); each bucket holds
+    exactly the keys whose signatures carry its top bits; with one bucket the structure is the
+    MWHC MPHF of the half-swapped signatures; the function is a bijection onto [0, n) for u64
+    and string keys and several bucket counts."""
+    bad = []
+    G = 0x9E3779B97F4A7C15
+    for t, want in enumerate(SPLITMIX0, start=1):
+        key = (-(4 - t) * G) % (1 << 64)
+        if int(o.hem_signatures_u64(np.array([key], np.uint64), 0)[0]) != want:
+            bad.append(f"hem signature of state -{4 - t}*GAMMA is not published output {t}")
+        if int(o.hem_signatures_u64(np.array([key ^ 0x1234], np.uint64), 0x1234)[0]) != want:
+            bad.append("hem signature does not depend on key XOR seed alone")
+    n = 40_000
+    keys = workloads.u64_keys(n, gen_seed=11)
+    sigs = o.hem_signatures_u64(keys, 5)
+    for k in (0, 1, 6, 10):
+        rc, r = o.hem_build(sigs, k, seed=5)
+        if rc != 0:
+            bad.append(f"hem k={k}: status {rc}")
+            continue
+        bo = r["bucket_off"].astype(np.int64)
+        top = (sigs >> np.uint64(64 - k)).astype(np.int64) if k else np.zeros(n, np.int64)
+        if bo[-1] != n or not np.array_equal(np.diff(bo), np.bincount(top, minlength=1 << k)):
+            bad.append(f"hem k={k}: bucket sizes differ from the signatures' top bits")
+        f = o.hem_lookup(r, sigs)
+        if not np.array_equal(np.sort(f), np.arange(n, dtype=np.uint64)):
+            bad.append(f"hem k={k}: lookup is not a bijection onto [0, n)")
+        if k == 0:
+            swapped = (sigs << np.uint64(32)) | (sigs >> np.uint64(32))
+            rc1, one = o.mphf_build_u64(swapped, seed=5)
+            if rc1 != 0 or not np.array_equal(one["words"], r["codes"]) or not np.array_equal(one["rank"], r["rank"]):
+                bad.append("hem k=0: not the MWHC MPHF of the half-swapped signatures")
+        if k == 6:
+            for b in (0, 17, 63):
+                inb = np.sort(f[top == b])
+                if not np.array_equal(inb, np.arange(bo[b], bo[b + 1], dtype=np.uint64)):
+                    bad.append(f"hem k=6: bucket {b}'s keys do not map onto its own range")
+    data, offs = workloads.str_keys(9000, gen_seed=12)
+    sg = o.hem_signatures_str(data, offs, 2)
+    rc, r = o.hem_build(sg, 3, seed=2)
+    f = o.hem_lookup(r, sg) if rc == 0 else None
+    if rc != 0 or not np.array_equal(np.sort(f), np.arange(9000, dtype=np.uint64)):
+        bad.append(f"hem strings: status {rc} or not a bijection")
+    return bad
+
+
 ALL_PINS = [pin_splitmix, pin_hash_closed_form, pin_part_size, pin_worked_examples,
             pin_bruteforce_tripartite, pin_bruteforce_generic, pin_invariants, pin_mphf, pin_errors,
-            pin_string_digest, pin_static_function]
+            pin_string_digest, pin_static_function, pin_hem]
 
 
 def run_all(o, pins=None) -> list:

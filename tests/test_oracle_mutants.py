@@ -39,6 +39,10 @@ MUTANTS = {
     "static function field one bit short": ("while (b < 64 && ((sigma - 1) >> b) != 0)", "while (b < 64 && ((sigma - 1) >> (b + 1)) != 0)"),
     "static function packing shifted": ("|= (uint64_t)((u[v] >> t) & 1u) << (bit % 64);", "|= (uint64_t)((u[v] >> t) & 1u) << ((bit + 1) % 64);"),
     "static function lookup drops a vertex": ("+ orc_sf_field(words, b, t[2])) % sigma", ") % sigma"),
+    "hem signature adds the seed": ("return orc_fin((key ^ seed) + 4 * ORC_GAMMA);", "return orc_fin((key + seed) + 4 * ORC_GAMMA);"),
+    "hem bucket key not swapped": ("return (sig << 32) | (sig >> 32);", "return sig;"),
+    "hem bucket offset dropped": ("return bucket_off[b] + f;", "return f;"),
+    "hem bucket from the low bits": ("uint64_t b = k ? sig >> (64 - k) : 0;", "uint64_t b = k ? sig & ((1ull << k) - 1) : 0;"),
 }
 
 
