@@ -466,6 +466,66 @@ def sf_leg(args, mx, torch, n: int, kind: int, ws, keys=None, data=None, offs=No
     return res
 
 
+def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None) -> dict:
+    """HEM split (Section 3) of the same keys for each k in --hem-k: 64-bit signatures, 2^k
+    buckets by their top bits, one MWHC MPHF per bucket by the batched kernel; builds timed like
+    the plain leg (steps capped at 3), then one lookup of all n keys timed with HIP events and
+    checked to be a bijection onto [0, n)."""
+    dev = torch.device("cuda:0")
+    gamma = (123, 100)
+    ws = torch.empty(max(mx.hem_workspace_bytes(n, k, gamma) for k in args.hem_k), dtype=torch.uint8, device=dev)
+    out = torch.empty(n, dtype=torch.int64, device=dev)
+    rows = {}
+    for k in args.hem_k:
+        def step():
+            if kind == mx.KEYS_U64:
+                return mx.hem_build(keys=keys, k=k, seed=0, gamma=gamma, ws=ws)
+            return mx.hem_build(data=data, offs=offs, k=k, seed=0, gamma=gamma, ws=ws)
+
+        h = step()
+        torch.cuda.synchronize()
+        mx.phase_times(reset=True)
+        steps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            del h
+            h = step()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        phases = {p: round(v[0] / steps, 3) for p, v in mx.phase_times(reset=True).items() if v[1]}
+        B = 1 << k
+        words = h["codes"].numel() + h["rank"].numel()
+        bits = 64 * words + 64 * (4 * B + 3)  # codes, rank samples, three offset arrays and the seeds
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        if kind == mx.KEYS_U64:
+            mx.hem_lookup(h, keys=keys, out=out)
+        else:
+            mx.hem_lookup(h, data=data, offs=offs, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        lk_ms = e0.elapsed_time(e1)
+        # a bijection onto [0, n): every value in range and every slot hit once
+        inrange = bool(int(out.min().item()) >= 0 and int(out.max().item()) < n)
+        hit = torch.zeros(n, dtype=torch.uint8, device=dev)
+        if inrange:
+            hit.index_fill_(0, out, 1)
+        ok = inrange and int(hit.sum(dtype=torch.int64).item()) == n
+        del hit
+        sizes = (h["bucket_off"][1:] - h["bucket_off"][:-1])
+        rows[f"k{k}"] = dict(buckets=B, ms_per_build=round(sec * 1e3, 3), keys_per_s=round(n / sec, 1),
+                             bits_per_key=round(bits / n, 4), max_bucket=int(sizes.max().item()),
+                             max_tries=h["tries"], max_rounds=h["n_rounds"], phases_ms=phases,
+                             lookup_all_ms=round(lk_ms, 3), lookup_ns_per_key=round(lk_ms * 1e6 / n, 4),
+                             bijection=ok)
+        log(f"[hem] k={k}: {sec * 1e3:.1f} ms/build, {n / sec / 1e9:.3f} G keys/s, {bits / n:.3f} bits/key, "
+            f"lookup {lk_ms * 1e6 / n:.3f} ns/key, bijection ok={ok}")
+        del h, sizes
+    del ws, out
+    torch.cuda.empty_cache()
+    return dict(workload="hem_split_same_keys", rows=rows)
+
+
 SERVE_WORKLOAD = "mwhc_served_poisson_sizes_loguniform_1e3_1e8_u64_or_str_gamma1.23"
 
 
@@ -569,8 +629,10 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="ceilings,plain,lookup,sf,batched,served",
-                    help="comma list of: ceilings, plain, lookup and sf (need plain), batched, served")
+    ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
+                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served")
+    ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[15],
+                    help="bucket-count exponents of the hem leg")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
@@ -753,6 +815,11 @@ def main() -> int:
                     data=None if kind == mx.KEYS_U64 else data, offs=None if kind == mx.KEYS_U64 else offs)
 
     del ws, codes, rank
+    torch.cuda.empty_cache()
+    hem = None
+    if "hem" in legs:
+        hem = hem_leg(args, mx, torch, n, kind, keys=keys if kind == mx.KEYS_U64 else None,
+                      data=None if kind == mx.KEYS_U64 else data, offs=None if kind == mx.KEYS_U64 else offs)
     if cfg["kind"] == "u64":
         del keys
     else:
@@ -783,6 +850,7 @@ def main() -> int:
         "phases": phase_rows,
         "lookup": lookup,
         "static_function": sf,
+        "hem": hem,
         "batched": batched,
         "served": served,
     }

@@ -279,6 +279,46 @@ MPHX_API int mphx_graph_launch(void* graph, void* stream);
 MPHX_API int mphx_graph_destroy(void* graph);
 
 /* ---------------------------------------------------------------------------------------
+ * HEM split of one key set (Section 3, "Practical workarounds"): each key gets a 64-bit
+ * signature -- fin(s + 4*GAMMA), s = key XOR seed, for u64 keys (a bijection: no two keys
+ * collide); fin(a XOR fin(b)) of the string digest (a, b) -- whose top k bits pick one of 2^k
+ * buckets; the signature with its two 32-bit halves swapped is the key inside the bucket, and
+ * each bucket gets the MWHC MPHF of its keys (hash seed `seed`, retries seed+1, ... per bucket)
+ * built by the batched kernel.  f(x) = bucket_off[b] + the bucket MPHF's value.
+ *   k in [9, 18] (2^k buckets); outputs (dev, caller-allocated): bucket_off, code_off, rank_off
+ *   (2^k + 1 each: where bucket b's keys, ceil(m_b/32) code words and ceil(m_b/512) rank
+ *   samples start), seeds (2^k: each bucket's seed used), codes and rank (at least the
+ *   mphx_hem_capacity words).  ws (dev, 256-byte aligned): mphx_hem_workspace_bytes bytes;
+ *   it admits buckets up to n/2^k + 8 sqrt(n/2^k) + 64 keys (MPHX_ENOMEM beyond).  Pick k so
+ *   that buckets hold hundreds of keys or more: at gamma < 1.5 a bucket of exactly two keys
+ *   has parts of one vertex, both edges are (0, 1, 2), and it fails under every seed.
+ * Errors: MPHX_EINVAL for bad arguments; MPHX_ECORE (MPHX_ERANGE) when some bucket failed --
+ * a 2-core on every try, or two keys with one 64-bit signature (probability about
+ * n^2 / 2^65 for string keys) -- info->n_core then counts the failed buckets: build again
+ * with another seed.  info->tries / n_rounds are the largest over the buckets.  Synchronises.
+ * mphx_hem_lookup_*: out[i] = f(key i) (dev, n uint64); seed and k as built.  Enqueue only.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den);
+MPHX_API int mphx_hem_capacity(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den, uint64_t* code_words,
+                               uint64_t* rank_words);
+MPHX_API int mphx_hem_build_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed, uint32_t gamma_num,
+                                uint32_t gamma_den, uint32_t max_tries, uint64_t* bucket_off, uint64_t* code_off,
+                                uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank, void* ws,
+                                size_t ws_bytes, void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint32_t k, uint64_t seed,
+                                uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* bucket_off,
+                                uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes,
+                                uint64_t* rank, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_hem_lookup_u64(const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,
+                                 const uint64_t* seeds, const uint64_t* codes, const uint64_t* rank, uint32_t k,
+                                 uint32_t gamma_num, uint32_t gamma_den, uint64_t seed, const uint64_t* keys,
+                                 uint64_t n, uint64_t* out, void* stream);
+MPHX_API int mphx_hem_lookup_str(const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,
+                                 const uint64_t* seeds, const uint64_t* codes, const uint64_t* rank, uint32_t k,
+                                 uint32_t gamma_num, uint32_t gamma_den, uint64_t seed, const uint8_t* bytes,
+                                 const uint64_t* offs, uint64_t n, uint64_t* out, void* stream);
+
+/* ---------------------------------------------------------------------------------------
  * Build server: continuous admission of MPHF builds of mixed sizes under an HBM budget.
  *
  * mphx_server_create allocates one device pool of hbm_budget bytes on `device` (the only

@@ -59,6 +59,14 @@ _SIGS = {
                                  C.POINTER(MphfInfo)]),
     "mphx_sf_lookup_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _u64, _vp, _vp]),
     "mphx_sf_lookup_str": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
+    "mphx_hem_workspace_bytes": (_sz, [_u64, _u32, _u32, _u32]),
+    "mphx_hem_capacity": (_i32, [_u64, _u32, _u32, _u32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "mphx_hem_build_u64": (_i32, [_vp, _u64, _u32, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp,
+                                  C.POINTER(MphfInfo)]),
+    "mphx_hem_build_str": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                  _vp, C.POINTER(MphfInfo)]),
+    "mphx_hem_lookup_u64": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u64, _vp, _u64, _vp, _vp]),
+    "mphx_hem_lookup_str": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u64, _vp, _vp, _u64, _vp, _vp]),
     "mphx_mphf_lookup_u64": (_i32, [_vp, _vp, _u64, _u64, _vp, _u64, _vp, _vp]),
     "mphx_mphf_lookup_str": (_i32, [_vp, _vp, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
     "mphx_hash_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp]),
@@ -270,6 +278,77 @@ def lookup_str(codes, rank, P: int, seed: int, data: torch.Tensor, offs: torch.T
     _check(out, torch.int64, "out", n)
     rc = lib().mphx_mphf_lookup_str(_ptr(codes), _ptr(rank), P, seed, _ptr(data), _ptr(offs), n, _ptr(out),
                                     _stream(data.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+# ---- HEM split (Section 3: signatures, 2^k buckets, an MPHF per bucket) -------------------------
+def hem_workspace_bytes(n: int, k: int, gamma=(123, 100)) -> int:
+    return int(lib().mphx_hem_workspace_bytes(n, k, gamma[0], gamma[1]))
+
+
+def hem_capacity(n: int, k: int, gamma=(123, 100)):
+    cw, rw = C.c_uint64(), C.c_uint64()
+    rc = lib().mphx_hem_capacity(n, k, gamma[0], gamma[1], C.byref(cw), C.byref(rw))
+    if rc:
+        _err(rc)
+    return int(cw.value), int(rw.value)
+
+
+def hem_build(keys=None, data=None, offs=None, k: int = 15, seed: int = 0, gamma=(123, 100), max_tries: int = 64,
+              ws=None) -> dict:
+    """HEM split of u64 keys (keys) or string keys (data + offs).  Returns device tables
+    (bucket_off, code_off, rank_off, seeds, codes, rank) and the build info."""
+    if keys is not None:
+        _check(keys, torch.int64, "keys")
+        n, dev = keys.numel(), keys.device
+    else:
+        _check(data, torch.uint8, "data")
+        _check(offs, torch.int64, "offs")
+        n, dev = offs.numel() - 1, data.device
+    B = 1 << k
+    cw, rw = hem_capacity(n, k, gamma)
+    t = {name: torch.empty(B + 1, dtype=torch.int64, device=dev) for name in ("bucket_off", "code_off", "rank_off")}
+    t["seeds"] = torch.empty(B, dtype=torch.int64, device=dev)
+    codes = torch.empty(max(cw, 1), dtype=torch.int64, device=dev)
+    rank = torch.empty(max(rw, 1), dtype=torch.int64, device=dev)
+    ws = ws if ws is not None else _workspace(hem_workspace_bytes(n, k, gamma), dev)
+    info = MphfInfo()
+    common = (_ptr(t["bucket_off"]), _ptr(t["code_off"]), _ptr(t["rank_off"]), _ptr(t["seeds"]), _ptr(codes),
+              _ptr(rank), _ptr(ws), ws.numel(), _stream(dev), C.byref(info))
+    if keys is not None:
+        rc = lib().mphx_hem_build_u64(_ptr(keys), n, k, seed, gamma[0], gamma[1], max_tries, *common)
+    else:
+        rc = lib().mphx_hem_build_str(_ptr(data), _ptr(offs), n, k, seed, gamma[0], gamma[1], max_tries, *common)
+    if rc:
+        _err(rc, info.as_dict())
+    d = info.as_dict()
+    nc = int(t["code_off"][-1].item())
+    nr = int(t["rank_off"][-1].item())
+    d.update(t, codes=codes[:nc], rank=rank[:nr], k=k, seed=seed, gamma=gamma, n=n)
+    return d
+
+
+def hem_lookup(h: dict, keys=None, data=None, offs=None, out=None) -> torch.Tensor:
+    if keys is not None:
+        _check(keys, torch.int64, "keys")
+        n, dev = keys.numel(), keys.device
+    else:
+        _check(data, torch.uint8, "data")
+        _check(offs, torch.int64, "offs")
+        n, dev = offs.numel() - 1, data.device
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=dev)
+    _check(out, torch.int64, "out", n)
+    codes = h["codes"] if h["codes"].numel() else h["bucket_off"]
+    rank = h["rank"] if h["rank"].numel() else h["bucket_off"]
+    tables = (_ptr(h["bucket_off"]), _ptr(h["code_off"]), _ptr(h["rank_off"]), _ptr(h["seeds"]), _ptr(codes),
+              _ptr(rank), h["k"], h["gamma"][0], h["gamma"][1], h["seed"])
+    if keys is not None:
+        rc = lib().mphx_hem_lookup_u64(*tables, _ptr(keys), n, _ptr(out), _stream(dev))
+    else:
+        rc = lib().mphx_hem_lookup_str(*tables, _ptr(data), _ptr(offs), n, _ptr(out), _stream(dev))
     if rc:
         _err(rc)
     return out

@@ -1102,6 +1102,62 @@ size_t mphx_batch_workspace_bytes(uint32_t B, uint64_t max_bucket, uint32_t gnum
     return batch_ws_bytes(B, max_bucket, gnum, gden, grid);
 }
 
+// ---- HEM split (Section 3) ---------------------------------------------------------------
+// Workspace: signature records and the partition's second buffer (8n each), the partition's
+// histograms, the processing order and per-bucket results, and the batched build's scratch
+// for buckets up to the bound below (bucket sizes are binomial around n / 2^k).
+static uint64_t hem_max_bucket(uint64_t n, uint32_t k)
+{
+    const uint64_t mean = n >> k;
+    uint64_t r = 1;
+    while (r * r < mean) r++;
+    return mean + 8 * r + 64;
+}
+
+struct HemLayout {
+    uint2 *rec, *tmp;
+    void* aux;
+    uint32_t* order;
+    mphx_bucket_result* results;
+    uint8_t* batch;
+    size_t batch_bytes;
+};
+
+static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, HemLayout& L)
+{
+    const uint32_t B = 1u << k;
+    L.rec = c.take<uint2>(n);
+    L.tmp = c.take<uint2>(n);
+    L.aux = c.take<uint8_t>(hem_aux_bytes(n, k));
+    L.order = c.take<uint32_t>(B);
+    L.results = c.take<mphx_bucket_result>(B);
+    L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, nullptr);
+    L.batch = c.take<uint8_t>(L.batch_bytes);
+}
+
+size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden)
+{
+    if (k < 9 || k > 18 || gnum == 0 || gden == 0) return 0;
+    Carve c(nullptr);
+    HemLayout L;
+    layout_hem(c, n, k, gnum, gden, L);
+    return c.off;
+}
+
+int mphx_hem_capacity(uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, uint64_t* code_words,
+                      uint64_t* rank_words)
+{
+    g_err.clear();
+    if (k < 9 || k > 18 || gnum == 0 || gden == 0 || !code_words || !rank_words)
+        return fail(MPHX_EINVAL, "k must be in [9, 18], gamma positive, outputs non-null");
+    // sum over buckets of 3 ceil(n_b num / 3 den) <= n num / den + 3 * 2^k vertices
+    const uint64_t B = 1ull << k;
+    const uint64_t mv = (uint64_t)(((unsigned __int128)n * gnum + gden - 1) / gden) + 3 * B;
+    *code_words = mv / 32 + B + 1;
+    *rank_words = mv / 512 + B + 1;
+    return MPHX_OK;
+}
+
 int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order, uint32_t B,
                          uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
                          const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
@@ -1196,6 +1252,140 @@ int mphx_graph_destroy(void* graph)
     g_err.clear();
     if (!graph) return MPHX_OK;
     HIP_TRY(hipGraphExecDestroy((hipGraphExec_t)graph));
+    return MPHX_OK;
+}
+
+
+static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const uint64_t* offs, uint64_t n,
+                     uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* bucket_off,
+                     uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
+                     void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
+{
+    g_err.clear();
+    if (k < 9 || k > 18) return fail(MPHX_EINVAL, "k must be in [9, 18]");
+    if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
+    if (n >= 0xFFFFFFFFull) return fail(MPHX_EINVAL, "n must be < 2^32 - 1");
+    if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank) return fail(MPHX_EINVAL, "null output");
+    if (n > 0 && (kind == MPHX_KEYS_U64 ? !keys : (!bytes || !offs))) return fail(MPHX_EINVAL, "null keys");
+    if (kind == MPHX_KEYS_STR && ((uintptr_t)bytes & 3)) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    const size_t need = mphx_hem_workspace_bytes(n, k, gnum, gden);
+    if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    const uint32_t B = 1u << k;
+    Carve c(ws);
+    HemLayout L;
+    layout_hem(c, n, k, gnum, gden, L);
+    {
+        Timed tm(PH_HASH, s);
+        if (kind == MPHX_KEYS_U64)
+            HIP_TRY(launch_hem_sig_u64(keys, n, seed, L.rec, s));
+        else
+            HIP_TRY(launch_hem_sig_str(bytes, offs, n, seed, L.rec, s));
+    }
+    {
+        Timed tm(PH_BUILD, s);
+        HIP_TRY(launch_hem_partition(L.rec, n, k, L.tmp, bucket_off, L.aux, s));
+    }
+    std::vector<uint64_t> bo(B + 1), co(B + 1), ro(B + 1);
+    std::vector<uint32_t> order(B);
+    HIP_TRY(hipMemcpyAsync(bo.data(), bucket_off, (B + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    uint64_t max_bucket = 0;
+    int rc = mphx_batch_layout(bo.data(), B, gnum, gden, co.data(), ro.data(), order.data(), &max_bucket);
+    if (rc) return rc;
+    if (max_bucket > hem_max_bucket(n, k))
+        return fail(MPHX_ENOMEM, "largest bucket %llu exceeds the workspace's bound %llu",
+                    (unsigned long long)max_bucket, (unsigned long long)hem_max_bucket(n, k));
+    HIP_TRY(hipMemcpyAsync(code_off, co.data(), (B + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(rank_off, ro.data(), (B + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(L.order, order.data(), B * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    {
+        Timed tm(PH_OTHER, s);
+        // the partitioned records read as u64 are the bucket keys
+        rc = batch_enqueue(reinterpret_cast<const uint64_t*>(L.rec), bucket_off, L.order, B, max_bucket, seed, gnum,
+                           gden, max_tries, code_off, rank_off, codes, rank, L.results, L.batch, L.batch_bytes,
+                           nullptr, s);
+        if (rc) return rc;
+    }
+    std::vector<mphx_bucket_result> res(B);
+    HIP_TRY(hipMemcpyAsync(res.data(), L.results, B * sizeof(mphx_bucket_result), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<uint64_t> sd(B);
+    uint32_t tries = 0, rounds = 0, failed = 0;
+    int worst = MPHX_OK;
+    for (uint32_t b = 0; b < B; b++) {
+        sd[b] = res[b].seed_used;
+        tries = std::max(tries, res[b].tries);
+        rounds = std::max(rounds, res[b].n_rounds);
+        if (res[b].status != MPHX_OK) {
+            failed++;
+            if (worst == MPHX_OK) worst = res[b].status;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(seeds, sd.data(), B * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g_timers.harvest();
+    if (info) {
+        memset(info, 0, sizeof *info);
+        info->m = co[B] * 32;
+        info->seed_used = seed;
+        info->tries = tries;
+        info->n_rounds = rounds;
+        info->n_core = failed;
+    }
+    if (worst != MPHX_OK)
+        return fail(worst == MPHX_ERANGE ? MPHX_ERANGE : MPHX_ECORE,
+                    "%u of %u buckets failed (two keys with one signature, or a 2-core on every try): "
+                    "build again with another seed", failed, B);
+    return MPHX_OK;
+}
+
+int mphx_hem_build_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed, uint32_t gamma_num,
+                       uint32_t gamma_den, uint32_t max_tries, uint64_t* bucket_off, uint64_t* code_off,
+                       uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank, void* ws,
+                       size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    return hem_build(MPHX_KEYS_U64, keys, nullptr, nullptr, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off,
+                     code_off, rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
+}
+
+int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint32_t k, uint64_t seed,
+                       uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* bucket_off,
+                       uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
+                       void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    return hem_build(MPHX_KEYS_STR, nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off,
+                     code_off, rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
+}
+
+int mphx_hem_lookup_u64(const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,
+                        const uint64_t* seeds, const uint64_t* codes, const uint64_t* rank, uint32_t k,
+                        uint32_t gamma_num, uint32_t gamma_den, uint64_t seed, const uint64_t* keys, uint64_t n,
+                        uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank || !keys || !out || k < 9 || k > 18 ||
+        gamma_num == 0 || gamma_den == 0)
+        return fail(MPHX_EINVAL, "null pointer, k outside [9, 18] or bad gamma");
+    HemTables t{bucket_off, code_off, rank_off, seeds, codes, rank, k, gamma_num, gamma_den};
+    HIP_TRY(launch_hem_lookup_u64(t, seed, keys, n, out, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_hem_lookup_str(const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,
+                        const uint64_t* seeds, const uint64_t* codes, const uint64_t* rank, uint32_t k,
+                        uint32_t gamma_num, uint32_t gamma_den, uint64_t seed, const uint8_t* bytes,
+                        const uint64_t* offs, uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank || !bytes || !offs || !out || k < 9 ||
+        k > 18 || gamma_num == 0 || gamma_den == 0)
+        return fail(MPHX_EINVAL, "null pointer, k outside [9, 18] or bad gamma");
+    if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    HemTables t{bucket_off, code_off, rank_off, seeds, codes, rank, k, gamma_num, gamma_den};
+    HIP_TRY(launch_hem_lookup_str(t, seed, bytes, offs, n, out, (hipStream_t)stream));
     return MPHX_OK;
 }
 

@@ -304,6 +304,37 @@ __device__ __forceinline__ uint64_t sf_eval_edge(const uint64_t* words, uint64_t
     return s % sigma;
 }
 
+// ----- HEM split (Section 3): signatures, buckets by their top bits, an MPHF per bucket ------
+__device__ __forceinline__ uint64_t hem_signature_u64(uint64_t key, uint64_t seed) { return fin((key ^ seed) + 4 * kGamma); }
+__device__ __forceinline__ uint64_t hem_signature_digest(uint64_t a, uint64_t b) { return fin(a ^ fin(b)); }
+// the key a signature stands for inside its bucket: its two 32-bit halves swapped
+__device__ __forceinline__ uint64_t hem_bucket_key(uint64_t sig) { return (sig << 32) | (sig >> 32); }
+
+struct HemTables {
+    const uint64_t* bucket_off;  // 2^k + 1 key offsets
+    const uint64_t* code_off;    // 2^k + 1 code-word offsets
+    const uint64_t* rank_off;    // 2^k + 1 rank-sample offsets
+    const uint64_t* seeds;       // 2^k bucket seeds
+    const uint64_t* codes;
+    const uint64_t* rank;
+    uint32_t k, gnum, gden;
+};
+
+__device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,
+                                              uint32_t v2);
+
+__device__ __forceinline__ uint64_t hem_eval(const HemTables& t, uint64_t sig)
+{
+    const uint64_t b = t.k ? sig >> (64 - t.k) : 0;
+    const uint64_t lo = t.bucket_off[b], nb = t.bucket_off[b + 1] - lo;
+    const uint64_t num = nb * (uint64_t)t.gnum, den = 3ull * t.gden;  // nb < 2^32: no overflow
+    const uint64_t P = (num + den - 1) / den;
+    const uint64_t s = hem_bucket_key(sig) ^ t.seeds[b];
+    uint32_t v0, v1, v2;
+    edge_of_digest(s, s, P, v0, v1, v2);
+    return lo + eval_edge(t.codes + t.code_off[b], t.rank + t.rank_off[b], v0, v1, v2);
+}
+
 __device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,
                                               uint32_t v2)
 {

@@ -142,8 +142,11 @@ struct EvalTables {
     uint64_t* out;
     uint64_t sigma;
     uint32_t bits;
+    HemTables hem;
 };
-constexpr int kHsEdges = 0, kHsEvalMphf = 1, kHsEvalSf = 2;
+// kHsHemSig writes each key's HEM signature record (out as uint2: high half, low half);
+// kHsEvalHem evaluates a HEM split
+constexpr int kHsEdges = 0, kHsEvalMphf = 1, kHsEvalSf = 2, kHsHemSig = 3, kHsEvalHem = 4;
 
 template <int kMode>
 __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __restrict__ bytes,
@@ -312,7 +315,13 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
             const uint64_t b = fin(B ^ sb ^ len);
             uint32_t v0, v1, v2;
             edge_of_digest(a, b, P, v0, v1, v2);
-            if constexpr (kMode == kHsEvalMphf) {
+            if constexpr (kMode == kHsHemSig || kMode == kHsEvalHem) {
+                const uint64_t sig = hem_signature_digest(a, b);
+                if constexpr (kMode == kHsHemSig)
+                    reinterpret_cast<uint2*>(mt.out)[i] = make_uint2((uint32_t)(sig >> 32), (uint32_t)sig);
+                else
+                    mt.out[i] = hem_eval(mt.hem, sig);
+            } else if constexpr (kMode == kHsEvalMphf) {
                 mt.out[i] = eval_edge(mt.codes, mt.rank, v0, v1, v2);
             } else if constexpr (kMode == kHsEvalSf) {
                 mt.out[i] = sf_eval_edge(mt.codes, mt.sigma, mt.bits, v0, v1, v2);
@@ -458,7 +467,7 @@ hipError_t launch_lookup_str_words(const uint64_t* codes, const uint64_t* rank, 
     const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
     const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
     k_hash_str_words<kHsEvalMphf><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
-                                                         EvalTables{codes, rank, out, 0, 0});
+                                                         EvalTables{codes, rank, out, 0, 0, HemTables{}});
     return hipGetLastError();
 }
 
@@ -470,7 +479,68 @@ hipError_t launch_sf_lookup_str_words(const uint64_t* words, uint64_t sigma, uin
     const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
     const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
     k_hash_str_words<kHsEvalSf><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
-                                                       EvalTables{words, nullptr, out, sigma, b});
+                                                       EvalTables{words, nullptr, out, sigma, b, HemTables{}});
+    return hipGetLastError();
+}
+
+// HEM signature records of u64 keys: (signature >> 32, signature & 0xFFFFFFFF), which read as
+// a u64 are the half-swapped signature (the key inside its bucket).
+__global__ __launch_bounds__(256) void k_hem_sig_u64(const uint64_t* __restrict__ keys, uint64_t n, uint64_t seed,
+                                                     uint2* __restrict__ rec)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t sig = hem_signature_u64(keys[i], seed);
+        rec[i] = make_uint2((uint32_t)(sig >> 32), (uint32_t)sig);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_hem_lookup_u64(HemTables t, uint64_t seed, const uint64_t* __restrict__ keys,
+                                                        uint64_t n, uint64_t* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = hem_eval(t, hem_signature_u64(keys[i], seed));
+}
+
+hipError_t launch_hem_sig_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint2* rec, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_hem_sig_u64<<<grid_cap(n, 16384), 256, 0, s>>>(keys, n, seed, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint2* rec,
+                              hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
+    const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
+    EvalTables t{};
+    t.out = reinterpret_cast<uint64_t*>(rec);
+    // P only shapes the (unused) edge: any valid value
+    k_hash_str_words<kHsHemSig><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, 1, nullptr, PartHist1{nullptr, 0, 0}, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_hem_lookup_u64(const HemTables& t, uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out,
+                                 hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_hem_lookup_u64<<<grid_cap(n, 16384), 256, 0, s>>>(t, seed, keys, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hem_lookup_str(const HemTables& ht, uint64_t seed, const uint8_t* bytes, const uint64_t* offs,
+                                 uint64_t n, uint64_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
+    const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
+    EvalTables t{};
+    t.out = out;
+    t.hem = ht;
+    k_hash_str_words<kHsEvalHem><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, 1, nullptr, PartHist1{nullptr, 0, 0}, t);
     return hipGetLastError();
 }
 

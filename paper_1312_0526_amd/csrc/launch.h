@@ -160,6 +160,19 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
 // assignment, ranking, lookup (solve.hip)
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
                                uint8_t* code8, unsigned grid_cap, hipStream_t s);
+// HEM split (keys.hip, part.hip): signature records (high, low half: a u64 read gives the
+// bucket key), their partition into 2^k buckets in place (tmp: n more pairs; 9 <= k <= 18)
+// with bucket_off[0..2^k] written on the device, and lookups
+hipError_t launch_hem_sig_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint2* rec, hipStream_t s);
+hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint2* rec,
+                              hipStream_t s);
+size_t hem_aux_bytes(uint64_t n, uint32_t k);
+hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, uint64_t* bucket_off, void* aux,
+                                hipStream_t s);
+hipError_t launch_hem_lookup_u64(const HemTables& t, uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out,
+                                 hipStream_t s);
+hipError_t launch_hem_lookup_str(const HemTables& t, uint64_t seed, const uint8_t* bytes, const uint64_t* offs,
+                                 uint64_t n, uint64_t* out, hipStream_t s);
 // static functions (solve.hip; string lookups in keys.hip)
 hipError_t launch_sf_lookup_str_words(const uint64_t* words, uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed,
                                       const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,

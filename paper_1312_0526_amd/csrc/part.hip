@@ -706,6 +706,46 @@ hipError_t launch_claims_resolve(const PeelState& st, uint32_t r, uint64_t count
         s);
 }
 
+// HEM: bucket_off[b] for b in [0, 2^k] from the second pass's scan
+__global__ __launch_bounds__(256) void k_hem_bucket_off(const uint32_t* __restrict__ ginfo, uint32_t NH,
+                                                        const uint32_t* __restrict__ off2, uint64_t n, uint32_t B,
+                                                        uint64_t* __restrict__ bucket_off)
+{
+    const GroupInfo g(ginfo);
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b <= B; b += gridDim.x * blockDim.x)
+        bucket_off[b] = bucket_start(g, off2, NH, n, b);
+}
+
+size_t hem_aux_bytes(uint64_t n, uint32_t k)
+{
+    const uint32_t NH = 1u << (k - 8);
+    return aux_layout((uint64_t)NH * tiles_of(n), n, NH).total;
+}
+
+hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, uint64_t* bucket_off, void* aux,
+                                hipStream_t s)
+{
+    // the group digit is x >> (40 - k): k >= 9 keeps the shift below 32 (at least two groups)
+    if (k < 9 || k > 18) return hipErrorInvalidValue;
+    const uint32_t NH = 1u << (k - 8), gsh = 40 - k, B = 1u << k;
+    const AuxLayout L = aux_layout((uint64_t)NH * tiles_of(n), n, NH);
+    uint8_t* base = reinterpret_cast<uint8_t*>(aux);
+    uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
+    const uint64_t nt1 = tiles_of(n);
+    if (n == 0) return launch_zero(bucket_off, (B + 1ull) * sizeof(uint64_t), s);
+    if (nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{rec}, n, gsh, NH, nt1, hist1);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return partition_then(
+        Records{rec}, n, gsh, NH, hist1, tmp, rec, L, base,
+        [&](const uint32_t* ginfo, const uint32_t* off2) {
+            k_hem_bucket_off<<<(B + 256) / 256, 256, 0, s>>>(ginfo, NH, off2, n, B, bucket_off);
+            return hipGetLastError();
+        },
+        s);
+}
+
 hipError_t launch_update_apply(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s)
 {
     if (count == 0) return hipSuccess;
