@@ -350,26 +350,15 @@ LOOKUP_BATCH = 1 << 16
 LOOKUP_REPEATS = 10
 
 
-def lookup_leg(mx, torch, r: dict, n: int, kind: int, keys=None, data=None, offs=None,
-               ceilings=None) -> dict:
-    """Evaluation of the MPHF just built, in the paper's lookup-experiment shape (Section 5,
-    Table 2): 10^7 distinct keys of the set (its first ones), in batches of 2^16 keys, all
-    batches repeated 10 times back to back on the stream; per-batch time from HIP events."""
-    nk = min(LOOKUP_KEYS, n)
-    dev = torch.device("cuda:0")
-    out = torch.empty(nk, dtype=torch.int64, device=dev)
-    codes, rank, P, seed = r["codes"], r["rank"], r["P"], r["seed_used"]
-
-    def run(b0, b1):
-        if kind == mx.KEYS_U64:
-            mx.lookup_u64(codes, rank, P, seed, keys[b0:b1], out=out[b0:b1])
-        else:
-            mx.lookup_str(codes, rank, P, seed, data, offs[b0:b1 + 1], out=out[b0:b1])
-
+def table2_lookups(torch, n: int, nk: int, run, out) -> dict:
+    """Lookups in the paper's lookup-experiment shape (Section 5, Table 2): the first nk keys
+    of the set in batches of 2^16 keys, all batches repeated 10 times back to back on the
+    stream; per-batch time from HIP events.  run(b0, b1) evaluates keys [b0, b1) into
+    out[b0:b1].  Checks that the values are distinct, below n, and that the batched
+    evaluation equals one call over all keys."""
     batches = [(b, min(b + LOOKUP_BATCH, nk)) for b in range(0, nk, LOOKUP_BATCH)]
     run(0, nk)
     torch.cuda.synchronize()
-    # the values of distinct keys are distinct and below n
     distinct = int(torch.unique(out).numel())
     ok = distinct == nk and int(out.min().item()) >= 0 and int(out.max().item()) < n
     whole = out.clone()
@@ -382,7 +371,7 @@ def lookup_leg(mx, torch, r: dict, n: int, kind: int, keys=None, data=None, offs
             ev[j].record()
             j += 1
     torch.cuda.synchronize()
-    ok = ok and bool(torch.equal(out, whole))  # batched evaluation equals one call over all keys
+    ok = ok and bool(torch.equal(out, whole))
     per_key = []
     for k in range(1, j):
         b0, b1 = batches[(k - 1) % len(batches)]
@@ -390,21 +379,39 @@ def lookup_leg(mx, torch, r: dict, n: int, kind: int, keys=None, data=None, offs
     total_ms = ev[0].elapsed_time(ev[j - 1])
     mean = sum(per_key) / len(per_key)
     sd = (sum((x - mean) ** 2 for x in per_key) / len(per_key)) ** 0.5
-    lookups = LOOKUP_REPEATS * nk
-    rate = lookups / (total_ms / 1e3)
+    rate = LOOKUP_REPEATS * nk / (total_ms / 1e3)
+    del whole
+    return dict(workload=f"lookup_{nk}_keys_batches_of_{LOOKUP_BATCH}", keys=nk, batch=LOOKUP_BATCH,
+                batches=len(batches) * LOOKUP_REPEATS, ns_per_key=round(mean, 4), rel_std=round(sd / mean, 4),
+                lookups_per_s=round(rate, 1), values_distinct_and_in_range=ok)
+
+
+def lookup_leg(mx, torch, r: dict, n: int, kind: int, keys=None, data=None, offs=None,
+               ceilings=None) -> dict:
+    """Evaluation of the MPHF just built in the shape of Table 2 (see table2_lookups)."""
+    nk = min(LOOKUP_KEYS, n)
+    out = torch.empty(nk, dtype=torch.int64, device=torch.device("cuda:0"))
+    codes, rank, P, seed = r["codes"], r["rank"], r["P"], r["seed_used"]
+
+    def run(b0, b1):
+        if kind == mx.KEYS_U64:
+            mx.lookup_u64(codes, rank, P, seed, keys[b0:b1], out=out[b0:b1])
+        else:
+            mx.lookup_str(codes, rank, P, seed, data, offs[b0:b1 + 1], out=out[b0:b1])
+
+    res = table2_lookups(torch, n, nk, run, out)
+    res["paper_ns_per_key_one_core"] = "199-415 (Table 2, three CPUs, one thread)"
+    rate = res["lookups_per_s"]
     # each lookup gathers three code words, one rank sample and the hinge's rank block: about
     # four random lines besides the streamed key
-    res = dict(workload=f"lookup_{nk}_keys_batches_of_{LOOKUP_BATCH}", keys=nk, batch=LOOKUP_BATCH,
-               batches=len(batches) * LOOKUP_REPEATS, ns_per_key=round(mean, 4), rel_std=round(sd / mean, 4),
-               lookups_per_s=round(rate, 1), values_distinct_and_in_range=ok,
-               paper_ns_per_key_one_core="199-415 (Table 2, three CPUs, one thread)")
     if ceilings and ceilings.get("load8_Gops"):
         res["roofline"] = dict(bound="random gathers", achieved=round(4 * rate / 1e9, 2),
                                peak=ceilings["load8_Gops"], unit="G gathers/s",
                                frac=round(4 * rate / 1e9 / ceilings["load8_Gops"], 3))
-    log(f"[lookup] {nk} keys in {len(batches)} batches of {LOOKUP_BATCH} x {LOOKUP_REPEATS}: "
-        f"{mean:.3f} ns/key per batch (rel. sd {sd / mean:.3f}), {rate / 1e9:.2f} G lookups/s, ok={ok}")
-    del out, whole
+    log(f"[lookup] {nk} keys in batches of {LOOKUP_BATCH} x {LOOKUP_REPEATS}: {res['ns_per_key']:.3f} ns/key "
+        f"per batch (rel. sd {res['rel_std']:.3f}), {rate / 1e9:.2f} G lookups/s, "
+        f"ok={res['values_distinct_and_in_range']}")
+    del out
     return res
 
 
@@ -512,14 +519,24 @@ def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None)
             hit.index_fill_(0, out, 1)
         ok = inrange and int(hit.sum(dtype=torch.int64).item()) == n
         del hit
+        nk = min(LOOKUP_KEYS, n)
+
+        def run(b0, b1):
+            if kind == mx.KEYS_U64:
+                mx.hem_lookup(h, keys=keys[b0:b1], out=out[b0:b1])
+            else:
+                mx.hem_lookup(h, data=data, offs=offs[b0:b1 + 1], out=out[b0:b1])
+
+        t2 = table2_lookups(torch, n, nk, run, out[:nk])
         sizes = (h["bucket_off"][1:] - h["bucket_off"][:-1])
         rows[f"k{k}"] = dict(buckets=B, ms_per_build=round(sec * 1e3, 3), keys_per_s=round(n / sec, 1),
                              bits_per_key=round(bits / n, 4), max_bucket=int(sizes.max().item()),
                              max_tries=h["tries"], max_rounds=h["n_rounds"], phases_ms=phases,
                              lookup_all_ms=round(lk_ms, 3), lookup_ns_per_key=round(lk_ms * 1e6 / n, 4),
-                             bijection=ok)
+                             bijection=ok, table2_lookup=t2)
         log(f"[hem] k={k}: {sec * 1e3:.1f} ms/build, {n / sec / 1e9:.3f} G keys/s, {bits / n:.3f} bits/key, "
-            f"lookup {lk_ms * 1e6 / n:.3f} ns/key, bijection ok={ok}")
+            f"lookup {lk_ms * 1e6 / n:.3f} ns/key, bijection ok={ok}; Table 2 shape {t2['ns_per_key']:.3f} ns/key "
+            f"per batch, ok={t2['values_distinct_and_in_range']}")
         del h, sizes
     del ws, out
     torch.cuda.empty_cache()
@@ -631,7 +648,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
                     help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served")
-    ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[15],
+    ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
                     help="bucket-count exponents of the hem leg")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
