@@ -543,6 +543,86 @@ def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None)
     return dict(workload="hem_split_same_keys", rows=rows)
 
 
+def hem_host_leg(args, mx, torch) -> dict:
+    """HEM split of a u64 key set held in host memory (pinned when the host allows) and larger than device memory
+    would allow in place: the keys stream over PCIe in chunks, only their 8-byte signatures stay
+    on the device.  Times whole builds (transfers included), then streams the keys again to look
+    every one up and checks that the values form a bijection onto [0, n)."""
+    dev = torch.device("cuda:0")
+    n, k = args.hem_host_n, args.hem_host_k
+    chunk, batch = args.hem_host_chunk, args.hem_host_batch
+    gamma = (123, 100)
+    t0 = time.perf_counter()
+    try:
+        hk = torch.empty(n, dtype=torch.int64, pin_memory=True)
+        memory = "pinned"
+    except RuntimeError as e:  # the host may cap page-locked memory: ordinary pages then
+        log(f"[hem_host] pinned allocation of {8 * n / 1e9:.1f} GB refused ({str(e).splitlines()[0]}): pageable")
+        hk = torch.empty(n, dtype=torch.int64)
+        hk[::512] = 0  # touch every page before timing
+        memory = "pageable"
+    t_pin = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for c0 in range(0, n, chunk):  # the u64 key generator on the device, copied down
+        c1 = min(n, c0 + chunk)
+        hk[c0:c1].copy_(mx.gen_keys_u64(c1 - c0, gen_seed=0, start=c0, device=dev))
+    torch.cuda.synchronize()
+    log(f"[hem_host] {n} keys ({8 * n / 1e9:.1f} GB) in {memory} host memory: allocated in {t_pin:.1f} s, "
+        f"generated in {time.perf_counter() - t0:.1f} s")
+    need = mx.hem_host_workspace_bytes(n, k, mx.KEYS_U64, chunk, 0, batch, gamma)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    in_place = mx.hem_workspace_bytes(n, k, gamma) + 8 * n  # the in-HBM split: keys + its workspace
+    log(f"[hem_host] device workspace {need / 1e9:.1f} GB (the in-HBM split would need {in_place / 1e9:.1f} GB)")
+
+    mx.set_option("timing", 1)
+
+    def step():
+        return mx.hem_build_host(keys=hk, k=k, seed=0, gamma=gamma, chunk_keys=chunk, batch_keys=batch, ws=ws,
+                                 device=dev)
+
+    h = step()
+    torch.cuda.synchronize()
+    mx.phase_times(reset=True)
+    steps = max(1, min(args.steps, 2))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        del h
+        h = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    phases = {p: round(v[0] / steps, 3) for p, v in mx.phase_times(reset=True).items() if v[1]}
+    B = 1 << k
+    bits = 64 * (h["codes"].numel() + h["rank"].numel()) + 64 * (4 * B + 3)
+    del ws
+    torch.cuda.empty_cache()
+    # every key looked up, chunk by chunk from host memory; the values must hit [0, n) once each
+    hit = torch.zeros(n, dtype=torch.uint8, device=dev)
+    out = torch.empty(chunk, dtype=torch.int64, device=dev)
+    dk = torch.empty(chunk, dtype=torch.int64, device=dev)
+    ok = True
+    t0 = time.perf_counter()
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        dk[: c1 - c0].copy_(hk[c0:c1], non_blocking=True)
+        f = mx.hem_lookup(h, keys=dk[: c1 - c0], out=out[: c1 - c0])
+        ok = ok and bool(int(f.min().item()) >= 0 and int(f.max().item()) < n)
+        if ok:
+            hit.index_fill_(0, f, 1)
+    ok = ok and int(hit.sum(dtype=torch.int64).item()) == n
+    torch.cuda.synchronize()
+    t_check = time.perf_counter() - t0
+    del hit, out, dk, h, hk
+    torch.cuda.empty_cache()
+    log(f"[hem_host] k={k}: {sec:.2f} s/build = {n / sec / 1e9:.3f} G keys/s with transfers, phases {phases}, "
+        f"{bits / n:.3f} bits/key; all-key lookups from host memory in {t_check:.1f} s, bijection ok={ok}")
+    return dict(workload=f"hem_host_u64_n{n}_k{k}", host_memory=memory, keys=n, key_bytes=8 * n, k=k,
+                chunk_keys=chunk,
+                batch_keys=batch, device_workspace_bytes=need, in_hbm_split_bytes=in_place,
+                s_per_build=round(sec, 3), keys_per_s=round(n / sec, 1), phases_ms=phases,
+                stream_GBps=round(8 * n / (phases.get("hash", 0) / 1e3) / 1e9, 1) if phases.get("hash") else None,
+                bits_per_key=round(bits / n, 4), bijection=ok, check_s=round(t_check, 1))
+
+
 SERVE_WORKLOAD = "mwhc_served_poisson_sizes_loguniform_1e3_1e8_u64_or_str_gamma1.23"
 
 
@@ -647,9 +727,13 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
-                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served")
+                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host")
     ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
                     help="bucket-count exponents of the hem leg")
+    ap.add_argument("--hem-host-n", type=int, default=1 << 34, help="keys of the hem_host leg (host memory)")
+    ap.add_argument("--hem-host-k", type=int, default=18)
+    ap.add_argument("--hem-host-chunk", type=int, default=1 << 27, help="keys per host-to-device chunk")
+    ap.add_argument("--hem-host-batch", type=int, default=1 << 28, help="keys per gathered batch of groups")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
@@ -702,6 +786,8 @@ def main() -> int:
             side["batched"] = batched_leg(args, mx, torch, np, workloads)
         if "served" in legs:
             side["served"] = served_leg(args, mx, torch, np, workloads)
+        if "hem_host" in legs:
+            side["hem_host"] = hem_host_leg(args, mx, torch)
         print(json.dumps(side), flush=True)
         return 0
 
@@ -844,6 +930,7 @@ def main() -> int:
     torch.cuda.empty_cache()
     batched = batched_leg(args, mx, torch, np, workloads) if "batched" in legs else None
     served = served_leg(args, mx, torch, np, workloads) if "served" in legs else None
+    hem_host = hem_host_leg(args, mx, torch) if "hem_host" in legs else None
 
     out = {
         "metric": "edges peeled/s (hash+peel+assign+rank), plain single-hypergraph build",
@@ -870,6 +957,7 @@ def main() -> int:
         "hem": hem,
         "batched": batched,
         "served": served,
+        "hem_host": hem_host,
     }
     print(json.dumps(out), flush=True)
     return 0

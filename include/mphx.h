@@ -309,6 +309,39 @@ MPHX_API int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint
                                 uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* bucket_off,
                                 uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes,
                                 uint64_t* rank, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
+/* ---------------------------------------------------------------------------------------
+ * The HEM split with the keys in HOST memory, for key sets larger than device memory (the
+ * paper's key sets reach 7.6 * 10^9 keys, Table 1).  The result -- every output
+ * above, bit for bit -- equals mphx_hem_build_* on the same keys, seed, k and gamma; the
+ * lookups are mphx_hem_lookup_* (device keys, in batches of any size).
+ *   keys (host, n uint64) or bytes + offs (host: key i is bytes[offs[i], offs[i+1]), offs
+ *   non-decreasing, n + 1 entries): read by hipMemcpyAsync in chunks of at most chunk_keys keys
+ *   (strings: and at most chunk_bytes bytes from the 256-byte boundary below the chunk's first
+ *   key, so every key must be shorter than chunk_bytes - 255).  Pinned memory (hipHostMalloc)
+ *   gives the full PCIe rate; pageable memory works, slower.  Device memory: 8 bytes per key
+ *   for the grouped signatures plus chunk and batch buffers: mphx_hem_host_workspace_bytes
+ *   (kind = MPHX_KEYS_U64 or MPHX_KEYS_STR; chunk_bytes ignored for u64; 0 for bad
+ *   arguments).  Each chunk's signatures are grouped by their top k - 8 bits; then batches of
+ *   consecutive groups holding at most batch_keys keys are gathered from every chunk,
+ *   partitioned into their buckets and built.  Outputs, seeds and errors as above;
+ *   MPHX_ENOMEM also when one group holds more than batch_keys keys (groups hold about
+ *   n / 2^(k-8): take batch_keys at least twice that).  chunk_keys, batch_keys in
+ *   [1, 2^31 - 1), chunk_bytes >= 512.  Synchronises.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API size_t mphx_hem_host_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den,
+                                              int kind, uint64_t chunk_keys, uint64_t chunk_bytes,
+                                              uint64_t batch_keys);
+MPHX_API int mphx_hem_build_host_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed,
+                                     uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries,
+                                     uint64_t chunk_keys, uint64_t batch_keys, uint64_t* bucket_off,
+                                     uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes,
+                                     uint64_t* rank, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_hem_build_host_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint32_t k,
+                                     uint64_t seed, uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries,
+                                     uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys,
+                                     uint64_t* bucket_off, uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds,
+                                     uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, void* stream,
+                                     mphx_mphf_info* info);
 MPHX_API int mphx_hem_lookup_u64(const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,
                                  const uint64_t* seeds, const uint64_t* codes, const uint64_t* rank, uint32_t k,
                                  uint32_t gamma_num, uint32_t gamma_den, uint64_t seed, const uint64_t* keys,

@@ -10,5 +10,5 @@ from ._lib import (  # noqa: F401
     mphf_build_str, mphf_build_u64, mphf_workspace_bytes, part_size, peel, phase_times, set_option,
     PROBE_ATOMIC_ADD, PROBE_ATOMIC_ADD_RET, PROBE_LDS_ATOMIC_ADD, PROBE_LOAD8, PROBE_STORE1, probe_copy, probe_random,
     sf_bits, sf_build_str, sf_build_u64, sf_lookup_str, sf_lookup_u64, sf_words, sf_workspace_bytes,
-    hem_build, hem_capacity, hem_lookup, hem_workspace_bytes,
+    hem_build, hem_build_host, hem_capacity, hem_host_workspace_bytes, hem_lookup, hem_workspace_bytes,
 )

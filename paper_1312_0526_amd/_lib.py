@@ -65,6 +65,11 @@ _SIGS = {
                                   C.POINTER(MphfInfo)]),
     "mphx_hem_build_str": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                   _vp, C.POINTER(MphfInfo)]),
+    "mphx_hem_host_workspace_bytes": (_sz, [_u64, _u32, _u32, _u32, _i32, _u64, _u64, _u64]),
+    "mphx_hem_build_host_u64": (_i32, [_vp, _u64, _u32, _u64, _u32, _u32, _u32, _u64, _u64, _vp, _vp, _vp, _vp, _vp,
+                                       _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
+    "mphx_hem_build_host_str": (_i32, [_vp, _vp, _u64, _u32, _u64, _u32, _u32, _u32, _u64, _u64, _u64, _vp, _vp, _vp,
+                                       _vp, _vp, _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
     "mphx_hem_lookup_u64": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u64, _vp, _u64, _vp, _vp]),
     "mphx_hem_lookup_str": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _u32, _u32, _u32, _u64, _vp, _vp, _u64, _vp, _vp]),
     "mphx_mphf_lookup_u64": (_i32, [_vp, _vp, _u64, _u64, _vp, _u64, _vp, _vp]),
@@ -321,6 +326,62 @@ def hem_build(keys=None, data=None, offs=None, k: int = 15, seed: int = 0, gamma
         rc = lib().mphx_hem_build_u64(_ptr(keys), n, k, seed, gamma[0], gamma[1], max_tries, *common)
     else:
         rc = lib().mphx_hem_build_str(_ptr(data), _ptr(offs), n, k, seed, gamma[0], gamma[1], max_tries, *common)
+    if rc:
+        _err(rc, info.as_dict())
+    d = info.as_dict()
+    nc = int(t["code_off"][-1].item())
+    nr = int(t["rank_off"][-1].item())
+    d.update(t, codes=codes[:nc], rank=rank[:nr], k=k, seed=seed, gamma=gamma, n=n)
+    return d
+
+
+def _check_host(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or t.is_cuda:
+        raise TypeError(f"{name} must be a host (CPU) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def hem_host_workspace_bytes(n: int, k: int, kind: int, chunk_keys: int, chunk_bytes: int = 0, batch_keys: int = 0,
+                             gamma=(123, 100)) -> int:
+    return int(lib().mphx_hem_host_workspace_bytes(n, k, gamma[0], gamma[1], kind, chunk_keys, chunk_bytes,
+                                                   batch_keys))
+
+
+def hem_build_host(keys=None, data=None, offs=None, k: int = 15, seed: int = 0, gamma=(123, 100), max_tries: int = 64,
+                   chunk_keys: int = 1 << 26, chunk_bytes: int = 1 << 30, batch_keys: int = 1 << 28, ws=None,
+                   device="cuda") -> dict:
+    """HEM split of keys held in host memory (CPU tensors, pinned for the full PCIe rate): u64
+    keys (keys) or string keys (data + offs).  The device tables equal hem_build's."""
+    dev = torch.device(device)
+    if keys is not None:
+        _check_host(keys, torch.int64, "keys")
+        n, kind = keys.numel(), KEYS_U64
+    else:
+        _check_host(data, torch.uint8, "data")
+        _check_host(offs, torch.int64, "offs")
+        n, kind = offs.numel() - 1, KEYS_STR
+    B = 1 << k
+    cw, rw = hem_capacity(n, k, gamma)
+    t = {name: torch.empty(B + 1, dtype=torch.int64, device=dev) for name in ("bucket_off", "code_off", "rank_off")}
+    t["seeds"] = torch.empty(B, dtype=torch.int64, device=dev)
+    codes = torch.empty(max(cw, 1), dtype=torch.int64, device=dev)
+    rank = torch.empty(max(rw, 1), dtype=torch.int64, device=dev)
+    need = hem_host_workspace_bytes(n, k, kind, chunk_keys, chunk_bytes, batch_keys, gamma)
+    if need == 0:
+        raise ValueError("bad k, gamma, chunk or batch size")
+    ws = ws if ws is not None else _workspace(need, dev)
+    info = MphfInfo()
+    common = (_ptr(t["bucket_off"]), _ptr(t["code_off"]), _ptr(t["rank_off"]), _ptr(t["seeds"]), _ptr(codes),
+              _ptr(rank), _ptr(ws), ws.numel(), _stream(dev), C.byref(info))
+    if keys is not None:
+        rc = lib().mphx_hem_build_host_u64(_ptr(keys), n, k, seed, gamma[0], gamma[1], max_tries, chunk_keys,
+                                           batch_keys, *common)
+    else:
+        rc = lib().mphx_hem_build_host_str(_ptr(data), _ptr(offs), n, k, seed, gamma[0], gamma[1], max_tries,
+                                           chunk_keys, chunk_bytes, batch_keys, *common)
     if rc:
         _err(rc, info.as_dict())
     d = info.as_dict()

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -1256,6 +1257,43 @@ int mphx_graph_destroy(void* graph)
 }
 
 
+// The per-bucket results of a HEM build: seeds written, info filled, failed buckets reported.
+static int hem_finish(uint32_t B, const mphx_bucket_result* results, uint64_t seed, uint64_t code_words,
+                      uint64_t* seeds, hipStream_t s, mphx_mphf_info* info)
+{
+    std::vector<mphx_bucket_result> res(B);
+    HIP_TRY(hipMemcpyAsync(res.data(), results, B * sizeof(mphx_bucket_result), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<uint64_t> sd(B);
+    uint32_t tries = 0, rounds = 0, failed = 0;
+    int worst = MPHX_OK;
+    for (uint32_t b = 0; b < B; b++) {
+        sd[b] = res[b].seed_used;
+        tries = std::max(tries, res[b].tries);
+        rounds = std::max(rounds, res[b].n_rounds);
+        if (res[b].status != MPHX_OK) {
+            failed++;
+            if (worst == MPHX_OK) worst = res[b].status;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(seeds, sd.data(), B * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    g_timers.harvest();
+    if (info) {
+        memset(info, 0, sizeof *info);
+        info->m = code_words * 32;
+        info->seed_used = seed;
+        info->tries = tries;
+        info->n_rounds = rounds;
+        info->n_core = failed;
+    }
+    if (worst != MPHX_OK)
+        return fail(worst == MPHX_ERANGE ? MPHX_ERANGE : MPHX_ECORE,
+                    "%u of %u buckets failed (two keys with one signature, or a 2-core on every try): "
+                    "build again with another seed", failed, B);
+    return MPHX_OK;
+}
+
 static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const uint64_t* offs, uint64_t n,
                      uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* bucket_off,
                      uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
@@ -1307,37 +1345,201 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
                            nullptr, s);
         if (rc) return rc;
     }
-    std::vector<mphx_bucket_result> res(B);
-    HIP_TRY(hipMemcpyAsync(res.data(), L.results, B * sizeof(mphx_bucket_result), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::vector<uint64_t> sd(B);
-    uint32_t tries = 0, rounds = 0, failed = 0;
-    int worst = MPHX_OK;
-    for (uint32_t b = 0; b < B; b++) {
-        sd[b] = res[b].seed_used;
-        tries = std::max(tries, res[b].tries);
-        rounds = std::max(rounds, res[b].n_rounds);
-        if (res[b].status != MPHX_OK) {
-            failed++;
-            if (worst == MPHX_OK) worst = res[b].status;
+    return hem_finish(B, L.results, seed, co[B], seeds, s, info);
+}
+
+// ---- HEM split with the keys in host memory (key sets beyond HBM) ------------------------
+// The keys stream through the device in chunks: each chunk's signatures are grouped by their
+// top k - 8 bits into the resident signature array, so the device holds 8 bytes per key and
+// never the keys.  Then batches of consecutive groups are gathered from every chunk,
+// partitioned into their buckets and built by the batched kernel.  Each bucket's MPHF depends
+// only on the set of its keys, so the result equals the in-HBM split's.
+static constexpr uint32_t kHemRunMax = 1u << 16;    // records per gather run
+static constexpr uint32_t kHemRunSlots = 1u << 16;  // runs per gather launch
+
+struct HemHostLayout {
+    uint2 *sig, *csig, *bsig, *btmp;
+    uint8_t* stage;
+    uint64_t* soffs;
+    void *caux, *baux;
+    uint64_t* lbo;
+    uint32_t* order;
+    HemRun* runs;
+    mphx_bucket_result* results;
+    uint8_t* batch;
+    size_t batch_bytes;
+};
+
+static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden,
+                            uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys, HemHostLayout& L)
+{
+    const uint32_t B = 1u << k;
+    L.sig = c.take<uint2>(n);
+    if (kind == MPHX_KEYS_U64) {
+        L.stage = reinterpret_cast<uint8_t*>(c.take<uint64_t>(chunk_keys));
+        L.soffs = nullptr;
+    } else {
+        L.stage = c.take<uint8_t>(chunk_bytes);
+        L.soffs = c.take<uint64_t>(chunk_keys + 1);
+    }
+    L.csig = c.take<uint2>(chunk_keys);
+    L.caux = c.take<uint8_t>(hem_aux_bytes(chunk_keys, k));
+    L.bsig = c.take<uint2>(batch_keys);
+    L.btmp = c.take<uint2>(batch_keys);
+    L.baux = c.take<uint8_t>(hem_aux_bytes(batch_keys, k));
+    L.lbo = c.take<uint64_t>(B + 1);
+    L.order = c.take<uint32_t>(B);
+    L.runs = c.take<HemRun>(kHemRunSlots);
+    L.results = c.take<mphx_bucket_result>(B);
+    L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, nullptr);
+    L.batch = c.take<uint8_t>(L.batch_bytes);
+}
+
+static int hem_host_args(int kind, uint32_t k, uint32_t gnum, uint32_t gden, uint64_t chunk_keys,
+                         uint64_t chunk_bytes, uint64_t batch_keys)
+{
+    if (k < 9 || k > 18) return fail(MPHX_EINVAL, "k must be in [9, 18]");
+    if (gnum == 0 || gden == 0) return fail(MPHX_EINVAL, "bad gamma");
+    if (chunk_keys == 0 || chunk_keys >= 0x7FFFFFFFull) return fail(MPHX_EINVAL, "chunk_keys must be in [1, 2^31 - 1)");
+    if (batch_keys == 0 || batch_keys >= 0x7FFFFFFFull) return fail(MPHX_EINVAL, "batch_keys must be in [1, 2^31 - 1)");
+    if (kind == MPHX_KEYS_STR && chunk_bytes < 512) return fail(MPHX_EINVAL, "chunk_bytes must be at least 512");
+    return MPHX_OK;
+}
+
+static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes, const uint64_t* hoffs, uint64_t n,
+                          uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+                          uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys, uint64_t* bucket_off,
+                          uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
+                          void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
+{
+    g_err.clear();
+    int rc = hem_host_args(kind, k, gnum, gden, chunk_keys, chunk_bytes, batch_keys);
+    if (rc) return rc;
+    if (max_tries == 0) return fail(MPHX_EINVAL, "max_tries must be positive");
+    if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank) return fail(MPHX_EINVAL, "null output");
+    if (n > 0 && (kind == MPHX_KEYS_U64 ? !hkeys : (!hbytes || !hoffs))) return fail(MPHX_EINVAL, "null keys");
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    const size_t need = mphx_hem_host_workspace_bytes(n, k, gnum, gden, kind, chunk_keys, chunk_bytes, batch_keys);
+    if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if (kind == MPHX_KEYS_STR && n > 0)
+        for (uint64_t i = 0; i < n; i++)
+            if (hoffs[i + 1] < hoffs[i]) return fail(MPHX_EINVAL, "offsets decrease at key %llu", (unsigned long long)i);
+    const uint32_t NH = 1u << (k - 8), B = 1u << k;
+    Carve c(ws);
+    HemHostLayout L;
+    layout_hem_host(c, kind, n, k, gnum, gden, chunk_keys, chunk_bytes, batch_keys, L);
+
+    // host buffers the stream copies from or into; the guard, destroyed first, lets every copy
+    // finish before they go, on every return
+    std::vector<uint64_t> cbase;
+    std::vector<std::unique_ptr<uint32_t[]>> gst;  // per chunk: NH + 1 group starts (filled by the stream)
+    std::vector<uint64_t> bo(B + 1, 0), co(B + 1, 0), ro(B + 1, 0), lbo(B + 1);
+    std::vector<uint32_t> ord(B);
+    std::vector<uint64_t> co_l(B + 1), ro_l(B + 1);
+    std::vector<HemRun> runs;
+    struct DrainOnExit {
+        hipStream_t s;
+        ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+    } drain{s};
+
+    // 1. stream the chunks: signatures, grouped into the resident array at the chunk's place
+    {
+        Timed tm(PH_HASH, s);
+        for (uint64_t c0 = 0; c0 < n;) {
+            uint64_t c1 = std::min(n, c0 + chunk_keys);
+            if (kind == MPHX_KEYS_U64) {
+                HIP_TRY(hipMemcpyAsync(L.stage, hkeys + c0, (c1 - c0) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_hem_sig_u64(reinterpret_cast<const uint64_t*>(L.stage), c1 - c0, seed, L.csig, s));
+            } else {
+                // the chunk's bytes from a 256-byte boundary, so every key keeps its alignment phase
+                const uint64_t bbase = hoffs[c0] & ~255ull, limit = bbase + chunk_bytes;
+                c1 = (uint64_t)(std::upper_bound(hoffs + c0 + 1, hoffs + c1 + 1, limit) - hoffs) - 1;
+                if (c1 == c0)
+                    return fail(MPHX_EINVAL, "key %llu does not fit in chunk_bytes - 255 bytes", (unsigned long long)c0);
+                HIP_TRY(hipMemcpyAsync(L.stage, hbytes + bbase, hoffs[c1] - bbase, hipMemcpyHostToDevice, s));
+                HIP_TRY(hipMemcpyAsync(L.soffs, hoffs + c0, (c1 - c0 + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_offs_rebase(L.soffs, c1 - c0 + 1, bbase, s));
+                HIP_TRY(launch_hem_sig_str(L.stage, L.soffs, c1 - c0, seed, L.csig, s));
+            }
+            gst.emplace_back(new uint32_t[NH + 1]);
+            HIP_TRY(launch_hem_group_chunk(L.csig, c1 - c0, k, L.sig + c0, L.caux, gst.back().get(), s));
+            cbase.push_back(c0);
+            c0 = c1;
         }
     }
-    HIP_TRY(hipMemcpyAsync(seeds, sd.data(), B * sizeof(uint64_t), hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
-    g_timers.harvest();
-    if (info) {
-        memset(info, 0, sizeof *info);
-        info->m = co[B] * 32;
-        info->seed_used = seed;
-        info->tries = tries;
-        info->n_rounds = rounds;
-        info->n_core = failed;
+    const size_t C = cbase.size();
+    std::vector<uint64_t> gsize(NH, 0);
+    for (size_t j = 0; j < C; j++) {
+        const uint64_t cn = (j + 1 < C ? cbase[j + 1] : n) - cbase[j];
+        if (gst[j][0] != 0 || gst[j][NH] != cn) return fail(MPHX_EDEVICE, "chunk %zu: group starts inconsistent", j);
+        for (uint32_t h = 0; h < NH; h++) gsize[h] += gst[j][h + 1] - gst[j][h];
     }
-    if (worst != MPHX_OK)
-        return fail(worst == MPHX_ERANGE ? MPHX_ERANGE : MPHX_ECORE,
-                    "%u of %u buckets failed (two keys with one signature, or a 2-core on every try): "
-                    "build again with another seed", failed, B);
-    return MPHX_OK;
+
+    // 2. batches of consecutive groups: gather, partition into buckets, build
+    const uint64_t bound = hem_max_bucket(n, k);
+    uint64_t kbase = 0, cw = 0, rw = 0;
+    for (uint32_t g0 = 0; g0 < NH;) {
+        uint32_t g1 = g0 + 1;
+        uint64_t nb = gsize[g0];
+        if (nb > batch_keys)
+            return fail(MPHX_ENOMEM, "group %u holds %llu signatures, more than batch_keys", g0, (unsigned long long)nb);
+        while (g1 < NH && nb + gsize[g1] <= batch_keys) nb += gsize[g1++];
+        {
+            Timed tm(PH_BUILD, s);
+            uint64_t dst = 0;
+            runs.clear();
+            for (uint32_t h = g0; h < g1; h++)
+                for (size_t j = 0; j < C; j++) {
+                    const uint64_t src = cbase[j] + gst[j][h];
+                    for (uint64_t len = gst[j][h + 1] - gst[j][h], o = 0; o < len; o += kHemRunMax) {
+                        const uint32_t l = (uint32_t)std::min<uint64_t>(kHemRunMax, len - o);
+                        if (src + o + l > n || dst + l > nb) return fail(MPHX_EDEVICE, "gather run out of range");
+                        runs.push_back(HemRun{src + o, dst, l, 0});
+                        dst += l;
+                    }
+                }
+            if (dst != nb) return fail(MPHX_EDEVICE, "batch of groups [%u, %u) gathered %llu of %llu", g0, g1,
+                                       (unsigned long long)dst, (unsigned long long)nb);
+            for (size_t r0 = 0; r0 < runs.size(); r0 += kHemRunSlots) {
+                const uint32_t cnt = (uint32_t)std::min<size_t>(kHemRunSlots, runs.size() - r0);
+                HIP_TRY(hipMemcpyAsync(L.runs, runs.data() + r0, cnt * sizeof(HemRun), hipMemcpyHostToDevice, s));
+                HIP_TRY(launch_hem_gather(L.sig, L.runs, cnt, L.bsig, s));
+            }
+            HIP_TRY(launch_hem_partition(L.bsig, nb, k, L.btmp, L.lbo, L.baux, s));
+        }
+        HIP_TRY(hipMemcpyAsync(lbo.data(), L.lbo, (B + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const uint32_t b0 = g0 << 8, Bb = (g1 - g0) << 8;
+        if (lbo[b0] != 0 || lbo[b0 + Bb] != nb) return fail(MPHX_EDEVICE, "batch bucket offsets inconsistent");
+        uint64_t mb = 0;
+        rc = mphx_batch_layout(&lbo[b0], Bb, gnum, gden, co_l.data(), ro_l.data(), &ord[b0], &mb);
+        if (rc) return rc;
+        if (mb > bound)
+            return fail(MPHX_ENOMEM, "largest bucket %llu exceeds the workspace's bound %llu", (unsigned long long)mb,
+                        (unsigned long long)bound);
+        for (uint32_t j = 0; j <= Bb; j++) {
+            bo[b0 + j] = kbase + lbo[b0 + j];
+            co[b0 + j] = cw + co_l[j];
+            ro[b0 + j] = rw + ro_l[j];
+        }
+        HIP_TRY(hipMemcpyAsync(code_off + b0, &co[b0], (Bb + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(rank_off + b0, &ro[b0], (Bb + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(L.order, &ord[b0], Bb * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        {
+            Timed tm(PH_OTHER, s);
+            rc = batch_enqueue(reinterpret_cast<const uint64_t*>(L.bsig), L.lbo + b0, L.order, Bb, mb, seed, gnum,
+                               gden, max_tries, code_off + b0, rank_off + b0, codes, rank, L.results + b0, L.batch,
+                               L.batch_bytes, nullptr, s);
+            if (rc) return rc;
+        }
+        kbase += nb;
+        cw += co_l[Bb];
+        rw += ro_l[Bb];
+        g0 = g1;
+    }
+    HIP_TRY(hipMemcpyAsync(bucket_off, bo.data(), (B + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+    return hem_finish(B, L.results, seed, co[B], seeds, s, info);
 }
 
 int mphx_hem_build_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed, uint32_t gamma_num,
@@ -1356,6 +1558,41 @@ int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, u
 {
     return hem_build(MPHX_KEYS_STR, nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off,
                      code_off, rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
+}
+
+size_t mphx_hem_host_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den, int kind,
+                                     uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys)
+{
+    if (kind != MPHX_KEYS_U64 && kind != MPHX_KEYS_STR) return 0;
+    if (k < 9 || k > 18 || gamma_num == 0 || gamma_den == 0 || chunk_keys == 0 || chunk_keys >= 0x7FFFFFFFull ||
+        batch_keys == 0 || batch_keys >= 0x7FFFFFFFull || (kind == MPHX_KEYS_STR && chunk_bytes < 512))
+        return 0;
+    Carve c(nullptr);
+    HemHostLayout L;
+    layout_hem_host(c, kind, n, k, gamma_num, gamma_den, chunk_keys, chunk_bytes, batch_keys, L);
+    return c.off;
+}
+
+int mphx_hem_build_host_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed, uint32_t gamma_num,
+                            uint32_t gamma_den, uint32_t max_tries, uint64_t chunk_keys, uint64_t batch_keys,
+                            uint64_t* bucket_off, uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds,
+                            uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, void* stream,
+                            mphx_mphf_info* info)
+{
+    return hem_host_build(MPHX_KEYS_U64, keys, nullptr, nullptr, n, k, seed, gamma_num, gamma_den, max_tries,
+                          chunk_keys, 0, batch_keys, bucket_off, code_off, rank_off, seeds, codes, rank, ws, ws_bytes,
+                          (hipStream_t)stream, info);
+}
+
+int mphx_hem_build_host_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint32_t k, uint64_t seed,
+                            uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t chunk_keys,
+                            uint64_t chunk_bytes, uint64_t batch_keys, uint64_t* bucket_off, uint64_t* code_off,
+                            uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank, void* ws,
+                            size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    return hem_host_build(MPHX_KEYS_STR, nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries,
+                          chunk_keys, chunk_bytes, batch_keys, bucket_off, code_off, rank_off, seeds, codes, rank, ws,
+                          ws_bytes, (hipStream_t)stream, info);
 }
 
 int mphx_hem_lookup_u64(const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,

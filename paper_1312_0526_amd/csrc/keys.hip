@@ -523,6 +523,20 @@ hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_offs_rebase(uint64_t* __restrict__ offs, uint64_t count, uint64_t base)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        offs[i] -= base;
+}
+
+hipError_t launch_offs_rebase(uint64_t* offs, uint64_t count, uint64_t base, hipStream_t s)
+{
+    if (count == 0 || base == 0) return hipSuccess;
+    k_offs_rebase<<<grid_cap(count, 16384), 256, 0, s>>>(offs, count, base);
+    return hipGetLastError();
+}
+
 hipError_t launch_hem_lookup_u64(const HemTables& t, uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out,
                                  hipStream_t s)
 {

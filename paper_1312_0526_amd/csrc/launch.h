@@ -194,4 +194,16 @@ hipError_t launch_lookup_str_words(const uint64_t* codes, const uint64_t* rank, 
                                    hipStream_t s);
 hipError_t launch_bijection(const uint64_t* vals, uint64_t n, uint32_t* bitmap, Ctrl* ctrl, hipStream_t s);
 
+// Out-of-core HEM: a chunk's signature records grouped by their top k - 8 bits into out (aux:
+// hem_aux_bytes(cn, k)), its NH + 1 group starts copied to host memory; runs of records
+// gathered into a batch buffer; string offsets shifted down by base.
+struct HemRun {
+    uint64_t src, dst;
+    uint32_t len, pad;
+};
+hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, uint2* out, void* aux,
+                                  uint32_t* host_gstart, hipStream_t s);
+hipError_t launch_hem_gather(const uint2* src, const HemRun* runs, uint32_t nruns, uint2* dst, hipStream_t s);
+hipError_t launch_offs_rebase(uint64_t* offs, uint64_t count, uint64_t base, hipStream_t s);
+
 }  // namespace mphx

@@ -746,6 +746,51 @@ hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, 
         s);
 }
 
+// Out-of-core HEM, first level: one chunk's signature records grouped by their top k - 8 bits
+// (the partition's first pass alone) into out; the chunk's NH + 1 group starts are copied to
+// host_gstart (pageable or pinned host memory, valid once the stream has reached the copy).
+hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, uint2* out, void* aux,
+                                  uint32_t* host_gstart, hipStream_t s)
+{
+    if (k < 9 || k > 18 || cn == 0) return hipErrorInvalidValue;
+    const uint32_t NH = 1u << (k - 8), gsh = 40 - k;
+    const uint64_t nt1 = tiles_of(cn);
+    if (nt1 > 0x7FFFFFFFull || cn >= 0xFFFFFFFFull) return hipErrorInvalidValue;
+    const AuxLayout L = aux_layout((uint64_t)NH * nt1, cn, NH);
+    uint8_t* base = reinterpret_cast<uint8_t*>(aux);
+    uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
+    uint32_t* ginfo = reinterpret_cast<uint32_t*>(base + L.ginfo);
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{csig}, cn, gsh, NH, nt1, hist1);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    err = launch_scan_u32(hist1, (uint64_t)NH * nt1, hist1, base + L.scan, L.scan_bytes, s);
+    if (err != hipSuccess) return err;
+    k_part_scatter1<Records><<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{csig}, cn, gsh, NH, nt1, hist1, out);
+    k_part_groups<<<1, kPtBlock, 0, s>>>(hist1, NH, nt1, cn, ginfo);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return hipMemcpyAsync(host_gstart, ginfo, (NH + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+}
+
+// Out-of-core HEM, second level: runs of grouped signatures copied into one batch buffer, one
+// workgroup per run (runs are at most 2^16 records; the host checks every run against both
+// buffers before the launch).
+__global__ __launch_bounds__(256) void k_hem_gather(const uint2* __restrict__ src, const HemRun* __restrict__ runs,
+                                                    uint2* __restrict__ dst)
+{
+    const HemRun r = runs[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < r.len; i += 256)
+        dst[r.dst + i] = src[r.src + i];
+}
+
+hipError_t launch_hem_gather(const uint2* src, const HemRun* runs, uint32_t nruns, uint2* dst, hipStream_t s)
+{
+    if (nruns == 0) return hipSuccess;
+    if (nruns > 0x7FFFFFFFu) return hipErrorInvalidValue;
+    k_hem_gather<<<nruns, 256, 0, s>>>(src, runs, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_update_apply(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s)
 {
     if (count == 0) return hipSuccess;

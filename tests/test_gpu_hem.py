@@ -91,3 +91,70 @@ def test_hem_two_key_buckets_never_build(mx, o):
         mx.hem_build(keys=dev(keys), k=k, seed=seed)
     assert e.value.status == mx.ECORE
     assert e.value.info["n_core"] >= int((sizes == 2).sum())
+
+
+# ---- keys in host memory, streamed in chunks (key sets beyond device memory) ----------------
+def _same_tables(a, b):
+    for key in ("bucket_off", "code_off", "rank_off", "seeds", "codes", "rank"):
+        assert np.array_equal(host(a[key]), host(b[key])), key
+
+
+def _host_u64(keys, pinned=False):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(keys).view(np.int64))
+    return t.pin_memory() if pinned else t
+
+
+@pytest.mark.parametrize("n,k,seed,chunk,batch,pinned", [
+    (300_000, 12, 1, 40_000, 60_000, False),      # 8 chunks, 5 batches of 3-4 groups
+    (1_000_000, 10, 3, 1 << 20, 1 << 20, True),   # one chunk, one batch, pinned
+    (200_000, 9, 0, 65_537, 150_000, False),      # ragged chunks, one group per batch
+    (120_000, 12, 2, 7_777, 10_000, True),        # 16 chunks, one group per batch
+])
+def test_hem_host_u64_matches_oracle_and_device_build(mx, o, n, k, seed, chunk, batch, pinned):
+    keys = workloads.u64_keys(n, gen_seed=100 + k)
+    got = mx.hem_build_host(keys=_host_u64(keys, pinned), k=k, seed=seed, chunk_keys=chunk, batch_keys=batch)
+    rc, ref = o.hem_build(o.hem_signatures_u64(keys, seed), k, seed=seed)
+    assert rc == 0
+    _assert_same(got, ref)
+    _same_tables(got, mx.hem_build(keys=dev(keys), k=k, seed=seed))
+    f = mx.hem_lookup(got, keys=dev(keys))
+    assert np.array_equal(host(f), o.hem_lookup(ref, o.hem_signatures_u64(keys, seed)))
+
+
+def test_hem_host_str_matches_oracle(mx, o):
+    import torch
+
+    data, offs = workloads.str_keys(100_000, gen_seed=31)
+    got = mx.hem_build_host(data=torch.from_numpy(data), offs=torch.from_numpy(offs.view(np.int64)), k=11, seed=6,
+                            chunk_keys=20_000, chunk_bytes=1 << 19, batch_keys=30_000)
+    sigs = o.hem_signatures_str(data, offs, 6)
+    rc, ref = o.hem_build(sigs, 11, seed=6)
+    assert rc == 0
+    _assert_same(got, ref)
+    f = mx.hem_lookup(got, data=dev(data), offs=dev(offs))
+    assert np.array_equal(host(f), o.hem_lookup(ref, sigs))
+
+
+def test_hem_host_empty_and_errors(mx):
+    import torch
+
+    empty = mx.hem_build_host(keys=torch.empty(0, dtype=torch.int64), k=9, chunk_keys=1000, batch_keys=1000)
+    _same_tables(empty, mx.hem_build(keys=torch.empty(0, dtype=torch.int64, device="cuda"), k=9))
+    keys = _host_u64(workloads.u64_keys(50_000))
+    with pytest.raises(mx.MphxError) as e:  # groups of about 25,000 keys
+        mx.hem_build_host(keys=keys, k=9, chunk_keys=10_000, batch_keys=20_000)
+    assert e.value.status == mx.ENOMEM
+    # a key longer than a chunk's bytes
+    lens = np.array([10, 600, 10], dtype=np.int64)
+    offs = np.zeros(4, dtype=np.int64)
+    offs[1:] = np.cumsum(lens)
+    data = torch.from_numpy(np.arange(offs[-1], dtype=np.int64).astype(np.uint8))
+    with pytest.raises(mx.MphxError) as e:
+        mx.hem_build_host(data=data, offs=torch.from_numpy(offs), k=9, chunk_keys=10, chunk_bytes=512, batch_keys=100)
+    assert e.value.status == mx.EINVAL
+    with pytest.raises(ValueError):
+        mx.hem_build_host(keys=keys, k=9, chunk_keys=0, batch_keys=100)
+    with pytest.raises(TypeError):
+        mx.hem_build_host(keys=keys.cuda(), k=9)
