@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <atomic>
 #include <memory>
+#include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -1395,6 +1397,97 @@ static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t
     L.batch = c.take<uint8_t>(L.batch_bytes);
 }
 
+// Host-to-device copies for the streamed build.  Pinned sources are copied directly; pageable
+// ones pass through two pinned staging buffers owned by the library: host threads fill one
+// buffer while the DMA engine drains the other (an event per buffer says when it is free).
+// The buffers live until the process ends; one streamed build uses them at a time.
+class HostStager {
+  public:
+    static constexpr size_t kPiece = size_t(1) << 27;  // bytes per staged copy
+
+    explicit HostStager(hipStream_t s) : s_(s), lock_(pool().mu) {}
+    ~HostStager()
+    {
+        for (hipEvent_t& e : ev_)
+            if (e) {
+                (void)hipEventSynchronize(e);
+                (void)hipEventDestroy(e);
+            }
+    }
+
+    hipError_t copy(void* dst, const void* src, size_t bytes)
+    {
+        if (bytes == 0) return hipSuccess;
+        if (is_pinned(src)) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s_);
+        Pool& p = pool();
+        if (!p.buf[0]) {
+            for (void*& b : p.buf) {
+                hipError_t e = hipHostMalloc(&b, kPiece, hipHostMallocDefault);
+                if (e != hipSuccess) return e;
+            }
+        }
+        for (hipEvent_t& e : ev_)
+            if (!e) {
+                hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+                if (err != hipSuccess) return err;
+            }
+        for (size_t o = 0; o < bytes; o += kPiece) {
+            const size_t len = std::min(kPiece, bytes - o);
+            const int i = next_;
+            next_ ^= 1;
+            hipError_t err = hipEventSynchronize(ev_[i]);  // the buffer's previous copy has drained
+            if (err != hipSuccess) return err;
+            parallel_copy(p.buf[i], static_cast<const uint8_t*>(src) + o, len);
+            err = hipMemcpyAsync(static_cast<uint8_t*>(dst) + o, p.buf[i], len, hipMemcpyHostToDevice, s_);
+            if (err != hipSuccess) return err;
+            err = hipEventRecord(ev_[i], s_);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+
+  private:
+    struct Pool {
+        std::mutex mu;
+        void* buf[2] = {nullptr, nullptr};
+    };
+    static Pool& pool()
+    {
+        static Pool p;
+        return p;
+    }
+    static bool is_pinned(const void* p)
+    {
+        hipPointerAttribute_t a;
+        if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+            (void)hipGetLastError();  // pageable memory may be reported as an error: clear it
+            return false;
+        }
+        return a.type == hipMemoryTypeHost;
+    }
+    static void parallel_copy(void* dst, const uint8_t* src, size_t len)
+    {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const size_t T = std::min<size_t>(std::min(8u, hw), std::max<size_t>(1, len >> 22));
+        if (T <= 1) {
+            memcpy(dst, src, len);
+            return;
+        }
+        std::vector<std::thread> th;
+        const size_t per = (len + T - 1) / T;
+        for (size_t t = 0; t < T; t++) {
+            const size_t a = t * per, b = std::min(len, a + per);
+            if (a < b) th.emplace_back([=] { memcpy(static_cast<uint8_t*>(dst) + a, src + a, b - a); });
+        }
+        for (std::thread& x : th) x.join();
+    }
+
+    hipStream_t s_;
+    std::lock_guard<std::mutex> lock_;
+    hipEvent_t ev_[2] = {nullptr, nullptr};
+    int next_ = 0;
+};
+
 static int hem_host_args(int kind, uint32_t k, uint32_t gnum, uint32_t gden, uint64_t chunk_keys,
                          uint64_t chunk_bytes, uint64_t batch_keys)
 {
@@ -1441,6 +1534,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
         hipStream_t s;
         ~DrainOnExit() { (void)hipStreamSynchronize(s); }
     } drain{s};
+    HostStager stager(s);  // destroyed before the drain: its events are waited for first
 
     // 1. stream the chunks: signatures, grouped into the resident array at the chunk's place
     {
@@ -1448,7 +1542,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
         for (uint64_t c0 = 0; c0 < n;) {
             uint64_t c1 = std::min(n, c0 + chunk_keys);
             if (kind == MPHX_KEYS_U64) {
-                HIP_TRY(hipMemcpyAsync(L.stage, hkeys + c0, (c1 - c0) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+                HIP_TRY(stager.copy(L.stage, hkeys + c0, (c1 - c0) * sizeof(uint64_t)));
                 HIP_TRY(launch_hem_sig_u64(reinterpret_cast<const uint64_t*>(L.stage), c1 - c0, seed, L.csig, s));
             } else {
                 // the chunk's bytes from a 256-byte boundary, so every key keeps its alignment phase
@@ -1456,8 +1550,8 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
                 c1 = (uint64_t)(std::upper_bound(hoffs + c0 + 1, hoffs + c1 + 1, limit) - hoffs) - 1;
                 if (c1 == c0)
                     return fail(MPHX_EINVAL, "key %llu does not fit in chunk_bytes - 255 bytes", (unsigned long long)c0);
-                HIP_TRY(hipMemcpyAsync(L.stage, hbytes + bbase, hoffs[c1] - bbase, hipMemcpyHostToDevice, s));
-                HIP_TRY(hipMemcpyAsync(L.soffs, hoffs + c0, (c1 - c0 + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+                HIP_TRY(stager.copy(L.stage, hbytes + bbase, hoffs[c1] - bbase));
+                HIP_TRY(stager.copy(L.soffs, hoffs + c0, (c1 - c0 + 1) * sizeof(uint64_t)));
                 HIP_TRY(launch_offs_rebase(L.soffs, c1 - c0 + 1, bbase, s));
                 HIP_TRY(launch_hem_sig_str(L.stage, L.soffs, c1 - c0, seed, L.csig, s));
             }
