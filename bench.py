@@ -483,7 +483,14 @@ def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None)
     ws = torch.empty(max(mx.hem_workspace_bytes(n, k, gamma) for k in args.hem_k), dtype=torch.uint8, device=dev)
     out = torch.empty(n, dtype=torch.int64, device=dev)
     rows = {}
-    for k in args.hem_k:
+    for k, tune in [(k, t) for k in args.hem_k for t in args.hem_tune]:
+        block, grid = (int(x) for x in tune.split("x"))
+        mx.set_option("hem_block", block)
+        mx.set_option("hem_grid", grid)
+        if ws.numel() < mx.hem_workspace_bytes(n, k, gamma):
+            del ws
+            ws = torch.empty(mx.hem_workspace_bytes(n, k, gamma), dtype=torch.uint8, device=dev)
+
         def step():
             if kind == mx.KEYS_U64:
                 return mx.hem_build(keys=keys, k=k, seed=0, gamma=gamma, ws=ws)
@@ -529,15 +536,17 @@ def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None)
 
         t2 = table2_lookups(torch, n, nk, run, out[:nk])
         sizes = (h["bucket_off"][1:] - h["bucket_off"][:-1])
-        rows[f"k{k}"] = dict(buckets=B, ms_per_build=round(sec * 1e3, 3), keys_per_s=round(n / sec, 1),
+        rows[f"k{k}" + ("" if tune == "1024x0" else f"_{tune}")] = dict(buckets=B, block=block, grid=grid, ms_per_build=round(sec * 1e3, 3), keys_per_s=round(n / sec, 1),
                              bits_per_key=round(bits / n, 4), max_bucket=int(sizes.max().item()),
                              max_tries=h["tries"], max_rounds=h["n_rounds"], phases_ms=phases,
                              lookup_all_ms=round(lk_ms, 3), lookup_ns_per_key=round(lk_ms * 1e6 / n, 4),
                              bijection=ok, table2_lookup=t2)
-        log(f"[hem] k={k}: {sec * 1e3:.1f} ms/build, {n / sec / 1e9:.3f} G keys/s, {bits / n:.3f} bits/key, "
+        log(f"[hem] k={k} block x grid {tune}: {sec * 1e3:.1f} ms/build, {n / sec / 1e9:.3f} G keys/s, {bits / n:.3f} bits/key, "
             f"lookup {lk_ms * 1e6 / n:.3f} ns/key, bijection ok={ok}; Table 2 shape {t2['ns_per_key']:.3f} ns/key "
             f"per batch, ok={t2['values_distinct_and_in_range']}")
         del h, sizes
+    mx.set_option("hem_block", 1024)
+    mx.set_option("hem_grid", 0)
     del ws, out
     torch.cuda.empty_cache()
     return dict(workload="hem_split_same_keys", rows=rows)
@@ -730,6 +739,8 @@ def main() -> int:
                     help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host")
     ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
                     help="bucket-count exponents of the hem leg")
+    ap.add_argument("--hem-tune", type=lambda s: s.split(","), default=["1024x0"],
+                    help="batched-kernel block x grid shapes of the hem leg (grid 0 = one per compute unit)")
     ap.add_argument("--hem-host-n", type=int, default=1 << 34, help="keys of the hem_host leg (host memory)")
     ap.add_argument("--hem-host-k", type=int, default=18)
     ap.add_argument("--hem-host-chunk", type=int, default=1 << 27, help="keys per host-to-device chunk")

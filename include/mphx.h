@@ -457,6 +457,11 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 sort-based round update of Section 4.2 -- instead of device atomics; the
  *                 claims of the next round then come from the updated records.  0 = never.
  *                 The same codes either way.
+ *   "hem_block"   256, 512 or 1024 (default 1024): workgroup size of the batched kernel that
+ *                 builds the HEM split's buckets (mphx_hem_build_*, mphx_hem_build_host_*).
+ *   "hem_grid"    0..65536 (default 0 = one workgroup per compute unit): its persistent grid.
+ *                 Both shape the work only, never the result; the HEM workspaces depend on the
+ *                 grid, so query them after setting it.
  * Returns MPHX_EINVAL for an unknown key or value.
  *
  * mphx_phase_times copies the accumulated per-phase kernel time (ms) and launch counts of

@@ -27,6 +27,8 @@ struct Options {
     std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
     std::atomic<int> claim_lists{28};  // claim lists from n >= 2^claim_lists keys on (0 = never)
     std::atomic<int> update_lists{16}; // claim-list rounds with 2 * layer >= m * update_lists / 100
+    std::atomic<int> hem_block{1024};  // batched-kernel workgroup size for the HEM split's buckets
+    std::atomic<int> hem_grid{0};      // its persistent grid (0 = one workgroup per compute unit)
                                        // delete through a sorted update list (0 = never)
 };
 
@@ -391,6 +393,12 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "update_lists")) {
         if (value < 0 || value > 100) return fail(MPHX_EINVAL, "update_lists must be in 0..100");
         g_opt.update_lists = (int)value;
+    } else if (!strcmp(key, "hem_block")) {
+        if (value != 256 && value != 512 && value != 1024) return fail(MPHX_EINVAL, "hem_block must be 256, 512 or 1024");
+        g_opt.hem_block = (int)value;
+    } else if (!strcmp(key, "hem_grid")) {
+        if (value < 0 || value > (1 << 16)) return fail(MPHX_EINVAL, "hem_grid must be in 0..65536");
+        g_opt.hem_grid = (int)value;
     } else {
         return fail(MPHX_EINVAL, "unknown option '%s'", key);
     }
@@ -406,6 +414,8 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "part_build")) return g_opt.part_build;
     if (!strcmp(key, "claim_lists")) return g_opt.claim_lists;
     if (!strcmp(key, "update_lists")) return g_opt.update_lists;
+    if (!strcmp(key, "hem_block")) return g_opt.hem_block;
+    if (!strcmp(key, "hem_grid")) return g_opt.hem_grid;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
@@ -1117,6 +1127,16 @@ static uint64_t hem_max_bucket(uint64_t n, uint32_t k)
     return mean + 8 * r + 64;
 }
 
+// The batched kernel's shape for the HEM split's many equal buckets (library options).
+static mphx_batch_tuning hem_tuning()
+{
+    mphx_batch_tuning t{};
+    t.block = (uint32_t)g_opt.hem_block.load();
+    t.grid = (uint32_t)g_opt.hem_grid.load();
+    t.scope = 0;
+    return t;
+}
+
 struct HemLayout {
     uint2 *rec, *tmp;
     void* aux;
@@ -1134,7 +1154,8 @@ static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t
     L.aux = c.take<uint8_t>(hem_aux_bytes(n, k));
     L.order = c.take<uint32_t>(B);
     L.results = c.take<mphx_bucket_result>(B);
-    L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, nullptr);
+    const mphx_batch_tuning t = hem_tuning();
+    L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, &t);
     L.batch = c.take<uint8_t>(L.batch_bytes);
 }
 
@@ -1312,6 +1333,7 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
     const size_t need = mphx_hem_workspace_bytes(n, k, gnum, gden);
     if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
     const uint32_t B = 1u << k;
+    const mphx_batch_tuning tune = hem_tuning();
     Carve c(ws);
     HemLayout L;
     layout_hem(c, n, k, gnum, gden, L);
@@ -1344,7 +1366,7 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
         // the partitioned records read as u64 are the bucket keys
         rc = batch_enqueue(reinterpret_cast<const uint64_t*>(L.rec), bucket_off, L.order, B, max_bucket, seed, gnum,
                            gden, max_tries, code_off, rank_off, codes, rank, L.results, L.batch, L.batch_bytes,
-                           nullptr, s);
+                           &tune, s);
         if (rc) return rc;
     }
     return hem_finish(B, L.results, seed, co[B], seeds, s, info);
@@ -1393,7 +1415,8 @@ static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t
     L.order = c.take<uint32_t>(B);
     L.runs = c.take<HemRun>(kHemRunSlots);
     L.results = c.take<mphx_bucket_result>(B);
-    L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, nullptr);
+    const mphx_batch_tuning t = hem_tuning();
+    L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, &t);
     L.batch = c.take<uint8_t>(L.batch_bytes);
 }
 
@@ -1518,6 +1541,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
         for (uint64_t i = 0; i < n; i++)
             if (hoffs[i + 1] < hoffs[i]) return fail(MPHX_EINVAL, "offsets decrease at key %llu", (unsigned long long)i);
     const uint32_t NH = 1u << (k - 8), B = 1u << k;
+    const mphx_batch_tuning tune = hem_tuning();
     Carve c(ws);
     HemHostLayout L;
     layout_hem_host(c, kind, n, k, gnum, gden, chunk_keys, chunk_bytes, batch_keys, L);
@@ -1624,7 +1648,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
             Timed tm(PH_OTHER, s);
             rc = batch_enqueue(reinterpret_cast<const uint64_t*>(L.bsig), L.lbo + b0, L.order, Bb, mb, seed, gnum,
                                gden, max_tries, code_off + b0, rank_off + b0, codes, rank, L.results + b0, L.batch,
-                               L.batch_bytes, nullptr, s);
+                               L.batch_bytes, &tune, s);
             if (rc) return rc;
         }
         kbase += nb;

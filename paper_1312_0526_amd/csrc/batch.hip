@@ -180,9 +180,12 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t count, uint32_t* wt
     return total;
 }
 
-// The partitioned record build works on tiles of kBatchTile vertices (64 KiB of records in
-// LDS) and parts of at most kBatchMaxBuckets tiles; larger parts fall back to atomics.
-constexpr uint32_t kBatchTile = 8192;
+// The partitioned record build works on LDS tiles of records and parts of at most
+// kBatchMaxBuckets tiles; larger parts fall back to atomics.  Vertices per tile: 8192 (64 KB
+// of records) for 1024-thread workgroups; 4096 for smaller ones, whose ~48 KB of LDS lets
+// three share a compute unit.
+template <int kBlock>
+constexpr uint32_t batch_tile() { return kBlock >= 1024 ? 8192u : 4096u; }
 constexpr uint32_t kBatchMaxBuckets = 2048;
 
 // Part-k local vertex of key i: recomputed from a u64 key, read from the stored edge else.
@@ -223,6 +226,7 @@ template <int kBlock, int kScope>
 __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* slot)
 {
     using S = Sc<kScope>;
+    constexpr uint32_t kBatchTile = batch_tile<kBlock>();
     __shared__ uint32_t s_ltail, s_err, s_degsum;
     __shared__ uint32_t s_cnt[kBatchMaxBuckets], s_bnd[kBatchMaxBuckets + 1], s_wtot[kBlock / kWave];
     __shared__ unsigned long long s_tab[kBatchTile];
@@ -276,32 +280,40 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             uint2* pairs = reinterpret_cast<uint2*>(L.slots);
             uint32_t* stage = reinterpret_cast<uint32_t*>(pairs + n);
             for (uint32_t k = 0; k < 3; k++) {
-                for (uint32_t b = tid; b < nbk; b += kBlock)
-                    s_cnt[b] = 0;
-                __syncthreads();
-                for (uint32_t i = tid; i < n; i += kBlock)
-                    atomicAdd(&s_cnt[bucket_local(d, L, i, sd, P, k) / kBatchTile], 1u);
-                __syncthreads();
-                lds_exclusive_scan<kBlock>(s_cnt, nbk, s_wtot);
-                for (uint32_t b = tid; b < nbk; b += kBlock)
-                    s_bnd[b] = s_cnt[b];
-                if (tid == 0)
-                    s_bnd[nbk] = n;
-                __syncthreads();
-                for (uint32_t i = tid; i < n; i += kBlock) {
-                    const uint32_t u = bucket_local(d, L, i, sd, P, k);
-                    const uint32_t pos = atomicAdd(&s_cnt[u / kBatchTile], 1u);
-                    pairs[pos] = make_uint2(u % kBatchTile, i);
+                if (nbk > 1) {  // one tile: the keys go straight into it below
+                    for (uint32_t b = tid; b < nbk; b += kBlock)
+                        s_cnt[b] = 0;
+                    __syncthreads();
+                    for (uint32_t i = tid; i < n; i += kBlock)
+                        atomicAdd(&s_cnt[bucket_local(d, L, i, sd, P, k) / kBatchTile], 1u);
+                    __syncthreads();
+                    lds_exclusive_scan<kBlock>(s_cnt, nbk, s_wtot);
+                    for (uint32_t b = tid; b < nbk; b += kBlock)
+                        s_bnd[b] = s_cnt[b];
+                    if (tid == 0)
+                        s_bnd[nbk] = n;
+                    __syncthreads();
+                    for (uint32_t i = tid; i < n; i += kBlock) {
+                        const uint32_t u = bucket_local(d, L, i, sd, P, k);
+                        const uint32_t pos = atomicAdd(&s_cnt[u / kBatchTile], 1u);
+                        pairs[pos] = make_uint2(u % kBatchTile, i);
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
                 uint32_t degsum = 0;
                 for (uint32_t b = 0; b < nbk; b++) {
                     for (uint32_t v = tid; v < kBatchTile; v += kBlock)
                         s_tab[v] = 0;
                     __syncthreads();
-                    for (uint32_t j = s_bnd[b] + tid; j < s_bnd[b + 1]; j += kBlock) {
-                        const uint2 pr = pairs[j];
-                        atomicAdd(&s_tab[pr.x], (unsigned long long)(Rec::kOne + pr.y));
+                    if (nbk == 1) {
+                        for (uint32_t i = tid; i < n; i += kBlock)
+                            atomicAdd(&s_tab[bucket_local(d, L, i, sd, P, k)],
+                                      (unsigned long long)(Rec::kOne + i));
+                    } else {
+                        for (uint32_t j = s_bnd[b] + tid; j < s_bnd[b + 1]; j += kBlock) {
+                            const uint2 pr = pairs[j];
+                            atomicAdd(&s_tab[pr.x], (unsigned long long)(Rec::kOne + pr.y));
+                        }
                     }
                     __syncthreads();
                     const uint64_t v0 = (uint64_t)b * kBatchTile;

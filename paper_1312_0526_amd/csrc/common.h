@@ -102,7 +102,8 @@ __device__ __forceinline__ uint64_t wave_append(unsigned long long* tail, bool w
 // value v at global position i.
 template <typename T, int kBlock, int kCap>
 struct BlockAppender {
-    static_assert(kCap >= 4 * kBlock, "buffer must hold several calls");
+    // a push adds at most 2 * kBlock entries and flushes beyond kCap - 2 * kBlock
+    static_assert(kCap >= 3 * kBlock, "buffer must hold several calls");
     T buf[kCap];
     uint32_t wtot[kBlock / kWave];
     uint32_t count;

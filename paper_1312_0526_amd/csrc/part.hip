@@ -460,8 +460,10 @@ __global__ __launch_bounds__(kAccBlock) void k_update_accum(const uint2* __restr
 // lowest position claimed and not cancelled is the hinge, and that claim is the winner and
 // appends (c, hinge | live positions << 8) to the layer.  The grid is persistent: a block walks buckets b,
 // b + grid, ... so sparse rounds cost few launches.
-using ClaimAppender = BlockAppender<uint2, kResBlock, 4 * kResBlock>;
-constexpr uint32_t kResGridPerCU = 2;  // 64 KiB table + 16 KiB appender per block
+// 64 KiB table, 15 KiB appender and the bounds of kResWin buckets: two blocks per compute unit
+using ClaimAppender = BlockAppender<uint2, kResBlock, 3 * kResBlock + kResBlock / 4 * 3>;
+constexpr uint32_t kResGridPerCU = 2;
+constexpr uint32_t kResWin = 128;
 
 __global__ __launch_bounds__(kResBlock) void k_claims_resolve(const uint2* __restrict__ in,
                                                               const uint32_t* __restrict__ ginfo, uint32_t NH,
@@ -474,6 +476,7 @@ __global__ __launch_bounds__(kResBlock) void k_claims_resolve(const uint2* __res
     __shared__ uint32_t tab[(1u << kClShift) / 4];
     __shared__ ClaimAppender app;
     __shared__ unsigned long long s_fresh;
+    __shared__ uint32_t s_lo[kResWin + 1];  // bucket starts of the current window (count < 2^32)
     constexpr uint32_t kMask = (1u << kClShift) - 1;
     const GroupInfo g(ginfo);
     const uint64_t base = lstart[r];
@@ -482,34 +485,46 @@ __global__ __launch_bounds__(kResBlock) void k_claims_resolve(const uint2* __res
         s_fresh = 0;
     app.init();
     unsigned long long fresh = 0;
-    for (uint32_t b = blockIdx.x; b < nbuckets; b += gridDim.x) {
-        const uint64_t lo = bucket_start(g, off2, NH, count, b);
-        const uint64_t hi = bucket_start(g, off2, NH, count, b + 1);
-        if (lo == hi)
-            continue;  // uniform per block
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += kResBlock)
-            tab[(in[i].x & kMask) >> 2] = 0u;
+    // a contiguous range of buckets per block; each window's bounds are read in parallel, so an
+    // empty bucket costs no dependent global loads
+    const uint32_t per = (nbuckets + gridDim.x - 1) / gridDim.x;
+    const uint32_t b0 = (uint32_t)min<uint64_t>(nbuckets, (uint64_t)blockIdx.x * per);
+    const uint32_t b1 = (uint32_t)min<uint64_t>(nbuckets, (uint64_t)b0 + per);
+    for (uint32_t w0 = b0; w0 < b1; w0 += kResWin) {
+        const uint32_t w1 = min(b1, w0 + kResWin);
+        for (uint32_t j = threadIdx.x; j <= w1 - w0; j += kResBlock)
+            s_lo[j] = (uint32_t)bucket_start(g, off2, NH, count, w0 + j);
         __syncthreads();
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += kResBlock) {
-            const uint2 c = in[i];
-            atomicOr(&tab[(c.x & kMask) >> 2], 1u << (8 * (c.x & 3) + c.y));
-        }
-        __syncthreads();
-        for (uint64_t i0 = lo; i0 < hi; i0 += kResBlock) {
-            const uint64_t i = i0 + threadIdx.x;
-            bool win = false;
-            uint2 c = make_uint2(0u, 0u);
-            if (i < hi) {
-                c = in[i];
-                const uint32_t t = tab[(c.x & kMask) >> 2] >> (8 * (c.x & 3));
-                const uint32_t live = t & ~(t >> 4) & 7u;
-                win = c.y < 4 && live != 0 && (uint32_t)__builtin_ctz(live) == c.y;
-                fresh += (c.y < 4 && ((live >> c.y) & 1u)) ? 1u : 0u;
-                c.y |= live << 8;  // the layer entry also names every position at degree 1
+        for (uint32_t b = w0; b < w1; b++) {
+            const uint64_t lo = s_lo[b - w0];
+            const uint64_t hi = s_lo[b - w0 + 1];
+            if (lo == hi)
+                continue;  // uniform per block
+            for (uint64_t i = lo + threadIdx.x; i < hi; i += kResBlock)
+                tab[(in[i].x & kMask) >> 2] = 0u;
+            __syncthreads();
+            for (uint64_t i = lo + threadIdx.x; i < hi; i += kResBlock) {
+                const uint2 c = in[i];
+                atomicOr(&tab[(c.x & kMask) >> 2], 1u << (8 * (c.x & 3) + c.y));
             }
-            app.push(win, c, false, c, &lcount[r], out);
+            __syncthreads();
+            for (uint64_t i0 = lo; i0 < hi; i0 += kResBlock) {
+                const uint64_t i = i0 + threadIdx.x;
+                bool win = false;
+                uint2 c = make_uint2(0u, 0u);
+                if (i < hi) {
+                    c = in[i];
+                    const uint32_t t = tab[(c.x & kMask) >> 2] >> (8 * (c.x & 3));
+                    const uint32_t live = t & ~(t >> 4) & 7u;
+                    win = c.y < 4 && live != 0 && (uint32_t)__builtin_ctz(live) == c.y;
+                    fresh += (c.y < 4 && ((live >> c.y) & 1u)) ? 1u : 0u;
+                    c.y |= live << 8;  // the layer entry also names every position at degree 1
+                }
+                app.push(win, c, false, c, &lcount[r], out);
+            }
+            __syncthreads();  // the table is reused by the next bucket
         }
-        __syncthreads();  // the table is reused by the next bucket
+        __syncthreads();  // the window's bounds are reused by the next window
     }
     app.flush(&lcount[r], out);
     if (fresh)
