@@ -457,6 +457,11 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 sort-based round update of Section 4.2 -- instead of device atomics; the
  *                 claims of the next round then come from the updated records.  0 = never.
  *                 The same codes either way.
+ *   "batch_lds"   1 (default) = in the batched kernel (mphx_build_batch*, the server's
+ *                 batching lane, the HEM split) with 1024-thread workgroups, a bucket whose
+ *                 4-byte records and edge states fit in 158 KB of LDS (about 18,000 keys) is
+ *                 built and peeled entirely in LDS; 0 = every bucket through device memory.
+ *                 The same codes either way.
  *   "hem_block"   256, 512 or 1024 (default 1024): workgroup size of the batched kernel that
  *                 builds the HEM split's buckets (mphx_hem_build_*, mphx_hem_build_host_*).
  *   "hem_grid"    0..65536 (default 0 = one workgroup per compute unit): its persistent grid.

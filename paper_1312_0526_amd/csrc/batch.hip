@@ -187,6 +187,18 @@ __device__ uint32_t lds_exclusive_scan(uint32_t* a, uint32_t count, uint32_t* wt
 template <int kBlock>
 constexpr uint32_t batch_tile() { return kBlock >= 1024 ? 8192u : 4096u; }
 constexpr uint32_t kBatchMaxBuckets = 2048;
+// LDS shared by the two bucket builds: the partitioned record build's tile, counts and bounds,
+// or (1024-thread workgroups) a whole bucket's 4-byte records and edge states.
+template <int kBlock>
+constexpr uint32_t batch_part_bytes() { return batch_tile<kBlock>() * 8 + (2 * kBatchMaxBuckets + 1) * 4; }
+template <int kBlock>
+constexpr uint32_t batch_lds_bytes() { return kBlock >= 1024 ? 158u * 1024 : batch_part_bytes<kBlock>(); }
+// A bucket whose records (m words) and states (n words) fit runs entirely in LDS.
+template <int kBlock>
+__device__ __forceinline__ bool bucket_fits_lds(uint64_t n, uint64_t m)
+{
+    return kBlock >= 1024 && ((m + 3) & ~3ull) + n <= batch_lds_bytes<kBlock>() / 4;
+}
 
 // Part-k local vertex of key i: recomputed from a u64 key, read from the stored edge else.
 __device__ __forceinline__ uint32_t bucket_local(const BucketDesc& d, const SlotLayout& L, uint32_t i, uint64_t sd,
@@ -222,14 +234,54 @@ __device__ __forceinline__ void write_result(BucketResult* r, uint64_t seed_used
     r->n_rounds = rounds;
 }
 
+// Codes (one byte per vertex, code8 in device memory or LDS) packed 2 bits per vertex into
+// d.codes, counted per 512 vertices and scanned into the rank samples d.rank.
+template <int kBlock>
+__device__ void pack_codes(const uint8_t* code8, uint32_t m, const BucketDesc& d, const SlotLayout& L)
+{
+    const uint32_t tid = threadIdx.x;
+    const uint32_t nwords = (m + 31) / 32, nblocks = (m + 511) / 512;
+    for (uint32_t base = 0; base < nwords; base += kBlock) {
+        uint32_t w = base + tid;
+        uint64_t x = 0;
+        if (w < nwords) {
+            if (32 * w + 32 <= m) {
+                const uint4* p = reinterpret_cast<const uint4*>(code8 + 32 * w);
+                uint4 q0 = p[0], q1 = p[1];
+                uint32_t dw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+                for (int q = 0; q < 8; q++)
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        x |= (uint64_t)((dw[q] >> (8 * u)) & 3u) << (2 * (4 * q + u));
+            } else {
+                for (uint32_t q = 0; 32 * w + q < m; q++)
+                    x |= (uint64_t)(code8[32 * w + q] & 3u) << (2 * q);
+            }
+            d.codes[w] = x;
+        }
+        uint32_t c = nz_pairs(x);
+        c += __shfl_xor(c, 1, 16);
+        c += __shfl_xor(c, 2, 16);
+        c += __shfl_xor(c, 4, 16);
+        c += __shfl_xor(c, 8, 16);
+        if (w < nwords && (w & 15) == 0)
+            L.bcount[w >> 4] = c;
+    }
+    __syncthreads();
+    block_exclusive_scan<kBlock>(L.bcount, d.rank, nblocks);
+}
+
 template <int kBlock, int kScope>
-__device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* slot)
+__device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* slot, uint8_t* lds)
 {
     using S = Sc<kScope>;
     constexpr uint32_t kBatchTile = batch_tile<kBlock>();
     __shared__ uint32_t s_ltail, s_err, s_degsum;
-    __shared__ uint32_t s_cnt[kBatchMaxBuckets], s_bnd[kBatchMaxBuckets + 1], s_wtot[kBlock / kWave];
-    __shared__ unsigned long long s_tab[kBatchTile];
+    __shared__ uint32_t s_wtot[kBlock / kWave];
+    unsigned long long* s_tab = reinterpret_cast<unsigned long long*>(lds);  // kBatchTile records
+    uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_tab + kBatchTile);       // kBatchMaxBuckets
+    uint32_t* s_bnd = s_cnt + kBatchMaxBuckets;                              // kBatchMaxBuckets + 1
     if (threadIdx.x == 0)
         s_degsum = 0;
     const uint32_t tid = threadIdx.x;
@@ -485,37 +537,167 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
         }
         __syncthreads();
     }
-    // pack codes, count per 512 vertices, exclusive scan into the rank samples
-    const uint32_t nwords = (m + 31) / 32, nblocks = (m + 511) / 512;
-    for (uint32_t base = 0; base < nwords; base += kBlock) {
-        uint32_t w = base + tid;
-        uint64_t x = 0;
-        if (w < nwords) {
-            if (32 * w + 32 <= m) {
-                const uint4* p = reinterpret_cast<const uint4*>(code8 + 32 * w);
-                uint4 q0 = p[0], q1 = p[1];
-                uint32_t dw[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
-#pragma unroll
-                for (int q = 0; q < 8; q++)
-#pragma unroll
-                    for (int u = 0; u < 4; u++)
-                        x |= (uint64_t)((dw[q] >> (8 * u)) & 3u) << (2 * (4 * q + u));
-            } else {
-                for (uint32_t q = 0; 32 * w + q < m; q++)
-                    x |= (uint64_t)(code8[32 * w + q] & 3u) << (2 * q);
-            }
-            d.codes[w] = x;
-        }
-        uint32_t c = nz_pairs(x);
-        c += __shfl_xor(c, 1, 16);
-        c += __shfl_xor(c, 2, 16);
-        c += __shfl_xor(c, 4, 16);
-        c += __shfl_xor(c, 8, 16);
-        if (w < nwords && (w & 15) == 0)
-            L.bcount[w >> 4] = c;
-    }
+    pack_codes<kBlock>(code8, m, d, L);
+    if (tid == 0)
+        write_result(d.result, sd, t + 1, 0, nrounds);
     __syncthreads();
-    block_exclusive_scan<kBlock>(L.bcount, d.rank, nblocks);
+}
+
+// The same build for a bucket that fits in LDS: 4-byte records (degree in bits [24, 32), sum of
+// incident edge ids in [0, 24): no carry while degrees stay <= 255 and ids below 2^16) and the
+// edge states live in LDS, so every atomic of the rounds is an LDS atomic; the layer slots stay
+// in the slot area.  Same rounds, hinges and layers as build_bucket, hence the same codes.
+template <int kBlock>
+__device__ void build_bucket_lds(const BatchArgs& a, const BucketDesc& d, uint8_t* slot, uint8_t* lds)
+{
+    __shared__ uint32_t s_ltail, s_err;
+    constexpr uint32_t kOne32 = 1u << 24, kSum = kOne32 - 1;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n = (uint32_t)d.n;
+    const uint64_t P = part_size_dev(n, a.gnum, a.gden);
+    const uint32_t m = (uint32_t)(3 * P);
+    SlotLayout L;
+    slot_layout(slot, n, m, &L);
+    uint32_t* rec = reinterpret_cast<uint32_t*>(lds);  // m records
+    uint32_t* state = rec + ((m + 3) & ~3u);            // n edge states
+    const uint64_t total = d.keys ? 0 : d.offs[n];
+
+    uint32_t t = 0, nrounds = 0;
+    bool ok = false;
+    int status = 0;
+    uint64_t sd = d.seed;
+    for (t = 0; t < a.max_tries; t++) {
+        sd = d.seed + t;
+        for (uint32_t v = tid; v < m; v += kBlock)
+            rec[v] = 0;
+        for (uint32_t e = tid; e < n; e += kBlock)
+            state[e] = kUnclaimed;
+        if (tid == 0) {
+            s_ltail = 0;
+            s_err = 0;
+        }
+        const uint64_t sa = fin(sd + kGamma), sb = fin(sd + 2 * kGamma);
+        if (!d.keys) {  // string keys: digest once, keep the edges
+            for (uint32_t i = tid; i < n; i += kBlock) {
+                uint64_t o0 = d.offs[i], o1 = d.offs[i + 1], ha, hb;
+                digest_str(d.bytes, o0, o1 - o0, total, sa, sb, ha, hb);
+                uint3 ev;
+                edge_of_digest(ha, hb, P, ev.x, ev.y, ev.z);
+                L.edges[i] = ev;
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += kBlock) {
+            const uint3 ev = bucket_edge(d, L, i, sd, P);
+            const uint32_t o0 = atomicAdd(&rec[ev.x], kOne32 + i);
+            const uint32_t o1 = atomicAdd(&rec[ev.y], kOne32 + i);
+            const uint32_t o2 = atomicAdd(&rec[ev.z], kOne32 + i);
+            if (max(o0, max(o1, o2)) >= kMaxDegree * kOne32)  // a degree would pass 255
+                s_err = 1;
+        }
+        __syncthreads();
+        if (s_err) {
+            status = -2;  // degree above 255: no seed helps a duplicate-heavy bucket
+            break;
+        }
+        // round 0: a degree-1 vertex claims its edge; the lowest part wins
+        for (uint32_t base = 0; base < m; base += kBlock) {
+            const uint32_t v = base + tid;
+            bool first = false;
+            uint32_t e = 0;
+            if (v < m) {
+                const uint32_t x = rec[v];
+                if ((x >> 24) == 1 && (x & kSum) < n) {
+                    e = x & kSum;
+                    first = atomicMin(&state[e], part_of(v, P)) == kUnclaimed;
+                }
+            }
+            const uint32_t pos = block_append(&s_ltail, first, false);
+            if (first)
+                L.slots[pos].x = e;
+        }
+        if (tid == 0)
+            L.lstart[0] = 0;
+        __syncthreads();
+        uint32_t r = 0, lo = 0;
+        for (;;) {
+            // as in build_bucket: applying layer r claims round r + 1
+            const uint32_t hi = s_ltail;
+            __syncthreads();
+            if (tid == 0)
+                L.lstart[r + 1] = hi;
+            if (lo == hi)
+                break;
+            const uint32_t rr = (r + 1) << 2;
+            for (uint32_t base = lo; base < hi; base += kBlock) {
+                const uint32_t i = base + tid;
+                uint32_t c0 = 0, c1 = 0;
+                bool f0 = false, f1 = false;
+                if (i < hi) {
+                    const uint32_t e = L.slots[i].x;
+                    const uint32_t h = state[e] & 3u;
+                    const uint3 ev = bucket_edge(d, L, e, sd, P);
+                    const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
+                    const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
+                    const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
+                    L.slots[i] = make_uint3(vh, va, vb);
+                    const uint32_t oa = atomicSub(&rec[va], kOne32 + e);
+                    const uint32_t ob = atomicSub(&rec[vb], kOne32 + e);
+                    if ((oa >> 24) == 2) {
+                        c0 = (oa & kSum) - e;
+                        f0 = atomicMin(&state[c0], rr | part_of(va, P)) == kUnclaimed;
+                    }
+                    if ((ob >> 24) == 2) {
+                        c1 = (ob & kSum) - e;
+                        f1 = atomicMin(&state[c1], rr | part_of(vb, P)) == kUnclaimed;
+                    }
+                    if (!f0) {  // the first requested slot holds the first appended edge
+                        c0 = c1;
+                        f0 = f1;
+                        f1 = false;
+                    }
+                }
+                const uint32_t pos = block_append(&s_ltail, f0, f1);
+                if (f0)
+                    L.slots[pos].x = c0;
+                if (f1)
+                    L.slots[pos + 1].x = c1;
+            }
+            __syncthreads();
+            lo = hi;
+            r++;
+        }
+        nrounds = r;
+        const bool all = s_ltail == n;
+        __syncthreads();
+        if (all) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) {
+        if (tid == 0)
+            write_result(d.result, sd, t < a.max_tries ? t + 1 : a.max_tries, status ? status : 1, nrounds);
+        __syncthreads();
+        return;
+    }
+    // assignment, last layer first, with the codes as bytes in LDS over the records
+    uint8_t* code8 = lds;
+    for (uint32_t v = tid; v < m; v += kBlock)
+        code8[v] = 0;
+    __syncthreads();
+    for (int32_t r = (int32_t)nrounds - 1; r >= 0; r--) {
+        const uint32_t lo = L.lstart[r], hi = L.lstart[r + 1];
+        for (uint32_t i = lo + tid; i < hi; i += kBlock) {
+            const uint3 sl = L.slots[i];
+            const uint32_t k = part_of(sl.x, P);
+            const uint32_t ca = code8[sl.y], cb = code8[sl.z];
+            const uint32_t g = (k + 6 - (ca == 3 ? 0 : ca) - (cb == 3 ? 0 : cb)) % 3;
+            code8[sl.x] = (uint8_t)(g ? g : 3);
+        }
+        __syncthreads();
+    }
+    pack_codes<kBlock>(code8, m, d, L);
     if (tid == 0)
         write_result(d.result, sd, t + 1, 0, nrounds);
     __syncthreads();
@@ -525,6 +707,7 @@ template <int kBlock, int kScope>
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
 {
     __shared__ uint32_t s_idx;
+    __shared__ __align__(16) uint8_t s_lds[batch_lds_bytes<kBlock>()];
     uint8_t* slot = a.slots + (uint64_t)blockIdx.x * a.slot_bytes;
     for (;;) {
         if (threadIdx.x == 0)
@@ -535,7 +718,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
         if (idx >= a.B)
             break;
         const BucketDesc d = a.descs[a.order ? a.order[idx] : idx];
-        build_bucket<kBlock, kScope>(a, d, slot);
+        const bool in_lds = d.n <= a.max_n && bucket_fits_lds<kBlock>(d.n, 3 * part_size_dev(d.n, a.gnum, a.gden));
+        if (in_lds && a.lds_path)
+            build_bucket_lds<kBlock>(a, d, slot, s_lds);
+        else
+            build_bucket<kBlock, kScope>(a, d, slot, s_lds);
     }
 }
 

@@ -66,6 +66,7 @@ struct BatchArgs {
     uint64_t slot_bytes;
     uint64_t max_n;          // largest bucket a slot can hold
     unsigned int* next;      // queue cursor
+    uint32_t lds_path;       // 1: buckets that fit run in LDS (1024-thread workgroups)
 };
 
 // batched builds (batch.hip)

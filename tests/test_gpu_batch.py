@@ -71,6 +71,24 @@ def test_batch_matches_oracle(mx, o, block, grid, scope):
     assert (res["tries"] > 1).sum() > 20  # small buckets retry often at gamma 1.23
 
 
+@pytest.mark.parametrize("lds", [0, 1])
+def test_batch_lds_path_on_and_off(mx, o, lds):
+    # buckets up to about 18,000 keys run in LDS with 1024-thread workgroups, larger ones (and
+    # every bucket with the option off) through device memory: the same codes either way
+    import torch
+
+    mx.set_option("batch_lds", lds)
+    try:
+        off = _offsets(SIZES)
+        keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+        bb = mx.BatchBuild(off, block=1024, grid=0, scope=0)
+        bb.run(keys)
+        torch.cuda.synchronize()
+        _check_buckets(mx, o, bb, _host_keys(SIZES), SIZES)
+    finally:
+        mx.set_option("batch_lds", 1)
+
+
 def test_batch_large_buckets_sampled(mx, o):
     import torch
 
