@@ -742,7 +742,7 @@ def main() -> int:
     ap.add_argument("--hem-tune", type=lambda s: s.split(","), default=["1024x0"],
                     help="batched-kernel block x grid shapes of the hem leg (grid 0 = one per compute unit)")
     ap.add_argument("--hem-host-n", type=int, default=1 << 34, help="keys of the hem_host leg (host memory)")
-    ap.add_argument("--hem-host-k", type=int, default=18)
+    ap.add_argument("--hem-host-k", type=int, default=20)
     ap.add_argument("--hem-host-chunk", type=int, default=1 << 27, help="keys per host-to-device chunk")
     ap.add_argument("--hem-host-batch", type=int, default=1 << 28, help="keys per gathered batch of groups")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),

@@ -285,7 +285,8 @@ MPHX_API int mphx_graph_destroy(void* graph);
  * buckets; the signature with its two 32-bit halves swapped is the key inside the bucket, and
  * each bucket gets the MWHC MPHF of its keys (hash seed `seed`, retries seed+1, ... per bucket)
  * built by the batched kernel.  f(x) = bucket_off[b] + the bucket MPHF's value.
- *   k in [9, 18] (2^k buckets); outputs (dev, caller-allocated): bucket_off, code_off, rank_off
+ *   k in [9, 20] (2^k buckets; beyond 2^18 each of the 2^18 buckets of the top 18 bits is split
+ *   by the next k - 18 bits); outputs (dev, caller-allocated): bucket_off, code_off, rank_off
  *   (2^k + 1 each: where bucket b's keys, ceil(m_b/32) code words and ceil(m_b/512) rank
  *   samples start), seeds (2^k: each bucket's seed used), codes and rank (at least the
  *   mphx_hem_capacity words).  ws (dev, 256-byte aligned): mphx_hem_workspace_bytes bytes;

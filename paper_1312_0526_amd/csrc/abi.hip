@@ -1143,8 +1143,13 @@ static mphx_batch_tuning hem_tuning()
     return t;
 }
 
+// Up to 2^18 buckets come straight from the two-pass partition; beyond, each of the 2^18
+// coarse buckets is split by the next k - 18 bits.
+static constexpr uint32_t kHemMaxK = 20, kHemCoarseK = 18;
+
 struct HemLayout {
     uint2 *rec, *tmp;
+    uint64_t* coff;  // coarse bucket offsets (k > 18 only)
     void* aux;
     uint32_t* order;
     mphx_bucket_result* results;
@@ -1154,10 +1159,11 @@ struct HemLayout {
 
 static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, HemLayout& L)
 {
-    const uint32_t B = 1u << k;
+    const uint32_t B = 1u << k, kc = std::min(k, kHemCoarseK);
     L.rec = c.take<uint2>(n);
     L.tmp = c.take<uint2>(n);
-    L.aux = c.take<uint8_t>(hem_aux_bytes(n, k));
+    L.coff = k > kc ? c.take<uint64_t>((1ull << kc) + 1) : nullptr;
+    L.aux = c.take<uint8_t>(hem_aux_bytes(n, kc));
     L.order = c.take<uint32_t>(B);
     L.results = c.take<mphx_bucket_result>(B);
     const mphx_batch_tuning t = hem_tuning();
@@ -1167,7 +1173,7 @@ static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t
 
 size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden)
 {
-    if (k < 9 || k > 18 || gnum == 0 || gden == 0) return 0;
+    if (k < 9 || k > kHemMaxK || gnum == 0 || gden == 0) return 0;
     Carve c(nullptr);
     HemLayout L;
     layout_hem(c, n, k, gnum, gden, L);
@@ -1178,8 +1184,8 @@ int mphx_hem_capacity(uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, uint
                       uint64_t* rank_words)
 {
     g_err.clear();
-    if (k < 9 || k > 18 || gnum == 0 || gden == 0 || !code_words || !rank_words)
-        return fail(MPHX_EINVAL, "k must be in [9, 18], gamma positive, outputs non-null");
+    if (k < 9 || k > kHemMaxK || gnum == 0 || gden == 0 || !code_words || !rank_words)
+        return fail(MPHX_EINVAL, "k must be in [9, 20], gamma positive, outputs non-null");
     // sum over buckets of 3 ceil(n_b num / 3 den) <= n num / den + 3 * 2^k vertices
     const uint64_t B = 1ull << k;
     const uint64_t mv = (uint64_t)(((unsigned __int128)n * gnum + gden - 1) / gden) + 3 * B;
@@ -1330,7 +1336,7 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
                      void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
 {
     g_err.clear();
-    if (k < 9 || k > 18) return fail(MPHX_EINVAL, "k must be in [9, 18]");
+    if (k < 9 || k > kHemMaxK) return fail(MPHX_EINVAL, "k must be in [9, 20]");
     if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
     if (n >= 0xFFFFFFFFull) return fail(MPHX_EINVAL, "n must be < 2^32 - 1");
     if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank) return fail(MPHX_EINVAL, "null output");
@@ -1351,10 +1357,13 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
         else
             HIP_TRY(launch_hem_sig_str(bytes, offs, n, seed, L.rec, s));
     }
+    const uint32_t kc = std::min(k, kHemCoarseK);
     {
         Timed tm(PH_BUILD, s);
-        HIP_TRY(launch_hem_partition(L.rec, n, k, L.tmp, bucket_off, L.aux, s));
+        HIP_TRY(launch_hem_partition(L.rec, n, kc, L.tmp, k > kc ? L.coff : bucket_off, L.aux, s));
+        if (k > kc) HIP_TRY(launch_hem_refine(L.rec, L.coff, kc, k, L.tmp, bucket_off, s));
     }
+    const uint2* bkeys = k > kc ? L.tmp : L.rec;  // the signatures in bucket order
     std::vector<uint64_t> bo(B + 1), co(B + 1), ro(B + 1);
     std::vector<uint32_t> order(B);
     HIP_TRY(hipMemcpyAsync(bo.data(), bucket_off, (B + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -1371,7 +1380,7 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
     {
         Timed tm(PH_OTHER, s);
         // the partitioned records read as u64 are the bucket keys
-        rc = batch_enqueue(reinterpret_cast<const uint64_t*>(L.rec), bucket_off, L.order, B, max_bucket, seed, gnum,
+        rc = batch_enqueue(reinterpret_cast<const uint64_t*>(bkeys), bucket_off, L.order, B, max_bucket, seed, gnum,
                            gden, max_tries, code_off, rank_off, codes, rank, L.results, L.batch, L.batch_bytes,
                            &tune, s);
         if (rc) return rc;
@@ -1394,6 +1403,7 @@ struct HemHostLayout {
     uint64_t* soffs;
     void *caux, *baux;
     uint64_t* lbo;
+    uint64_t* lbo_c;  // a batch's coarse bucket offsets (k > 18 only)
     uint32_t* order;
     HemRun* runs;
     mphx_bucket_result* results;
@@ -1404,7 +1414,7 @@ struct HemHostLayout {
 static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden,
                             uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys, HemHostLayout& L)
 {
-    const uint32_t B = 1u << k;
+    const uint32_t B = 1u << k, kc = std::min(k, kHemCoarseK);
     L.sig = c.take<uint2>(n);
     if (kind == MPHX_KEYS_U64) {
         L.stage = reinterpret_cast<uint8_t*>(c.take<uint64_t>(chunk_keys));
@@ -1414,11 +1424,12 @@ static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t
         L.soffs = c.take<uint64_t>(chunk_keys + 1);
     }
     L.csig = c.take<uint2>(chunk_keys);
-    L.caux = c.take<uint8_t>(hem_aux_bytes(chunk_keys, k));
+    L.caux = c.take<uint8_t>(hem_aux_bytes(chunk_keys, kc));
     L.bsig = c.take<uint2>(batch_keys);
     L.btmp = c.take<uint2>(batch_keys);
-    L.baux = c.take<uint8_t>(hem_aux_bytes(batch_keys, k));
+    L.baux = c.take<uint8_t>(hem_aux_bytes(batch_keys, kc));
     L.lbo = c.take<uint64_t>(B + 1);
+    L.lbo_c = k > kc ? c.take<uint64_t>((1ull << kc) + 1) : nullptr;
     L.order = c.take<uint32_t>(B);
     L.runs = c.take<HemRun>(kHemRunSlots);
     L.results = c.take<mphx_bucket_result>(B);
@@ -1521,7 +1532,7 @@ class HostStager {
 static int hem_host_args(int kind, uint32_t k, uint32_t gnum, uint32_t gden, uint64_t chunk_keys,
                          uint64_t chunk_bytes, uint64_t batch_keys)
 {
-    if (k < 9 || k > 18) return fail(MPHX_EINVAL, "k must be in [9, 18]");
+    if (k < 9 || k > kHemMaxK) return fail(MPHX_EINVAL, "k must be in [9, 20]");
     if (gnum == 0 || gden == 0) return fail(MPHX_EINVAL, "bad gamma");
     if (chunk_keys == 0 || chunk_keys >= 0x7FFFFFFFull) return fail(MPHX_EINVAL, "chunk_keys must be in [1, 2^31 - 1)");
     if (batch_keys == 0 || batch_keys >= 0x7FFFFFFFull) return fail(MPHX_EINVAL, "batch_keys must be in [1, 2^31 - 1)");
@@ -1547,7 +1558,8 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
     if (kind == MPHX_KEYS_STR && n > 0)
         for (uint64_t i = 0; i < n; i++)
             if (hoffs[i + 1] < hoffs[i]) return fail(MPHX_EINVAL, "offsets decrease at key %llu", (unsigned long long)i);
-    const uint32_t NH = 1u << (k - 8), B = 1u << k;
+    const uint32_t kc = std::min(k, kHemCoarseK), NH = 1u << (kc - 8), B = 1u << k;
+    const uint32_t gshift = k - kc + 8;  // a group holds 2^gshift buckets
     const mphx_batch_tuning tune = hem_tuning();
     Carve c(ws);
     HemHostLayout L;
@@ -1587,7 +1599,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
                 HIP_TRY(launch_hem_sig_str(L.stage, L.soffs, c1 - c0, seed, L.csig, s));
             }
             gst.emplace_back(new uint32_t[NH + 1]);
-            HIP_TRY(launch_hem_group_chunk(L.csig, c1 - c0, k, L.sig + c0, L.caux, gst.back().get(), s));
+            HIP_TRY(launch_hem_group_chunk(L.csig, c1 - c0, kc, L.sig + c0, L.caux, gst.back().get(), s));
             cbase.push_back(c0);
             c0 = c1;
         }
@@ -1631,11 +1643,13 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
                 HIP_TRY(hipMemcpyAsync(L.runs, runs.data() + r0, cnt * sizeof(HemRun), hipMemcpyHostToDevice, s));
                 HIP_TRY(launch_hem_gather(L.sig, L.runs, cnt, L.bsig, s));
             }
-            HIP_TRY(launch_hem_partition(L.bsig, nb, k, L.btmp, L.lbo, L.baux, s));
+            HIP_TRY(launch_hem_partition(L.bsig, nb, kc, L.btmp, k > kc ? L.lbo_c : L.lbo, L.baux, s));
+            if (k > kc) HIP_TRY(launch_hem_refine(L.bsig, L.lbo_c, kc, k, L.btmp, L.lbo, s));
         }
+        const uint2* bkeys = k > kc ? L.btmp : L.bsig;  // the batch's signatures in bucket order
         HIP_TRY(hipMemcpyAsync(lbo.data(), L.lbo, (B + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const uint32_t b0 = g0 << 8, Bb = (g1 - g0) << 8;
+        const uint32_t b0 = g0 << gshift, Bb = (g1 - g0) << gshift;
         if (lbo[b0] != 0 || lbo[b0 + Bb] != nb) return fail(MPHX_EDEVICE, "batch bucket offsets inconsistent");
         uint64_t mb = 0;
         rc = mphx_batch_layout(&lbo[b0], Bb, gnum, gden, co_l.data(), ro_l.data(), &ord[b0], &mb);
@@ -1653,7 +1667,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
         HIP_TRY(hipMemcpyAsync(L.order, &ord[b0], Bb * sizeof(uint32_t), hipMemcpyHostToDevice, s));
         {
             Timed tm(PH_OTHER, s);
-            rc = batch_enqueue(reinterpret_cast<const uint64_t*>(L.bsig), L.lbo + b0, L.order, Bb, mb, seed, gnum,
+            rc = batch_enqueue(reinterpret_cast<const uint64_t*>(bkeys), L.lbo + b0, L.order, Bb, mb, seed, gnum,
                                gden, max_tries, code_off + b0, rank_off + b0, codes, rank, L.results + b0, L.batch,
                                L.batch_bytes, &tune, s);
             if (rc) return rc;
@@ -1689,7 +1703,7 @@ size_t mphx_hem_host_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num,
                                      uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys)
 {
     if (kind != MPHX_KEYS_U64 && kind != MPHX_KEYS_STR) return 0;
-    if (k < 9 || k > 18 || gamma_num == 0 || gamma_den == 0 || chunk_keys == 0 || chunk_keys >= 0x7FFFFFFFull ||
+    if (k < 9 || k > kHemMaxK || gamma_num == 0 || gamma_den == 0 || chunk_keys == 0 || chunk_keys >= 0x7FFFFFFFull ||
         batch_keys == 0 || batch_keys >= 0x7FFFFFFFull || (kind == MPHX_KEYS_STR && chunk_bytes < 512))
         return 0;
     Carve c(nullptr);
@@ -1727,9 +1741,9 @@ int mphx_hem_lookup_u64(const uint64_t* bucket_off, const uint64_t* code_off, co
 {
     g_err.clear();
     if (n == 0) return MPHX_OK;
-    if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank || !keys || !out || k < 9 || k > 18 ||
+    if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank || !keys || !out || k < 9 || k > kHemMaxK ||
         gamma_num == 0 || gamma_den == 0)
-        return fail(MPHX_EINVAL, "null pointer, k outside [9, 18] or bad gamma");
+        return fail(MPHX_EINVAL, "null pointer, k outside [9, 20] or bad gamma");
     HemTables t{bucket_off, code_off, rank_off, seeds, codes, rank, k, gamma_num, gamma_den};
     HIP_TRY(launch_hem_lookup_u64(t, seed, keys, n, out, (hipStream_t)stream));
     return MPHX_OK;
@@ -1743,8 +1757,8 @@ int mphx_hem_lookup_str(const uint64_t* bucket_off, const uint64_t* code_off, co
     g_err.clear();
     if (n == 0) return MPHX_OK;
     if (!bucket_off || !code_off || !rank_off || !seeds || !codes || !rank || !bytes || !offs || !out || k < 9 ||
-        k > 18 || gamma_num == 0 || gamma_den == 0)
-        return fail(MPHX_EINVAL, "null pointer, k outside [9, 18] or bad gamma");
+        k > kHemMaxK || gamma_num == 0 || gamma_den == 0)
+        return fail(MPHX_EINVAL, "null pointer, k outside [9, 20] or bad gamma");
     if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
     HemTables t{bucket_off, code_off, rank_off, seeds, codes, rank, k, gamma_num, gamma_den};
     HIP_TRY(launch_hem_lookup_str(t, seed, bytes, offs, n, out, (hipStream_t)stream));

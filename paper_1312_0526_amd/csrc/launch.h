@@ -162,7 +162,8 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
                                uint8_t* code8, unsigned grid_cap, hipStream_t s);
 // HEM split (keys.hip, part.hip): signature records (high, low half: a u64 read gives the
-// bucket key), their partition into 2^k buckets in place (tmp: n more pairs; 9 <= k <= 18)
+// bucket key), their partition into 2^k buckets in place (tmp: n more pairs; 9 <= k <= 18; larger
+// k through launch_hem_refine)
 // with bucket_off[0..2^k] written on the device, and lookups
 hipError_t launch_hem_sig_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint2* rec, hipStream_t s);
 hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint2* rec,
@@ -205,6 +206,10 @@ struct HemRun {
 hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, uint2* out, void* aux,
                                   uint32_t* host_gstart, hipStream_t s);
 hipError_t launch_hem_gather(const uint2* src, const HemRun* runs, uint32_t nruns, uint2* dst, hipStream_t s);
+// More than 2^18 buckets: records partitioned into 2^kc coarse buckets (coarse_off, 2^kc + 1)
+// split stably by the next k - kc <= 2 bits into out, with the 2^k + 1 fine offsets.
+hipError_t launch_hem_refine(const uint2* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint2* out,
+                             uint64_t* fine_off, hipStream_t s);
 hipError_t launch_offs_rebase(uint64_t* offs, uint64_t count, uint64_t base, hipStream_t s);
 
 }  // namespace mphx

@@ -761,6 +761,77 @@ hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, 
         s);
 }
 
+// HEM beyond 2^18 buckets: each coarse bucket b (top kc bits) split, stably, by the next
+// k - kc bits (at most 2) into fine buckets b * D + j, one workgroup per coarse bucket;
+// fine_off[0 .. 2^k] written.
+constexpr uint32_t kRefBlock = 256;
+
+__global__ __launch_bounds__(kRefBlock) void k_hem_refine(const uint2* __restrict__ in,
+                                                          const uint64_t* __restrict__ coarse_off, uint32_t nb,
+                                                          uint32_t k, uint32_t d, uint2* __restrict__ out,
+                                                          uint64_t* __restrict__ fine_off)
+{
+    __shared__ uint32_t s_cnt[4], s_wtot[kRefBlock / kWave][4];
+    __shared__ uint64_t s_start[4];
+    const uint32_t b = blockIdx.x, D = 1u << d, sh = 32 - k;
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint64_t lo = coarse_off[b], hi = coarse_off[b + 1];
+    if (threadIdx.x < 4)
+        s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kRefBlock)
+        atomicAdd(&s_cnt[(in[i].x >> sh) & (D - 1)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t at = lo;
+        for (uint32_t j = 0; j < D; j++) {
+            s_start[j] = at;
+            fine_off[(uint64_t)b * D + j] = at;
+            at += s_cnt[j];
+        }
+        if (b + 1 == nb)
+            fine_off[(uint64_t)nb * D] = hi;
+    }
+    __syncthreads();
+    for (uint64_t c = lo; c < hi; c += kRefBlock) {
+        const uint64_t i = c + threadIdx.x;
+        const bool have = i < hi;
+        const uint2 x = have ? in[i] : make_uint2(0u, 0u);
+        const uint32_t dg = have ? (x.x >> sh) & (D - 1) : D;
+        uint32_t below = 0;
+        for (uint32_t j = 0; j < D; j++) {
+            const uint64_t mj = __ballot(dg == j);
+            if (lane == 0)
+                s_wtot[w][j] = (uint32_t)__popcll(mj);
+            if (dg == j)
+                below = lanes_below(mj);
+        }
+        __syncthreads();
+        if (have) {
+            uint64_t pos = s_start[dg] + below;
+            for (uint32_t q = 0; q < w; q++)
+                pos += s_wtot[q][dg];
+            out[pos] = x;
+        }
+        __syncthreads();
+        if (threadIdx.x < D) {
+            uint32_t t = 0;
+            for (uint32_t q = 0; q < kRefBlock / kWave; q++)
+                t += s_wtot[q][threadIdx.x];
+            s_start[threadIdx.x] += t;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_hem_refine(const uint2* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint2* out,
+                             uint64_t* fine_off, hipStream_t s)
+{
+    if (kc < 9 || kc > 18 || k <= kc || k - kc > 2) return hipErrorInvalidValue;
+    k_hem_refine<<<1u << kc, kRefBlock, 0, s>>>(in, coarse_off, 1u << kc, k, k - kc, out, fine_off);
+    return hipGetLastError();
+}
+
 // Out-of-core HEM, first level: one chunk's signature records grouped by their top k - 8 bits
 // (the partition's first pass alone) into out; the chunk's NH + 1 group starts are copied to
 // host_gstart (pageable or pinned host memory, valid once the stream has reached the copy).

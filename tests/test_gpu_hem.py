@@ -71,7 +71,7 @@ def test_hem_empty_and_errors(mx):
     got = mx.hem_build(keys=torch.empty(0, dtype=torch.int64, device="cuda"), k=9)
     assert int(got["bucket_off"].abs().sum()) == 0 and got["codes"].numel() == 0
     keys = dev(workloads.u64_keys(1000))
-    for bad_k in (8, 19):  # k = 8 would need a 32-bit group shift
+    for bad_k in (8, 21):  # k = 8 would need a 32-bit group shift
         with pytest.raises((mx.MphxError, ValueError)):
             mx.hem_build(keys=keys, k=bad_k)
 
@@ -158,3 +158,28 @@ def test_hem_host_empty_and_errors(mx):
         mx.hem_build_host(keys=keys, k=9, chunk_keys=0, batch_keys=100)
     with pytest.raises(TypeError):
         mx.hem_build_host(keys=keys.cuda(), k=9)
+
+
+# ---- more than 2^18 buckets: each bucket of the top 18 bits split by the next k - 18 bits ----
+# gamma = 2 keeps buckets of a few dozen keys buildable within the retry budget on both sides
+# (at 1.23 they hit a 2-core on most tries); the split itself does not depend on gamma.
+def test_hem_k19_matches_oracle(mx, o):
+    keys = workloads.u64_keys(12_000_000, gen_seed=219)
+    got = mx.hem_build(keys=dev(keys), k=19, seed=7, gamma=(2, 1))
+    sigs = o.hem_signatures_u64(keys, 7)
+    rc, ref = o.hem_build(sigs, 19, seed=7, gnum=2, gden=1)
+    assert rc == 0
+    _assert_same(got, ref)
+    sample = keys[:: 97]
+    f = mx.hem_lookup(got, keys=dev(sample))
+    assert np.array_equal(host(f), o.hem_lookup(ref, o.hem_signatures_u64(sample, 7), gnum=2, gden=1))
+
+
+def test_hem_host_k20_matches_oracle_and_device_build(mx, o):
+    keys = workloads.u64_keys(24_000_000, gen_seed=220)
+    got = mx.hem_build_host(keys=_host_u64(keys), k=20, seed=7, gamma=(2, 1), chunk_keys=5_000_000,
+                            batch_keys=8_000_000)
+    rc, ref = o.hem_build(o.hem_signatures_u64(keys, 7), 20, seed=7, gnum=2, gden=1)
+    assert rc == 0
+    _assert_same(got, ref)
+    _same_tables(got, mx.hem_build(keys=dev(keys), k=20, seed=7, gamma=(2, 1)))
