@@ -35,7 +35,7 @@ struct SlotLayout {
     uint32_t* state;   // n edge states
     uint32_t* lstart;  // n + 2 layer starts
     uint32_t* bcount;  // ceil(m/512)
-    uint3* edges;      // n edges (string keys; u64 keys in the LDS build)
+    uint3* edges;      // n edges (string keys only)
 };
 
 __host__ __device__ __forceinline__ uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -589,8 +589,6 @@ __device__ void build_bucket_lds(const BatchArgs& a, const BucketDesc& d, uint8_
         __syncthreads();
         for (uint32_t i = tid; i < n; i += kBlock) {
             const uint3 ev = bucket_edge(d, L, i, sd, P);
-            if (d.keys)
-                L.edges[i] = ev;  // the rounds read the edge back instead of the key
             const uint32_t o0 = atomicAdd(&rec[ev.x], kOne32 + i);
             const uint32_t o1 = atomicAdd(&rec[ev.y], kOne32 + i);
             const uint32_t o2 = atomicAdd(&rec[ev.z], kOne32 + i);
@@ -638,7 +636,7 @@ __device__ void build_bucket_lds(const BatchArgs& a, const BucketDesc& d, uint8_
                 if (i < hi) {
                     const uint32_t e = L.slots[i].x;
                     const uint32_t h = state[e] & 3u;
-                    const uint3 ev = L.edges[e];
+                    const uint3 ev = bucket_edge(d, L, e, sd, P);
                     const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
                     const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
