@@ -459,9 +459,10 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 claims of the next round then come from the updated records.  0 = never.
  *                 The same codes either way.
  *   "batch_lds"   1 (default) = in the batched kernel (mphx_build_batch*, the server's
- *                 batching lane, the HEM split) with 1024-thread workgroups, a bucket whose
- *                 4-byte records and edge states fit in 158 KB of LDS (about 18,000 keys) is
- *                 built and peeled entirely in LDS; 0 = every bucket through device memory.
+ *                 batching lane, the HEM split) a bucket whose 4-byte records and edge states
+ *                 fit in the workgroup's LDS budget (1024 threads: 158 KB, about 18,000 keys;
+ *                 512: 78 KB, about 9,000; 256: 48 KB, about 5,500) is built and peeled
+ *                 entirely in LDS; 0 = every bucket through device memory.
  *                 The same codes either way.
  *   "hem_block"   256, 512 or 1024 (default 1024): workgroup size of the batched kernel that
  *                 builds the HEM split's buckets (mphx_hem_build_*, mphx_hem_build_host_*).

@@ -188,16 +188,20 @@ template <int kBlock>
 constexpr uint32_t batch_tile() { return kBlock >= 1024 ? 8192u : 4096u; }
 constexpr uint32_t kBatchMaxBuckets = 2048;
 // LDS shared by the two bucket builds: the partitioned record build's tile, counts and bounds,
-// or (1024-thread workgroups) a whole bucket's 4-byte records and edge states.
+// or a whole bucket's 4-byte records and edge states.  1024-thread workgroups take 158 KB (one
+// per compute unit), 512-thread ones 78 KB (two), 256-thread ones 48 KB (three).
 template <int kBlock>
 constexpr uint32_t batch_part_bytes() { return batch_tile<kBlock>() * 8 + (2 * kBatchMaxBuckets + 1) * 4; }
 template <int kBlock>
-constexpr uint32_t batch_lds_bytes() { return kBlock >= 1024 ? 158u * 1024 : batch_part_bytes<kBlock>(); }
+constexpr uint32_t batch_lds_bytes()
+{
+    return kBlock >= 1024 ? 158u * 1024 : (kBlock >= 512 ? 78u * 1024 : batch_part_bytes<kBlock>());
+}
 // A bucket whose records (m words) and states (n words) fit runs entirely in LDS.
 template <int kBlock>
 __device__ __forceinline__ bool bucket_fits_lds(uint64_t n, uint64_t m)
 {
-    return kBlock >= 1024 && ((m + 3) & ~3ull) + n <= batch_lds_bytes<kBlock>() / 4;
+    return ((m + 3) & ~3ull) + n <= batch_lds_bytes<kBlock>() / 4;
 }
 
 // Part-k local vertex of key i: recomputed from a u64 key, read from the stored edge else.
