@@ -30,6 +30,7 @@ struct Options {
     std::atomic<int> hem_block{1024};  // batched-kernel workgroup size for the HEM split's buckets
     std::atomic<int> hem_grid{0};      // its persistent grid (0 = one workgroup per compute unit)
     std::atomic<int> batch_lds{1};     // 1 = batched buckets that fit run entirely in LDS
+    std::atomic<int> batch_sort_deletes{8};  // sorted deletes for layers with 2 * layer * this >= m
                                        // delete through a sorted update list (0 = never)
 };
 
@@ -400,6 +401,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "batch_lds")) {
         if (value != 0 && value != 1) return fail(MPHX_EINVAL, "batch_lds must be 0 or 1");
         g_opt.batch_lds = (int)value;
+    } else if (!strcmp(key, "batch_sort_deletes")) {
+        if (value < 0 || value > 1024) return fail(MPHX_EINVAL, "batch_sort_deletes must be in 0..1024");
+        g_opt.batch_sort_deletes = (int)value;
     } else if (!strcmp(key, "hem_grid")) {
         if (value < 0 || value > (1 << 16)) return fail(MPHX_EINVAL, "hem_grid must be in 0..65536");
         g_opt.hem_grid = (int)value;
@@ -421,6 +425,7 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "hem_block")) return g_opt.hem_block;
     if (!strcmp(key, "hem_grid")) return g_opt.hem_grid;
     if (!strcmp(key, "batch_lds")) return g_opt.batch_lds;
+    if (!strcmp(key, "batch_sort_deletes")) return g_opt.batch_sort_deletes;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
@@ -1075,6 +1080,7 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
     a.slot_bytes = batch_slot_bytes(max_bucket, gnum, gden);
     a.max_n = max_bucket;
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
+    a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
     HIP_TRY(launch_batch_descs(descs, keys, bucket_off, B, seed, code_off, rank_off, codes, rank,
                                reinterpret_cast<BucketResult*>(results), s));
     HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), s));
@@ -1241,6 +1247,7 @@ int mphx_build_batch(const mphx_bucket* buckets, uint32_t B, const uint32_t* ord
     a.slot_bytes = batch_slot_bytes(max_bucket, gnum, gden);
     a.max_n = max_bucket;
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
+    a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
     HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), (hipStream_t)stream));
     return MPHX_OK;
 }

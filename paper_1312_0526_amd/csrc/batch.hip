@@ -473,6 +473,76 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             if (lo == hi)
                 break;
             const uint32_t rr = (r + 1) << 2;
+            // A dense layer of a u64 bucket deletes through a sorted list instead of device
+            // atomics (Section 4.2's sorted update list, inside the workgroup): its deletes
+            // are grouped by tile of kBatchTile vertices in the free edge area, then each tile's
+            // records are loaded into LDS, the deletes applied with LDS atomics (the same old
+            // (degree, sum) per delete, hence the same claims) and the tile written back.
+            const uint32_t L2 = 2 * (hi - lo), mt = (m + kBatchTile - 1) / kBatchTile;
+            if (a.sort_div && d.keys && (uint64_t)L2 * a.sort_div >= m && (uint64_t)L2 <= 3ull * n / 2 &&
+                mt <= kBatchMaxBuckets) {
+                uint2* dl = reinterpret_cast<uint2*>(L.edges);  // 12n bytes: up to 1.5n deletes
+                for (uint32_t b = tid; b < mt; b += kBlock)
+                    s_cnt[b] = 0;
+                __syncthreads();
+                for (uint32_t i = lo + tid; i < hi; i += kBlock) {
+                    const uint32_t e = L.slots[i].x, h = S::ld(L.state + e) & 3u;
+                    const uint3 ev = bucket_edge(d, L, e, sd, P);
+                    atomicAdd(&s_cnt[(h == 0 ? ev.y : (h == 1 ? ev.z : ev.x)) / kBatchTile], 1u);
+                    atomicAdd(&s_cnt[(h == 0 ? ev.z : (h == 1 ? ev.x : ev.y)) / kBatchTile], 1u);
+                }
+                __syncthreads();
+                lds_exclusive_scan<kBlock>(s_cnt, mt, s_wtot);
+                for (uint32_t b = tid; b < mt; b += kBlock)
+                    s_bnd[b] = s_cnt[b];
+                if (tid == 0)
+                    s_bnd[mt] = L2;
+                __syncthreads();
+                for (uint32_t i = lo + tid; i < hi; i += kBlock) {
+                    const uint32_t e = L.slots[i].x, h = S::ld(L.state + e) & 3u;
+                    const uint3 ev = bucket_edge(d, L, e, sd, P);
+                    const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
+                    const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
+                    const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
+                    L.slots[i] = make_uint3(vh, va, vb);
+                    dl[atomicAdd(&s_cnt[va / kBatchTile], 1u)] = make_uint2(va % kBatchTile, e);
+                    dl[atomicAdd(&s_cnt[vb / kBatchTile], 1u)] = make_uint2(vb % kBatchTile, e);
+                }
+                __syncthreads();
+                for (uint32_t t = 0; t < mt; t++) {
+                    const uint32_t j0 = s_bnd[t], j1 = s_bnd[t + 1];
+                    if (j0 == j1)
+                        continue;  // uniform per block
+                    const uint64_t v0 = (uint64_t)t * kBatchTile;
+                    const uint32_t cnt = (uint32_t)min<uint64_t>(kBatchTile, m - v0);
+                    for (uint32_t v = tid; v < cnt; v += kBlock)
+                        s_tab[v] = S::ld(L.rec + v0 + v);
+                    __syncthreads();
+                    for (uint32_t base = j0; base < j1; base += kBlock) {
+                        const uint32_t j = base + tid;
+                        uint32_t c = 0;
+                        bool f = false;
+                        if (j < j1) {
+                            const uint2 dv = dl[j];
+                            const uint64_t old = atomicAdd(&s_tab[dv.x], 0ull - (Rec::kOne + dv.y));
+                            if (Rec::deg(old) == 2) {
+                                c = (uint32_t)(Rec::edge(old) - dv.y);
+                                f = S::fetch_min(L.state + c, rr | part_of((uint32_t)(v0 + dv.x), P)) == kUnclaimed;
+                            }
+                        }
+                        const uint32_t pos = block_append(&s_ltail, f, false);
+                        if (f)
+                            L.slots[pos].x = c;
+                    }
+                    __syncthreads();
+                    for (uint32_t v = tid; v < cnt; v += kBlock)
+                        L.rec[v0 + v] = s_tab[v];
+                    __syncthreads();
+                }
+                lo = hi;
+                r++;
+                continue;
+            }
             for (uint32_t base = lo; base < hi; base += kBlock) {
                 uint32_t i = base + tid;
                 uint32_t c0 = 0, c1 = 0;

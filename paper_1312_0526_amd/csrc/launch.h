@@ -66,7 +66,8 @@ struct BatchArgs {
     uint64_t slot_bytes;
     uint64_t max_n;          // largest bucket a slot can hold
     unsigned int* next;      // queue cursor
-    uint32_t lds_path;       // 1: buckets that fit run in LDS (1024-thread workgroups)
+    uint32_t lds_path;       // 1: buckets that fit run in LDS
+    uint32_t sort_div;       // > 0: a layer deletes through a sorted list when 2 * layer * sort_div >= m
 };
 
 // batched builds (batch.hip)

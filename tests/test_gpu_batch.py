@@ -71,13 +71,15 @@ def test_batch_matches_oracle(mx, o, block, grid, scope):
     assert (res["tries"] > 1).sum() > 20  # small buckets retry often at gamma 1.23
 
 
-@pytest.mark.parametrize("lds", [0, 1])
-def test_batch_lds_path_on_and_off(mx, o, lds):
+@pytest.mark.parametrize("lds,sort_div", [(0, 0), (0, 8), (1, 8)])
+def test_batch_lds_path_on_and_off(mx, o, lds, sort_div):
     # buckets up to about 18,000 keys run in LDS with 1024-thread workgroups, larger ones (and
-    # every bucket with the option off) through device memory: the same codes either way
+    # every bucket with the option off) through device memory, whose dense layers delete
+    # through sorted lists unless that is off too: the same codes every way
     import torch
 
     mx.set_option("batch_lds", lds)
+    mx.set_option("batch_sort_deletes", sort_div)
     try:
         off = _offsets(SIZES)
         keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
@@ -87,6 +89,7 @@ def test_batch_lds_path_on_and_off(mx, o, lds):
         _check_buckets(mx, o, bb, _host_keys(SIZES), SIZES)
     finally:
         mx.set_option("batch_lds", 1)
+        mx.set_option("batch_sort_deletes", 8)
 
 
 def test_batch_large_buckets_sampled(mx, o):
