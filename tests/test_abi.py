@@ -56,6 +56,39 @@ def test_options_roundtrip(mx):
         mx.set_option("no_such_option", 1)
 
 
+@pytest.mark.parametrize("key,default,good,bad", [
+    ("batch_lds", 1, 0, 2),
+    ("batch_sort_deletes", 8, 0, 1025),
+    ("hem_block", 1024, 256, 300),
+    ("hem_grid", 0, 512, 1 << 17),
+])
+def test_batch_and_hem_options(mx, key, default, good, bad):
+    assert mx.get_option(key) == default
+    mx.set_option(key, good)
+    try:
+        assert mx.get_option(key) == good
+        with pytest.raises(mx.MphxError):
+            mx.set_option(key, bad)
+        assert mx.get_option(key) == good  # a refused value changes nothing
+    finally:
+        mx.set_option(key, default)
+
+
+def test_hem_workspaces_follow_k_range_and_shape(mx):
+    # k outside [9, 20] has no workspace; the grid option sizes the batched scratch
+    assert mx.hem_workspace_bytes(1 << 20, 8) == 0 and mx.hem_workspace_bytes(1 << 20, 21) == 0
+    assert mx.hem_host_workspace_bytes(1 << 20, 21, mx.KEYS_U64, 1 << 16, 0, 1 << 18) == 0
+    base = mx.hem_workspace_bytes(1 << 20, 12)
+    assert base > 16 * (1 << 20)  # signatures and the partition's second buffer at least
+    mx.set_option("hem_grid", 4096)
+    try:
+        assert mx.hem_workspace_bytes(1 << 20, 12) > base
+    finally:
+        mx.set_option("hem_grid", 0)
+    # beyond 2^18 buckets the coarse offsets of the refinement come on top
+    assert mx.hem_workspace_bytes(1 << 22, 19) > mx.hem_workspace_bytes(1 << 22, 18)
+
+
 def test_info_struct_mirrors_match_the_header(mx):
     # the C side asserts the same sizes (80 and 40 bytes)
     assert C.sizeof(mx._lib.MphfInfo) == 80 and C.sizeof(mx._lib.PeelInfo) == 40
