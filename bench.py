@@ -677,7 +677,7 @@ def served_leg(args, mx, torch, np, workloads) -> dict:
     log(f"[served] plain path, same {nreq} requests back to back: {plain_span:.2f} s = "
         f"{plain_rate / 1e9:.3f} G keys/s")
     # saturation estimate: everything submitted at once
-    srv = mx.Server(hbm_budget=args.serve_budget, slots=args.serve_slots)
+    srv = mx.Server(hbm_budget=args.serve_budget, slots=args.serve_slots, batch_max_keys=args.serve_lane_max)
     warm = [submit(srv, i) for i in range(min(8, nreq))]
     for t in warm:
         srv.wait(t)
@@ -760,6 +760,8 @@ def main() -> int:
     ap.add_argument("--serve-max", type=int, default=100_000_000)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget", type=int, default=64 << 30)
+    ap.add_argument("--serve-lane-max", type=int, default=1 << 17,
+                    help="requests of at most this many keys take the server's batching lane")
     ap.add_argument("--serve-rates", type=lambda s: [float(x) for x in s.split(",")], default=[0.5, 0.9])
     args = ap.parse_args()
     if args.summarize_kernel_stats:
