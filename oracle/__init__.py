@@ -41,6 +41,7 @@ def _bind(lib):
         "orc_digest_str": (None, [_u8p, C.c_uint64, C.c_uint64, _u64p, _u64p]),
         "orc_hash_str": (None, [_u8p, _u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u32p]),
         "orc_peel": (C.c_int, [_u32p, C.c_uint64, C.c_uint64, C.c_uint64, _u32p, _u32p, _u8p, _u8p, _u64p]),
+        "orc_peel_r": (C.c_int, [_u32p, C.c_uint64, C.c_uint64, C.c_uint32, _u32p, _u32p, _u8p, _u8p, _u64p]),
         "orc_assign": (C.c_int, [_u32p, C.c_uint64, C.c_uint64, _u32p, _u32p, _u8p, _u8p]),
         "orc_pack_rank": (None, [_u8p, C.c_uint64, _u64p, _u64p]),
         "orc_lookup_u64": (None, [_u64p, _u64p, C.c_uint64, C.c_uint64, _u64p, C.c_uint64, _u64p]),
@@ -140,6 +141,21 @@ class Oracle:
         e = edges if n else np.zeros((1, 3), np.uint32)
         rc = self.lib.orc_peel(_p(e, _u32p), n, m, part_size, _p(order, _u32p), _p(rnd, _u32p),
                                _p(core, _u8p), _p(hinge, _u8p), _p(info, _u64p))
+        return int(rc), dict(order=order, round=rnd, core_mask=core, hinge=hinge,
+                             n_peeled=int(info[0]), n_rounds=int(info[1]), max_degree=int(info[2]))
+
+    def peel_r(self, edges: np.ndarray, m: int, r: int):
+        """r-hypergraph peel (2 <= r <= 8): (status, dict as peel)."""
+        edges = np.ascontiguousarray(edges, dtype=np.uint32).reshape(-1, r)
+        n = edges.shape[0]
+        order = np.empty(n, np.uint32)
+        rnd = np.empty(n, np.uint32)
+        core = np.empty(n, np.uint8)
+        hinge = np.empty(n, np.uint8)
+        info = np.zeros(3, np.uint64)
+        e = edges if n else np.zeros((1, r), np.uint32)
+        rc = self.lib.orc_peel_r(_p(e, _u32p), n, m, r, _p(order, _u32p), _p(rnd, _u32p), _p(core, _u8p),
+                                 _p(hinge, _u8p), _p(info, _u64p))
         return int(rc), dict(order=order, round=rnd, core_mask=core, hinge=hinge,
                              n_peeled=int(info[0]), n_rounds=int(info[1]), max_degree=int(info[2]))
 

@@ -751,3 +751,127 @@ void orc_hem_lookup(const uint64_t* sigs, uint64_t n, uint32_t k, const uint64_t
     for (uint64_t i = 0; i < n; i++)
         out[i] = orc_hem_eval(sigs[i], k, bucket_off, code_off, rank_off, seeds, codes, rank, gnum, gden);
 }
+
+/* ------------------------------------------------------------------------------------------
+ * Peeling of an r-hypergraph, 2 <= r <= 8 (Section 2 defines r-hypergraphs; the paper works
+ * with r = 3 and notes the generalization is direct).  The same definitions as orc_peel on a
+ * generic edge list: edge e is edges[r*e .. r*e + r), a labelled incidence record per vertex
+ * (degree and XOR of incident edge ids, Section 4.1), synchronous rounds (Section 4.2) whose
+ * layer is every edge holding a vertex of degree 1 at the round's start, the hinge the lowest
+ * tuple position among those vertices, and the canonical order (by round, ascending id inside
+ * a round, the 2-core edges last in ascending id).  Statuses as orc_peel.
+ * ------------------------------------------------------------------------------------------ */
+int orc_peel_r(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t r, uint32_t* order, uint32_t* round,
+               uint8_t* core_mask, uint8_t* hinge_out, uint64_t* info)
+{
+    if (r < 2 || r > 8 || n > 0xFFFFFFFFull || m > 0x100000000ull)
+        return ORC_EINVAL;
+    for (uint64_t e = 0; e < n; e++) {
+        const uint32_t* t = edges + (uint64_t)r * e;
+        for (uint32_t a = 0; a < r; a++) {
+            if (t[a] >= m)
+                return ORC_EINVAL;
+            for (uint32_t b = a + 1; b < r; b++)
+                if (t[a] == t[b])
+                    return ORC_EINVAL;
+        }
+    }
+    uint32_t* deg = calloc(m ? m : 1, sizeof(uint32_t));
+    uint32_t* lab = calloc(m ? m : 1, sizeof(uint32_t));
+    uint8_t* hinge = malloc(n ? n : 1);
+    uint32_t* frontier = malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* next = malloc((m ? m : 1) * sizeof(uint32_t));
+    uint32_t* layer = malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!deg || !lab || !hinge || !frontier || !next || !layer) {
+        free(deg); free(lab); free(hinge); free(frontier); free(next); free(layer);
+        return ORC_ENOMEM;
+    }
+    uint32_t maxdeg = 0;
+    for (uint64_t e = 0; e < n; e++)
+        for (uint32_t k = 0; k < r; k++) {
+            uint32_t v = edges[(uint64_t)r * e + k];
+            deg[v] += 1;
+            lab[v] = lab[v] ^ (uint32_t)e;
+            if (deg[v] > maxdeg)
+                maxdeg = deg[v];
+        }
+    if (ORC_MAX_DEGREE < maxdeg) {  /* some degree above the limit */
+        free(deg); free(lab); free(hinge); free(frontier); free(next); free(layer);
+        if (info) { info[0] = 0; info[1] = 0; info[2] = maxdeg; }
+        return ORC_ERANGE;
+    }
+    for (uint64_t e = 0; e < n; e++) {
+        round[e] = ORC_NONE;
+        hinge[e] = 0xFF;
+    }
+    uint64_t nf = 0;
+    for (uint64_t v = 0; v < m; v++)
+        if (deg[v] == 1)
+            frontier[nf++] = (uint32_t)v;
+    uint32_t rd = 0;
+    uint64_t peeled = 0;
+    for (;;) {
+        /* retrieve at every vertex of degree 1 at the round's start (no mutation) */
+        uint64_t nl = 0;
+        for (uint64_t i = 0; i < nf; i++) {
+            uint32_t v = frontier[i];
+            if (deg[v] != 1)  /* no longer of degree 1 */
+                continue;
+            uint32_t e = lab[v];
+            uint8_t k = 0;
+            while (edges[(uint64_t)r * e + k] != v)
+                k++;
+            if (round[e] == ORC_NONE) {
+                round[e] = rd;
+                hinge[e] = k;
+                layer[nl++] = e;
+            } else if (hinge[e] > k) {  /* a lower position also found it */
+                hinge[e] = k;
+            }
+        }
+        if (nl == 0)
+            break;
+        /* delete every layer edge at all of its r vertices */
+        uint64_t nn = 0;
+        for (uint64_t i = 0; i < nl; i++) {
+            uint32_t e = layer[i];
+            for (uint32_t k = 0; k < r; k++) {
+                uint32_t u = edges[(uint64_t)r * e + k];
+                deg[u] -= 1;
+                lab[u] ^= e;
+                if (deg[u] == 1)  /* a candidate of the next round */
+                    next[nn++] = u;
+            }
+        }
+        peeled += nl;
+        uint32_t* tmp = frontier;
+        frontier = next;
+        next = tmp;
+        nf = nn;
+        rd += 1;
+    }
+    uint64_t* start = calloc((uint64_t)rd + 2, sizeof(uint64_t));
+    if (!start) {
+        free(deg); free(lab); free(hinge); free(frontier); free(next); free(layer);
+        return ORC_ENOMEM;
+    }
+    for (uint64_t e = 0; e < n; e++)
+        start[(round[e] == ORC_NONE ? rd : round[e]) + 1] += 1;
+    for (uint64_t j = 0; j <= rd; j++)
+        start[j + 1] += start[j];
+    for (uint64_t e = 0; e < n; e++)
+        order[start[round[e] == ORC_NONE ? rd : round[e]]++] = (uint32_t)e;
+    for (uint64_t e = 0; e < n; e++) {
+        core_mask[e] = round[e] == ORC_NONE ? 1 : 0;
+        if (hinge_out)
+            hinge_out[e] = hinge[e];
+    }
+    if (info) {
+        info[0] = peeled;
+        info[1] = rd;
+        info[2] = maxdeg;
+    }
+    free(start);
+    free(deg); free(lab); free(hinge); free(frontier); free(next); free(layer);
+    return ORC_OK;
+}

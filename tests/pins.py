@@ -48,7 +48,7 @@ def bf_sync_peel(edges: np.ndarray, m: int):
     """Synchronous layered peel by definition: every round recompute degrees over the edges
     still present; an edge leaves in this round iff one of its vertices has degree 1; its
     hinge is the lowest position holding such a vertex."""
-    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
+    edges = _as_tuples(edges)
     n = len(edges)
     alive = np.ones(n, bool)
     rnd = np.full(n, NONE, np.uint32)
@@ -67,6 +67,12 @@ def bf_sync_peel(edges: np.ndarray, m: int):
     key = np.where(rnd == NONE, r, rnd).astype(np.int64)
     order = np.lexsort((np.arange(n), key)).astype(np.uint32)
     return dict(round=rnd, hinge=hinge, core_mask=alive.astype(np.uint8), order=order, n_rounds=r)
+
+
+def _as_tuples(edges) -> np.ndarray:
+    """Edges as an (n, r) int64 array: a 2-D input keeps its width, a flat one is read as r = 3."""
+    a = np.asarray(edges, dtype=np.int64)
+    return a if a.ndim == 2 else a.reshape(-1, 3)
 
 
 def bf_max_core(edges) -> set:
@@ -103,22 +109,22 @@ def random_generic(n, m, rng):
 def peeling_order_ok(edges, order, hinge, n_peeled) -> bool:
     """Definition of a peeling order (Section 1): when an edge is removed, its hinge vertex has
     degree 1, i.e. it occurs in no edge placed later (core edges sit after every peeled one)."""
-    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
-    n = len(edges)
+    edges = _as_tuples(edges)
+    n, r = edges.shape
     if n == 0:
         return True
     pos = np.empty(n, np.int64)
     pos[np.asarray(order, dtype=np.int64)] = np.arange(n)
     m = int(edges.max()) + 1
     last = np.full(m, -1, np.int64)
-    np.maximum.at(last, edges.ravel(), np.repeat(pos, 3))
+    np.maximum.at(last, edges.ravel(), np.repeat(pos, r))
     peeled = np.asarray(order[:n_peeled], dtype=np.int64)
     h = edges[peeled, np.asarray(hinge, dtype=np.int64)[peeled]]
     return bool(np.all(last[h] == pos[peeled]))
 
 
 def core_min_degree_ok(edges, core_mask) -> bool:
-    edges = np.asarray(edges, dtype=np.int64).reshape(-1, 3)
+    edges = _as_tuples(edges)
     c = edges[np.asarray(core_mask, bool)]
     if len(c) == 0:
         return True
@@ -133,12 +139,25 @@ def unpack_codes(words, m):
     return c[:m]
 
 
-def core_fraction_closed_form(gamma: float) -> float:
-    lam = 3.0 / gamma
+def core_fraction_closed_form(gamma: float, r: int = 3) -> float:
+    """Fraction of the edges in the 2-core of a random r-hypergraph with gamma vertices per edge:
+    p^r, p the largest root of p = 1 - exp(-(r/gamma) p^(r-1)) (Molloy's CORE analysis)."""
+    lam = r / gamma
     p = 1.0
     for _ in range(100000):
-        p = 1.0 - math.exp(-lam * p * p)
-    return p ** 3
+        p = 1.0 - math.exp(-lam * p ** (r - 1))
+    return p ** r
+
+
+def random_uniform_r(n, m, r, rng):
+    """n edges of r distinct vertices below m (rows with a repeat are drawn again)."""
+    e = rng.integers(0, m, size=(n, r), dtype=np.int64)
+    while True:
+        s = np.sort(e, axis=1)
+        bad = (s[:, 1:] == s[:, :-1]).any(axis=1)
+        if not bad.any():
+            return e.astype(np.uint32)
+        e[bad] = rng.integers(0, m, size=(int(bad.sum()), r), dtype=np.int64)
 
 
 # --------------------------------------------------------------------------------------------
@@ -361,6 +380,61 @@ def pin_errors(o) -> list:
     return bad
 
 
+def pin_general_r(o, seed=9) -> list:
+    """r-hypergraphs, 2 <= r <= 8: tiny inputs against the exhaustive maximum 2-core and the
+    definition-direct synchronous peel; r = 3 against the tripartite-free r = 3 peel; the
+    peeling-order invariants at r = 5; the 2-core fraction at r = 4 against its closed form on
+    both sides of the threshold (c*_4 = 0.772 edges per vertex, gamma* = 1.295); the errors."""
+    bad = []
+    rng = np.random.default_rng(seed)
+    for r in (2, 4, 5, 8):
+        for trial in range(25):
+            n = int(rng.integers(1, 11))
+            m = int(rng.integers(r, r + 7))
+            edges = random_uniform_r(n, m, r, rng)
+            rc, got = o.peel_r(edges, m, r)
+            if rc != 0:
+                bad.append(f"r={r} trial {trial}: status {rc}")
+                continue
+            if set(np.nonzero(got["core_mask"])[0].tolist()) != bf_max_core(edges):
+                bad.append(f"r={r} trial {trial}: core differs from the maximum 2-core")
+            b = bf_sync_peel(edges, m)
+            peeled = b["core_mask"] == 0
+            if not (np.array_equal(got["round"], b["round"]) and np.array_equal(got["order"], b["order"])
+                    and np.array_equal(got["hinge"][peeled], b["hinge"][peeled])):
+                bad.append(f"r={r} trial {trial}: differs from the synchronous peel by definition")
+    edges = random_uniform_r(3000, 3600, 3, rng)
+    rc3, a = o.peel(edges, 3600, 0)
+    rcr, b = o.peel_r(edges, 3600, 3)
+    if rc3 != rcr or any(not np.array_equal(a[k], b[k]) for k in ("order", "round", "core_mask", "hinge")):
+        bad.append("r = 3 differs from the three-vertex peel")
+    edges = random_uniform_r(20_000, 30_000, 5, rng)
+    rc, got = o.peel_r(edges, 30_000, 5)
+    if rc != 0 or not peeling_order_ok(edges, got["order"], got["hinge"], got["n_peeled"]):
+        bad.append("r = 5: not a peeling order")
+    if not core_min_degree_ok(edges, got["core_mask"]):
+        bad.append("r = 5: a core vertex of degree below 2")
+    n = 200_000
+    for gamma in (1.20, 1.40):
+        m = int(gamma * n)
+        rc, got = o.peel_r(random_uniform_r(n, m, 4, rng), m, 4)
+        frac = 1.0 - got["n_peeled"] / n
+        want = core_fraction_closed_form(gamma, 4)
+        if rc != 0 or abs(frac - want) > 0.01:
+            bad.append(f"r = 4, gamma = {gamma}: core fraction {frac:.4f}, closed form {want:.4f}")
+    star = np.array([[0, 1 + i] for i in range(256)], np.uint32)
+    if o.peel_r(star, 257, 2)[0] != -2 or o.peel_r(star[:255], 256, 2)[0] != 0:
+        bad.append("r = 2: degree 256 must give ERANGE and 255 not")
+    if o.peel_r(np.array([[0, 1, 1, 2]], np.uint32), 3, 4)[0] != -1:
+        bad.append("r = 4: a repeated vertex must give EINVAL")
+    if o.peel_r(np.array([[0, 5]], np.uint32), 5, 2)[0] != -1:
+        bad.append("r = 2: a vertex id >= m must give EINVAL")
+    for r in (1, 9):
+        if o.peel_r(np.zeros((1, r), np.uint32), 10, r)[0] != -1:
+            bad.append(f"r = {r} must give EINVAL")
+    return bad
+
+
 def pin_threshold(o, n=200_000) -> list:
     """Section 1: above c_3 ~ 1.221 the 2-core is empty w.h.p.; below it the core holds the
     fraction p^3 of the edges (p the largest root of p = 1 - exp(-(3/gamma) p^2))."""
@@ -530,7 +604,7 @@ def pin_hem(o) -> list:
 
 ALL_PINS = [pin_splitmix, pin_hash_closed_form, pin_part_size, pin_worked_examples,
             pin_bruteforce_tripartite, pin_bruteforce_generic, pin_invariants, pin_mphf, pin_errors,
-            pin_string_digest, pin_static_function, pin_hem]
+            pin_string_digest, pin_static_function, pin_hem, pin_general_r]
 
 
 def run_all(o, pins=None) -> list:

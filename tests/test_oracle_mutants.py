@@ -43,6 +43,10 @@ MUTANTS = {
     "hem bucket key not swapped": ("return (sig << 32) | (sig >> 32);", "return sig;"),
     "hem bucket offset dropped": ("return bucket_off[b] + f;", "return f;"),
     "hem bucket from the low bits": ("uint64_t b = k ? sig >> (64 - k) : 0;", "uint64_t b = k ? sig & ((1ull << k) - 1) : 0;"),
+    "general r hinge takes the higher position": ("} else if (hinge[e] > k) {", "} else if (hinge[e] < k) {"),
+    "general r deletes skip the last vertex": ("            for (uint32_t k = 0; k < r; k++) {\n                uint32_t u = edges[(uint64_t)r * e + k];",
+                                               "            for (uint32_t k = 0; k + 1 < r; k++) {\n                uint32_t u = edges[(uint64_t)r * e + k];"),
+    "general r edges read with stride 3": ("            uint32_t v = edges[(uint64_t)r * e + k];", "            uint32_t v = edges[(uint64_t)3 * e + k];"),
 }
 
 
