@@ -114,6 +114,18 @@ MPHX_API int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* 
               uint8_t* core_mask, uint8_t* hinge, void* ws, size_t ws_bytes, void* stream,
               mphx_peel_info* info /* host, may be NULL */);
 
+/* The same peel for r-hypergraphs, 2 <= r <= 8 (Section 2 defines r-hypergraphs; the paper
+ * works with r = 3 and notes that the generalization is direct): edges (dev) n x r row-major
+ * uint32 vertex ids, each < m, r distinct ids per edge; hinge[e] in 0..r-1.  Same outputs,
+ * conditions and errors as mphx_peel, plus MPHX_EINVAL for r outside [2, 8];
+ * mphx_peel_r_workspace_bytes returns 0 for such r.  For r >= 3 a random r-hypergraph with
+ * more than 1/c*_r vertices per edge peels completely with high probability (c*_3 = 0.818,
+ * c*_4 = 0.772). */
+MPHX_API size_t mphx_peel_r_workspace_bytes(uint64_t n, uint64_t m, uint32_t r);
+MPHX_API int mphx_peel_r(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t r, uint32_t* order,
+                         uint32_t* round, uint8_t* core_mask, uint8_t* hinge, void* ws, size_t ws_bytes,
+                         void* stream, mphx_peel_info* info);
+
 /* ---------------------------------------------------------------------------------------
  * MWHC minimal perfect hash build (Section 3): hash the keys to a tripartite 3-hypergraph,
  * peel it (retrying with seed+1, seed+2, ... while a 2-core remains, up to max_tries),

@@ -47,6 +47,8 @@ _SIGS = {
     "mphx_part_size": (_u64, [_u64, _u32, _u32]),
     "mphx_peel_workspace_bytes": (_sz, [_u64, _u64]),
     "mphx_peel": (_i32, [_vp, _u64, _u64, _vp, _vp, _vp, _vp, _vp, _sz, _vp, C.POINTER(PeelInfo)]),
+    "mphx_peel_r_workspace_bytes": (_sz, [_u64, _u64, _u32]),
+    "mphx_peel_r": (_i32, [_vp, _u64, _u64, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp, C.POINTER(PeelInfo)]),
     "mphx_mphf_workspace_bytes": (_sz, [_u64, _u32, _u32, _i32]),
     "mphx_mphf_build_u64": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
     "mphx_mphf_build_str": (_i32, [_vp, _vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp,
@@ -195,6 +197,28 @@ def peel(edges: torch.Tensor, m: int, with_hinge: bool = True) -> dict:
     info = PeelInfo()
     rc = lib().mphx_peel(_ptr(edges), n, m, _ptr(order), _ptr(rnd), _ptr(core), _ptr(hinge), _ptr(ws), ws.numel(),
                          _stream(dev), C.byref(info))
+    if rc:
+        _err(rc)
+    return dict(order=order, round=rnd, core_mask=core, hinge=hinge, n_peeled=int(info.n_peeled),
+                n_rounds=int(info.n_rounds), frontier_total=int(info.frontier_total), claims=int(info.claims),
+                frontier0=int(info.frontier0))
+
+
+def peel_r(edges: torch.Tensor, m: int, with_hinge: bool = True) -> dict:
+    """Layered peel of an n x r uint32 edge list (device), 2 <= r <= 8; outputs as peel."""
+    if edges.dim() != 2 or not 2 <= edges.shape[1] <= 8:
+        raise ValueError("edges must be n x r with 2 <= r <= 8")
+    _check(edges, torch.int32, "edges")
+    n, r = edges.shape
+    dev = edges.device
+    order = torch.empty(n, dtype=torch.int32, device=dev)
+    rnd = torch.empty(n, dtype=torch.int32, device=dev)
+    core = torch.empty(n, dtype=torch.uint8, device=dev)
+    hinge = torch.empty(n, dtype=torch.uint8, device=dev) if with_hinge else None
+    ws = _workspace(lib().mphx_peel_r_workspace_bytes(n, m, r), dev)
+    info = PeelInfo()
+    rc = lib().mphx_peel_r(_ptr(edges), n, m, r, _ptr(order), _ptr(rnd), _ptr(core), _ptr(hinge), _ptr(ws),
+                           ws.numel(), _stream(dev), C.byref(info))
     if rc:
         _err(rc)
     return dict(order=order, round=rnd, core_mask=core, hinge=hinge, n_peeled=int(info.n_peeled),

@@ -346,7 +346,7 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
     return MPHX_OK;
 }
 
-int check_build_errors(Ctrl* dctrl, uint64_t n, hipStream_t s, uint64_t& first_front)
+int check_build_errors(Ctrl* dctrl, uint64_t n, hipStream_t s, uint64_t& first_front, uint32_t r = 3)
 {
     Ctrl h;
     int rc = read_ctrl(dctrl, h, s);
@@ -354,10 +354,41 @@ int check_build_errors(Ctrl* dctrl, uint64_t n, hipStream_t s, uint64_t& first_f
     first_front = h.ftail;
     if (h.err & kErrBadEdge)
         return fail(MPHX_EINVAL, "edge with a vertex id >= m or a repeated vertex");
-    // every degree field at most 255 and their total exactly 3n: no field overflowed
-    if ((h.err & kErrDegree) || h.degsum != 3 * n)
+    // every degree field at most 255 and their total exactly r n: no field overflowed
+    if ((h.err & kErrDegree) || h.degsum != (uint64_t)r * n)
         return fail(MPHX_ERANGE, "a vertex has degree above %u", MPHX_MAX_DEGREE);
     return MPHX_OK;
+}
+
+// The round loop of an r-hypergraph peel: as run_rounds, with the r-vertex apply.
+int run_rounds_r(PeelState& st, uint32_t r, Ctrl& h, uint64_t* peeled, hipStream_t s)
+{
+    uint32_t rd = 0;
+    uint32_t batch = (uint32_t)std::max(1, g_opt.round_batch.load());
+    unsigned long long next_layer = 0;
+    HIP_TRY(hipMemcpyAsync(&next_layer, st.lcount, sizeof next_layer, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (;;) {
+        uint64_t upto = std::min<uint64_t>((uint64_t)rd + batch, st.rcap);
+        st.grid_cap = auto_grid(next_layer);
+        for (; rd < upto; rd++) {
+            Timed t(PH_APPLY, s);
+            HIP_TRY(launch_apply_r(st, r, rd, s));
+        }
+        HIP_TRY(hipMemcpyAsync(&next_layer, st.lcount + rd, sizeof next_layer, hipMemcpyDeviceToHost, s));
+        int rc = read_ctrl(st.ctrl, h, s);
+        if (rc) return rc;
+        if (h.nrounds != 0xFFFFFFFFu) {
+            uint64_t p = 0;
+            HIP_TRY(hipMemcpyAsync(&p, st.lstart + h.nrounds, sizeof p, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            *peeled = p;
+            return MPHX_OK;
+        }
+        if (rd >= st.rcap)
+            return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
+        batch = std::min<uint32_t>(batch * 2, 64);
+    }
 }
 
 }  // namespace
@@ -514,6 +545,81 @@ int mphx_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t* order, ui
     {
         Timed t(PH_ORDER, s);
         HIP_TRY(launch_peel_finalize(L.state, n, round, core_mask, hinge, s));
+        HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.ids, L.tilehist, L.scan, L.scan_bytes, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    g_timers.harvest();
+    if (info) {
+        info->n_peeled = peeled;
+        info->n_rounds = h.nrounds;
+        info->frontier_total = h.ftail;
+        info->claims = h.claims;
+        info->frontier0 = f0;
+    }
+    return MPHX_OK;
+}
+
+size_t mphx_peel_r_workspace_bytes(uint64_t n, uint64_t m, uint32_t r)
+{
+    if (r < 2 || r > 8) return 0;
+    return mphx_peel_workspace_bytes(n, m);
+}
+
+int mphx_peel_r(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t r, uint32_t* order, uint32_t* round,
+                uint8_t* core_mask, uint8_t* hinge, void* ws, size_t ws_bytes, void* stream, mphx_peel_info* info)
+{
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (r < 2 || r > 8) return fail(MPHX_EINVAL, "r must be in [2, 8]");
+    if (n >= 0xFFFFFFFFull || m > 0x100000000ull)
+        return fail(MPHX_EINVAL, "n must be < 2^32 - 1 and m <= 2^32");
+    if (n > 0 && (!edges || !order || !round || !core_mask))
+        return fail(MPHX_EINVAL, "null pointer argument");
+    if (!ws || !aligned256(ws))
+        return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < mphx_peel_r_workspace_bytes(n, m, r))
+        return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, mphx_peel_r_workspace_bytes(n, m, r));
+    if (info) memset(info, 0, sizeof *info);
+    if (n == 0) return MPHX_OK;
+
+    Carve c(ws);
+    PeelLayout L;
+    layout_peel(c, n, m, L);
+    PeelState st{};
+    st.edges = edges;
+    st.n = n;
+    st.m = m;
+    st.tripartite = false;
+    st.rec = L.rec;
+    st.slots = L.slots;
+    st.state = L.state;
+    st.lstart = L.lstart;
+    st.lcount = L.lcount;
+    st.ctrl = L.ctrl;
+    st.rcap = round_cap(n);
+
+    HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
+    HIP_TRY(launch_fill_u32(L.state, n, kUnclaimed, s));
+    HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));
+    HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
+    {
+        Timed t(PH_BUILD, s);
+        HIP_TRY(launch_edges_build_r(edges, n, m, r, L.rec, L.ctrl, s));
+    }
+    {
+        Timed t(PH_FRONTIER, s);
+        HIP_TRY(launch_round0_r(st, r, s));
+    }
+    uint64_t f0 = 0;
+    int rc = check_build_errors(L.ctrl, n, s, f0, r);
+    if (rc) return rc;
+    Ctrl h;
+    uint64_t peeled = 0;
+    rc = run_rounds_r(st, r, h, &peeled, s);
+    if (rc) return rc;
+    {
+        Timed t(PH_ORDER, s);
+        HIP_TRY(launch_peel_finalize_r(L.state, n, round, core_mask, hinge, s));
         HIP_TRY(launch_order_sort(round, n, h.nrounds, order, L.ids, L.tilehist, L.scan, L.scan_bytes, s));
     }
     HIP_TRY(hipStreamSynchronize(s));

@@ -197,6 +197,15 @@ hipError_t launch_lookup_str_words(const uint64_t* codes, const uint64_t* rank, 
                                    hipStream_t s);
 hipError_t launch_bijection(const uint64_t* vals, uint64_t n, uint32_t* bitmap, Ctrl* ctrl, hipStream_t s);
 
+// r-hypergraph peel, 2 <= r <= 8 (peel.hip): edge lists of r vertices each; edge states are
+// (round << 3) | hinge position; hipErrorInvalidValue for r outside [2, 8].
+hipError_t launch_edges_build_r(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t r, uint64_t* rec, Ctrl* ctrl,
+                                hipStream_t s);
+hipError_t launch_round0_r(const PeelState& st, uint32_t r, hipStream_t s);
+hipError_t launch_apply_r(const PeelState& st, uint32_t r, uint32_t round, hipStream_t s);
+hipError_t launch_peel_finalize_r(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask,
+                                  uint8_t* hinge, hipStream_t s);
+
 // Out-of-core HEM: a chunk's signature records grouped by their top k - 8 bits into out (aux:
 // hem_aux_bytes(cn, k)), its NH + 1 group starts copied to host memory; runs of records
 // gathered into a batch buffer; string offsets shifted down by base.

@@ -538,6 +538,225 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// r-hypergraphs, 2 <= r <= 8 (generic edge lists of r vertices each).  The same records,
+// rounds and atomic claims as the three-vertex generic peel; an edge state is
+// (round << 3) | hinge position, three bits holding positions below 8.
+// ------------------------------------------------------------------------------------------
+template <int kR>
+__device__ __forceinline__ uint32_t position_r(const uint32_t* edges, uint32_t e, uint32_t v)
+{
+    const uint32_t* t = edges + (uint64_t)kR * e;
+    uint32_t k = 0;
+#pragma unroll
+    for (uint32_t q = 1; q < kR; q++)
+        if (t[q] == v)
+            k = q;
+    return k;
+}
+
+template <int kR>
+__global__ __launch_bounds__(256) void k_edges_build_r(const uint32_t* __restrict__ edges, uint64_t n, uint64_t m,
+                                                       uint64_t* __restrict__ rec, Ctrl* ctrl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        uint32_t t[kR];
+        bool bad = false;
+#pragma unroll
+        for (uint32_t q = 0; q < kR; q++) {
+            t[q] = edges[(uint64_t)kR * e + q];
+            bad = bad || t[q] >= m;
+        }
+#pragma unroll
+        for (uint32_t a = 0; a < kR; a++)
+#pragma unroll
+            for (uint32_t b = a + 1; b < kR; b++)
+                bad = bad || t[a] == t[b];
+        if (bad) {
+            atomicOr(&ctrl->err, kErrBadEdge);
+            continue;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kR; q++)
+            Rec::add(rec, t[q], (uint32_t)e);
+    }
+}
+
+// Round 0 as k_round0: degree-1 vertices claim their edges, the lowest position wins.
+template <int kR>
+__global__ __launch_bounds__(kPeelBlock) void k_round0_r(const uint64_t* __restrict__ rec, uint64_t m,
+                                                         const uint32_t* __restrict__ edges, uint64_t n,
+                                                         uint32_t* __restrict__ state, uint3* __restrict__ slots,
+                                                         unsigned long long* __restrict__ lcount, Ctrl* ctrl)
+{
+    __shared__ LayerAppender app;
+    __shared__ unsigned long long s_deg, s_ones;
+    if (threadIdx.x == 0)
+        s_deg = s_ones = 0;
+    app.init();
+    auto out = [slots](uint64_t i, uint32_t e) { slots[i].x = e; };
+    unsigned long long mydeg = 0, myones = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < m; base += stride) {
+        const uint64_t v = base + threadIdx.x;
+        bool first = false;
+        uint32_t e = 0;
+        if (v < m) {
+            const uint64_t x = rec[v];
+            const uint32_t d = Rec::deg(x);
+            mydeg += d;
+            if (d > kMaxDegree)
+                atomicOr(&ctrl->err, kErrDegree);
+            if (d == 1 && Rec::edge(x) < n) {
+                e = Rec::edge(x);
+                first = atomicMin(&state[e], position_r<kR>(edges, e, (uint32_t)v)) == kUnclaimed;
+                myones++;
+            }
+        }
+        app.push(first, e, false, 0u, &lcount[0], out);
+    }
+    app.flush(&lcount[0], out);
+    if (mydeg) atomicAdd(&s_deg, mydeg);
+    if (myones) atomicAdd(&s_ones, myones);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_deg) atomicAdd(&ctrl->degsum, s_deg);
+        if (s_ones) {
+            atomicAdd(&ctrl->ftail, s_ones);
+            atomicAdd(&ctrl->claims, s_ones);
+        }
+    }
+}
+
+// Round r: every layer edge is deleted at its r - 1 vertices other than the hinge; a vertex
+// taken to degree 1 claims its last edge for round r + 1 (lowest position wins, atomicMin).
+template <int kR>
+__global__ __launch_bounds__(kPeelBlock) void k_apply_r(uint64_t* __restrict__ rec, const uint32_t* __restrict__ edges,
+                                                        uint32_t* __restrict__ state, uint3* __restrict__ slots,
+                                                        uint64_t* __restrict__ lstart,
+                                                        unsigned long long* __restrict__ lcount, Ctrl* ctrl, uint32_t r)
+{
+    const uint64_t lo = lstart[r];
+    const uint64_t hi = lo + lcount[r];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        lstart[r + 1] = hi;
+        if (hi == lo)
+            atomicMin(&ctrl->nrounds, r);
+    }
+    if (lo + (uint64_t)blockIdx.x * blockDim.x >= hi)
+        return;  // whole block idle (uniform)
+    __shared__ LayerAppender app;
+    __shared__ unsigned long long s_push, s_claims;
+    if (threadIdx.x == 0)
+        s_push = s_claims = 0;
+    app.init();
+    auto out = [slots, hi](uint64_t j, uint32_t x) { slots[hi + j].x = x; };
+    unsigned long long mypush = 0, myclaims = 0;
+    const uint32_t rr = (r + 1) << 3;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = lo + (uint64_t)blockIdx.x * blockDim.x; base < hi; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        uint32_t e = 0, h = 0;
+        if (i < hi) {
+            e = slots[i].x;
+            h = state[e] & 7u;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < kR; q++) {
+            bool f = false;
+            uint32_t c = 0;
+            if (i < hi && q != h) {
+                const uint32_t v = edges[(uint64_t)kR * e + q];
+                const uint64_t old = Rec::del(rec, v, e);
+                if (Rec::deg(old) == 2) {
+                    c = (uint32_t)(Rec::edge(old) - e);
+                    const uint32_t o = atomicMin(&state[c], rr | position_r<kR>(edges, c, v));
+                    f = o == kUnclaimed;
+                    mypush++;
+                    myclaims += (f || (o >> 3) == r + 1) ? 1u : 0u;
+                }
+            }
+            app.push(f, c, false, 0u, &lcount[r + 1], out);
+        }
+    }
+    app.flush(&lcount[r + 1], out);
+    if (mypush) atomicAdd(&s_push, mypush);
+    if (myclaims) atomicAdd(&s_claims, myclaims);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_push) atomicAdd(&ctrl->ftail, s_push);
+        if (s_claims) atomicAdd(&ctrl->claims, s_claims);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_peel_finalize_r(const uint32_t* __restrict__ state, uint64_t n,
+                                                         uint32_t* __restrict__ round, uint8_t* __restrict__ core_mask,
+                                                         uint8_t* __restrict__ hinge)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        const uint32_t s = state[e];
+        const bool core = s == kUnclaimed;
+        round[e] = core ? kRoundCore : (s >> 3);
+        core_mask[e] = core ? 1 : 0;
+        if (hinge)
+            hinge[e] = core ? 0xFF : (uint8_t)(s & 7u);
+    }
+}
+
+#define MPHX_FOR_R(R, CALL) \
+    switch (R) {            \
+    case 2: CALL(2); break; \
+    case 3: CALL(3); break; \
+    case 4: CALL(4); break; \
+    case 5: CALL(5); break; \
+    case 6: CALL(6); break; \
+    case 7: CALL(7); break; \
+    case 8: CALL(8); break; \
+    default: return hipErrorInvalidValue; \
+    }
+
+hipError_t launch_edges_build_r(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t r, uint64_t* rec, Ctrl* ctrl,
+                                hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+#define MPHX_CALL(K) k_edges_build_r<K><<<grid_for(n, 8192), 256, 0, s>>>(edges, n, m, rec, ctrl)
+    MPHX_FOR_R(r, MPHX_CALL)
+#undef MPHX_CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_round0_r(const PeelState& st, uint32_t r, hipStream_t s)
+{
+    if (st.m == 0) return hipSuccess;
+    const unsigned g = grid_for(st.m, 8192);
+#define MPHX_CALL(K) \
+    k_round0_r<K><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.n, st.state, st.slots, st.lcount, st.ctrl)
+    MPHX_FOR_R(r, MPHX_CALL)
+#undef MPHX_CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_r(const PeelState& st, uint32_t r, uint32_t round, hipStream_t s)
+{
+    const unsigned g = grid_for(st.n, st.grid_cap);
+#define MPHX_CALL(K) \
+    k_apply_r<K><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, st.ctrl, round)
+    MPHX_FOR_R(r, MPHX_CALL)
+#undef MPHX_CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_peel_finalize_r(const uint32_t* state, uint64_t n, uint32_t* round, uint8_t* core_mask,
+                                  uint8_t* hinge, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_peel_finalize_r<<<grid_for(n, 8192), 256, 0, s>>>(state, n, round, core_mask, hinge);
+    return hipGetLastError();
+}
+#undef MPHX_FOR_R
+
 hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, ApplyMode mode, hipStream_t s)
 {
     unsigned g = grid_for(st.n, st.grid_cap);
