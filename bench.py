@@ -227,6 +227,45 @@ def summarize_kernel_stats(csv_path: str, out_path: str, title: str, command: st
     return 0
 
 
+def peel_r_leg(args, mx, torch) -> dict:
+    """The generic peel of random r-uniform hypergraphs (Section 2's r-hypergraphs) with 2^27
+    edges, device-generated, vertices per edge just above each r's peeling threshold 1/c*_r
+    (1.23 for r = 3 above 1.222, 1.33 for r = 4 above 1.295, 1.45 for r = 5 above 1.424):
+    whole peels (records, rounds, canonical order) timed."""
+    dev = torch.device("cuda:0")
+    n = args.peel_r_n
+    rows = {}
+    for r, gamma in ((3, 1.23), (4, 1.33), (5, 1.45)):
+        m = int(gamma * n)
+        g = torch.Generator(device=dev)
+        g.manual_seed(r)
+        edges = torch.randint(0, m, (n, r), dtype=torch.int64, device=dev, generator=g)
+        while True:  # r distinct vertices per edge: redraw the rows with a repeat
+            srt = torch.sort(edges, dim=1).values
+            bad = (srt[:, 1:] == srt[:, :-1]).any(dim=1)
+            nb = int(bad.sum().item())
+            if nb == 0:
+                break
+            edges[bad] = torch.randint(0, m, (nb, r), dtype=torch.int64, device=dev, generator=g)
+        e32 = edges.to(torch.int32)
+        del edges, srt, bad
+        got = mx.peel_r(e32, m)
+        torch.cuda.synchronize()
+        steps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            got = mx.peel_r(e32, m)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        rows[f"r{r}"] = dict(edges=n, vertices=m, ms_per_peel=round(sec * 1e3, 3), edges_per_s=round(n / sec, 1),
+                             rounds=got["n_rounds"], peeled=got["n_peeled"])
+        log(f"[peel_r] r={r} n={n} m={m}: {sec * 1e3:.1f} ms/peel, {n / sec / 1e9:.3f} G edges/s, "
+            f"{got['n_rounds']} rounds, {got['n_peeled']} peeled")
+        del e32, got
+        torch.cuda.empty_cache()
+    return dict(workload=f"peel_r_uniform_n{n}", rows=rows)
+
+
 def batched_leg(args, mx, torch, np, workloads) -> dict:
     """65,536 independent u64 buckets, sizes floor(100 * 10^(4u)), one captured persistent
     launch per step; beside it the plain path on a sample of the same buckets."""
@@ -736,11 +775,12 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
-                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host")
+                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host, peel_r")
     ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
                     help="bucket-count exponents of the hem leg")
     ap.add_argument("--hem-tune", type=lambda s: s.split(","), default=["1024x0"],
                     help="batched-kernel block x grid shapes of the hem leg (grid 0 = one per compute unit)")
+    ap.add_argument("--peel-r-n", type=int, default=1 << 27, help="edges of the peel_r leg")
     ap.add_argument("--hem-host-n", type=int, default=1 << 34, help="keys of the hem_host leg (host memory)")
     ap.add_argument("--hem-host-k", type=int, default=20)
     ap.add_argument("--hem-host-chunk", type=int, default=1 << 27, help="keys per host-to-device chunk")
@@ -801,6 +841,8 @@ def main() -> int:
             side["served"] = served_leg(args, mx, torch, np, workloads)
         if "hem_host" in legs:
             side["hem_host"] = hem_host_leg(args, mx, torch)
+        if "peel_r" in legs:
+            side["peel_r"] = peel_r_leg(args, mx, torch)
         print(json.dumps(side), flush=True)
         return 0
 
