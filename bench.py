@@ -774,6 +774,8 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-placement-probe", action="store_true",
+                    help="time the first allocation's physical layout, without probing the other")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
                     help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host, peel_r")
     ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
@@ -847,26 +849,68 @@ def main() -> int:
         return 0
 
     # ---- inputs, generated on the device before timing --------------------------------------
-    t0 = time.perf_counter()
-    if cfg["kind"] == "u64":
-        keys = mx.gen_keys_u64(n, gen_seed=0, device=dev)
-        key_bytes = 8 * n
-        kind = mx.KEYS_U64
-    else:
-        q = torch.from_numpy(workloads.quantile_table().view(np.int16)).to(dev)
-        data, offs = mx.gen_str_keys(n, q, gen_seed=0, device=dev)
-        key_bytes = int(offs[-1].item())
-        kind = mx.KEYS_STR
-    torch.cuda.synchronize()
-    log(f"[bench] {cfg['workload']} n={n}: keys generated on device in {time.perf_counter() - t0:.1f} s "
-        f"({key_bytes / 1e9:.2f} GB of key bytes)")
-
+    # The driver places the ~270 GB of keys and workspace in one of two physical layouts that
+    # alternate from one full allocation to the next; in one of them the random-access phases
+    # (apply, the record build) run about 20 % slower.  Unless --no-placement-probe, one build
+    # is timed in the first layout, everything is released and allocated again (the other
+    # layout), one build timed there, and if it was slower the allocation is repeated once
+    # more (back to the first layout).  Both probe times are reported; the timed steps run on
+    # the chosen allocation and are the same builds either way.
     P = mx.part_size(n, gamma)
     m = 3 * P
-    ws = torch.empty(mx.mphf_workspace_bytes(n, gamma, kind), dtype=torch.uint8, device=dev)
-    codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
-    rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
-    log(f"[bench] workspace {ws.numel() / 1e9:.2f} GB, device memory in use "
+    kind = mx.KEYS_U64 if cfg["kind"] == "u64" else mx.KEYS_STR
+    qtab = None if kind == mx.KEYS_U64 else torch.from_numpy(workloads.quantile_table().view(np.int16)).to(dev)
+    bufs = {}
+
+    def allocate():
+        t0 = time.perf_counter()
+        if kind == mx.KEYS_U64:
+            bufs["keys"] = mx.gen_keys_u64(n, gen_seed=0, device=dev)
+        else:
+            bufs["data"], bufs["offs"] = mx.gen_str_keys(n, qtab, gen_seed=0, device=dev)
+        bufs["ws"] = torch.empty(mx.mphf_workspace_bytes(n, gamma, kind), dtype=torch.uint8, device=dev)
+        bufs["codes"] = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
+        bufs["rank"] = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def build_once():
+        out = (bufs["codes"], bufs["rank"])
+        if kind == mx.KEYS_U64:
+            return mx.mphf_build_u64(bufs["keys"], seed=0, gamma=gamma, ws=bufs["ws"], out=out)
+        return mx.mphf_build_str(bufs["data"], bufs["offs"], seed=0, gamma=gamma, ws=bufs["ws"], out=out)
+
+    def probe_ms():  # apply + build phase time of one build
+        mx.phase_times(reset=True)
+        build_once()
+        torch.cuda.synchronize()
+        ph = mx.phase_times(reset=True)
+        return ph["apply"][0] + ph["build"][0]
+
+    mx.set_option("timing", 1)
+    t_alloc = allocate()
+    placement = None
+    if not args.no_placement_probe:
+        tries = [probe_ms()]
+        bufs.clear()
+        torch.cuda.empty_cache()
+        allocate()
+        tries.append(probe_ms())
+        if tries[1] > 1.02 * tries[0]:
+            bufs.clear()
+            torch.cuda.empty_cache()
+            allocate()
+            tries.append(probe_ms())
+        placement = dict(apply_build_ms=[round(x, 1) for x in tries], allocations=len(tries),
+                         note="one build per allocation; the timed steps use the last one")
+        log(f"[bench] placement probe: apply + build {', '.join(f'{x:.1f}' for x in tries)} ms "
+            f"over {len(tries)} allocations")
+    keys, data, offs = bufs.get("keys"), bufs.get("data"), bufs.get("offs")
+    ws, codes, rank = bufs["ws"], bufs["codes"], bufs["rank"]
+    bufs.clear()
+    key_bytes = 8 * n if kind == mx.KEYS_U64 else int(offs[-1].item())
+    log(f"[bench] {cfg['workload']} n={n}: keys generated on device in {t_alloc:.1f} s with the workspace "
+        f"({key_bytes / 1e9:.2f} GB of key bytes); workspace {ws.numel() / 1e9:.2f} GB, device memory in use "
         f"{torch.cuda.memory_allocated() / 1e9:.1f} GB")
 
     def step():
@@ -1002,7 +1046,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": cfg["workload"], "n": n, "gamma": "123/100", "m": m,
                    "key_bytes": key_bytes, "rounds": r["n_rounds"], "tries": r["tries"],
-                   "parallelism": "single GPU", **({"options": options} if options else {})},
+                   "parallelism": "single GPU", **({"options": options} if options else {}),
+                   **({"placement": placement} if placement else {})},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "ceilings": ceilings,
