@@ -774,6 +774,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=0, help="override the number of keys")
     ap.add_argument("--cpu-sample", type=int, default=1 << 26, help="keys in the oracle's timed sample (~15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--placement-tries", type=int, default=2, help="allocations the placement probe makes")
     ap.add_argument("--no-placement-probe", action="store_true",
                     help="time the first allocation's physical layout, without probing the other")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
@@ -849,13 +850,13 @@ def main() -> int:
         return 0
 
     # ---- inputs, generated on the device before timing --------------------------------------
-    # The driver places the ~270 GB of keys and workspace in one of two physical layouts that
-    # alternate from one full allocation to the next; in one of them the random-access phases
-    # (apply, the record build) run about 20 % slower.  Unless --no-placement-probe, one build
-    # is timed in the first layout, everything is released and allocated again (the other
-    # layout), one build timed there, and if it was slower the allocation is repeated once
-    # more (back to the first layout).  Both probe times are reported; the timed steps run on
-    # the chosen allocation and are the same builds either way.
+    # The driver places the ~270 GB of keys and workspace in one of two physical layouts, on
+    # some boxes alternating from one full allocation to the next; in one of them the random-
+    # access phases (apply, the record build) run about 20 % slower.  Unless
+    # --no-placement-probe, one build is timed in each of --placement-tries allocations
+    # (everything released and allocated again in between), then in up to two more until the
+    # last is within 2 % of the best seen; the timed steps run on that last allocation and the
+    # probe times are reported.  The timed steps are the same builds either way.
     P = mx.part_size(n, gamma)
     m = 3 * P
     kind = mx.KEYS_U64 if cfg["kind"] == "u64" else mx.KEYS_STR
@@ -892,11 +893,10 @@ def main() -> int:
     placement = None
     if not args.no_placement_probe:
         tries = [probe_ms()]
-        bufs.clear()
-        torch.cuda.empty_cache()
-        allocate()
-        tries.append(probe_ms())
-        if tries[1] > 1.02 * tries[0]:
+        for j in range(args.placement_tries - 1 + 2):
+            # after the requested tries, at most two more until the last is within 2 % of the best
+            if j >= args.placement_tries - 1 and tries[-1] <= 1.02 * min(tries):
+                break
             bufs.clear()
             torch.cuda.empty_cache()
             allocate()
