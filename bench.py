@@ -120,6 +120,16 @@ def sources_digest(phase: str) -> str:
     return h.hexdigest()[:16]
 
 
+def need_another_allocation(tries: list, requested: int) -> bool:
+    """Placement probe: allocate again until `requested` allocations were probed, then at most
+    two more while the last probe is more than 2 % slower than the best seen."""
+    if len(tries) < requested:
+        return True
+    if len(tries) >= requested + 2:
+        return False
+    return tries[-1] > 1.02 * min(tries)
+
+
 def counters_traffic(workload: str, phase: str):
     """HBM bytes per launch of a phase from the committed counter summary, or None when there
     is none or the phase's kernel sources changed since it was taken."""
@@ -289,9 +299,7 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     # full release) while the last allocation's step is more than 2 % slower than the best seen
     keys, bb, t = setup()
     probes = [t]
-    while not args.no_placement_probe and len(probes) < 1 + max(1, args.placement_tries - 1) + 2:
-        if len(probes) >= args.placement_tries and probes[-1] <= 1.02 * min(probes):
-            break
+    while not args.no_placement_probe and need_another_allocation(probes, args.placement_tries):
         bb.destroy_graph()
         del bb, keys
         torch.cuda.empty_cache()
@@ -916,10 +924,7 @@ def main() -> int:
     placement = None
     if not args.no_placement_probe:
         tries = [probe_ms()]
-        for j in range(args.placement_tries - 1 + 2):
-            # after the requested tries, at most two more until the last is within 2 % of the best
-            if j >= args.placement_tries - 1 and tries[-1] <= 1.02 * min(tries):
-                break
+        while need_another_allocation(tries, args.placement_tries):
             bufs.clear()
             torch.cuda.empty_cache()
             allocate()

@@ -1,0 +1,50 @@
+"""Host-side logic of bench.py (CPU only): the one-GPU contract, the algorithmic-byte model
+of the priced phases, the counters' staleness guard and the placement probe's rule."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
+
+
+def test_algorithmic_bytes_per_unit():
+    n, m = 1 << 20, 3 * 430_000
+    st = dict(n=n, m=m, kind="str", key_bytes=60 * n, frontier_total=0, frontier0=0, claims=0, lists=False,
+              update_deletes=0, update_records=0)
+    assert bench.algorithmic_bytes("assign", st) == 15 * n  # slot, two code reads, one code write
+    assert bench.algorithmic_bytes("hash", st) == 60 * n + 8 * n + 12 * n  # bytes, offset, edge
+    assert bench.algorithmic_bytes("hash", dict(st, kind="u64")) == 8 * n + 12 * n
+    assert bench.algorithmic_bytes("build", st) == 12 * n + 8 * m
+
+
+def test_counters_are_ignored_when_stale_or_missing():
+    assert bench.counters_traffic("no_such_workload", "assign") is None
+    assert bench.counters_traffic("mwhc_str_n2^31_mean60B_gamma1.23", "no_such_phase") is None
+    d1, d2 = bench.sources_digest("assign"), bench.sources_digest("assign")
+    assert d1 == d2 and len(d1) == 16
+    assert bench.sources_digest("assign") != bench.sources_digest("hash")
+
+
+def test_placement_probe_rule():
+    def run(seq, requested=2):
+        tries, it = [], iter(seq)
+        tries.append(next(it))
+        while bench.need_another_allocation(tries, requested):
+            tries.append(next(it))
+        return tries
+
+    assert run([240, 280, 240, 280]) == [240, 280, 240]  # alternating layouts: back to the fast one
+    assert run([280, 240, 280]) == [280, 240]
+    assert run([286, 279, 286, 279]) == [286, 279]  # every layout slow: stop within 2 % of the best
+    assert run([279, 286, 279, 286]) == [279, 286, 279]
+    assert run([300, 300, 300, 300, 300], requested=4) == [300] * 4
+    assert run([250, 300, 300, 300, 300]) == [250, 300, 300, 300]  # at most two beyond the request
