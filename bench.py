@@ -881,7 +881,7 @@ def main() -> int:
         return 0
 
     # ---- inputs, generated on the device before timing --------------------------------------
-    # The driver places the ~270 GB of keys and workspace in one of two physical layouts, on
+    # The device memory allocator places the ~270 GB of keys and workspace in one of two physical layouts, on
     # some boxes alternating from one full allocation to the next; in one of them the random-
     # access phases (apply, the record build) run about 20 % slower.  Unless
     # --no-placement-probe, one build is timed in each of --placement-tries allocations
