@@ -144,6 +144,23 @@ def counters_traffic(workload: str, phase: str):
     return (row["fetch_bytes"] + row["write_bytes"]) / row["launches"]
 
 
+def counters_step_traffic(workload: str):
+    """HBM bytes of one whole build (every kernel of the counted run except the input
+    generators, which run before the timed region), or None when there is no summary or any
+    phase's kernel sources changed since it was taken."""
+    path = COUNTERS_FILE.format(workload=workload.replace("^", ""))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        doc = json.load(fh)
+    phases = doc.get("phases", {})
+    if set(phases) != set(PHASE_SOURCES) or any(phases[p].get("sources_digest") != sources_digest(p)
+                                                for p in phases):
+        return None
+    return sum(v["fetch_bytes"] + v["write_bytes"] for k, v in doc.get("kernels", {}).items()
+               if not k.startswith("k_gen_"))
+
+
 def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy_write_dir: str,
                        workload: str, command: str) -> int:
     """Writes profiles/hbm_counters_<workload>.{json,txt} from two rocprofv3 --pmc runs
@@ -987,6 +1004,19 @@ def main() -> int:
     if traffic is not None:
         roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roofline["traffic_GBps"] = round(traffic * phase_rows[dom]["launches"] / (phase_rows[dom]["ms"] / 1e3) / 1e9, 1)
+    # the whole step: every phase's algorithmic bytes, and the counted HBM bytes of one build,
+    # over the step time (host gaps included)
+    step_alg = sum(v["alg_bytes"] for v in phase_rows.values())
+    step = dict(alg_bytes=int(step_alg), alg_GBps=round(step_alg / (ms_per_step / 1e3) / 1e9, 1),
+                alg_frac=round(step_alg / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4), peak=HBM_PEAK_GBS,
+                unit="GB/s", traffic=None, traffic_GBps=None, traffic_frac=None)
+    step_traffic = counters_step_traffic(cfg["workload"]) if n == cfg["n"] else None
+    if step_traffic is not None:
+        t_gbs = step_traffic / (ms_per_step / 1e3) / 1e9
+        step.update(traffic=round(step_traffic), traffic_GBps=round(t_gbs, 1), traffic_frac=round(t_gbs / HBM_PEAK_GBS, 4),
+                    traffic_vs_copy=round(t_gbs / ceilings["copy_GBps"], 3) if ceilings else None)
+    log(f"[bench] step: {step['alg_GBps']:.1f} GB/s algorithmic ({step['alg_frac']:.3f} of peak), counted "
+        f"{step['traffic_GBps']} GB/s ({step['traffic_frac']} of peak)")
     # the dominant phase against the measured ceilings of the random operations it is made of:
     # each class's rate over the phase time, against the probe's rate for that class alone
     ops = random_ops(dom, st)
@@ -1077,6 +1107,7 @@ def main() -> int:
                    "parallelism": "single GPU", **({"options": options} if options else {}),
                    **({"placement": placement} if placement else {})},
         "roofline": roofline,
+        "step_roofline": step,
         "cpu_baseline": cpu,
         "ceilings": ceilings,
         "phases": phase_rows,

@@ -48,3 +48,21 @@ def test_placement_probe_rule():
     assert run([279, 286, 279, 286]) == [279, 286, 279]
     assert run([300, 300, 300, 300, 300], requested=4) == [300] * 4
     assert run([250, 300, 300, 300, 300]) == [250, 300, 300, 300]  # at most two beyond the request
+
+
+def test_step_traffic_sums_every_build_kernel(monkeypatch):
+    import json
+
+    assert bench.counters_step_traffic("no_such_workload") is None
+    w = "mwhc_str_n2^31_mean60B_gamma1.23"
+    with open(bench.COUNTERS_FILE.format(workload=w.replace("^", ""))) as fh:
+        doc = json.load(fh)
+    monkeypatch.setattr(bench, "sources_digest", lambda p: doc["phases"][p]["sources_digest"])
+    total = bench.counters_step_traffic(w)
+    build = [v for k, v in doc["kernels"].items() if not k.startswith("k_gen_")]
+    assert total == sum(v["fetch_bytes"] + v["write_bytes"] for v in build)
+    # the phases' kernels are a part of the build's, the generators none of it
+    assert total > sum(v["fetch_bytes"] + v["write_bytes"] for v in doc["phases"].values())
+    assert total < sum(v["fetch_bytes"] + v["write_bytes"] for v in doc["kernels"].values())
+    monkeypatch.setattr(bench, "sources_digest", lambda p: "0" * 16)  # any kernel source changed
+    assert bench.counters_step_traffic(w) is None
