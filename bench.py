@@ -411,6 +411,38 @@ def ceilings_leg(mx, torch) -> dict:
     return out
 
 
+FOOTPRINT_MB = (32, 128, 256, 512, 660, 880, 1320, 2640, 16384)
+
+
+def footprint_leg(mx, torch) -> dict:
+    """The random probes as a function of the table's footprint: 2^30 random 8-byte loads,
+    1-byte stores, returning 8-byte atomics and 4-byte atomics over tables from inside the
+    last-level cache (256 MB) to 16 GiB.  The sizes in between are those of the code array
+    (m bytes at 2^31 keys: 2640 MB), one part of it (880 MB) and its 2-bit form (660 MB)."""
+    dev = torch.device("cuda:0")
+    table = torch.zeros(16 << 30, dtype=torch.uint8, device=dev)
+    count = 1 << 30
+    rows = {}
+    for name, op, esz in (("load8", mx.PROBE_LOAD8, 8), ("store1", mx.PROBE_STORE1, 1),
+                          ("atomic_add_ret", mx.PROBE_ATOMIC_ADD_RET, 8), ("atomic_add32", mx.PROBE_ATOMIC_ADD32, 4)):
+        rates = {}
+        for mb in FOOTPRINT_MB:
+            slots = (mb << 20) // esz
+            assert slots * esz <= table.numel()
+            mx.probe_random(op, table, slots, count // 8, seed=1)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            mx.probe_random(op, table, slots, count, seed=2)
+            b.record()
+            b.synchronize()
+            rates[str(mb)] = round(count / a.elapsed_time(b) / 1e6, 2)
+        rows[name] = rates
+        log(f"[footprint] {name} G/s by MB: {rates}")
+    del table
+    torch.cuda.empty_cache()
+    return dict(unit="G operations/s", count=count, footprint_MB=list(FOOTPRINT_MB), rates=rows)
+
+
 def random_ops(phase: str, st: dict) -> dict:
     """Random device-memory operations per step of a phase (atomics and gathers to arrays far
     larger than the caches), the count its measured ceiling applies to."""
@@ -826,7 +858,8 @@ def main() -> int:
     ap.add_argument("--no-placement-probe", action="store_true",
                     help="time the first allocation's physical layout, without probing the other")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
-                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host, peel_r")
+                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host, peel_r, "
+                         "footprint")
     ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
                     help="bucket-count exponents of the hem leg")
     ap.add_argument("--hem-tune", type=lambda s: s.split(","), default=["1024x0"],
@@ -894,6 +927,8 @@ def main() -> int:
             side["hem_host"] = hem_host_leg(args, mx, torch)
         if "peel_r" in legs:
             side["peel_r"] = peel_r_leg(args, mx, torch)
+        if "footprint" in legs:
+            side["footprint"] = footprint_leg(mx, torch)
         print(json.dumps(side), flush=True)
         return 0
 

@@ -551,6 +551,7 @@ def check_bijection(vals: torch.Tensor) -> int:
 
 
 PROBE_ATOMIC_ADD, PROBE_ATOMIC_ADD_RET, PROBE_LOAD8, PROBE_STORE1, PROBE_LDS_ATOMIC_ADD = 1, 2, 3, 4, 5
+PROBE_ATOMIC_ADD32, PROBE_ATOMIC_ADD_WG = 6, 7
 
 
 def probe_copy(src: torch.Tensor, dst: torch.Tensor, grid: int = 0):

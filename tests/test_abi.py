@@ -36,6 +36,14 @@ def test_every_declared_symbol_is_exported(mx):
     assert missing == []
 
 
+def test_binding_constants_match_the_header(mx):
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define MPHX_((?:PROBE|KEYS)_\w+)\s+(\d+)", text))
+    assert len(defs) >= 9
+    for name, value in defs.items():
+        assert getattr(mx, name) == int(value), name
+
+
 def test_part_size_matches_oracle(mx):
     import oracle
 
