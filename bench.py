@@ -301,9 +301,29 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     off = np.zeros(len(sizes) + 1, np.uint64)
     off[1:] = np.cumsum(sizes)
     total = int(off[-1])
+    block, grid = args.batch_block, args.batch_grid
+    tune = None
+    if not args.no_batch_autotune and block == 0 and grid == 0:
+        # the library's autotuner on every 16th bucket in size order (the same size mix at a
+        # sixteenth of the keys); the full batch then runs with the fastest tuning
+        pick = np.argsort(sizes, kind="stable")[::16]
+        s_sizes = sizes[pick]
+        s_off = np.zeros(len(s_sizes) + 1, np.uint64)
+        s_off[1:] = np.cumsum(s_sizes)
+        s_keys = mx.gen_buckets_u64(torch.from_numpy(s_off.view(np.int64)).to(dev))
+        sb = mx.BatchBuild(s_off)
+        tune = sb.autotune(s_keys, reps=2)
+        block, grid = tune["candidates"][tune["best"]]
+        tune.update(sample_buckets=len(s_sizes), sample_keys=int(s_off[-1]))
+        log(f"[batched] autotune on {len(s_sizes)} buckets: " +
+            ", ".join(f"{b}x{g} {ms:.1f} ms" for (b, g), ms in zip(tune["candidates"], tune["ms"])) +
+            f" -> {block}x{grid}")
+        del sb, s_keys
+        torch.cuda.empty_cache()
+
     def setup():
         keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).to(dev))
-        bb = mx.BatchBuild(off, block=args.batch_block, grid=args.batch_grid)
+        bb = mx.BatchBuild(off, block=block, grid=grid)
         bb.capture(keys)
         bb.launch()  # warm
         torch.cuda.synchronize()
@@ -361,7 +381,7 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     out = dict(workload=BATCH_WORKLOAD, buckets=len(sizes), keys=total, ms_per_step=round(sec * 1000, 3),
                value=round(ok_keys / sec, 1), unit="edges/s", failed_buckets=int((~ok).sum()),
                retries=extra_tries, block=bb.tuning.block, grid=bb.tuning.grid,
-               placement_probe_ms=[round(x, 1) for x in probes],
+               placement_probe_ms=[round(x, 1) for x in probes], autotune=tune,
                plain_same_buckets=dict(value=round(plain_rate, 1), unit="edges/s", buckets=len(sample)),
                speedup_vs_plain=round(ok_keys / sec / plain_rate, 2))
     del bb, keys
@@ -879,6 +899,8 @@ def main() -> int:
     ap.add_argument("--batch-buckets", type=int, default=65536)
     ap.add_argument("--batch-block", type=int, default=0)
     ap.add_argument("--batch-grid", type=int, default=0)
+    ap.add_argument("--no-batch-autotune", action="store_true",
+                    help="batched leg: skip the autotuner (block/grid from --batch-block/--batch-grid, else 1024 x one per CU)")
     ap.add_argument("--plain-sample", type=int, default=256)
     ap.add_argument("--serve-requests", type=int, default=300)
     ap.add_argument("--serve-max", type=int, default=100_000_000)

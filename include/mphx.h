@@ -266,6 +266,32 @@ MPHX_API int mphx_graph_capture_batch_u64(const uint64_t* keys, const uint64_t* 
                                           const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
                                           mphx_bucket_result* results, void* ws, size_t ws_bytes,
                                           const mphx_batch_tuning* tuning, void** graph);
+/* Autotuning the batched launch.  The workgroup size fixes the per-workgroup LDS budget and
+ * the vertex tile the records are built in (1024 threads: 158 KB, tiles of 8192 vertices,
+ * one workgroup per compute unit; 512: 78 KB, 4096 vertices; 256: 48 KB, 4096 vertices), and
+ * the grid how many workgroups share a compute unit; every tuning builds the same outputs.
+ * mphx_batch_tuning_candidates writes up to `cap` candidate tunings to `out` (host; NULL
+ * with cap 0 to ask for the count) and returns how many there are: (1024, 1 per CU),
+ * (512, 1 per CU), (512, 2 per CU), (256, 2 per CU), (256, 3 per CU).
+ * mphx_batch_autotune_u64 runs mphx_build_batch_u64 with each of the ncand tunings in
+ * `cands` (host) on the given buckets -- a sample of the workload, which the caller chooses
+ * -- once untimed and then `reps` times (1..100), timed by HIP events on `stream`, and writes
+ * the index of the fastest to *best (host) and each candidate's best time in ms to ms[i]
+ * (host, nullable; -1 for a candidate whose workspace, mphx_batch_workspace_bytes with that
+ * tuning, exceeds ws_bytes, which is then skipped).  The other arguments are those of
+ * mphx_build_batch_u64, and the outputs hold the build afterwards.  Synchronises (not for
+ * graph capture).  Errors: MPHX_EINVAL for a bad argument or candidate (before any device
+ * work), MPHX_ENOMEM if no candidate fits, MPHX_EDEVICE if a launch failed.  B = 0 returns
+ * MPHX_OK with *best = 0 and no device work. */
+MPHX_API uint32_t mphx_batch_tuning_candidates(mphx_batch_tuning* out, uint32_t cap);
+MPHX_API int mphx_batch_autotune_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order,
+                                     uint32_t B, uint64_t max_bucket, uint64_t seed, uint32_t gamma_num,
+                                     uint32_t gamma_den, uint32_t max_tries, const uint64_t* code_off,
+                                     const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                                     mphx_bucket_result* results, void* ws, size_t ws_bytes,
+                                     const mphx_batch_tuning* cands, uint32_t ncand, uint32_t reps, float* ms,
+                                     uint32_t* best, void* stream);
+
 /* The general form: B buckets described one by one (dev array `buckets`), each with its own
  * keys (u64 `keys`, or 4-byte-aligned string `bytes` + n+1 `offs` with keys == NULL), seed,
  * output buffers (codes ceil(m_b/32) words, rank ceil(m_b/512)) and result slot.  order (dev,

@@ -94,6 +94,9 @@ _SIGS = {
                                     _vp, _sz, _vp, _vp]),
     "mphx_graph_capture_batch_u64": (_i32, [_vp, _vp, _vp, _u32, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp,
                                             _vp, _vp, _sz, _vp, C.POINTER(C.c_void_p)]),
+    "mphx_batch_tuning_candidates": (_u32, [_vp, _u32]),
+    "mphx_batch_autotune_u64": (_i32, [_vp, _vp, _vp, _u32, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp,
+                                       _vp, _sz, _vp, _u32, _u32, _vp, C.POINTER(C.c_uint32), _vp]),
     "mphx_batch_desc_workspace_bytes": (_sz, [_u64, _u32, _u32, _vp]),
     "mphx_build_batch": (_i32, [_vp, _u32, _vp, _u64, _u32, _u32, _u32, _vp, _sz, _vp, _vp]),
     "mphx_graph_launch": (_i32, [_vp, _vp]),
@@ -675,6 +678,35 @@ class BatchBuild:
                 self.gamma[0], self.gamma[1], self.max_tries, _ptr(self.code_off), _ptr(self.rank_off),
                 _ptr(self.codes), _ptr(self.rank), _ptr(self.results), _ptr(self.ws), self.ws.numel(),
                 C.byref(self.tuning))
+
+    def autotune(self, keys, candidates=None, reps=2, max_ws_bytes=64 << 30):
+        """Times each candidate tuning (default: the library's list) on this plan's buckets and
+        keeps the fastest for later run() / capture() calls.  The workspace grows to the largest
+        candidate's, up to max_ws_bytes (candidates beyond it are skipped).  Returns
+        dict(best, candidates [(block, grid)], ms [best time per candidate, -1 if skipped])."""
+        if candidates is None:
+            cnt = lib().mphx_batch_tuning_candidates(None, 0)
+            arr = (BatchTuning * cnt)()
+            lib().mphx_batch_tuning_candidates(arr, cnt)
+        else:
+            arr = (BatchTuning * len(candidates))(*[BatchTuning(b, g, sc, 0) for b, g, sc in candidates])
+        n = len(arr)
+        need = max(lib().mphx_batch_workspace_bytes(self.B, self.max_bucket, self.gamma[0], self.gamma[1],
+                                                    C.byref(arr[i])) for i in range(n))
+        want = min(need, max_ws_bytes)
+        if want > self.ws.numel():
+            self.ws = None
+            torch.cuda.empty_cache()
+            self.ws = _workspace(want, self.device)
+        args = list(self._args(keys))[:-1]  # everything but the tuning
+        ms = (C.c_float * n)()
+        best = C.c_uint32(0)
+        rc = lib().mphx_batch_autotune_u64(*args, arr, n, reps, ms, C.byref(best), _stream(self.device))
+        if rc:
+            _err(rc)
+        self.tuning = BatchTuning(arr[best.value].block, arr[best.value].grid, arr[best.value].scope, 0)
+        return dict(best=int(best.value), candidates=[(int(a.block), int(a.grid)) for a in arr],
+                    ms=[round(float(x), 3) for x in ms])
 
     def run(self, keys, max_bucket=None):
         """Enqueue the whole batch on the current stream (no synchronisation)."""

@@ -1317,6 +1317,86 @@ int mphx_build_batch_u64(const uint64_t* keys, const uint64_t* bucket_off, const
                          codes, rank, results, ws, ws_bytes, t, (hipStream_t)stream);
 }
 
+uint32_t mphx_batch_tuning_candidates(mphx_batch_tuning* out, uint32_t cap)
+{
+    // The workgroup size fixes the LDS budget and tile (1024 threads: 158 KB, 8192-vertex
+    // tiles, one workgroup per compute unit; 512: 78 KB and 4096, up to two; 256: 48 KB and
+    // 4096, up to three), so each size comes with the grids its occupancy allows.
+    unsigned block = 0, cus = 0;
+    if (batch_tuning(nullptr, block, cus)) cus = 256;
+    const mphx_batch_tuning c[] = {{1024, cus, 0, 0}, {512, cus, 0, 0}, {512, 2 * cus, 0, 0},
+                                   {256, 2 * cus, 0, 0}, {256, 3 * cus, 0, 0}};
+    const uint32_t n = (uint32_t)(sizeof(c) / sizeof(c[0]));
+    for (uint32_t i = 0; i < n && i < cap && out; i++) out[i] = c[i];
+    return n;
+}
+
+int mphx_batch_autotune_u64(const uint64_t* keys, const uint64_t* bucket_off, const uint32_t* order, uint32_t B,
+                            uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
+                            const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
+                            mphx_bucket_result* results, void* ws, size_t ws_bytes,
+                            const mphx_batch_tuning* cands, uint32_t ncand, uint32_t reps, float* ms,
+                            uint32_t* best, void* stream)
+{
+    g_err.clear();
+    // every argument is checked before the first device call
+    if (!cands || ncand == 0 || !best) return fail(MPHX_EINVAL, "candidates and best must be given");
+    if (reps == 0 || reps > 100) return fail(MPHX_EINVAL, "reps must be in [1, 100]");
+    if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
+    std::vector<unsigned> grids(ncand);
+    for (uint32_t i = 0; i < ncand; i++) {
+        unsigned block = 0;
+        int rc = batch_tuning(&cands[i], block, grids[i]);
+        if (rc) return rc;
+    }
+    *best = 0;
+    if (B == 0) {
+        for (uint32_t i = 0; ms && i < ncand; i++) ms[i] = 0.0f;
+        return MPHX_OK;
+    }
+    if (!keys || !bucket_off || !order || !code_off || !rank_off || !codes || !rank || !results)
+        return fail(MPHX_EINVAL, "null pointer argument");
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct Events {
+        hipEvent_t* e;
+        ~Events()
+        {
+            for (int i = 0; i < 2; i++)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } guard{ev};
+    HIP_TRY(hipEventCreate(&ev[0]));
+    HIP_TRY(hipEventCreate(&ev[1]));
+    float top = -1.0f;
+    for (uint32_t i = 0; i < ncand; i++) {
+        float t = -1.0f;  // -1: the candidate's workspace does not fit in ws_bytes
+        if (batch_ws_bytes(B, max_bucket, gnum, gden, grids[i]) <= ws_bytes) {
+            // one untimed build, then the best of reps; every build rewrites the same outputs
+            for (uint32_t r = 0; r <= reps; r++) {
+                HIP_TRY(hipEventRecord(ev[0], s));
+                int rc = batch_enqueue(keys, bucket_off, order, B, max_bucket, seed, gnum, gden, max_tries, code_off,
+                                       rank_off, codes, rank, results, ws, ws_bytes, &cands[i], s);
+                if (rc) return rc;
+                HIP_TRY(hipEventRecord(ev[1], s));
+                HIP_TRY(hipEventSynchronize(ev[1]));
+                float x = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&x, ev[0], ev[1]));
+                if (r > 0 && (t < 0.0f || x < t)) t = x;
+            }
+            if (top < 0.0f || t < top) {
+                top = t;
+                *best = i;
+            }
+        }
+        if (ms) ms[i] = t;
+    }
+    if (top < 0.0f) return fail(MPHX_ENOMEM, "no candidate's workspace fits in %zu bytes", ws_bytes);
+    return MPHX_OK;
+}
+
 size_t mphx_batch_desc_workspace_bytes(uint64_t max_bucket, uint32_t gnum, uint32_t gden, const mphx_batch_tuning* t)
 {
     unsigned block = 0, grid = 0;

@@ -154,3 +154,25 @@ def test_workspace_sizes_scale_linearly(mx):
     b = mx.mphf_workspace_bytes(1 << 24)
     slope = (b - a) / (1 << 23)
     assert 37.5 < slope < 38.2
+
+
+def test_batch_autotune_arguments_need_no_device(mx):
+    lib = mx.lib()
+    n = lib.mphx_batch_tuning_candidates(None, 0)
+    arr = (mx.BatchTuning * n)()
+    assert lib.mphx_batch_tuning_candidates(arr, n) == n == 5
+    assert {a.block for a in arr} == {256, 512, 1024} and all(a.grid > 0 for a in arr)
+    best, ms = C.c_uint32(7), (C.c_float * n)()
+
+    def call(B=1, cands=arr, ncand=n, reps=1, keys=None, gnum=123):
+        return lib.mphx_batch_autotune_u64(keys, None, None, B, 10, 0, gnum, 100, 8, None, None, None, None, None,
+                                           None, 0, cands, ncand, reps, ms, C.byref(best), None)
+
+    assert call(ncand=0) == mx.EINVAL
+    assert call(cands=None) == mx.EINVAL
+    assert call(reps=0) == mx.EINVAL and call(reps=101) == mx.EINVAL
+    assert call(gnum=0) == mx.EINVAL
+    bad = (mx.BatchTuning * 1)(mx.BatchTuning(300, 1, 0, 0))
+    assert call(cands=bad, ncand=1) == mx.EINVAL
+    assert call() == mx.EINVAL  # null keys and outputs for a non-empty batch
+    assert call(B=0) == 0 and best.value == 0 and list(ms) == [0.0] * n

@@ -177,3 +177,31 @@ def test_build_batch_descriptors_mixed_kinds(mx, o):
                 assert got["n_rounds"] == ref["n_rounds"], b
                 assert np.array_equal(got["codes"].cpu().numpy().view(np.uint64), ref["words"]), b
                 assert np.array_equal(got["rank"].cpu().numpy().view(np.uint64), ref["rank"]), b
+
+
+def test_autotune_picks_a_candidate_and_every_tuning_builds_the_same(mx, o):
+    # the autotuner times the library's candidate tunings on this batch, keeps the fastest, and
+    # leaves the batch built; a later run with the chosen tuning equals the oracle bucket by bucket
+    import torch
+
+    off = _offsets(SIZES)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    keys_h = _host_keys(SIZES)
+    bb = mx.BatchBuild(off, block=1024)
+    ws_before = bb.ws.numel()
+    t = bb.autotune(keys, reps=1)
+    assert len(t["candidates"]) == 5 and 0 <= t["best"] < 5
+    assert all(ms > 0 for ms in t["ms"]) and t["ms"][t["best"]] == min(t["ms"])
+    assert (bb.tuning.block, bb.tuning.grid) == tuple(t["candidates"][t["best"]])
+    assert bb.ws.numel() >= ws_before
+    torch.cuda.synchronize()
+    _check_buckets(mx, o, bb, keys_h, SIZES)  # the outputs of the last timed build
+    bb.codes.zero_()
+    bb.rank.zero_()
+    bb.run(keys)
+    torch.cuda.synchronize()
+    _check_buckets(mx, o, bb, keys_h, SIZES)
+    # a workspace cap below every candidate but the 1024-thread one skips the others
+    bb2 = mx.BatchBuild(off, block=1024)
+    t2 = bb2.autotune(keys, candidates=[(1024, 0, 0), (256, 4096, 0)], reps=1, max_ws_bytes=bb2.ws.numel())
+    assert t2["best"] == 0 and t2["ms"][0] > 0 and t2["ms"][1] == -1
