@@ -226,6 +226,36 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
     return 0
 
 
+def summarize_l2(pmc_dir: str, out_path: str, title: str, command: str) -> int:
+    """Writes a per-kernel table of a rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum run: L2
+    requests that hit and missed, summed over dispatches, and the hit rate."""
+    import csv
+    import glob
+
+    acc = {}
+    for f in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+            name = name.split("(")[0].split("<")[0].split("::")[-1]
+            row = acc.setdefault(name, {"dispatches": set(), "TCC_HIT_sum": 0.0, "TCC_MISS_sum": 0.0})
+            row["dispatches"].add(r["Dispatch_Id"])
+            if r["Counter_Name"] in ("TCC_HIT_sum", "TCC_MISS_sum"):
+                row[r["Counter_Name"]] += float(r["Counter_Value"])
+    lines = [f"# {title}", "", f"command: {command}", "",
+             "L2 (TCC) requests summed over each kernel's dispatches; hit rate = hits / (hits + misses).", "",
+             f"{'kernel':28s} {'disp':>5s} {'hits_M':>10s} {'misses_M':>10s} {'hit_rate':>9s}"]
+    for k, v in sorted(acc.items(), key=lambda kv: -(kv[1]["TCC_HIT_sum"] + kv[1]["TCC_MISS_sum"])):
+        tot = v["TCC_HIT_sum"] + v["TCC_MISS_sum"]
+        if tot < 1e6:
+            continue
+        lines.append(f"{k:28s} {len(v['dispatches']):5d} {v['TCC_HIT_sum'] / 1e6:10.1f} {v['TCC_MISS_sum'] / 1e6:10.1f} "
+                     f"{v['TCC_HIT_sum'] / tot:9.3f}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    return 0
+
+
 def summarize_kernel_stats(csv_path: str, out_path: str, title: str, command: str) -> int:
     """Writes a text table of a rocprofv3 --stats kernel_stats.csv."""
     import csv
@@ -894,6 +924,8 @@ def main() -> int:
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
                     help="library option to set before timing (mphx_set_option), e.g. claim_lists=0")
+    ap.add_argument("--summarize-l2", nargs=3, metavar=("PMC_DIR", "OUT_TXT", "TITLE"),
+                    help="write a per-kernel L2 hit-rate table from a rocprofv3 --pmc TCC_HIT_sum TCC_MISS_sum run")
     ap.add_argument("--summarize-kernel-stats", nargs=3, metavar=("STATS_CSV", "OUT_TXT", "TITLE"),
                     help="write a text table of a rocprofv3 kernel_stats.csv (command from --counters-command)")
     ap.add_argument("--batch-buckets", type=int, default=65536)
@@ -912,6 +944,8 @@ def main() -> int:
     args = ap.parse_args()
     if args.summarize_kernel_stats:
         return summarize_kernel_stats(*args.summarize_kernel_stats, command=args.counters_command)
+    if args.summarize_l2:
+        return summarize_l2(*args.summarize_l2, command=args.counters_command)
     if args.summarize_counters:
         return summarize_counters(*args.summarize_counters, workload=CONFIGS[args.config]["workload"],
                                   command=args.counters_command)

@@ -66,3 +66,19 @@ def test_step_traffic_sums_every_build_kernel(monkeypatch):
     assert total < sum(v["fetch_bytes"] + v["write_bytes"] for v in doc["kernels"].values())
     monkeypatch.setattr(bench, "sources_digest", lambda p: "0" * 16)  # any kernel source changed
     assert bench.counters_step_traffic(w) is None
+
+
+def test_l2_summary_sums_dispatches_and_rates(tmp_path):
+    d = tmp_path / "pmc" / "sub"
+    d.mkdir(parents=True)
+    head = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+    rows = ["1,\"mphx::k_assign_round(uint3 const*)\",TCC_HIT_sum,1000000", "1,\"mphx::k_assign_round(uint3 const*)\",TCC_MISS_sum,3000000",
+            "2,\"mphx::k_assign_round(uint3 const*)\",TCC_HIT_sum,1000000", "2,\"mphx::k_assign_round(uint3 const*)\",TCC_MISS_sum,3000000",
+            "3,\"void mphx::k_apply<(mphx::ApplyMode)1>(int)\",TCC_HIT_sum,9000000",
+            "3,\"void mphx::k_apply<(mphx::ApplyMode)1>(int)\",TCC_MISS_sum,1000000"]
+    (d / "p_counter_collection.csv").write_text(head + "\n".join(rows) + "\n")
+    out = tmp_path / "l2.txt"
+    assert bench.summarize_l2(str(tmp_path / "pmc"), str(out), "t", "cmd") == 0
+    table = {ln.split()[0]: ln.split() for ln in out.read_text().splitlines() if ln.startswith("k_")}
+    assert table["k_assign_round"][1:] == ["2", "2.0", "6.0", "0.250"]
+    assert table["k_apply"][1:] == ["1", "9.0", "1.0", "0.900"]
