@@ -10,6 +10,8 @@
   those keys, the MPHF is a bijection onto [0, n) over all keys, the rank samples equal the
   prefix counts of the codes, and the oracle's evaluation of the GPU tables agrees with the
   GPU lookup at sampled keys.
+* 65,536 u64 buckets of 100 to 10^6 keys in one captured batched launch: every bucket builds,
+  and the largest buckets and a random sample equal the oracle's single builds.
 """
 import numpy as np
 import pytest
@@ -136,3 +138,37 @@ def test_config3_sampled_parity(mx):
     prefix = np.concatenate([[0], np.cumsum(per_block)[:-1]])
     assert np.array_equal(rank.astype(np.int64), prefix)
     assert int(nz.sum()) == n
+
+
+@pytest.mark.timeout(600)
+def test_config4_full_batch_sampled_parity(mx):
+    # 65,536 buckets of 100 to 10^6 u64 keys (log-uniform, 7.09e9 keys) in one captured
+    # persistent launch at 1024 threads x one workgroup per compute unit, as the benchmark runs
+    # it: every bucket builds, the sum of the per-bucket code and rank lengths is the layout's,
+    # and the largest buckets and a random sample equal the oracle's single builds
+    import torch
+
+    o = oracle.Oracle()
+    sizes = workloads.bucket_sizes(65536, 100, 1_000_000, seed=0)
+    off = np.zeros(len(sizes) + 1, np.uint64)
+    off[1:] = np.cumsum(sizes)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    bb = mx.BatchBuild(off, block=1024, grid=0)
+    bb.capture(keys)
+    bb.launch()
+    bb.launch()  # a replay rebuilds the same tables
+    torch.cuda.synchronize()
+    res = bb.bucket_results()
+    assert (res["status"] == 0).all() and (res["tries"] >= 1).all()
+    assert int(bb.code_off_h[-1]) == bb.codes.numel() and int(bb.rank_off_h[-1]) == bb.rank.numel()
+    rng = np.random.default_rng(11)
+    which = np.argsort(-sizes, kind="stable")[:2].tolist() + rng.choice(len(sizes), 24, replace=False).tolist()
+    for b in which:
+        kb = host(keys[int(off[b]):int(off[b + 1])], np.uint64)
+        assert np.array_equal(kb, workloads.u64_keys(int(sizes[b]), gen_seed=workloads.bucket_gen_seed(b))), b
+        rc, ref = o.mphf_build_u64(kb, seed=0, max_tries=bb.max_tries)
+        assert rc == 0 and res[b]["tries"] == ref["tries"] and res[b]["seed_used"] == ref["seed_used"], b
+        assert res[b]["n_rounds"] == ref["n_rounds"], b
+        assert np.array_equal(host(bb.bucket_codes(b), np.uint64), ref["words"]), b
+        assert np.array_equal(host(bb.bucket_rank(b), np.uint64), ref["rank"]), b
+    bb.destroy_graph()
