@@ -12,6 +12,8 @@
   GPU lookup at sampled keys.
 * 65,536 u64 buckets of 100 to 10^6 keys in one captured batched launch: every bucket builds,
   and the largest buckets and a random sample equal the oracle's single builds.
+* The served workload at full size (requests of 10^3 to 10^8 keys): every result equals the
+  request built alone, the largest ones are bijections, small ones equal the oracle.
 """
 import numpy as np
 import pytest
@@ -172,3 +174,58 @@ def test_config4_full_batch_sampled_parity(mx):
         assert np.array_equal(host(bb.bucket_codes(b), np.uint64), ref["words"]), b
         assert np.array_equal(host(bb.bucket_rank(b), np.uint64), ref["rank"]), b
     bb.destroy_graph()
+
+
+@pytest.mark.timeout(600)
+def test_config5_served_full_sizes(mx):
+    # 60 requests of the served workload (sizes log-uniform 1e3..1e8, u64 or string keys, each
+    # a prefix of one device-generated key set per kind, as the benchmark builds them), all
+    # submitted at once to a server with the benchmark's budget and slots: every result equals
+    # the same request built alone, the largest of each kind is a bijection, and the small
+    # requests equal the oracle's builds
+    import torch
+
+    max_n = 100_000_000
+    keys = mx.gen_keys_u64(max_n, gen_seed=7)
+    q = torch.from_numpy(workloads.quantile_table().view(np.int16)).cuda()
+    data, offs = mx.gen_str_keys(max_n, q, gen_seed=8)
+    nreq = 60
+    sizes = workloads.request_sizes(nreq, 1000, max_n, seed=1)
+    kinds = (workloads.stream(np.uint64(2), np.arange(1, nreq + 1, dtype=np.uint64)) & np.uint64(1)).astype(int)
+    assert sizes.max() > 3 * 10**7 and set(kinds) == {0, 1}
+
+    def req(i):
+        n = int(sizes[i])
+        return (keys[:n],) if kinds[i] == 0 else (data, offs[: n + 1])
+
+    srv = mx.Server(hbm_budget=64 << 30, slots=4)
+    tickets = [srv.submit_u64(*req(i), seed=i) if kinds[i] == 0 else srv.submit_str(*req(i), seed=i)
+               for i in range(nreq)]
+    res = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    for i, r in enumerate(res):
+        assert r["status"] == 0, i
+        a = mx.mphf_build_u64(*req(i), seed=i) if kinds[i] == 0 else mx.mphf_build_str(*req(i), seed=i)
+        assert (r["tries"], r["seed_used"], r["P"]) == (a["tries"], a["seed_used"], a["P"]), i
+        assert torch.equal(r["codes"], a["codes"]) and torch.equal(r["rank"], a["rank"]), i
+    for kind in (0, 1):
+        i = int(np.argmax(np.where(kinds == kind, sizes, 0)))
+        r = res[i]
+        if kind == 0:
+            f = mx.lookup_u64(r["codes"], r["rank"], r["P"], r["seed_used"], keys[: int(sizes[i])])
+        else:
+            f = mx.lookup_str(r["codes"], r["rank"], r["P"], r["seed_used"], data, offs[: int(sizes[i]) + 1])
+        assert mx.check_bijection(f) == 0, i
+    o = oracle.Oracle()
+    small = [i for i in range(nreq) if sizes[i] <= 200_000][:8]
+    assert len(small) >= 4
+    for i in small:
+        n = int(sizes[i])
+        if kinds[i] == 0:
+            rc, ref = o.mphf_build_u64(host(keys[:n], np.uint64), seed=i)
+        else:
+            oh = host(offs[: n + 1], np.uint64)
+            rc, ref = o.mphf_build_str(data[: int(oh[-1])].cpu().numpy(), oh, seed=i)
+        assert rc == 0 and np.array_equal(host(res[i]["codes"], np.uint64), ref["words"]), i
+        assert np.array_equal(host(res[i]["rank"], np.uint64), ref["rank"]), i
+    srv.close()
