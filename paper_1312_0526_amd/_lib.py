@@ -682,8 +682,11 @@ class BatchBuild:
     def autotune(self, keys, candidates=None, reps=2, max_ws_bytes=64 << 30):
         """Times each candidate tuning (default: the library's list) on this plan's buckets and
         keeps the fastest for later run() / capture() calls.  The workspace grows to the largest
-        candidate's, up to max_ws_bytes (candidates beyond it are skipped).  Returns
-        dict(best, candidates [(block, grid)], ms [best time per candidate, -1 if skipped])."""
+        candidate's, up to max_ws_bytes (candidates beyond it are skipped).  A graph captured
+        before is destroyed (it holds the old tuning and may hold the old workspace): capture
+        again afterwards.  Returns dict(best, candidates [(block, grid)], ms [best time per
+        candidate, -1 if skipped])."""
+        self.destroy_graph()
         if candidates is None:
             cnt = lib().mphx_batch_tuning_candidates(None, 0)
             arr = (BatchTuning * cnt)()

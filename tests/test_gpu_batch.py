@@ -189,7 +189,9 @@ def test_autotune_picks_a_candidate_and_every_tuning_builds_the_same(mx, o):
     keys_h = _host_keys(SIZES)
     bb = mx.BatchBuild(off, block=1024)
     ws_before = bb.ws.numel()
+    bb.capture(keys)
     t = bb.autotune(keys, reps=1)
+    assert bb.graph is None  # the graph held the old workspace: dropped
     assert len(t["candidates"]) == 5 and 0 <= t["best"] < 5
     assert all(ms > 0 for ms in t["ms"]) and t["ms"][t["best"]] == min(t["ms"])
     assert (bb.tuning.block, bb.tuning.grid) == tuple(t["candidates"][t["best"]])
@@ -201,6 +203,13 @@ def test_autotune_picks_a_candidate_and_every_tuning_builds_the_same(mx, o):
     bb.run(keys)
     torch.cuda.synchronize()
     _check_buckets(mx, o, bb, keys_h, SIZES)
+    bb.codes.zero_()
+    bb.rank.zero_()
+    bb.capture(keys)  # captured again with the chosen tuning and the new workspace
+    bb.launch()
+    torch.cuda.synchronize()
+    _check_buckets(mx, o, bb, keys_h, SIZES)
+    bb.destroy_graph()
     # a workspace cap below every candidate but the 1024-thread one skips the others
     bb2 = mx.BatchBuild(off, block=1024)
     t2 = bb2.autotune(keys, candidates=[(1024, 0, 0), (256, 4096, 0)], reps=1, max_ws_bytes=bb2.ws.numel())
