@@ -150,6 +150,7 @@ def test_config4_full_batch_sampled_parity(mx):
     # and the largest buckets and a random sample equal the oracle's single builds
     import torch
 
+    torch.cuda.empty_cache()
     o = oracle.Oracle()
     sizes = workloads.bucket_sizes(65536, 100, 1_000_000, seed=0)
     off = np.zeros(len(sizes) + 1, np.uint64)
@@ -185,6 +186,8 @@ def test_config5_served_full_sizes(mx):
     # requests equal the oracle's builds
     import torch
 
+    # the server allocates its pool itself: give back what earlier tests left in torch's cache
+    torch.cuda.empty_cache()
     max_n = 100_000_000
     keys = mx.gen_keys_u64(max_n, gen_seed=7)
     q = torch.from_numpy(workloads.quantile_table().view(np.int16)).cuda()
