@@ -790,6 +790,11 @@ class Server:
         idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
         h = C.c_void_p()
         rc = lib().mphx_server_create(idx, int(hbm_budget), int(slots), int(batch_max_keys), C.byref(h))
+        if rc == ENOMEM:
+            # the server allocates its pool itself; memory torch has cached but not in use
+            # cannot serve that until it is given back
+            torch.cuda.empty_cache()
+            rc = lib().mphx_server_create(idx, int(hbm_budget), int(slots), int(batch_max_keys), C.byref(h))
         if rc:
             raise MphxError(rc, "server create failed")
         self.h = h
