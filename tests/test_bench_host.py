@@ -1,5 +1,6 @@
 """Host-side logic of bench.py (CPU only): the one-GPU contract, the algorithmic-byte model
-of the priced phases, the counters' staleness guard and the placement probe's rule."""
+of the priced phases, the counters' staleness guard, the whole-build traffic sum, the L2
+hit-rate summary and the placement probe's rule."""
 import os
 import subprocess
 import sys
