@@ -40,50 +40,98 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(phase: str, st: dict) -> float:
-    """Bytes each phase must move at least once, at element size (not cache-line size).
+# Algorithmic bytes per edge of each step of the path, frozen before measuring: every logical
+# element counted once per required access at its element size, never at cache-line size.
+#   hash    u64: key 8 + edge 12; strings: the key bytes + an 8-byte offset + edge 12
+#   build   edge 12 read + three 5-byte (degree, label) records read and written (3 x 10)
+#   frontier  degrees read (1.23 per edge) + first frontier written (about 1.05 per edge)
+#   peel    per peeled edge: label 4, claim 2, edge 12, two 10-byte record read-modify-writes
+#           20, hinge degree 1, round 4, frontier push and pop 8
+#   order   round read 4 + order written 4 (the generic peel only)
+#   assign  edge 12, hinge 1, two value reads and one value write of 1 byte each
+#   rank    codes and used flags read 2.5, packed codes and samples written 0.3
+PER_EDGE = dict(hash_u64=20.0, hash_str_fixed=20.0, build=42.0, frontier=2.3, peel=51.0, order=8.0,
+                assign=16.0, rank=2.8)
 
-    n keys/edges, m = 3P vertices, key_bytes = total key bytes, F = frontier entries over all
-    rounds, F0 = initial frontier; an 8-byte per-vertex record read-modify-write counts 16 B.
+
+def round0_deletes_in_frontier(st: dict) -> bool:
+    """True when round 0's deletes run inside the round-0 kernel (claim lists with update
+    lists): its layer is then peeled under the frontier timer, not by the apply launches."""
+    return bool(st.get("lists", False) and st.get("round0_updates", False))
+
+
+def algorithmic_bytes(phase: str, st: dict) -> float:
+    """Bytes a phase must move at least once per build, from the per-edge model above.
+
+    Each peeled edge's 51 bytes go to the kernel that deletes it: round 0's layer to the
+    round-0 kernel (frontier timer) when that kernel deletes it, every other layer to the
+    apply launches.  The claim resolution and the update-list accumulation are this
+    implementation's own traffic and have no bytes of their own in the model.
     """
-    n, m = st["n"], st["m"]
-    F, F0, C = st["frontier_total"], st["frontier0"], st["claims"]
+    n = st["n"]
+    L0 = st.get("layer0", 0)
     if phase == "hash":
-        # key (u64: 8 B; strings: the bytes + one 8 B offset) read, 12 B edge written
-        key = 8 * n if st["kind"] == "u64" else st["key_bytes"] + 8 * n
-        return key + 12 * n
+        if st["kind"] == "u64":
+            return PER_EDGE["hash_u64"] * n
+        return st["key_bytes"] + PER_EDGE["hash_str_fixed"] * n
     if phase == "build":
-        # every edge read once, every 8 B vertex record written once
-        return 12 * n + 8 * m
-    lists = st.get("lists", False)
-    U, T = st.get("update_deletes", 0), st.get("update_records", 0)
+        return PER_EDGE["build"] * n
     if phase == "frontier":
-        # round 0: every record read; per degree-1 vertex an edge-state RMW (8 B) and at most
-        # one 4 B layer append; with claim lists, the hinge test instead: the edge's lower-part
-        # vertices (about 4 B) and their records (about 8 B), and an 8 B layer entry (when
-        # round 0 also writes its hinge-first slots and deletes, those are counted under apply)
-        return 8 * m + (20 if lists else 12) * F0
+        return PER_EDGE["frontier"] * n + (PER_EDGE["peel"] * L0 if round0_deletes_in_frontier(st) else 0.0)
     if phase == "apply":
-        # per edge: slot read 8 (edge + hinge, or edge + state read) + edge read 12 + slot
-        # write 12; per delete a record RMW (16 B), or an 8 B update-list entry in rounds that
-        # use update lists; per vertex taken to degree 1 by an atomic delete: an edge-state
-        # RMW 8 + at most one 4 B append, or one 8 B claim written
-        return 32 * n + 16 * (2 * n - U) + 8 * U + (8 if lists else 12) * (F - F0)
-    if phase == "update":
-        # update lists: every delete read back once (8 B), every record it changes read and
-        # written once (16 B)
-        return 8 * U + 16 * T
-    if phase == "resolve":
-        # claims of rounds 1.. read back (8 B each); per layer edge its state (4 B) and layer
-        # entry (8 B) written
-        return 8 * (F - F0) + 12 * n
+        return PER_EDGE["peel"] * (n - L0 if round0_deletes_in_frontier(st) else n)
+    if phase == "order":
+        return PER_EDGE["order"] * n
     if phase == "assign":
-        # 12 B slot read + two code reads + one code write (1 B each)
-        return 15 * n
+        return PER_EDGE["assign"] * n
     if phase == "rank":
-        # code bytes read, packed words written, per-512 counts written/read, rank written
-        return m + m / 4 + 16 * m / 512
+        return PER_EDGE["rank"] * n
     return 0.0
+
+
+PEEL_PHASES = ("frontier", "apply", "resolve", "update")
+
+
+def peel_roofline(phase_rows: dict, peel_traffic, n: int) -> dict:
+    """The peel alone (round 0 through the last round: frontier, apply, resolve and update
+    phases) against the HBM peak: its model bytes and, when counters are current, its counted
+    HBM bytes per build, both over the summed kernel time of those phases."""
+    rows = [phase_rows[p] for p in PEEL_PHASES if p in phase_rows]
+    ms = sum(r["ms"] for r in rows)
+    alg = sum(r["alg_bytes"] for r in rows)
+    out = dict(phases=[p for p in PEEL_PHASES if p in phase_rows], ms=round(ms, 3), alg_bytes=int(alg),
+               alg_GBps=None, alg_frac=None, traffic=None, traffic_GBps=None, traffic_frac=None,
+               amplification=None, peak=HBM_PEAK_GBS, unit="GB/s",
+               edges_per_s=round(n / (ms / 1e3), 1) if ms > 0 else None)
+    if ms <= 0:
+        return out
+    a = alg / (ms / 1e3) / 1e9
+    out.update(alg_GBps=round(a, 1), alg_frac=round(a / HBM_PEAK_GBS, 4))
+    if peel_traffic is not None:
+        t = peel_traffic / (ms / 1e3) / 1e9
+        out.update(traffic=round(peel_traffic), traffic_GBps=round(t, 1), traffic_frac=round(t / HBM_PEAK_GBS, 4),
+                   amplification=round(peel_traffic / alg, 2) if alg else None)
+    return out
+
+
+def kernel_roofline(phase: str, row: dict, traffic_per_launch) -> dict:
+    """The roofline object of one phase: model bytes per launch over the average launch time
+    (HIP events on the build's stream), against the HBM peak; `traffic` is the counted HBM
+    bytes per launch when the counters are current."""
+    per_launch = row["alg_bytes"] / row["launches"]
+    avg_s = row["ms"] / 1e3 / row["launches"]
+    ach = per_launch / avg_s / 1e9
+    out = dict(bound="hbm", kernel=phase, achieved=round(ach, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(ach / HBM_PEAK_GBS, 4),
+               traffic=None if traffic_per_launch is None else round(traffic_per_launch),
+               alg_bytes_per_launch=round(per_launch), launch_avg_us=round(avg_s * 1e6, 2),
+               launches=row["launches"])
+    if traffic_per_launch is not None:
+        out["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        out["traffic_GBps"] = round(traffic_per_launch / avg_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic_per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+        out["amplification"] = round(traffic_per_launch / per_launch, 2) if per_launch else None
+    return out
 
 
 # Phases, the kernels each is made of, and the sources those kernels are compiled from: HBM
@@ -181,6 +229,7 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
 
     fk, wk = per_kernel(fetch_dir), per_kernel(write_dir)
     cf, cw = per_kernel(copy_fetch_dir), per_kernel(copy_write_dir)
+    fw, ww = build_windows(dispatch_rows(fetch_dir)), build_windows(dispatch_rows(write_dir))
     copy_bytes = float(4 << 30)  # the ceilings leg copies 4 GiB: reads and writes that much
     f_scale = copy_bytes / (cf["k_copy"][0] / cf["k_copy"][1])
     w_scale = copy_bytes / (cw["k_copy"][0] / cw["k_copy"][1])
@@ -203,6 +252,12 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
                                  launches=sum(doc["kernels"][k]["dispatches"] for k in ks) if per_launch else builds,
                                  fetch_bytes=sum(doc["kernels"][k]["fetch_bytes"] for k in ks),
                                  write_bytes=sum(doc["kernels"][k]["write_bytes"] for k in ks))
+    # the same build cut in dispatch order: everything between the round-0 kernel and the
+    # first assignment launch is the peel, whichever kernels it is made of
+    if fw["builds"] and fw["builds"] == ww["builds"]:
+        doc["windows"] = dict(builds=fw["builds"], sources_digest={p: sources_digest(p) for p in PEEL_PHASES},
+                              **{w: dict(fetch_bytes=fw[w] * f_scale, write_bytes=ww[w] * w_scale)
+                                 for w in WINDOWS})
     path = COUNTERS_FILE.format(workload=workload.replace("^", ""))
     with open(path, "w") as fh:
         json.dump(doc, fh, indent=1)
@@ -220,10 +275,80 @@ def summarize_counters(fetch_dir: str, write_dir: str, copy_fetch_dir: str, copy
     for ph, v in doc["phases"].items():
         lines.append(f"{ph:10s} launches {v['launches']:4d}  fetch {v['fetch_bytes'] / 1e9:9.2f} GB  "
                      f"write {v['write_bytes'] / 1e9:9.2f} GB  sources {v['sources_digest']}")
+    if "windows" in doc:
+        lines += ["", f"Per build in dispatch order (mean over {doc['windows']['builds']} builds): hash and record "
+                  "build up to the round-0 kernel, the peel from it up to the first assignment launch, then "
+                  "assignment and rank:", ""]
+        for w in WINDOWS:
+            v = doc["windows"][w]
+            lines.append(f"{w:12s} fetch {v['fetch_bytes'] / 1e9:9.2f} GB  write {v['write_bytes'] / 1e9:9.2f} GB")
     with open(path[:-5] + ".txt", "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
     return 0
+
+
+WINDOWS = ("hash_build", "peel", "assign_rank")
+
+
+def dispatch_rows(d: str) -> list:
+    """(dispatch id, kernel name, counter value in bytes) of a rocprofv3 --pmc run, in
+    dispatch order."""
+    import csv
+    import glob
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+            name = name.split("(")[0].split("<")[0].split("::")[-1]
+            rows.append((int(r["Dispatch_Id"]), name, float(r["Counter_Value"]) * 1024.0))
+    rows.sort()
+    return rows
+
+
+def build_windows(rows: list) -> dict:
+    """Counter bytes of each build's three windows, averaged over the builds in the run: a
+    build starts at its hashing kernel; the peel window opens at the round-0 kernel and closes
+    at the first assignment launch.  Kernels outside any build (input generators, probes) and
+    incomplete builds are left out."""
+    sums = {w: 0.0 for w in WINDOWS}
+    builds, cur, state = 0, None, None
+    for _, name, b in rows:
+        if name.startswith("k_hash_"):
+            if cur is not None and state == "assign_rank":
+                builds += 1
+                for w in WINDOWS:
+                    sums[w] += cur[w]
+            cur, state = {w: 0.0 for w in WINDOWS}, "hash_build"
+        elif cur is None:
+            continue
+        elif name.startswith("k_round0") and state == "hash_build":
+            state = "peel"
+        elif name.startswith("k_assign_round") and state == "peel":
+            state = "assign_rank"
+        elif name.startswith("k_gen_") or name.startswith("k_copy") or name.startswith("k_probe"):
+            continue
+        cur[state] += b
+    if cur is not None and state == "assign_rank":
+        builds += 1
+        for w in WINDOWS:
+            sums[w] += cur[w]
+    return dict(builds=builds, **{w: (sums[w] / builds if builds else 0.0) for w in WINDOWS})
+
+
+def counters_peel_traffic(workload: str):
+    """Counted HBM bytes of one build's peel window, or None when there is no summary or a
+    peel phase's kernel sources changed since it was taken."""
+    path = COUNTERS_FILE.format(workload=workload.replace("^", ""))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        doc = json.load(fh)
+    w = doc.get("windows")
+    if not w or any(w["sources_digest"].get(p) != sources_digest(p) for p in PEEL_PHASES):
+        return None
+    return w["peel"]["fetch_bytes"] + w["peel"]["write_bytes"]
 
 
 def summarize_l2(pmc_dir: str, out_path: str, title: str, command: str) -> int:
@@ -499,16 +624,18 @@ def random_ops(phase: str, st: dict) -> dict:
     n, F, F0 = st["n"], st["frontier_total"], st["frontier0"]
     lists = st.get("lists", False)
     U = st.get("update_deletes", 0)
+    L0 = st.get("layer0", 0) if round0_deletes_in_frontier(st) else 0
     if phase == "apply":
-        # per edge: edge-triple gather (and the state, without claim lists), two returning
-        # deletes unless they went to an update list; per vertex taken to degree 1: one
-        # atomicMin claim without claim lists
+        # per edge the apply launches delete: edge-triple gather (and the state, without claim
+        # lists), two returning deletes unless they went to an update list; per vertex taken
+        # to degree 1: one atomicMin claim without claim lists
         if lists:
-            return dict(atomics=2 * n - U, loads=n)
+            return dict(atomics=2 * n - U, loads=n - L0)
         return dict(atomics=2 * n + (F - F0), loads=2 * n)
     if phase == "frontier":
-        # with claim lists the hinge test gathers the lower-part vertices and their records
-        return dict(atomics=0, loads=F0) if lists else dict(atomics=F0, loads=0)
+        # with claim lists the hinge test gathers the lower-part vertices and their records;
+        # when round 0 also deletes its layer, one edge gather per layer-0 edge
+        return dict(atomics=0, loads=F0 + L0) if lists else dict(atomics=F0, loads=0)
     if phase == "assign":
         return dict(atomics=0, loads=2 * n, stores=n)
     return {}
@@ -1075,6 +1202,7 @@ def main() -> int:
     lists_from = mx.get_option("claim_lists")
     st = dict(n=n, m=m, kind=cfg["kind"], key_bytes=key_bytes, frontier_total=r["frontier_total"],
               frontier0=r["frontier0"], claims=r["claims"], lists=lists_from > 0 and n >= (1 << lists_from),
+              round0_updates=mx.get_option("update_lists") > 0, layer0=r["layer0"],
               update_deletes=r["update_deletes"], update_records=r["update_records"])
     phase_rows = {}
     for name, (ms, launches) in phases.items():
@@ -1087,14 +1215,16 @@ def main() -> int:
                                 alg_bytes=int(b), alg_GBps=round(gbs, 1))
         log(f"[bench]   {name:10s} {per_step_ms:9.3f} ms/step  {launches // args.steps:5d} launches  "
             f"{b / 1e9:8.2f} GB alg  {gbs:8.1f} GB/s")
-    dom = max(phase_rows, key=lambda k: phase_rows[k]["ms"])
-    ach = phase_rows[dom]["alg_GBps"]
+    # the dominant kernel: the phase with the most time among those the model prices
+    priced = {k: v for k, v in phase_rows.items() if v["alg_bytes"] > 0}
+    dom = max(priced, key=lambda k: priced[k]["ms"])
     traffic = counters_traffic(cfg["workload"], dom) if n == cfg["n"] else None
-    roofline = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None if traffic is None else round(traffic))
-    if traffic is not None:
-        roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-        roofline["traffic_GBps"] = round(traffic * phase_rows[dom]["launches"] / (phase_rows[dom]["ms"] / 1e3) / 1e9, 1)
+    roofline = kernel_roofline(dom, phase_rows[dom], traffic)
+    log(f"[bench] dominant kernel {dom}: {roofline['alg_bytes_per_launch'] / 1e9:.3f} GB/launch over "
+        f"{roofline['launch_avg_us']:.1f} us = {roofline['achieved']:.1f} GB/s ({roofline['frac']:.4f} of peak)")
+    peel = peel_roofline(phase_rows, counters_peel_traffic(cfg["workload"]) if n == cfg["n"] else None, n)
+    log(f"[bench] peel alone: {peel['ms']:.1f} ms, model {peel['alg_frac']} of peak, counted {peel['traffic_frac']} "
+        f"of peak (amplification {peel['amplification']})")
     # the whole step: every phase's algorithmic bytes, and the counted HBM bytes of one build,
     # over the step time (host gaps included)
     step_alg = sum(v["alg_bytes"] for v in phase_rows.values())
@@ -1105,7 +1235,8 @@ def main() -> int:
     if step_traffic is not None:
         t_gbs = step_traffic / (ms_per_step / 1e3) / 1e9
         step.update(traffic=round(step_traffic), traffic_GBps=round(t_gbs, 1), traffic_frac=round(t_gbs / HBM_PEAK_GBS, 4),
-                    traffic_vs_copy=round(t_gbs / ceilings["copy_GBps"], 3) if ceilings else None)
+                    traffic_vs_copy=round(t_gbs / ceilings["copy_GBps"], 3) if ceilings else None,
+                    amplification=round(step_traffic / step_alg, 2) if step_alg else None)
     log(f"[bench] step: {step['alg_GBps']:.1f} GB/s algorithmic ({step['alg_frac']:.3f} of peak), counted "
         f"{step['traffic_GBps']} GB/s ({step['traffic_frac']} of peak)")
     # the dominant phase against the measured ceilings of the random operations it is made of:
@@ -1198,6 +1329,7 @@ def main() -> int:
                    "parallelism": "single GPU", **({"options": options} if options else {}),
                    **({"placement": placement} if placement else {})},
         "roofline": roofline,
+        "peel_roofline": peel,
         "step_roofline": step,
         "cpu_baseline": cpu,
         "ceilings": ceilings,

@@ -49,6 +49,7 @@ extern "C" {
 #define MPHX_ERANGE (-2)
 #define MPHX_ENOMEM (-3)
 #define MPHX_EDEVICE (-4)
+#define MPHX_ECANCELED (-5) /* server: the request was not started before the server was destroyed */
 #define MPHX_ECORE 1
 #define MPHX_EDUP 2
 
@@ -78,6 +79,7 @@ typedef struct mphx_mphf_info {
     uint64_t frontier0;      /* last try: vertices of degree 1 before round 0 */
     uint64_t update_deletes; /* last try: deletes applied through update lists */
     uint64_t update_records; /* last try: vertex records those deletes changed */
+    uint64_t layer0;         /* last try: edges removed in round 0 */
 } mphx_mphf_info;
 
 /* Message describing the last failure on the calling thread ("" if none). */
@@ -402,13 +404,17 @@ MPHX_API int mphx_hem_lookup_str(const uint64_t* bucket_off, const uint64_t* cod
  * request's keys and output buffers are caller-owned device memory that must stay valid until
  * the ticket completes.  Requests are admitted in arrival order as workers and pool memory
  * free up (a later request that fits may pass the queue head a bounded number of times);
- * admitted builds run concurrently.  A request whose workspace exceeds the whole budget
- * completes at once with MPHX_ENOMEM; smaller ones wait and never fail for lack of memory.
+ * admitted builds run concurrently.  A request whose workspace exceeds what the pool can give
+ * a build (the budget less the batching lane's reservation, if any) completes at once with
+ * MPHX_ENOMEM; smaller ones wait and never fail for lack of memory: the queue head is passed
+ * at most 8 times by later requests that fit, then admitted before any of them.
  * Each result (status, tries, seed, codes, rank) is exactly what mphx_mphf_build_u64/_str
  * returns for the request alone.  Times are seconds of mphx_server_clock() (steady clock):
  * t_submit at submission, t_start at admission, t_done when the outputs are complete.
  * mphx_server_poll returns 0 (done, *res filled) or 1 (pending); mphx_server_wait blocks.
- * mphx_server_destroy finishes all queued work, then frees the pool.
+ * mphx_server_destroy completes every request not admitted yet with MPHX_ECANCELED, waits for
+ * the admitted builds to finish, then frees the pool; no other call on the server may overlap
+ * or follow it.
  * --------------------------------------------------------------------------------------- */
 typedef struct mphx_server mphx_server;
 
@@ -511,6 +517,12 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *   "hem_grid"    0..65536 (default 0 = one workgroup per compute unit): its persistent grid.
  *                 Both shape the work only, never the result; the HEM workspaces depend on the
  *                 grid, so query them after setting it.
+ *   "list_cap"    c >= 0 (default 0 = m): records a claim-list round may keep in its list (at
+ *                 most m, the buffers' size).  A round with more claims, or a round 0 with
+ *                 more deletes, makes the try start again with atomic claims (the same codes
+ *                 either way); a small value exercises that fallback.
+ *   "list_fallbacks" (read; set only to 0 to reset) tries redone with atomic claims after
+ *                 a list overflowed, over the process.
  * Returns MPHX_EINVAL for an unknown key or value.
  *
  * mphx_phase_times copies the accumulated per-phase kernel time (ms) and launch counts of

@@ -13,10 +13,11 @@ import torch  # loads the HIP runtime first, so the library binds to the same on
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmphx.so")
 
-OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ECORE, EDUP = 0, -1, -2, -3, -4, 1, 2
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ECANCELED, ECORE, EDUP = 0, -1, -2, -3, -4, -5, 1, 2
 ROUND_CORE = 0xFFFFFFFF
 KEYS_U64, KEYS_STR = 0, 1
-_NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECORE: "ECORE", EDUP: "EDUP"}
+_NAMES = {EINVAL: "EINVAL", ERANGE: "ERANGE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ECANCELED: "ECANCELED",
+          ECORE: "ECORE", EDUP: "EDUP"}
 
 
 class MphxError(RuntimeError):
@@ -35,7 +36,7 @@ class MphfInfo(C.Structure):
     _fields_ = [("P", C.c_uint64), ("m", C.c_uint64), ("seed_used", C.c_uint64), ("tries", C.c_uint32),
                 ("n_rounds", C.c_uint32), ("n_core", C.c_uint64), ("frontier_total", C.c_uint64),
                 ("claims", C.c_uint64), ("frontier0", C.c_uint64), ("update_deletes", C.c_uint64),
-                ("update_records", C.c_uint64)]
+                ("update_records", C.c_uint64), ("layer0", C.c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -29,6 +29,8 @@ struct Options {
     std::atomic<int> update_lists{16}; // claim-list rounds with 2 * layer >= m * update_lists / 100
     std::atomic<int> hem_block{1024};  // batched-kernel workgroup size for the HEM split's buckets
     std::atomic<int> hem_grid{0};      // its persistent grid (0 = one workgroup per compute unit)
+    std::atomic<int64_t> list_cap{0};  // records a claim-list round may hold (0 = m, the buffers' size)
+    std::atomic<int64_t> list_fallbacks{0};  // tries redone with atomic claims after a list overflowed
     std::atomic<int> batch_lds{1};     // 1 = batched buckets that fit run entirely in LDS
     std::atomic<int> batch_sort_deletes{8};  // sorted deletes for layers with 2 * layer * this >= m
                                        // delete through a sorted update list (0 = never)
@@ -293,7 +295,7 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
         if (r > 0) {
             HIP_TRY(hipMemcpyAsync(&est, st.ccount + r, sizeof est, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (est > st.m)
+            if (est > st.lcap)
                 return kListOverflow;  // the list holds m records; no layer of a large random graph comes near
             Timed t(PH_RESOLVE, s);
             HIP_TRY(launch_claims_resolve(st, r, est, in_tmp, s));
@@ -308,7 +310,7 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
             unsigned long long dels = 0;
             HIP_TRY(hipMemcpyAsync(&dels, st.dcount, sizeof dels, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (dels > st.m)
+            if (dels > st.lcap)
                 return kListOverflow;  // layer 0 larger than m/2 edges: redo with atomic claims
             Timed t(PH_UPDATE, s);
             HIP_TRY(launch_update_apply(st, 0, dels, s));
@@ -318,7 +320,7 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
             continue;
         }
         // a layer of at most est edges deletes at most 2 est times, which the list must hold
-        const bool updates = upd > 0 && 2 * est <= st.m && 200 * (unsigned __int128)est >= (unsigned __int128)upd * st.m;
+        const bool updates = upd > 0 && 2 * est <= st.lcap && 200 * (unsigned __int128)est >= (unsigned __int128)upd * st.m;
         {
             Timed t(PH_APPLY, s);
             HIP_TRY(launch_apply(st, r, true, updates ? ApplyMode::kUpdateList : ApplyMode::kClaimList, s));
@@ -328,7 +330,7 @@ int run_rounds_lists(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
             unsigned long long dels = 0;
             HIP_TRY(hipMemcpyAsync(&dels, st.dcount + r, sizeof dels, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (dels > st.m)
+            if (dels > st.lcap)
                 return fail(MPHX_ERANGE, "update list of round %u overflowed (%llu deletes)", r, dels);
             Timed t(PH_UPDATE, s);
             HIP_TRY(launch_update_apply(st, r, dels, s));
@@ -438,6 +440,12 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "hem_grid")) {
         if (value < 0 || value > (1 << 16)) return fail(MPHX_EINVAL, "hem_grid must be in 0..65536");
         g_opt.hem_grid = (int)value;
+    } else if (!strcmp(key, "list_cap")) {
+        if (value < 0) return fail(MPHX_EINVAL, "list_cap must be >= 0");
+        g_opt.list_cap = value;
+    } else if (!strcmp(key, "list_fallbacks")) {
+        if (value != 0) return fail(MPHX_EINVAL, "list_fallbacks can only be reset to 0");
+        g_opt.list_fallbacks = 0;
     } else {
         return fail(MPHX_EINVAL, "unknown option '%s'", key);
     }
@@ -457,6 +465,8 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "hem_grid")) return g_opt.hem_grid;
     if (!strcmp(key, "batch_lds")) return g_opt.batch_lds;
     if (!strcmp(key, "batch_sort_deletes")) return g_opt.batch_sort_deletes;
+    if (!strcmp(key, "list_cap")) return g_opt.list_cap;
+    if (!strcmp(key, "list_fallbacks")) return g_opt.list_fallbacks;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
     return MPHX_EINVAL;
 }
@@ -809,6 +819,9 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     st.ctrl = L.ctrl;
     st.rcap = round_cap(n);
     st.lists = lists;
+    st.lcap = m;
+    if (g_opt.list_cap.load() > 0)
+        st.lcap = std::min<uint64_t>(m, (uint64_t)g_opt.list_cap.load());
     st.claims = L.claims;
     st.claims_tmp = L.claims_tmp;
     st.ccount = L.ccount;
@@ -865,6 +878,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         }
         rc = st.lists ? run_rounds_lists(st, h, &peeled, s) : run_rounds(st, h, &peeled, s);
         if (rc == kListOverflow) {  // redo this try with atomic claims
+            g_opt.list_fallbacks++;
             st.lists = false;
             t--;
             continue;
@@ -897,6 +911,8 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     // Assignment in reverse round order with exact grids from the layer bounds.
     std::vector<uint64_t> lb(h.nrounds + 1);
     HIP_TRY(hipMemcpyAsync(lb.data(), L.lstart, lb.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) info->layer0 = h.nrounds ? lb[1] - lb[0] : 0;
     if (sf) {
         // u (one narrow element per vertex, over the records) solved layer by layer, then packed
         const uint32_t b = mphx_sf_bits(sf->sigma);
@@ -1127,7 +1143,7 @@ int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_
 namespace {
 
 static_assert(sizeof(mphx_bucket_result) == sizeof(BucketResult), "bucket result layouts agree");
-static_assert(sizeof(mphx_mphf_info) == 80 && sizeof(mphx_peel_info) == 40, "info layouts as documented");
+static_assert(sizeof(mphx_mphf_info) == 88 && sizeof(mphx_peel_info) == 40, "info layouts as documented");
 static_assert(sizeof(mphx_bucket) == sizeof(BucketDesc), "bucket descriptor layouts agree");
 
 int batch_tuning(const mphx_batch_tuning* t, unsigned& block, unsigned& grid)

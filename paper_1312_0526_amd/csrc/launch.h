@@ -27,6 +27,8 @@ struct PeelState {
     // partitioned by edge and resolved in LDS into the next layer.
     bool lists;
     uint2* claims;          // m (edge, position) claims of one round
+    uint64_t lcap;          // records a round may keep in the list (<= m); more make the try
+                            // fall back to atomic claims
     uint2* claims_tmp;      // m, the partition's other buffer
     unsigned long long* ccount;  // rcap + 2 claim counts: ccount[r] = claims that form layer r
     // Sorted update lists (dense rounds of a claim-list run): apply(r) appends one (vertex,

@@ -526,7 +526,7 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
         if (!st.tripartite) return hipErrorInvalidValue;
         if (st.round0_updates)
             k_round0_updates<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount,
-                                                      st.claims, st.dcount, st.m, st.ctrl, st.vin, st.vout);
+                                                      st.claims, st.dcount, st.lcap, st.ctrl, st.vin, st.vout);
         else
             k_round0_lists<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount, st.ctrl);
     } else if (st.tripartite)
@@ -763,7 +763,7 @@ hipError_t launch_apply(const PeelState& st, uint32_t r, bool hinge_in_slot, App
     if (mode != ApplyMode::kAtomicClaims && !st.tripartite) return hipErrorInvalidValue;
 #define MPHX_APPLY(TRI, MODE, HINGE)                                                                        \
     k_apply<TRI, MODE><<<g, kPeelBlock, 0, s>>>(st.rec, st.edges, st.state, st.slots, st.lstart, st.lcount, \
-                                                st.claims, st.ccount, st.dcount, st.m, st.ctrl, r, st.P, HINGE,   \
+                                                st.claims, st.ccount, st.dcount, st.lcap, st.ctrl, r, st.P, HINGE,   \
                                                 st.vin, st.vout)
     switch (mode) {
     case ApplyMode::kClaimList: MPHX_APPLY(true, ApplyMode::kClaimList, hinge_in_slot); break;

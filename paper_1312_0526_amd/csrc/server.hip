@@ -4,8 +4,11 @@
 // own HIP stream (default priority).  Requests wait in arrival order; whenever a worker is idle
 // it admits the first waiting request whose workspace fits in the pool (first fit), so a later
 // small request may pass a large one that does not fit yet -- but only a bounded number of
-// times, after which the head of the queue blocks admission until it fits.  Admitted builds run
-// concurrently on their streams and overlap on the device; each frees its workspace when done.
+// times, after which the head of the queue blocks admission until it fits.  A request whose
+// workspace exceeds what the pool can ever give it (the budget less the lane's reservation)
+// fails at submission, so the head always fits once the running builds are done.  Admitted
+// builds run concurrently on their streams and overlap on the device; each frees its workspace
+// when done.  Destroying the server cancels the requests not admitted yet.
 //
 // Requests of at most `batch_max_keys` keys take a separate lane: one more worker gathers every
 // such request waiting at that moment (same gamma and try limit, at most kLaneMax) and builds
@@ -109,6 +112,7 @@ struct mphx_server {
     uint64_t next_ticket = 1;
     uint32_t running = 0;
     size_t in_use = 0, peak_in_use = 0;
+    size_t job_cap = 0;  // largest workspace a plain request can ever be given
 
     // batching lane
     uint64_t lane_max = 0;                  // 0 = no lane
@@ -200,19 +204,42 @@ struct mphx_server {
         (void)hipStreamDestroy(st);
     }
 
-    // Take the next admissible job (called with mu held); false if none fits now.
+    // Take the next admissible job (called with mu held); false if none fits now.  A later
+    // job admitted while the head does not fit counts as one pass of the head; once the head
+    // has been passed kMaxSkips times, nothing behind it is admitted before it.
     bool admit(Job& out, size_t& off)
     {
         for (size_t i = 0; i < pending.size(); i++) {
+            if (i > 0 && pending[0].skipped >= kMaxSkips)
+                return false;
             if (alloc.alloc(pending[i].ws_bytes, off)) {
+                if (i > 0) pending[0].skipped++;
                 out = pending[i];
                 pending.erase(pending.begin() + (long)i);
                 return true;
             }
-            if (i == 0 && ++pending[0].skipped > kMaxSkips)
-                return false;  // the head has waited long enough: no more backfill
         }
         return false;
+    }
+
+    // Complete every request not admitted yet with MPHX_ECANCELED (called with mu held).
+    void cancel_pending()
+    {
+        const double t = now_s();
+        for (std::deque<Job>* q : {&pending, &lane_pending}) {
+            for (const Job& j : *q) {
+                mphx_request_result r{};
+                r.status = MPHX_ECANCELED;
+                r.P = mphx_part_size(j.req.n, j.req.gamma_num ? j.req.gamma_num : 1,
+                                     j.req.gamma_den ? j.req.gamma_den : 1);
+                r.m = 3 * r.P;
+                r.t_submit = j.t_submit;
+                r.t_start = r.t_done = t;
+                done[j.ticket] = r;
+            }
+            q->clear();
+        }
+        cv_done.notify_all();
     }
 
     void worker()
@@ -302,6 +329,8 @@ int mphx_server_create(int device, size_t hbm_budget, uint32_t slots, uint64_t b
             s->in_use += ws + extra;
         }
     }
+    // the lane's reservation sits at the pool's start: the rest is one free range
+    s->job_cap = s->budget - s->in_use;
     for (uint32_t i = 0; i < slots; i++)
         s->workers.emplace_back([s] { s->worker(); });
     if (s->lane_max)
@@ -324,14 +353,15 @@ int mphx_server_submit(mphx_server* s, const mphx_request* req, uint64_t* ticket
     j.ticket = s->next_ticket++;
     *ticket = j.ticket;
     s->known[j.ticket] = true;
-    if (((j.ws_bytes + 255) & ~(size_t)255) > s->budget) {
+    auto fail_now = [&](int status) {
         mphx_request_result r{};
-        r.status = MPHX_ENOMEM;
+        r.status = status;
         r.t_submit = r.t_start = r.t_done = j.t_submit;
-        s->done[j.ticket] = r;  // can never fit: fails at once instead of waiting forever
+        s->done[j.ticket] = r;
         s->cv_done.notify_all();
         return MPHX_OK;
-    }
+    };
+    const size_t ws_al = (j.ws_bytes + 255) & ~(size_t)255;
     if (s->to_lane(j.req)) {
         const mphx_request& q = j.req;
         // only if the request's own slots (at its gamma) fit the lane's reserved workspace
@@ -344,6 +374,8 @@ int mphx_server_submit(mphx_server* s, const mphx_request* req, uint64_t* ticket
             return MPHX_OK;
         }
     }
+    // beyond what the pool can ever give a plain build: fails at once instead of waiting forever
+    if (ws_al > s->job_cap) return fail_now(MPHX_ENOMEM);
     s->pending.push_back(j);
     s->cv_work.notify_all();
     return MPHX_OK;
@@ -391,6 +423,7 @@ int mphx_server_destroy(mphx_server* s)
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stopping = true;
+        s->cancel_pending();
     }
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();

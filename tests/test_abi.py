@@ -98,10 +98,22 @@ def test_hem_workspaces_follow_k_range_and_shape(mx):
 
 
 def test_info_struct_mirrors_match_the_header(mx):
-    # the C side asserts the same sizes (80 and 40 bytes)
-    assert C.sizeof(mx._lib.MphfInfo) == 80 and C.sizeof(mx._lib.PeelInfo) == 40
+    # the C side asserts the same sizes (88 and 40 bytes)
+    assert C.sizeof(mx._lib.MphfInfo) == 88 and C.sizeof(mx._lib.PeelInfo) == 40
     names = [f for f, _ in mx._lib.MphfInfo._fields_]
-    assert names[-2:] == ["update_deletes", "update_records"]
+    assert names[-3:] == ["update_deletes", "update_records", "layer0"]
+
+
+def test_list_cap_option(mx):
+    assert mx.get_option("list_cap") == 0 and mx.get_option("list_fallbacks") == 0
+    for bad in (("list_cap", -1), ("list_fallbacks", 1)):
+        with pytest.raises(mx.MphxError):
+            mx.set_option(*bad)
+    mx.set_option("list_cap", 1000)
+    try:
+        assert mx.get_option("list_cap") == 1000
+    finally:
+        mx.set_option("list_cap", 0)
 
 
 def test_static_function_sizes(mx):

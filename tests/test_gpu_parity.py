@@ -423,3 +423,32 @@ def test_mphf_claim_lists_strings_retries_and_failures(mx, o, upd):
     finally:
         mx.set_option("claim_lists", 28)
         mx.set_option("update_lists", 16)
+
+
+@pytest.mark.parametrize("upd,cap", [(16, 1000), (0, 5000), (16, 0)],
+                         ids=["round0-deletes-overflow", "round1-claims-overflow", "no-overflow"])
+def test_claim_list_overflow_redoes_the_try_with_atomic_claims(mx, o, upd, cap):
+    """A claim-list round whose records exceed the list (forced here with a small list_cap)
+    makes the try start again with atomic claims; the MPHF and a static function built that
+    way equal the oracle's, and the fallback counter shows the redo happened."""
+    mx.set_option("claim_lists", 10)
+    mx.set_option("update_lists", upd)
+    mx.set_option("list_cap", cap)
+    mx.set_option("list_fallbacks", 0)
+    try:
+        keys = workloads.u64_keys(100_000, gen_seed=47)
+        got = mx.mphf_build_u64(dev(keys), seed=3)
+        rc, ref = o.mphf_build_u64(keys, seed=3)
+        assert rc == 0
+        _assert_mphf_equal(got, ref)
+        vals = (workloads.u64_keys(100_000, gen_seed=48) % 1000).astype(np.uint32)
+        sf = mx.sf_build_u64(dev(keys), dev(vals), 1000, seed=3)
+        rc, sref = o.sf_build_u64(keys, vals, 1000, seed=3)
+        assert rc == 0 and sf["seed_used"] == sref["seed_used"]
+        assert np.array_equal(host(sf["words"], np.uint64), sref["words"])
+        assert mx.get_option("list_fallbacks") == (2 if cap else 0)
+    finally:
+        mx.set_option("claim_lists", 28)
+        mx.set_option("update_lists", 16)
+        mx.set_option("list_cap", 0)
+        mx.set_option("list_fallbacks", 0)

@@ -115,3 +115,63 @@ def test_over_budget_request_fails_fast(mx):
     assert srv.wait(tb)["status"] == mx.ENOMEM
     assert srv.wait(ts)["status"] == 0
     srv.close()
+
+
+def _n_with_workspace_in(mx, lo, hi):
+    """Some n whose build workspace lies in (lo, hi] bytes (bisection on n)."""
+    a, b = 1, 1 << 31
+    while a < b:
+        mid = (a + b) // 2
+        if mx.mphf_workspace_bytes(mid) <= lo:
+            a = mid + 1
+        else:
+            b = mid
+    assert lo < mx.mphf_workspace_bytes(a) <= hi
+    return a
+
+
+def test_request_beyond_the_lane_reservation_fails_at_once(mx):
+    """With the batching lane holding part of the pool, a plain request whose workspace fits the
+    budget but not the rest of the pool can never start: it completes with ENOMEM at submission
+    instead of blocking the queue (and the server's shutdown) for good."""
+    budget = 2 << 30
+    srv = mx.Server(hbm_budget=budget, slots=2)
+    base = srv.stats()["in_use"]
+    assert base > 0  # the lane's reservation
+    n = _n_with_workspace_in(mx, budget - base, budget - 4096)
+    big = _dev(workloads.u64_keys(n, gen_seed=5))
+    tb = srv.submit_u64(big)
+    assert srv.poll(tb)["status"] == mx.ENOMEM  # done at submission
+    small = _dev(workloads.u64_keys(300_000, gen_seed=6))  # above the lane limit: a plain build
+    ts = srv.submit_u64(small, seed=4)
+    r = srv.wait(ts)
+    assert r["status"] == 0
+    a = mx.mphf_build_u64(small, seed=4)
+    assert r["seed_used"] == a["seed_used"] and np.array_equal(r["codes"].cpu().numpy(), a["codes"].cpu().numpy())
+    srv.close()
+
+
+def test_small_requests_pass_a_blocked_head_a_bounded_number_of_times(mx):
+    """A large request that does not fit beside a running one waits at the queue head; small
+    requests behind it that fit are admitted first (continuous admission), but at most 8 of
+    them before the head, and every request completes."""
+    n_big, n_small, k = 120_000_000, 200_000, 12
+    ws_big, ws_small = mx.mphf_workspace_bytes(n_big), mx.mphf_workspace_bytes(n_small)
+    budget = (ws_big + 255) // 256 * 256 + 4 * ((ws_small + 255) // 256 * 256) + 4096
+    srv = mx.Server(hbm_budget=budget, slots=4, batch_max_keys=0)
+    big1 = _dev(workloads.u64_keys(n_big, gen_seed=8))
+    big2 = _dev(workloads.u64_keys(n_big, gen_seed=9))
+    smalls = [_dev(workloads.u64_keys(n_small, gen_seed=30 + i)) for i in range(k)]
+    t1 = srv.submit_u64(big1, seed=1)
+    t2 = srv.submit_u64(big2, seed=2)
+    ts = [srv.submit_u64(x, seed=40 + i) for i, x in enumerate(smalls)]
+    r1, r2 = srv.wait(t1), srv.wait(t2)
+    rs = [srv.wait(t) for t in ts]
+    assert r1["status"] == 0 and r2["status"] == 0 and all(r["status"] == 0 for r in rs)
+    ahead = sum(r["t_start"] < r2["t_start"] for r in rs)
+    assert 1 <= ahead <= 8, ahead
+    # the two large builds never ran at once: the pool holds only one
+    assert r2["t_start"] >= r1["t_done"]
+    a = mx.mphf_build_u64(smalls[-1], seed=40 + k - 1)
+    assert np.array_equal(rs[-1]["codes"].cpu().numpy(), a["codes"].cpu().numpy())
+    srv.close()
