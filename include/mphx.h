@@ -159,6 +159,19 @@ MPHX_API int mphx_mphf_build_str(const uint8_t* bytes, const uint64_t* offs, uin
                         uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* codes,
                         uint64_t* rank, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mphx_mphf_build_u64 without the ws argument.  Its
+ * workspace is a device array of 128 MiB (134,217,728 bytes) that the library
+ * holds on every device it runs on until the process ends; the call allocates nothing.  It
+ * takes keys with a workspace up to that size (at gamma = 1.23, n <= 1,917,869 u64 keys) and
+ * returns MPHX_ENOMEM, with a message, beyond it.  Arguments, outputs and results are those of
+ * mphx_mphf_build_u64 (the same codes, rank and info).  Every call on a device shares that
+ * device's array: calls that overlap on one device (other host threads, other streams) race
+ * and must be serialized by the caller. */
+MPHX_API int mphx_mphf_build_u64_static(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gamma_num,
+                                        uint32_t gamma_den, uint32_t max_tries, uint64_t* codes, uint64_t* rank,
+                                        void* stream, mphx_mphf_info* info);
+
 /* Evaluate a built MPHF (Section 3 definition; Section 5 lookup): out[i] = f(key i) (dev,
  * n uint64).  P and seed are the build's info->P and info->seed_used.  Enqueue only. */
 MPHX_API int mphx_mphf_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,

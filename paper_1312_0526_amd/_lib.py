@@ -54,6 +54,7 @@ _SIGS = {
     "mphx_mphf_build_u64": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp, C.POINTER(MphfInfo)]),
     "mphx_mphf_build_str": (_i32, [_vp, _vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp,
                                    C.POINTER(MphfInfo)]),
+    "mphx_mphf_build_u64_static": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, C.POINTER(MphfInfo)]),
     "mphx_sf_bits": (_u32, [_u64]),
     "mphx_sf_words": (_u64, [_u64, _u32, _u32, _u64]),
     "mphx_sf_workspace_bytes": (_sz, [_u64, _u32, _u32, _i32]),
@@ -263,6 +264,26 @@ def mphf_build_u64(keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_trie
     info = MphfInfo()
     rc = lib().mphx_mphf_build_u64(_ptr(keys), n, seed, gamma[0], gamma[1], max_tries, _ptr(codes), _ptr(rank),
                                    _ptr(ws), ws.numel(), _stream(keys.device), C.byref(info))
+    if rc:
+        _err(rc, info.as_dict())
+    return _result(codes, rank, info, m)
+
+
+def mphf_build_u64_static(keys: torch.Tensor, out, seed: int = 0, gamma=(123, 100), max_tries: int = 64) -> dict:
+    """mphf_build_u64 through the allocation-free entry point: the library's own static device
+    workspace (128 MiB per device), outputs out=(codes, rank) passed by the caller; nothing is
+    allocated on the call."""
+    _check(keys, torch.int64, "keys")
+    n = keys.numel()
+    m = 3 * part_size(n, gamma)
+    codes, rank = out
+    _check(codes, torch.int64, "codes")
+    _check(rank, torch.int64, "rank")
+    if codes.numel() < (m + 31) // 32 or rank.numel() < (m + 511) // 512:
+        raise ValueError("output buffers too small")
+    info = MphfInfo()
+    rc = lib().mphx_mphf_build_u64_static(_ptr(keys), n, seed, gamma[0], gamma[1], max_tries, _ptr(codes), _ptr(rank),
+                                          _stream(keys.device), C.byref(info))
     if rc:
         _err(rc, info.as_dict())
     return _result(codes, rank, info, m)

@@ -963,6 +963,60 @@ int mphx_mphf_build_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_
                       info);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of the allocation-free build: one array per device, held from the library's load
+// to the end of the process.  Host code never passes the array's name to a kernel or a copy:
+// on the host it is only a stand-in for the device symbol, so each device's address is looked
+// up once (with that device current) and kept here.
+constexpr size_t kStaticScratchBytes = 128ull << 20;
+__device__ __attribute__((used)) __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // by device ordinal
+
+int static_scratch(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr.size() <= (size_t)dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(MPHX_EDEVICE, "device %d: address of the static workspace: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MPHX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mphx_mphf_build_u64_static(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gamma_num,
+                               uint32_t gamma_den, uint32_t max_tries, uint64_t* codes, uint64_t* rank, void* stream,
+                               mphx_mphf_info* info)
+{
+    g_err.clear();
+    if (gamma_num == 0 || gamma_den == 0) return fail(MPHX_EINVAL, "gamma must be a positive fraction");
+    if (n >= 0xFFFFFFFFull) return fail(MPHX_EINVAL, "n must be < 2^32 - 1");
+    const size_t need = mphx_mphf_workspace_bytes(n, gamma_num, gamma_den, MPHX_KEYS_U64);
+    if (need > kStaticScratchBytes)
+        return fail(MPHX_ENOMEM, "%llu keys need %zu bytes of workspace; the allocation-free build has %zu",
+                    (unsigned long long)n, need, kStaticScratchBytes);
+    void* ws = nullptr;
+    int rc = static_scratch(&ws);
+    if (rc) return rc;
+    KeySrc k{MPHX_KEYS_U64, keys, nullptr, nullptr};
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, codes, rank, ws, kStaticScratchBytes,
+                      (hipStream_t)stream, info);
+}
+
 int mphx_mphf_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint32_t gamma_num,
                         uint32_t gamma_den, uint32_t max_tries, uint64_t* codes, uint64_t* rank, void* ws,
                         size_t ws_bytes, void* stream, mphx_mphf_info* info)
