@@ -51,10 +51,10 @@ def _bind(lib):
         "orc_mphf_build_str": (C.c_int, [_u8p, _u64p, C.c_uint64, C.c_uint64, C.c_uint32, C.c_uint32,
                                          C.c_uint32, _u64p, _u64p, _u64p]),
         "orc_hem_signature_u64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
-        "orc_hem_signature_str": (C.c_uint64, [_u8p, C.c_uint64, C.c_uint64]),
-        "orc_hem_build": (C.c_int, [_u64p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+        "orc_hem_signature_str": (None, [_u8p, C.c_uint64, C.c_uint64, _u64p, _u64p]),
+        "orc_hem_build": (C.c_int, [_u64p, _u64p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                     _u64p, _u64p, _u64p, _u64p, _u64p, _u64p]),
-        "orc_hem_lookup": (None, [_u64p, C.c_uint64, C.c_uint32, _u64p, _u64p, _u64p, _u64p, _u64p, _u64p,
+        "orc_hem_lookup": (None, [_u64p, _u64p, C.c_uint64, C.c_uint32, _u64p, _u64p, _u64p, _u64p, _u64p, _u64p,
                                   C.c_uint32, C.c_uint32, _u64p]),
         "orc_sf_bits": (C.c_uint32, [C.c_uint64]),
         "orc_sf_assign": (C.c_int, [_u32p, C.c_uint64, C.c_uint64, _u32p, _u32p, _u8p, _u32p, C.c_uint64, _u32p]),
@@ -322,20 +322,34 @@ class Oracle:
         return np.array([self.lib.orc_hem_signature_u64(int(x), seed) for x in keys], np.uint64)
 
     def hem_signatures_str(self, data, offs, seed):
+        """(n, 2) array: each string's 128-bit signature (a, b)."""
         data = np.ascontiguousarray(data, dtype=np.uint8)
         if data.size == 0:
             data = np.zeros(1, np.uint8)
         offs = np.ascontiguousarray(offs, dtype=np.uint64)
-        out = np.empty(len(offs) - 1, np.uint64)
+        out = np.empty((len(offs) - 1, 2), np.uint64)
         base = data.ctypes.data
+        a, b = C.c_uint64(), C.c_uint64()
         for i in range(len(out)):
             p = C.cast(base + int(offs[i]), _u8p)
-            out[i] = self.lib.orc_hem_signature_str(p, int(offs[i + 1] - offs[i]), seed)
+            self.lib.orc_hem_signature_str(p, int(offs[i + 1] - offs[i]), seed, C.byref(a), C.byref(b))
+            out[i, 0], out[i, 1] = a.value, b.value
         return out
 
+    @staticmethod
+    def _sig_words(sigs):
+        """First and second signature words: a 1-D array holds 64-bit (u64-key) signatures, an
+        (n, 2) array 128-bit (string) ones."""
+        sigs = np.asarray(sigs, dtype=np.uint64)
+        if sigs.ndim == 2:
+            first = np.ascontiguousarray(sigs[:, 0])
+            second = np.ascontiguousarray(sigs[:, 1])
+            return first, (second if len(second) else np.zeros(1, np.uint64)), len(first)
+        return np.ascontiguousarray(sigs), None, len(sigs)
+
     def hem_build(self, sigs, k, seed=0, gnum=123, gden=100, max_tries=64):
-        sigs = np.ascontiguousarray(sigs, dtype=np.uint64)
-        n = len(sigs)
+        sigs, sigs2, n = self._sig_words(sigs)
+        s2 = _p(sigs2, _u64p) if sigs2 is not None else C.cast(None, _u64p)
         B = 1 << k
         bo = np.zeros(B + 1, np.uint64)
         co = np.zeros(B + 1, np.uint64)
@@ -343,23 +357,24 @@ class Oracle:
         seeds = np.zeros(B, np.uint64)
         sg = sigs if n else np.zeros(1, np.uint64)
         none = C.cast(None, _u64p)
-        rc = self.lib.orc_hem_build(_p(sg, _u64p), n, k, seed, gnum, gden, max_tries, _p(bo, _u64p), _p(co, _u64p),
-                                    _p(ro, _u64p), _p(seeds, _u64p), none, none)
+        rc = self.lib.orc_hem_build(_p(sg, _u64p), s2, n, k, seed, gnum, gden, max_tries, _p(bo, _u64p),
+                                    _p(co, _u64p), _p(ro, _u64p), _p(seeds, _u64p), none, none)
         if rc != 0:
             return int(rc), None
         codes = np.zeros(max(int(co[-1]), 1), np.uint64)
         rank = np.zeros(max(int(ro[-1]), 1), np.uint64)
-        rc = self.lib.orc_hem_build(_p(sg, _u64p), n, k, seed, gnum, gden, max_tries, _p(bo, _u64p), _p(co, _u64p),
-                                    _p(ro, _u64p), _p(seeds, _u64p), _p(codes, _u64p), _p(rank, _u64p))
+        rc = self.lib.orc_hem_build(_p(sg, _u64p), s2, n, k, seed, gnum, gden, max_tries, _p(bo, _u64p),
+                                    _p(co, _u64p), _p(ro, _u64p), _p(seeds, _u64p), _p(codes, _u64p), _p(rank, _u64p))
         return int(rc), dict(bucket_off=bo, code_off=co, rank_off=ro, seeds=seeds, codes=codes[: int(co[-1])],
                              rank=rank[: int(ro[-1])], k=k)
 
     def hem_lookup(self, r, sigs, gnum=123, gden=100):
-        sigs = np.ascontiguousarray(sigs, dtype=np.uint64)
-        out = np.empty(len(sigs), np.uint64)
+        sigs, sigs2, n = self._sig_words(sigs)
+        s2 = _p(sigs2, _u64p) if sigs2 is not None else C.cast(None, _u64p)
+        out = np.empty(n, np.uint64)
         codes = r["codes"] if len(r["codes"]) else np.zeros(1, np.uint64)
         rank = r["rank"] if len(r["rank"]) else np.zeros(1, np.uint64)
-        self.lib.orc_hem_lookup(_p(sigs, _u64p), len(sigs), r["k"], _p(r["bucket_off"], _u64p),
+        self.lib.orc_hem_lookup(_p(sigs if n else np.zeros(1, np.uint64), _u64p), s2, n, r["k"], _p(r["bucket_off"], _u64p),
                                 _p(r["code_off"], _u64p), _p(r["rank_off"], _u64p), _p(r["seeds"], _u64p),
                                 _p(codes, _u64p), _p(rank, _u64p), gnum, gden, _p(out, _u64p))
         return out

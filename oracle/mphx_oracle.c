@@ -41,14 +41,16 @@
  *  - rank table: one u64 per 512 vertices holding the number of hinge vertices strictly
  *    before the block (exclusive rank), so the MPHF maps onto [0, n);
  *  - retries: seed, seed+1, ... up to max_tries; degree above 255 is an error;
- *  - HEM split (Section 3, "Practical workarounds"): a key's 64-bit signature is
- *    fin(s + 4*GAMMA) for u64 keys (s = key XOR seed, a bijection: no two keys collide) and
- *    fin(a XOR fin(b)) of the string digest (a, b); the top k bits pick one of 2^k buckets,
- *    the signature with its two 32-bit halves swapped is the key inside the bucket, and each
- *    bucket gets the MWHC MPHF of its keys (hash seed = the build's seed, retries seed+1, ...);
- *    f(x) = (keys in earlier buckets) + the bucket MPHF's value; a bucket that fails (two keys
- *    with one signature, or max_tries 2-cores) fails the build, which the caller redoes with
- *    another seed;
+ *  - HEM split (Section 3, "Practical workarounds", signatures chosen so that no two keys
+ *    share one): a u64 key's signature is the 64-bit fin(s + 4*GAMMA) (s = key XOR seed, a
+ *    bijection) and a byte string's the whole 128-bit digest (a, b) under the seed; the top k
+ *    bits of the signature's first word pick one of 2^k buckets; inside its bucket the key is
+ *    the digest pair (swap(first word), second word) -- (swap(sig), swap(sig)) for u64 keys,
+ *    (swap(a), b) for strings, swap exchanging the 32-bit halves -- whose edge under seed t is
+ *    the edge of the digest (x XOR t, y XOR t); each bucket gets the MWHC MPHF of its keys
+ *    (hash seed = the build's seed, retries seed+1, ...); f(x) = (keys in earlier buckets) +
+ *    the bucket MPHF's value; a bucket that fails (max_tries 2-cores) fails the build, which
+ *    the caller redoes with another seed;
  *  - static functions (Section 3, any sigma in [1, 2^32]): values must lie in [0, sigma);
  *    u = 0 on vertices that are no hinge; each u is stored in b = (bits of sigma - 1) bits,
  *    vertex v's field at bits [v*b, v*b + b) of the little-endian bit string of the u64
@@ -152,6 +154,14 @@ void orc_hash_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64
         orc_digest_str(bytes + offs[i], offs[i + 1] - offs[i], seed, &a, &b);
         orc_edge_of_digest(a, b, P, edges + 3 * i);
     }
+}
+
+/* Keys given as 128-bit digests (x_i, y_i): under seed t the edge is that of the digest
+ * (x_i XOR t, y_i XOR t).  A u64 key is the pair (key, key). */
+void orc_hash_pairs(const uint64_t* x, const uint64_t* y, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges)
+{
+    for (uint64_t i = 0; i < n; i++)
+        orc_edge_of_digest(x[i] ^ seed, y[i] ^ seed, P, edges + 3 * i);
 }
 
 /* ------------------------------------------------------------------------------------------
@@ -526,6 +536,8 @@ static int orc_keys_equal(int kind, const void* keys, const uint64_t* offs, uint
 {
     if (kind == 0)
         return ((const uint64_t*)keys)[i] == ((const uint64_t*)keys)[j];
+    if (kind == 2) /* digest pairs: first words in keys, second words in offs */
+        return ((const uint64_t*)keys)[i] == ((const uint64_t*)keys)[j] && offs[i] == offs[j];
     uint64_t li = offs[i + 1] - offs[i], lj = offs[j + 1] - offs[j];
     if (li != lj)
         return 0;
@@ -544,8 +556,10 @@ static int orc_cmp_triple(const void* pa, const void* pb)
     return a < b ? -1 : (a > b);
 }
 
-/* values == NULL: the MPHF (words = 2-bit codes, rank = samples); else the static function
- * with those values in [0, sigma) (words = packed u, rank unused). */
+/* kind 0: u64 keys; 1: byte strings (keys = bytes, offs = offsets); 2: digest pairs (keys =
+ * first words, offs = second words).  values == NULL: the MPHF (words = 2-bit codes, rank =
+ * samples); else the static function with those values in [0, sigma) (words = packed u, rank
+ * unused). */
 static int orc_build(int kind, const void* keys, const uint64_t* offs, uint64_t n, const uint32_t* values,
                      uint64_t sigma, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
                      uint64_t* words, uint64_t* rank, uint64_t* info)
@@ -580,6 +594,8 @@ static int orc_build(int kind, const void* keys, const uint64_t* offs, uint64_t 
         uint64_t s = seed + t;
         if (kind == 0)
             orc_hash_u64((const uint64_t*)keys, n, s, P, edges);
+        else if (kind == 2)
+            orc_hash_pairs((const uint64_t*)keys, offs, n, s, P, edges);
         else
             orc_hash_str((const uint8_t*)keys, offs, n, s, P, edges);
         int rc = orc_peel(edges, n, m, P, order, round, core, hinge, pinfo);
@@ -673,23 +689,31 @@ int orc_sf_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t*
  * ------------------------------------------------------------------------------------------ */
 uint64_t orc_hem_signature_u64(uint64_t key, uint64_t seed) { return orc_fin((key ^ seed) + 4 * ORC_GAMMA); }
 
-uint64_t orc_hem_signature_str(const uint8_t* x, uint64_t len, uint64_t seed)
+/* A byte string's signature: its whole 128-bit digest (a, b) under the seed. */
+void orc_hem_signature_str(const uint8_t* x, uint64_t len, uint64_t seed, uint64_t* a, uint64_t* b)
 {
-    uint64_t a, b;
-    orc_digest_str(x, len, seed, &a, &b);
-    return orc_fin(a ^ orc_fin(b));
+    orc_digest_str(x, len, seed, a, b);
 }
 
-/* The key a signature stands for inside its bucket: its two 32-bit halves swapped. */
+/* The first word of the pair a signature stands for inside its bucket: the signature's first
+ * word with its two 32-bit halves swapped. */
 static uint64_t orc_hem_bucket_key(uint64_t sig) { return (sig << 32) | (sig >> 32); }
 
-/* sigs: the n signatures.  k in [0, 32].  Outputs: bucket_off (2^k + 1 key offsets), code_off
+/* The bucket key of signature i: (swap(sigs[i]), sigs2[i]), or (swap, swap) without sigs2. */
+static void orc_hem_pair(const uint64_t* sigs, const uint64_t* sigs2, uint64_t i, uint64_t* x, uint64_t* y)
+{
+    *x = orc_hem_bucket_key(sigs[i]);
+    *y = sigs2 ? sigs2[i] : *x;
+}
+
+/* sigs: the n signatures' first words; sigs2: their second words (string keys) or NULL (u64
+ * keys).  k in [0, 32].  Outputs: bucket_off (2^k + 1 key offsets), code_off
  * and rank_off (2^k + 1: where bucket b's ceil(m_b/32) codes and ceil(m_b/512) rank samples
  * start), seeds (2^k: each bucket's seed used), codes and rank (sized by code_off[2^k] and
  * rank_off[2^k]: the caller calls with codes == NULL first to learn them).  Returns ORC_OK,
  * or the first failing bucket's status (ORC_ECORE / ORC_EDUP / ORC_ERANGE). */
-int orc_hem_build(const uint64_t* sigs, uint64_t n, uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden,
-                  uint32_t max_tries, uint64_t* bucket_off, uint64_t* code_off, uint64_t* rank_off,
+int orc_hem_build(const uint64_t* sigs, const uint64_t* sigs2, uint64_t n, uint32_t k, uint64_t seed, uint32_t gnum,
+                  uint32_t gden, uint32_t max_tries, uint64_t* bucket_off, uint64_t* code_off, uint64_t* rank_off,
                   uint64_t* seeds, uint64_t* codes, uint64_t* rank)
 {
     if (k > 32 || gnum == 0 || gden == 0 || max_tries == 0)
@@ -709,47 +733,56 @@ int orc_hem_build(const uint64_t* sigs, uint64_t n, uint32_t k, uint64_t seed, u
     }
     if (!codes)
         return ORC_OK;
-    /* counting sort of the bucket keys by bucket, stable in key order */
-    uint64_t* keys = malloc((n ? n : 1) * sizeof(uint64_t));
+    /* counting sort of the bucket keys (digest pairs) by bucket, stable in key order */
+    uint64_t* kx = malloc((n ? n : 1) * sizeof(uint64_t));
+    uint64_t* ky = malloc((n ? n : 1) * sizeof(uint64_t));
     uint64_t* fill = malloc(B * sizeof(uint64_t));
-    if (!keys || !fill) {
-        free(keys); free(fill);
+    if (!kx || !ky || !fill) {
+        free(kx); free(ky); free(fill);
         return ORC_ENOMEM;
     }
     for (uint64_t b = 0; b < B; b++)
         fill[b] = bucket_off[b];
-    for (uint64_t i = 0; i < n; i++)
-        keys[fill[k ? sigs[i] >> (64 - k) : 0]++] = orc_hem_bucket_key(sigs[i]);
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t at = fill[k ? sigs[i] >> (64 - k) : 0]++;
+        orc_hem_pair(sigs, sigs2, i, &kx[at], &ky[at]);
+    }
     int status = ORC_OK;
     for (uint64_t b = 0; b < B && status == ORC_OK; b++) {
         uint64_t info[6];
-        status = orc_mphf_build_u64(keys + bucket_off[b], bucket_off[b + 1] - bucket_off[b], seed, gnum, gden,
-                                    max_tries, codes + code_off[b], rank + rank_off[b], info);
+        uint64_t lo = bucket_off[b];
+        status = orc_build(2, kx + lo, ky + lo, bucket_off[b + 1] - lo, NULL, 0, seed, gnum, gden, max_tries,
+                           codes + code_off[b], rank + rank_off[b], info);
         seeds[b] = info[2];
     }
-    free(keys);
+    free(kx);
+    free(ky);
     free(fill);
     return status;
 }
 
-/* f(x) for a key with signature sig. */
-static uint64_t orc_hem_eval(uint64_t sig, uint32_t k, const uint64_t* bucket_off, const uint64_t* code_off,
-                             const uint64_t* rank_off, const uint64_t* seeds, const uint64_t* codes,
-                             const uint64_t* rank, uint32_t gnum, uint32_t gden)
+/* f(x) for the key of signature i. */
+static uint64_t orc_hem_eval(const uint64_t* sigs, const uint64_t* sigs2, uint64_t i, uint32_t k,
+                             const uint64_t* bucket_off, const uint64_t* code_off, const uint64_t* rank_off,
+                             const uint64_t* seeds, const uint64_t* codes, const uint64_t* rank, uint32_t gnum,
+                             uint32_t gden)
 {
+    uint64_t sig = sigs[i];
     uint64_t b = k ? sig >> (64 - k) : 0;
     uint64_t nb = bucket_off[b + 1] - bucket_off[b];
-    uint64_t key = orc_hem_bucket_key(sig), f;
-    orc_lookup_u64(codes + code_off[b], rank + rank_off[b], orc_part_size(nb, gnum, gden), seeds[b], &key, 1, &f);
-    return bucket_off[b] + f;
+    uint64_t x, y;
+    uint32_t t[3];
+    orc_hem_pair(sigs, sigs2, i, &x, &y);
+    orc_hash_pairs(&x, &y, 1, seeds[b], orc_part_size(nb, gnum, gden), t);
+    return bucket_off[b] + orc_eval_edge(codes + code_off[b], rank + rank_off[b], t);
 }
 
-void orc_hem_lookup(const uint64_t* sigs, uint64_t n, uint32_t k, const uint64_t* bucket_off,
+void orc_hem_lookup(const uint64_t* sigs, const uint64_t* sigs2, uint64_t n, uint32_t k, const uint64_t* bucket_off,
                     const uint64_t* code_off, const uint64_t* rank_off, const uint64_t* seeds,
                     const uint64_t* codes, const uint64_t* rank, uint32_t gnum, uint32_t gden, uint64_t* out)
 {
     for (uint64_t i = 0; i < n; i++)
-        out[i] = orc_hem_eval(sigs[i], k, bucket_off, code_off, rank_off, seeds, codes, rank, gnum, gden);
+        out[i] = orc_hem_eval(sigs, sigs2, i, k, bucket_off, code_off, rank_off, seeds, codes, rank, gnum, gden);
 }
 
 /* ------------------------------------------------------------------------------------------

@@ -593,12 +593,39 @@ def pin_hem(o) -> list:
                 inb = np.sort(f[top == b])
                 if not np.array_equal(inb, np.arange(bo[b], bo[b + 1], dtype=np.uint64)):
                     bad.append(f"hem k=6: bucket {b}'s keys do not map onto its own range")
+    # string keys: the signature is the whole 128-bit digest, the bucket the top bits of its
+    # first word
     data, offs = workloads.str_keys(9000, gen_seed=12)
     sg = o.hem_signatures_str(data, offs, 2)
+    for i in (0, 4321, 8999):
+        a_, b_ = o.digest_str(bytes(data[offs[i]:offs[i + 1]]), 2)
+        if (int(sg[i, 0]), int(sg[i, 1])) != (a_, b_):
+            bad.append("hem string signature is not the key's 128-bit digest")
     rc, r = o.hem_build(sg, 3, seed=2)
     f = o.hem_lookup(r, sg) if rc == 0 else None
     if rc != 0 or not np.array_equal(np.sort(f), np.arange(9000, dtype=np.uint64)):
         bad.append(f"hem strings: status {rc} or not a bijection")
+    elif not np.array_equal(np.diff(r["bucket_off"].astype(np.int64)),
+                            np.bincount((sg[:, 0] >> np.uint64(61)).astype(np.int64), minlength=8)):
+        bad.append("hem strings: buckets are not the top bits of the signature's first word")
+    # a 128-bit signature whose second word is the first with its halves swapped stands for the
+    # same bucket key as the 64-bit signature: both splits are the same structure
+    sw = (sigs << np.uint64(32)) | (sigs >> np.uint64(32))
+    for k in (0, 6):
+        rc1, r1 = o.hem_build(sigs, k, seed=5)
+        rc2, r2 = o.hem_build(np.stack([sigs, sw], axis=1), k, seed=5)
+        if rc1 != 0 or rc2 != 0 or any(not np.array_equal(r1[x], r2[x]) for x in
+                                      ("bucket_off", "seeds", "codes", "rank")):
+            bad.append(f"hem k={k}: a 128-bit signature (s, swap(s)) differs from the 64-bit signature s")
+    # signatures that agree in their first word and differ in the second are distinct keys:
+    # no collision, the split is a bijection
+    rng = np.random.default_rng(3)
+    pairs = rng.integers(0, 1 << 63, size=(3000, 2), dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+    pairs[2970:, 0] = pairs[:30, 0]
+    rc, r = o.hem_build(pairs, 2, seed=9)
+    f = o.hem_lookup(r, pairs) if rc == 0 else None
+    if rc != 0 or not np.array_equal(np.sort(f), np.arange(3000, dtype=np.uint64)):
+        bad.append(f"hem: signatures sharing their first word collide (status {rc})")
     return bad
 
 

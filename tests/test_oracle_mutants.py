@@ -41,7 +41,11 @@ MUTANTS = {
     "static function lookup drops a vertex": ("+ orc_sf_field(words, b, t[2])) % sigma", ") % sigma"),
     "hem signature adds the seed": ("return orc_fin((key ^ seed) + 4 * ORC_GAMMA);", "return orc_fin((key + seed) + 4 * ORC_GAMMA);"),
     "hem bucket key not swapped": ("return (sig << 32) | (sig >> 32);", "return sig;"),
-    "hem bucket offset dropped": ("return bucket_off[b] + f;", "return f;"),
+    "hem bucket offset dropped": ("return bucket_off[b] + orc_eval_edge(", "return 0 * bucket_off[b] + orc_eval_edge("),
+    "hem string signature folded to its first word": ("*y = sigs2 ? sigs2[i] : *x;", "*y = *x;"),
+    "hem pair hash without the seed on the second word": ("orc_edge_of_digest(x[i] ^ seed, y[i] ^ seed, P, edges + 3 * i);",
+                                                         "orc_edge_of_digest(x[i] ^ seed, y[i], P, edges + 3 * i);"),
+    "hem string bucket key unswapped": ("*x = orc_hem_bucket_key(sigs[i]);", "*x = sigs2 ? sigs[i] : orc_hem_bucket_key(sigs[i]);"),
     "hem bucket from the low bits": ("uint64_t b = k ? sig >> (64 - k) : 0;", "uint64_t b = k ? sig & ((1ull << k) - 1) : 0;"),
     "general r hinge takes the higher position": ("} else if (hinge[e] > k) {", "} else if (hinge[e] < k) {"),
     "general r deletes skip the last vertex": ("            for (uint32_t k = 0; k < r; k++) {\n                uint32_t u = edges[(uint64_t)r * e + k];",
