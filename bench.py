@@ -770,22 +770,22 @@ def sf_leg(args, mx, torch, n: int, kind: int, ws, keys=None, data=None, offs=No
 
 
 def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None) -> dict:
-    """HEM split (Section 3) of the same keys for each k in --hem-k: 64-bit signatures, 2^k
-    buckets by their top bits, one MWHC MPHF per bucket by the batched kernel; builds timed like
+    """HEM split (Section 3) of the same keys for each k in --hem-k: signatures (64-bit for u64
+    keys, the whole 128-bit digest for strings), 2^k buckets by their top bits, one MWHC MPHF per bucket by the batched kernel; builds timed like
     the plain leg (steps capped at 3), then one lookup of all n keys timed with HIP events and
     checked to be a bijection onto [0, n)."""
     dev = torch.device("cuda:0")
     gamma = (123, 100)
-    ws = torch.empty(max(mx.hem_workspace_bytes(n, k, gamma) for k in args.hem_k), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(mx.hem_workspace_bytes(n, k, gamma, kind) for k in args.hem_k), dtype=torch.uint8, device=dev)
     out = torch.empty(n, dtype=torch.int64, device=dev)
     rows = {}
     for k, tune in [(k, t) for k in args.hem_k for t in args.hem_tune]:
         block, grid = (int(x) for x in tune.split("x"))
         mx.set_option("hem_block", block)
         mx.set_option("hem_grid", grid)
-        if ws.numel() < mx.hem_workspace_bytes(n, k, gamma):
+        if ws.numel() < mx.hem_workspace_bytes(n, k, gamma, kind):
             del ws
-            ws = torch.empty(mx.hem_workspace_bytes(n, k, gamma), dtype=torch.uint8, device=dev)
+            ws = torch.empty(mx.hem_workspace_bytes(n, k, gamma, kind), dtype=torch.uint8, device=dev)
 
         def step():
             if kind == mx.KEYS_U64:
@@ -876,7 +876,7 @@ def hem_host_leg(args, mx, torch) -> dict:
         f"generated in {time.perf_counter() - t0:.1f} s")
     need = mx.hem_host_workspace_bytes(n, k, mx.KEYS_U64, chunk, 0, batch, gamma)
     ws = torch.empty(need, dtype=torch.uint8, device=dev)
-    in_place = mx.hem_workspace_bytes(n, k, gamma) + 8 * n  # the in-HBM split: keys + its workspace
+    in_place = mx.hem_workspace_bytes(n, k, gamma, mx.KEYS_U64) + 8 * n  # the in-HBM split: keys + its workspace
     log(f"[hem_host] device workspace {need / 1e9:.1f} GB (the in-HBM split would need {in_place / 1e9:.1f} GB)")
 
     mx.set_option("timing", 1)

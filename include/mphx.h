@@ -332,27 +332,32 @@ MPHX_API int mphx_graph_launch(void* graph, void* stream);
 MPHX_API int mphx_graph_destroy(void* graph);
 
 /* ---------------------------------------------------------------------------------------
- * HEM split of one key set (Section 3, "Practical workarounds"): each key gets a 64-bit
- * signature -- fin(s + 4*GAMMA), s = key XOR seed, for u64 keys (a bijection: no two keys
- * collide); fin(a XOR fin(b)) of the string digest (a, b) -- whose top k bits pick one of 2^k
- * buckets; the signature with its two 32-bit halves swapped is the key inside the bucket, and
- * each bucket gets the MWHC MPHF of its keys (hash seed `seed`, retries seed+1, ... per bucket)
- * built by the batched kernel.  f(x) = bucket_off[b] + the bucket MPHF's value.
+ * HEM split of one key set (Section 3, "Practical workarounds", with signatures that no two
+ * keys share): a u64 key's signature is fin(s + 4*GAMMA), s = key XOR seed (64 bits, a
+ * bijection); a string key's is its whole 128-bit digest (a, b) under seed (two distinct
+ * strings share one with probability about n^2 / 2^129).  The top k bits of the signature's
+ * first word pick one of 2^k buckets; inside it the key is the digest pair (swap(first word),
+ * second word) -- (swap(sig), swap(sig)) for u64 keys, (swap(a), b) for strings, swap
+ * exchanging the 32-bit halves -- whose edge under seed t is that of the digest (x XOR t,
+ * y XOR t) (for u64 keys: the MWHC hash of the key swap(sig)).  Each bucket gets the MWHC MPHF
+ * of its keys (hash seed `seed`, retries seed+1, ... per bucket) built by the batched kernel.
+ * f(x) = bucket_off[b] + the bucket MPHF's value.
  *   k in [9, 20] (2^k buckets; beyond 2^18 each of the 2^18 buckets of the top 18 bits is split
  *   by the next k - 18 bits); outputs (dev, caller-allocated): bucket_off, code_off, rank_off
  *   (2^k + 1 each: where bucket b's keys, ceil(m_b/32) code words and ceil(m_b/512) rank
  *   samples start), seeds (2^k: each bucket's seed used), codes and rank (at least the
- *   mphx_hem_capacity words).  ws (dev, 256-byte aligned): mphx_hem_workspace_bytes bytes;
+ *   mphx_hem_capacity words).  ws (dev, 256-byte aligned): mphx_hem_workspace_bytes bytes
+ *   (key_kind MPHX_KEYS_U64: 8-byte signature records; MPHX_KEYS_STR: 16-byte ones);
  *   it admits buckets up to n/2^k + 8 sqrt(n/2^k) + 64 keys (MPHX_ENOMEM beyond).  Pick k so
  *   that buckets hold hundreds of keys or more: at gamma < 1.5 a bucket of exactly two keys
  *   has parts of one vertex, both edges are (0, 1, 2), and it fails under every seed.
  * Errors: MPHX_EINVAL for bad arguments; MPHX_ECORE (MPHX_ERANGE) when some bucket failed --
- * a 2-core on every try, or two keys with one 64-bit signature (probability about
- * n^2 / 2^65 for string keys) -- info->n_core then counts the failed buckets: build again
- * with another seed.  info->tries / n_rounds are the largest over the buckets.  Synchronises.
+ * a 2-core on every try (or two equal keys) -- info->n_core then counts the failed buckets:
+ * build again with another seed.  info->tries / n_rounds are the largest over the buckets.  Synchronises.
  * mphx_hem_lookup_*: out[i] = f(key i) (dev, n uint64); seed and k as built.  Enqueue only.
  * --------------------------------------------------------------------------------------- */
-MPHX_API size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den);
+MPHX_API size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den,
+                                         int key_kind);
 MPHX_API int mphx_hem_capacity(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den, uint64_t* code_words,
                                uint64_t* rank_words);
 MPHX_API int mphx_hem_build_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed, uint32_t gamma_num,
@@ -373,7 +378,8 @@ MPHX_API int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint
  *   (strings: and at most chunk_bytes bytes from the 256-byte boundary below the chunk's first
  *   key, so every key must be shorter than chunk_bytes - 255).  Pinned memory (hipHostMalloc)
  *   gives the full PCIe rate; pageable memory works, slower.  Device memory: 8 bytes per key
- *   for the grouped signatures plus chunk and batch buffers: mphx_hem_host_workspace_bytes
+ *   (u64 keys) or 16 (strings) for the grouped signatures plus chunk and batch buffers:
+ *   mphx_hem_host_workspace_bytes
  *   (kind = MPHX_KEYS_U64 or MPHX_KEYS_STR; chunk_bytes ignored for u64; 0 for bad
  *   arguments).  Each chunk's signatures are grouped by their top k - 8 bits; then batches of
  *   consecutive groups holding at most batch_keys keys are gathered from every chunk,

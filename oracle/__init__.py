@@ -52,6 +52,8 @@ def _bind(lib):
                                          C.c_uint32, _u64p, _u64p, _u64p]),
         "orc_hem_signature_u64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
         "orc_hem_signature_str": (None, [_u8p, C.c_uint64, C.c_uint64, _u64p, _u64p]),
+        "orc_hem_signatures_u64": (None, [_u64p, C.c_uint64, C.c_uint64, _u64p]),
+        "orc_hem_signatures_str": (None, [_u8p, _u64p, C.c_uint64, C.c_uint64, _u64p, _u64p]),
         "orc_hem_build": (C.c_int, [_u64p, _u64p, C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                     _u64p, _u64p, _u64p, _u64p, _u64p, _u64p]),
         "orc_hem_lookup": (None, [_u64p, _u64p, C.c_uint64, C.c_uint32, _u64p, _u64p, _u64p, _u64p, _u64p, _u64p,
@@ -319,7 +321,10 @@ class Oracle:
     # --- HEM split (Section 3: signatures, 2^k buckets, one MPHF per bucket) ---------------------
     def hem_signatures_u64(self, keys, seed):
         keys = np.ascontiguousarray(keys, dtype=np.uint64)
-        return np.array([self.lib.orc_hem_signature_u64(int(x), seed) for x in keys], np.uint64)
+        out = np.empty(len(keys), np.uint64)
+        if len(keys):
+            self.lib.orc_hem_signatures_u64(_p(keys, _u64p), len(keys), seed, _p(out, _u64p))
+        return out
 
     def hem_signatures_str(self, data, offs, seed):
         """(n, 2) array: each string's 128-bit signature (a, b)."""
@@ -327,14 +332,11 @@ class Oracle:
         if data.size == 0:
             data = np.zeros(1, np.uint8)
         offs = np.ascontiguousarray(offs, dtype=np.uint64)
-        out = np.empty((len(offs) - 1, 2), np.uint64)
-        base = data.ctypes.data
-        a, b = C.c_uint64(), C.c_uint64()
-        for i in range(len(out)):
-            p = C.cast(base + int(offs[i]), _u8p)
-            self.lib.orc_hem_signature_str(p, int(offs[i + 1] - offs[i]), seed, C.byref(a), C.byref(b))
-            out[i, 0], out[i, 1] = a.value, b.value
-        return out
+        n = len(offs) - 1
+        a, b = np.empty(max(n, 1), np.uint64), np.empty(max(n, 1), np.uint64)
+        if n:
+            self.lib.orc_hem_signatures_str(_p(data, _u8p), _p(offs, _u64p), n, seed, _p(a, _u64p), _p(b, _u64p))
+        return np.stack([a[:n], b[:n]], axis=1)
 
     @staticmethod
     def _sig_words(sigs):

@@ -695,6 +695,20 @@ void orc_hem_signature_str(const uint8_t* x, uint64_t len, uint64_t seed, uint64
     orc_digest_str(x, len, seed, a, b);
 }
 
+/* Signatures of n keys (the per-key functions above, in a loop). */
+void orc_hem_signatures_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t* out)
+{
+    for (uint64_t i = 0; i < n; i++)
+        out[i] = orc_hem_signature_u64(keys[i], seed);
+}
+
+void orc_hem_signatures_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint64_t* a,
+                            uint64_t* b)
+{
+    for (uint64_t i = 0; i < n; i++)
+        orc_hem_signature_str(bytes + offs[i], offs[i + 1] - offs[i], seed, a + i, b + i);
+}
+
 /* The first word of the pair a signature stands for inside its bucket: the signature's first
  * word with its two 32-bit halves swapped. */
 static uint64_t orc_hem_bucket_key(uint64_t sig) { return (sig << 32) | (sig >> 32); }

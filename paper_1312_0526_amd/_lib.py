@@ -63,7 +63,7 @@ _SIGS = {
                                  C.POINTER(MphfInfo)]),
     "mphx_sf_lookup_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _u64, _vp, _vp]),
     "mphx_sf_lookup_str": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
-    "mphx_hem_workspace_bytes": (_sz, [_u64, _u32, _u32, _u32]),
+    "mphx_hem_workspace_bytes": (_sz, [_u64, _u32, _u32, _u32, _i32]),
     "mphx_hem_capacity": (_i32, [_u64, _u32, _u32, _u32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "mphx_hem_build_u64": (_i32, [_vp, _u64, _u32, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp,
                                   C.POINTER(MphfInfo)]),
@@ -338,8 +338,8 @@ def lookup_str(codes, rank, P: int, seed: int, data: torch.Tensor, offs: torch.T
 
 
 # ---- HEM split (Section 3: signatures, 2^k buckets, an MPHF per bucket) -------------------------
-def hem_workspace_bytes(n: int, k: int, gamma=(123, 100)) -> int:
-    return int(lib().mphx_hem_workspace_bytes(n, k, gamma[0], gamma[1]))
+def hem_workspace_bytes(n: int, k: int, gamma=(123, 100), kind: int = KEYS_U64) -> int:
+    return int(lib().mphx_hem_workspace_bytes(n, k, gamma[0], gamma[1], kind))
 
 
 def hem_capacity(n: int, k: int, gamma=(123, 100)):
@@ -367,7 +367,8 @@ def hem_build(keys=None, data=None, offs=None, k: int = 15, seed: int = 0, gamma
     t["seeds"] = torch.empty(B, dtype=torch.int64, device=dev)
     codes = torch.empty(max(cw, 1), dtype=torch.int64, device=dev)
     rank = torch.empty(max(rw, 1), dtype=torch.int64, device=dev)
-    ws = ws if ws is not None else _workspace(hem_workspace_bytes(n, k, gamma), dev)
+    kind = KEYS_U64 if keys is not None else KEYS_STR
+    ws = ws if ws is not None else _workspace(hem_workspace_bytes(n, k, gamma, kind), dev)
     info = MphfInfo()
     common = (_ptr(t["bucket_off"]), _ptr(t["code_off"]), _ptr(t["rank_off"]), _ptr(t["seeds"]), _ptr(codes),
               _ptr(rank), _ptr(ws), ws.numel(), _stream(dev), C.byref(info))

@@ -1228,7 +1228,7 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
                   uint64_t max_bucket, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
                   const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
                   mphx_bucket_result* results, void* ws, size_t ws_bytes, const mphx_batch_tuning* t,
-                  hipStream_t s)
+                  hipStream_t s, bool pairs = false)
 {
     if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
     if (B == 0) return MPHX_OK;
@@ -1257,8 +1257,9 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
     a.max_n = max_bucket;
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
     a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
+    a.pairs = pairs ? 1u : 0u;
     HIP_TRY(launch_batch_descs(descs, keys, bucket_off, B, seed, code_off, rank_off, codes, rank,
-                               reinterpret_cast<BucketResult*>(results), s));
+                               reinterpret_cast<BucketResult*>(results), s, pairs ? 2u : 1u));
     HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), s));
     return MPHX_OK;
 }
@@ -1329,8 +1330,12 @@ static mphx_batch_tuning hem_tuning()
 // coarse buckets is split by the next k - 18 bits.
 static constexpr uint32_t kHemMaxK = 20, kHemCoarseK = 18;
 
+}  // extern "C"
+
+// Signature records: uint2 (8 bytes) for u64 keys, uint4 (16 bytes: the whole digest) for strings.
+template <class R>
 struct HemLayout {
-    uint2 *rec, *tmp;
+    R *rec, *tmp;
     uint64_t* coff;  // coarse bucket offsets (k > 18 only)
     void* aux;
     uint32_t* order;
@@ -1339,11 +1344,12 @@ struct HemLayout {
     size_t batch_bytes;
 };
 
-static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, HemLayout& L)
+template <class R>
+static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, HemLayout<R>& L)
 {
     const uint32_t B = 1u << k, kc = std::min(k, kHemCoarseK);
-    L.rec = c.take<uint2>(n);
-    L.tmp = c.take<uint2>(n);
+    L.rec = c.take<R>(n);
+    L.tmp = c.take<R>(n);
     L.coff = k > kc ? c.take<uint64_t>((1ull << kc) + 1) : nullptr;
     L.aux = c.take<uint8_t>(hem_aux_bytes(n, kc));
     L.order = c.take<uint32_t>(B);
@@ -1353,12 +1359,21 @@ static void layout_hem(Carve& c, uint64_t n, uint32_t k, uint32_t gnum, uint32_t
     L.batch = c.take<uint8_t>(L.batch_bytes);
 }
 
-size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden)
+extern "C" {
+
+size_t mphx_hem_workspace_bytes(uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden, int key_kind)
 {
     if (k < 9 || k > kHemMaxK || gnum == 0 || gden == 0) return 0;
     Carve c(nullptr);
-    HemLayout L;
-    layout_hem(c, n, k, gnum, gden, L);
+    if (key_kind == MPHX_KEYS_U64) {
+        HemLayout<uint2> L;
+        layout_hem(c, n, k, gnum, gden, L);
+    } else if (key_kind == MPHX_KEYS_STR) {
+        HemLayout<uint4> L;
+        layout_hem(c, n, k, gnum, gden, L);
+    } else {
+        return 0;
+    }
     return c.off;
 }
 
@@ -1593,11 +1608,16 @@ static int hem_finish(uint32_t B, const mphx_bucket_result* results, uint64_t se
     return MPHX_OK;
 }
 
-static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const uint64_t* offs, uint64_t n,
-                     uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* bucket_off,
+}  // extern "C"
+
+template <class R>
+static int hem_build(const uint64_t* keys, const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint32_t k,
+                     uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries, uint64_t* bucket_off,
                      uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
                      void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
 {
+    constexpr bool kStr = sizeof(R) == 16;
+    const int kind = kStr ? MPHX_KEYS_STR : MPHX_KEYS_U64;
     g_err.clear();
     if (k < 9 || k > kHemMaxK) return fail(MPHX_EINVAL, "k must be in [9, 20]");
     if (gnum == 0 || gden == 0 || max_tries == 0) return fail(MPHX_EINVAL, "bad gamma or max_tries");
@@ -1606,19 +1626,19 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
     if (n > 0 && (kind == MPHX_KEYS_U64 ? !keys : (!bytes || !offs))) return fail(MPHX_EINVAL, "null keys");
     if (kind == MPHX_KEYS_STR && ((uintptr_t)bytes & 3)) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
     if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
-    const size_t need = mphx_hem_workspace_bytes(n, k, gnum, gden);
+    const size_t need = mphx_hem_workspace_bytes(n, k, gnum, gden, kind);
     if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
     const uint32_t B = 1u << k;
     const mphx_batch_tuning tune = hem_tuning();
     Carve c(ws);
-    HemLayout L;
+    HemLayout<R> L;
     layout_hem(c, n, k, gnum, gden, L);
     {
         Timed tm(PH_HASH, s);
-        if (kind == MPHX_KEYS_U64)
-            HIP_TRY(launch_hem_sig_u64(keys, n, seed, L.rec, s));
-        else
+        if constexpr (kStr)
             HIP_TRY(launch_hem_sig_str(bytes, offs, n, seed, L.rec, s));
+        else
+            HIP_TRY(launch_hem_sig_u64(keys, n, seed, L.rec, s));
     }
     const uint32_t kc = std::min(k, kHemCoarseK);
     {
@@ -1626,7 +1646,7 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
         HIP_TRY(launch_hem_partition(L.rec, n, kc, L.tmp, k > kc ? L.coff : bucket_off, L.aux, s));
         if (k > kc) HIP_TRY(launch_hem_refine(L.rec, L.coff, kc, k, L.tmp, bucket_off, s));
     }
-    const uint2* bkeys = k > kc ? L.tmp : L.rec;  // the signatures in bucket order
+    const R* bkeys = k > kc ? L.tmp : L.rec;  // the signatures in bucket order
     std::vector<uint64_t> bo(B + 1), co(B + 1), ro(B + 1);
     std::vector<uint32_t> order(B);
     HIP_TRY(hipMemcpyAsync(bo.data(), bucket_off, (B + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
@@ -1642,14 +1662,17 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
     HIP_TRY(hipMemcpyAsync(L.order, order.data(), B * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     {
         Timed tm(PH_OTHER, s);
-        // the partitioned records read as u64 are the bucket keys
+        // the partitioned records read as u64 words are the bucket keys (u64 keys) or digest
+        // pairs (strings)
         rc = batch_enqueue(reinterpret_cast<const uint64_t*>(bkeys), bucket_off, L.order, B, max_bucket, seed, gnum,
                            gden, max_tries, code_off, rank_off, codes, rank, L.results, L.batch, L.batch_bytes,
-                           &tune, s);
+                           &tune, s, kStr);
         if (rc) return rc;
     }
     return hem_finish(B, L.results, seed, co[B], seeds, s, info);
 }
+
+extern "C" {
 
 // ---- HEM split with the keys in host memory (key sets beyond HBM) ------------------------
 // The keys stream through the device in chunks: each chunk's signatures are grouped by their
@@ -1660,8 +1683,11 @@ static int hem_build(int kind, const uint64_t* keys, const uint8_t* bytes, const
 static constexpr uint32_t kHemRunMax = 1u << 16;    // records per gather run
 static constexpr uint32_t kHemRunSlots = 1u << 16;  // runs per gather launch
 
+}  // extern "C"
+
+template <class R>
 struct HemHostLayout {
-    uint2 *sig, *csig, *bsig, *btmp;
+    R *sig, *csig, *bsig, *btmp;
     uint8_t* stage;
     uint64_t* soffs;
     void *caux, *baux;
@@ -1674,11 +1700,12 @@ struct HemHostLayout {
     size_t batch_bytes;
 };
 
+template <class R>
 static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t gnum, uint32_t gden,
-                            uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys, HemHostLayout& L)
+                            uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys, HemHostLayout<R>& L)
 {
     const uint32_t B = 1u << k, kc = std::min(k, kHemCoarseK);
-    L.sig = c.take<uint2>(n);
+    L.sig = c.take<R>(n);
     if (kind == MPHX_KEYS_U64) {
         L.stage = reinterpret_cast<uint8_t*>(c.take<uint64_t>(chunk_keys));
         L.soffs = nullptr;
@@ -1686,10 +1713,10 @@ static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t
         L.stage = c.take<uint8_t>(chunk_bytes);
         L.soffs = c.take<uint64_t>(chunk_keys + 1);
     }
-    L.csig = c.take<uint2>(chunk_keys);
+    L.csig = c.take<R>(chunk_keys);
     L.caux = c.take<uint8_t>(hem_aux_bytes(chunk_keys, kc));
-    L.bsig = c.take<uint2>(batch_keys);
-    L.btmp = c.take<uint2>(batch_keys);
+    L.bsig = c.take<R>(batch_keys);
+    L.btmp = c.take<R>(batch_keys);
     L.baux = c.take<uint8_t>(hem_aux_bytes(batch_keys, kc));
     L.lbo = c.take<uint64_t>(B + 1);
     L.lbo_c = k > kc ? c.take<uint64_t>((1ull << kc) + 1) : nullptr;
@@ -1700,6 +1727,8 @@ static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t
     L.batch_bytes = mphx_batch_workspace_bytes(B, hem_max_bucket(n, k), gnum, gden, &t);
     L.batch = c.take<uint8_t>(L.batch_bytes);
 }
+
+extern "C" {
 
 // Host-to-device copies for the streamed build.  Pinned sources are copied directly; pageable
 // ones pass through two pinned staging buffers owned by the library: host threads fill one
@@ -1803,12 +1832,17 @@ static int hem_host_args(int kind, uint32_t k, uint32_t gnum, uint32_t gden, uin
     return MPHX_OK;
 }
 
-static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes, const uint64_t* hoffs, uint64_t n,
+}  // extern "C"
+
+template <class R>
+static int hem_host_build(const uint64_t* hkeys, const uint8_t* hbytes, const uint64_t* hoffs, uint64_t n,
                           uint32_t k, uint64_t seed, uint32_t gnum, uint32_t gden, uint32_t max_tries,
                           uint64_t chunk_keys, uint64_t chunk_bytes, uint64_t batch_keys, uint64_t* bucket_off,
                           uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
                           void* ws, size_t ws_bytes, hipStream_t s, mphx_mphf_info* info)
 {
+    constexpr bool kStr = sizeof(R) == 16;
+    const int kind = kStr ? MPHX_KEYS_STR : MPHX_KEYS_U64;
     g_err.clear();
     int rc = hem_host_args(kind, k, gnum, gden, chunk_keys, chunk_bytes, batch_keys);
     if (rc) return rc;
@@ -1825,7 +1859,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
     const uint32_t gshift = k - kc + 8;  // a group holds 2^gshift buckets
     const mphx_batch_tuning tune = hem_tuning();
     Carve c(ws);
-    HemHostLayout L;
+    HemHostLayout<R> L;
     layout_hem_host(c, kind, n, k, gnum, gden, chunk_keys, chunk_bytes, batch_keys, L);
 
     // host buffers the stream copies from or into; the guard, destroyed first, lets every copy
@@ -1847,7 +1881,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
         Timed tm(PH_HASH, s);
         for (uint64_t c0 = 0; c0 < n;) {
             uint64_t c1 = std::min(n, c0 + chunk_keys);
-            if (kind == MPHX_KEYS_U64) {
+            if constexpr (!kStr) {
                 HIP_TRY(stager.copy(L.stage, hkeys + c0, (c1 - c0) * sizeof(uint64_t)));
                 HIP_TRY(launch_hem_sig_u64(reinterpret_cast<const uint64_t*>(L.stage), c1 - c0, seed, L.csig, s));
             } else {
@@ -1909,7 +1943,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
             HIP_TRY(launch_hem_partition(L.bsig, nb, kc, L.btmp, k > kc ? L.lbo_c : L.lbo, L.baux, s));
             if (k > kc) HIP_TRY(launch_hem_refine(L.bsig, L.lbo_c, kc, k, L.btmp, L.lbo, s));
         }
-        const uint2* bkeys = k > kc ? L.btmp : L.bsig;  // the batch's signatures in bucket order
+        const R* bkeys = k > kc ? L.btmp : L.bsig;  // the batch's signatures in bucket order
         HIP_TRY(hipMemcpyAsync(lbo.data(), L.lbo, (B + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const uint32_t b0 = g0 << gshift, Bb = (g1 - g0) << gshift;
@@ -1932,7 +1966,7 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
             Timed tm(PH_OTHER, s);
             rc = batch_enqueue(reinterpret_cast<const uint64_t*>(bkeys), L.lbo + b0, L.order, Bb, mb, seed, gnum,
                                gden, max_tries, code_off + b0, rank_off + b0, codes, rank, L.results + b0, L.batch,
-                               L.batch_bytes, &tune, s);
+                               L.batch_bytes, &tune, s, kStr);
             if (rc) return rc;
         }
         kbase += nb;
@@ -1944,13 +1978,15 @@ static int hem_host_build(int kind, const uint64_t* hkeys, const uint8_t* hbytes
     return hem_finish(B, L.results, seed, co[B], seeds, s, info);
 }
 
+extern "C" {
+
 int mphx_hem_build_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64_t seed, uint32_t gamma_num,
                        uint32_t gamma_den, uint32_t max_tries, uint64_t* bucket_off, uint64_t* code_off,
                        uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank, void* ws,
                        size_t ws_bytes, void* stream, mphx_mphf_info* info)
 {
-    return hem_build(MPHX_KEYS_U64, keys, nullptr, nullptr, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off,
-                     code_off, rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
+    return hem_build<uint2>(keys, nullptr, nullptr, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off, code_off,
+                            rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
 }
 
 int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint32_t k, uint64_t seed,
@@ -1958,8 +1994,8 @@ int mphx_hem_build_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, u
                        uint64_t* code_off, uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank,
                        void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info)
 {
-    return hem_build(MPHX_KEYS_STR, nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off,
-                     code_off, rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
+    return hem_build<uint4>(nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries, bucket_off, code_off,
+                            rank_off, seeds, codes, rank, ws, ws_bytes, (hipStream_t)stream, info);
 }
 
 size_t mphx_hem_host_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num, uint32_t gamma_den, int kind,
@@ -1970,8 +2006,13 @@ size_t mphx_hem_host_workspace_bytes(uint64_t n, uint32_t k, uint32_t gamma_num,
         batch_keys == 0 || batch_keys >= 0x7FFFFFFFull || (kind == MPHX_KEYS_STR && chunk_bytes < 512))
         return 0;
     Carve c(nullptr);
-    HemHostLayout L;
-    layout_hem_host(c, kind, n, k, gamma_num, gamma_den, chunk_keys, chunk_bytes, batch_keys, L);
+    if (kind == MPHX_KEYS_U64) {
+        HemHostLayout<uint2> L;
+        layout_hem_host(c, kind, n, k, gamma_num, gamma_den, chunk_keys, chunk_bytes, batch_keys, L);
+    } else {
+        HemHostLayout<uint4> L;
+        layout_hem_host(c, kind, n, k, gamma_num, gamma_den, chunk_keys, chunk_bytes, batch_keys, L);
+    }
     return c.off;
 }
 
@@ -1981,7 +2022,7 @@ int mphx_hem_build_host_u64(const uint64_t* keys, uint64_t n, uint32_t k, uint64
                             uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, void* stream,
                             mphx_mphf_info* info)
 {
-    return hem_host_build(MPHX_KEYS_U64, keys, nullptr, nullptr, n, k, seed, gamma_num, gamma_den, max_tries,
+    return hem_host_build<uint2>(keys, nullptr, nullptr, n, k, seed, gamma_num, gamma_den, max_tries,
                           chunk_keys, 0, batch_keys, bucket_off, code_off, rank_off, seeds, codes, rank, ws, ws_bytes,
                           (hipStream_t)stream, info);
 }
@@ -1992,7 +2033,7 @@ int mphx_hem_build_host_str(const uint8_t* bytes, const uint64_t* offs, uint64_t
                             uint64_t* rank_off, uint64_t* seeds, uint64_t* codes, uint64_t* rank, void* ws,
                             size_t ws_bytes, void* stream, mphx_mphf_info* info)
 {
-    return hem_host_build(MPHX_KEYS_STR, nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries,
+    return hem_host_build<uint4>(nullptr, bytes, offs, n, k, seed, gamma_num, gamma_den, max_tries,
                           chunk_keys, chunk_bytes, batch_keys, bucket_off, code_off, rank_off, seeds, codes, rank, ws,
                           ws_bytes, (hipStream_t)stream, info);
 }

@@ -204,26 +204,43 @@ __device__ __forceinline__ bool bucket_fits_lds(uint64_t n, uint64_t m)
     return ((m + 3) & ~3ull) + n <= batch_lds_bytes<kBlock>() / 4;
 }
 
-// Part-k local vertex of key i: recomputed from a u64 key, read from the stored edge else.
-__device__ __forceinline__ uint32_t bucket_local(const BucketDesc& d, const SlotLayout& L, uint32_t i, uint64_t sd,
-                                                 uint64_t P, uint32_t k)
+// Digest of key i under seed sd for keys given by words: a u64 key x is the digest (x ^ sd,
+// x ^ sd), a digest pair (x, y) the digest (x ^ sd, y ^ sd).
+__device__ __forceinline__ void key_digest(const BatchArgs& a, const BucketDesc& d, uint32_t i, uint64_t sd,
+                                           uint64_t& x, uint64_t& y)
+{
+    if (a.pairs) {
+        const ulonglong2 w = reinterpret_cast<const ulonglong2*>(d.keys)[i];
+        x = w.x ^ sd;
+        y = w.y ^ sd;
+    } else {
+        x = y = d.keys[i] ^ sd;
+    }
+}
+
+// Part-k local vertex of key i: recomputed from a key given by words, read from the stored
+// edge else.
+__device__ __forceinline__ uint32_t bucket_local(const BatchArgs& a, const BucketDesc& d, const SlotLayout& L,
+                                                 uint32_t i, uint64_t sd, uint64_t P, uint32_t k)
 {
     if (d.keys) {
-        const uint64_t s = d.keys[i] ^ sd;
-        return (uint32_t)range_reduce(fin(s + (uint64_t)(k + 1) * kGamma), P);
+        uint64_t x, y;
+        key_digest(a, d, i, sd, x, y);
+        return (uint32_t)range_reduce(fin((k == 2 ? y : x) + (uint64_t)(k + 1) * kGamma), P);
     }
     const uint3 ev = L.edges[i];
     return (k == 0 ? ev.x : (k == 1 ? ev.y : ev.z)) - (uint32_t)(k * P);
 }
 
-// Edge of key i of a bucket: recomputed for u64 keys, stored for string keys.
-__device__ __forceinline__ uint3 bucket_edge(const BucketDesc& d, const SlotLayout& L, uint32_t i, uint64_t sd,
-                                             uint64_t P)
+// Edge of key i of a bucket: recomputed for keys given by words, stored for string keys.
+__device__ __forceinline__ uint3 bucket_edge(const BatchArgs& a, const BucketDesc& d, const SlotLayout& L, uint32_t i,
+                                             uint64_t sd, uint64_t P)
 {
     if (d.keys) {
-        uint64_t s = d.keys[i] ^ sd;
+        uint64_t x, y;
+        key_digest(a, d, i, sd, x, y);
         uint32_t v0, v1, v2;
-        edge_of_digest(s, s, P, v0, v1, v2);
+        edge_of_digest(x, y, P, v0, v1, v2);
         return make_uint3(v0, v1, v2);
     }
     return L.edges[i];
@@ -341,7 +358,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                         s_cnt[b] = 0;
                     __syncthreads();
                     for (uint32_t i = tid; i < n; i += kBlock)
-                        atomicAdd(&s_cnt[bucket_local(d, L, i, sd, P, k) / kBatchTile], 1u);
+                        atomicAdd(&s_cnt[bucket_local(a, d, L, i, sd, P, k) / kBatchTile], 1u);
                     __syncthreads();
                     lds_exclusive_scan<kBlock>(s_cnt, nbk, s_wtot);
                     for (uint32_t b = tid; b < nbk; b += kBlock)
@@ -350,7 +367,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                         s_bnd[nbk] = n;
                     __syncthreads();
                     for (uint32_t i = tid; i < n; i += kBlock) {
-                        const uint32_t u = bucket_local(d, L, i, sd, P, k);
+                        const uint32_t u = bucket_local(a, d, L, i, sd, P, k);
                         const uint32_t pos = atomicAdd(&s_cnt[u / kBatchTile], 1u);
                         pairs[pos] = make_uint2(u % kBatchTile, i);
                     }
@@ -363,7 +380,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     __syncthreads();
                     if (nbk == 1) {
                         for (uint32_t i = tid; i < n; i += kBlock)
-                            atomicAdd(&s_tab[bucket_local(d, L, i, sd, P, k)],
+                            atomicAdd(&s_tab[bucket_local(a, d, L, i, sd, P, k)],
                                       (unsigned long long)(Rec::kOne + i));
                     } else {
                         for (uint32_t j = s_bnd[b] + tid; j < s_bnd[b + 1]; j += kBlock) {
@@ -426,7 +443,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 L.rec[v] = 0;
             __syncthreads();
             for (uint32_t i = tid; i < n; i += kBlock) {
-                const uint3 ev = bucket_edge(d, L, i, sd, P);
+                const uint3 ev = bucket_edge(a, d, L, i, sd, P);
                 uint32_t dg = S::rec_add(L.rec, ev.x, i);
                 dg = max(dg, S::rec_add(L.rec, ev.y, i));
                 dg = max(dg, S::rec_add(L.rec, ev.z, i));
@@ -487,7 +504,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 __syncthreads();
                 for (uint32_t i = lo + tid; i < hi; i += kBlock) {
                     const uint32_t e = L.slots[i].x, h = S::ld(L.state + e) & 3u;
-                    const uint3 ev = bucket_edge(d, L, e, sd, P);
+                    const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     atomicAdd(&s_cnt[(h == 0 ? ev.y : (h == 1 ? ev.z : ev.x)) / kBatchTile], 1u);
                     atomicAdd(&s_cnt[(h == 0 ? ev.z : (h == 1 ? ev.x : ev.y)) / kBatchTile], 1u);
                 }
@@ -500,7 +517,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 __syncthreads();
                 for (uint32_t i = lo + tid; i < hi; i += kBlock) {
                     const uint32_t e = L.slots[i].x, h = S::ld(L.state + e) & 3u;
-                    const uint3 ev = bucket_edge(d, L, e, sd, P);
+                    const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
                     const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
@@ -550,7 +567,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 if (i < hi) {
                     uint32_t e = L.slots[i].x;
                     uint32_t h = S::ld(L.state + e) & 3u;
-                    uint3 ev = bucket_edge(d, L, e, sd, P);
+                    uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
                     uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
@@ -662,7 +679,7 @@ __device__ void build_bucket_lds(const BatchArgs& a, const BucketDesc& d, uint8_
         }
         __syncthreads();
         for (uint32_t i = tid; i < n; i += kBlock) {
-            const uint3 ev = bucket_edge(d, L, i, sd, P);
+            const uint3 ev = bucket_edge(a, d, L, i, sd, P);
             const uint32_t o0 = atomicAdd(&rec[ev.x], kOne32 + i);
             const uint32_t o1 = atomicAdd(&rec[ev.y], kOne32 + i);
             const uint32_t o2 = atomicAdd(&rec[ev.z], kOne32 + i);
@@ -710,7 +727,7 @@ __device__ void build_bucket_lds(const BatchArgs& a, const BucketDesc& d, uint8_
                 if (i < hi) {
                     const uint32_t e = L.slots[i].x;
                     const uint32_t h = state[e] & 3u;
-                    const uint3 ev = bucket_edge(d, L, e, sd, P);
+                    const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
                     const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
@@ -800,15 +817,16 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
     }
 }
 
-// Descriptors of the buckets of one u64 key array split by offsets, with outputs at offsets.
+// Descriptors of the buckets of one key array (u64 keys or digest pairs, wpk words per key)
+// split by offsets, with outputs at offsets.
 __global__ __launch_bounds__(256) void k_batch_descs(BucketDesc* descs, const uint64_t* keys, const uint64_t* off,
                                                      uint32_t B, uint64_t seed, const uint64_t* code_off,
                                                      const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
-                                                     BucketResult* results)
+                                                     BucketResult* results, uint32_t wpk)
 {
     for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < B; b += gridDim.x * blockDim.x) {
         BucketDesc d;
-        d.keys = keys + off[b];
+        d.keys = keys + off[b] * wpk;
         d.bytes = nullptr;
         d.offs = nullptr;
         d.n = off[b + 1] - off[b];
@@ -822,12 +840,13 @@ __global__ __launch_bounds__(256) void k_batch_descs(BucketDesc* descs, const ui
 
 hipError_t launch_batch_descs(BucketDesc* descs, const uint64_t* keys, const uint64_t* off, uint32_t B, uint64_t seed,
                               const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
-                              BucketResult* results, hipStream_t s)
+                              BucketResult* results, hipStream_t s, uint32_t words_per_key)
 {
     if (B == 0) return hipSuccess;
+    if (words_per_key != 1 && words_per_key != 2) return hipErrorInvalidValue;
     unsigned g = (B + 255) / 256;
     k_batch_descs<<<g < 4096 ? g : 4096, 256, 0, s>>>(descs, keys, off, B, seed, code_off, rank_off, codes, rank,
-                                                      results);
+                                                      results, words_per_key);
     return hipGetLastError();
 }
 

@@ -306,9 +306,12 @@ __device__ __forceinline__ uint64_t sf_eval_edge(const uint64_t* words, uint64_t
 }
 
 // ----- HEM split (Section 3): signatures, buckets by their top bits, an MPHF per bucket ------
+// A u64 key's signature is 64 bits (a bijection of the key); a string key's is its whole 128-bit
+// digest (a, b).  The top k bits of the first word pick the bucket; inside it the key is the
+// digest pair (swap(first word), second word) -- (swap(sig), swap(sig)) for u64 keys,
+// (swap(a), b) for strings, swap exchanging the 32-bit halves -- whose edge under the
+// bucket's seed t is the edge of the digest (x ^ t, y ^ t).
 __device__ __forceinline__ uint64_t hem_signature_u64(uint64_t key, uint64_t seed) { return fin((key ^ seed) + 4 * kGamma); }
-__device__ __forceinline__ uint64_t hem_signature_digest(uint64_t a, uint64_t b) { return fin(a ^ fin(b)); }
-// the key a signature stands for inside its bucket: its two 32-bit halves swapped
 __device__ __forceinline__ uint64_t hem_bucket_key(uint64_t sig) { return (sig << 32) | (sig >> 32); }
 
 struct HemTables {
@@ -324,16 +327,30 @@ struct HemTables {
 __device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,
                                               uint32_t v2);
 
-__device__ __forceinline__ uint64_t hem_eval(const HemTables& t, uint64_t sig)
+// f(key) from its signature's first word `top` (the bucket) and its bucket pair (x, y).
+__device__ __forceinline__ uint64_t hem_eval_pair(const HemTables& t, uint64_t top, uint64_t x, uint64_t y)
 {
-    const uint64_t b = t.k ? sig >> (64 - t.k) : 0;
+    const uint64_t b = t.k ? top >> (64 - t.k) : 0;
     const uint64_t lo = t.bucket_off[b], nb = t.bucket_off[b + 1] - lo;
     const uint64_t num = nb * (uint64_t)t.gnum, den = 3ull * t.gden;  // nb < 2^32: no overflow
     const uint64_t P = (num + den - 1) / den;
-    const uint64_t s = hem_bucket_key(sig) ^ t.seeds[b];
+    const uint64_t sd = t.seeds[b];
     uint32_t v0, v1, v2;
-    edge_of_digest(s, s, P, v0, v1, v2);
+    edge_of_digest(x ^ sd, y ^ sd, P, v0, v1, v2);
     return lo + eval_edge(t.codes + t.code_off[b], t.rank + t.rank_off[b], v0, v1, v2);
+}
+
+// u64 keys: the 64-bit signature
+__device__ __forceinline__ uint64_t hem_eval(const HemTables& t, uint64_t sig)
+{
+    const uint64_t x = hem_bucket_key(sig);
+    return hem_eval_pair(t, sig, x, x);
+}
+
+// string keys: the 128-bit digest (a, b)
+__device__ __forceinline__ uint64_t hem_eval_digest(const HemTables& t, uint64_t a, uint64_t b)
+{
+    return hem_eval_pair(t, a, hem_bucket_key(a), b);
 }
 
 __device__ __forceinline__ uint64_t eval_edge(const uint64_t* codes, const uint64_t* rank, uint32_t v0, uint32_t v1,

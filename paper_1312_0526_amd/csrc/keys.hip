@@ -144,8 +144,8 @@ struct EvalTables {
     uint32_t bits;
     HemTables hem;
 };
-// kHsHemSig writes each key's HEM signature record (out as uint2: high half, low half);
-// kHsEvalHem evaluates a HEM split
+// kHsHemSig writes each key's HEM signature record, its whole digest (out as uint4: high and
+// low half of a, then low and high half of b); kHsEvalHem evaluates a HEM split
 constexpr int kHsEdges = 0, kHsEvalMphf = 1, kHsEvalSf = 2, kHsHemSig = 3, kHsEvalHem = 4;
 
 template <int kMode>
@@ -315,12 +315,11 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
             const uint64_t b = fin(B ^ sb ^ len);
             uint32_t v0, v1, v2;
             edge_of_digest(a, b, P, v0, v1, v2);
-            if constexpr (kMode == kHsHemSig || kMode == kHsEvalHem) {
-                const uint64_t sig = hem_signature_digest(a, b);
-                if constexpr (kMode == kHsHemSig)
-                    reinterpret_cast<uint2*>(mt.out)[i] = make_uint2((uint32_t)(sig >> 32), (uint32_t)sig);
-                else
-                    mt.out[i] = hem_eval(mt.hem, sig);
+            if constexpr (kMode == kHsHemSig) {
+                reinterpret_cast<uint4*>(mt.out)[i] =
+                    make_uint4((uint32_t)(a >> 32), (uint32_t)a, (uint32_t)b, (uint32_t)(b >> 32));
+            } else if constexpr (kMode == kHsEvalHem) {
+                mt.out[i] = hem_eval_digest(mt.hem, a, b);
             } else if constexpr (kMode == kHsEvalMphf) {
                 mt.out[i] = eval_edge(mt.codes, mt.rank, v0, v1, v2);
             } else if constexpr (kMode == kHsEvalSf) {
@@ -510,7 +509,7 @@ hipError_t launch_hem_sig_u64(const uint64_t* keys, uint64_t n, uint64_t seed, u
     return hipGetLastError();
 }
 
-hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint2* rec,
+hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint4* rec,
                               hipStream_t s)
 {
     if (n == 0) return hipSuccess;

@@ -70,13 +70,16 @@ struct BatchArgs {
     unsigned int* next;      // queue cursor
     uint32_t lds_path;       // 1: buckets that fit run in LDS
     uint32_t sort_div;       // > 0: a layer deletes through a sorted list when 2 * layer * sort_div >= m
+    uint32_t pairs;          // 1: every bucket's keys are 128-bit digest pairs (2 u64 words per key:
+                             // the edge under seed t is that of the digest (x ^ t, y ^ t))
 };
 
 // batched builds (batch.hip)
 uint64_t batch_slot_bytes(uint64_t max_n, uint32_t gnum, uint32_t gden);
+// words_per_key: 1 for u64 keys, 2 for digest pairs (BatchArgs::pairs)
 hipError_t launch_batch_descs(BucketDesc* descs, const uint64_t* keys, const uint64_t* off, uint32_t B, uint64_t seed,
                               const uint64_t* code_off, const uint64_t* rank_off, uint64_t* codes, uint64_t* rank,
-                              BucketResult* results, hipStream_t s);
+                              BucketResult* results, hipStream_t s, uint32_t words_per_key = 1);
 hipError_t launch_batch(const BatchArgs& a, unsigned block, unsigned grid, bool wg_scope, hipStream_t s);
 
 // utilities (scan.hip)
@@ -164,15 +167,18 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
 // assignment, ranking, lookup (solve.hip)
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
                                uint8_t* code8, unsigned grid_cap, hipStream_t s);
-// HEM split (keys.hip, part.hip): signature records (high, low half: a u64 read gives the
-// bucket key), their partition into 2^k buckets in place (tmp: n more pairs; 9 <= k <= 18; larger
-// k through launch_hem_refine)
-// with bucket_off[0..2^k] written on the device, and lookups
+// HEM split (keys.hip, part.hip): signature records, their partition into 2^k buckets in place
+// (tmp: n more records; 9 <= k <= 18; larger k through launch_hem_refine) with
+// bucket_off[0..2^k] written on the device, and lookups.  A u64 key's record is uint2 (high,
+// low half of its signature: a u64 read gives the bucket key); a string key's is uint4 (high
+// and low half of a, then b: two u64 reads give the bucket's digest pair (swap(a), b)).
 hipError_t launch_hem_sig_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint2* rec, hipStream_t s);
-hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint2* rec,
+hipError_t launch_hem_sig_str(const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t seed, uint4* rec,
                               hipStream_t s);
 size_t hem_aux_bytes(uint64_t n, uint32_t k);
 hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, uint64_t* bucket_off, void* aux,
+                                hipStream_t s);
+hipError_t launch_hem_partition(uint4* rec, uint64_t n, uint32_t k, uint4* tmp, uint64_t* bucket_off, void* aux,
                                 hipStream_t s);
 hipError_t launch_hem_lookup_u64(const HemTables& t, uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out,
                                  hipStream_t s);
@@ -217,10 +223,15 @@ struct HemRun {
 };
 hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, uint2* out, void* aux,
                                   uint32_t* host_gstart, hipStream_t s);
+hipError_t launch_hem_group_chunk(const uint4* csig, uint64_t cn, uint32_t k, uint4* out, void* aux,
+                                  uint32_t* host_gstart, hipStream_t s);
 hipError_t launch_hem_gather(const uint2* src, const HemRun* runs, uint32_t nruns, uint2* dst, hipStream_t s);
+hipError_t launch_hem_gather(const uint4* src, const HemRun* runs, uint32_t nruns, uint4* dst, hipStream_t s);
 // More than 2^18 buckets: records partitioned into 2^kc coarse buckets (coarse_off, 2^kc + 1)
 // split stably by the next k - kc <= 2 bits into out, with the 2^k + 1 fine offsets.
 hipError_t launch_hem_refine(const uint2* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint2* out,
+                             uint64_t* fine_off, hipStream_t s);
+hipError_t launch_hem_refine(const uint4* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint4* out,
                              uint64_t* fine_off, hipStream_t s);
 hipError_t launch_offs_rebase(uint64_t* offs, uint64_t count, uint64_t base, hipStream_t s);
 

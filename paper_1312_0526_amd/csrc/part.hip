@@ -89,15 +89,21 @@ __device__ __forceinline__ uint32_t local_of(uint32_t v, uint32_t k, uint64_t P)
 // First-pass sources: part k's column of the edge list as (local vertex, edge) pairs, or a
 // list of (key, value) records.
 struct EdgeColumn {
+    using Rec = uint2;
     const uint32_t* edges;
     uint32_t k;
     uint64_t P;
     __device__ uint2 load(uint64_t i) const { return make_uint2(local_of(edges[3 * i + k], k, P), (uint32_t)i); }
 };
-struct Records {
-    const uint2* in;
-    __device__ uint2 load(uint64_t i) const { return in[i]; }
+// Records whose first 32-bit word carries the digits: (key, value) pairs, or the 16-byte
+// signature records of the HEM split of string keys.
+template <class R>
+struct RecordsT {
+    using Rec = R;
+    const R* in;
+    __device__ R load(uint64_t i) const { return in[i]; }
 };
+using Records = RecordsT<uint2>;
 
 struct GroupInfo {
     const uint32_t* hstart;  // NH + 1 element offsets of the groups
@@ -106,7 +112,8 @@ struct GroupInfo {
 };
 
 // ---- pass 1 histograms of a record list (the vertex build gets its own from hashing) -------
-__global__ __launch_bounds__(kPtBlock) void k_part_hist1(Records src, uint64_t n, uint32_t gsh, uint32_t NH,
+template <class Src>
+__global__ __launch_bounds__(kPtBlock) void k_part_hist1(Src src, uint64_t n, uint32_t gsh, uint32_t NH,
                                                          uint64_t nt1, uint32_t* __restrict__ hist1)
 {
     __shared__ uint32_t c[kMaxGroups];
@@ -128,15 +135,16 @@ __global__ __launch_bounds__(kPtBlock) void k_part_hist1(Records src, uint64_t n
 template <class Src>
 __global__ __launch_bounds__(kPtBlock) void k_part_scatter1(Src src, uint64_t n, uint32_t gsh, uint32_t NH,
                                                             uint64_t nt1, const uint32_t* __restrict__ off1,
-                                                            uint2* __restrict__ out)
+                                                            typename Src::Rec* __restrict__ out)
 {
-    __shared__ uint2 buf[kPtTile];
+    using R = typename Src::Rec;
+    __shared__ R buf[kPtTile];
     __shared__ uint32_t cnt[kMaxGroups], lst[kMaxGroups], gof[kMaxGroups], wtot[kWaves];
     for (uint32_t j = threadIdx.x; j < kMaxGroups; j += kPtBlock)
         cnt[j] = 0;
     __syncthreads();
     const uint64_t t0 = (uint64_t)blockIdx.x * kPtTile;
-    uint2 p[kPtPer];
+    R p[kPtPer];
     uint32_t rk[kPtPer];
 #pragma unroll
     for (uint32_t q = 0; q < kPtPer; q++) {
@@ -160,7 +168,7 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter1(Src src, uint64_t n,
     __syncthreads();
     const uint32_t total = (uint32_t)min<uint64_t>(kPtTile, n - t0);
     for (uint32_t s = threadIdx.x; s < total; s += kPtBlock) {
-        const uint2 x = buf[s];
+        const R x = buf[s];
         const uint32_t h = x.x >> gsh;
         out[(uint64_t)gof[h] + (s - lst[h])] = x;
     }
@@ -258,7 +266,8 @@ __device__ __forceinline__ uint32_t group_of_tile(const GroupInfo& g, uint32_t N
 }
 
 // ---- pass 2 histograms: bucket digits per (group, tile) ----------------------------------------
-__global__ __launch_bounds__(kPtBlock) void k_part_hist2(const uint2* __restrict__ in, const uint32_t* __restrict__ ginfo,
+template <class R>
+__global__ __launch_bounds__(kPtBlock) void k_part_hist2(const R* __restrict__ in, const uint32_t* __restrict__ ginfo,
                                                          uint32_t NH, uint32_t bsh, uint32_t* __restrict__ hist2)
 {
     __shared__ uint32_t c[kDigits];
@@ -285,11 +294,12 @@ __global__ __launch_bounds__(kPtBlock) void k_part_hist2(const uint2* __restrict
 }
 
 // ---- pass 2 scatter: pairs grouped by bucket key >> bsh ----------------------------------------
-__global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const uint2* __restrict__ in, const uint32_t* __restrict__ ginfo,
+template <class R>
+__global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const R* __restrict__ in, const uint32_t* __restrict__ ginfo,
                                                             uint32_t NH, uint32_t bsh, const uint32_t* __restrict__ off2,
-                                                            uint2* __restrict__ out)
+                                                            R* __restrict__ out)
 {
-    __shared__ uint2 buf[kPtTile];
+    __shared__ R buf[kPtTile];
     __shared__ uint32_t cnt[kDigits], lst[kDigits], gof[kDigits], wtot[kWaves];
     __shared__ uint32_t s_h;
     const GroupInfo g(ginfo);
@@ -302,7 +312,7 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const uint2* __restr
     const uint32_t j = b - g.tbase[h], tiles = g.tbase[h + 1] - g.tbase[h];
     const uint64_t lo = (uint64_t)g.hstart[h] + (uint64_t)j * kPtTile;
     const uint32_t total = (uint32_t)(min<uint64_t>(lo + kPtTile, g.hstart[h + 1]) - lo);
-    uint2 p[kPtPer];
+    R p[kPtPer];
     uint32_t rk[kPtPer];
 #pragma unroll
     for (uint32_t q = 0; q < kPtPer; q++) {
@@ -328,7 +338,7 @@ __global__ __launch_bounds__(kPtBlock) void k_part_scatter2(const uint2* __restr
     }
     __syncthreads();
     for (uint32_t s = threadIdx.x; s < total; s += kPtBlock) {
-        const uint2 q = buf[s];
+        const R q = buf[s];
         const uint32_t d = (q.x >> bsh) & (kDigits - 1);
         out[(uint64_t)gof[d] + (s - lst[d])] = q;
     }
@@ -585,8 +595,8 @@ AuxLayout updates_aux(uint64_t m)
 }
 
 // Second pass + per-bucket kernel, after the first pass left the pairs grouped in mid.
-template <class Last>
-hipError_t second_pass_then(uint64_t n, uint32_t gsh, uint32_t NH, const uint32_t* off1, uint2* mid, uint2* out,
+template <class R, class Last>
+hipError_t second_pass_then(uint64_t n, uint32_t gsh, uint32_t NH, const uint32_t* off1, R* mid, R* out,
                             const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
 {
     const uint64_t nt1 = tiles_of(n), nt2 = nt1 + NH;
@@ -608,8 +618,8 @@ hipError_t second_pass_then(uint64_t n, uint32_t gsh, uint32_t NH, const uint32_
 
 // Both passes + per-bucket kernel, after the first-pass histograms (off1, scanned here).
 template <class Src, class Last>
-hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32_t* off1, uint2* mid, uint2* out,
-                          const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
+hipError_t partition_then(Src src, uint64_t n, uint32_t gsh, uint32_t NH, uint32_t* off1, typename Src::Rec* mid,
+                          typename Src::Rec* out, const AuxLayout& L, uint8_t* base, Last last, hipStream_t s)
 {
     const uint64_t nt1 = tiles_of(n);
     hipError_t err = launch_scan_u32(off1, (uint64_t)NH * nt1, off1, base + L.scan, L.scan_bytes, s);
@@ -737,8 +747,10 @@ size_t hem_aux_bytes(uint64_t n, uint32_t k)
     return aux_layout((uint64_t)NH * tiles_of(n), n, NH).total;
 }
 
-hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, uint64_t* bucket_off, void* aux,
-                                hipStream_t s)
+namespace {
+
+template <class R>
+hipError_t hem_partition(R* rec, uint64_t n, uint32_t k, R* tmp, uint64_t* bucket_off, void* aux, hipStream_t s)
 {
     // the group digit is x >> (40 - k): k >= 9 keeps the shift below 32 (at least two groups)
     if (k < 9 || k > 18) return hipErrorInvalidValue;
@@ -749,11 +761,11 @@ hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, 
     const uint64_t nt1 = tiles_of(n);
     if (n == 0) return launch_zero(bucket_off, (B + 1ull) * sizeof(uint64_t), s);
     if (nt1 > 0x7FFFFFFFull || n >= 0xFFFFFFFFull) return hipErrorInvalidValue;
-    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{rec}, n, gsh, NH, nt1, hist1);
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(RecordsT<R>{rec}, n, gsh, NH, nt1, hist1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     return partition_then(
-        Records{rec}, n, gsh, NH, hist1, tmp, rec, L, base,
+        RecordsT<R>{rec}, n, gsh, NH, hist1, tmp, rec, L, base,
         [&](const uint32_t* ginfo, const uint32_t* off2) {
             k_hem_bucket_off<<<(B + 256) / 256, 256, 0, s>>>(ginfo, NH, off2, n, B, bucket_off);
             return hipGetLastError();
@@ -761,14 +773,29 @@ hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, 
         s);
 }
 
+}  // namespace
+
+hipError_t launch_hem_partition(uint2* rec, uint64_t n, uint32_t k, uint2* tmp, uint64_t* bucket_off, void* aux,
+                                hipStream_t s)
+{
+    return hem_partition(rec, n, k, tmp, bucket_off, aux, s);
+}
+
+hipError_t launch_hem_partition(uint4* rec, uint64_t n, uint32_t k, uint4* tmp, uint64_t* bucket_off, void* aux,
+                                hipStream_t s)
+{
+    return hem_partition(rec, n, k, tmp, bucket_off, aux, s);
+}
+
 // HEM beyond 2^18 buckets: each coarse bucket b (top kc bits) split, stably, by the next
 // k - kc bits (at most 2) into fine buckets b * D + j, one workgroup per coarse bucket;
 // fine_off[0 .. 2^k] written.
 constexpr uint32_t kRefBlock = 256;
 
-__global__ __launch_bounds__(kRefBlock) void k_hem_refine(const uint2* __restrict__ in,
+template <class R>
+__global__ __launch_bounds__(kRefBlock) void k_hem_refine(const R* __restrict__ in,
                                                           const uint64_t* __restrict__ coarse_off, uint32_t nb,
-                                                          uint32_t k, uint32_t d, uint2* __restrict__ out,
+                                                          uint32_t k, uint32_t d, R* __restrict__ out,
                                                           uint64_t* __restrict__ fine_off)
 {
     __shared__ uint32_t s_cnt[4], s_wtot[kRefBlock / kWave][4];
@@ -796,7 +823,7 @@ __global__ __launch_bounds__(kRefBlock) void k_hem_refine(const uint2* __restric
     for (uint64_t c = lo; c < hi; c += kRefBlock) {
         const uint64_t i = c + threadIdx.x;
         const bool have = i < hi;
-        const uint2 x = have ? in[i] : make_uint2(0u, 0u);
+        const R x = have ? in[i] : R{};
         const uint32_t dg = have ? (x.x >> sh) & (D - 1) : D;
         uint32_t below = 0;
         for (uint32_t j = 0; j < D; j++) {
@@ -824,19 +851,33 @@ __global__ __launch_bounds__(kRefBlock) void k_hem_refine(const uint2* __restric
     }
 }
 
-hipError_t launch_hem_refine(const uint2* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint2* out,
-                             uint64_t* fine_off, hipStream_t s)
+template <class R>
+hipError_t hem_refine(const R* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, R* out, uint64_t* fine_off,
+                      hipStream_t s)
 {
     if (kc < 9 || kc > 18 || k <= kc || k - kc > 2) return hipErrorInvalidValue;
     k_hem_refine<<<1u << kc, kRefBlock, 0, s>>>(in, coarse_off, 1u << kc, k, k - kc, out, fine_off);
     return hipGetLastError();
 }
 
+hipError_t launch_hem_refine(const uint2* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint2* out,
+                             uint64_t* fine_off, hipStream_t s)
+{
+    return hem_refine(in, coarse_off, kc, k, out, fine_off, s);
+}
+
+hipError_t launch_hem_refine(const uint4* in, const uint64_t* coarse_off, uint32_t kc, uint32_t k, uint4* out,
+                             uint64_t* fine_off, hipStream_t s)
+{
+    return hem_refine(in, coarse_off, kc, k, out, fine_off, s);
+}
+
 // Out-of-core HEM, first level: one chunk's signature records grouped by their top k - 8 bits
 // (the partition's first pass alone) into out; the chunk's NH + 1 group starts are copied to
 // host_gstart (pageable or pinned host memory, valid once the stream has reached the copy).
-hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, uint2* out, void* aux,
-                                  uint32_t* host_gstart, hipStream_t s)
+template <class R>
+hipError_t hem_group_chunk(const R* csig, uint64_t cn, uint32_t k, R* out, void* aux, uint32_t* host_gstart,
+                           hipStream_t s)
 {
     if (k < 9 || k > 18 || cn == 0) return hipErrorInvalidValue;
     const uint32_t NH = 1u << (k - 8), gsh = 40 - k;
@@ -846,35 +887,59 @@ hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, ui
     uint8_t* base = reinterpret_cast<uint8_t*>(aux);
     uint32_t* hist1 = reinterpret_cast<uint32_t*>(base + L.hist1);
     uint32_t* ginfo = reinterpret_cast<uint32_t*>(base + L.ginfo);
-    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{csig}, cn, gsh, NH, nt1, hist1);
+    k_part_hist1<<<(unsigned)nt1, kPtBlock, 0, s>>>(RecordsT<R>{csig}, cn, gsh, NH, nt1, hist1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     err = launch_scan_u32(hist1, (uint64_t)NH * nt1, hist1, base + L.scan, L.scan_bytes, s);
     if (err != hipSuccess) return err;
-    k_part_scatter1<Records><<<(unsigned)nt1, kPtBlock, 0, s>>>(Records{csig}, cn, gsh, NH, nt1, hist1, out);
+    k_part_scatter1<RecordsT<R>><<<(unsigned)nt1, kPtBlock, 0, s>>>(RecordsT<R>{csig}, cn, gsh, NH, nt1, hist1, out);
     k_part_groups<<<1, kPtBlock, 0, s>>>(hist1, NH, nt1, cn, ginfo);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
     return hipMemcpyAsync(host_gstart, ginfo, (NH + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
 }
 
+hipError_t launch_hem_group_chunk(const uint2* csig, uint64_t cn, uint32_t k, uint2* out, void* aux,
+                                  uint32_t* host_gstart, hipStream_t s)
+{
+    return hem_group_chunk(csig, cn, k, out, aux, host_gstart, s);
+}
+
+hipError_t launch_hem_group_chunk(const uint4* csig, uint64_t cn, uint32_t k, uint4* out, void* aux,
+                                  uint32_t* host_gstart, hipStream_t s)
+{
+    return hem_group_chunk(csig, cn, k, out, aux, host_gstart, s);
+}
+
 // Out-of-core HEM, second level: runs of grouped signatures copied into one batch buffer, one
 // workgroup per run (runs are at most 2^16 records; the host checks every run against both
 // buffers before the launch).
-__global__ __launch_bounds__(256) void k_hem_gather(const uint2* __restrict__ src, const HemRun* __restrict__ runs,
-                                                    uint2* __restrict__ dst)
+template <class R>
+__global__ __launch_bounds__(256) void k_hem_gather(const R* __restrict__ src, const HemRun* __restrict__ runs,
+                                                    R* __restrict__ dst)
 {
     const HemRun r = runs[blockIdx.x];
     for (uint32_t i = threadIdx.x; i < r.len; i += 256)
         dst[r.dst + i] = src[r.src + i];
 }
 
-hipError_t launch_hem_gather(const uint2* src, const HemRun* runs, uint32_t nruns, uint2* dst, hipStream_t s)
+template <class R>
+hipError_t hem_gather(const R* src, const HemRun* runs, uint32_t nruns, R* dst, hipStream_t s)
 {
     if (nruns == 0) return hipSuccess;
     if (nruns > 0x7FFFFFFFu) return hipErrorInvalidValue;
     k_hem_gather<<<nruns, 256, 0, s>>>(src, runs, dst);
     return hipGetLastError();
+}
+
+hipError_t launch_hem_gather(const uint2* src, const HemRun* runs, uint32_t nruns, uint2* dst, hipStream_t s)
+{
+    return hem_gather(src, runs, nruns, dst, s);
+}
+
+hipError_t launch_hem_gather(const uint4* src, const HemRun* runs, uint32_t nruns, uint4* dst, hipStream_t s)
+{
+    return hem_gather(src, runs, nruns, dst, s);
 }
 
 hipError_t launch_update_apply(const PeelState& st, uint32_t r, uint64_t count, hipStream_t s)

@@ -95,6 +95,15 @@ def test_hem_workspaces_follow_k_range_and_shape(mx):
         mx.set_option("hem_grid", 0)
     # beyond 2^18 buckets the coarse offsets of the refinement come on top
     assert mx.hem_workspace_bytes(1 << 22, 19) > mx.hem_workspace_bytes(1 << 22, 18)
+    # string keys' signature records are 16 bytes (the whole digest), u64 keys' 8: two arrays
+    # of n records each
+    n = 1 << 20
+    diff = mx.hem_workspace_bytes(n, 12, kind=mx.KEYS_STR) - mx.hem_workspace_bytes(n, 12, kind=mx.KEYS_U64)
+    assert diff == 2 * 8 * n
+    assert mx.hem_workspace_bytes(n, 12, kind=7) == 0
+    host_diff = (mx.hem_host_workspace_bytes(n, 12, mx.KEYS_STR, 1 << 16, 1 << 20, 1 << 18)
+                 - mx.hem_host_workspace_bytes(n, 12, mx.KEYS_U64, 1 << 16, 0, 1 << 18))
+    assert host_diff >= 8 * (n + (1 << 16) + 2 * (1 << 18))
 
 
 def test_info_struct_mirrors_match_the_header(mx):

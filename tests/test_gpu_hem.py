@@ -175,6 +175,37 @@ def test_hem_k19_matches_oracle(mx, o):
     assert np.array_equal(host(f), o.hem_lookup(ref, o.hem_signatures_u64(sample, 7), gnum=2, gden=1))
 
 
+def _str_subset(data, offs, idx):
+    """The keys idx of a string set, as a new (bytes, offsets) pair with 4-byte aligned data."""
+    lens = (offs[idx + 1] - offs[idx]).astype(np.int64)
+    so = np.zeros(len(idx) + 1, np.int64)
+    so[1:] = np.cumsum(lens)
+    sd = np.zeros(((int(so[-1]) + 3) // 4) * 4 or 4, np.uint8)
+    for j, i in enumerate(idx):
+        sd[so[j]:so[j + 1]] = data[offs[i]:offs[i + 1]]
+    return sd, so.view(np.uint64)
+
+
+def test_hem_str_k19_matches_oracle_in_hbm_and_from_host(mx, o):
+    """String keys at 2^19 buckets: the 128-bit signature records through the two-pass
+    partition and the refinement by the next bit, in HBM and streamed from host memory."""
+    import torch
+
+    data, offs = workloads.str_keys(6_000_000, gen_seed=319)
+    got = mx.hem_build(data=dev(data), offs=dev(offs), k=19, seed=8, gamma=(2, 1))
+    sigs = o.hem_signatures_str(data, offs, 8)
+    rc, ref = o.hem_build(sigs, 19, seed=8, gnum=2, gden=1)
+    assert rc == 0
+    _assert_same(got, ref)
+    sample = np.arange(0, 6_000_000, 89)
+    sd, so = _str_subset(data, offs, sample)
+    f = mx.hem_lookup(got, data=dev(sd), offs=dev(so))
+    assert np.array_equal(host(f), o.hem_lookup(ref, sigs[sample], gnum=2, gden=1))
+    got_h = mx.hem_build_host(data=torch.from_numpy(data), offs=torch.from_numpy(offs.view(np.int64)), k=19, seed=8,
+                              gamma=(2, 1), chunk_keys=1_500_000, chunk_bytes=1 << 27, batch_keys=2_500_000)
+    _assert_same(got_h, ref)
+
+
 def test_hem_host_k20_matches_oracle_and_device_build(mx, o):
     keys = workloads.u64_keys(24_000_000, gen_seed=220)
     got = mx.hem_build_host(keys=_host_u64(keys), k=20, seed=7, gamma=(2, 1), chunk_keys=5_000_000,
