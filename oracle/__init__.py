@@ -36,6 +36,7 @@ def compile_oracle(src: str = SRC, out: str = LIB, extra=()) -> str:
 def _bind(lib):
     sig = {
         "orc_splitmix": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+        "orc_set_progress": (None, [C.c_int]),
         "orc_part_size": (C.c_uint64, [C.c_uint64, C.c_uint32, C.c_uint32]),
         "orc_hash_u64": (None, [_u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u32p]),
         "orc_digest_str": (None, [_u8p, C.c_uint64, C.c_uint64, _u64p, _u64p]),

@@ -59,6 +59,7 @@
  * No floating point anywhere.  All arithmetic is on unsigned integers.
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -73,6 +74,10 @@
 #define ORC_MAX_DEGREE 255u
 
 static const uint64_t ORC_GAMMA = 0x9E3779B97F4A7C15ull;
+
+/* Progress lines on stderr from the peel and the assignment (long runs only; off by default). */
+static int orc_progress = 0;
+void orc_set_progress(int on) { orc_progress = on; }
 
 /* SplitMix64 output function (Steele, Lea & Flood 2014; Stafford's "Mix13" constants). */
 static uint64_t orc_fin(uint64_t z)
@@ -221,6 +226,10 @@ int orc_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t part_size, 
         if (info) { info[0] = 0; info[1] = 0; info[2] = maxdeg; }
         return ORC_ERANGE;
     }
+    if (orc_progress) {
+        fprintf(stderr, "[oracle] %llu incidence records built, maximum degree %u\n", (unsigned long long)(3 * n), maxdeg);
+        fflush(stderr);
+    }
 
     for (uint64_t e = 0; e < n; e++) {
         round[e] = ORC_NONE;
@@ -275,6 +284,11 @@ int orc_peel(const uint32_t* edges, uint64_t n, uint64_t m, uint64_t part_size, 
             }
         }
         peeled += nl;
+        if (orc_progress) {
+            fprintf(stderr, "[oracle] round %u: %llu edges peeled (%llu in all)\n", r, (unsigned long long)nl,
+                    (unsigned long long)peeled);
+            fflush(stderr);
+        }
         uint32_t* tmp = frontier;
         frontier = next;
         next = tmp;
@@ -349,6 +363,10 @@ int orc_assign(const uint32_t* edges, uint64_t n, uint64_t m, const uint32_t* or
             /* f(x) = k requires g[vk] + g[v1] + g[v2] = k (mod 3). */
             g[vk] = (uint8_t)((k + 6 - g[v1] - g[v2]) % 3);
             used[vk] = 1;
+        }
+        if (orc_progress) {
+            fprintf(stderr, "[oracle] layer of round %u assigned (%llu edges)\n", rr, (unsigned long long)(end - begin));
+            fflush(stderr);
         }
         end = begin;
     }
@@ -891,6 +909,11 @@ int orc_peel_r(const uint32_t* edges, uint64_t n, uint64_t m, uint32_t r, uint32
             }
         }
         peeled += nl;
+        if (orc_progress) {
+            fprintf(stderr, "[oracle] round %u: %llu edges peeled (%llu in all)\n", r, (unsigned long long)nl,
+                    (unsigned long long)peeled);
+            fflush(stderr);
+        }
         uint32_t* tmp = frontier;
         frontier = next;
         next = tmp;
