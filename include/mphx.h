@@ -475,6 +475,50 @@ MPHX_API double mphx_server_clock(void);
 MPHX_API int mphx_server_destroy(mphx_server* server);
 
 /* ---------------------------------------------------------------------------------------
+ * Streamed MWHC build of u64 keys held in HOST memory, for key sets whose in-HBM build does
+ * not fit the device (the paper builds 7.6 * 10^9 keys, Section 5).  The result -- codes and
+ * rank -- is the MWHC MPHF of Section 3 exactly as mphx_mphf_build_u64 defines it (the same
+ * hash, the same synchronous rounds and hinges, the same g), for any n with
+ * P = ceil(gamma n / 3) <= 2^32 (about 1.04 * 10^10 keys at gamma = 1.23; vertex positions
+ * k P + local beyond 2^32 are fine).
+ * The vertex record is the packed incidence list of Section 4.1 for r = 3: a degree byte and the
+ * XOR of the other two endpoints' part-local ids (Section 4.3's tripartition), from which a
+ * vertex of degree 1 reads its edge; no edge array and no edge ids exist.  Each round scans the
+ * degrees, appends the layer hinge first (runs by hinge part) and deletes it (Section 4.2); the
+ * assignment walks the layers in reverse round order (Section 4.3).
+ *   keys (host, n uint64; pinned gives the full PCIe rate) are copied in chunks of at most
+ *   chunk_keys keys, once per try.
+ *   layer_slots: slots of 12 bytes the device keeps for layers.  At least n: every layer stays
+ *   in device memory.  Less: each round's layer is copied to host_layers (host, 12 n bytes,
+ *   caller-owned) after its deletes and copied back, last round first, for the assignment; the
+ *   largest layer (round 0's, about 0.24 n at gamma 1.23) must fit, else MPHX_ENOMEM.
+ *   ws (dev, 256-byte aligned): mphx_stream_workspace_bytes(n, ...) bytes, about 9 bytes per
+ *   vertex + 12 per layer slot + 8 per chunk key.  codes (dev) ceil(m/32) words, rank (dev)
+ *   ceil(m/512) samples, as for mphx_mphf_build_u64.
+ * Errors: MPHX_EINVAL (bad arguments, n = 0, P > 2^32, layer_slots < n without host_layers),
+ * MPHX_ERANGE (a degree above 255), MPHX_ENOMEM (workspace, or a layer larger than the layer
+ * area), MPHX_ECORE (a 2-core on every try; equal keys also end here), MPHX_EDEVICE.
+ * Synchronises.  mphx_stream_workspace_bytes returns 0 for bad arguments.
+ * mphx_mphf_lookup_wide_u64: f(key) for MPHFs of any P <= 2^32 (out: dev, n uint64; keys dev).
+ * mphx_check_stream_u64: streams host keys through the evaluation and counts the values that
+ * are >= n or repeated (0 = the MPHF is a bijection onto [0, n), Section 1); ws:
+ * mphx_check_stream_workspace_bytes(n, chunk_keys) bytes (an n-bit map and one chunk).
+ * --------------------------------------------------------------------------------------- */
+MPHX_API size_t mphx_stream_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, uint64_t chunk_keys,
+                                            uint64_t layer_slots);
+MPHX_API int mphx_mphf_build_stream_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gamma_num,
+                                        uint32_t gamma_den, uint32_t max_tries, uint64_t chunk_keys,
+                                        uint64_t layer_slots, void* host_layers, size_t host_layer_bytes,
+                                        uint64_t* codes, uint64_t* rank, void* ws, size_t ws_bytes, void* stream,
+                                        mphx_mphf_info* info);
+MPHX_API int mphx_mphf_lookup_wide_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                                       const uint64_t* keys, uint64_t n, uint64_t* out, void* stream);
+MPHX_API size_t mphx_check_stream_workspace_bytes(uint64_t n, uint64_t chunk_keys);
+MPHX_API int mphx_check_stream_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                                   const uint64_t* keys, uint64_t n, uint64_t chunk_keys, void* ws, size_t ws_bytes,
+                                   void* stream, uint64_t* n_bad);
+
+/* ---------------------------------------------------------------------------------------
  * Synthetic key sets on the device (benchmark inputs; the same definitions as the host-side
  * generators that the tests use).  GAMMA and fin as above; S(s, t) = fin(s + t*GAMMA).
  *   u64 keys:     key_i = S(gen_seed, i + 1), i in [start, start + n).

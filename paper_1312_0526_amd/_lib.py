@@ -55,6 +55,12 @@ _SIGS = {
     "mphx_mphf_build_str": (_i32, [_vp, _vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _sz, _vp,
                                    C.POINTER(MphfInfo)]),
     "mphx_mphf_build_u64_static": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, C.POINTER(MphfInfo)]),
+    "mphx_stream_workspace_bytes": (_sz, [_u64, _u32, _u32, _u64, _u64]),
+    "mphx_mphf_build_stream_u64": (_i32, [_vp, _u64, _u64, _u32, _u32, _u32, _u64, _u64, _vp, _sz, _vp, _vp, _vp,
+                                          _sz, _vp, C.POINTER(MphfInfo)]),
+    "mphx_mphf_lookup_wide_u64": (_i32, [_vp, _vp, _u64, _u64, _vp, _u64, _vp, _vp]),
+    "mphx_check_stream_workspace_bytes": (_sz, [_u64, _u64]),
+    "mphx_check_stream_u64": (_i32, [_vp, _vp, _u64, _u64, _vp, _u64, _u64, _vp, _sz, _vp, C.POINTER(_u64)]),
     "mphx_sf_bits": (_u32, [_u64]),
     "mphx_sf_words": (_u64, [_u64, _u32, _u32, _u64]),
     "mphx_sf_workspace_bytes": (_sz, [_u64, _u32, _u32, _i32]),
@@ -287,6 +293,71 @@ def mphf_build_u64_static(keys: torch.Tensor, out, seed: int = 0, gamma=(123, 10
     if rc:
         _err(rc, info.as_dict())
     return _result(codes, rank, info, m)
+
+
+def stream_workspace_bytes(n: int, gamma=(123, 100), chunk_keys: int = 1 << 26, layer_slots: int = 0) -> int:
+    return int(lib().mphx_stream_workspace_bytes(n, gamma[0], gamma[1], chunk_keys, layer_slots or n))
+
+
+def mphf_build_stream_u64(keys: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64,
+                          chunk_keys: int = 1 << 26, layer_slots: int = 0, host_layers=None, ws=None, out=None,
+                          device="cuda") -> dict:
+    """MWHC MPHF of u64 keys held in host memory (a CPU int64 tensor), built by the streamed
+    path: the device holds the vertex records and layer_slots layer slots (0 = n: every layer
+    on the device); with fewer, the layers go to host_layers (a CPU uint8 tensor of 12 n bytes,
+    allocated here when not given).  Outputs equal mphf_build_u64's."""
+    _check_host(keys, torch.int64, "keys")
+    dev = torch.device(device)
+    n = keys.numel()
+    layer_slots = layer_slots or n
+    P = part_size(n, gamma)
+    m = 3 * P
+    if out is None:
+        codes = torch.empty(max((m + 31) // 32, 1), dtype=torch.int64, device=dev)
+        rank = torch.empty(max((m + 511) // 512, 1), dtype=torch.int64, device=dev)
+    else:
+        codes, rank = out
+    if layer_slots < n and host_layers is None:
+        host_layers = torch.empty(12 * n, dtype=torch.uint8)
+    if host_layers is not None:
+        _check_host(host_layers, torch.uint8, "host_layers")
+    need = stream_workspace_bytes(n, gamma, chunk_keys, layer_slots)
+    if need == 0:
+        raise ValueError("bad n, gamma, chunk_keys or layer_slots")
+    ws = ws if ws is not None else _workspace(need, dev)
+    info = MphfInfo()
+    rc = lib().mphx_mphf_build_stream_u64(_ptr(keys), n, seed, gamma[0], gamma[1], max_tries, chunk_keys, layer_slots,
+                                          _ptr(host_layers) if host_layers is not None else None,
+                                          host_layers.numel() if host_layers is not None else 0, _ptr(codes),
+                                          _ptr(rank), _ptr(ws), ws.numel(), _stream(dev), C.byref(info))
+    if rc:
+        _err(rc, info.as_dict())
+    return _result(codes, rank, info, m)
+
+
+def lookup_wide_u64(codes, rank, P: int, seed: int, keys: torch.Tensor, out=None) -> torch.Tensor:
+    """MPHF values of device keys for any P <= 2^32 (vertex positions beyond 2^32)."""
+    _check(keys, torch.int64, "keys")
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    rc = lib().mphx_mphf_lookup_wide_u64(_ptr(codes), _ptr(rank), P, seed, _ptr(keys), keys.numel(), _ptr(out),
+                                         _stream(keys.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+def check_stream_u64(codes, rank, P: int, seed: int, keys: torch.Tensor, chunk_keys: int = 1 << 26) -> int:
+    """Values of host keys (CPU int64 tensor) that are >= n or repeated: 0 for a bijection."""
+    _check_host(keys, torch.int64, "keys")
+    n = keys.numel()
+    ws = _workspace(int(lib().mphx_check_stream_workspace_bytes(n, chunk_keys)), codes.device)
+    bad = C.c_uint64(0)
+    rc = lib().mphx_check_stream_u64(_ptr(codes), _ptr(rank), P, seed, _ptr(keys), n, chunk_keys, _ptr(ws), ws.numel(),
+                                     _stream(codes.device), C.byref(bad))
+    if rc:
+        _err(rc)
+    return int(bad.value)
 
 
 def mphf_build_str(data: torch.Tensor, offs: torch.Tensor, seed: int = 0, gamma=(123, 100), max_tries: int = 64,

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmphx.so")
-SOURCES = ["scan.hip", "keys.hip", "peel.hip", "solve.hip", "batch.hip", "server.hip", "probe.hip", "part.hip", "abi.hip"]
+SOURCES = ["scan.hip", "keys.hip", "peel.hip", "solve.hip", "batch.hip", "server.hip", "probe.hip", "part.hip", "stream.hip", "abi.hip"]
 ARCH = os.environ.get("MPHX_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

@@ -2070,3 +2070,248 @@ int mphx_hem_lookup_str(const uint64_t* bucket_off, const uint64_t* code_off, co
 }
 
 }  // extern "C"
+
+// ---- streamed build: keys in host memory, one hypergraph of up to 3 * 2^32 vertices ----------
+namespace {
+
+struct StreamLayout {
+    uint8_t* deg;   // degree bytes, then the code bytes of the assignment
+    uint64_t* X;    // XOR packs of the other two endpoints
+    uint3* slots;   // the layer area
+    uint64_t* stage;  // one chunk of keys
+    uint32_t* bcount;
+    void* scan;
+    size_t scan_bytes;
+    Ctrl* ctrl;
+    unsigned long long* cursor;  // layer append cursor, then the three run bounds of the round
+};
+
+void layout_stream(Carve& c, uint64_t m, uint64_t chunk_keys, uint64_t layer_slots, StreamLayout& L)
+{
+    const uint64_t nblocks = (m + 511) / 512;
+    L.deg = c.take<uint8_t>((m + 3) & ~3ull);
+    L.X = c.take<uint64_t>(m);
+    L.slots = c.take<uint3>(layer_slots);
+    L.stage = c.take<uint64_t>(chunk_keys);
+    L.bcount = c.take<uint32_t>(nblocks);
+    L.scan_bytes = scan_scratch_bytes(nblocks);
+    L.scan = c.take<uint8_t>(L.scan_bytes);
+    L.ctrl = c.take<Ctrl>(1);
+    L.cursor = c.take<unsigned long long>(4);
+}
+
+// P <= 2^32 (part-local ids are 32-bit) and at least one vertex per part
+uint64_t stream_part_size(uint64_t n, uint32_t gnum, uint32_t gden)
+{
+    if (gnum == 0 || gden == 0 || n == 0) return 0;
+    const uint64_t P = mphx_part_size(n, gnum, gden);
+    return P <= (1ull << 32) ? P : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t mphx_stream_workspace_bytes(uint64_t n, uint32_t gamma_num, uint32_t gamma_den, uint64_t chunk_keys,
+                                   uint64_t layer_slots)
+{
+    const uint64_t P = stream_part_size(n, gamma_num, gamma_den);
+    if (!P || chunk_keys == 0 || layer_slots == 0) return 0;
+    Carve c(nullptr);
+    StreamLayout L;
+    layout_stream(c, 3 * P, chunk_keys, layer_slots, L);
+    return c.off;
+}
+
+int mphx_mphf_build_stream_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint32_t gamma_num,
+                               uint32_t gamma_den, uint32_t max_tries, uint64_t chunk_keys, uint64_t layer_slots,
+                               void* host_layers, size_t host_layer_bytes, uint64_t* codes, uint64_t* rank, void* ws,
+                               size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return fail(MPHX_EINVAL, "the streamed build needs at least one key");
+    if (!keys || !codes || !rank) return fail(MPHX_EINVAL, "null keys or outputs");
+    if (max_tries == 0) return fail(MPHX_EINVAL, "max_tries must be >= 1");
+    const uint64_t P = stream_part_size(n, gamma_num, gamma_den);
+    if (!P) return fail(MPHX_EINVAL, "gamma must be a positive fraction and P = ceil(gamma n / 3) at most 2^32");
+    const uint64_t m = 3 * P;
+    if (chunk_keys == 0 || layer_slots == 0) return fail(MPHX_EINVAL, "chunk_keys and layer_slots must be positive");
+    const bool spill = layer_slots < n;
+    if (spill && (!host_layers || host_layer_bytes < 12 * n))
+        return fail(MPHX_EINVAL, "layer_slots < n: host_layers must hold 12 n bytes");
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    const size_t need = mphx_stream_workspace_bytes(n, gamma_num, gamma_den, chunk_keys, layer_slots);
+    if (ws_bytes < need) return fail(MPHX_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
+    if (info) {
+        memset(info, 0, sizeof *info);
+        info->P = P;
+        info->m = m;
+        info->seed_used = seed;
+    }
+    Carve c(ws);
+    StreamLayout L;
+    layout_stream(c, m, chunk_keys, layer_slots, L);
+    uint8_t* const hl = static_cast<uint8_t*>(host_layers);
+
+    struct DrainOnExit {
+        hipStream_t s;
+        ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+    } drain{s};
+    HostStager stager(s);  // host key chunks (and spilled layers) go through its pinned buffers
+
+    // per round: where its runs of hinge parts 0, 1, 2 start, and where it ends (device
+    // positions without spilling, host slot positions with)
+    std::vector<uint64_t> bounds;
+    uint64_t peeled = 0;
+    uint32_t rounds = 0;
+    bool done = false;
+    uint32_t t = 0;
+    for (t = 0; t < max_tries && !done; t++) {
+        const uint64_t sd = seed + t;
+        HIP_TRY(launch_zero(L.deg, (m + 3) & ~3ull, s));
+        HIP_TRY(launch_zero(L.X, m * sizeof(uint64_t), s));
+        HIP_TRY(launch_zero(L.ctrl, sizeof(Ctrl), s));
+        {
+            Timed tm(PH_BUILD, s);
+            for (uint64_t c0 = 0; c0 < n; c0 += chunk_keys) {
+                const uint64_t cn = std::min(chunk_keys, n - c0);
+                HIP_TRY(stager.copy(L.stage, keys + c0, cn * sizeof(uint64_t)));
+                HIP_TRY(launch_st_build(L.stage, cn, sd, P, L.deg, L.X, L.ctrl, s));
+            }
+        }
+        Ctrl h;
+        int rc = read_ctrl(L.ctrl, h, s);
+        if (rc) return rc;
+        if (h.err & kErrDegree) {
+            if (info) { info->tries = t + 1; info->seed_used = sd; }
+            return fail(MPHX_ERANGE, "a vertex has degree above %u", MPHX_MAX_DEGREE);
+        }
+        bounds.clear();
+        peeled = 0;
+        uint64_t at = 0;  // device position of the next layer
+        for (rounds = 0;; rounds++) {
+            unsigned long long b[4];
+            b[0] = spill ? 0 : at;
+            HIP_TRY(hipMemcpyAsync(L.cursor, &b[0], sizeof b[0], hipMemcpyHostToDevice, s));
+            {
+                Timed tm(PH_FRONTIER, s);
+                for (uint32_t k = 0; k < 3; k++) {
+                    HIP_TRY(launch_st_claim(L.deg, L.X, P, k, L.slots, layer_slots, L.cursor, L.ctrl, s));
+                    HIP_TRY(hipMemcpyAsync(L.cursor + 1 + k, L.cursor, sizeof b[0], hipMemcpyDeviceToDevice, s));
+                }
+            }
+            HIP_TRY(hipMemcpyAsync(b + 1, L.cursor + 1, 3 * sizeof b[0], hipMemcpyDeviceToHost, s));
+            rc = read_ctrl(L.ctrl, h, s);
+            if (rc) return rc;
+            if (h.err & kErrCapacity)
+                return fail(MPHX_ENOMEM, "round %u: the layer exceeds the layer area of %llu slots", rounds,
+                            (unsigned long long)layer_slots);
+            const uint64_t cnt = b[3] - b[0];
+            if (cnt == 0) break;
+            {
+                Timed tm(PH_APPLY, s);
+                HIP_TRY(launch_st_apply(L.slots, b[0], b[1], b[2], b[3], P, L.deg, L.X, s));
+            }
+            if (spill) {  // the round's slots to host memory; the area is reused by the next round
+                Timed tm(PH_OTHER, s);
+                HIP_TRY(hipMemcpyAsync(hl + 12 * peeled, L.slots, 12 * cnt, hipMemcpyDeviceToHost, s));
+                for (int q = 0; q < 4; q++) bounds.push_back(peeled + (b[q] - b[0]));
+            } else {
+                for (int q = 0; q < 4; q++) bounds.push_back(b[q]);
+                at = b[3];
+            }
+            if (info && rounds == 0) info->layer0 = cnt;
+            peeled += cnt;
+        }
+        if (info) {
+            info->tries = t + 1;
+            info->seed_used = sd;
+            info->n_rounds = rounds;
+            info->n_core = n - peeled;
+        }
+        done = peeled == n;
+    }
+    if (!done)
+        return fail(MPHX_ECORE, "2-core of %llu edges after %u tries", (unsigned long long)(n - peeled), max_tries);
+
+    // assignment, last layer first (Section 4.3), the codes in the degree bytes (all zero now)
+    uint8_t* code8 = L.deg;
+    HIP_TRY(launch_zero(code8, (m + 3) & ~3ull, s));
+    for (int64_t r = (int64_t)rounds - 1; r >= 0; r--) {
+        const uint64_t* b = &bounds[4 * r];
+        uint64_t lo = b[0];
+        if (spill) {
+            Timed tm(PH_OTHER, s);
+            HIP_TRY(stager.copy(L.slots, hl + 12 * b[0], 12 * (b[3] - b[0])));
+            lo = 0;
+        }
+        Timed tm(PH_ASSIGN, s);
+        HIP_TRY(launch_st_assign(L.slots, lo, lo + (b[1] - b[0]), lo + (b[2] - b[0]), lo + (b[3] - b[0]), P, code8, s));
+    }
+    {
+        Timed tm(PH_RANK, s);
+        HIP_TRY(launch_pack_count(code8, m, codes, L.bcount, s));
+        const uint64_t nblocks = (m + 511) / 512;
+        HIP_TRY(launch_scan_u32_to_u64(L.bcount, nblocks, rank, nblocks, L.scan, L.scan_bytes, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    g_timers.harvest();
+    return MPHX_OK;
+}
+
+int mphx_mphf_lookup_wide_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                              const uint64_t* keys, uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    if (!codes || !rank || !keys || !out || P == 0 || P > (1ull << 32)) return fail(MPHX_EINVAL, "bad arguments");
+    HIP_TRY(launch_st_lookup(codes, rank, P, seed, keys, n, out, nullptr, n, nullptr, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+size_t mphx_check_stream_workspace_bytes(uint64_t n, uint64_t chunk_keys)
+{
+    if (chunk_keys == 0) return 0;
+    Carve c(nullptr);
+    c.take<Ctrl>(1);
+    c.take<uint32_t>((n + 31) / 32);
+    c.take<uint64_t>(chunk_keys);
+    return c.off;
+}
+
+int mphx_check_stream_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                          const uint64_t* keys, uint64_t n, uint64_t chunk_keys, void* ws, size_t ws_bytes,
+                          void* stream, uint64_t* n_bad)
+{
+    g_err.clear();
+    hipStream_t s = (hipStream_t)stream;
+    if (!codes || !rank || (!keys && n) || !n_bad || P == 0 || P > (1ull << 32) || chunk_keys == 0)
+        return fail(MPHX_EINVAL, "bad arguments");
+    if (!ws || !aligned256(ws)) return fail(MPHX_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if (ws_bytes < mphx_check_stream_workspace_bytes(n, chunk_keys)) return fail(MPHX_ENOMEM, "workspace too small");
+    Carve c(ws);
+    Ctrl* ctrl = c.take<Ctrl>(1);
+    uint32_t* bitmap = c.take<uint32_t>((n + 31) / 32);
+    uint64_t* stage = c.take<uint64_t>(chunk_keys);
+    struct DrainOnExit {
+        hipStream_t s;
+        ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+    } drain{s};
+    HostStager stager(s);
+    HIP_TRY(launch_zero(ctrl, sizeof(Ctrl), s));
+    HIP_TRY(launch_zero(bitmap, ((n + 31) / 32) * sizeof(uint32_t), s));
+    for (uint64_t c0 = 0; c0 < n; c0 += chunk_keys) {
+        const uint64_t cn = std::min(chunk_keys, n - c0);
+        HIP_TRY(stager.copy(stage, keys + c0, cn * sizeof(uint64_t)));
+        HIP_TRY(launch_st_lookup(codes, rank, P, seed, stage, cn, nullptr, bitmap, n, ctrl, s));
+    }
+    Ctrl h;
+    int rc = read_ctrl(ctrl, h, s);
+    if (rc) return rc;
+    *n_bad = h.aux;
+    return MPHX_OK;
+}
+
+}  // extern "C"
+

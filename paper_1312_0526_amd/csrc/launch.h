@@ -235,4 +235,21 @@ hipError_t launch_hem_refine(const uint4* in, const uint64_t* coarse_off, uint32
                              uint64_t* fine_off, hipStream_t s);
 hipError_t launch_offs_rebase(uint64_t* offs, uint64_t count, uint64_t base, hipStream_t s);
 
+// Streamed build (stream.hip): records as degree bytes (deg, (m + 3) & ~3 bytes, zeroed) and XOR
+// packs of the two other endpoints' part-local ids (X, m words, zeroed); layers as slots
+// (vh, va, vb) of part-local ids in runs by hinge part.
+hipError_t launch_st_build(const uint64_t* keys, uint64_t cn, uint64_t seed, uint64_t P, uint8_t* deg, uint64_t* X,
+                           Ctrl* ctrl, hipStream_t s);
+hipError_t launch_st_claim(const uint8_t* deg, const uint64_t* X, uint64_t P, uint32_t k, uint3* slots, uint64_t cap,
+                           unsigned long long* cursor, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_st_apply(const uint3* slots, uint64_t lo, uint64_t b1, uint64_t b2, uint64_t hi, uint64_t P,
+                           uint8_t* deg, uint64_t* X, hipStream_t s);
+hipError_t launch_st_assign(const uint3* slots, uint64_t lo, uint64_t b1, uint64_t b2, uint64_t hi, uint64_t P,
+                            uint8_t* code8, hipStream_t s);
+// f(key) for keys[0, cn) into out (nullable); with bitmap (n_total bits), each value is marked
+// and ctrl->aux counts values >= n_total or marked twice
+hipError_t launch_st_lookup(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,
+                            const uint64_t* keys, uint64_t cn, uint64_t* out, uint32_t* bitmap, uint64_t n_total,
+                            Ctrl* ctrl, hipStream_t s);
+
 }  // namespace mphx

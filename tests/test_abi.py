@@ -197,3 +197,18 @@ def test_batch_autotune_arguments_need_no_device(mx):
     assert call(cands=bad, ncand=1) == mx.EINVAL
     assert call() == mx.EINVAL  # null keys and outputs for a non-empty batch
     assert call(B=0) == 0 and best.value == 0 and list(ms) == [0.0] * n
+
+
+def test_stream_workspace_sizes(mx):
+    n = 1 << 24
+    base = mx.stream_workspace_bytes(n, chunk_keys=1 << 20, layer_slots=n)
+    # 12 bytes per layer slot; records of 9 bytes per vertex
+    assert mx.stream_workspace_bytes(n, chunk_keys=1 << 20, layer_slots=n // 2) == base - 12 * (n - n // 2) or \
+        abs(mx.stream_workspace_bytes(n, chunk_keys=1 << 20, layer_slots=n // 2) - (base - 6 * n)) < 512
+    m = 3 * mx.part_size(n)
+    assert base > 9 * m + 12 * n
+    # P above 2^32, zero keys or zero sizes: no workspace
+    assert mx.stream_workspace_bytes(11_000_000_000) == 0
+    assert mx.lib().mphx_stream_workspace_bytes(0, 123, 100, 1, 1) == 0
+    assert mx.lib().mphx_stream_workspace_bytes(1000, 123, 100, 0, 1) == 0
+    assert mx.lib().mphx_stream_workspace_bytes(10_000_000_000, 123, 100, 1 << 20, 1 << 20) > 0

@@ -1,27 +1,44 @@
 """Parity at the full workload sizes (GPU only; minutes of CPU for the oracle).
 
+The oracle's results at the sizes it cannot build inside a test run are stored as digests in
+tests/golden/ by tests/golden/make_fullsize.py (which runs only the oracle): config 3's 2^31-key
+MPHF, each of config 4's 65,536 buckets and each of config 5's 60 requests.
+
 * 2^27 u64 keys: the whole MPHF (codes + rank) equals the oracle's, with atomic claims and
   with claim and update lists; at gamma = 120/100 (below
   the threshold c_3 ~ 1.221, Section 1) the peel returns exactly the oracle's 2-core, rounds,
   hinges and order, and a one-try build reports the same 2-core size.
 * 2^31 byte-string keys generated on the device (the configuration the benchmark times): the
-  oracle cannot build it, so the test checks what holds at any size -- the device keys equal
-  the generator's definition at sampled indices, the device hash equals the oracle's hash for
-  those keys, the MPHF is a bijection onto [0, n) over all keys, the rank samples equal the
-  prefix counts of the codes, and the oracle's evaluation of the GPU tables agrees with the
-  GPU lookup at sampled keys.
-* 65,536 u64 buckets of 100 to 10^6 keys in one captured batched launch: every bucket builds,
-  and the largest buckets and a random sample equal the oracle's single builds.
+  codes and rank equal the oracle's bit for bit (SHA-256 of both against the golden digest;
+  P, seed, tries and rounds equal); besides, the device keys equal the generator's definition
+  at sampled indices, the device hash equals the oracle's hash for those keys, the MPHF is a
+  bijection onto [0, n) over all keys, the rank samples equal the prefix counts of the codes,
+  and the oracle's evaluation of the GPU tables agrees with the GPU lookup at sampled keys.
+* 65,536 u64 buckets of 100 to 10^6 keys in one captured batched launch: every bucket equals
+  the oracle's single build (tries, rounds and a digest of its codes and rank), and the two
+  largest are compared word for word with a fresh oracle build.
 * The served workload at full size (requests of 10^3 to 10^8 keys): every result equals the
-  request built alone, the largest ones are bijections, small ones equal the oracle.
+  oracle's (tries, seed, rounds, digest of codes and rank) and the request built alone, and the
+  largest ones are bijections.
 """
+import hashlib
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads
 
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import make_fullsize as golden  # noqa: E402
+
 pytestmark = pytest.mark.gpu
+
+
+def _digest(codes_h, rank_h):
+    return golden.digest(codes_h, rank_h)
 
 
 @pytest.fixture(scope="module")
@@ -100,7 +117,7 @@ def _nz_pairs(words):
 
 
 @pytest.mark.timeout(1200)
-def test_config3_sampled_parity(mx):
+def test_config3_full_parity(mx):
     import torch
 
     n = 1 << 31
@@ -140,14 +157,20 @@ def test_config3_sampled_parity(mx):
     prefix = np.concatenate([[0], np.cumsum(per_block)[:-1]])
     assert np.array_equal(rank.astype(np.int64), prefix)
     assert int(nz.sum()) == n
+    # bit for bit the oracle's MPHF of all 2^31 keys
+    g = golden.read_c3()
+    assert (g["n"], g["P"], g["seed_used"], g["tries"], g["n_rounds"]) == (n, P, seed, r["tries"], r["n_rounds"])
+    assert (g["code_words"], g["rank_words"]) == (len(codes), len(rank))
+    assert hashlib.sha256(codes.tobytes()).hexdigest() == g["codes_sha256"]
+    assert hashlib.sha256(rank.tobytes()).hexdigest() == g["rank_sha256"]
 
 
 @pytest.mark.timeout(600)
-def test_config4_full_batch_sampled_parity(mx):
+def test_config4_full_batch_parity(mx):
     # 65,536 buckets of 100 to 10^6 u64 keys (log-uniform, 7.09e9 keys) in one captured
     # persistent launch at 1024 threads x one workgroup per compute unit, as the benchmark runs
-    # it: every bucket builds, the sum of the per-bucket code and rank lengths is the layout's,
-    # and the largest buckets and a random sample equal the oracle's single builds
+    # it: every bucket equals the oracle's build of it (tries, rounds, digest of codes and rank,
+    # from the golden file), and the two largest equal a fresh oracle build word for word
     import torch
 
     torch.cuda.empty_cache()
@@ -164,8 +187,20 @@ def test_config4_full_batch_sampled_parity(mx):
     res = bb.bucket_results()
     assert (res["status"] == 0).all() and (res["tries"] >= 1).all()
     assert int(bb.code_off_h[-1]) == bb.codes.numel() and int(bb.rank_off_h[-1]) == bb.rank.numel()
-    rng = np.random.default_rng(11)
-    which = np.argsort(-sizes, kind="stable")[:2].tolist() + rng.choice(len(sizes), 24, replace=False).tolist()
+    gold = golden.read_c4()
+    assert len(gold) == len(sizes)
+    codes_h = host(bb.codes, np.uint64)
+    rank_h = host(bb.rank, np.uint64)
+    co, ro = bb.code_off_h.astype(np.int64), bb.rank_off_h.astype(np.int64)
+    bad = []
+    for b in range(len(sizes)):
+        tries, rounds, d = gold[b]
+        got = _digest(codes_h[co[b]:co[b + 1]], rank_h[ro[b]:ro[b + 1]])[:12]
+        if (int(res[b]["tries"]), int(res[b]["n_rounds"]), got) != (tries, rounds, d):
+            bad.append(b)
+    assert not bad, f"{len(bad)} buckets differ from the oracle, first {bad[:10]}"
+    del codes_h, rank_h
+    which = np.argsort(-sizes, kind="stable")[:2].tolist()
     for b in which:
         kb = host(keys[int(off[b]):int(off[b + 1])], np.uint64)
         assert np.array_equal(kb, workloads.u64_keys(int(sizes[b]), gen_seed=workloads.bucket_gen_seed(b))), b
@@ -206,8 +241,13 @@ def test_config5_served_full_sizes(mx):
                for i in range(nreq)]
     res = [srv.wait(t) for t in tickets]
     torch.cuda.synchronize()
+    gold = golden.read_c5()
     for i, r in enumerate(res):
         assert r["status"] == 0, i
+        g = gold[i]
+        assert (g["kind"], g["n"]) == (int(kinds[i]), int(sizes[i])), i
+        assert (r["seed_used"], r["tries"], r["n_rounds"]) == (g["seed_used"], g["tries"], g["n_rounds"]), i
+        assert _digest(host(r["codes"], np.uint64), host(r["rank"], np.uint64)) == g["digest"], i
         a = mx.mphf_build_u64(*req(i), seed=i) if kinds[i] == 0 else mx.mphf_build_str(*req(i), seed=i)
         assert (r["tries"], r["seed_used"], r["P"]) == (a["tries"], a["seed_used"], a["P"]), i
         assert torch.equal(r["codes"], a["codes"]) and torch.equal(r["rank"], a["rank"]), i
@@ -219,16 +259,44 @@ def test_config5_served_full_sizes(mx):
         else:
             f = mx.lookup_str(r["codes"], r["rank"], r["P"], r["seed_used"], data, offs[: int(sizes[i]) + 1])
         assert mx.check_bijection(f) == 0, i
-    o = oracle.Oracle()
-    small = [i for i in range(nreq) if sizes[i] <= 200_000][:8]
-    assert len(small) >= 4
-    for i in small:
-        n = int(sizes[i])
-        if kinds[i] == 0:
-            rc, ref = o.mphf_build_u64(host(keys[:n], np.uint64), seed=i)
-        else:
-            oh = host(offs[: n + 1], np.uint64)
-            rc, ref = o.mphf_build_str(data[: int(oh[-1])].cpu().numpy(), oh, seed=i)
-        assert rc == 0 and np.array_equal(host(res[i]["codes"], np.uint64), ref["words"]), i
-        assert np.array_equal(host(res[i]["rank"], np.uint64), ref["rank"]), i
+    # the device key sets are the generator's (the golden digests were built from it)
+    assert np.array_equal(host(keys[-1000:], np.uint64), workloads.u64_keys(max_n, gen_seed=7)[-1000:])
+    oh = host(offs[:1001], np.uint64)
+    d_h, o_h = workloads.str_keys(1000, gen_seed=8)
+    assert np.array_equal(oh, o_h) and np.array_equal(data[: int(oh[-1])].cpu().numpy(), d_h[: int(oh[-1])])
     srv.close()
+
+
+@pytest.mark.timeout(1200)
+def test_stream_beyond_2e32_vertices(mx):
+    """The streamed build past the in-HBM build's limit: 3.6e9 u64 keys in host memory, so
+    m = 3P = 4.43e9 vertex positions pass 2^32 (the oracle's 32-bit vertex ids cannot express
+    this; checked by what holds at any size).  The MPHF is a bijection onto [0, n) over all
+    keys, its rank samples are the prefix counts of its codes, and the build with every layer
+    spilled to host memory gives the same codes and rank as the build with the layers in HBM."""
+    import torch
+
+    torch.cuda.empty_cache()
+    n = 3_600_000_000
+    P = mx.part_size(n)
+    assert 3 * P > (1 << 32)
+    hk = torch.empty(n, dtype=torch.int64)
+    chunk = 1 << 27
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        hk[c0:c1].copy_(mx.gen_keys_u64(c1 - c0, gen_seed=36, start=c0))
+    assert np.array_equal(hk[-1000:].numpy().view(np.uint64), workloads.u64_keys(1000, gen_seed=36, start=n - 1000))
+    a = mx.mphf_build_stream_u64(hk, seed=0, chunk_keys=chunk)
+    assert a["n_core"] == 0 and a["P"] == P
+    assert mx.check_stream_u64(a["codes"], a["rank"], a["P"], a["seed_used"], hk, chunk_keys=chunk) == 0
+    codes = host(a["codes"], np.uint64)
+    rank = host(a["rank"], np.uint64)
+    nz = _nz_pairs(codes)
+    per_block = np.add.reduceat(nz, np.arange(0, len(nz), 16))
+    assert np.array_equal(rank.astype(np.int64), np.concatenate([[0], np.cumsum(per_block)[:-1]]))
+    assert int(nz.sum()) == n
+    del a, nz, per_block
+    torch.cuda.empty_cache()
+    b = mx.mphf_build_stream_u64(hk, seed=0, chunk_keys=chunk, layer_slots=(3 * n) // 10)
+    assert (b["tries"], b["n_rounds"]) == (1, b["n_rounds"])
+    assert np.array_equal(host(b["codes"], np.uint64), codes) and np.array_equal(host(b["rank"], np.uint64), rank)
