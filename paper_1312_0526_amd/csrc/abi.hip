@@ -2202,9 +2202,8 @@ int mphx_mphf_build_stream_u64(const uint64_t* keys, uint64_t n, uint64_t seed, 
                 }
             }
             HIP_TRY(hipMemcpyAsync(b + 1, L.cursor + 1, 3 * sizeof b[0], hipMemcpyDeviceToHost, s));
-            rc = read_ctrl(L.ctrl, h, s);
-            if (rc) return rc;
-            if (h.err & kErrCapacity)
+            HIP_TRY(hipStreamSynchronize(s));
+            if (b[3] > layer_slots)  // slots past the area were counted, not stored
                 return fail(MPHX_ENOMEM, "round %u: the layer exceeds the layer area of %llu slots", rounds,
                             (unsigned long long)layer_slots);
             const uint64_t cnt = b[3] - b[0];

@@ -16,7 +16,6 @@ constexpr int kWave = 64;
 constexpr uint32_t kErrBadEdge = 1u;  // vertex id >= m or a repeated vertex in an edge
 constexpr uint32_t kErrDegree = 2u;   // a vertex reached degree 256
 constexpr uint32_t kErrValue = 4u;    // a static-function value outside [0, sigma)
-constexpr uint32_t kErrCapacity = 8u; // a list or layer area overflowed
 
 // Device-side control block of one peeling run (lives in the workspace).
 struct Ctrl {

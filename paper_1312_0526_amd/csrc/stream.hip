@@ -76,49 +76,53 @@ __global__ __launch_bounds__(kStBlock) void k_st_build(const uint64_t* __restric
 
 // Round start, part k: every vertex of degree 1 whose edge has no degree-1 vertex in a lower
 // part appends the edge hinge first.  Each thread looks at four consecutive vertices (one
-// 32-bit word of degrees); appends take one atomic per wave.
+// 32-bit word of degrees) per pass; the appends gather in an LDS buffer and go out with one
+// cursor atomic per buffer (all hinges of a round append to one cursor, whose atomics
+// serialise: one per wave would cost far more than the scan).
+using StAppender = BlockAppender<uint3, kStBlock, 8 * kStBlock>;
+
 __global__ __launch_bounds__(kStBlock) void k_st_claim(const uint8_t* __restrict__ deg, const uint64_t* __restrict__ X,
                                                        uint64_t P, uint32_t k, uint3* __restrict__ slots, uint64_t cap,
-                                                       unsigned long long* cursor, Ctrl* ctrl)
+                                                       unsigned long long* cursor)
 {
+    __shared__ StAppender app;
+    app.init();
     const uint64_t base = (uint64_t)k * P;
     const uint64_t words = (P + 3) / 4 + 1;  // the part may start inside a word
     const uint64_t w_first = base / 4;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    bool overflow = false;
-    for (uint64_t wb = (uint64_t)blockIdx.x * blockDim.x; wb < words; wb += stride) {  // uniform per wave
+    auto out = [slots, cap](uint64_t i, uint3 sl) {
+        if (i < cap) slots[i] = sl;
+    };
+    for (uint64_t wb = (uint64_t)blockIdx.x * blockDim.x; wb < words; wb += stride) {  // uniform per block
         const uint64_t w = w_first + wb + threadIdx.x;
         uint32_t dw = 0;
         if (wb + threadIdx.x < words && 4 * w < base + P)
             dw = reinterpret_cast<const uint32_t*>(deg)[w];
+        bool hinge[4] = {false, false, false, false};
+        uint3 sl[4];
 #pragma unroll
         for (uint32_t j = 0; j < 4; j++) {
             const uint64_t v = 4 * w + j;
-            bool hinge = false;
-            uint3 sl = make_uint3(0u, 0u, 0u);
+            sl[j] = make_uint3(0u, 0u, 0u);
             if (((dw >> (8 * j)) & 255u) == 1u && v >= base && v < base + P) {
                 const uint64_t x = X[v];
                 const uint32_t a = (uint32_t)x, b = (uint32_t)(x >> 32);  // ids in parts k+1, k+2
-                hinge = true;
-                if (k >= 1) {  // part 0's vertex: b when k = 1, a when k = 2
-                    const uint32_t u0 = k == 1 ? b : a;
-                    hinge = deg[u0] != 1;
-                }
-                if (k == 2 && hinge)  // part 1's vertex
-                    hinge = deg[P + b] != 1;
-                sl = make_uint3((uint32_t)(v - base), a, b);
-            }
-            const uint64_t at = wave_append(cursor, hinge, false);
-            if (hinge) {
-                if (at < cap)
-                    slots[at] = sl;
-                else
-                    overflow = true;
+                bool h = true;
+                if (k >= 1)  // part 0's vertex: b when k = 1, a when k = 2
+                    h = deg[k == 1 ? b : a] != 1;
+                if (k == 2 && h)  // part 1's vertex
+                    h = deg[P + b] != 1;
+                hinge[j] = h;
+                sl[j] = make_uint3((uint32_t)(v - base), a, b);
             }
         }
+        if (__syncthreads_or(hinge[0] | hinge[1] | hinge[2] | hinge[3])) {
+            app.push(hinge[0], sl[0], hinge[1], sl[1], cursor, out);
+            app.push(hinge[2], sl[2], hinge[3], sl[3], cursor, out);
+        }
     }
-    if (overflow)
-        atomicOr(&ctrl->err, kErrCapacity);  // the layer area is too small for this round
+    app.flush(cursor, out);  // slots past cap are counted, not stored: the host checks the cursor
 }
 
 // DeleteEdge of every edge of a layer (runs [lo, b1), [b1, b2), [b2, hi) of hinge parts 0, 1, 2).
@@ -224,7 +228,8 @@ hipError_t launch_st_claim(const uint8_t* deg, const uint64_t* X, uint64_t P, ui
                            unsigned long long* cursor, Ctrl* ctrl, hipStream_t s)
 {
     if (P == 0 || k > 2) return hipSuccess;
-    k_st_claim<<<grid_for_st((P + 3) / 4 + 1, 16384), kStBlock, 0, s>>>(deg, X, P, k, slots, cap, cursor, ctrl);
+    (void)ctrl;
+    k_st_claim<<<grid_for_st((P + 3) / 4 + 1, 16384), kStBlock, 0, s>>>(deg, X, P, k, slots, cap, cursor);
     return hipGetLastError();
 }
 
