@@ -40,6 +40,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """The host CPU the oracle ran on: model name, logical CPUs, and those this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return dict(cpu_model=model, nproc=os.cpu_count(), cpus_usable=usable)
+
+
 # Algorithmic bytes per edge of each step of the path, frozen before measuring: every logical
 # element counted once per required access at its element size, never at cache-line size.
 #   hash    u64: key 8 + edge 12; strings: the key bytes + an 8-byte offset + edge 12
@@ -448,6 +466,47 @@ def peel_r_leg(args, mx, torch) -> dict:
     return dict(workload=f"peel_r_uniform_n{n}", rows=rows)
 
 
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+
+
+def golden_header(path: str) -> list:
+    """Comment lines of a golden digest file (plain or gzip text), or [] when it is absent."""
+    import gzip
+
+    if not os.path.exists(path):
+        return []
+    opener = gzip.open if path.endswith(".gz") else open
+    with opener(path, "rt") as fh:
+        return [ln[1:].strip() for ln in fh if ln.startswith("#")]
+
+
+def oracle_all_core_c4() -> dict:
+    """The all-core oracle run behind the 65,536-bucket golden digests: one unchanged oracle
+    build per bucket, buckets spread over processes; wall time and keys from its header."""
+    import re
+
+    for ln in golden_header(os.path.join(GOLDEN_DIR, "c4_buckets_65536.txt.gz")):
+        m = re.match(r"(\d+) oracle processes on (\d+) host CPUs, (\d+) s wall, (\d+) keys", ln)
+        if m:
+            procs, cpus, wall, keys = (int(x) for x in m.groups())
+            return dict(value=round(keys / wall, 1), unit="keys/s", processes=procs, host_cpus=cpus, wall_s=wall,
+                        keys=keys, kind="oracle", source="tests/golden/c4_buckets_65536.txt.gz (make_fullsize.py c4)")
+    return {}
+
+
+def oracle_per_request_c5(np) -> dict:
+    """Single-threaded oracle build times of the served workload's 60 full-size requests
+    (golden digests' run; key generation excluded): p50 and p99."""
+    path = os.path.join(GOLDEN_DIR, "c5_served_60.txt")
+    if not os.path.exists(path):
+        return {}
+    secs = [float(ln.split()[-1]) for ln in open(path) if not ln.startswith("#") and ln.strip()]
+    head = [h for h in golden_header(path) if "host CPUs" in h]
+    return dict(requests=len(secs), p50_ms=round(float(np.percentile(secs, 50)) * 1e3, 1),
+                p99_ms=round(float(np.percentile(secs, 99)) * 1e3, 1), kind="oracle", cores=1,
+                source="tests/golden/c5_served_60.txt (make_fullsize.py c5)" + (f": {head[0]}" if head else ""))
+
+
 def batched_leg(args, mx, torch, np, workloads) -> dict:
     """65,536 independent u64 buckets, sizes floor(100 * 10^(4u)), one captured persistent
     launch per step; beside it the plain path on a sample of the same buckets."""
@@ -518,27 +577,48 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     extra_tries = int(res["tries"].sum() - len(res))
     log(f"[batched] median {sec * 1000:.1f} ms/step, {ok_keys / sec / 1e9:.3f} G keys/s, "
         f"{int((~ok).sum())} failed buckets, {extra_tries} retries")
-    # the plain path (one mphf_build_u64 per bucket) on a random sample of the same buckets
+    # the plain path (one mphf_build_u64 per bucket) on a random sample of the same buckets,
+    # with one workspace and one pair of output buffers allocated before timing (sized for the
+    # sample's largest bucket), so the calls time the build, not allocation
     rng = np.random.default_rng(1)
     sample = rng.choice(len(sizes), size=min(args.plain_sample, len(sizes)), replace=False)
+    nmax = int(sizes[sample].max())
+    mmax = 3 * mx.part_size(nmax, (123, 100))
+    pws = torch.empty(mx.mphf_workspace_bytes(nmax), dtype=torch.uint8, device=dev)
+    pout = (torch.empty((mmax + 31) // 32, dtype=torch.int64, device=dev),
+            torch.empty((mmax + 511) // 512, dtype=torch.int64, device=dev))
+    mx.mphf_build_u64(keys[int(off[sample[0]]):int(off[sample[0] + 1])], seed=0, ws=pws, out=pout)  # warm
     plain_keys = plain_sec = 0
+    by_class = {}
     for b in sample:
         kb = keys[int(off[b]):int(off[b + 1])]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        mx.mphf_build_u64(kb, seed=0)
+        mx.mphf_build_u64(kb, seed=0, ws=pws, out=pout)
         torch.cuda.synchronize()
-        plain_sec += time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        plain_sec += dt
         plain_keys += int(sizes[b])
+        c = by_class.setdefault(f"1e{int(np.log10(sizes[b]))}", [0, 0.0, 0])
+        c[0] += int(sizes[b])
+        c[1] += dt
+        c[2] += 1
     plain_rate = plain_keys / plain_sec
-    log(f"[batched] plain path on {len(sample)} sampled buckets: {plain_rate / 1e9:.3f} G keys/s")
+    del pws, pout
+    log(f"[batched] plain path on {len(sample)} sampled buckets (preallocated workspace and outputs): "
+        f"{plain_rate / 1e9:.3f} G keys/s; " +
+        ", ".join(f"{k}..: {v[0] / v[1] / 1e9:.3f} G keys/s over {v[2]}" for k, v in sorted(by_class.items())))
     bb.destroy_graph()
     out = dict(workload=BATCH_WORKLOAD, buckets=len(sizes), keys=total, ms_per_step=round(sec * 1000, 3),
                value=round(ok_keys / sec, 1), unit="edges/s", failed_buckets=int((~ok).sum()),
                retries=extra_tries, block=bb.tuning.block, grid=bb.tuning.grid,
                placement_probe_ms=[round(x, 1) for x in probes], autotune=tune,
-               plain_same_buckets=dict(value=round(plain_rate, 1), unit="edges/s", buckets=len(sample)),
-               speedup_vs_plain=round(ok_keys / sec / plain_rate, 2))
+               plain_same_buckets=dict(value=round(plain_rate, 1), unit="edges/s", buckets=len(sample),
+                                       note="one mphx_mphf_build_u64 per bucket into a preallocated workspace "
+                                            "and outputs (no allocation in the timed calls)",
+                                       by_size=dict((k, dict(buckets=v[2], keys_per_s=round(v[0] / v[1], 1)))
+                                                    for k, v in sorted(by_class.items()))),
+               speedup_vs_plain=round(ok_keys / sec / plain_rate, 2), oracle_all_core=oracle_all_core_c4())
     del bb, keys
     torch.cuda.empty_cache()
     return out
@@ -848,6 +928,151 @@ def hem_leg(args, mx, torch, n: int, kind: int, keys=None, data=None, offs=None)
     return dict(workload="hem_split_same_keys", rows=rows)
 
 
+def stream_leg(args, mx, torch) -> dict:
+    """One MWHC MPHF over a u64 key set held in host memory, too large for the in-HBM build
+    (the paper's 7.6e9 keys, Section 5): the streamed build (vertex records with the XOR of the
+    other two endpoints, no edge ids), once with every layer in device memory and once with the
+    layers spilled to host memory past a layer area of 0.3 n slots.  Whole builds are timed with
+    their transfers; then every key is streamed through the evaluation and the values checked to
+    form a bijection onto [0, n)."""
+    dev = torch.device("cuda:0")
+    n, chunk = args.stream_n, args.stream_chunk
+    gamma = (123, 100)
+    P = mx.part_size(n, gamma)
+    m = 3 * P
+    t0 = time.perf_counter()
+    hk = torch.empty(n, dtype=torch.int64)
+    for c0 in range(0, n, chunk):  # the u64 key generator on the device, copied down
+        c1 = min(n, c0 + chunk)
+        hk[c0:c1].copy_(mx.gen_keys_u64(c1 - c0, gen_seed=0, start=c0, device=dev))
+    torch.cuda.synchronize()
+    log(f"[stream] {n} keys ({8 * n / 1e9:.1f} GB) in pageable host memory, generated in "
+        f"{time.perf_counter() - t0:.1f} s; P = {P}, m = {m} vertices")
+    codes = torch.empty((m + 31) // 32, dtype=torch.int64, device=dev)
+    rank = torch.empty((m + 511) // 512, dtype=torch.int64, device=dev)
+    # the in-HBM build's workspace per key at 2^31 keys (claim lists on), scaled, plus the keys
+    in_hbm = mx.mphf_workspace_bytes(1 << 31, gamma) / (1 << 31) * n + 8 * n
+    rows = {}
+    host_layers = None
+    for name, slots in (("layers_in_hbm", n), ("layers_spilled", (3 * n) // 10)):
+        need = mx.stream_workspace_bytes(n, gamma, chunk, slots)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        if slots < n and host_layers is None:
+            host_layers = torch.empty(12 * n, dtype=torch.uint8)
+            host_layers[::4096] = 0  # touch every page before timing
+        mx.set_option("timing", 1)
+        mx.phase_times(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = mx.mphf_build_stream_u64(hk, seed=0, gamma=gamma, chunk_keys=chunk, layer_slots=slots,
+                                     host_layers=host_layers if slots < n else None, ws=ws, out=(codes, rank),
+                                     device=dev)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        ph = {k: round(v[0], 1) for k, v in mx.phase_times(reset=True).items() if v[1]}
+        t1 = time.perf_counter()
+        bad = mx.check_stream_u64(codes, rank, r["P"], r["seed_used"], hk, chunk_keys=chunk)
+        t_check = time.perf_counter() - t1
+        rows[name] = dict(layer_slots=slots, device_workspace_bytes=need, s_per_build=round(sec, 3),
+                          keys_per_s=round(n / sec, 1), tries=r["tries"], rounds=r["n_rounds"], layer0=r["layer0"],
+                          phases_ms=ph, bijection=bad == 0, bad_values=bad, check_s=round(t_check, 2))
+        log(f"[stream] {name}: {sec:.2f} s/build = {n / sec / 1e9:.3f} G keys/s (device workspace {need / 1e9:.1f} GB, "
+            f"tries {r['tries']}, rounds {r['n_rounds']}); phases {ph}; all {n} keys looked up in {t_check:.1f} s, "
+            f"bijection ok={bad == 0}")
+        del ws, r
+        torch.cuda.empty_cache()
+    bits = 64 * (codes.numel() + rank.numel()) / n
+    del codes, rank, hk, host_layers
+    return dict(workload=f"mwhc_stream_u64_n{n}_gamma1.23", n=n, vertices=m, chunk_keys=chunk,
+                host_key_bytes=8 * n, in_hbm_build_bytes_estimate=int(in_hbm), bits_per_key=round(bits, 4),
+                rows=rows, paper_context="Section 5: 7.6e9 keys built in under 21 h on one CPU with a disk "
+                                         "(Intel i7 E5520, 32 GiB)")
+
+
+def hem_host_str_leg(args, mx, torch, np, workloads) -> dict:
+    """HEM split of a byte-string key set held in host memory: n-gram-like keys (log-normal
+    lengths with mean 23 B, clamped to 8..512 B, distinct by construction), 128-bit signatures
+    (16 bytes per key stay on the device).  Times whole builds with their transfers, then
+    streams every key again, looks it up and checks that the values form a bijection."""
+    dev = torch.device("cuda:0")
+    n, k, chunk, batch = args.hem_host_str_n, args.hem_host_k, args.hem_host_chunk, args.hem_host_batch
+    chunk_bytes = 64 * chunk
+    gamma = (123, 100)
+    qtab = torch.from_numpy(workloads.quantile_table(args.hem_host_str_mean).view(np.int16)).to(dev)
+    t0 = time.perf_counter()
+    # lengths first, to size the host byte array
+    total = 0
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        _, offs = mx.gen_str_keys(c1 - c0, qtab, gen_seed=0, start=c0, device=dev)
+        total += int(offs[-1].item())
+        del offs
+    hd = torch.empty(total + 8, dtype=torch.uint8)
+    ho = torch.empty(n + 1, dtype=torch.int64)
+    hd[::4096] = 0  # touch every page before timing
+    ho[::512] = 0
+    base = 0
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        d, o = mx.gen_str_keys(c1 - c0, qtab, gen_seed=0, start=c0, device=dev)
+        ln = int(o[-1].item())
+        hd[base:base + ln].copy_(d[:ln])
+        ho[c0:c1 + 1].copy_(o + base)
+        base += ln
+        del d, o
+    torch.cuda.synchronize()
+    log(f"[hem_host_str] {n} string keys ({total / 1e9:.1f} GB of bytes, mean {total / n:.1f} B, and "
+        f"{8 * (n + 1) / 1e9:.1f} GB of offsets) in pageable host memory, generated in {time.perf_counter() - t0:.1f} s")
+    need = mx.hem_host_workspace_bytes(n, k, mx.KEYS_STR, chunk, chunk_bytes, batch, gamma)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    mx.set_option("timing", 1)
+
+    def step():
+        return mx.hem_build_host(data=hd, offs=ho, k=k, seed=0, gamma=gamma, chunk_keys=chunk,
+                                 chunk_bytes=chunk_bytes, batch_keys=batch, ws=ws, device=dev)
+
+    h = step()
+    torch.cuda.synchronize()
+    mx.phase_times(reset=True)
+    steps = max(1, min(args.steps, 2))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        del h
+        h = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    phases = {p: round(v[0] / steps, 3) for p, v in mx.phase_times(reset=True).items() if v[1]}
+    B = 1 << k
+    bits = 64 * (h["codes"].numel() + h["rank"].numel()) + 64 * (4 * B + 3)
+    del ws
+    torch.cuda.empty_cache()
+    hit = torch.zeros(n, dtype=torch.uint8, device=dev)
+    ok = True
+    t0 = time.perf_counter()
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        b0, b1 = int(ho[c0]), int(ho[c1])
+        dd = hd[b0:b1].to(dev)
+        do = (ho[c0:c1 + 1] - b0).to(dev)
+        f = mx.hem_lookup(h, data=dd, offs=do)
+        ok = ok and bool(int(f.min().item()) >= 0 and int(f.max().item()) < n)
+        if ok:
+            hit.index_fill_(0, f, 1)
+        del dd, do, f
+    ok = ok and int(hit.sum(dtype=torch.int64).item()) == n
+    torch.cuda.synchronize()
+    t_check = time.perf_counter() - t0
+    del hit, h, hd, ho
+    torch.cuda.empty_cache()
+    log(f"[hem_host_str] k={k}: {sec:.2f} s/build = {n / sec / 1e9:.3f} G keys/s with transfers, phases {phases}, "
+        f"{bits / n:.3f} bits/key; all-key lookups in {t_check:.1f} s, bijection ok={ok}")
+    return dict(workload=f"hem_host_str_n{n}_mean{args.hem_host_str_mean:g}B_k{k}", keys=n, key_bytes=total,
+                offset_bytes=8 * (n + 1), k=k, chunk_keys=chunk, chunk_bytes=chunk_bytes, batch_keys=batch,
+                device_workspace_bytes=need, s_per_build=round(sec, 3), keys_per_s=round(n / sec, 1),
+                phases_ms=phases, bits_per_key=round(bits / n, 4), bijection=ok, check_s=round(t_check, 1),
+                signature_bits=128)
+
+
 def hem_host_leg(args, mx, torch) -> dict:
     """HEM split of a u64 key set held in host memory (pinned when the host allows) and larger than device memory
     would allow in place: the keys stream over PCIe in chunks, only their 8-byte signatures stay
@@ -1019,7 +1244,8 @@ def served_leg(args, mx, torch, np, workloads) -> dict:
                 saturation_builds_per_s=round(sat_rate, 2), saturation_edges_per_s=round(sat_edges, 1),
                 plain_same_requests=dict(value=round(plain_rate, 1), unit="edges/s", requests=nreq,
                                          note="one mphf_build after another on one stream"),
-                speedup_vs_plain=round(sat_edges / plain_rate, 2), rates=rows)
+                speedup_vs_plain=round(sat_edges / plain_rate, 2), rates=rows,
+                oracle_per_request=oracle_per_request_c5(np))
 
 
 def main() -> int:
@@ -1035,8 +1261,8 @@ def main() -> int:
     ap.add_argument("--no-placement-probe", action="store_true",
                     help="time the first allocation's physical layout, without probing the other")
     ap.add_argument("--legs", default="ceilings,plain,lookup,sf,hem,batched,served",
-                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host, peel_r, "
-                         "footprint")
+                    help="comma list of: ceilings, plain, lookup, sf and hem (need plain), batched, served, hem_host, "
+                         "hem_host_str, stream, peel_r, footprint")
     ap.add_argument("--hem-k", type=lambda s: [int(x) for x in s.split(",")], default=[17],
                     help="bucket-count exponents of the hem leg")
     ap.add_argument("--hem-tune", type=lambda s: s.split(","), default=["1024x0"],
@@ -1046,6 +1272,10 @@ def main() -> int:
     ap.add_argument("--hem-host-k", type=int, default=20)
     ap.add_argument("--hem-host-chunk", type=int, default=1 << 27, help="keys per host-to-device chunk")
     ap.add_argument("--hem-host-batch", type=int, default=1 << 28, help="keys per gathered batch of groups")
+    ap.add_argument("--stream-n", type=int, default=7_600_000_000, help="keys of the stream leg (host memory)")
+    ap.add_argument("--hem-host-str-n", type=int, default=1 << 32, help="string keys of the hem_host_str leg")
+    ap.add_argument("--hem-host-str-mean", type=float, default=23.0, help="mean key length of the hem_host_str leg")
+    ap.add_argument("--stream-chunk", type=int, default=1 << 27, help="keys per host-to-device chunk of the stream leg")
     ap.add_argument("--summarize-counters", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write profiles/hbm_counters_<workload> from rocprofv3 --pmc output directories")
     ap.add_argument("--counters-command", default="", help="the command the counter runs used (recorded)")
@@ -1061,13 +1291,14 @@ def main() -> int:
     ap.add_argument("--no-batch-autotune", action="store_true",
                     help="batched leg: skip the autotuner (block/grid from --batch-block/--batch-grid, else 1024 x one per CU)")
     ap.add_argument("--plain-sample", type=int, default=256)
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate of the served leg")
     ap.add_argument("--serve-max", type=int, default=100_000_000)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget", type=int, default=64 << 30)
     ap.add_argument("--serve-lane-max", type=int, default=1 << 17,
                     help="requests of at most this many keys take the server's batching lane")
-    ap.add_argument("--serve-rates", type=lambda s: [float(x) for x in s.split(",")], default=[0.5, 0.9])
+    ap.add_argument("--serve-rates", type=lambda s: [float(x) for x in s.split(",")], default=[0.25, 0.5, 1.0, 2.0, 4.0],
+                    help="offered rates as multiples of the measured saturation rate")
     args = ap.parse_args()
     if args.summarize_kernel_stats:
         return summarize_kernel_stats(*args.summarize_kernel_stats, command=args.counters_command)
@@ -1108,6 +1339,10 @@ def main() -> int:
             side["served"] = served_leg(args, mx, torch, np, workloads)
         if "hem_host" in legs:
             side["hem_host"] = hem_host_leg(args, mx, torch)
+        if "stream" in legs:
+            side["stream"] = stream_leg(args, mx, torch)
+        if "hem_host_str" in legs:
+            side["hem_host_str"] = hem_host_str_leg(args, mx, torch, np, workloads)
         if "peel_r" in legs:
             side["peel_r"] = peel_r_leg(args, mx, torch)
         if "footprint" in legs:
@@ -1278,7 +1513,7 @@ def main() -> int:
         cs = time.perf_counter() - c0
         cpu = dict(value=round(ns / cs, 1), unit="keys/s", cores=1, kind="oracle",
                    sample=f"first {ns} keys of the same generator, single-threaded C oracle, "
-                          f"{cs:.1f} s (status {rc})")
+                          f"{cs:.1f} s (status {rc})", **host_cpu())
         log(f"[bench] oracle: {ns} keys in {cs:.2f} s = {ns / cs / 1e6:.3f} M keys/s")
 
     lookup = None
@@ -1310,6 +1545,7 @@ def main() -> int:
     batched = batched_leg(args, mx, torch, np, workloads) if "batched" in legs else None
     served = served_leg(args, mx, torch, np, workloads) if "served" in legs else None
     hem_host = hem_host_leg(args, mx, torch) if "hem_host" in legs else None
+    stream = stream_leg(args, mx, torch) if "stream" in legs else None
 
     out = {
         "metric": "edges peeled/s (hash+peel+assign+rank), plain single-hypergraph build",
@@ -1340,6 +1576,7 @@ def main() -> int:
         "batched": batched,
         "served": served,
         "hem_host": hem_host,
+        "stream": stream,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -60,15 +60,16 @@ def u64_keys(n: int, gen_seed: int = 0, start: int = 0) -> np.ndarray:
     return stream(np.uint64(gen_seed), idx + np.uint64(1))
 
 
-def quantile_table() -> np.ndarray:
+def quantile_table(mean: float = STR_MEAN) -> np.ndarray:
     """Length table: entry u is the clamped log-normal quantile at (u + 0.5) / 65536.
 
-    mu = ln(60) - sigma^2 / 2 makes the unclamped mean exactly 60 bytes.
+    mu = ln(mean) - sigma^2 / 2 makes the unclamped mean exactly ``mean`` bytes (60 by
+    default; the host-memory string split also uses 23, the n-gram keys' average length).
     """
     from scipy.special import ndtri
 
     size = 1 << QTABLE_BITS
-    mu = math.log(STR_MEAN) - STR_SIGMA * STR_SIGMA / 2.0
+    mu = math.log(mean) - STR_SIGMA * STR_SIGMA / 2.0
     u = (np.arange(size, dtype=np.float64) + 0.5) / size
     q = np.floor(np.exp(mu + STR_SIGMA * ndtri(u)) + 0.5)
     return np.clip(q, STR_MIN_LEN, STR_MAX_LEN).astype(np.uint16)
