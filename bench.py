@@ -501,10 +501,14 @@ def oracle_per_request_c5(np) -> dict:
     if not os.path.exists(path):
         return {}
     secs = [float(ln.split()[-1]) for ln in open(path) if not ln.startswith("#") and ln.strip()]
-    head = [h for h in golden_header(path) if "host CPUs" in h]
+    import re
+
+    # the run's line, e.g. "16 oracle processes on 16 host CPUs, 62 s wall"
+    runs = [m.group(0) for m in map(re.compile(r"\d+ oracle processes on \d+ host CPUs, \d+ s wall").search,
+                                    golden_header(path)) if m]
     return dict(requests=len(secs), p50_ms=round(float(np.percentile(secs, 50)) * 1e3, 1),
                 p99_ms=round(float(np.percentile(secs, 99)) * 1e3, 1), kind="oracle", cores=1,
-                source="tests/golden/c5_served_60.txt (make_fullsize.py c5)" + (f": {head[0]}" if head else ""))
+                source="tests/golden/c5_served_60.txt (make_fullsize.py c5)" + (f": {runs[0]}" if runs else ""))
 
 
 def batched_leg(args, mx, torch, np, workloads) -> dict:
