@@ -68,6 +68,12 @@ def _bind(lib):
                                        C.c_uint32, C.c_uint32, _u64p, _u64p]),
         "orc_sf_lookup_u64": (None, [_u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u64p, C.c_uint64, _u64p]),
         "orc_sf_lookup_str": (None, [_u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u8p, _u64p, C.c_uint64, _u64p]),
+        "orc_sfr_rank_words": (C.c_uint64, [C.c_uint64]),
+        "orc_sf_rank_layout": (C.c_uint64, [_u64p, C.c_uint64, C.c_uint32, _u64p, _u64p, _u64p]),
+        "orc_sfr_lookup_u64": (None, [_u64p, _u64p, _u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u64p, C.c_uint64,
+                                      _u64p]),
+        "orc_sfr_lookup_str": (None, [_u64p, _u64p, _u64p, C.c_uint64, C.c_uint64, C.c_uint64, _u8p, _u64p,
+                                      C.c_uint64, _u64p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -318,6 +324,41 @@ class Oracle:
                                    _p(out, _u64p))
         return out
 
+    # --- ranked static-function layout (Section 3: ceil(log sigma) n + gamma n + o(n) bits) -----
+    def sf_rank_layout(self, words, m, sigma):
+        """The ranked layout of a static function given in the plain packed layout (m fields):
+        marks (m bits), rank samples (one per 1024 vertices plus the total), the non-zero fields
+        in vertex order, and their number."""
+        b = self.sf_bits(sigma)
+        marks = np.zeros(max((m + 63) // 64, 1), np.uint64)
+        rank = np.zeros(int(self.lib.orc_sfr_rank_words(m)), np.uint64)
+        vals = np.zeros(max((m * b + 63) // 64, 1), np.uint64)
+        w = np.ascontiguousarray(words, dtype=np.uint64) if len(words) else np.zeros(1, np.uint64)
+        count = int(self.lib.orc_sf_rank_layout(_p(w, _u64p), m, b, _p(marks, _u64p), _p(rank, _u64p),
+                                                _p(vals, _u64p)))
+        return dict(marks=marks[: (m + 63) // 64], rank=rank, vals=vals[: (count * b + 63) // 64], count=count)
+
+    def sfr_lookup_u64(self, marks, rank, vals, sigma, P, seed, keys):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.empty(len(keys), np.uint64)
+        mk, rk, vl = (np.ascontiguousarray(x, dtype=np.uint64) if len(x) else np.zeros(1, np.uint64)
+                      for x in (marks, rank, vals))
+        self.lib.orc_sfr_lookup_u64(_p(mk, _u64p), _p(rk, _u64p), _p(vl, _u64p), sigma, P, seed, _p(keys, _u64p),
+                                    len(keys), _p(out, _u64p))
+        return out
+
+    def sfr_lookup_str(self, marks, rank, vals, sigma, P, seed, data, offs):
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        if data.size == 0:
+            data = np.zeros(1, np.uint8)
+        offs = np.ascontiguousarray(offs, dtype=np.uint64)
+        n = len(offs) - 1
+        out = np.empty(n, np.uint64)
+        mk, rk, vl = (np.ascontiguousarray(x, dtype=np.uint64) if len(x) else np.zeros(1, np.uint64)
+                      for x in (marks, rank, vals))
+        self.lib.orc_sfr_lookup_str(_p(mk, _u64p), _p(rk, _u64p), _p(vl, _u64p), sigma, P, seed, _p(data, _u8p),
+                                    _p(offs, _u64p), n, _p(out, _u64p))
+        return out
 
     # --- HEM split (Section 3: signatures, 2^k buckets, one MPHF per bucket) ---------------------
     def hem_signatures_u64(self, keys, seed):

@@ -545,6 +545,102 @@ void orc_sf_lookup_str(const uint64_t* words, uint64_t sigma, uint64_t P, uint64
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Ranked static-function layout (Section 3: ceil(log sigma) n + gamma n + o(n) bits with a
+ * ranking structure).  Only the vertices whose value u[v] is not zero keep a field; u is zero
+ * off the hinges, so there are at most n of them.
+ *   marks: m bits, bit v % 64 of word v / 64 set iff u[v] != 0;
+ *   rank:  rank[j] = the number of marked vertices below vertex ORC_SFR_BLOCK * j, for
+ *          j = 0 .. ceil(m / ORC_SFR_BLOCK); the last entry is the number of fields;
+ *   vals:  the fields of the marked vertices in vertex order, field i at bits [i b, i b + b)
+ *          of the little-endian bit string of the words.
+ * A vertex without a mark has u = 0.  Built here from the packed plain layout (one field per
+ * vertex, as orc_sf_pack writes it).
+ * ------------------------------------------------------------------------------------------ */
+#define ORC_SFR_BLOCK 1024
+
+uint64_t orc_sfr_rank_words(uint64_t m)
+{
+    return (m + ORC_SFR_BLOCK - 1) / ORC_SFR_BLOCK + 1;
+}
+
+static void orc_put_field(uint64_t* words, uint32_t b, uint64_t i, uint64_t x)
+{
+    for (uint32_t t = 0; t < b; t++) {
+        uint64_t bit = i * b + t;
+        words[bit / 64] |= ((x >> t) & 1u) << (bit % 64);
+    }
+}
+
+/* Returns the number of fields; vals must hold ceil(fields * b / 64) words. */
+uint64_t orc_sf_rank_layout(const uint64_t* words, uint64_t m, uint32_t b, uint64_t* marks, uint64_t* rank,
+                            uint64_t* vals)
+{
+    for (uint64_t w = 0; w < (m + 63) / 64; w++)
+        marks[w] = 0;
+    uint64_t count = 0;
+    for (uint64_t v = 0; v < m; v++) {
+        if (v % ORC_SFR_BLOCK == 0)
+            rank[v / ORC_SFR_BLOCK] = count;
+        if (orc_sf_field(words, b, v) != 0) {
+            marks[v / 64] |= 1ull << (v % 64);
+            count++;
+        }
+    }
+    rank[(m + ORC_SFR_BLOCK - 1) / ORC_SFR_BLOCK] = count;
+    for (uint64_t w = 0; w < (count * b + 63) / 64; w++)
+        vals[w] = 0;
+    uint64_t i = 0;
+    for (uint64_t v = 0; v < m; v++)
+        if ((marks[v / 64] >> (v % 64)) & 1u)
+            orc_put_field(vals, b, i++, orc_sf_field(words, b, v));
+    return count;
+}
+
+/* u[v] through the ranking structure: zero without a mark, else the field whose index is the
+ * number of marked vertices below v (the block's sample plus the marks in the block before v,
+ * counted one by one). */
+static uint64_t orc_sfr_value(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint32_t b,
+                              uint64_t v)
+{
+    if (!((marks[v / 64] >> (v % 64)) & 1u))
+        return 0;
+    uint64_t r = rank[v / ORC_SFR_BLOCK];
+    for (uint64_t x = v - v % ORC_SFR_BLOCK; x < v; x++)
+        r += (marks[x / 64] >> (x % 64)) & 1u;
+    return orc_sf_field(vals, b, r);
+}
+
+static uint64_t orc_sfr_eval_edge(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma,
+                                  const uint32_t t[3])
+{
+    uint32_t b = orc_sf_bits(sigma);
+    return (orc_sfr_value(marks, rank, vals, b, t[0]) + orc_sfr_value(marks, rank, vals, b, t[1]) +
+            orc_sfr_value(marks, rank, vals, b, t[2])) % sigma;
+}
+
+void orc_sfr_lookup_u64(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma, uint64_t P,
+                        uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t t[3];
+        orc_hash_u64(keys + i, 1, seed, P, t);
+        out[i] = orc_sfr_eval_edge(marks, rank, vals, sigma, t);
+    }
+}
+
+void orc_sfr_lookup_str(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma, uint64_t P,
+                        uint64_t seed, const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t a, b;
+        uint32_t t[3];
+        orc_digest_str(bytes + offs[i], offs[i + 1] - offs[i], seed, &a, &b);
+        orc_edge_of_digest(a, b, P, t);
+        out[i] = orc_sfr_eval_edge(marks, rank, vals, sigma, t);
+    }
+}
+
+/* ------------------------------------------------------------------------------------------
  * Whole MPHF build: hash (Section 3 / 4.3), peel (Section 4.2), retry with the next seed
  * while a 2-core remains, assign (Section 3 / 4.3), pack and rank (Section 5).
  * info[0] = P, info[1] = m, info[2] = seed used, info[3] = tries, info[4] = rounds,

@@ -629,9 +629,67 @@ def pin_hem(o) -> list:
     return bad
 
 
+def pin_sf_ranked(o, seed=11) -> list:
+    """Ranked static-function layout (Section 3: ceil(log sigma) n + gamma n + o(n) bits with
+    a ranking structure). A hand-worked layout; on built functions every key's lookup through
+    the ranking structure returns its value, at most n fields are kept (u is zero off the
+    hinges) and the space stays within b n + m + the rank samples."""
+    bad = []
+    # Worked example: m = 2100 vertices (blocks of 1024: two whole, one of 52), sigma = 8 (3
+    # bits), non-zero values u[0] = 5, u[63] = 1, u[64] = 7, u[1023] = 2, u[1024] = 3,
+    # u[2099] = 4.  Marks: word 0 bits 0 and 63, word 1 bit 0, word 15 bit 63, word 16 bit 0,
+    # word 32 bit 51 (2099 = 32 * 64 + 51).  Rank samples: 0 below vertex 0, 4 below 1024,
+    # 5 below 2048, 6 in all.  Fields 5, 1, 7, 2, 3, 4 at bits 0, 3, 6, 9, 12, 15 form the
+    # word 5 + 8 + 448 + 1024 + 12288 + 131072 = 144845.
+    u = np.zeros(2100, np.uint32)
+    for v, x in ((0, 5), (63, 1), (64, 7), (1023, 2), (1024, 3), (2099, 4)):
+        u[v] = x
+    lay = o.sf_rank_layout(o.sf_pack(u, 8), 2100, 8)
+    want_marks = np.zeros(33, np.uint64)
+    want_marks[0] = 0x8000000000000001
+    want_marks[1] = 1
+    want_marks[15] = 0x8000000000000000
+    want_marks[16] = 1
+    want_marks[32] = 0x0008000000000000
+    if (lay["count"] != 6 or not np.array_equal(lay["marks"], want_marks)
+            or lay["rank"].tolist() != [0, 4, 5, 6] or lay["vals"].tolist() != [144845]):
+        bad.append(f"sf ranked: worked example gave count {lay['count']}, rank {lay['rank'].tolist()}, "
+                   f"vals {lay['vals'].tolist()}")
+    # built functions: lookups through the ranking structure, the field count, the space
+    rng = np.random.default_rng(seed)
+    n = 20000
+    keys = workloads.u64_keys(n, gen_seed=seed)
+    for sigma in (1, 2, 256, 1_000_003, 1 << 32):
+        values = rng.integers(0, sigma, n, dtype=np.uint64).astype(np.uint32)
+        rc, r = o.sf_build_u64(keys, values, sigma, seed=3)
+        if rc != 0:
+            bad.append(f"sf ranked sigma={sigma}: status {rc}")
+            continue
+        b, m = o.sf_bits(sigma), r["m"]
+        lay = o.sf_rank_layout(r["words"], m, sigma)
+        f = o.sfr_lookup_u64(lay["marks"], lay["rank"], lay["vals"], sigma, r["P"], r["seed_used"], keys)
+        if not np.array_equal(f, values.astype(np.uint64)):
+            bad.append(f"sf ranked sigma={sigma}: lookup differs from the values at {int((f != values).sum())} keys")
+        nonzero = int((values != 0).sum())
+        bits = m + 64 * len(lay["rank"]) + lay["count"] * b
+        # every key with a non-zero value needs a non-zero field on its edge, and no two keys
+        # share a hinge: between that many and n fields
+        if not (min(nonzero, 1) <= lay["count"] <= n) or bits > b * n + m + 64 * (m // 1024 + 2):
+            bad.append(f"sf ranked sigma={sigma}: {lay['count']} fields, {bits} bits")
+    data, offs = workloads.str_keys(5000, gen_seed=seed)
+    values = rng.integers(0, 1000, 5000).astype(np.uint32)
+    rc, r = o.sf_build_str(data, offs, values, 1000, seed=4)
+    if rc == 0:
+        lay = o.sf_rank_layout(r["words"], r["m"], 1000)
+        f = o.sfr_lookup_str(lay["marks"], lay["rank"], lay["vals"], 1000, r["P"], r["seed_used"], data, offs)
+    if rc != 0 or not np.array_equal(f, values.astype(np.uint64)):
+        bad.append(f"sf ranked str: status {rc} or lookup differs from the values")
+    return bad
+
+
 ALL_PINS = [pin_splitmix, pin_hash_closed_form, pin_part_size, pin_worked_examples,
             pin_bruteforce_tripartite, pin_bruteforce_generic, pin_invariants, pin_mphf, pin_errors,
-            pin_string_digest, pin_static_function, pin_hem, pin_general_r]
+            pin_string_digest, pin_static_function, pin_sf_ranked, pin_hem, pin_general_r]
 
 
 def run_all(o, pins=None) -> list:

@@ -39,6 +39,12 @@ MUTANTS = {
     "static function field one bit short": ("while (b < 64 && ((sigma - 1) >> b) != 0)", "while (b < 64 && ((sigma - 1) >> (b + 1)) != 0)"),
     "static function packing shifted": ("|= (uint64_t)((u[v] >> t) & 1u) << (bit % 64);", "|= (uint64_t)((u[v] >> t) & 1u) << ((bit + 1) % 64);"),
     "static function lookup drops a vertex": ("+ orc_sf_field(words, b, t[2])) % sigma", ") % sigma"),
+    "ranked lookup counts the vertex itself": ("for (uint64_t x = v - v % ORC_SFR_BLOCK; x < v; x++)",
+                                               "for (uint64_t x = v - v % ORC_SFR_BLOCK; x <= v; x++)"),
+    "ranked layout keeps zero fields": ("if (orc_sf_field(words, b, v) != 0) {", "if (1) {"),
+    "ranked field index skips one": ("orc_put_field(vals, b, i++, ", "orc_put_field(vals, b, ++i, "),
+    "ranked lookup reads the next block's sample": ("uint64_t r = rank[v / ORC_SFR_BLOCK];",
+                                                    "uint64_t r = rank[v / ORC_SFR_BLOCK + 1];"),
     "hem signature adds the seed": ("return orc_fin((key ^ seed) + 4 * ORC_GAMMA);", "return orc_fin((key + seed) + 4 * ORC_GAMMA);"),
     "hem bucket key not swapped": ("return (sig << 32) | (sig >> 32);", "return sig;"),
     "hem bucket offset dropped": ("return bucket_off[b] + orc_eval_edge(", "return 0 * bucket_off[b] + orc_eval_edge("),
