@@ -212,6 +212,44 @@ MPHX_API int mphx_sf_lookup_str(const uint64_t* words, uint64_t sigma, uint64_t 
                                 const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
                                 void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Static functions in the ranked layout (Section 3: ceil(log sigma) n + gamma n + o(n) bits
+ * through a ranking structure).  The keys, values, hash, peel and u are exactly those of
+ * mphx_sf_build_*; u is zero off the hinges, and only the vertices whose u is not zero keep a
+ * field (at most n):
+ *   marks (dev, caller-allocated) mphx_sfr_mark_words(n, gamma_num, gamma_den) uint64: bit
+ *          v % 64 of word v / 64 is set iff u[v] != 0 (m = 3P bits).
+ *   rank  (dev) mphx_sfr_rank_words(n, gamma_num, gamma_den) uint64: rank[j] = the number of
+ *          marked vertices below vertex 1024 j, j = 0 .. ceil(m / 1024); the last entry is the
+ *          number of fields.
+ *   vals  (dev) mphx_sfr_val_words(n, sigma) uint64 (may be null when that is 0): the fields of
+ *          the marked vertices in vertex order, field i at bits [i b, i b + b) of the
+ *          little-endian bit string, b = mphx_sf_bits(sigma); the words after the last field,
+ *          up to mphx_sfr_val_words(n, sigma), are 0.
+ *   ws    (dev) at least mphx_sf_workspace_bytes(n, ...) bytes, 256-byte aligned.
+ * Space: m + 64 (m / 1024 + 2) + fields * b bits, against b m for mphx_sf_build_*.  A lookup
+ * reads the mark word, one rank sample, up to 15 more mark words of the same block (two 64-byte
+ * lines) and the field.  Errors, info and synchronisation as mphx_sf_build_*; n = 0 writes
+ * nothing.  mphx_sfr_lookup_*: out[i] = f(key i) (dev, n uint64).  Enqueue only.
+ * --------------------------------------------------------------------------------------- */
+MPHX_API uint64_t mphx_sfr_mark_words(uint64_t n, uint32_t gamma_num, uint32_t gamma_den);
+MPHX_API uint64_t mphx_sfr_rank_words(uint64_t n, uint32_t gamma_num, uint32_t gamma_den);
+MPHX_API uint64_t mphx_sfr_val_words(uint64_t n, uint64_t sigma);
+MPHX_API int mphx_sfr_build_u64(const uint64_t* keys, const uint32_t* values, uint64_t n, uint64_t sigma,
+                                uint64_t seed, uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries,
+                                uint64_t* marks, uint64_t* rank, uint64_t* vals, void* ws, size_t ws_bytes,
+                                void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_sfr_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t* values, uint64_t n,
+                                uint64_t sigma, uint64_t seed, uint32_t gamma_num, uint32_t gamma_den,
+                                uint32_t max_tries, uint64_t* marks, uint64_t* rank, uint64_t* vals, void* ws,
+                                size_t ws_bytes, void* stream, mphx_mphf_info* info);
+MPHX_API int mphx_sfr_lookup_u64(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma,
+                                 uint64_t P, uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out,
+                                 void* stream);
+MPHX_API int mphx_sfr_lookup_str(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma,
+                                 uint64_t P, uint64_t seed, const uint8_t* bytes, const uint64_t* offs, uint64_t n,
+                                 uint64_t* out, void* stream);
+
 /* Hash keys to edges (Section 3 / Section 4.3), edges (dev) n x 3 uint32.  Enqueue only. */
 MPHX_API int mphx_hash_u64(const uint64_t* keys, uint64_t n, uint64_t seed, uint64_t P, uint32_t* edges,
                   void* stream);

@@ -12,5 +12,6 @@ from ._lib import (  # noqa: F401
     PROBE_ATOMIC_ADD, PROBE_ATOMIC_ADD32, PROBE_ATOMIC_ADD_RET, PROBE_ATOMIC_ADD_WG, PROBE_LDS_ATOMIC_ADD, PROBE_LOAD8,
     PROBE_STORE1, probe_copy, probe_random,
     sf_bits, sf_build_str, sf_build_u64, sf_lookup_str, sf_lookup_u64, sf_words, sf_workspace_bytes,
+    sfr_build_str, sfr_build_u64, sfr_lookup_str, sfr_lookup_u64, sfr_sizes,
     hem_build, hem_build_host, hem_capacity, hem_host_workspace_bytes, hem_lookup, hem_workspace_bytes,
 )

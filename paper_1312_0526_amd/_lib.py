@@ -69,6 +69,15 @@ _SIGS = {
                                  C.POINTER(MphfInfo)]),
     "mphx_sf_lookup_u64": (_i32, [_vp, _u64, _u64, _u64, _vp, _u64, _vp, _vp]),
     "mphx_sf_lookup_str": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
+    "mphx_sfr_mark_words": (_u64, [_u64, _u32, _u32]),
+    "mphx_sfr_rank_words": (_u64, [_u64, _u32, _u32]),
+    "mphx_sfr_val_words": (_u64, [_u64, _u64]),
+    "mphx_sfr_build_u64": (_i32, [_vp, _vp, _u64, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _vp,
+                                  C.POINTER(MphfInfo)]),
+    "mphx_sfr_build_str": (_i32, [_vp, _vp, _vp, _u64, _u64, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _sz, _vp,
+                                  C.POINTER(MphfInfo)]),
+    "mphx_sfr_lookup_u64": (_i32, [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _u64, _vp, _vp]),
+    "mphx_sfr_lookup_str": (_i32, [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _vp, _u64, _vp, _vp]),
     "mphx_hem_workspace_bytes": (_sz, [_u64, _u32, _u32, _u32, _i32]),
     "mphx_hem_capacity": (_i32, [_u64, _u32, _u32, _u32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "mphx_hem_build_u64": (_i32, [_vp, _u64, _u32, _u64, _u32, _u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp,
@@ -611,6 +620,89 @@ def sf_lookup_str(words, sigma: int, P: int, seed: int, data: torch.Tensor, offs
     _check(out, torch.int64, "out", n)
     rc = lib().mphx_sf_lookup_str(_ptr(words) if words.numel() else None, sigma, P, seed, _ptr(data), _ptr(offs), n,
                                   _ptr(out), _stream(data.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+# ---- static functions in the ranked layout (Section 3: a ranking structure over the values) -----
+def sfr_sizes(n: int, sigma: int, gamma=(123, 100)) -> tuple:
+    """Words of the marks, the rank samples and the fields (capacity for n fields)."""
+    L = lib()
+    return (int(L.mphx_sfr_mark_words(n, gamma[0], gamma[1])), int(L.mphx_sfr_rank_words(n, gamma[0], gamma[1])),
+            int(L.mphx_sfr_val_words(n, sigma)))
+
+
+def _sfr_outputs(n, sigma, gamma, device, out):
+    if out is not None:
+        return out
+    return tuple(torch.empty(max(w, 1), dtype=torch.int64, device=device) for w in sfr_sizes(n, sigma, gamma))
+
+
+def _sfr_finish(rc, info, n, sigma, gamma, outs):
+    if rc:
+        _err(rc, info.as_dict())
+    d = info.as_dict()
+    nm, nr, nv = sfr_sizes(n, sigma, gamma)
+    d["marks"], d["rank"], d["vals"] = outs[0][:nm], outs[1][:nr], outs[2][:nv]
+    return d
+
+
+def sfr_build_u64(keys: torch.Tensor, values: torch.Tensor, sigma: int, seed: int = 0, gamma=(123, 100),
+                  max_tries: int = 64, ws=None, out=None) -> dict:
+    """Static function of u64 keys in the ranked layout.  Returns info and the marks, the rank
+    samples (the last one is the number of fields) and the fields (int64 tensors of uint64
+    words); out = (marks, rank, vals) to reuse buffers."""
+    _check(keys, torch.int64, "keys")
+    n = keys.numel()
+    _check(values, torch.int32, "values", n)
+    outs = _sfr_outputs(n, sigma, gamma, keys.device, out)
+    ws = ws if ws is not None else _workspace(sf_workspace_bytes(n, gamma, KEYS_U64), keys.device)
+    info = MphfInfo()
+    rc = lib().mphx_sfr_build_u64(_ptr(keys), _ptr(values), n, sigma, seed, gamma[0], gamma[1], max_tries,
+                                  *(_ptr(t) for t in outs), _ptr(ws), ws.numel(), _stream(keys.device), C.byref(info))
+    return _sfr_finish(rc, info, n, sigma, gamma, outs)
+
+
+def sfr_build_str(data: torch.Tensor, offs: torch.Tensor, values: torch.Tensor, sigma: int, seed: int = 0,
+                  gamma=(123, 100), max_tries: int = 64, ws=None, out=None) -> dict:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    _check(values, torch.int32, "values", n)
+    outs = _sfr_outputs(n, sigma, gamma, data.device, out)
+    ws = ws if ws is not None else _workspace(sf_workspace_bytes(n, gamma, KEYS_STR), data.device)
+    info = MphfInfo()
+    rc = lib().mphx_sfr_build_str(_ptr(data), _ptr(offs), _ptr(values), n, sigma, seed, gamma[0], gamma[1],
+                                  max_tries, *(_ptr(t) for t in outs), _ptr(ws), ws.numel(), _stream(data.device),
+                                  C.byref(info))
+    return _sfr_finish(rc, info, n, sigma, gamma, outs)
+
+
+def sfr_lookup_u64(r: dict, sigma: int, keys: torch.Tensor, out=None) -> torch.Tensor:
+    """f(key) for every key through the ranked layout r (a dict from sfr_build_*)."""
+    _check(keys, torch.int64, "keys")
+    if out is None:
+        out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+    _check(out, torch.int64, "out", keys.numel())
+    vals = r["vals"]
+    rc = lib().mphx_sfr_lookup_u64(_ptr(r["marks"]), _ptr(r["rank"]), _ptr(vals) if vals.numel() else None, sigma,
+                                   r["P"], r["seed_used"], _ptr(keys), keys.numel(), _ptr(out), _stream(keys.device))
+    if rc:
+        _err(rc)
+    return out
+
+
+def sfr_lookup_str(r: dict, sigma: int, data: torch.Tensor, offs: torch.Tensor, out=None) -> torch.Tensor:
+    _check(data, torch.uint8, "data")
+    _check(offs, torch.int64, "offs")
+    n = offs.numel() - 1
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=data.device)
+    _check(out, torch.int64, "out", n)
+    vals = r["vals"]
+    rc = lib().mphx_sfr_lookup_str(_ptr(r["marks"]), _ptr(r["rank"]), _ptr(vals) if vals.numel() else None, sigma,
+                                   r["P"], r["seed_used"], _ptr(data), _ptr(offs), n, _ptr(out), _stream(data.device))
     if rc:
         _err(rc)
     return out

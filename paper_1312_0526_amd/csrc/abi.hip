@@ -756,6 +756,10 @@ int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, uint64_t
 struct SfArgs {
     const uint32_t* values;
     uint64_t sigma;
+    // the ranked layout's outputs (Section 3, ranking structure); null for the plain layout
+    uint64_t* marks = nullptr;
+    uint64_t* rank = nullptr;
+    uint64_t* vals = nullptr;
 };
 
 // The MPHF (codes + rank) or, with sf, the static function (codes = its packed fields).
@@ -774,7 +778,9 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
         if (k.kind == MPHX_KEYS_U64 && !k.keys) return fail(MPHX_EINVAL, "null keys");
         if (k.kind == MPHX_KEYS_STR && (!k.bytes || !k.offs)) return fail(MPHX_EINVAL, "null bytes/offs");
         if (k.kind == MPHX_KEYS_STR && ((uintptr_t)k.bytes & 3)) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
-        if (sf ? (!sf->values || (!codes && mphx_sf_bits(sf->sigma) > 0)) : (!codes || !rank))
+        const bool no_fields = sf && mphx_sf_bits(sf->sigma) == 0;
+        if (sf && sf->marks ? (!sf->values || !sf->rank || (!sf->vals && !no_fields))
+                            : sf ? (!sf->values || (!codes && !no_fields)) : (!codes || !rank))
             return fail(MPHX_EINVAL, "null values or output");
     }
     if (sf && (sf->sigma == 0 || sf->sigma > 0x100000000ull)) return fail(MPHX_EINVAL, "sigma must be in [1, 2^32]");
@@ -923,7 +929,18 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
             Timed tm(PH_ASSIGN, s);
             HIP_TRY(launch_sf_assign_round(L.slots + lb[r], st.vout + lb[r], lb[r + 1] - lb[r], sf->sigma, b, u, s));
         }
-        {
+        if (sf->marks) {
+            // ranked layout: marks and per-block counts, their prefix, then the fields compacted
+            Timed tm(PH_RANK, s);
+            const uint64_t nb = (m + kSfrBlock - 1) / kSfrBlock;
+            HIP_TRY(launch_sfr_marks(u, m, b, sf->marks, L.bcount, s));
+            HIP_TRY(launch_scan_u32_to_u64(L.bcount, nb, sf->rank, nb + 1, L.scan, L.scan_bytes, s));
+            if (b) {
+                const uint64_t cap = mphx_sfr_val_words(n, sf->sigma);
+                HIP_TRY(launch_zero(sf->vals, cap * sizeof(uint64_t), s));
+                HIP_TRY(launch_sfr_compact(u, m, b, sf->rank, sf->vals, cap, s));
+            }
+        } else {
             Timed tm(PH_RANK, s);
             HIP_TRY(launch_sf_pack(u, m, b, codes, s));
         }
@@ -1044,6 +1061,71 @@ int mphx_sf_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t
     SfArgs sf{values, sigma};
     return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, words, nullptr, ws, ws_bytes, (hipStream_t)stream,
                       info, &sf);
+}
+
+uint64_t mphx_sfr_mark_words(uint64_t n, uint32_t gamma_num, uint32_t gamma_den)
+{
+    return (3 * mphx_part_size(n, gamma_num, gamma_den) + 63) / 64;
+}
+
+uint64_t mphx_sfr_rank_words(uint64_t n, uint32_t gamma_num, uint32_t gamma_den)
+{
+    return (3 * mphx_part_size(n, gamma_num, gamma_den) + kSfrBlock - 1) / kSfrBlock + 1;
+}
+
+uint64_t mphx_sfr_val_words(uint64_t n, uint64_t sigma)
+{
+    return (n * mphx_sf_bits(sigma) + 63) / 64;
+}
+
+int mphx_sfr_build_u64(const uint64_t* keys, const uint32_t* values, uint64_t n, uint64_t sigma, uint64_t seed,
+                       uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* marks, uint64_t* rank,
+                       uint64_t* vals, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    KeySrc k{MPHX_KEYS_U64, keys, nullptr, nullptr};
+    SfArgs sf{values, sigma, marks, rank, vals};
+    if (n > 0 && !marks) return fail(MPHX_EINVAL, "null marks");
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, nullptr, nullptr, ws, ws_bytes,
+                      (hipStream_t)stream, info, &sf);
+}
+
+int mphx_sfr_build_str(const uint8_t* bytes, const uint64_t* offs, const uint32_t* values, uint64_t n, uint64_t sigma,
+                       uint64_t seed, uint32_t gamma_num, uint32_t gamma_den, uint32_t max_tries, uint64_t* marks,
+                       uint64_t* rank, uint64_t* vals, void* ws, size_t ws_bytes, void* stream, mphx_mphf_info* info)
+{
+    KeySrc k{MPHX_KEYS_STR, nullptr, bytes, offs};
+    SfArgs sf{values, sigma, marks, rank, vals};
+    if (n > 0 && !marks) return fail(MPHX_EINVAL, "null marks");
+    return mphf_build(k, n, seed, gamma_num, gamma_den, max_tries, nullptr, nullptr, ws, ws_bytes,
+                      (hipStream_t)stream, info, &sf);
+}
+
+int mphx_sfr_lookup_u64(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma, uint64_t P,
+                        uint64_t seed, const uint64_t* keys, uint64_t n, uint64_t* out, void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    const uint32_t b = mphx_sf_bits(sigma);
+    if (!marks || !rank || (!vals && b > 0) || !keys || !out || P == 0 || sigma == 0 || sigma > 0x100000000ull)
+        return fail(MPHX_EINVAL, "null pointer, P = 0 or sigma out of [1, 2^32]");
+    HIP_TRY(launch_sfr_lookup_u64(marks, rank, vals, sigma, b, P, seed, keys, n, out, (hipStream_t)stream));
+    return MPHX_OK;
+}
+
+int mphx_sfr_lookup_str(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma, uint64_t P,
+                        uint64_t seed, const uint8_t* bytes, const uint64_t* offs, uint64_t n, uint64_t* out,
+                        void* stream)
+{
+    g_err.clear();
+    if (n == 0) return MPHX_OK;
+    const uint32_t b = mphx_sf_bits(sigma);
+    if (!marks || !rank || (!vals && b > 0) || !bytes || !offs || !out || P == 0 || sigma == 0 ||
+        sigma > 0x100000000ull)
+        return fail(MPHX_EINVAL, "null pointer, P = 0 or sigma out of [1, 2^32]");
+    if ((uintptr_t)bytes & 3) return fail(MPHX_EINVAL, "bytes must be 4-byte aligned");
+    HIP_TRY(launch_sfr_lookup_str_words(marks, rank, vals, sigma, b, P, seed, bytes, offs, n, out,
+                                        (hipStream_t)stream));
+    return MPHX_OK;
 }
 
 int mphx_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint64_t P, uint64_t seed, const uint64_t* keys,

@@ -305,6 +305,35 @@ __device__ __forceinline__ uint64_t sf_eval_edge(const uint64_t* words, uint64_t
     return s % sigma;
 }
 
+// ----- ranked static-function layout (Section 3: ceil(log sigma) n + gamma n + o(n) bits) ----
+// Only vertices with u != 0 keep a field: bit v % 64 of marks[v / 64] says whether v has one;
+// rank[j] counts the marked vertices below vertex kSfrBlock * j; the fields of the marked
+// vertices follow in vertex order, b bits each, in vals.
+constexpr uint32_t kSfrBlock = 1024;  // vertices per rank sample: 16 mark words, two 64-byte lines
+
+__device__ __forceinline__ uint64_t sfr_value(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals,
+                                              uint32_t b, uint32_t v)
+{
+    const uint32_t w = v >> 6, below = v & 63;
+    const uint64_t mw = marks[w];
+    if (!((mw >> below) & 1))
+        return 0;
+    uint64_t r = rank[v / kSfrBlock] + __popcll(mw & ((1ull << below) - 1));
+    const uint32_t w0 = (v / kSfrBlock) * (kSfrBlock / 64);
+#pragma unroll
+    for (uint32_t k = 0; k < kSfrBlock / 64 - 1; k++)
+        r += w0 + k < w ? __popcll(marks[w0 + k]) : 0;
+    return sf_field(vals, b, (uint32_t)r);
+}
+
+__device__ __forceinline__ uint64_t sfr_eval_edge(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals,
+                                                  uint64_t sigma, uint32_t b, uint32_t v0, uint32_t v1, uint32_t v2)
+{
+    const uint64_t s = sfr_value(marks, rank, vals, b, v0) + sfr_value(marks, rank, vals, b, v1) +
+                       sfr_value(marks, rank, vals, b, v2);
+    return s % sigma;
+}
+
 // ----- HEM split (Section 3): signatures, buckets by their top bits, an MPHF per bucket ------
 // A u64 key's signature is 64 bits (a bijection of the key); a string key's is its whole 128-bit
 // digest (a, b).  The top k bits of the first word pick the bucket; inside it the key is the

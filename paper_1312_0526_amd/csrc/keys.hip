@@ -143,10 +143,12 @@ struct EvalTables {
     uint64_t sigma;
     uint32_t bits;
     HemTables hem;
+    const uint64_t* marks;  // ranked static function: marks (codes then holds its fields)
 };
 // kHsHemSig writes each key's HEM signature record, its whole digest (out as uint4: high and
 // low half of a, then low and high half of b); kHsEvalHem evaluates a HEM split
-constexpr int kHsEdges = 0, kHsEvalMphf = 1, kHsEvalSf = 2, kHsHemSig = 3, kHsEvalHem = 4;
+// (kHsEvalSfr: a static function in the ranked layout)
+constexpr int kHsEdges = 0, kHsEvalMphf = 1, kHsEvalSf = 2, kHsHemSig = 3, kHsEvalHem = 4, kHsEvalSfr = 5;
 
 template <int kMode>
 __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __restrict__ bytes,
@@ -324,6 +326,8 @@ __global__ __launch_bounds__(kHsBlock) void k_hash_str_words(const uint8_t* __re
                 mt.out[i] = eval_edge(mt.codes, mt.rank, v0, v1, v2);
             } else if constexpr (kMode == kHsEvalSf) {
                 mt.out[i] = sf_eval_edge(mt.codes, mt.sigma, mt.bits, v0, v1, v2);
+            } else if constexpr (kMode == kHsEvalSfr) {
+                mt.out[i] = sfr_eval_edge(mt.marks, mt.rank, mt.codes, mt.sigma, mt.bits, v0, v1, v2);
             } else {
                 edges[3 * i] = v0;
                 edges[3 * i + 1] = v1;
@@ -479,6 +483,18 @@ hipError_t launch_sf_lookup_str_words(const uint64_t* words, uint64_t sigma, uin
     const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
     k_hash_str_words<kHsEvalSf><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
                                                        EvalTables{words, nullptr, out, sigma, b, HemTables{}});
+    return hipGetLastError();
+}
+
+hipError_t launch_sfr_lookup_str_words(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals,
+                                       uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed, const uint8_t* bytes,
+                                       const uint64_t* offs, uint64_t n, uint64_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t chunks = (n + kHsBlock - 1) / kHsBlock;
+    const unsigned g = (unsigned)std::min<uint64_t>(chunks, 65536);
+    k_hash_str_words<kHsEvalSfr><<<g, kHsBlock, 0, s>>>(bytes, offs, n, seed, P, nullptr, PartHist1{nullptr, 0, 0},
+                                                        EvalTables{vals, rank, out, sigma, b, HemTables{}, marks});
     return hipGetLastError();
 }
 

@@ -195,6 +195,15 @@ hipError_t launch_sf_assign_round(const uint3* slots, const uint32_t* vals, uint
 hipError_t launch_sf_pack(const void* u, uint64_t m, uint32_t b, uint64_t* words, hipStream_t s);
 hipError_t launch_sf_lookup_u64(const uint64_t* words, uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed,
                                 const uint64_t* keys, uint64_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_sfr_marks(const void* u, uint64_t m, uint32_t b, uint64_t* marks, uint32_t* bcount, hipStream_t s);
+hipError_t launch_sfr_compact(const void* u, uint64_t m, uint32_t b, const uint64_t* rank, uint64_t* vals,
+                              uint64_t cap_words, hipStream_t s);
+hipError_t launch_sfr_lookup_u64(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma,
+                                 uint32_t b, uint64_t P, uint64_t seed, const uint64_t* keys, uint64_t n,
+                                 uint64_t* out, hipStream_t s);
+hipError_t launch_sfr_lookup_str_words(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals,
+                                       uint64_t sigma, uint32_t b, uint64_t P, uint64_t seed, const uint8_t* bytes,
+                                       const uint64_t* offs, uint64_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_sf_check(const uint32_t* vals, uint64_t n, uint64_t sigma, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_pack_count(const uint8_t* code8, uint64_t m, uint64_t* codes, uint32_t* bcount, hipStream_t s);
 hipError_t launch_lookup_u64(const uint64_t* codes, const uint64_t* rank, uint64_t P, uint64_t seed,

@@ -81,6 +81,130 @@ __global__ __launch_bounds__(256) void k_sf_lookup_u64(const uint64_t* __restric
     }
 }
 
+// Ranked layout, pass 1: one thread per mark word (64 vertices): bit t set iff u[64w + t] != 0;
+// the 16 words of a rank block sum their counts into bcount[block].
+template <typename T>
+__global__ __launch_bounds__(256) void k_sfr_marks(const T* __restrict__ u, uint64_t m, uint64_t nwords,
+                                                   uint64_t* __restrict__ marks, uint32_t* __restrict__ bcount)
+{
+    constexpr uint32_t kVec = 16 / sizeof(T);  // elements per 16-byte load
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < nwords; base += stride) {
+        const uint64_t w = base + threadIdx.x;
+        uint64_t x = 0;
+        if (w < nwords) {
+            const uint64_t v0 = 64 * w;
+            if (v0 + 64 <= m) {
+                const uint4* p = reinterpret_cast<const uint4*>(u + v0);
+#pragma unroll
+                for (uint32_t q = 0; q < 64 / kVec; q++) {
+                    union {
+                        uint4 v;
+                        T e[kVec];
+                    } c;
+                    c.v = p[q];
+#pragma unroll
+                    for (uint32_t t = 0; t < kVec; t++)
+                        x |= (uint64_t)(c.e[t] != 0) << (q * kVec + t);
+                }
+            } else {
+                for (uint64_t t = 0; v0 + t < m; t++)
+                    x |= (uint64_t)(u[v0 + t] != 0) << t;
+            }
+            marks[w] = x;
+        }
+        uint32_t c = __popcll(x);
+        c += __shfl_xor(c, 1, 16);
+        c += __shfl_xor(c, 2, 16);
+        c += __shfl_xor(c, 4, 16);
+        c += __shfl_xor(c, 8, 16);
+        if (w < nwords && (w & 15) == 0)
+            bcount[w >> 4] = c;
+    }
+}
+
+// Ranked layout, pass 2: one workgroup per rank block of 1024 vertices, 4 per thread.  The
+// block's fields occupy bits [rank[j] b, rank[j + 1] b) of vals; they are assembled in LDS
+// (word 0 = the word holding bit rank[j] b) and written out: words wholly inside the range with
+// plain stores, the first and last -- which neighbouring blocks may share -- with atomicOr into
+// zeroed memory.  Words from cap_words on are never written (there are at most n fields, one per
+// hinge, and cap_words holds n of them).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sfr_compact(const T* __restrict__ u, uint64_t m, uint32_t b,
+                                                     const uint64_t* __restrict__ rank, uint64_t* __restrict__ vals,
+                                                     uint64_t cap_words)
+{
+    constexpr uint32_t kWords = kSfrBlock * 32 / 64 + 2;  // b <= 32, plus the start offset
+    __shared__ unsigned long long s_out[kWords];
+    __shared__ uint32_t s_wave[256 / kWave];
+    const uint64_t nblocks = (m + kSfrBlock - 1) / kSfrBlock;
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    for (uint64_t j = blockIdx.x; j < nblocks; j += gridDim.x) {
+        const uint64_t v0 = j * kSfrBlock + 4 * tid;
+        uint32_t x[4];
+#pragma unroll
+        for (uint32_t t = 0; t < 4; t++)
+            x[t] = v0 + t < m ? (uint32_t)u[v0 + t] : 0u;
+        const uint32_t c = (x[0] != 0) + (x[1] != 0) + (x[2] != 0) + (x[3] != 0);
+        // exclusive prefix of c over the workgroup
+        uint32_t incl = c;
+#pragma unroll
+        for (uint32_t d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, kWave);
+            incl += lane >= d ? y : 0u;
+        }
+        if (lane == kWave - 1)
+            s_wave[wave] = incl;
+        for (uint32_t i = tid; i < kWords; i += blockDim.x)
+            s_out[i] = 0;
+        __syncthreads();
+        uint32_t pre = incl - c;
+        for (uint32_t q = 0; q < wave; q++)
+            pre += s_wave[q];
+        const uint64_t bit0 = rank[j] * b;
+        const uint32_t off0 = (uint32_t)(bit0 & 63);
+#pragma unroll
+        for (uint32_t t = 0; t < 4; t++) {
+            if (x[t] == 0)
+                continue;
+            const uint32_t lb = off0 + pre * b;
+            const uint32_t lw = lb >> 6, sh = lb & 63;
+            atomicOr(&s_out[lw], (unsigned long long)x[t] << sh);
+            if (sh + b > 64)
+                atomicOr(&s_out[lw + 1], (unsigned long long)x[t] >> (64 - sh));
+            pre++;
+        }
+        __syncthreads();
+        const uint32_t total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        if (total) {
+            const uint32_t nw = (off0 + total * b + 63) / 64;
+            unsigned long long* dst = reinterpret_cast<unsigned long long*>(vals) + (bit0 >> 6);
+            for (uint32_t i = tid; i < nw && (bit0 >> 6) + i < cap_words; i += blockDim.x) {
+                if (i == 0 || i == nw - 1)
+                    atomicOr(&dst[i], s_out[i]);
+                else
+                    dst[i] = s_out[i];
+            }
+        }
+        __syncthreads();  // s_out and s_wave are reused by the next block
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sfr_lookup_u64(const uint64_t* __restrict__ marks,
+                                                        const uint64_t* __restrict__ rank,
+                                                        const uint64_t* __restrict__ vals, uint64_t sigma, uint32_t b,
+                                                        uint64_t P, uint64_t seed, const uint64_t* __restrict__ keys,
+                                                        uint64_t n, uint64_t* __restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint64_t s = keys[i] ^ seed;
+        uint32_t v0, v1, v2;
+        edge_of_digest(s, s, P, v0, v1, v2);
+        out[i] = sfr_eval_edge(marks, rank, vals, sigma, b, v0, v1, v2);
+    }
+}
+
 // Flags a value outside [0, sigma) in ctrl->err.
 __global__ __launch_bounds__(256) void k_sf_check(const uint32_t* __restrict__ vals, uint64_t n, uint64_t sigma,
                                                   Ctrl* ctrl)
@@ -200,6 +324,42 @@ hipError_t launch_sf_pack(const void* u, uint64_t m, uint32_t b, uint64_t* words
     case 2: k_sf_pack<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)u, m, b, nwords, words); break;
     default: k_sf_pack<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)u, m, b, nwords, words);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sfr_marks(const void* u, uint64_t m, uint32_t b, uint64_t* marks, uint32_t* bcount, hipStream_t s)
+{
+    const uint64_t nwords = (m + 63) / 64;
+    if (nwords == 0) return hipSuccess;
+    const unsigned g = grid_cap(nwords, 16384);
+    switch (sf_elem_bytes(b)) {
+    case 1: k_sfr_marks<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)u, m, nwords, marks, bcount); break;
+    case 2: k_sfr_marks<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)u, m, nwords, marks, bcount); break;
+    default: k_sfr_marks<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)u, m, nwords, marks, bcount);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sfr_compact(const void* u, uint64_t m, uint32_t b, const uint64_t* rank, uint64_t* vals,
+                              uint64_t cap_words, hipStream_t s)
+{
+    const uint64_t nblocks = (m + kSfrBlock - 1) / kSfrBlock;
+    if (nblocks == 0 || b == 0) return hipSuccess;
+    const unsigned g = (unsigned)std::min<uint64_t>(nblocks, 8192);
+    switch (sf_elem_bytes(b)) {
+    case 1: k_sfr_compact<uint8_t><<<g, 256, 0, s>>>((const uint8_t*)u, m, b, rank, vals, cap_words); break;
+    case 2: k_sfr_compact<uint16_t><<<g, 256, 0, s>>>((const uint16_t*)u, m, b, rank, vals, cap_words); break;
+    default: k_sfr_compact<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)u, m, b, rank, vals, cap_words);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sfr_lookup_u64(const uint64_t* marks, const uint64_t* rank, const uint64_t* vals, uint64_t sigma,
+                                 uint32_t b, uint64_t P, uint64_t seed, const uint64_t* keys, uint64_t n,
+                                 uint64_t* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_sfr_lookup_u64<<<grid_cap(n, 16384), 256, 0, s>>>(marks, rank, vals, sigma, b, P, seed, keys, n, out);
     return hipGetLastError();
 }
 

@@ -132,6 +132,10 @@ def test_static_function_sizes(mx):
     for sigma in (1, 2, 3, 4, 255, 256, 257, 65_535, 65_536, 65_537, 1_000_003, (1 << 32) - 1, 1 << 32):
         assert mx.sf_bits(sigma) == o.sf_bits(sigma) == (sigma - 1).bit_length()
         assert mx.sf_words(12_345, sigma) == o.sf_words(3 * o.part_size(12_345), sigma)
+        # ranked layout: m mark bits, one rank sample per 1024 vertices plus the total, n fields
+        m = 3 * o.part_size(12_345)
+        assert mx.sfr_sizes(12_345, sigma) == ((m + 63) // 64, int(o.lib.orc_sfr_rank_words(m)),
+                                               (12_345 * mx.sf_bits(sigma) + 63) // 64)
     # without claim lists the values in layer order take n more u32; with them, the edge states
     assert mx.sf_workspace_bytes(1 << 20) - mx.mphf_workspace_bytes(1 << 20) >= 4 << 20
     mx.set_option("claim_lists", 20)
