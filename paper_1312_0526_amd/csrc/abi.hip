@@ -717,36 +717,42 @@ int keys_equal(const KeySrc& k, uint64_t a, uint64_t b, bool& eq, hipStream_t s)
     return MPHX_OK;
 }
 
-// After the last failed try: do identical core edges come from equal keys?
-int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, uint64_t m, bool& dup, hipStream_t s)
+// After the last failed try: do identical core edges come from equal keys?  The core edges
+// and the pairs of them with equal vertex triples are found on the device (the slot region,
+// 16n bytes, is free once the tries are over); only the pairs' keys are read back.
+int detect_duplicates(const KeySrc& k, const MphfLayout& L, uint64_t n, bool& dup, hipStream_t s)
 {
-    // An edge is in the 2-core exactly when all three of its vertices still have degree >= 2:
-    // a peeled edge keeps its hinge at degree 1 (deletes skip the hinge), and a core vertex
-    // has lost every peeled edge and kept at least two core edges.
     dup = false;
-    std::vector<uint64_t> rec(m);
-    std::vector<uint32_t> edges(3 * n);
-    HIP_TRY(hipMemcpyAsync(rec.data(), L.rec, rec.size() * 8, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(edges.data(), L.edges, edges.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    auto deg = [&rec](uint32_t v) { return (uint32_t)(rec[v] >> 40); };
-    std::vector<uint32_t> core;
-    for (uint64_t e = 0; e < n; e++)
-        if (deg(edges[3 * e]) >= 2 && deg(edges[3 * e + 1]) >= 2 && deg(edges[3 * e + 2]) >= 2)
-            core.push_back((uint32_t)e);
-    std::sort(core.begin(), core.end(), [&](uint32_t a, uint32_t b) {
-        for (int q = 0; q < 3; q++)
-            if (edges[3ull * a + q] != edges[3ull * b + q]) return edges[3ull * a + q] < edges[3ull * b + q];
-        return a < b;
-    });
-    for (size_t i = 0; i + 1 < core.size() && !dup; i++) {
-        uint32_t a = core[i], b = core[i + 1];
-        if (edges[3ull * a] == edges[3ull * b] && edges[3ull * a + 1] == edges[3ull * b + 1] &&
-            edges[3ull * a + 2] == edges[3ull * b + 2]) {
-            bool eq = false;
-            int rc = keys_equal(k, a, b, eq, s);
-            if (rc) return rc;
-            dup = eq;
+    HIP_TRY(launch_ctrl_init(L.ctrl, L.lstart, s));
+    HIP_TRY(launch_core_count(L.rec, L.edges, n, L.ctrl, s));
+    Ctrl h{};
+    int rc = read_ctrl(L.ctrl, h, s);
+    if (rc) return rc;
+    const uint64_t core = h.aux;
+    if (core < 2) return MPHX_OK;
+    // at most 2/3 full: tsize <= 3 core <= 3n entries of 4 bytes, leaving >= 4n bytes of pairs
+    uint64_t tsize = 2;
+    while (tsize < core + core / 2 + 1)
+        tsize <<= 1;
+    uint32_t* tab = reinterpret_cast<uint32_t*>(L.slots);
+    uint2* pairs = reinterpret_cast<uint2*>(tab + tsize);
+    const uint32_t pcap = (uint32_t)std::min<uint64_t>((16 * n - 4 * tsize) / sizeof(uint2), 1024);
+    HIP_TRY(launch_fill_u32(tab, tsize, kUnclaimed, s));
+    HIP_TRY(launch_core_pairs(L.rec, L.edges, n, tab, tsize, pairs, pcap, L.ctrl, s));
+    rc = read_ctrl(L.ctrl, h, s);
+    if (rc) return rc;
+    std::vector<uint2> hp((size_t)std::min<uint64_t>(h.dups, pcap));
+    if (!hp.empty()) {
+        HIP_TRY(hipMemcpyAsync(hp.data(), pairs, hp.size() * sizeof(uint2), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    for (const uint2& p : hp) {
+        bool eq = false;
+        rc = keys_equal(k, p.x, p.y, eq, s);
+        if (rc) return rc;
+        if (eq) {
+            dup = true;
+            break;
         }
     }
     return MPHX_OK;
@@ -908,7 +914,7 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     }
     if (!done) {
         bool dup = false;
-        int rc = detect_duplicates(k, L, n, m, dup, s);
+        int rc = detect_duplicates(k, L, n, dup, s);
         if (rc) return rc;
         if (dup) return fail(MPHX_EDUP, "duplicate keys: identical edges from equal keys stay in the 2-core");
         return fail(MPHX_ECORE, "2-core of %llu edges after %u tries", (unsigned long long)(n - peeled), max_tries);

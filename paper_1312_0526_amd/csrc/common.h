@@ -28,7 +28,8 @@ struct Ctrl {
     unsigned long long degsum; // sum of all degree fields (overflow check: must be 3n)
     unsigned long long updates;  // deletes applied through update lists
     unsigned long long touched;  // records those deletes changed
-    uint64_t pad[24];
+    unsigned long long dups;     // pairs of 2-core edges with equal vertex triples (failure path)
+    uint64_t pad[23];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl is one 256-byte slot");
 

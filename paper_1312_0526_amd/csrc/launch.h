@@ -165,6 +165,11 @@ hipError_t launch_order_sort(const uint32_t* round, uint64_t n, uint32_t nrounds
                              hipStream_t s);
 
 // assignment, ranking, lookup (solve.hip)
+// 2-core edges of a failed try: their count (ctrl->aux), then pairs with equal vertex triples
+// (tab: tsize entries, a power of two above the count, filled with kUnclaimed)
+hipError_t launch_core_count(const uint64_t* rec, const uint32_t* edges, uint64_t n, Ctrl* ctrl, hipStream_t s);
+hipError_t launch_core_pairs(const uint64_t* rec, const uint32_t* edges, uint64_t n, uint32_t* tab, uint64_t tsize,
+                             uint2* pairs, uint32_t pcap, Ctrl* ctrl, hipStream_t s);
 hipError_t launch_assign_round(const uint3* slots, const uint64_t* lstart, uint32_t r, uint64_t n_bound, uint64_t P,
                                uint8_t* code8, unsigned grid_cap, hipStream_t s);
 // HEM split (keys.hip, part.hip): signature records, their partition into 2^k buckets in place

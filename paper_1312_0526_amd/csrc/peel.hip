@@ -400,6 +400,77 @@ __global__ __launch_bounds__(kPeelBlock) void k_apply(uint64_t* __restrict__ rec
 }
 
 // ------------------------------------------------------------------------------------------
+// After a try that left a 2-core: which core edges share their vertex triple?  An edge is in
+// the core exactly when its three vertices still have degree >= 2 (a peeled edge keeps its
+// hinge at degree 1, the deletes skip it).  Pass 1 counts the core edges into ctrl->aux;
+// pass 2 inserts each into an open-addressing table of edge ids (more slots than core edges,
+// so every probe sequence ends) keyed by the triple, and a core edge whose triple is already
+// there records the pair (first edge, this edge): ctrl->dups counts them, the first pcap are
+// stored.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool core_edge(const uint64_t* rec, const uint32_t* edges, uint64_t e, uint3& t)
+{
+    t = make_uint3(edges[3 * e], edges[3 * e + 1], edges[3 * e + 2]);
+    return Rec::deg(rec[t.x]) >= 2 && Rec::deg(rec[t.y]) >= 2 && Rec::deg(rec[t.z]) >= 2;
+}
+
+__global__ __launch_bounds__(256) void k_core_count(const uint64_t* __restrict__ rec,
+                                                    const uint32_t* __restrict__ edges, uint64_t n, Ctrl* ctrl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    unsigned long long c = 0;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        uint3 t;
+        c += core_edge(rec, edges, e, t) ? 1u : 0u;
+    }
+    if (c)
+        atomicAdd(&ctrl->aux, c);
+}
+
+__global__ __launch_bounds__(256) void k_core_pairs(const uint64_t* __restrict__ rec,
+                                                    const uint32_t* __restrict__ edges, uint64_t n,
+                                                    uint32_t* __restrict__ tab, uint64_t tmask,
+                                                    uint2* __restrict__ pairs, uint32_t pcap, Ctrl* ctrl)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+        uint3 t;
+        if (!core_edge(rec, edges, e, t))
+            continue;
+        uint64_t h = fin(((uint64_t)t.x << 32 | t.y) ^ ((uint64_t)t.z * kGamma)) & tmask;
+        for (;;) {
+            const uint32_t old = atomicCAS(&tab[h], kUnclaimed, (uint32_t)e);
+            if (old == kUnclaimed)
+                break;
+            if (edges[3 * (uint64_t)old] == t.x && edges[3 * (uint64_t)old + 1] == t.y &&
+                edges[3 * (uint64_t)old + 2] == t.z) {
+                const unsigned long long j = atomicAdd(&ctrl->dups, 1ull);
+                if (j < pcap)
+                    pairs[j] = make_uint2(old, (uint32_t)e);
+                break;
+            }
+            h = (h + 1) & tmask;
+        }
+    }
+}
+
+hipError_t launch_core_count(const uint64_t* rec, const uint32_t* edges, uint64_t n, Ctrl* ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_core_count<<<(unsigned)std::min<uint64_t>((n + 255) / 256, 8192), 256, 0, s>>>(rec, edges, n, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_core_pairs(const uint64_t* rec, const uint32_t* edges, uint64_t n, uint32_t* tab, uint64_t tsize,
+                             uint2* pairs, uint32_t pcap, Ctrl* ctrl, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    k_core_pairs<<<(unsigned)std::min<uint64_t>((n + 255) / 256, 8192), 256, 0, s>>>(rec, edges, n, tab, tsize - 1,
+                                                                                      pairs, pcap, ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // Per-edge outputs of mphx_peel from the edge states.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_peel_finalize(const uint32_t* __restrict__ state, uint64_t n,

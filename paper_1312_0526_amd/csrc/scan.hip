@@ -41,6 +41,7 @@ __global__ void k_ctrl_init(Ctrl* ctrl, uint64_t* lstart)
         ctrl->degsum = 0;
         ctrl->updates = 0;
         ctrl->touched = 0;
+        ctrl->dups = 0;
         lstart[0] = 0;
     }
 }

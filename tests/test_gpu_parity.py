@@ -307,6 +307,33 @@ def test_mphf_core_and_duplicates(mx, o):
     assert o.mphf_build_u64(dup, max_tries=2)[0] == oracle.EDUP
 
 
+def test_mphf_duplicates_inside_large_cores(mx, o):
+    """Duplicate detection after the last try runs on the device (core edges, then pairs of
+    them with equal vertex triples): a large core without duplicates stays ECORE; duplicates
+    inside a large core, more duplicate pairs than the 1024 read back, and duplicate strings
+    give EDUP, as in the oracle."""
+    keys = workloads.u64_keys(200_000, gen_seed=21)
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_u64(dev(keys), gamma=(100, 100), max_tries=1)
+    rc, ref = o.mphf_build_u64(keys, gnum=100, max_tries=1)
+    assert ei.value.status == mx.ECORE and rc == oracle.ECORE
+    assert ei.value.info["n_core"] == ref["n_core"] > 100_000
+    for dup in (np.concatenate([keys, keys[7:9]]), np.concatenate([keys[:20_000], keys[:3000]])):
+        gamma = (100, 100) if len(dup) > 100_000 else (123, 100)
+        with pytest.raises(mx.MphxError) as ei:
+            mx.mphf_build_u64(dev(dup), gamma=gamma, max_tries=1)
+        assert ei.value.status == mx.EDUP
+        assert o.mphf_build_u64(dup, gnum=gamma[0], max_tries=1)[0] == oracle.EDUP
+    data, offs = workloads.str_keys(5000, gen_seed=22)
+    lens = np.diff(offs)
+    d2 = np.concatenate([data, data[offs[10]:offs[11]]])
+    o2 = np.concatenate([offs, [offs[-1] + lens[10]]]).astype(np.uint64)
+    with pytest.raises(mx.MphxError) as ei:
+        mx.mphf_build_str(dev(d2), dev(o2), max_tries=2)
+    assert ei.value.status == mx.EDUP
+    assert o.mphf_build_str(d2, o2, max_tries=2)[0] == oracle.EDUP
+
+
 def test_mphf_deterministic_across_launch_shapes(mx):
     keys = dev(workloads.u64_keys(300_000, gen_seed=9))
     outs = []
