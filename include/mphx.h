@@ -590,7 +590,7 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 each part's (vertex, edge) incidences into buckets of 2^14 vertices and
  *                 accumulating each bucket in LDS; 0 = device atomics straight into HBM.
  *                 Both give identical records; mphx_peel always uses the atomics.
- *   "claim_lists" b in 0..32 (default 28): mphx_mphf_build_* with n >= 2^b keys claims the
+ *   "claim_lists" b in 0..32 (default 26): mphx_mphf_build_* with n >= 2^b keys claims the
  *                 edges of each layer after the first by appending (edge, position) lists
  *                 that are radix-partitioned by edge and resolved in LDS, instead of one
  *                 device atomic per claim, and reads one count back per round.  0 = never.

@@ -25,7 +25,9 @@ struct Options {
     std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
     std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
-    std::atomic<int> claim_lists{28};  // claim lists from n >= 2^claim_lists keys on (0 = never)
+    std::atomic<int> claim_lists{26};  // claim lists from n >= 2^claim_lists keys on (0 = never);
+                                       // below 2^26 keys the per-round partition and resolve cost more
+                                       // than the atomic claims they replace
     std::atomic<int> update_lists{16}; // claim-list rounds with 2 * layer >= m * update_lists / 100
     std::atomic<int> hem_block{1024};  // batched-kernel workgroup size for the HEM split's buckets
     std::atomic<int> hem_grid{0};      // its persistent grid (0 = one workgroup per compute unit)

@@ -138,11 +138,12 @@ def test_static_function_sizes(mx):
                                                (12_345 * mx.sf_bits(sigma) + 63) // 64)
     # without claim lists the values in layer order take n more u32; with them, the edge states
     assert mx.sf_workspace_bytes(1 << 20) - mx.mphf_workspace_bytes(1 << 20) >= 4 << 20
+    old = mx.get_option("claim_lists")
     mx.set_option("claim_lists", 20)
     try:
         assert mx.sf_workspace_bytes(1 << 20) == mx.mphf_workspace_bytes(1 << 20)
     finally:
-        mx.set_option("claim_lists", 28)
+        mx.set_option("claim_lists", old)
 
 
 def test_update_lists_option_range(mx):

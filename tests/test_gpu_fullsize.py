@@ -67,6 +67,7 @@ def test_config2_full_parity(mx):
     assert np.array_equal(host(keys[:1000], np.uint64), keys_h[:1000])
     assert np.array_equal(host(keys[-1000:], np.uint64), keys_h[-1000:])
     r = mx.mphf_build_u64(keys, seed=0)
+    assert r["update_deletes"] > 0  # the default here: claim lists, dense rounds by update lists
     rc, ref = o.mphf_build_u64(keys_h, seed=0)
     assert rc == 0 and r["tries"] == ref["tries"] == 1 and r["n_rounds"] == ref["n_rounds"]
     assert np.array_equal(host(r["codes"], np.uint64), ref["words"])
@@ -88,19 +89,20 @@ def test_config2_full_parity(mx):
 
 
 @pytest.mark.timeout(1200)
-def test_config2_full_parity_claim_and_update_lists(mx):
-    """2^27 keys through the path the largest builds take by default: claim lists from round 1,
-    the dense rounds' deletes through sorted update lists."""
+def test_config2_full_parity_atomic_claims(mx):
+    """2^27 keys through the path smaller builds take by default (2^27 keys take claim lists
+    from round 1 and sorted update lists for the dense rounds): one device atomic per claim."""
     n = 1 << 27
     o = oracle.Oracle()
     keys_h = workloads.u64_keys(n)
     keys = mx.gen_keys_u64(n)
-    mx.set_option("claim_lists", 27)
+    old = mx.get_option("claim_lists")
+    mx.set_option("claim_lists", 0)
     try:
-        assert mx.get_option("update_lists") == 16
         r = mx.mphf_build_u64(keys, seed=0)
     finally:
-        mx.set_option("claim_lists", 28)
+        mx.set_option("claim_lists", old)
+    assert r["update_deletes"] == 0
     rc, ref = o.mphf_build_u64(keys_h, seed=0)
     assert rc == 0 and r["tries"] == ref["tries"] == 1 and r["n_rounds"] == ref["n_rounds"]
     assert np.array_equal(host(r["codes"], np.uint64), ref["words"])

@@ -400,11 +400,12 @@ def claim_mode(request, mx):
     (p = 1: nearly every round, p = 16: the dense ones, which the default picks), or one
     device atomic per claim."""
     lists, upd = request.param
+    old = mx.get_option("claim_lists"), mx.get_option("update_lists")
     mx.set_option("claim_lists", lists)
     mx.set_option("update_lists", upd)
     yield request.param
-    mx.set_option("claim_lists", 28)
-    mx.set_option("update_lists", 16)
+    mx.set_option("claim_lists", old[0])
+    mx.set_option("update_lists", old[1])
 
 
 @pytest.mark.parametrize("n,seed", [(1_000_000, 0), (12_000_000, 4), (1, 0), (7, 5)])
@@ -420,6 +421,7 @@ def test_mphf_claim_modes_match_oracle(mx, o, claim_mode, n, seed):
 
 @pytest.mark.parametrize("upd", [0, 1], ids=["claims", "update-lists"])
 def test_mphf_claim_lists_strings_retries_and_failures(mx, o, upd):
+    old = mx.get_option("claim_lists"), mx.get_option("update_lists")
     mx.set_option("claim_lists", 1)
     mx.set_option("update_lists", upd)
     try:
@@ -448,8 +450,8 @@ def test_mphf_claim_lists_strings_retries_and_failures(mx, o, upd):
             mx.mphf_build_u64(dev(dup), max_tries=2)
         assert ei.value.status == mx.EDUP
     finally:
-        mx.set_option("claim_lists", 28)
-        mx.set_option("update_lists", 16)
+        mx.set_option("claim_lists", old[0])
+        mx.set_option("update_lists", old[1])
 
 
 @pytest.mark.parametrize("upd,cap", [(16, 1000), (0, 5000), (16, 0)],
@@ -458,6 +460,7 @@ def test_claim_list_overflow_redoes_the_try_with_atomic_claims(mx, o, upd, cap):
     """A claim-list round whose records exceed the list (forced here with a small list_cap)
     makes the try start again with atomic claims; the MPHF and a static function built that
     way equal the oracle's, and the fallback counter shows the redo happened."""
+    old = mx.get_option("claim_lists"), mx.get_option("update_lists")
     mx.set_option("claim_lists", 10)
     mx.set_option("update_lists", upd)
     mx.set_option("list_cap", cap)
@@ -475,7 +478,7 @@ def test_claim_list_overflow_redoes_the_try_with_atomic_claims(mx, o, upd, cap):
         assert np.array_equal(host(sf["words"], np.uint64), sref["words"])
         assert mx.get_option("list_fallbacks") == (2 if cap else 0)
     finally:
-        mx.set_option("claim_lists", 28)
-        mx.set_option("update_lists", 16)
+        mx.set_option("claim_lists", old[0])
+        mx.set_option("update_lists", old[1])
         mx.set_option("list_cap", 0)
         mx.set_option("list_fallbacks", 0)

@@ -42,15 +42,17 @@ def values_for(n, sigma, seed):
     return rng.integers(0, sigma, n, dtype=np.uint64).astype(np.uint32)
 
 
-@pytest.fixture(params=[(28, 16), (1, 0), (1, 1), (1, 16), (0, 0)],
+@pytest.fixture(params=[(None, None), (1, 0), (1, 1), (1, 16), (0, 0)],
                 ids=["default", "claim-lists", "update-lists-most-rounds", "update-lists-dense-rounds", "atomic-claims"])
 def mode(request, mx):
     lists, upd = request.param
-    mx.set_option("claim_lists", lists)
-    mx.set_option("update_lists", upd)
+    old = mx.get_option("claim_lists"), mx.get_option("update_lists")
+    if lists is not None:
+        mx.set_option("claim_lists", lists)
+        mx.set_option("update_lists", upd)
     yield request.param
-    mx.set_option("claim_lists", 28)
-    mx.set_option("update_lists", 16)
+    mx.set_option("claim_lists", old[0])
+    mx.set_option("update_lists", old[1])
 
 
 @pytest.mark.parametrize("n,sigma", [(1_000_000, 256), (12_345, 3), (54_321, 1_000_003), (33_333, 65_521), (7, 2), (1, 1 << 32)])
