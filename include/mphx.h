@@ -613,6 +613,10 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 bucket built through device memory with 2 * layer * d >= m vertices deletes
  *                 through a list sorted by tile of vertices and applied in LDS instead of
  *                 device atomics; 0 = never.  The same codes either way.
+ *   "batch_claim_lists" 0 or 1 (default 1): in the batched kernel, the other layers of such
+ *                 a bucket (those of at most 3n/8 edges) record their next-layer claims in a
+ *                 list that is grouped by tile of edges and resolved in LDS, instead of one
+ *                 device atomicMin per claim; 0 = atomicMin.  The same codes either way.
  *   "hem_block"   256, 512 or 1024 (default 1024): workgroup size of the batched kernel that
  *                 builds the HEM split's buckets (mphx_hem_build_*, mphx_hem_build_host_*).
  *   "hem_grid"    0..65536 (default 0 = one workgroup per compute unit): its persistent grid.

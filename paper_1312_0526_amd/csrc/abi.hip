@@ -35,6 +35,7 @@ struct Options {
     std::atomic<int64_t> list_fallbacks{0};  // tries redone with atomic claims after a list overflowed
     std::atomic<int> batch_lds{1};     // 1 = batched buckets that fit run entirely in LDS
     std::atomic<int> batch_sort_deletes{8};  // sorted deletes for layers with 2 * layer * this >= m
+    std::atomic<int> batch_claim_lists{1};   // sparse rounds of key-word buckets claim through lists
                                        // delete through a sorted update list (0 = never)
 };
 
@@ -439,6 +440,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "batch_sort_deletes")) {
         if (value < 0 || value > 1024) return fail(MPHX_EINVAL, "batch_sort_deletes must be in 0..1024");
         g_opt.batch_sort_deletes = (int)value;
+    } else if (!strcmp(key, "batch_claim_lists")) {
+        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "batch_claim_lists must be 0 or 1");
+        g_opt.batch_claim_lists = (int)value;
     } else if (!strcmp(key, "hem_grid")) {
         if (value < 0 || value > (1 << 16)) return fail(MPHX_EINVAL, "hem_grid must be in 0..65536");
         g_opt.hem_grid = (int)value;
@@ -467,6 +471,7 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "hem_grid")) return g_opt.hem_grid;
     if (!strcmp(key, "batch_lds")) return g_opt.batch_lds;
     if (!strcmp(key, "batch_sort_deletes")) return g_opt.batch_sort_deletes;
+    if (!strcmp(key, "batch_claim_lists")) return g_opt.batch_claim_lists;
     if (!strcmp(key, "list_cap")) return g_opt.list_cap;
     if (!strcmp(key, "list_fallbacks")) return g_opt.list_fallbacks;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
@@ -1347,6 +1352,7 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
     a.max_n = max_bucket;
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
     a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
+    a.claim_lists = (uint32_t)g_opt.batch_claim_lists.load();
     a.pairs = pairs ? 1u : 0u;
     HIP_TRY(launch_batch_descs(descs, keys, bucket_off, B, seed, code_off, rank_off, codes, rank,
                                reinterpret_cast<BucketResult*>(results), s, pairs ? 2u : 1u));
@@ -1609,6 +1615,7 @@ int mphx_build_batch(const mphx_bucket* buckets, uint32_t B, const uint32_t* ord
     a.max_n = max_bucket;
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
     a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
+    a.claim_lists = (uint32_t)g_opt.batch_claim_lists.load();
     HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), (hipStream_t)stream));
     return MPHX_OK;
 }

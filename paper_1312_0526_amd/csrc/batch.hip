@@ -298,7 +298,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
 {
     using S = Sc<kScope>;
     constexpr uint32_t kBatchTile = batch_tile<kBlock>();
-    __shared__ uint32_t s_ltail, s_err, s_degsum;
+    __shared__ uint32_t s_ltail, s_err, s_degsum, s_ctail;
     __shared__ uint32_t s_wtot[kBlock / kWave];
     unsigned long long* s_tab = reinterpret_cast<unsigned long long*>(lds);  // kBatchTile records
     uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_tab + kBatchTile);       // kBatchMaxBuckets
@@ -554,6 +554,111 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     __syncthreads();
                     for (uint32_t v = tid; v < cnt; v += kBlock)
                         L.rec[v0 + v] = s_tab[v];
+                    __syncthreads();
+                }
+                lo = hi;
+                r++;
+                continue;
+            }
+            // A sparse layer of a bucket given by key words (whose edge area is free) may claim
+            // through a list instead of atomicMin on the states, the plain path's claim lists
+            // inside the workgroup: every delete that leaves a vertex at degree 1 records
+            // (remaining edge, the vertex's part); the records are grouped by tile of kClTile
+            // edges and each tile resolved in an LDS byte per edge (a bit per claiming part).
+            // A claim counts only while its edge is unclaimed (an edge already in a layer,
+            // this one included, keeps its state), and the lowest claiming part is the hinge:
+            // exactly the layer and hinges atomicMin gives.
+            constexpr uint32_t kClTile = kBatchTile * 8;  // edges per tile: one LDS byte each
+            const uint32_t ncl = (n + kClTile - 1) / kClTile;
+            if (a.claim_lists && d.keys && 8ull * (hi - lo) <= 3ull * n && ncl <= kBatchMaxBuckets) {
+                uint2* cl = reinterpret_cast<uint2*>(L.edges);  // 12n bytes: claims, then grouped
+                uint2* cg = cl + 2 * (hi - lo);                 // at most two per layer edge each
+                if (tid == 0)
+                    s_ctail = 0;
+                for (uint32_t b = tid; b < ncl; b += kBlock)
+                    s_cnt[b] = 0;
+                __syncthreads();
+                for (uint32_t base = lo; base < hi; base += kBlock) {
+                    const uint32_t i = base + tid;
+                    uint2 c0 = make_uint2(0u, 0u), c1 = make_uint2(0u, 0u);
+                    bool f0 = false, f1 = false;
+                    if (i < hi) {
+                        const uint32_t e = L.slots[i].x;
+                        const uint32_t h = S::ld(L.state + e) & 3u;
+                        const uint3 ev = bucket_edge(a, d, L, e, sd, P);
+                        const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
+                        const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
+                        const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
+                        L.slots[i] = make_uint3(vh, va, vb);
+                        const uint64_t oa = S::rec_del(L.rec, va, e);
+                        const uint64_t ob = S::rec_del(L.rec, vb, e);
+                        if (Rec::deg(oa) == 2) {
+                            c0 = make_uint2((uint32_t)(Rec::edge(oa) - e), part_of(va, P));
+                            f0 = true;
+                        }
+                        if (Rec::deg(ob) == 2) {
+                            c1 = make_uint2((uint32_t)(Rec::edge(ob) - e), part_of(vb, P));
+                            f1 = true;
+                        }
+                        if (!f0) {  // the first requested slot holds the first record
+                            c0 = c1;
+                            f0 = f1;
+                            f1 = false;
+                        }
+                        if (f0)
+                            atomicAdd(&s_cnt[c0.x / kClTile], 1u);
+                        if (f1)
+                            atomicAdd(&s_cnt[c1.x / kClTile], 1u);
+                    }
+                    const uint32_t pos = block_append(&s_ctail, f0, f1);
+                    if (f0)
+                        cl[pos] = c0;
+                    if (f1)
+                        cl[pos + 1] = c1;
+                }
+                __syncthreads();
+                const uint32_t nc = s_ctail;
+                lds_exclusive_scan<kBlock>(s_cnt, ncl, s_wtot);
+                for (uint32_t b = tid; b < ncl; b += kBlock)
+                    s_bnd[b] = s_cnt[b];
+                if (tid == 0)
+                    s_bnd[ncl] = nc;
+                __syncthreads();
+                for (uint32_t j = tid; j < nc; j += kBlock) {
+                    const uint2 c = cl[j];
+                    cg[atomicAdd(&s_cnt[c.x / kClTile], 1u)] = c;
+                }
+                __syncthreads();
+                uint32_t* tab = reinterpret_cast<uint32_t*>(s_tab);  // kClTile bytes
+                for (uint32_t tl = 0; tl < ncl; tl++) {
+                    const uint32_t j0 = s_bnd[tl], j1 = s_bnd[tl + 1];
+                    if (j0 == j1)
+                        continue;  // uniform per block
+                    for (uint32_t j = j0 + tid; j < j1; j += kBlock)
+                        tab[(cg[j].x % kClTile) >> 2] = 0u;
+                    __syncthreads();
+                    for (uint32_t j = j0 + tid; j < j1; j += kBlock) {
+                        const uint2 c = cg[j];
+                        if (S::ld(L.state + c.x) == kUnclaimed)
+                            atomicOr(&tab[(c.x % kClTile) >> 2], 1u << (8 * (c.x & 3) + c.y));
+                    }
+                    __syncthreads();
+                    for (uint32_t base = j0; base < j1; base += kBlock) {
+                        const uint32_t j = base + tid;
+                        bool win = false;
+                        uint32_t c = 0;
+                        if (j < j1) {
+                            const uint2 cc = cg[j];
+                            const uint32_t bits = (tab[(cc.x % kClTile) >> 2] >> (8 * (cc.x & 3))) & 7u;
+                            win = bits != 0 && (uint32_t)__builtin_ctz(bits) == cc.y;
+                            c = cc.x;
+                            if (win)
+                                L.state[c] = rr | cc.y;
+                        }
+                        const uint32_t pos = block_append(&s_ltail, win, false);
+                        if (win)
+                            L.slots[pos].x = c;
+                    }
                     __syncthreads();
                 }
                 lo = hi;

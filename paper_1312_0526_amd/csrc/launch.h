@@ -72,6 +72,8 @@ struct BatchArgs {
     uint32_t sort_div;       // > 0: a layer deletes through a sorted list when 2 * layer * sort_div >= m
     uint32_t pairs;          // 1: every bucket's keys are 128-bit digest pairs (2 u64 words per key:
                              // the edge under seed t is that of the digest (x ^ t, y ^ t))
+    uint32_t claim_lists;    // 1: sparse rounds of buckets given by key words resolve their claims
+                             // through a list grouped by edge tile, in LDS, instead of atomicMin
 };
 
 // batched builds (batch.hip)

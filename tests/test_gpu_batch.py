@@ -71,15 +71,20 @@ def test_batch_matches_oracle(mx, o, block, grid, scope):
     assert (res["tries"] > 1).sum() > 20  # small buckets retry often at gamma 1.23
 
 
-@pytest.mark.parametrize("lds,sort_div", [(0, 0), (0, 8), (1, 8)])
-def test_batch_lds_path_on_and_off(mx, o, lds, sort_div):
+_BATCH_OPTS = ("batch_lds", "batch_sort_deletes", "batch_claim_lists")
+
+
+@pytest.mark.parametrize("lds,sort_div,cl", [(0, 0, 0), (0, 0, 1), (0, 8, 0), (0, 8, 1), (1, 8, 1)])
+def test_batch_lds_path_on_and_off(mx, o, lds, sort_div, cl):
     # buckets up to about 18,000 keys run in LDS with 1024-thread workgroups, larger ones (and
     # every bucket with the option off) through device memory, whose dense layers delete
-    # through sorted lists unless that is off too: the same codes every way
+    # through sorted lists unless that is off too, and whose other layers claim through lists
+    # resolved in LDS unless that is off: the same codes every way
     import torch
 
-    mx.set_option("batch_lds", lds)
-    mx.set_option("batch_sort_deletes", sort_div)
+    old = [mx.get_option(k) for k in _BATCH_OPTS]
+    for k, v in zip(_BATCH_OPTS, (lds, sort_div, cl)):
+        mx.set_option(k, v)
     try:
         off = _offsets(SIZES)
         keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
@@ -88,8 +93,30 @@ def test_batch_lds_path_on_and_off(mx, o, lds, sort_div):
         torch.cuda.synchronize()
         _check_buckets(mx, o, bb, _host_keys(SIZES), SIZES)
     finally:
-        mx.set_option("batch_lds", 1)
-        mx.set_option("batch_sort_deletes", 8)
+        for k, v in zip(_BATCH_OPTS, old):
+            mx.set_option(k, v)
+
+
+@pytest.mark.parametrize("block", [256, 1024])
+def test_batch_claim_lists_over_several_edge_tiles(mx, o, block):
+    """Buckets of 40,000 to 300,000 keys through device memory: their claim lists span several
+    tiles of edges (32,768 per tile at 256 threads, 65,536 at 1024), each resolved in LDS."""
+    import torch
+
+    sizes = np.array([40_000, 70_001, 131_072, 299_999, 65_536, 100_003], np.uint64)
+    old = [mx.get_option(k) for k in _BATCH_OPTS]
+    for k, v in zip(_BATCH_OPTS, (0, 8, 1)):
+        mx.set_option(k, v)
+    try:
+        off = _offsets(sizes)
+        keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+        bb = mx.BatchBuild(off, block=block, grid=0, scope=0)
+        bb.run(keys)
+        torch.cuda.synchronize()
+        _check_buckets(mx, o, bb, _host_keys(sizes), sizes)
+    finally:
+        for k, v in zip(_BATCH_OPTS, old):
+            mx.set_option(k, v)
 
 
 def test_batch_large_buckets_sampled(mx, o):
