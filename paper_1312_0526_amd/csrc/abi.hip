@@ -1827,10 +1827,11 @@ static void layout_hem_host(Carve& c, int kind, uint64_t n, uint32_t k, uint32_t
 
 extern "C" {
 
-// Host-to-device copies for the streamed build.  Pinned sources are copied directly; pageable
-// ones pass through two pinned staging buffers owned by the library: host threads fill one
-// buffer while the DMA engine drains the other (an event per buffer says when it is free).
-// The buffers live until the process ends; one streamed build uses them at a time.
+// Host-device copies for the streamed builds.  Pinned host memory is copied directly; pageable
+// memory passes through two pinned staging buffers owned by the library.  Towards the device,
+// host threads fill one buffer while the DMA engine drains the other (an event per buffer says
+// when it is free); towards the host, the DMA engine fills one buffer while host threads empty
+// the other.  The buffers live until the process ends; one streamed build uses them at a time.
 class HostStager {
   public:
     static constexpr size_t kPiece = size_t(1) << 27;  // bytes per staged copy
@@ -1849,18 +1850,9 @@ class HostStager {
     {
         if (bytes == 0) return hipSuccess;
         if (is_pinned(src)) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s_);
+        hipError_t berr = ensure_buffers();
+        if (berr != hipSuccess) return berr;
         Pool& p = pool();
-        if (!p.buf[0]) {
-            for (void*& b : p.buf) {
-                hipError_t e = hipHostMalloc(&b, kPiece, hipHostMallocDefault);
-                if (e != hipSuccess) return e;
-            }
-        }
-        for (hipEvent_t& e : ev_)
-            if (!e) {
-                hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-                if (err != hipSuccess) return err;
-            }
         for (size_t o = 0; o < bytes; o += kPiece) {
             const size_t len = std::min(kPiece, bytes - o);
             const int i = next_;
@@ -1876,7 +1868,59 @@ class HostStager {
         return hipSuccess;
     }
 
+    // Device to host; returns when dst holds the bytes (the stream is drained up to the copy).
+    hipError_t copy_out(void* dst, const void* src, size_t bytes)
+    {
+        if (bytes == 0) return hipSuccess;
+        if (is_pinned(dst)) {
+            hipError_t err = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s_);
+            return err != hipSuccess ? err : hipStreamSynchronize(s_);
+        }
+        hipError_t err = ensure_buffers();
+        if (err != hipSuccess) return err;
+        const size_t pieces = (bytes + kPiece - 1) / kPiece;
+        auto len_of = [&](size_t j) { return std::min(kPiece, bytes - j * kPiece); };
+        // piece j goes through buffer j & 1; before a buffer is refilled, its last use (an
+        // earlier host-to-device copy, or piece j - 2, emptied below) has finished
+        auto issue = [&](size_t j) {
+            const int i = (int)(j & 1);
+            hipError_t e = hipEventSynchronize(ev_[i]);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(pool().buf[i], static_cast<const uint8_t*>(src) + j * kPiece, len_of(j),
+                                   hipMemcpyDeviceToHost, s_);
+            return e == hipSuccess ? hipEventRecord(ev_[i], s_) : e;
+        };
+        err = issue(0);
+        for (size_t j = 0; j < pieces && err == hipSuccess; j++) {
+            if (j + 1 < pieces)
+                err = issue(j + 1);
+            if (err == hipSuccess)
+                err = hipEventSynchronize(ev_[j & 1]);
+            if (err == hipSuccess)
+                parallel_copy(static_cast<uint8_t*>(dst) + j * kPiece, static_cast<const uint8_t*>(pool().buf[j & 1]),
+                              len_of(j));
+        }
+        return err;
+    }
+
   private:
+    hipError_t ensure_buffers()
+    {
+        Pool& p = pool();
+        if (!p.buf[0]) {
+            for (void*& b : p.buf) {
+                hipError_t e = hipHostMalloc(&b, kPiece, hipHostMallocDefault);
+                if (e != hipSuccess) return e;
+            }
+        }
+        for (hipEvent_t& e : ev_)
+            if (!e) {
+                hipError_t err = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+                if (err != hipSuccess) return err;
+            }
+        return hipSuccess;
+    }
+
     struct Pool {
         std::mutex mu;
         void* buf[2] = {nullptr, nullptr};
@@ -2311,7 +2355,7 @@ int mphx_mphf_build_stream_u64(const uint64_t* keys, uint64_t n, uint64_t seed, 
             }
             if (spill) {  // the round's slots to host memory; the area is reused by the next round
                 Timed tm(PH_OTHER, s);
-                HIP_TRY(hipMemcpyAsync(hl + 12 * peeled, L.slots, 12 * cnt, hipMemcpyDeviceToHost, s));
+                HIP_TRY(stager.copy_out(hl + 12 * peeled, L.slots, 12 * cnt));
                 for (int q = 0; q < 4; q++) bounds.push_back(peeled + (b[q] - b[0]));
             } else {
                 for (int q = 0; q < 4; q++) bounds.push_back(b[q]);

@@ -66,14 +66,15 @@ def test_stream_build_2e24_matches_oracle(mx, o, spill):
 
 
 def test_stream_build_pinned_keys_and_small_sets(mx, o):
-    """Pinned host keys; small key sets whose first tries leave a 2-core (retries with seed + 1
+    """Pinned host keys and layer buffer; small key sets whose first tries leave a 2-core (retries with seed + 1
     on both sides); one key; a set of two keys, which can never peel."""
     import torch
 
     keys = workloads.u64_keys(1_000_003, gen_seed=3)
     pinned = torch.empty(len(keys), dtype=torch.int64).pin_memory()
     pinned.copy_(_host(keys))
-    got = mx.mphf_build_stream_u64(pinned, seed=2, chunk_keys=300_000, layer_slots=400_000)
+    layers = torch.empty(12 * len(keys), dtype=torch.uint8).pin_memory()  # spilled layers pinned too
+    got = mx.mphf_build_stream_u64(pinned, seed=2, chunk_keys=300_000, layer_slots=400_000, host_layers=layers)
     rc, ref = o.mphf_build_u64(keys, seed=2)
     assert rc == 0
     _same(got, ref)
