@@ -531,7 +531,8 @@ MPHX_API int mphx_server_destroy(mphx_server* server);
  *   caller-owned) after its deletes and copied back, last round first, for the assignment; the
  *   largest layer (round 0's, about 0.24 n at gamma 1.23) must fit, else MPHX_ENOMEM.
  *   ws (dev, 256-byte aligned): mphx_stream_workspace_bytes(n, ...) bytes, about 9 bytes per
- *   vertex + 12 per layer slot + 8 per chunk key.  codes (dev) ceil(m/32) words, rank (dev)
+ *   vertex + 12 per layer slot + 16 per chunk key (two chunks: one is copied in on a stream of
+ *   the library's own while the records are built from the other).  codes (dev) ceil(m/32) words, rank (dev)
  *   ceil(m/512) samples, as for mphx_mphf_build_u64.
  * Errors: MPHX_EINVAL (bad arguments, n = 0, P > 2^32, layer_slots < n without host_layers),
  * MPHX_ERANGE (a degree above 255), MPHX_ENOMEM (workspace, or a layer larger than the layer

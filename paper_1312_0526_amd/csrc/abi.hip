@@ -1837,6 +1837,8 @@ class HostStager {
     static constexpr size_t kPiece = size_t(1) << 27;  // bytes per staged copy
 
     explicit HostStager(hipStream_t s) : s_(s), lock_(pool().mu) {}
+    // later copies are ordered on stream s (those already made keep their events)
+    void use_stream(hipStream_t s) { s_ = s; }
     ~HostStager()
     {
         for (hipEvent_t& e : ev_)
@@ -2219,7 +2221,7 @@ struct StreamLayout {
     uint8_t* deg;   // degree bytes, then the code bytes of the assignment
     uint64_t* X;    // XOR packs of the other two endpoints
     uint3* slots;   // the layer area
-    uint64_t* stage;  // one chunk of keys
+    uint64_t* stage[2];  // two chunks of keys: one copied in while the other is built from
     uint32_t* bcount;
     void* scan;
     size_t scan_bytes;
@@ -2230,10 +2232,11 @@ struct StreamLayout {
 void layout_stream(Carve& c, uint64_t m, uint64_t chunk_keys, uint64_t layer_slots, StreamLayout& L)
 {
     const uint64_t nblocks = (m + 511) / 512;
-    L.deg = c.take<uint8_t>((m + 3) & ~3ull);
+    L.deg = c.take<uint8_t>((m + 15) & ~15ull);  // whole 16-byte groups for the round scans
     L.X = c.take<uint64_t>(m);
     L.slots = c.take<uint3>(layer_slots);
-    L.stage = c.take<uint64_t>(chunk_keys);
+    L.stage[0] = c.take<uint64_t>(chunk_keys);
+    L.stage[1] = c.take<uint64_t>(chunk_keys);
     L.bcount = c.take<uint32_t>(nblocks);
     L.scan_bytes = scan_scratch_bytes(nblocks);
     L.scan = c.take<uint8_t>(L.scan_bytes);
@@ -2295,10 +2298,29 @@ int mphx_mphf_build_stream_u64(const uint64_t* keys, uint64_t n, uint64_t seed, 
     layout_stream(c, m, chunk_keys, layer_slots, L);
     uint8_t* const hl = static_cast<uint8_t*>(host_layers);
 
+    // Key chunks reach the device on a copy stream of their own, double-buffered, so the
+    // transfer of chunk i + 1 overlaps the record build of chunk i: ready[b] says a buffer
+    // holds its chunk, freed[b] that its build has read it.
+    struct CopyStream {
+        hipStream_t cs = nullptr;
+        hipEvent_t ready[2] = {nullptr, nullptr}, freed[2] = {nullptr, nullptr};
+        ~CopyStream()
+        {
+            if (cs) {
+                (void)hipStreamSynchronize(cs);
+                (void)hipStreamDestroy(cs);
+            }
+            for (hipEvent_t e : {ready[0], ready[1], freed[0], freed[1]})
+                if (e) (void)hipEventDestroy(e);
+        }
+    } cp;
     struct DrainOnExit {
         hipStream_t s;
         ~DrainOnExit() { (void)hipStreamSynchronize(s); }
     } drain{s};
+    HIP_TRY(hipStreamCreateWithFlags(&cp.cs, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&cp.ready[0], &cp.ready[1], &cp.freed[0], &cp.freed[1]})
+        HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     HostStager stager(s);  // host key chunks (and spilled layers) go through its pinned buffers
 
     // per round: where its runs of hinge parts 0, 1, 2 start, and where it ends (device
@@ -2310,16 +2332,25 @@ int mphx_mphf_build_stream_u64(const uint64_t* keys, uint64_t n, uint64_t seed, 
     uint32_t t = 0;
     for (t = 0; t < max_tries && !done; t++) {
         const uint64_t sd = seed + t;
-        HIP_TRY(launch_zero(L.deg, (m + 3) & ~3ull, s));
+        HIP_TRY(launch_zero(L.deg, (m + 15) & ~15ull, s));
         HIP_TRY(launch_zero(L.X, m * sizeof(uint64_t), s));
         HIP_TRY(launch_zero(L.ctrl, sizeof(Ctrl), s));
         {
             Timed tm(PH_BUILD, s);
-            for (uint64_t c0 = 0; c0 < n; c0 += chunk_keys) {
+            stager.use_stream(cp.cs);
+            HIP_TRY(hipEventRecord(cp.freed[0], s));
+            HIP_TRY(hipEventRecord(cp.freed[1], s));
+            for (uint64_t c0 = 0, i = 0; c0 < n; c0 += chunk_keys, i++) {
                 const uint64_t cn = std::min(chunk_keys, n - c0);
-                HIP_TRY(stager.copy(L.stage, keys + c0, cn * sizeof(uint64_t)));
-                HIP_TRY(launch_st_build(L.stage, cn, sd, P, L.deg, L.X, L.ctrl, s));
+                const int b = (int)(i & 1);
+                HIP_TRY(hipStreamWaitEvent(cp.cs, cp.freed[b], 0));
+                HIP_TRY(stager.copy(L.stage[b], keys + c0, cn * sizeof(uint64_t)));
+                HIP_TRY(hipEventRecord(cp.ready[b], cp.cs));
+                HIP_TRY(hipStreamWaitEvent(s, cp.ready[b], 0));
+                HIP_TRY(launch_st_build(L.stage[b], cn, sd, P, L.deg, L.X, L.ctrl, s));
+                HIP_TRY(hipEventRecord(cp.freed[b], s));
             }
+            stager.use_stream(s);  // the build waited for every copy; later copies go on s
         }
         Ctrl h;
         int rc = read_ctrl(L.ctrl, h, s);

@@ -75,54 +75,137 @@ __global__ __launch_bounds__(kStBlock) void k_st_build(const uint64_t* __restric
 }
 
 // Round start, part k: every vertex of degree 1 whose edge has no degree-1 vertex in a lower
-// part appends the edge hinge first.  Each thread looks at four consecutive vertices (one
-// 32-bit word of degrees) per pass; the appends gather in an LDS buffer and go out with one
-// cursor atomic per buffer (all hinges of a round append to one cursor, whose atomics
-// serialise: one per wave would cost far more than the scan).
-using StAppender = BlockAppender<uint3, kStBlock, 8 * kStBlock>;
+// part appends the edge hinge first.  The degree bytes are scanned 64 per thread per pass (four
+// coalesced 16-byte groups), bytes equal to 1 found with word arithmetic, and only those
+// vertices read their pack; a thread keeps a 64-bit mask of its hinges, one block-wide scan of
+// the mask counts places them, and the slots are staged in LDS and go out with one cursor
+// atomic per full buffer (a pass with more hinges than the buffer reserves its range at once).
+// All hinges of a round append to one cursor, whose atomics serialise, so they stay rare.
+constexpr uint32_t kStScanU = 4;      // 16-byte groups per thread per pass
+constexpr uint32_t kStStage = 2048;   // staged slots per block (24 KB)
+
+// bit 8j + 7 set iff byte j of w equals 1 (exact per byte: no borrow between bytes)
+__device__ __forceinline__ uint32_t bytes_eq1(uint32_t w)
+{
+    const uint32_t y = w ^ 0x01010101u;
+    return ~(((y & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | y) & 0x80808080u;
+}
+// those four flags as bits 0..3
+__device__ __forceinline__ uint32_t flags4(uint32_t f)
+{
+    return ((f >> 7) & 1u) | ((f >> 14) & 2u) | ((f >> 21) & 4u) | ((f >> 28) & 8u);
+}
 
 __global__ __launch_bounds__(kStBlock) void k_st_claim(const uint8_t* __restrict__ deg, const uint64_t* __restrict__ X,
                                                        uint64_t P, uint32_t k, uint3* __restrict__ slots, uint64_t cap,
                                                        unsigned long long* cursor)
 {
-    __shared__ StAppender app;
-    app.init();
-    const uint64_t base = (uint64_t)k * P;
-    const uint64_t words = (P + 3) / 4 + 1;  // the part may start inside a word
-    const uint64_t w_first = base / 4;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    __shared__ uint3 s_buf[kStStage];
+    __shared__ uint32_t s_wsum[kStBlock / kWave];
+    __shared__ uint32_t s_count;
+    __shared__ unsigned long long s_base;
+    const uint32_t tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    if (tid == 0)
+        s_count = 0;
+    const uint64_t base = (uint64_t)k * P, end = base + P;  // the part's vertices
+    const uint64_t g0 = base / 16, g1 = (end + 15) / 16;      // 16-byte groups covering them
+    const uint4* d4 = reinterpret_cast<const uint4*>(deg);
     auto out = [slots, cap](uint64_t i, uint3 sl) {
-        if (i < cap) slots[i] = sl;
+        if (i < cap) slots[i] = sl;  // slots past the area are counted, not stored
     };
-    for (uint64_t wb = (uint64_t)blockIdx.x * blockDim.x; wb < words; wb += stride) {  // uniform per block
-        const uint64_t w = w_first + wb + threadIdx.x;
-        uint32_t dw = 0;
-        if (wb + threadIdx.x < words && 4 * w < base + P)
-            dw = reinterpret_cast<const uint32_t*>(deg)[w];
-        bool hinge[4] = {false, false, false, false};
-        uint3 sl[4];
+    auto flush = [&]() {
+        __syncthreads();
+        const uint32_t c = s_count;
+        if (tid == 0 && c)
+            s_base = atomicAdd(cursor, (unsigned long long)c);
+        __syncthreads();
+        for (uint32_t i = tid; i < c; i += kStBlock)
+            out(s_base + i, s_buf[i]);
+        __syncthreads();
+        if (tid == 0)
+            s_count = 0;
+        __syncthreads();
+    };
+    // the pack of vertex v as a slot: (id in part k, ids in parts k+1, k+2)
+    auto slot_of = [&](uint64_t v) {
+        const uint64_t x = X[v];
+        return make_uint3((uint32_t)(v - base), (uint32_t)x, (uint32_t)(x >> 32));
+    };
+    constexpr uint64_t kPass = (uint64_t)kStScanU * kStBlock;  // groups per block per pass
+    for (uint64_t gb = g0 + (uint64_t)blockIdx.x * kPass; gb < g1; gb += (uint64_t)gridDim.x * kPass) {  // uniform
+        uint4 w[kStScanU];
 #pragma unroll
-        for (uint32_t j = 0; j < 4; j++) {
-            const uint64_t v = 4 * w + j;
-            sl[j] = make_uint3(0u, 0u, 0u);
-            if (((dw >> (8 * j)) & 255u) == 1u && v >= base && v < base + P) {
-                const uint64_t x = X[v];
-                const uint32_t a = (uint32_t)x, b = (uint32_t)(x >> 32);  // ids in parts k+1, k+2
+        for (uint32_t u = 0; u < kStScanU; u++) {
+            const uint64_t g = gb + u * kStBlock + tid;
+            w[u] = g < g1 ? d4[g] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        uint64_t hm = 0;  // bit 16u + j: byte j of group u is a hinge
+#pragma unroll
+        for (uint32_t u = 0; u < kStScanU; u++) {
+            const uint64_t g = gb + u * kStBlock + tid;
+            uint32_t mk = flags4(bytes_eq1(w[u].x)) | flags4(bytes_eq1(w[u].y)) << 4 |
+                          flags4(bytes_eq1(w[u].z)) << 8 | flags4(bytes_eq1(w[u].w)) << 12;
+            const uint64_t b0 = 16 * g;
+            if (b0 < base)
+                mk &= 0xFFFFu << (uint32_t)(base - b0);
+            if (b0 + 16 > end)
+                mk &= end > b0 ? 0xFFFFu >> (uint32_t)(b0 + 16 - end) : 0u;
+            while (mk) {
+                const uint32_t j = __builtin_ctz(mk);
+                mk &= mk - 1;
+                const uint3 sl = slot_of(b0 + j);
                 bool h = true;
                 if (k >= 1)  // part 0's vertex: b when k = 1, a when k = 2
-                    h = deg[k == 1 ? b : a] != 1;
+                    h = deg[k == 1 ? sl.z : sl.y] != 1;
                 if (k == 2 && h)  // part 1's vertex
-                    h = deg[P + b] != 1;
-                hinge[j] = h;
-                sl[j] = make_uint3((uint32_t)(v - base), a, b);
+                    h = deg[P + sl.z] != 1;
+                if (h)
+                    hm |= 1ull << (16 * u + j);
             }
         }
-        if (__syncthreads_or(hinge[0] | hinge[1] | hinge[2] | hinge[3])) {
-            app.push(hinge[0], sl[0], hinge[1], sl[1], cursor, out);
-            app.push(hinge[2], sl[2], hinge[3], sl[3], cursor, out);
+        // exclusive prefix of the hinge counts over the block, and their total
+        const uint32_t c = __popcll(hm);
+        uint32_t incl = c;
+#pragma unroll
+        for (uint32_t dd = 1; dd < kWave; dd <<= 1) {
+            const uint32_t y = __shfl_up(incl, dd, kWave);
+            incl += lane >= dd ? y : 0u;
         }
+        if (lane == kWave - 1)
+            s_wsum[wv] = incl;
+        __syncthreads();
+        uint32_t pre = incl - c, total = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < kStBlock / kWave; q++) {
+            pre += q < wv ? s_wsum[q] : 0u;
+            total += s_wsum[q];
+        }
+        if (total) {  // uniform
+            if (total > kStStage) {  // more than the buffer: reserve the range directly
+                if (tid == 0)
+                    s_base = atomicAdd(cursor, (unsigned long long)total);
+                __syncthreads();
+                uint64_t at = s_base + pre;
+                for (uint64_t mm = hm; mm; mm &= mm - 1) {
+                    const uint32_t bit = __builtin_ctzll(mm);
+                    out(at++, slot_of(16 * (gb + (bit >> 4) * kStBlock + tid) + (bit & 15)));
+                }
+            } else {
+                if (s_count + total > kStStage)
+                    flush();
+                uint32_t at = s_count + pre;
+                for (uint64_t mm = hm; mm; mm &= mm - 1) {
+                    const uint32_t bit = __builtin_ctzll(mm);
+                    s_buf[at++] = slot_of(16 * (gb + (bit >> 4) * kStBlock + tid) + (bit & 15));
+                }
+                __syncthreads();
+                if (tid == 0)
+                    s_count += total;
+            }
+        }
+        __syncthreads();  // s_wsum, s_base and s_count are reused by the next pass
     }
-    app.flush(cursor, out);  // slots past cap are counted, not stored: the host checks the cursor
+    flush();
 }
 
 // DeleteEdge of every edge of a layer (runs [lo, b1), [b1, b2), [b2, hi) of hinge parts 0, 1, 2).
@@ -229,7 +312,10 @@ hipError_t launch_st_claim(const uint8_t* deg, const uint64_t* X, uint64_t P, ui
 {
     if (P == 0 || k > 2) return hipSuccess;
     (void)ctrl;
-    k_st_claim<<<grid_for_st((P + 3) / 4 + 1, 16384), kStBlock, 0, s>>>(deg, X, P, k, slots, cap, cursor);
+    const uint64_t groups = (k * P + P + 15) / 16 - k * P / 16;
+    const uint64_t passes = (groups + kStScanU * kStBlock - 1) / (kStScanU * kStBlock);
+    k_st_claim<<<(unsigned)std::max<uint64_t>(1, std::min<uint64_t>(passes, 2048)), kStBlock, 0, s>>>(deg, X, P, k,
+                                                                                                   slots, cap, cursor);
     return hipGetLastError();
 }
 
