@@ -584,7 +584,9 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  * Tuning and diagnostics.
  * mphx_set_option / mphx_get_option (process-wide):
  *   "grid"        blocks per launch of the grid-stride peeling kernels (0 = automatic).
- *   "round_batch" peeling rounds enqueued between two checks of the termination flag.
+ *   "round_batch" peeling rounds enqueued before the first check of the termination flag
+ *                 (default 64; later checks come every 16 rounds).  Empty rounds past the end
+ *                 cost a launch each, a check a host round trip.
  *   "timing"      1 = record a HIP event pair on the caller's stream around every kernel
  *                 launch of mphx_peel / mphx_mphf_build_*, accumulated per phase.
  *   "part_build"  1 (default) = mphx_mphf_build_* builds the vertex records by partitioning

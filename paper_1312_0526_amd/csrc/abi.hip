@@ -22,7 +22,9 @@ thread_local std::string g_err;
 
 struct Options {
     std::atomic<int> grid{0};          // 0 = automatic
-    std::atomic<int> round_batch{8};   // rounds between termination checks (first batch)
+    std::atomic<int> round_batch{64};  // rounds before the first termination check; later ones every
+                                       // kLaterBatch (a peel at gamma 1.23 takes 57-64 rounds from
+                                       // 10^5 keys up, so one batch usually covers it)
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
     std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
     std::atomic<int> claim_lists{26};  // claim lists from n >= 2^claim_lists keys on (0 = never);
@@ -240,7 +242,9 @@ unsigned auto_grid(uint64_t work)
     return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 64), 8192);
 }
 
-// Enqueue rounds in growing batches until a round finds an empty layer.  On return
+constexpr uint32_t kLaterBatch = 16;
+
+// Enqueue rounds in batches until a round finds an empty layer.  On return
 // h.nrounds holds the number of non-empty layers and *peeled the number of peeled edges.
 int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
 {
@@ -270,7 +274,7 @@ int run_rounds(PeelState& st, Ctrl& h, uint64_t* peeled, hipStream_t s)
         }
         if (r >= st.rcap)
             return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
-        batch = std::min<uint32_t>(batch * 2, 64);
+        batch = kLaterBatch;
     }
 }
 
@@ -392,7 +396,7 @@ int run_rounds_r(PeelState& st, uint32_t r, Ctrl& h, uint64_t* peeled, hipStream
         }
         if (rd >= st.rcap)
             return fail(MPHX_ERANGE, "more than %llu peeling rounds", (unsigned long long)st.rcap);
-        batch = std::min<uint32_t>(batch * 2, 64);
+        batch = kLaterBatch;
     }
 }
 

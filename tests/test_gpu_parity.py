@@ -31,14 +31,17 @@ def o():
     return oracle.Oracle()
 
 
-@pytest.fixture(params=[(0, 8), (96, 1)], ids=["auto-grid", "small-grid-one-round-batches"])
+@pytest.fixture(params=[(0, None), (96, 1)], ids=["auto-grid", "small-grid-one-round-batches"])
 def record(request, mx):
-    """Launch shapes: automatic grids, and a small fixed grid with a check after every round."""
+    """Launch shapes: automatic grids with the default round batches, and a small fixed grid
+    with a check after the first round."""
+    old = mx.get_option("grid"), mx.get_option("round_batch")
     mx.set_option("grid", request.param[0])
-    mx.set_option("round_batch", request.param[1])
+    if request.param[1] is not None:
+        mx.set_option("round_batch", request.param[1])
     yield request.param
-    mx.set_option("grid", 0)
-    mx.set_option("round_batch", 8)
+    mx.set_option("grid", old[0])
+    mx.set_option("round_batch", old[1])
 
 
 def dev(a):
@@ -337,13 +340,14 @@ def test_mphf_duplicates_inside_large_cores(mx, o):
 def test_mphf_deterministic_across_launch_shapes(mx):
     keys = dev(workloads.u64_keys(300_000, gen_seed=9))
     outs = []
-    for grid, batch in ((0, 8), (64, 1), (1000, 64), (0, 3)):
+    old = mx.get_option("grid"), mx.get_option("round_batch")
+    for grid, batch in ((0, 8), (64, 1), (1000, 64), (0, 3), (0, 200)):
         mx.set_option("grid", grid)
         mx.set_option("round_batch", batch)
         r = mx.mphf_build_u64(keys)
         outs.append((host(r["codes"], np.uint64), host(r["rank"], np.uint64)))
-    mx.set_option("grid", 0)
-    mx.set_option("round_batch", 8)
+    mx.set_option("grid", old[0])
+    mx.set_option("round_batch", old[1])
     for c, r in outs[1:]:
         assert np.array_equal(c, outs[0][0]) and np.array_equal(r, outs[0][1])
 
