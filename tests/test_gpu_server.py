@@ -175,3 +175,30 @@ def test_small_requests_pass_a_blocked_head_a_bounded_number_of_times(mx):
     a = mx.mphf_build_u64(smalls[-1], seed=40 + k - 1)
     assert np.array_equal(rs[-1]["codes"].cpu().numpy(), a["codes"].cpu().numpy())
     srv.close()
+
+
+def test_shutdown_with_queued_requests_waits_for_the_running_build_only(mx):
+    """Destroying the server with requests still queued completes them with MPHX_ECANCELED
+    instead of building them: it returns once the build already admitted is done."""
+    import time
+
+    import torch
+
+    n, k = 60_000_000, 16
+    ws = mx.mphf_workspace_bytes(n)
+    keys = [_dev(workloads.u64_keys(n, gen_seed=70 + i)) for i in range(k)]
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        mx.mphf_build_u64(keys[0])
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    t_one = sorted(times)[1]
+    srv = mx.Server(hbm_budget=(ws + 255) // 256 * 256 + 4096, slots=1, batch_max_keys=0)
+    for i, x in enumerate(keys):
+        srv.submit_u64(x, seed=i)
+    assert srv.stats()["pending"] >= k // 2
+    t0 = time.perf_counter()
+    srv.close()
+    t_close = time.perf_counter() - t0
+    assert t_close < 3 * t_one, (t_close, t_one)  # building the queue would take about k t_one
