@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kStBlock) void k_st_build(const uint64_t* __restric
 // part appends the edge hinge first.  The degree bytes are scanned 64 per thread per pass (four
 // coalesced 16-byte groups), bytes equal to 1 found with word arithmetic, and only those
 // vertices read their pack; a thread keeps a 64-bit mask of its hinges, one block-wide scan of
-// the mask counts places them, and the slots are staged in LDS and go out with one cursor
+// the masks' bit counts gives every hinge its place, and the slots are staged in LDS and go out with one cursor
 // atomic per full buffer (a pass with more hinges than the buffer reserves its range at once).
 // All hinges of a round append to one cursor, whose atomics serialise, so they stay rare.
 constexpr uint32_t kStScanU = 4;      // 16-byte groups per thread per pass
