@@ -478,6 +478,14 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             L.lstart[0] = 0;
         __syncthreads();
         uint32_t r = 0, lo = 0;
+        // whether the current layer's slots carry their hinge part in .y (layers resolved from
+        // claim lists); else it is read from the edge state
+        bool hinge_in_slot = false;
+        auto hinge_of = [&](uint32_t i, uint32_t& e) {
+            const uint3 s0 = L.slots[i];
+            e = s0.x;
+            return hinge_in_slot ? (s0.y & 3u) : (S::ld(L.state + e) & 3u);
+        };
         for (;;) {
             // Layer r is [lo, hi).  Applying it claims round r + 1 at once: a vertex taken to
             // degree 1 claims its remaining edge, which is final unless that edge also leaves
@@ -503,7 +511,8 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     s_cnt[b] = 0;
                 __syncthreads();
                 for (uint32_t i = lo + tid; i < hi; i += kBlock) {
-                    const uint32_t e = L.slots[i].x, h = S::ld(L.state + e) & 3u;
+                    uint32_t e;
+                    const uint32_t h = hinge_of(i, e);
                     const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     atomicAdd(&s_cnt[(h == 0 ? ev.y : (h == 1 ? ev.z : ev.x)) / kBatchTile], 1u);
                     atomicAdd(&s_cnt[(h == 0 ? ev.z : (h == 1 ? ev.x : ev.y)) / kBatchTile], 1u);
@@ -516,7 +525,8 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     s_bnd[mt] = L2;
                 __syncthreads();
                 for (uint32_t i = lo + tid; i < hi; i += kBlock) {
-                    const uint32_t e = L.slots[i].x, h = S::ld(L.state + e) & 3u;
+                    uint32_t e;
+                    const uint32_t h = hinge_of(i, e);
                     const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
@@ -558,6 +568,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 }
                 lo = hi;
                 r++;
+                hinge_in_slot = false;  // the next layer was claimed by atomicMin
                 continue;
             }
             // A sparse layer of a bucket given by key words (whose edge area is free) may claim
@@ -583,8 +594,8 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     uint2 c0 = make_uint2(0u, 0u), c1 = make_uint2(0u, 0u);
                     bool f0 = false, f1 = false;
                     if (i < hi) {
-                        const uint32_t e = L.slots[i].x;
-                        const uint32_t h = S::ld(L.state + e) & 3u;
+                        uint32_t e;
+                        const uint32_t h = hinge_of(i, e);
                         const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                         const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                         const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
@@ -646,23 +657,25 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     for (uint32_t base = j0; base < j1; base += kBlock) {
                         const uint32_t j = base + tid;
                         bool win = false;
-                        uint32_t c = 0;
+                        uint32_t c = 0, c_part = 0;
                         if (j < j1) {
                             const uint2 cc = cg[j];
                             const uint32_t bits = (tab[(cc.x % kClTile) >> 2] >> (8 * (cc.x & 3))) & 7u;
                             win = bits != 0 && (uint32_t)__builtin_ctz(bits) == cc.y;
                             c = cc.x;
+                            c_part = cc.y;
                             if (win)
                                 L.state[c] = rr | cc.y;
                         }
                         const uint32_t pos = block_append(&s_ltail, win, false);
                         if (win)
-                            L.slots[pos].x = c;
+                            L.slots[pos] = make_uint3(c, c_part, 0u);
                     }
                     __syncthreads();
                 }
                 lo = hi;
                 r++;
+                hinge_in_slot = true;  // the resolve wrote each slot's hinge part
                 continue;
             }
             for (uint32_t base = lo; base < hi; base += kBlock) {
@@ -670,8 +683,8 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 uint32_t c0 = 0, c1 = 0;
                 bool f0 = false, f1 = false;
                 if (i < hi) {
-                    uint32_t e = L.slots[i].x;
-                    uint32_t h = S::ld(L.state + e) & 3u;
+                    uint32_t e;
+                    uint32_t h = hinge_of(i, e);
                     uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
@@ -702,6 +715,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             __syncthreads();
             lo = hi;
             r++;
+            hinge_in_slot = false;  // the next layer was claimed by atomicMin
         }
         nrounds = r;
         const bool all = s_ltail == n;
