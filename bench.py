@@ -1578,6 +1578,9 @@ def main() -> int:
     else:
         del data, offs
     torch.cuda.empty_cache()
+    # the batched and served legs read no phase times: no per-launch event pairs (they would
+    # slow the plain builds that serve as their comparators and the server's workers)
+    mx.set_option("timing", 0)
     batched = batched_leg(args, mx, torch, np, workloads) if "batched" in legs else None
     served = served_leg(args, mx, torch, np, workloads) if "served" in legs else None
     hem_host = hem_host_leg(args, mx, torch) if "hem_host" in legs else None
