@@ -618,10 +618,11 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 device atomics; 0 = never.  The same codes either way.
  *   "batch_claim_lists" 0 or 1 (default 1): in the batched kernel, the other layers of such
  *                 a bucket (those of at most 3n/8 edges: with sorted deletes off, all) record
- *                 their next-layer claims in a list that is grouped by tile of edges and
- *                 resolved in LDS, which also writes each winner's hinge part into its layer
- *                 slot, instead of one device atomicMin per claim and a state read per edge
- *                 in the next round; 0 = atomicMin.  The same codes either way.
+ *                 their next-layer claims (and cancels of claims made stale within the
+ *                 round) in a list that is grouped by tile of edges and resolved in LDS,
+ *                 which also writes each winner's hinge part into its layer slot, instead
+ *                 of one device atomicMin per claim and a state read per edge in the next
+ *                 round; 0 = atomicMin.  The same codes either way.
  *   "hem_block"   256, 512 or 1024 (default 1024): workgroup size of the batched kernel that
  *                 builds the HEM split's buckets (mphx_hem_build_*, mphx_hem_build_host_*).
  *   "hem_grid"    0..65536 (default 0 = one workgroup per compute unit): its persistent grid.

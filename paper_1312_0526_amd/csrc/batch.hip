@@ -574,11 +574,15 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             // A sparse layer of a bucket given by key words (whose edge area is free) may claim
             // through a list instead of atomicMin on the states, the plain path's claim lists
             // inside the workgroup: every delete that leaves a vertex at degree 1 records
-            // (remaining edge, the vertex's part); the records are grouped by tile of kClTile
-            // edges and each tile resolved in an LDS byte per edge (a bit per claiming part).
-            // A claim counts only while its edge is unclaimed (an edge already in a layer,
-            // this one included, keeps its state), and the lowest claiming part is the hinge:
-            // exactly the layer and hinges atomicMin gives.
+            // (remaining edge, the vertex's part), and one that leaves it at degree 0 records a
+            // cancel (its own edge, 4 | the vertex's part): the vertex fell 2 -> 1 -> 0 in this
+            // round, so its claim named this edge, which leaves now.  The records are grouped
+            // by tile of kClTile edges and each tile resolved in an LDS byte per edge (claim
+            // bits 0..2, cancel bits 4..6): the lowest part claimed and not cancelled is the
+            // hinge -- exactly the layer and hinges atomicMin gives.  The winner's slot gets
+            // (edge, hinge | parts at degree 1 << 8): the next round reads the hinge there and
+            // skips the deletes at the other degree-1 vertices, which drop to 0 and are never
+            // read again.  The states are still written for rounds that claim by atomicMin.
             constexpr uint32_t kClTile = kBatchTile * 8;  // edges per tile: one LDS byte each
             const uint32_t ncl = (n + kClTile - 1) / kClTile;
             if (a.claim_lists && d.keys && 8ull * (hi - lo) <= 3ull * n && ncl <= kBatchMaxBuckets) {
@@ -594,21 +598,31 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     uint2 c0 = make_uint2(0u, 0u), c1 = make_uint2(0u, 0u);
                     bool f0 = false, f1 = false;
                     if (i < hi) {
-                        uint32_t e;
-                        const uint32_t h = hinge_of(i, e);
+                        const uint3 s0 = L.slots[i];
+                        const uint32_t e = s0.x;
+                        const uint32_t h = hinge_in_slot ? (s0.y & 3u) : (S::ld(L.state + e) & 3u);
+                        const uint32_t ones = hinge_in_slot ? (s0.y >> 8) & 7u : 0u;
                         const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                         const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                         const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
                         const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
                         L.slots[i] = make_uint3(vh, va, vb);
-                        const uint64_t oa = S::rec_del(L.rec, va, e);
-                        const uint64_t ob = S::rec_del(L.rec, vb, e);
+                        const uint32_t pa = h == 2 ? 0u : h + 1, pb = h == 0 ? 2u : h - 1;  // parts of va, vb
+                        const bool sa = (ones >> pa) & 1u, sb = (ones >> pb) & 1u;
+                        const uint64_t oa = sa ? Rec::kOne : S::rec_del(L.rec, va, e);
+                        const uint64_t ob = sb ? Rec::kOne : S::rec_del(L.rec, vb, e);
                         if (Rec::deg(oa) == 2) {
-                            c0 = make_uint2((uint32_t)(Rec::edge(oa) - e), part_of(va, P));
+                            c0 = make_uint2((uint32_t)(Rec::edge(oa) - e), pa);
+                            f0 = true;
+                        } else if (Rec::deg(oa) == 1 && !sa) {
+                            c0 = make_uint2(e, 4u | pa);
                             f0 = true;
                         }
                         if (Rec::deg(ob) == 2) {
-                            c1 = make_uint2((uint32_t)(Rec::edge(ob) - e), part_of(vb, P));
+                            c1 = make_uint2((uint32_t)(Rec::edge(ob) - e), pb);
+                            f1 = true;
+                        } else if (Rec::deg(ob) == 1 && !sb) {
+                            c1 = make_uint2(e, 4u | pb);
                             f1 = true;
                         }
                         if (!f0) {  // the first requested slot holds the first record
@@ -650,32 +664,32 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     __syncthreads();
                     for (uint32_t j = j0 + tid; j < j1; j += kBlock) {
                         const uint2 c = cg[j];
-                        if (S::ld(L.state + c.x) == kUnclaimed)
-                            atomicOr(&tab[(c.x % kClTile) >> 2], 1u << (8 * (c.x & 3) + c.y));
+                        atomicOr(&tab[(c.x % kClTile) >> 2], 1u << (8 * (c.x & 3) + c.y));
                     }
                     __syncthreads();
                     for (uint32_t base = j0; base < j1; base += kBlock) {
                         const uint32_t j = base + tid;
                         bool win = false;
-                        uint32_t c = 0, c_part = 0;
+                        uint32_t c = 0, hinge_word = 0;
                         if (j < j1) {
                             const uint2 cc = cg[j];
-                            const uint32_t bits = (tab[(cc.x % kClTile) >> 2] >> (8 * (cc.x & 3))) & 7u;
-                            win = bits != 0 && (uint32_t)__builtin_ctz(bits) == cc.y;
+                            const uint32_t t = tab[(cc.x % kClTile) >> 2] >> (8 * (cc.x & 3));
+                            const uint32_t live = t & ~(t >> 4) & 7u;
+                            win = cc.y < 4 && live != 0 && (uint32_t)__builtin_ctz(live) == cc.y;
                             c = cc.x;
-                            c_part = cc.y;
+                            hinge_word = cc.y | live << 8;
                             if (win)
                                 L.state[c] = rr | cc.y;
                         }
                         const uint32_t pos = block_append(&s_ltail, win, false);
                         if (win)
-                            L.slots[pos] = make_uint3(c, c_part, 0u);
+                            L.slots[pos] = make_uint3(c, hinge_word, 0u);
                     }
                     __syncthreads();
                 }
                 lo = hi;
                 r++;
-                hinge_in_slot = true;  // the resolve wrote each slot's hinge part
+                hinge_in_slot = true;  // the resolve wrote each slot's hinge and degree-1 parts
                 continue;
             }
             for (uint32_t base = lo; base < hi; base += kBlock) {
