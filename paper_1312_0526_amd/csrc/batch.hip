@@ -504,8 +504,22 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             // records are loaded into LDS, the deletes applied with LDS atomics (the same old
             // (degree, sum) per delete, hence the same claims) and the tile written back.
             const uint32_t L2 = 2 * (hi - lo), mt = (m + kBatchTile - 1) / kBatchTile;
-            if (a.sort_div && d.keys && (uint64_t)L2 * a.sort_div >= m && (uint64_t)L2 <= 3ull * n / 2 &&
-                mt <= kBatchMaxBuckets) {
+            constexpr uint32_t kClTile = kBatchTile * 8;  // claim-list tile: edges, one LDS byte each
+            const uint32_t ncl = (n + kClTile - 1) / kClTile;
+            const bool sorted_round = a.sort_div && d.keys && (uint64_t)L2 * a.sort_div >= m &&
+                                      (uint64_t)L2 <= 3ull * n / 2 && mt <= kBatchMaxBuckets;
+            const bool list_round = !sorted_round && a.claim_lists && d.keys && 8ull * (hi - lo) <= 3ull * n &&
+                                    ncl <= kBatchMaxBuckets;
+            if (!list_round && hinge_in_slot) {
+                // a layer resolved from claim lists left the states alone; the claims by
+                // atomicMin below must find its edges taken, so they get their states now
+                for (uint32_t i = lo + tid; i < hi; i += kBlock) {
+                    const uint3 s0 = L.slots[i];
+                    L.state[s0.x] = (r << 2) | (s0.y & 3u);
+                }
+                __syncthreads();
+            }
+            if (sorted_round) {
                 uint2* dl = reinterpret_cast<uint2*>(L.edges);  // 12n bytes: up to 1.5n deletes
                 for (uint32_t b = tid; b < mt; b += kBlock)
                     s_cnt[b] = 0;
@@ -582,10 +596,9 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             // hinge -- exactly the layer and hinges atomicMin gives.  The winner's slot gets
             // (edge, hinge | parts at degree 1 << 8): the next round reads the hinge there and
             // skips the deletes at the other degree-1 vertices, which drop to 0 and are never
-            // read again.  The states are still written for rounds that claim by atomicMin.
-            constexpr uint32_t kClTile = kBatchTile * 8;  // edges per tile: one LDS byte each
-            const uint32_t ncl = (n + kClTile - 1) / kClTile;
-            if (a.claim_lists && d.keys && 8ull * (hi - lo) <= 3ull * n && ncl <= kBatchMaxBuckets) {
+            // read again.  No state is read or written; a later round that claims by atomicMin
+            // first gives its layer's edges their states (above).
+            if (list_round) {
                 uint2* cl = reinterpret_cast<uint2*>(L.edges);  // 12n bytes: claims, then grouped
                 uint2* cg = cl + 2 * (hi - lo);                 // at most two per layer edge each
                 if (tid == 0)
@@ -678,8 +691,6 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                             win = cc.y < 4 && live != 0 && (uint32_t)__builtin_ctz(live) == cc.y;
                             c = cc.x;
                             hinge_word = cc.y | live << 8;
-                            if (win)
-                                L.state[c] = rr | cc.y;
                         }
                         const uint32_t pos = block_append(&s_ltail, win, false);
                         if (win)
