@@ -299,6 +299,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
     using S = Sc<kScope>;
     constexpr uint32_t kBatchTile = batch_tile<kBlock>();
     __shared__ uint32_t s_ltail, s_err, s_degsum, s_ctail;
+    __shared__ uint32_t s_l0part[3];  // where layer 0's appends of parts 0, 1, 2 end
     __shared__ uint32_t s_wtot[kBlock / kWave];
     unsigned long long* s_tab = reinterpret_cast<unsigned long long*>(lds);  // kBatchTile records
     uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_tab + kBatchTile);       // kBatchMaxBuckets
@@ -325,6 +326,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
     uint64_t sd = d.seed;
     for (t = 0; t < a.max_tries; t++) {
         sd = d.seed + t;
+        bool l0_in_slot = false;  // layer 0's slots carry their hinge part (partitioned build)
         for (uint32_t e = tid; e < n; e += kBlock)
             L.state[e] = kUnclaimed;
         if (tid == 0) {
@@ -423,20 +425,23 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     if (s_degsum != n)
                         s_err = 1;
                     s_degsum = 0;
+                    s_l0part[k] = s_ltail;
                 }
                 __syncthreads();
             }
-            // Layer 0 moves to the front of the slots.  Slot j overwrites staged entries at
-            // most j, so a block-wide chunk is read in full before any of it is written.
+            // Layer 0 moves to the front of the slots, each slot with its hinge part (the
+            // appends came part by part).  Slot j overwrites staged entries at most j, so a
+            // block-wide chunk is read in full before any of it is written.
             const uint32_t l0 = min(s_ltail, n);
             for (uint32_t base = 0; base < l0; base += kBlock) {
                 const uint32_t j = base + tid;
                 const uint32_t e = j < l0 ? stage[j] : 0u;
                 __syncthreads();
                 if (j < l0)
-                    L.slots[j].x = e;
+                    L.slots[j] = make_uint3(e, j < s_l0part[0] ? 0u : (j < s_l0part[1] ? 1u : 2u), 0u);
                 __syncthreads();
             }
+            l0_in_slot = true;
         } else {
             // very large bucket: records with device atomics, round 0 with atomicMin
             for (uint32_t v = tid; v < m; v += kBlock)
@@ -478,9 +483,10 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             L.lstart[0] = 0;
         __syncthreads();
         uint32_t r = 0, lo = 0;
-        // whether the current layer's slots carry their hinge part in .y (layers resolved from
-        // claim lists); else it is read from the edge state
-        bool hinge_in_slot = false;
+        // whether the current layer's slots carry their hinge part in .y (layer 0 from the
+        // partitioned record build, layers resolved from claim lists); else it is read from
+        // the edge state
+        bool hinge_in_slot = l0_in_slot;
         auto hinge_of = [&](uint32_t i, uint32_t& e) {
             const uint3 s0 = L.slots[i];
             e = s0.x;
