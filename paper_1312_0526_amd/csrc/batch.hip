@@ -232,6 +232,16 @@ __device__ __forceinline__ uint32_t bucket_local(const BatchArgs& a, const Bucke
     return (k == 0 ? ev.x : (k == 1 ? ev.y : ev.z)) - (uint32_t)(k * P);
 }
 
+// The three part-local vertices of key i of a bucket given by key words (bucket_local for k = 0, 1, 2).
+__device__ __forceinline__ uint3 word_key_locals(const BatchArgs& a, const BucketDesc& d, uint32_t i, uint64_t sd,
+                                                 uint64_t P)
+{
+    uint64_t x, y;
+    key_digest(a, d, i, sd, x, y);
+    return make_uint3((uint32_t)range_reduce(fin(x + kGamma), P), (uint32_t)range_reduce(fin(x + 2 * kGamma), P),
+                      (uint32_t)range_reduce(fin(y + 3 * kGamma), P));
+}
+
 // Edge of key i of a bucket: recomputed for keys given by words, stored for string keys.
 __device__ __forceinline__ uint3 bucket_edge(const BatchArgs& a, const BucketDesc& d, const SlotLayout& L, uint32_t i,
                                              uint64_t sd, uint64_t P)
@@ -345,12 +355,107 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
         }
         __syncthreads();
         const uint32_t nbk = (uint32_t)((P + kBatchTile - 1) / kBatchTile);
-        if (nbk <= kBatchMaxBuckets) {
+        // Records of part k's tile at v0 (cnt vertices, accumulated in s_tab) written once; round
+        // 0 rides along: a vertex of degree 1 in part k claims its edge unless a lower part
+        // already did, so the hinge is the lowest part and each edge enters layer 0 once (the
+        // parts run in order).  The claimed edges are appended to stage.
+        auto write_tile = [&](uint32_t k, uint64_t v0, uint32_t cnt, uint32_t* stage, uint32_t& degsum) {
+            for (uint32_t base = 0; base < cnt; base += kBlock) {
+                const uint32_t v = base + tid;
+                bool first = false;
+                uint32_t e = 0;
+                if (v < cnt) {
+                    const uint64_t x = s_tab[v];
+                    const uint32_t dg = Rec::deg(x);
+                    degsum += dg;
+                    if (dg > kMaxDegree)
+                        s_err = 1;
+                    L.rec[(uint64_t)k * P + v0 + v] = x;
+                    if (dg == 1 && Rec::edge(x) < n) {
+                        e = Rec::edge(x);
+                        first = k == 0 || L.state[e] == kUnclaimed;
+                        if (first)
+                            L.state[e] = k;
+                    }
+                }
+                const uint32_t pos = block_append(&s_ltail, first, false);
+                if (first && pos < n)  // more only from wrapped records, flagged below
+                    stage[pos] = e;
+            }
+        };
+        // every degree field of part k at most 255 and their total n (no field wrapped); the
+        // end of part k's layer-0 appends
+        auto close_part = [&](uint32_t k, uint32_t degsum) {
+            if (degsum)
+                atomicAdd(&s_degsum, degsum);
+            __syncthreads();
+            if (tid == 0) {
+                if (s_degsum != n)
+                    s_err = 1;
+                s_degsum = 0;
+                s_l0part[k] = s_ltail;
+            }
+            __syncthreads();
+        };
+        constexpr uint32_t kPackBits = 12, kPackTile = 1u << kPackBits;
+        const uint32_t nbp = (uint32_t)((P + kPackTile - 1) / kPackTile);
+        if (d.keys && n <= (1u << (32 - kPackBits)) && 3 * nbp <= kBatchMaxBuckets) {
+            // Keys given by words: all three parts partitioned in one pass.  Each key's three
+            // (vertex in tile, key) pairs are packed in a word (12 + 20 bits) and grouped by
+            // (part, tile of kPackTile vertices); the keys are read and hashed twice in all.
+            // The pairs (12n bytes) fill the slot area, layer 0 is staged in the free edge area.
+            uint32_t* pairs = reinterpret_cast<uint32_t*>(L.slots);
+            uint32_t* stage = reinterpret_cast<uint32_t*>(L.edges);
+            for (uint32_t b = tid; b < 3 * nbp; b += kBlock)
+                s_cnt[b] = 0;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += kBlock) {
+                const uint3 u = word_key_locals(a, d, i, sd, P);
+                atomicAdd(&s_cnt[u.x >> kPackBits], 1u);
+                atomicAdd(&s_cnt[nbp + (u.y >> kPackBits)], 1u);
+                atomicAdd(&s_cnt[2 * nbp + (u.z >> kPackBits)], 1u);
+            }
+            __syncthreads();
+            lds_exclusive_scan<kBlock>(s_cnt, 3 * nbp, s_wtot);
+            for (uint32_t b = tid; b < 3 * nbp; b += kBlock)
+                s_bnd[b] = s_cnt[b];
+            if (tid == 0)
+                s_bnd[3 * nbp] = 3 * n;
+            __syncthreads();
+            for (uint32_t i = tid; i < n; i += kBlock) {
+                const uint3 u = word_key_locals(a, d, i, sd, P);
+                const uint32_t hi_i = i << kPackBits;
+                pairs[atomicAdd(&s_cnt[u.x >> kPackBits], 1u)] = hi_i | (u.x & (kPackTile - 1));
+                pairs[atomicAdd(&s_cnt[nbp + (u.y >> kPackBits)], 1u)] = hi_i | (u.y & (kPackTile - 1));
+                pairs[atomicAdd(&s_cnt[2 * nbp + (u.z >> kPackBits)], 1u)] = hi_i | (u.z & (kPackTile - 1));
+            }
+            __syncthreads();
+            for (uint32_t k = 0; k < 3; k++) {
+                uint32_t degsum = 0;
+                for (uint32_t b = 0; b < nbp; b++) {
+                    for (uint32_t v = tid; v < kPackTile; v += kBlock)
+                        s_tab[v] = 0;
+                    __syncthreads();
+                    for (uint32_t j = s_bnd[k * nbp + b] + tid; j < s_bnd[k * nbp + b + 1]; j += kBlock) {
+                        const uint32_t pr = pairs[j];
+                        atomicAdd(&s_tab[pr & (kPackTile - 1)], (unsigned long long)(Rec::kOne + (pr >> kPackBits)));
+                    }
+                    __syncthreads();
+                    const uint64_t v0 = (uint64_t)b * kPackTile;
+                    write_tile(k, v0, (uint32_t)min<uint64_t>(kPackTile, P - v0), stage, degsum);
+                    __syncthreads();
+                }
+                close_part(k, degsum);
+            }
+            // layer 0 to the front of the slots, each slot with its hinge part
+            const uint32_t l0 = min(s_ltail, n);
+            for (uint32_t j = tid; j < l0; j += kBlock)
+                L.slots[j] = make_uint3(stage[j], j < s_l0part[0] ? 0u : (j < s_l0part[1] ? 1u : 2u), 0u);
+            l0_in_slot = true;
+        } else if (nbk <= kBatchMaxBuckets) {
             // Records part by part without device atomics: the part's (vertex, key) pairs are
             // grouped by tile of kBatchTile vertices (LDS counts, one scatter into the slot
-            // area), each tile accumulated in LDS and written once.  Round 0 rides along: a
-            // vertex of degree 1 in part k claims its edge unless a lower part already did, so
-            // the hinge is the lowest part and each edge enters layer 0 once.
+            // area), each tile accumulated in LDS and written once.
             // The slot area (12n bytes) holds the pairs (8n) and, behind them, layer 0 (4n).
             uint2* pairs = reinterpret_cast<uint2*>(L.slots);
             uint32_t* stage = reinterpret_cast<uint32_t*>(pairs + n);
@@ -392,42 +497,10 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     }
                     __syncthreads();
                     const uint64_t v0 = (uint64_t)b * kBatchTile;
-                    const uint32_t cnt = (uint32_t)min<uint64_t>(kBatchTile, P - v0);
-                    for (uint32_t base = 0; base < cnt; base += kBlock) {
-                        const uint32_t v = base + tid;
-                        bool first = false;
-                        uint32_t e = 0;
-                        if (v < cnt) {
-                            const uint64_t x = s_tab[v];
-                            const uint32_t dg = Rec::deg(x);
-                            degsum += dg;
-                            if (dg > kMaxDegree)
-                                s_err = 1;
-                            L.rec[(uint64_t)k * P + v0 + v] = x;
-                            if (dg == 1 && Rec::edge(x) < n) {
-                                e = Rec::edge(x);
-                                first = k == 0 || L.state[e] == kUnclaimed;
-                                if (first)
-                                    L.state[e] = k;
-                            }
-                        }
-                        const uint32_t pos = block_append(&s_ltail, first, false);
-                        if (first && pos < n)  // more only from wrapped records, flagged below
-                            stage[pos] = e;
-                    }
+                    write_tile(k, v0, (uint32_t)min<uint64_t>(kBatchTile, P - v0), stage, degsum);
                     __syncthreads();
                 }
-                // every degree field at most 255 and their total n (no field wrapped)
-                if (degsum)
-                    atomicAdd(&s_degsum, degsum);
-                __syncthreads();
-                if (tid == 0) {
-                    if (s_degsum != n)
-                        s_err = 1;
-                    s_degsum = 0;
-                    s_l0part[k] = s_ltail;
-                }
-                __syncthreads();
+                close_part(k, degsum);
             }
             // Layer 0 moves to the front of the slots, each slot with its hinge part (the
             // appends came part by part).  Slot j overwrites staged entries at most j, so a
@@ -662,6 +735,60 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 }
                 __syncthreads();
                 const uint32_t nc = s_ctail;
+                if (nc <= kBatchTile / 2) {
+                    // Few records (a sparse round): resolve them in one LDS hash table keyed by
+                    // edge, at most half full (open addressing, linear probing), instead of
+                    // grouping them by tile -- the same bits per edge, so the same winners.
+                    uint32_t* hkey = reinterpret_cast<uint32_t*>(s_tab);
+                    uint32_t* hbits = hkey + kBatchTile;
+                    uint32_t lg = 6;
+                    while ((1u << lg) < 2 * nc)
+                        lg++;
+                    const uint32_t mask = (1u << lg) - 1;
+                    for (uint32_t j = tid; j <= mask; j += kBlock) {
+                        hkey[j] = kUnclaimed;
+                        hbits[j] = 0u;
+                    }
+                    __syncthreads();
+                    for (uint32_t j = tid; j < nc; j += kBlock) {
+                        const uint2 c = cl[j];
+                        uint32_t h = (c.x * 0x9E3779B1u) >> (32 - lg);
+                        for (;;) {
+                            const uint32_t old = atomicCAS(&hkey[h], kUnclaimed, c.x);
+                            if (old == kUnclaimed || old == c.x)
+                                break;
+                            h = (h + 1) & mask;
+                        }
+                        atomicOr(&hbits[h], 1u << c.y);
+                    }
+                    __syncthreads();
+                    for (uint32_t base = 0; base < nc; base += kBlock) {
+                        const uint32_t j = base + tid;
+                        bool win = false;
+                        uint32_t c = 0, hinge_word = 0;
+                        if (j < nc) {
+                            const uint2 cc = cl[j];
+                            if (cc.y < 4) {
+                                uint32_t h = (cc.x * 0x9E3779B1u) >> (32 - lg);
+                                while (hkey[h] != cc.x)
+                                    h = (h + 1) & mask;
+                                const uint32_t t = hbits[h];
+                                const uint32_t live = t & ~(t >> 4) & 7u;
+                                win = live != 0 && (uint32_t)__builtin_ctz(live) == cc.y;
+                                c = cc.x;
+                                hinge_word = cc.y | live << 8;
+                            }
+                        }
+                        const uint32_t pos = block_append(&s_ltail, win, false);
+                        if (win)
+                            L.slots[pos] = make_uint3(c, hinge_word, 0u);
+                    }
+                    __syncthreads();
+                    lo = hi;
+                    r++;
+                    hinge_in_slot = true;
+                    continue;
+                }
                 lds_exclusive_scan<kBlock>(s_cnt, ncl, s_wtot);
                 for (uint32_t b = tid; b < ncl; b += kBlock)
                     s_bnd[b] = s_cnt[b];
