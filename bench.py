@@ -581,6 +581,7 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     extra_tries = int(res["tries"].sum() - len(res))
     log(f"[batched] median {sec * 1000:.1f} ms/step, {ok_keys / sec / 1e9:.3f} G keys/s, "
         f"{int((~ok).sum())} failed buckets, {extra_tries} retries")
+    clock = batch_clock_step(mx, torch, bb, keys)
     # the plain path (one mphf_build_u64 per bucket) on a random sample of the same buckets,
     # with one workspace and one pair of output buffers allocated before timing (sized for the
     # sample's largest bucket), so the calls time the build, not allocation
@@ -622,10 +623,48 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
                                             "and outputs (no allocation in the timed calls)",
                                        by_size=dict((k, dict(buckets=v[2], keys_per_s=round(v[0] / v[1], 1)))
                                                     for k, v in sorted(by_class.items()))),
-               speedup_vs_plain=round(ok_keys / sec / plain_rate, 2), oracle_all_core=oracle_all_core_c4())
+               speedup_vs_plain=round(ok_keys / sec / plain_rate, 2), oracle_all_core=oracle_all_core_c4(),
+               phase_clock=clock)
     del bb, keys
     torch.cuda.empty_cache()
     return out
+
+
+BATCH_CLOCK_PHASES = ("records", "deletes", "claim_grouping", "resolve", "other_rounds", "assign", "pack",
+                      "lds_buckets", "queue")
+
+
+def batch_clock_step(mx, torch, bb, keys) -> dict:
+    """One untimed step more with the kernel that clocks its phases (option batch_clock): each
+    phase's workgroup time averaged over the grid, and the work counts.  With two workgroups
+    per compute unit their phases overlap, so the averages add up to the step but a phase's
+    average is not the time the chip spends in it."""
+    grid = bb.tuning.grid or torch.cuda.get_device_properties(0).multi_processor_count
+    mx.batch_clock(reset=True)
+    mx.set_option("batch_clock", 1)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bb.run(keys)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3
+        c = mx.batch_clock(reset=True)
+    finally:
+        mx.set_option("batch_clock", 0)
+    per_wg = 1e3 / c["tick_hz"] / grid
+    phases = {p: round(c[p] * per_wg, 2) for p in BATCH_CLOCK_PHASES}
+    counts = {k: v for k, v in c.items() if k not in BATCH_CLOCK_PHASES and k not in ("tick_hz", "workgroup")}
+    dels_s = phases["deletes"] / 1e3
+    log(f"[batched] clocked step {step_ms:.1f} ms ({bb.tuning.block} x {grid}), workgroup time per phase: " +
+        ", ".join(f"{p} {v:.1f}" for p, v in phases.items()) + f" ms; workgroup lifetime "
+        f"{c['workgroup'] * per_wg:.1f} ms; {c['deletes_issued'] / max(1, c['device_keys']):.3f} deletes per "
+        f"device-path key ({c['deletes_issued'] / 1e9:.2f} G, {c['deletes_issued'] / max(dels_s, 1e-9) / 1e9:.1f} G/s "
+        f"over the deletes' average workgroup time), {c['list_records'] / max(1, c['device_keys']):.3f} list records "
+        f"per key")
+    return dict(step_ms=round(step_ms, 1), block=bb.tuning.block, grid=grid,
+                workgroup_ms=round(c["workgroup"] * per_wg, 2), phases_ms=phases, counts=counts,
+                note="ticks of each phase summed over workgroups / grid / tick rate (option batch_clock); "
+                     "an untimed extra step with the clocked kernel")
 
 
 def ceilings_leg(mx, torch) -> dict:

@@ -622,7 +622,12 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 round) in a list that is grouped by tile of edges and resolved in LDS,
  *                 which also writes each winner's hinge part into its layer slot, instead
  *                 of one device atomicMin per claim and a state read per edge in the next
- *                 round; 0 = atomicMin.  The same codes either way.
+ *                 round; 0 = atomicMin.  The same codes either way.  A sparse round (at most
+ *                 half an LDS tile of records) resolves in one LDS hash table keyed by edge.
+ *   "batch_clock" 0 or 1 (default 0): batched launches run the instantiation of the kernel
+ *                 that adds its per-phase workgroup time and work counts to the device's
+ *                 batch clock (mphx_batch_clock); 0 = the kernel without clocks.  The same
+ *                 outputs either way; the clock costs a few registers and atomics per bucket.
  *   "hem_block"   256, 512 or 1024 (default 1024): workgroup size of the batched kernel that
  *                 builds the HEM split's buckets (mphx_hem_build_*, mphx_hem_build_host_*).
  *   "hem_grid"    0..65536 (default 0 = one workgroup per compute unit): its persistent grid.
@@ -645,6 +650,19 @@ MPHX_API int mphx_set_option(const char* key, int64_t value);
 MPHX_API int64_t mphx_get_option(const char* key);
 MPHX_API int mphx_phase_times(double* ms, uint64_t* launches, int max_phases, int reset);
 MPHX_API const char* mphx_phase_name(int i);
+/* mphx_batch_clock copies up to max_entries entries of the current device's batch clock to
+ * out (host) and, if reset, zeroes it; returns the number of entries (MPHX_EDEVICE on a HIP
+ * error, MPHX_EINVAL for a null out with max_entries > 0).  Entry 0 is the wall-clock tick
+ * rate in Hz; then, summed over the workgroups of every launch made with option batch_clock=1
+ * since the last reset: ticks spent in the record build (hashing, partition, records, layer 0),
+ * the rounds' deletes, the grouping of claim lists, their resolve, rounds claiming by
+ * atomicMin or sorted deletes, the assignment, code packing and rank, whole buckets of the LDS
+ * path, the bucket queue, and the workgroups' lifetimes; then the device-path bucket and key
+ * counts, tries, rounds, deletes issued in list rounds, claim-list records, and the LDS-path
+ * bucket and key counts.  mphx_batch_clock_name(i) names entry i.  Phase ticks divided by the
+ * grid give the average workgroup's time in that phase. */
+MPHX_API int mphx_batch_clock(uint64_t* out, int max_entries, int reset);
+MPHX_API const char* mphx_batch_clock_name(int i);
 
 /* ---------------------------------------------------------------------------------------
  * Machine-ceiling probes (measurement only; none is on the build path).  The streaming copy

@@ -5,7 +5,7 @@ Hypergraphs" (arXiv 1312.0526).  The work runs in the HIP kernels of libmphx.so 
 ABI of include/mphx.h; this package only marshals torch tensors and streams into that ABI.
 """
 from ._lib import (  # noqa: F401
-    BatchBuild, BatchTuning, Server, build_batch, gen_buckets_u64, ECANCELED, ECORE, EDEVICE, EDUP, EINVAL, ENOMEM, ERANGE, KEYS_STR, KEYS_U64, OK, ROUND_CORE, LIB_PATH, MphxError,
+    BatchBuild, BatchTuning, Server, batch_clock, build_batch, gen_buckets_u64, ECANCELED, ECORE, EDEVICE, EDUP, EINVAL, ENOMEM, ERANGE, KEYS_STR, KEYS_U64, OK, ROUND_CORE, LIB_PATH, MphxError,
     check_bijection, gen_keys_u64, gen_str_keys, get_option, hash_str, hash_u64, lib, lookup_str, lookup_u64,
     mphf_build_str, mphf_build_u64, mphf_build_u64_static, mphf_workspace_bytes,
     mphf_build_stream_u64, stream_workspace_bytes, lookup_wide_u64, check_stream_u64, part_size, peel, peel_r, phase_times, set_option,

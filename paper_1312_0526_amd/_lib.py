@@ -127,6 +127,8 @@ _SIGS = {
     "mphx_server_destroy": (_i32, [_vp]),
     "mphx_phase_times": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_uint64), _i32, _i32]),
     "mphx_phase_name": (C.c_char_p, [_i32]),
+    "mphx_batch_clock": (_i32, [C.POINTER(C.c_uint64), _i32, _i32]),
+    "mphx_batch_clock_name": (C.c_char_p, [_i32]),
     "mphx_probe_copy": (_i32, [_vp, _vp, _u64, _u32, _vp]),
     "mphx_probe_random": (_i32, [_i32, _vp, _u64, _u64, _u64, _u32, _u32, _vp]),
 }
@@ -195,6 +197,16 @@ def phase_times(reset: bool = False) -> dict:
     cnt = (C.c_uint64 * 16)()
     k = lib().mphx_phase_times(ms, cnt, 16, int(reset))
     return {lib().mphx_phase_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(k)}
+
+
+def batch_clock(reset: bool = False) -> dict:
+    """The current device's batch clock (launches made with option batch_clock=1): entry name ->
+    value; "tick_hz" is the tick rate, phase entries are ticks summed over workgroups."""
+    out = (C.c_uint64 * 64)()
+    k = lib().mphx_batch_clock(out, 64, int(reset))
+    if k < 0:
+        _err(k)
+    return {lib().mphx_batch_clock_name(i).decode(): int(out[i]) for i in range(min(k, 64))}
 
 
 def part_size(n: int, gamma=(123, 100)) -> int:

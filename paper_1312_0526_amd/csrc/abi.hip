@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "launch.h"
 #include "mphx.h"
 
@@ -31,6 +32,7 @@ struct Options {
                                        // below 2^26 keys the per-round partition and resolve cost more
                                        // than the atomic claims they replace
     std::atomic<int> update_lists{16}; // claim-list rounds with 2 * layer >= m * update_lists / 100
+                                       // delete through a sorted update list (0 = never)
     std::atomic<int> hem_block{1024};  // batched-kernel workgroup size for the HEM split's buckets
     std::atomic<int> hem_grid{0};      // its persistent grid (0 = one workgroup per compute unit)
     std::atomic<int64_t> list_cap{0};  // records a claim-list round may hold (0 = m, the buffers' size)
@@ -40,7 +42,7 @@ struct Options {
                                              // (0: off; claim lists that carry the hinge in the slot
                                              // beat them on every layer)
     std::atomic<int> batch_claim_lists{1};   // sparse rounds of key-word buckets claim through lists
-                                       // delete through a sorted update list (0 = never)
+    std::atomic<int> batch_clock{0};   // 1 = batched launches run the kernel that clocks its phases
 };
 
 Options g_opt;
@@ -449,6 +451,9 @@ int mphx_set_option(const char* key, int64_t value)
     } else if (!strcmp(key, "batch_claim_lists")) {
         if (value != 0 && value != 1) return fail(MPHX_EINVAL, "batch_claim_lists must be 0 or 1");
         g_opt.batch_claim_lists = (int)value;
+    } else if (!strcmp(key, "batch_clock")) {
+        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "batch_clock must be 0 or 1");
+        g_opt.batch_clock = (int)value;
     } else if (!strcmp(key, "hem_grid")) {
         if (value < 0 || value > (1 << 16)) return fail(MPHX_EINVAL, "hem_grid must be in 0..65536");
         g_opt.hem_grid = (int)value;
@@ -478,6 +483,7 @@ int64_t mphx_get_option(const char* key)
     if (!strcmp(key, "batch_lds")) return g_opt.batch_lds;
     if (!strcmp(key, "batch_sort_deletes")) return g_opt.batch_sort_deletes;
     if (!strcmp(key, "batch_claim_lists")) return g_opt.batch_claim_lists;
+    if (!strcmp(key, "batch_clock")) return g_opt.batch_clock;
     if (!strcmp(key, "list_cap")) return g_opt.list_cap;
     if (!strcmp(key, "list_fallbacks")) return g_opt.list_fallbacks;
     fail(MPHX_EINVAL, "unknown option '%s'", key);
@@ -501,6 +507,16 @@ int mphx_phase_times(double* ms, uint64_t* launches, int max_phases, int reset)
 }
 
 const char* mphx_phase_name(int i) { return (i >= 0 && i < PH_COUNT) ? kPhaseNames[i] : ""; }
+
+int mphx_batch_clock(uint64_t* out, int max_entries, int reset)
+{
+    if (max_entries < 0 || (max_entries > 0 && !out)) return fail(MPHX_EINVAL, "null output");
+    hipError_t err = batch_clock_read(out, max_entries, reset != 0);
+    if (err != hipSuccess) return fail(MPHX_EDEVICE, "batch clock: %s", hipGetErrorString(err));
+    return (int)kBatchClockEntries;
+}
+
+const char* mphx_batch_clock_name(int i) { return batch_clock_name(i); }
 
 size_t mphx_peel_workspace_bytes(uint64_t n, uint64_t m)
 {
@@ -1359,6 +1375,7 @@ int batch_enqueue(const uint64_t* keys, const uint64_t* bucket_off, const uint32
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
     a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
     a.claim_lists = (uint32_t)g_opt.batch_claim_lists.load();
+    a.clock = (uint32_t)g_opt.batch_clock.load();
     a.pairs = pairs ? 1u : 0u;
     HIP_TRY(launch_batch_descs(descs, keys, bucket_off, B, seed, code_off, rank_off, codes, rank,
                                reinterpret_cast<BucketResult*>(results), s, pairs ? 2u : 1u));
@@ -1622,6 +1639,7 @@ int mphx_build_batch(const mphx_bucket* buckets, uint32_t B, const uint32_t* ord
     a.lds_path = (uint32_t)g_opt.batch_lds.load();
     a.sort_div = (uint32_t)g_opt.batch_sort_deletes.load();
     a.claim_lists = (uint32_t)g_opt.batch_claim_lists.load();
+    a.clock = (uint32_t)g_opt.batch_clock.load();
     HIP_TRY(launch_batch(a, block, grid, !(t && t->scope == 1), (hipStream_t)stream));
     return MPHX_OK;
 }

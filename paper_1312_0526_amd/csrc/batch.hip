@@ -17,6 +17,7 @@
 // the edge's vertices hinge first for the assignment.  u64 keys recompute their edge from the
 // key when needed; string keys keep their edges in the slot.
 #include "common.h"
+#include "batch.h"
 #include "launch.h"
 
 namespace mphx {
@@ -303,10 +304,76 @@ __device__ void pack_codes(const uint8_t* code8, uint32_t m, const BucketDesc& d
     block_exclusive_scan<kBlock>(L.bcount, d.rank, nblocks);
 }
 
-template <int kBlock, int kScope>
+// The batch clock: per-phase workgroup time (wall-clock ticks, summed over workgroups) and work
+// counts, added by the kernel instantiated with kClock (BatchArgs::clock); entry 0 is reserved
+// for the tick rate, which the host fills in when it reads the clock.
+enum : int {
+    kClRecords = 1, kClDeletes, kClGroup, kClResolve, kClOther, kClAssign, kClPack, kClLds, kClQueue, kClLife,
+    kClBuckets, kClKeys, kClTries, kClRounds, kClDels, kClRecs, kClLdsBuckets, kClLdsKeys
+};
+static_assert(kClLdsKeys + 1 == kBatchClockEntries, "batch clock entries");
+__device__ unsigned long long g_batch_clock[kBatchClockEntries];
+
+// Thread 0 marks phase boundaries right after workgroup barriers; the time since the last mark
+// goes to the phase that ended.  Without kOn every member is empty.
+template <bool kOn>
+struct PhaseClock {
+    uint64_t t = 0, recs = 0, dels = 0;
+    uint64_t acc[kClPack + 1] = {};
+    __device__ __forceinline__ void start()
+    {
+        if constexpr (kOn)
+            t = wall_clock64();
+    }
+    __device__ __forceinline__ void mark(int k)
+    {
+        if constexpr (kOn) {
+            if (threadIdx.x == 0) {
+                const uint64_t t2 = wall_clock64();
+                acc[k] += t2 - t;
+                t = t2;
+            }
+        }
+    }
+    __device__ __forceinline__ void deletes(uint32_t c)
+    {
+        if constexpr (kOn)
+            dels += c;
+    }
+    __device__ __forceinline__ void records(uint32_t c)
+    {
+        if constexpr (kOn)
+            recs += c;
+    }
+    // every thread of the workgroup calls this once per bucket
+    __device__ __forceinline__ void flush(uint64_t n, uint32_t tries, uint32_t rounds)
+    {
+        if constexpr (kOn) {
+            uint64_t dsum = dels;
+            for (int o = kWave / 2; o > 0; o >>= 1)
+                dsum += __shfl_xor(dsum, o, kWave);
+            if ((threadIdx.x & (kWave - 1)) == 0 && dsum)
+                atomicAdd(&g_batch_clock[kClDels], (unsigned long long)dsum);
+            dels = 0;
+            if (threadIdx.x == 0) {
+                for (int k = kClRecords; k <= kClPack; k++)
+                    atomicAdd(&g_batch_clock[k], (unsigned long long)acc[k]);
+                atomicAdd(&g_batch_clock[kClBuckets], 1ull);
+                atomicAdd(&g_batch_clock[kClKeys], (unsigned long long)n);
+                atomicAdd(&g_batch_clock[kClTries], (unsigned long long)tries);
+                atomicAdd(&g_batch_clock[kClRounds], (unsigned long long)rounds);
+                atomicAdd(&g_batch_clock[kClRecs], (unsigned long long)recs);
+            }
+        }
+    }
+};
+
+template <int kBlock, int kScope, bool kClock>
 __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* slot, uint8_t* lds)
 {
     using S = Sc<kScope>;
+    PhaseClock<kClock> clk;
+    clk.start();
     constexpr uint32_t kBatchTile = batch_tile<kBlock>();
     __shared__ uint32_t s_ltail, s_err, s_degsum, s_ctail;
     __shared__ uint32_t s_l0part[3];  // where layer 0's appends of parts 0, 1, 2 end
@@ -548,6 +615,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             }
         }
         __syncthreads();
+        clk.mark(kClRecords);
         if (s_err) {
             status = -2;  // degree above 255: no seed helps a duplicate-heavy bucket
             break;
@@ -659,6 +727,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                         L.rec[v0 + v] = s_tab[v];
                     __syncthreads();
                 }
+                clk.mark(kClOther);
                 lo = hi;
                 r++;
                 hinge_in_slot = false;  // the next layer was claimed by atomicMin
@@ -701,6 +770,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                         L.slots[i] = make_uint3(vh, va, vb);
                         const uint32_t pa = h == 2 ? 0u : h + 1, pb = h == 0 ? 2u : h - 1;  // parts of va, vb
                         const bool sa = (ones >> pa) & 1u, sb = (ones >> pb) & 1u;
+                        clk.deletes(2u - sa - sb);
                         const uint64_t oa = sa ? Rec::kOne : S::rec_del(L.rec, va, e);
                         const uint64_t ob = sb ? Rec::kOne : S::rec_del(L.rec, vb, e);
                         if (Rec::deg(oa) == 2) {
@@ -734,7 +804,9 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                         cl[pos + 1] = c1;
                 }
                 __syncthreads();
+                clk.mark(kClDeletes);
                 const uint32_t nc = s_ctail;
+                clk.records(nc);
                 if (nc <= kBatchTile / 2) {
                     // Few records (a sparse round): resolve them in one LDS hash table keyed by
                     // edge, at most half full (open addressing, linear probing), instead of
@@ -784,6 +856,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                             L.slots[pos] = make_uint3(c, hinge_word, 0u);
                     }
                     __syncthreads();
+                    clk.mark(kClResolve);
                     lo = hi;
                     r++;
                     hinge_in_slot = true;
@@ -800,6 +873,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     cg[atomicAdd(&s_cnt[c.x / kClTile], 1u)] = c;
                 }
                 __syncthreads();
+                clk.mark(kClGroup);
                 uint32_t* tab = reinterpret_cast<uint32_t*>(s_tab);  // kClTile bytes
                 for (uint32_t tl = 0; tl < ncl; tl++) {
                     const uint32_t j0 = s_bnd[tl], j1 = s_bnd[tl + 1];
@@ -831,6 +905,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     }
                     __syncthreads();
                 }
+                clk.mark(kClResolve);
                 lo = hi;
                 r++;
                 hinge_in_slot = true;  // the resolve wrote each slot's hinge and degree-1 parts
@@ -871,6 +946,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     L.slots[pos + 1].x = c1;
             }
             __syncthreads();
+            clk.mark(kClOther);
             lo = hi;
             r++;
             hinge_in_slot = false;  // the next layer was claimed by atomicMin
@@ -878,6 +954,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
         nrounds = r;
         const bool all = s_ltail == n;
         __syncthreads();
+        clk.mark(kClDeletes);  // the empty-layer check that ended the rounds
         if (all) {
             ok = true;
             break;
@@ -887,6 +964,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
         if (tid == 0)
             write_result(d.result, sd, t < a.max_tries ? t + 1 : a.max_tries, status ? status : 1, nrounds);
         __syncthreads();
+        clk.flush(n, t < a.max_tries ? t + 1 : a.max_tries, nrounds);
         return;
     }
     // assignment, last layer first; codes as bytes in the record area
@@ -905,10 +983,13 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
         }
         __syncthreads();
     }
+    clk.mark(kClAssign);
     pack_codes<kBlock>(code8, m, d, L);
     if (tid == 0)
         write_result(d.result, sd, t + 1, 0, nrounds);
     __syncthreads();
+    clk.mark(kClPack);
+    clk.flush(n, t + 1, nrounds);
 }
 
 // The same build for a bucket that fits in LDS: 4-byte records (degree in bits [24, 32), sum of
@@ -1071,26 +1152,57 @@ __device__ void build_bucket_lds(const BatchArgs& a, const BucketDesc& d, uint8_
     __syncthreads();
 }
 
-template <int kBlock, int kScope>
-__global__ __launch_bounds__(kBlock) void k_batch(BatchArgs a)
+// Waves per SIMD the launch shapes need resident: 1024 threads = 16 waves per compute unit, 512
+// two workgroups per compute unit, 256 three.
+template <int kBlock>
+constexpr int batch_waves_per_eu() { return kBlock >= 512 ? 4 : 3; }
+
+template <int kBlock, int kScope, bool kClock>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<kBlock>())))
+void k_batch(BatchArgs a)
 {
     __shared__ uint32_t s_idx;
     __shared__ __align__(16) uint8_t s_lds[batch_lds_bytes<kBlock>()];
     uint8_t* slot = a.slots + (uint64_t)blockIdx.x * a.slot_bytes;
+    uint64_t t_life = 0, t_q = 0, t_queue = 0, t_lds = 0, n_lds = 0, k_lds = 0;
+    if constexpr (kClock)
+        t_life = wall_clock64();
     for (;;) {
+        if constexpr (kClock)
+            t_q = wall_clock64();
         if (threadIdx.x == 0)
             s_idx = atomicAdd(a.next, 1u);
         __syncthreads();
         const uint32_t idx = s_idx;
         __syncthreads();
+        if constexpr (kClock) {
+            const uint64_t t2 = wall_clock64();
+            t_queue += t2 - t_q;
+            t_q = t2;
+        }
         if (idx >= a.B)
             break;
         const BucketDesc d = a.descs[a.order ? a.order[idx] : idx];
         const bool in_lds = d.n <= a.max_n && bucket_fits_lds<kBlock>(d.n, 3 * part_size_dev(d.n, a.gnum, a.gden));
-        if (in_lds && a.lds_path)
+        if (in_lds && a.lds_path) {
             build_bucket_lds<kBlock>(a, d, slot, s_lds);
-        else
-            build_bucket<kBlock, kScope>(a, d, slot, s_lds);
+            if constexpr (kClock) {
+                t_lds += wall_clock64() - t_q;
+                n_lds++;
+                k_lds += d.n;
+            }
+        } else {
+            build_bucket<kBlock, kScope, kClock>(a, d, slot, s_lds);
+        }
+    }
+    if constexpr (kClock) {
+        if (threadIdx.x == 0) {
+            atomicAdd(&g_batch_clock[kClQueue], (unsigned long long)t_queue);
+            atomicAdd(&g_batch_clock[kClLds], (unsigned long long)t_lds);
+            atomicAdd(&g_batch_clock[kClLdsBuckets], (unsigned long long)n_lds);
+            atomicAdd(&g_batch_clock[kClLdsKeys], (unsigned long long)k_lds);
+            atomicAdd(&g_batch_clock[kClLife], (unsigned long long)(wall_clock64() - t_life));
+        }
     }
 }
 
@@ -1132,15 +1244,60 @@ hipError_t launch_batch(const BatchArgs& a, unsigned block, unsigned grid, bool 
     hipError_t err = launch_zero(a.next, sizeof(unsigned int), s);
     if (err != hipSuccess) return err;
     constexpr int W = __HIP_MEMORY_SCOPE_WORKGROUP, A = __HIP_MEMORY_SCOPE_AGENT;
+    if (a.clock) {  // the instantiation that clocks its phases
+        switch (block) {
+        case 256:
+            wg_scope ? k_batch<256, W, true><<<grid, 256, 0, s>>>(a) : k_batch<256, A, true><<<grid, 256, 0, s>>>(a);
+            break;
+        case 512:
+            wg_scope ? k_batch<512, W, true><<<grid, 512, 0, s>>>(a) : k_batch<512, A, true><<<grid, 512, 0, s>>>(a);
+            break;
+        case 1024:
+            wg_scope ? k_batch<1024, W, true><<<grid, 1024, 0, s>>>(a)
+                     : k_batch<1024, A, true><<<grid, 1024, 0, s>>>(a);
+            break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (block) {
-    case 256: wg_scope ? k_batch<256, W><<<grid, 256, 0, s>>>(a) : k_batch<256, A><<<grid, 256, 0, s>>>(a); break;
-    case 512: wg_scope ? k_batch<512, W><<<grid, 512, 0, s>>>(a) : k_batch<512, A><<<grid, 512, 0, s>>>(a); break;
+    case 256: wg_scope ? k_batch<256, W, false><<<grid, 256, 0, s>>>(a) : k_batch<256, A, false><<<grid, 256, 0, s>>>(a); break;
+    case 512: wg_scope ? k_batch<512, W, false><<<grid, 512, 0, s>>>(a) : k_batch<512, A, false><<<grid, 512, 0, s>>>(a); break;
     case 1024:
-        wg_scope ? k_batch<1024, W><<<grid, 1024, 0, s>>>(a) : k_batch<1024, A><<<grid, 1024, 0, s>>>(a);
+        wg_scope ? k_batch<1024, W, false><<<grid, 1024, 0, s>>>(a) : k_batch<1024, A, false><<<grid, 1024, 0, s>>>(a);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t batch_clock_read(uint64_t* out, int max_entries, bool reset)
+{
+    unsigned long long h[kBatchClockEntries] = {};
+    hipError_t err = hipMemcpyFromSymbol(h, HIP_SYMBOL(g_batch_clock), sizeof h, 0, hipMemcpyDeviceToHost);
+    if (err != hipSuccess) return err;
+    int dev = 0, khz = 0;
+    err = hipGetDevice(&dev);
+    if (err == hipSuccess)
+        err = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (err != hipSuccess) return err;
+    h[0] = (unsigned long long)khz * 1000ull;
+    for (int i = 0; i < max_entries && i < kBatchClockEntries; i++)
+        out[i] = h[i];
+    if (reset) {
+        const unsigned long long z[kBatchClockEntries] = {};
+        err = hipMemcpyToSymbol(HIP_SYMBOL(g_batch_clock), z, sizeof z, 0, hipMemcpyHostToDevice);
+    }
+    return err;
+}
+
+const char* batch_clock_name(int i)
+{
+    static const char* const kNames[kBatchClockEntries] = {
+        "tick_hz",  "records", "deletes",        "claim_grouping", "resolve",        "other_rounds",     "assign",
+        "pack",     "lds_buckets", "queue",      "workgroup",      "device_buckets", "device_keys",      "tries",
+        "rounds",   "deletes_issued", "list_records", "lds_bucket_count", "lds_keys"};
+    return (i >= 0 && i < kBatchClockEntries) ? kNames[i] : "";
 }
 
 }  // namespace mphx

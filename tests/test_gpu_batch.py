@@ -119,6 +119,22 @@ def test_batch_claim_lists_over_several_edge_tiles(mx, o, block):
             mx.set_option(k, v)
 
 
+@pytest.mark.parametrize("block", [512, 1024])
+def test_batch_record_build_packed_boundary(mx, o, block):
+    """Buckets on both sides of the one-pass record partition's limit: up to 2^20 keys given by
+    key words pack each (vertex in tile, key) pair in one word; above it the parts are
+    partitioned one by one with 8-byte pairs.  Both against the oracle."""
+    import torch
+
+    sizes = np.array([(1 << 20) - 1, 1 << 20, (1 << 20) + 1, 1_500_000], np.uint64)
+    off = _offsets(sizes)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    bb = mx.BatchBuild(off, block=block, grid=0, scope=0)
+    bb.run(keys)
+    torch.cuda.synchronize()
+    _check_buckets(mx, o, bb, keys.cpu().numpy().view(np.uint64), sizes)
+
+
 def test_batch_large_buckets_sampled(mx, o):
     import torch
 
@@ -176,6 +192,48 @@ def test_batch_rejects_oversize_bucket(mx):
     res = bb.bucket_results()
     assert res[1]["status"] == mx.EINVAL
     assert res[0]["status"] in (0, 1) and res[2]["status"] in (0, 1)
+
+
+@pytest.mark.parametrize("block", [512, 1024])
+def test_batch_clock_counts_the_work_and_changes_nothing(mx, o, block):
+    """The clocked kernel (option batch_clock) builds the same outputs as the plain one, and its
+    counters add up: every bucket and key counted once, by the LDS path or the device path, and
+    the phases within the workgroups' lifetimes."""
+    import torch
+
+    sizes = np.concatenate([[1, 7, 3000], workloads.bucket_sizes(40, 100, 200_000, seed=11)]).astype(np.uint64)
+    off = _offsets(sizes)
+    keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+    bb = mx.BatchBuild(off, block=block, grid=0, scope=0)
+    bb.run(keys)
+    torch.cuda.synchronize()
+    ref_codes = [bb.bucket_codes(b).cpu().numpy().copy() for b in range(len(sizes))]
+    ref_res = bb.bucket_results().copy()
+    old = mx.get_option("batch_clock")
+    try:
+        mx.batch_clock(reset=True)
+        mx.set_option("batch_clock", 1)
+        bb.run(keys)
+        torch.cuda.synchronize()
+        c = mx.batch_clock(reset=True)
+    finally:
+        mx.set_option("batch_clock", old)
+    res = bb.bucket_results()
+    assert np.array_equal(res, ref_res)
+    for b in range(len(sizes)):
+        assert np.array_equal(bb.bucket_codes(b).cpu().numpy(), ref_codes[b]), b
+    assert c["tick_hz"] > 0
+    assert c["device_buckets"] + c["lds_bucket_count"] == len(sizes)
+    assert c["device_keys"] + c["lds_keys"] == int(sizes.sum())
+    big = sizes > 20_000  # too large for the LDS path at either workgroup size
+    assert c["device_buckets"] >= int(big.sum()) and c["device_keys"] >= int(sizes[big].sum())
+    assert c["tries"] >= c["device_buckets"] and c["rounds"] > 0 and c["list_records"] > 0
+    # two deletes per edge of the device-path buckets' list rounds at most
+    assert 0 < c["deletes_issued"] <= 2 * c["device_keys"]
+    phases = ("records", "deletes", "claim_grouping", "resolve", "other_rounds", "assign", "pack", "lds_buckets", "queue")
+    assert all(c[p] >= 0 for p in phases) and c["records"] > 0 and c["deletes"] > 0 and c["assign"] > 0
+    assert sum(c[p] for p in phases) <= c["workgroup"]
+    assert mx.batch_clock()["workgroup"] == 0  # the read above reset it
 
 
 def test_build_batch_descriptors_mixed_kinds(mx, o):
