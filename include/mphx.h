@@ -623,7 +623,8 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 which also writes each winner's hinge part into its layer slot, instead
  *                 of one device atomicMin per claim and a state read per edge in the next
  *                 round; 0 = atomicMin.  The same codes either way.  A sparse round (at most
- *                 half an LDS tile of records) resolves in one LDS hash table keyed by edge.
+ *                 as many records as an LDS record tile has vertices) resolves in one LDS
+ *                 hash table keyed by edge.
  *   "batch_clock" 0 or 1 (default 0): batched launches run the instantiation of the kernel
  *                 that adds its per-phase workgroup time and work counts to the device's
  *                 batch clock (mphx_batch_clock); 0 = the kernel without clocks.  The same

@@ -807,31 +807,33 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 clk.mark(kClDeletes);
                 const uint32_t nc = s_ctail;
                 clk.records(nc);
-                if (nc <= kBatchTile / 2) {
+                if (nc <= kBatchTile && n < (1u << 24)) {
                     // Few records (a sparse round): resolve them in one LDS hash table keyed by
-                    // edge, at most half full (open addressing, linear probing), instead of
-                    // grouping them by tile -- the same bits per edge, so the same winners.
-                    uint32_t* hkey = reinterpret_cast<uint32_t*>(s_tab);
-                    uint32_t* hbits = hkey + kBatchTile;
+                    // edge, at most half full (open addressing, linear probing; an entry is the
+                    // edge << 8 | its claim and cancel bits), instead of grouping them by tile --
+                    // the same bits per edge, so the same winners.
+                    uint32_t* htab = reinterpret_cast<uint32_t*>(s_tab);  // up to 2 kBatchTile entries
                     uint32_t lg = 6;
                     while ((1u << lg) < 2 * nc)
                         lg++;
                     const uint32_t mask = (1u << lg) - 1;
-                    for (uint32_t j = tid; j <= mask; j += kBlock) {
-                        hkey[j] = kUnclaimed;
-                        hbits[j] = 0u;
-                    }
+                    for (uint32_t j = tid; j <= mask; j += kBlock)
+                        htab[j] = kUnclaimed;
                     __syncthreads();
                     for (uint32_t j = tid; j < nc; j += kBlock) {
                         const uint2 c = cl[j];
+                        const uint32_t bit = 1u << c.y;
                         uint32_t h = (c.x * 0x9E3779B1u) >> (32 - lg);
                         for (;;) {
-                            const uint32_t old = atomicCAS(&hkey[h], kUnclaimed, c.x);
-                            if (old == kUnclaimed || old == c.x)
+                            const uint32_t old = atomicCAS(&htab[h], kUnclaimed, c.x << 8 | bit);
+                            if (old == kUnclaimed)
                                 break;
+                            if (old >> 8 == c.x) {
+                                atomicOr(&htab[h], bit);
+                                break;
+                            }
                             h = (h + 1) & mask;
                         }
-                        atomicOr(&hbits[h], 1u << c.y);
                     }
                     __syncthreads();
                     for (uint32_t base = 0; base < nc; base += kBlock) {
@@ -841,10 +843,11 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                         if (j < nc) {
                             const uint2 cc = cl[j];
                             if (cc.y < 4) {
+                                // the edge was inserted before any empty entry on its probe path
                                 uint32_t h = (cc.x * 0x9E3779B1u) >> (32 - lg);
-                                while (hkey[h] != cc.x)
+                                while (htab[h] >> 8 != cc.x)
                                     h = (h + 1) & mask;
-                                const uint32_t t = hbits[h];
+                                const uint32_t t = htab[h] & 0xFFu;
                                 const uint32_t live = t & ~(t >> 4) & 7u;
                                 win = live != 0 && (uint32_t)__builtin_ctz(live) == cc.y;
                                 c = cc.x;
