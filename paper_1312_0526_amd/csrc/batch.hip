@@ -233,12 +233,10 @@ __device__ __forceinline__ uint32_t bucket_local(const BatchArgs& a, const Bucke
     return (k == 0 ? ev.x : (k == 1 ? ev.y : ev.z)) - (uint32_t)(k * P);
 }
 
-// The three part-local vertices of key i of a bucket given by key words (bucket_local for k = 0, 1, 2).
-__device__ __forceinline__ uint3 word_key_locals(const BatchArgs& a, const BucketDesc& d, uint32_t i, uint64_t sd,
-                                                 uint64_t P)
+// The three part-local vertices of a key given by words, from its digest (x, y) under the try's
+// seed (bucket_local for k = 0, 1, 2).
+__device__ __forceinline__ uint3 digest_locals(uint64_t x, uint64_t y, uint64_t P)
 {
-    uint64_t x, y;
-    key_digest(a, d, i, sd, x, y);
     return make_uint3((uint32_t)range_reduce(fin(x + kGamma), P), (uint32_t)range_reduce(fin(x + 2 * kGamma), P),
                       (uint32_t)range_reduce(fin(y + 3 * kGamma), P));
 }
@@ -465,6 +463,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             __syncthreads();
         };
         constexpr uint32_t kPackBits = 12, kPackTile = 1u << kPackBits;
+        constexpr uint32_t kU = 4;  // keys or pairs each thread loads before using any of them
         const uint32_t nbp = (uint32_t)((P + kPackTile - 1) / kPackTile);
         if (d.keys && n <= (1u << (32 - kPackBits)) && 3 * nbp <= kBatchMaxBuckets) {
             // Keys given by words: all three parts partitioned in one pass.  Each key's three
@@ -476,11 +475,19 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             for (uint32_t b = tid; b < 3 * nbp; b += kBlock)
                 s_cnt[b] = 0;
             __syncthreads();
-            for (uint32_t i = tid; i < n; i += kBlock) {
-                const uint3 u = word_key_locals(a, d, i, sd, P);
-                atomicAdd(&s_cnt[u.x >> kPackBits], 1u);
-                atomicAdd(&s_cnt[nbp + (u.y >> kPackBits)], 1u);
-                atomicAdd(&s_cnt[2 * nbp + (u.z >> kPackBits)], 1u);
+            for (uint32_t i0 = tid; i0 < n; i0 += kU * kBlock) {
+                uint64_t x[kU], y[kU];
+                for (uint32_t q = 0; q < kU; q++)
+                    if (i0 + q * kBlock < n)
+                        key_digest(a, d, i0 + q * kBlock, sd, x[q], y[q]);
+                for (uint32_t q = 0; q < kU; q++) {
+                    if (i0 + q * kBlock < n) {
+                        const uint3 u = digest_locals(x[q], y[q], P);
+                        atomicAdd(&s_cnt[u.x >> kPackBits], 1u);
+                        atomicAdd(&s_cnt[nbp + (u.y >> kPackBits)], 1u);
+                        atomicAdd(&s_cnt[2 * nbp + (u.z >> kPackBits)], 1u);
+                    }
+                }
             }
             __syncthreads();
             lds_exclusive_scan<kBlock>(s_cnt, 3 * nbp, s_wtot);
@@ -489,12 +496,21 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             if (tid == 0)
                 s_bnd[3 * nbp] = 3 * n;
             __syncthreads();
-            for (uint32_t i = tid; i < n; i += kBlock) {
-                const uint3 u = word_key_locals(a, d, i, sd, P);
-                const uint32_t hi_i = i << kPackBits;
-                pairs[atomicAdd(&s_cnt[u.x >> kPackBits], 1u)] = hi_i | (u.x & (kPackTile - 1));
-                pairs[atomicAdd(&s_cnt[nbp + (u.y >> kPackBits)], 1u)] = hi_i | (u.y & (kPackTile - 1));
-                pairs[atomicAdd(&s_cnt[2 * nbp + (u.z >> kPackBits)], 1u)] = hi_i | (u.z & (kPackTile - 1));
+            for (uint32_t i0 = tid; i0 < n; i0 += kU * kBlock) {
+                uint64_t x[kU], y[kU];
+                for (uint32_t q = 0; q < kU; q++)
+                    if (i0 + q * kBlock < n)
+                        key_digest(a, d, i0 + q * kBlock, sd, x[q], y[q]);
+                for (uint32_t q = 0; q < kU; q++) {
+                    const uint32_t i = i0 + q * kBlock;
+                    if (i < n) {
+                        const uint3 u = digest_locals(x[q], y[q], P);
+                        const uint32_t hi_i = i << kPackBits;
+                        pairs[atomicAdd(&s_cnt[u.x >> kPackBits], 1u)] = hi_i | (u.x & (kPackTile - 1));
+                        pairs[atomicAdd(&s_cnt[nbp + (u.y >> kPackBits)], 1u)] = hi_i | (u.y & (kPackTile - 1));
+                        pairs[atomicAdd(&s_cnt[2 * nbp + (u.z >> kPackBits)], 1u)] = hi_i | (u.z & (kPackTile - 1));
+                    }
+                }
             }
             __syncthreads();
             for (uint32_t k = 0; k < 3; k++) {
@@ -503,9 +519,16 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                     for (uint32_t v = tid; v < kPackTile; v += kBlock)
                         s_tab[v] = 0;
                     __syncthreads();
-                    for (uint32_t j = s_bnd[k * nbp + b] + tid; j < s_bnd[k * nbp + b + 1]; j += kBlock) {
-                        const uint32_t pr = pairs[j];
-                        atomicAdd(&s_tab[pr & (kPackTile - 1)], (unsigned long long)(Rec::kOne + (pr >> kPackBits)));
+                    const uint32_t j1 = s_bnd[k * nbp + b + 1];
+                    for (uint32_t j0 = s_bnd[k * nbp + b] + tid; j0 < j1; j0 += kU * kBlock) {
+                        uint32_t pr[kU];
+                        for (uint32_t q = 0; q < kU; q++)
+                            if (j0 + q * kBlock < j1)
+                                pr[q] = pairs[j0 + q * kBlock];
+                        for (uint32_t q = 0; q < kU; q++)
+                            if (j0 + q * kBlock < j1)
+                                atomicAdd(&s_tab[pr[q] & (kPackTile - 1)],
+                                          (unsigned long long)(Rec::kOne + (pr[q] >> kPackBits)));
                     }
                     __syncthreads();
                     const uint64_t v0 = (uint64_t)b * kPackTile;
