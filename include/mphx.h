@@ -612,10 +612,14 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 512: 78 KB, about 9,000; 256: 48 KB, about 5,500) is built and peeled
  *                 entirely in LDS; 0 = every bucket through device memory.
  *                 The same codes either way.
- *   "batch_sort_deletes" d in 0..1024 (default 0): in the batched kernel, a layer of a u64
- *                 bucket built through device memory with 2 * layer * d >= m vertices deletes
+ *   "batch_sort_deletes" d in 0..1024 (default 4): in the batched kernel, a layer of a
+ *                 bucket given by key words (at most 2^20 keys, built through device memory)
+ *                 with 2 * layer * d >= m vertices, whose slots carry their hinges, deletes
  *                 through a list sorted by tile of vertices and applied in LDS instead of
- *                 device atomics; 0 = never.  The same codes either way.
+ *                 device atomics; its claims clear part bits of the edge states and a scan
+ *                 of the states appends the next layer; 0 = never.  The default takes layer
+ *                 0 only (at gamma 1.23 it holds about a quarter of the edges).  The same
+ *                 codes either way.
  *   "batch_claim_lists" 0 or 1 (default 1): in the batched kernel, the other layers of such
  *                 a bucket (those of at most 3n/8 edges: with sorted deletes off, all) record
  *                 their next-layer claims (and cancels of claims made stale within the

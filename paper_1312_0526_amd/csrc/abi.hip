@@ -38,9 +38,9 @@ struct Options {
     std::atomic<int64_t> list_cap{0};  // records a claim-list round may hold (0 = m, the buffers' size)
     std::atomic<int64_t> list_fallbacks{0};  // tries redone with atomic claims after a list overflowed
     std::atomic<int> batch_lds{1};     // 1 = batched buckets that fit run entirely in LDS
-    std::atomic<int> batch_sort_deletes{0};  // sorted deletes for layers with 2 * layer * this >= m
-                                             // (0: off; claim lists that carry the hinge in the slot
-                                             // beat them on every layer)
+    std::atomic<int> batch_sort_deletes{4};  // sorted deletes for layers with 2 * layer * this >= m
+                                             // (0: off; 4 takes layer 0 only, the one layer where
+                                             // they beat the claim lists' device atomics)
     std::atomic<int> batch_claim_lists{1};   // sparse rounds of key-word buckets claim through lists
     std::atomic<int> batch_clock{0};   // 1 = batched launches run the kernel that clocks its phases
 };

@@ -95,6 +95,10 @@ struct Sc {
     {
         return __hip_atomic_fetch_min(p, x, __ATOMIC_RELAXED, kScope);
     }
+    __device__ static __forceinline__ uint32_t fetch_and(uint32_t* p, uint32_t x)
+    {
+        return __hip_atomic_fetch_and(p, x, __ATOMIC_RELAXED, kScope);
+    }
 };
 
 // Workgroup-wide exclusive scan of count values (in -> out).
@@ -394,6 +398,9 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
     SlotLayout L;
     slot_layout(slot, n, m, &L);
     const uint64_t total = d.keys ? 0 : d.offs[n];
+    // packed (vertex in tile, key) words: tiles of kPackTile vertices, keys below 2^20
+    constexpr uint32_t kPackBits = 12, kPackTile = 1u << kPackBits;
+    const uint32_t nbp = (uint32_t)((P + kPackTile - 1) / kPackTile);
 
     uint32_t t = 0, nrounds = 0;
     bool ok = false;
@@ -462,9 +469,7 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             }
             __syncthreads();
         };
-        constexpr uint32_t kPackBits = 12, kPackTile = 1u << kPackBits;
         constexpr uint32_t kU = 4;  // keys or pairs each thread loads before using any of them
-        const uint32_t nbp = (uint32_t)((P + kPackTile - 1) / kPackTile);
         if (d.keys && n <= (1u << (32 - kPackBits)) && 3 * nbp <= kBatchMaxBuckets) {
             // Keys given by words: all three parts partitioned in one pass.  Each key's three
             // (vertex in tile, key) pairs are packed in a word (12 + 20 bits) and grouped by
@@ -668,19 +673,26 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
             if (lo == hi)
                 break;
             const uint32_t rr = (r + 1) << 2;
-            // A dense layer of a u64 bucket deletes through a sorted list instead of device
-            // atomics (Section 4.2's sorted update list, inside the workgroup): its deletes
-            // are grouped by tile of kBatchTile vertices in the free edge area, then each tile's
-            // records are loaded into LDS, the deletes applied with LDS atomics (the same old
-            // (degree, sum) per delete, hence the same claims) and the tile written back.
-            const uint32_t L2 = 2 * (hi - lo), mt = (m + kBatchTile - 1) / kBatchTile;
+            // A dense layer of a bucket given by key words may delete through a sorted list
+            // instead of device atomics (Section 4.2's sorted update list, inside the
+            // workgroup): its deletes, packed (vertex in tile, edge) like the record build's
+            // pairs, are grouped by (part, tile of kPackTile vertices) in the free edge area;
+            // each tile's records are loaded into LDS, the deletes applied with LDS atomics, and
+            // the tile written back.  A delete that takes a vertex from degree 2 to 1 marks its
+            // record (bit 63; degrees stay below 256 and sums below 2^28, so the bit is free);
+            // a marked vertex still at degree 1 once the tile's deletes are done claims its
+            // remaining edge -- the record's sum -- by clearing the part's bit in the edge's
+            // state (no return value).  A scan of the states then appends the claimed edges,
+            // each with its lowest claiming part as hinge and the claiming parts as the degree-1
+            // parts: the layer and hinges the claim lists give.
+            const uint32_t L2 = 2 * (hi - lo);
             constexpr uint32_t kClTile = kBatchTile * 8;  // claim-list tile: edges, one LDS byte each
             const uint32_t ncl = (n + kClTile - 1) / kClTile;
-            const bool sorted_round = a.sort_div && d.keys && (uint64_t)L2 * a.sort_div >= m &&
-                                      (uint64_t)L2 <= 3ull * n / 2 && mt <= kBatchMaxBuckets;
+            const bool sorted_round = a.sort_div && d.keys && hinge_in_slot && (uint64_t)L2 * a.sort_div >= m &&
+                                      n <= (1u << (32 - kPackBits)) && 3 * nbp <= kBatchMaxBuckets;
             const bool list_round = !sorted_round && a.claim_lists && d.keys && 8ull * (hi - lo) <= 3ull * n &&
                                     ncl <= kBatchMaxBuckets;
-            if (!list_round && hinge_in_slot) {
+            if (!list_round && !sorted_round && hinge_in_slot) {
                 // a layer resolved from claim lists left the states alone; the claims by
                 // atomicMin below must find its edges taken, so they get their states now
                 for (uint32_t i = lo + tid; i < hi; i += kBlock) {
@@ -690,70 +702,108 @@ __device__ void build_bucket(const BatchArgs& a, const BucketDesc& d, uint8_t* s
                 __syncthreads();
             }
             if (sorted_round) {
-                uint2* dl = reinterpret_cast<uint2*>(L.edges);  // 12n bytes: up to 1.5n deletes
-                for (uint32_t b = tid; b < mt; b += kBlock)
+                constexpr uint64_t kMark = 1ull << 63;
+                constexpr uint32_t kCollected = 0xFFFFFFF0u;  // a claimed edge, already appended
+                uint32_t* se = reinterpret_cast<uint32_t*>(L.edges);  // the layer's edges, skip bits on top
+                uint32_t* dl = se + n;                                // up to 2n packed deletes
+                for (uint32_t b = tid; b < 3 * nbp; b += kBlock)
                     s_cnt[b] = 0;
                 __syncthreads();
                 for (uint32_t i = lo + tid; i < hi; i += kBlock) {
-                    uint32_t e;
-                    const uint32_t h = hinge_of(i, e);
-                    const uint3 ev = bucket_edge(a, d, L, e, sd, P);
-                    atomicAdd(&s_cnt[(h == 0 ? ev.y : (h == 1 ? ev.z : ev.x)) / kBatchTile], 1u);
-                    atomicAdd(&s_cnt[(h == 0 ? ev.z : (h == 1 ? ev.x : ev.y)) / kBatchTile], 1u);
-                }
-                __syncthreads();
-                lds_exclusive_scan<kBlock>(s_cnt, mt, s_wtot);
-                for (uint32_t b = tid; b < mt; b += kBlock)
-                    s_bnd[b] = s_cnt[b];
-                if (tid == 0)
-                    s_bnd[mt] = L2;
-                __syncthreads();
-                for (uint32_t i = lo + tid; i < hi; i += kBlock) {
-                    uint32_t e;
-                    const uint32_t h = hinge_of(i, e);
+                    const uint3 s0 = L.slots[i];
+                    const uint32_t e = s0.x, h = s0.y & 3u, ones = (s0.y >> 8) & 7u;
                     const uint3 ev = bucket_edge(a, d, L, e, sd, P);
                     const uint32_t vh = h == 0 ? ev.x : (h == 1 ? ev.y : ev.z);
                     const uint32_t va = h == 0 ? ev.y : (h == 1 ? ev.z : ev.x);
                     const uint32_t vb = h == 0 ? ev.z : (h == 1 ? ev.x : ev.y);
                     L.slots[i] = make_uint3(vh, va, vb);
-                    dl[atomicAdd(&s_cnt[va / kBatchTile], 1u)] = make_uint2(va % kBatchTile, e);
-                    dl[atomicAdd(&s_cnt[vb / kBatchTile], 1u)] = make_uint2(vb % kBatchTile, e);
+                    const uint32_t pa = h == 2 ? 0u : h + 1, pb = h == 0 ? 2u : h - 1;  // parts of va, vb
+                    const uint32_t sa = (ones >> pa) & 1u, sb = (ones >> pb) & 1u;    // degree 1: skip
+                    se[i - lo] = e | sa << 30 | sb << 31;
+                    clk.deletes(2u - sa - sb);
+                    if (!sa)
+                        atomicAdd(&s_cnt[pa * nbp + ((va - pa * (uint32_t)P) >> kPackBits)], 1u);
+                    if (!sb)
+                        atomicAdd(&s_cnt[pb * nbp + ((vb - pb * (uint32_t)P) >> kPackBits)], 1u);
                 }
                 __syncthreads();
-                for (uint32_t t = 0; t < mt; t++) {
-                    const uint32_t j0 = s_bnd[t], j1 = s_bnd[t + 1];
-                    if (j0 == j1)
+                const uint32_t ndl = lds_exclusive_scan<kBlock>(s_cnt, 3 * nbp, s_wtot);
+                for (uint32_t b = tid; b < 3 * nbp; b += kBlock)
+                    s_bnd[b] = s_cnt[b];
+                if (tid == 0)
+                    s_bnd[3 * nbp] = ndl;
+                __syncthreads();
+                for (uint32_t i = lo + tid; i < hi; i += kBlock) {
+                    const uint3 sl = L.slots[i];
+                    const uint32_t w = se[i - lo], e = w & 0x3FFFFFFFu;
+                    const uint32_t pa = part_of(sl.y, P), pb = part_of(sl.z, P);
+                    const uint32_t la = sl.y - pa * (uint32_t)P, lb = sl.z - pb * (uint32_t)P;
+                    if (!(w >> 30 & 1u))
+                        dl[atomicAdd(&s_cnt[pa * nbp + (la >> kPackBits)], 1u)] = e << kPackBits | (la & (kPackTile - 1));
+                    if (!(w >> 31))
+                        dl[atomicAdd(&s_cnt[pb * nbp + (lb >> kPackBits)], 1u)] = e << kPackBits | (lb & (kPackTile - 1));
+                }
+                __syncthreads();
+                for (uint32_t t = 0; t < 3 * nbp; t++) {
+                    const uint32_t j1 = s_bnd[t + 1];
+                    if (s_bnd[t] == j1)
                         continue;  // uniform per block
-                    const uint64_t v0 = (uint64_t)t * kBatchTile;
-                    const uint32_t cnt = (uint32_t)min<uint64_t>(kBatchTile, m - v0);
+                    const uint32_t k = t / nbp;
+                    const uint64_t tv = (uint64_t)(t - k * nbp) * kPackTile;
+                    const uint64_t v0 = (uint64_t)k * P + tv;
+                    const uint32_t cnt = (uint32_t)min<uint64_t>(kPackTile, P - tv);
                     for (uint32_t v = tid; v < cnt; v += kBlock)
                         s_tab[v] = S::ld(L.rec + v0 + v);
                     __syncthreads();
-                    for (uint32_t base = j0; base < j1; base += kBlock) {
-                        const uint32_t j = base + tid;
-                        uint32_t c = 0;
-                        bool f = false;
-                        if (j < j1) {
-                            const uint2 dv = dl[j];
-                            const uint64_t old = atomicAdd(&s_tab[dv.x], 0ull - (Rec::kOne + dv.y));
-                            if (Rec::deg(old) == 2) {
-                                c = (uint32_t)(Rec::edge(old) - dv.y);
-                                f = S::fetch_min(L.state + c, rr | part_of((uint32_t)(v0 + dv.x), P)) == kUnclaimed;
+                    for (uint32_t j0 = s_bnd[t] + tid; j0 < j1; j0 += kU * kBlock) {
+                        uint32_t dv[kU];
+                        for (uint32_t q = 0; q < kU; q++)
+                            if (j0 + q * kBlock < j1)
+                                dv[q] = dl[j0 + q * kBlock];
+                        for (uint32_t q = 0; q < kU; q++) {
+                            if (j0 + q * kBlock < j1) {
+                                unsigned long long* x = &s_tab[dv[q] & (kPackTile - 1)];
+                                const uint64_t old = atomicAdd(x, 0ull - (Rec::kOne + (dv[q] >> kPackBits)));
+                                if ((old >> 40 & 0xFFu) == 2)
+                                    atomicOr(x, (unsigned long long)kMark);
                             }
                         }
-                        const uint32_t pos = block_append(&s_ltail, f, false);
-                        if (f)
-                            L.slots[pos].x = c;
                     }
                     __syncthreads();
-                    for (uint32_t v = tid; v < cnt; v += kBlock)
-                        L.rec[v0 + v] = s_tab[v];
+                    for (uint32_t v = tid; v < cnt; v += kBlock) {
+                        uint64_t x = s_tab[v];
+                        if (x & kMark) {
+                            x &= ~kMark;
+                            if ((x >> 40 & 0xFFu) == 1)
+                                S::fetch_and(L.state + Rec::edge(x), ~(1u << k));
+                        }
+                        L.rec[v0 + v] = x;
+                    }
                     __syncthreads();
                 }
+                // the next layer: edges whose state lost part bits (and nothing else) this round
+                for (uint32_t c0 = 0; c0 < n; c0 += kU * kBlock) {
+                    uint32_t st[kU];
+                    for (uint32_t q = 0; q < kU; q++) {
+                        const uint32_t c = c0 + q * kBlock + tid;
+                        st[q] = c < n ? S::ld(L.state + c) : kUnclaimed;
+                    }
+                    for (uint32_t q = 0; q < kU; q++) {
+                        const uint32_t c = c0 + q * kBlock + tid;
+                        const uint32_t bits = ~st[q] & 7u;
+                        const bool hit = st[q] >= 0xFFFFFFF8u && bits != 0;
+                        if (hit)
+                            L.state[c] = kCollected;
+                        const uint32_t pos = block_append(&s_ltail, hit, false);
+                        if (hit)
+                            L.slots[pos] = make_uint3(c, (uint32_t)__builtin_ctz(bits) | bits << 8, 0u);
+                    }
+                }
+                __syncthreads();
                 clk.mark(kClOther);
                 lo = hi;
                 r++;
-                hinge_in_slot = false;  // the next layer was claimed by atomicMin
+                hinge_in_slot = true;  // the scan wrote each slot's hinge and degree-1 parts
                 continue;
             }
             // A sparse layer of a bucket given by key words (whose edge area is free) may claim
