@@ -520,28 +520,23 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     off[1:] = np.cumsum(sizes)
     total = int(off[-1])
     block, grid = args.batch_block, args.batch_grid
-    tune = None
-    if not args.no_batch_autotune and block == 0 and grid == 0:
-        # the library's autotuner on every 16th bucket in size order (the same size mix at a
-        # sixteenth of the keys); the full batch then runs with the fastest tuning
-        pick = np.argsort(sizes, kind="stable")[::16]
-        s_sizes = sizes[pick]
-        s_off = np.zeros(len(s_sizes) + 1, np.uint64)
-        s_off[1:] = np.cumsum(s_sizes)
-        s_keys = mx.gen_buckets_u64(torch.from_numpy(s_off.view(np.int64)).to(dev))
-        sb = mx.BatchBuild(s_off)
-        tune = sb.autotune(s_keys, reps=2)
-        block, grid = tune["candidates"][tune["best"]]
-        tune.update(sample_buckets=len(s_sizes), sample_keys=int(s_off[-1]))
-        log(f"[batched] autotune on {len(s_sizes)} buckets: " +
-            ", ".join(f"{b}x{g} {ms:.1f} ms" for (b, g), ms in zip(tune["candidates"], tune["ms"])) +
-            f" -> {block}x{grid}")
-        del sb, s_keys
-        torch.cuda.empty_cache()
+    autotune = not args.no_batch_autotune and block == 0 and grid == 0
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    tunes = []
 
     def setup():
         keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).to(dev))
         bb = mx.BatchBuild(off, block=block, grid=grid)
+        if autotune:
+            # the library's autotuner on the full batch, in this allocation (which shape wins
+            # depends on the allocation's physical layout), between the two shapes that win at
+            # this workload: 1024 threads x one workgroup per CU and 512 x two (the 256-thread
+            # shapes ran 4-10 % slower on every sample); one timed build each
+            t = bb.autotune(keys, candidates=[(1024, cus, 0), (512, 2 * cus, 0)], reps=1)
+            tunes.append(t)
+            log(f"[batched] autotune on the full batch: " +
+                ", ".join(f"{b}x{g} {ms:.1f} ms" for (b, g), ms in zip(t["candidates"], t["ms"])) +
+                f" -> {bb.tuning.block}x{bb.tuning.grid}")
         bb.capture(keys)
         bb.launch()  # warm
         torch.cuda.synchronize()
@@ -617,7 +612,7 @@ def batched_leg(args, mx, torch, np, workloads) -> dict:
     out = dict(workload=BATCH_WORKLOAD, buckets=len(sizes), keys=total, ms_per_step=round(sec * 1000, 3),
                value=round(ok_keys / sec, 1), unit="edges/s", failed_buckets=int((~ok).sum()),
                retries=extra_tries, block=bb.tuning.block, grid=bb.tuning.grid,
-               placement_probe_ms=[round(x, 1) for x in probes], autotune=tune,
+               placement_probe_ms=[round(x, 1) for x in probes], autotune=tunes[-1] if tunes else None,
                plain_same_buckets=dict(value=round(plain_rate, 1), unit="edges/s", buckets=len(sample),
                                        note="one mphx_mphf_build_u64 per bucket into a preallocated workspace "
                                             "and outputs (no allocation in the timed calls)",
