@@ -135,6 +135,30 @@ def test_batch_record_build_packed_boundary(mx, o, block):
     _check_buckets(mx, o, bb, keys.cpu().numpy().view(np.uint64), sizes)
 
 
+@pytest.mark.parametrize("cl", [1, 0])
+def test_batch_sorted_deletes_on_nearly_every_layer(mx, o, cl):
+    """batch_sort_deletes = 1024 sends every layer of at least m/2048 edges through the sorted
+    deletes (their skips of degree-1 vertices, the marks and the state scan), between claim-list
+    rounds (cl = 1) or atomicMin rounds (cl = 0); every bucket against the oracle."""
+    import torch
+
+    sizes = np.array([5_000, 20_000, 40_000, 131_072, 299_999], np.uint64)
+    old = [mx.get_option(k) for k in _BATCH_OPTS]
+    for k, v in zip(_BATCH_OPTS, (0, 1024, cl)):
+        mx.set_option(k, v)
+    try:
+        off = _offsets(sizes)
+        keys = mx.gen_buckets_u64(torch.from_numpy(off.view(np.int64)).cuda())
+        for block in (512, 1024):
+            bb = mx.BatchBuild(off, block=block, grid=0, scope=0)
+            bb.run(keys)
+            torch.cuda.synchronize()
+            _check_buckets(mx, o, bb, _host_keys(sizes), sizes)
+    finally:
+        for k, v in zip(_BATCH_OPTS, old):
+            mx.set_option(k, v)
+
+
 def test_batch_large_buckets_sampled(mx, o):
     import torch
 
