@@ -600,12 +600,18 @@ hipError_t launch_round0(const PeelState& st, hipStream_t s)
                                                       st.claims, st.dcount, st.lcap, st.ctrl, st.vin, st.vout);
         else
             k_round0_lists<<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.slots, st.lcount, st.ctrl);
-    } else if (st.tripartite)
-        k_round0<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots, st.lcount,
-                                                st.ctrl);
-    else
-        k_round0<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots, st.lcount,
-                                                 st.ctrl);
+    } else {
+        // at least eight vertices per thread and at most 1024 blocks: every block ends with
+        // four atomics on the same counters, which serialise (one thread per vertex made them
+        // most of this kernel's time at 10^6 keys)
+        g = grid_for((st.m + 7) / 8, 1024);
+        if (st.tripartite)
+            k_round0<true><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots,
+                                                    st.lcount, st.ctrl);
+        else
+            k_round0<false><<<g, kPeelBlock, 0, s>>>(st.rec, st.m, st.edges, st.P, st.n, st.state, st.slots,
+                                                     st.lcount, st.ctrl);
+    }
     return hipGetLastError();
 }
 
