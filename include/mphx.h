@@ -583,7 +583,8 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
 /* ---------------------------------------------------------------------------------------
  * Tuning and diagnostics.
  * mphx_set_option / mphx_get_option (process-wide):
- *   "grid"        blocks per launch of the grid-stride peeling kernels (0 = automatic).
+ *   "grid"        blocks per launch of the grid-stride peeling kernels (0 = automatic: one
+ *                 256-thread block per 256 edges of the layer, between 64 and 1024).
  *   "round_batch" peeling rounds enqueued before the first check of the termination flag
  *                 (default 64; later checks come every 16 rounds).  Empty rounds past the end
  *                 cost a launch each, a check a host round trip.

@@ -238,12 +238,17 @@ int read_ctrl(Ctrl* dctrl, Ctrl& h, hipStream_t s)
     return MPHX_OK;
 }
 
+// Apply grids: one 256-thread block per 256 layer edges, between 64 and 1024 blocks (four per
+// compute unit; the kernels stride over larger layers).  A batch of rounds shares the grid of
+// its first layer, so a larger cap launched thousands of idle blocks into the small rounds
+// after it: 1024 against 8192 measured 2-4 % faster from 10^7 to 6x10^7 keys and no slower
+// at 2^27 and 2^31.
 unsigned auto_grid(uint64_t work)
 {
     int g = g_opt.grid.load();
     if (g > 0) return (unsigned)g;
     uint64_t b = (work + 255) / 256;
-    return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 64), 8192);
+    return (unsigned)std::min<uint64_t>(std::max<uint64_t>(b, 64), 1024);
 }
 
 constexpr uint32_t kLaterBatch = 16;
