@@ -590,10 +590,13 @@ MPHX_API int mphx_gen_str_bytes(uint8_t* bytes, const uint64_t* offs, uint64_t n
  *                 cost a launch each, a check a host round trip.
  *   "timing"      1 = record a HIP event pair on the caller's stream around every kernel
  *                 launch of mphx_peel / mphx_mphf_build_*, accumulated per phase.
- *   "part_build"  1 (default) = mphx_mphf_build_* builds the vertex records by partitioning
- *                 each part's (vertex, edge) incidences into buckets of 2^14 vertices and
- *                 accumulating each bucket in LDS; 0 = device atomics straight into HBM.
- *                 Both give identical records; mphx_peel always uses the atomics.
+ *   "part_build"  b in 0..32 (default 21): mphx_mphf_build_* with n >= 2^b keys builds the
+ *                 vertex records by partitioning each part's (vertex, edge) incidences into
+ *                 buckets of 2^14 vertices and accumulating each bucket in LDS; smaller key
+ *                 sets (and every set with b = 0) use device atomics straight into the
+ *                 records, one launch against the partition's dozen, faster while the
+ *                 records stay in the caches (1 = always partitioned).  Both give identical
+ *                 records; mphx_peel always uses the atomics.
  *   "claim_lists" b in 0..32 (default 26): mphx_mphf_build_* with n >= 2^b keys claims the
  *                 edges of each layer after the first by appending (edge, position) lists
  *                 that are radix-partitioned by edge and resolved in LDS, instead of one

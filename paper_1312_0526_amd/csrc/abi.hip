@@ -27,7 +27,10 @@ struct Options {
                                        // kLaterBatch (a peel at gamma 1.23 takes 57-64 rounds from
                                        // 10^5 keys up, so one batch usually covers it)
     std::atomic<int> timing{0};        // 1 = HIP events around every launch, per phase
-    std::atomic<int> part_build{1};    // 1 = partitioned record build, 0 = device atomics
+    std::atomic<int> part_build{21};   // partitioned record build from n >= 2^part_build keys on,
+                                       // device atomics below (0 = never): below ~2^21 keys the
+                                       // records stay cache-resident and the build's one launch
+                                       // beats the partition's dozen
     std::atomic<int> claim_lists{26};  // claim lists from n >= 2^claim_lists keys on (0 = never);
                                        // below 2^26 keys the per-round partition and resolve cost more
                                        // than the atomic claims they replace
@@ -436,7 +439,7 @@ int mphx_set_option(const char* key, int64_t value)
         if (value != 0 && value != 1) return fail(MPHX_EINVAL, "timing must be 0 or 1");
         g_opt.timing = (int)value;
     } else if (!strcmp(key, "part_build")) {
-        if (value != 0 && value != 1) return fail(MPHX_EINVAL, "part_build must be 0 or 1");
+        if (value < 0 || value > 32) return fail(MPHX_EINVAL, "part_build must be in 0..32");
         g_opt.part_build = (int)value;
     } else if (!strcmp(key, "claim_lists")) {
         if (value < 0 || value > 32) return fail(MPHX_EINVAL, "claim_lists must be in 0..32");
@@ -880,7 +883,8 @@ int mphf_build(const KeySrc& k, uint64_t n, uint64_t seed, uint32_t gnum, uint32
     bool done = false;
     for (t = 0; t < max_tries; t++) {
         uint64_t sd = seed + t;
-        const bool part = g_opt.part_build.load() != 0;
+        const int pb = g_opt.part_build.load();
+        const bool part = pb > 0 && n >= (1ull << pb);  // pb <= 32
         if (!part)
             HIP_TRY(launch_zero(L.rec, m * sizeof(uint64_t), s));
         HIP_TRY(launch_zero(L.lcount, (st.rcap + 2) * sizeof(unsigned long long), s));

@@ -66,6 +66,7 @@ def test_options_roundtrip(mx):
 
 @pytest.mark.parametrize("key,default,good,bad", [
     ("batch_lds", 1, 0, 2),
+    ("part_build", 21, 1, 33),
     ("batch_sort_deletes", 4, 8, 1025),
     ("batch_claim_lists", 1, 0, 2),
     ("batch_clock", 0, 1, 2),

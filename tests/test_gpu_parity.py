@@ -355,9 +355,10 @@ def test_mphf_deterministic_across_launch_shapes(mx):
 @pytest.fixture(params=[1, 0], ids=["partitioned-build", "atomic-build"])
 def build_mode(request, mx):
     """The two record builds: radix-partitioned with LDS accumulation, and device atomics."""
-    mx.set_option("part_build", request.param)
+    old = mx.get_option("part_build")
+    mx.set_option("part_build", request.param)  # 1: partitioned at every size, 0: atomics
     yield request.param
-    mx.set_option("part_build", 1)
+    mx.set_option("part_build", old)
 
 
 @pytest.mark.parametrize("n", [12_000_000, 333_333])
@@ -374,11 +375,12 @@ def test_mphf_record_builds_match_oracle(mx, o, build_mode, n):
 def test_mphf_record_builds_agree_on_strings(mx):
     data, offs = workloads.str_keys(700_000, gen_seed=2)
     outs = []
+    old = mx.get_option("part_build")
     for mode in (1, 0):
         mx.set_option("part_build", mode)
         r = mx.mphf_build_str(dev(data), dev(offs), seed=1)
         outs.append((host(r["codes"], np.uint64), host(r["rank"], np.uint64), r["n_rounds"]))
-    mx.set_option("part_build", 1)
+    mx.set_option("part_build", old)
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
     assert outs[0][2] == outs[1][2]
 
